@@ -1,0 +1,453 @@
+"""Pins of the FP64 oracle against what the paper and the mathematics fix.
+
+Every check here is independent of the oracle's own code route: closed forms,
+invariants, exact enumeration, brute force on tiny inputs written with a
+different construction of H (bit parity instead of the Sylvester recursion),
+and library routines (LU, least squares, torch's bfloat16 rounding, scipy's
+Bessel functions). A plausible mistake in the oracle -- a missing 1/sqrt(d)
+per transform, a reversed transform order, a transposed W, a sign error in
+the gradient, a dropped normaliser -- fails at least one of them.
+"""
+import json
+import math
+import os
+
+import numpy as np
+import pytest
+import scipy.linalg
+import scipy.special
+
+from oracle import sorf_oracle as O
+from paper_2206_01580_amd import workloads as W
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def parity_hadamard(d):
+    """H[i, j] = (-1)^{popcount(i & j)} -- a construction independent of the
+    Sylvester recursion."""
+    H = np.empty((d, d))
+    for i in range(d):
+        for j in range(d):
+            H[i, j] = -1.0 if bin(i & j).count("1") % 2 else 1.0
+    return H
+
+
+def fwht_inplace(v):
+    """Plain iterative fast Walsh-Hadamard transform (unnormalised), natural
+    order, written independently of the oracle for the route cross-check."""
+    v = np.array(v, dtype=np.float64)
+    n = v.shape[-1]
+    h = 1
+    while h < n:
+        for i in range(0, n, 2 * h):
+            a = v[..., i:i + h].copy()
+            b = v[..., i + h:i + 2 * h].copy()
+            v[..., i:i + h] = a + b
+            v[..., i + h:i + 2 * h] = a - b
+        h *= 2
+    return v
+
+
+# ---------------------------------------------------------------- P1
+@pytest.mark.parametrize("d", [1, 2, 4, 8, 16, 64, 128])
+def test_p1_hadamard_identities(d):
+    H = O.hadamard(d)
+    assert np.array_equal(H, H.T)
+    assert np.array_equal(H @ H.T, d * np.eye(d))
+    assert np.array_equal(H, parity_hadamard(d))
+
+
+def test_p1_rejects_non_power_of_two():
+    with pytest.raises(ValueError):
+        O.hadamard(12)
+
+
+# ---------------------------------------------------------------- P2
+@pytest.mark.parametrize("d,T", [(2, 1), (8, 2), (64, 3), (128, 3), (256, 2)])
+def test_p2_blocks_orthogonal_and_row_norms(d, T):
+    rng = np.random.default_rng(d * 10 + T)
+    sigma = 1.7
+    signs = W.draw_signs(rng, 1, T, 3, d)[0]
+    Wm = O.dense_w(signs, sigma)
+    assert Wm.shape == (3 * d, d)
+    for s in range(3):
+        B = Wm[s * d:(s + 1) * d] * sigma / math.sqrt(d)
+        assert np.abs(B @ B.T - np.eye(d)).max() < 1e-13
+    norms = np.linalg.norm(Wm, axis=1)
+    assert np.abs(norms - math.sqrt(d) / sigma).max() < 1e-12
+
+
+# ---------------------------------------------------------------- P3
+@pytest.mark.parametrize("d,T", [(4, 1), (16, 2), (128, 3)])
+def test_p3_fwht_route_equals_dense_route(d, T):
+    rng = np.random.default_rng(7 + d)
+    S, sigma = 3, 2.5
+    signs = W.draw_signs(rng, 1, T, S, d)[0]
+    x = rng.standard_normal((5, d))
+    Wm = O.dense_w(signs, sigma)
+    dense = x @ Wm.T
+    # fast route: per stack, T rounds of (sign flip, FWHT), then 1/sqrt(d) per round
+    fast = np.empty_like(dense)
+    for s in range(S):
+        v = x.copy()
+        for t in range(T):
+            v = fwht_inplace(v * signs[t, s]) / math.sqrt(d)
+        fast[:, s * d:(s + 1) * d] = v * math.sqrt(d) / sigma
+    assert np.abs(fast - dense).max() < 1e-12 * max(1.0, np.abs(dense).max())
+
+
+# ---------------------------------------------------------------- P4
+def _golden_cases():
+    with open(os.path.join(GOLDEN, "worked_d2.json")) as f:
+        g = json.load(f)
+    return [(g["common"], c) for c in g["cases"]]
+
+
+@pytest.mark.parametrize("common,case", _golden_cases(), ids=lambda v: v.get("name", ""))
+def test_p4_worked_examples(common, case):
+    d, sigma = common["d"], common["sigma"]
+    signs = np.array(case["signs"], dtype=np.int8)[:, None, :]          # [T, S=1, d]
+    Wm = O.dense_w(signs, sigma)
+    assert np.abs(Wm - np.array(case["W"])).max() < 1e-15
+    x = np.array([common["x"]], dtype=np.float64)
+    bias = np.array([common["bias"]])
+    alpha = np.array(common["alpha"])
+    ptr = np.array([0, 1])
+    Z = O.molecule_features(x, np.array([0]), ptr, signs[None], bias, sigma)
+    assert np.abs(Z[0] - case["z"]).max() < 5e-7
+    E = O.predict_energies(Z, alpha)
+    assert abs(E[0] - case["E"]) < 5e-7
+    g = O.grad_x(x, np.array([0]), ptr, signs[None], bias, sigma, alpha)
+    assert np.abs(g[0] - case["dEdx"]).max() < 5e-7
+    # the same values from the closed form of the hand derivation
+    u = np.array(case["W"]) @ x[0] + bias[0]
+    assert np.abs(Z[0] - np.cos(u)).max() < 1e-15
+
+
+# ---------------------------------------------------------------- P5
+def test_p5_zero_input_gives_bias_cosines():
+    p = W.random_problem(11, d=16, n_stacks=3, n_transforms=3, n_elements=2, n_mols=4,
+                         min_atoms=1, max_atoms=3)
+    x0 = np.zeros_like(p.x)
+    z = O.atom_features(x0, p.element, p.signs, p.bias, p.sigma)
+    D = p.n_features
+    expect = math.sqrt(2.0 / D) * np.cos(p.bias[p.element].astype(np.float64))
+    assert np.abs(z - expect).max() < 1e-15
+
+
+def test_p5_single_atom_molecule_is_its_feature():
+    p = W.random_problem(12, d=8, n_stacks=2, n_mols=5, min_atoms=1, max_atoms=1)
+    Z = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma)
+    z = O.atom_features(p.x, p.element, p.signs, p.bias, p.sigma)
+    assert np.array_equal(Z, z)
+
+
+def test_p5_d1_single_transform():
+    # d = 1, one transform: W = s / sigma (H_1 = 1, c = 1/sigma)
+    for s in (1, -1):
+        Wm = O.dense_w(np.array([[[s]]], dtype=np.int8), 0.5)
+        assert Wm.shape == (1, 1) and Wm[0, 0] == s / 0.5
+
+
+def test_p5_empty_molecules_give_zero_rows():
+    p = W.random_problem(13, d=4, n_stacks=2, n_mols=6, min_atoms=0, max_atoms=2)
+    Z = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma)
+    empty = np.diff(p.mol_ptr) == 0
+    assert empty.any()
+    assert np.all(Z[empty] == 0.0)
+
+
+# ---------------------------------------------------------------- brute force
+def test_brute_force_tiny_molecule_features():
+    """Pure-Python loops over atoms/stacks/rows, H from bit parity."""
+    p = W.random_problem(21, d=4, n_stacks=2, n_transforms=2, n_elements=2, n_mols=3,
+                         min_atoms=1, max_atoms=3)
+    d, S, T = p.d, p.n_stacks, p.n_transforms
+    Hp = parity_hadamard(d)
+    D = S * d
+    c = (math.sqrt(d) / p.sigma) / d ** (T / 2)
+    Zb = np.zeros((p.n_mols, D))
+    for m in range(p.n_mols):
+        for i in range(p.mol_ptr[m], p.mol_ptr[m + 1]):
+            e = p.element[i]
+            for s in range(S):
+                v = [float(t) for t in p.x[i]]
+                for t in range(T):
+                    v = [sum(Hp[r, j] * p.signs[e, t, s, j] * v[j] for j in range(d))
+                         for r in range(d)]
+                for r in range(d):
+                    Zb[m, s * d + r] += math.sqrt(2.0 / D) * math.cos(c * v[r] + float(p.bias[e, s * d + r]))
+    Z = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma)
+    assert np.abs(Z - Zb).max() < 1e-13
+
+
+def test_transform_order_matters():
+    """Reversing the transform order changes W (guards the t=0-first reading)."""
+    rng = np.random.default_rng(3)
+    signs = W.draw_signs(rng, 1, 3, 1, 8)[0]
+    A = O.dense_w(signs, 1.0)
+    B = O.dense_w(signs[::-1].copy(), 1.0)
+    assert np.abs(A - B).max() > 0.1
+
+
+# ---------------------------------------------------------------- P6
+def test_p6_invariants():
+    p = W.random_problem(31, d=16, n_stacks=4, n_mols=6, min_atoms=1, max_atoms=7)
+    Z = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma)
+    # atom permutation inside each molecule
+    perm = np.concatenate([np.random.default_rng(m).permutation(np.arange(p.mol_ptr[m], p.mol_ptr[m + 1]))
+                           for m in range(p.n_mols)])
+    Zp = O.molecule_features(p.x[perm], p.element[perm], p.mol_ptr, p.signs, p.bias, p.sigma)
+    assert np.abs(Z - Zp).max() < 1e-14
+    # molecule permutation permutes rows, leaves G unchanged
+    mp = np.random.default_rng(5).permutation(p.n_mols)
+    q = p.subset(mp)
+    Zq = O.molecule_features(q.x, q.element, q.mol_ptr, q.signs, q.bias, q.sigma)
+    assert np.abs(Zq - Z[mp]).max() < 1e-15
+    G, _ = O.gram(Z)
+    Gq, _ = O.gram(Zq)
+    assert np.abs(G - Gq).max() < 1e-13
+    # duplicates give identical rows
+    dup = p.subset([2, 2])
+    Zd = O.molecule_features(dup.x, dup.element, dup.mol_ptr, dup.signs, dup.bias, dup.sigma)
+    assert np.array_equal(Zd[0], Zd[1])
+    # G symmetric positive semidefinite, Z^T y linear in y
+    assert np.array_equal(G, G.T)
+    assert np.linalg.eigvalsh(G).min() > -1e-12
+    y1, y2 = np.random.default_rng(1).standard_normal((2, p.n_mols))
+    _, r1 = O.gram(Z, y1)
+    _, r2 = O.gram(Z, y2)
+    _, r12 = O.gram(Z, 2 * y1 - 3 * y2)
+    assert np.abs(r12 - (2 * r1 - 3 * r2)).max() < 1e-12
+
+
+def test_p6_mean_squared_norm_over_phase_is_one():
+    """E_b |z(x)|^2 = 1: averaging cos^2 over a uniform phase shift is 1/2, so
+    the sqrt(2/D) normaliser gives unit mean squared norm. Exact on a uniform
+    grid of >= 3 shifts."""
+    p = W.random_problem(41, d=32, n_stacks=2, n_mols=1, min_atoms=1, max_atoms=1)
+    vals = []
+    for k in range(8):
+        b = (p.bias.astype(np.float64) + 2 * math.pi * k / 8)
+        z = O.atom_features(p.x, p.element, p.signs, b, p.sigma)
+        vals.append((z ** 2).sum())
+    assert abs(np.mean(vals) - 1.0) < 1e-13
+
+
+def test_gram_brute_force():
+    rng = np.random.default_rng(2)
+    Z = rng.standard_normal((5, 3))
+    y = rng.standard_normal(5)
+    G, r = O.gram(Z, y)
+    for i in range(3):
+        for j in range(3):
+            assert abs(G[i, j] - sum(Z[m, i] * Z[m, j] for m in range(5))) < 1e-13
+        assert abs(r[i] - sum(Z[m, i] * y[m] for m in range(5))) < 1e-13
+
+
+# ---------------------------------------------------------------- P7
+@pytest.mark.parametrize("d", [2, 4, 8])
+def test_p7_single_transform_expectation_closed_form(d):
+    """T = 1: row r of W is (1/sigma) H_r * s, so over Rademacher s the mean
+    of cos(w . delta) is prod_j cos(delta_j / sigma). Exact enumeration of all
+    2^d sign patterns."""
+    sigma = 1.3
+    delta = np.random.default_rng(d).standard_normal(d)
+    acc = 0.0
+    for pat in range(2 ** d):
+        s = np.array([[[-1 if (pat >> j) & 1 else 1 for j in range(d)]]], dtype=np.int8)
+        Wm = O.dense_w(s, sigma)
+        acc += np.cos(Wm @ delta).mean()
+    assert abs(acc / 2 ** d - np.prod(np.cos(delta / sigma))) < 1e-13
+
+
+@pytest.mark.parametrize("T", [2, 3])
+def test_p7_multi_transform_expectation_enumerated(T):
+    """T >= 2 at d = 4: average over D_0 in closed form (product of cosines
+    of the columns of c * H D_{T-1} ... H D_1 H), then enumerate the remaining
+    sign matrices; must equal the oracle's full enumeration over all
+    2^(T d) patterns."""
+    d, sigma = 4, 0.9
+    delta = np.array([0.7, -0.4, 0.9, 0.2])
+    Hp = parity_hadamard(d)
+    c = (math.sqrt(d) / sigma) / d ** (T / 2)
+    # semi-closed form
+    acc_sc = 0.0
+    nrest = 2 ** (d * (T - 1))
+    for pat in range(nrest):
+        M = Hp.copy()                                  # after D_0: H (D_0 applied to input)
+        for t in range(1, T):
+            st = np.array([-1 if (pat >> (d * (t - 1) + j)) & 1 else 1 for j in range(d)])
+            M = Hp @ np.diag(st) @ M
+        # row r of W = c * M[r, :] * s0 ; E_{s0} cos(sum_j c M_rj s0_j delta_j)
+        acc_sc += np.prod(np.cos(c * M * delta[None, :]), axis=1).mean()
+    acc_sc /= nrest
+    # full enumeration through the oracle
+    acc = 0.0
+    for pat in range(2 ** (d * T)):
+        s = np.array([[[-1 if (pat >> (d * t + j)) & 1 else 1 for j in range(d)]] for t in range(T)],
+                     dtype=np.int8)
+        acc += np.cos(O.dense_w(s, sigma) @ delta).mean()
+    acc /= 2 ** (d * T)
+    assert abs(acc - acc_sc) < 1e-13
+
+
+# ---------------------------------------------------------------- P8
+def sphere_kernel(d, r):
+    """Characteristic function of the uniform distribution on the sphere of
+    radius sqrt(d): Gamma(d/2) (2/s)^(d/2-1) J_{d/2-1}(s) with s = sqrt(d) r."""
+    s = math.sqrt(d) * r
+    nu = d / 2 - 1
+    return math.exp(math.lgamma(d / 2) + nu * math.log(2 / s)) * scipy.special.jv(nu, s)
+
+
+def _mc_kernel(d, T, r, n_blocks, seed):
+    rng = np.random.default_rng(seed)
+    delta = rng.standard_normal(d)
+    delta *= r / np.linalg.norm(delta)          # sigma = 1, |delta| = r
+    H = O.hadamard(d)
+    c = O.sorf_scale(d, T, 1.0)
+    means = np.empty(n_blocks)
+    signs = W.draw_signs(rng, 1, T, n_blocks, d)[0]
+    for b in range(n_blocks):
+        v = delta.copy()
+        for t in range(T):
+            v = H @ (signs[t, b] * v)
+        means[b] = np.cos(c * v).mean()
+    return means.mean(), means.std(ddof=1) / math.sqrt(n_blocks)
+
+
+@pytest.mark.parametrize("d,r", [(64, 1.0), (64, 1.6), (128, 1.0)])
+def test_p8_monte_carlo_limit_matches_sphere_kernel(d, r):
+    mean, se = _mc_kernel(d, 3, r, 6000, seed=d + int(10 * r))
+    kd = sphere_kernel(d, r)
+    gauss = math.exp(-r * r / 2)
+    assert abs(mean - kd) <= 4 * se, (mean, kd, se)
+    # and within the stated bias allowance of the Gaussian the method targets
+    assert abs(mean - gauss) <= abs(kd - gauss) + 4 * se
+    assert abs(kd - gauss) < 1e-2
+
+
+def test_p8_normalisation_is_essential():
+    """Without the per-transform 1/sqrt(d) the row norm is off by d^{(T-1)/2}
+    and the estimator collapses to ~0 -- the test above would fail."""
+    d, T = 64, 3
+    signs = W.draw_signs(np.random.default_rng(0), 1, T, 1, d)[0]
+    Wm = O.dense_w(signs, 2.0)
+    assert abs(np.linalg.norm(Wm[0]) - math.sqrt(d) / 2.0) < 1e-12
+    assert abs(np.linalg.norm(Wm[0]) * d ** ((T - 1) / 2) - 256.0) < 1e-9
+
+
+# ---------------------------------------------------------------- P9 / P11
+def test_p9_planted_solution():
+    p = W.random_problem(51, d=16, n_stacks=2, n_mols=80, min_atoms=1, max_atoms=6)
+    Z = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma)
+    a_star = np.random.default_rng(0).standard_normal(Z.shape[1])
+    y = Z @ a_star
+    G, r = O.gram(Z, y)
+    lam = 1e-3
+    a = O.solve(G, r, lam)
+    closed = np.linalg.solve(G + lam * np.eye(len(G)), G @ a_star)
+    assert np.abs(a - closed).max() < 1e-8 * np.abs(closed).max()
+    a0 = O.solve(G, r, 1e-12)
+    assert np.abs(a0 - a_star).max() < 1e-4
+
+
+def test_p11_cholesky_vs_lu_vs_lstsq():
+    rng = np.random.default_rng(9)
+    Z = rng.standard_normal((60, 20))
+    y = rng.standard_normal(60)
+    G, r = O.gram(Z, y)
+    a = O.solve(G, r, 1e-10)
+    lu = scipy.linalg.lu_solve(scipy.linalg.lu_factor(G + 1e-10 * np.eye(20)), r)
+    ls = np.linalg.lstsq(Z, y, rcond=None)[0]
+    assert np.abs(a - lu).max() < 1e-10
+    assert np.abs(a - ls).max() < 1e-8
+
+
+# ---------------------------------------------------------------- P10
+def _energy(x, p, alpha, dE):
+    Z = O.molecule_features(x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma)
+    return float(dE @ (Z @ alpha))
+
+
+def test_p10_gradient_central_differences():
+    p = W.random_problem(61, d=8, n_stacks=3, n_mols=3, min_atoms=1, max_atoms=3)
+    alpha = p.alpha.astype(np.float64)
+    dE = np.array([1.0, -0.5, 2.0])
+    g = O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, alpha, dE)
+    x = p.x.astype(np.float64)
+    h = 1e-4
+    fd = np.zeros_like(x)
+    for i in range(x.shape[0]):
+        for j in range(x.shape[1]):
+            xp = x.copy(); xp[i, j] += h
+            xm = x.copy(); xm[i, j] -= h
+            fd[i, j] = (_energy(xp, p, alpha, dE) - _energy(xm, p, alpha, dE)) / (2 * h)
+    assert np.abs(g - fd).max() < 1e-7 * max(1.0, np.abs(g).max())
+
+
+def test_p10_forces_central_differences_through_jacobians():
+    p = W.random_problem(62, d=8, n_stacks=2, n_mols=2, min_atoms=2, max_atoms=3, with_J=True)
+    alpha = p.alpha.astype(np.float64)
+    ones = np.ones(p.n_mols)
+    g = O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, alpha)
+    F = O.forces(g, p.J, p.J_ptr, p.mol_ptr)
+    x = p.x.astype(np.float64)
+    d, h = p.d, 1e-4
+    for m in range(p.n_mols):
+        a0, a1 = p.mol_ptr[m], p.mol_ptr[m + 1]
+        n = a1 - a0
+        blk = p.J[p.J_ptr[m]:p.J_ptr[m + 1]].astype(np.float64).reshape(n, d, 3 * n)
+        for k in range(3 * n):
+            # linearised x(r + h e_k) = x + h J[:, :, k]
+            xp = x.copy(); xp[a0:a1] += h * blk[:, :, k]
+            xm = x.copy(); xm[a0:a1] -= h * blk[:, :, k]
+            fd = -(_energy(xp, p, alpha, ones) - _energy(xm, p, alpha, ones)) / (2 * h)
+            assert abs(F[3 * a0 + k] - fd) < 1e-7 * max(1.0, abs(fd))
+
+
+# ---------------------------------------------------------------- precision emulation
+def test_round_bf16_matches_torch():
+    torch = pytest.importorskip("torch")
+    rng = np.random.default_rng(4)
+    a = (rng.standard_normal(100000) * np.exp(rng.uniform(-20, 20, 100000))).astype(np.float32)
+    a = np.concatenate([a, np.array([1.0 + 2 ** -8, 1.0 + 3 * 2 ** -8, -1.0 - 2 ** -8, 0.0],
+                                    dtype=np.float32)])
+    ref = torch.from_numpy(a).to(torch.bfloat16).to(torch.float32).numpy()
+    assert np.array_equal(O.round_bf16(a), ref)
+    # ties to even
+    assert O.round_bf16(np.float32(1.0 + 2 ** -8)) == np.float32(1.0)
+    assert O.round_bf16(np.float32(1.0 + 3 * 2 ** -8)) == np.float32(1.0 + 2 ** -6)
+
+
+def test_round_fp16_ties_to_even():
+    assert O.round_fp16(np.float32(1.0 + 2 ** -11)) == np.float32(1.0)
+    assert O.round_fp16(np.float32(1.0 + 3 * 2 ** -11)) == np.float32(1.0 + 2 ** -9)
+    assert O.round_fp16(np.float32(2 ** -24)) == np.float32(2 ** -24)
+
+
+@pytest.mark.parametrize("kind,scale", [("bf16", 0), ("fp16", 8)])
+def test_hilo_split_is_accurate(kind, scale):
+    rng = np.random.default_rng(8)
+    z = (rng.standard_normal(10000) * 0.05).astype(np.float32)
+    hi, lo = O.split_hilo(z, kind, scale)
+    s = 2.0 ** scale
+    rel = np.abs((hi.astype(np.float64) + lo - z.astype(np.float64) * s)) / np.abs(z * s).max()
+    bound = 2.0 ** -16 if kind == "bf16" else 2.0 ** -21
+    assert rel.max() <= bound
+
+
+def test_gram_emulated_error_ordering():
+    rng = np.random.default_rng(10)
+    Z = (rng.standard_normal((400, 48)) * 0.03).astype(np.float32)
+    exact = Z.astype(np.float64).T @ Z.astype(np.float64)
+    nrm = np.linalg.norm(exact)
+    err = {m: np.linalg.norm(O.gram_emulated(Z, m, 10 if m.startswith("fp16") else 0) - exact) / nrm
+           for m in ("fp32", "bf16", "fp16", "bf16_hilo", "fp16_hilo")}
+    assert err["fp32"] < 1e-14
+    assert err["bf16_hilo"] < err["bf16"] / 50
+    assert err["fp16_hilo"] < err["fp16"] / 50
+    assert err["fp16_hilo"] < err["bf16_hilo"]
+    assert err["bf16"] < 5e-3 and err["bf16_hilo"] < 5e-5
