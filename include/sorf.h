@@ -1,0 +1,169 @@
+/*
+ * sorf.h -- C ABI of the MI355X (gfx950) SORF hot-path library.
+ *
+ * Structured orthogonal random features (arXiv 2206.01580, Theory section):
+ *
+ *   z(x_i)  = sqrt(2/D) * cos(c * H D_{T-1} ... H D_1 H D_0 x_i + b_e)     (RFF feature map;
+ *             SORF approximation W ~ (sqrt(d)/sigma) [H_i D_i]_{N_transform}, stacked N_F/d times)
+ *   Z_m     = sum_{i in molecule m} z(x_i)                                  (atomic energy decomposition)
+ *   (Z^T Z + lambda I) alpha = Z^T y                                         (regularised normal equation)
+ *   E_m     = Z_m alpha                                                       (prediction)
+ *   F       = -dE/dr = -sum_i J_i^T dE/dx_i                                  (forces via derivative features)
+ *
+ * with H the +-1 Walsh-Hadamard matrix of order d (Sylvester recursion, natural
+ * order: H[i][j] = (-1)^popcount(i & j)), D_t diagonal Rademacher sign matrices
+ * that depend on the element e of the atom, the transform t and the stack s,
+ * c = (sqrt(d)/sigma) * d^(-T/2), D = n_stacks * d features ordered f = s*d + j,
+ * and b_e the per-element phase vector.
+ *
+ * Conventions shared by every call:
+ *   - Pointers named in the structs and arguments are DEVICE pointers unless a
+ *     comment says "host". All buffers are owned by the caller; the library
+ *     keeps no state and never frees anything.
+ *   - Every compute call is asynchronous on `stream` (a hipStream_t; NULL means
+ *     the default stream), returns a status immediately, never prints and never
+ *     allocates device memory. Host-side validation of sizes, flags and null
+ *     pointers happens before any HIP call and returns SORF_ERR_INVALID_ARG or
+ *     SORF_ERR_UNSUPPORTED; a failed launch returns SORF_ERR_DEVICE.
+ *   - Preconditions that live in device memory are NOT checked (CSR offsets
+ *     non-decreasing with mol_ptr[0] = 0 and mol_ptr[n_mols] = n_atoms, element
+ *     ids in [0, n_elements)); sorf_validate_batch checks them on request.
+ *   - Float arrays (x, bias, alpha, Z, grad_x) must be 16-byte aligned, sign words
+ *     4-byte aligned (any allocation from hipMalloc is); misaligned pointers are
+ *     rejected with SORF_ERR_INVALID_ARG.
+ *   - Results are deterministic: no floating-point atomics, fixed summation order.
+ *   - Distinct streams may run calls concurrently; calls that write the same
+ *     output buffer must be ordered by the caller.
+ */
+#ifndef SORF_H
+#define SORF_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define SORF_ABI_VERSION 1
+
+typedef void* sorf_stream_t; /* a hipStream_t */
+
+typedef enum {
+  SORF_OK = 0,
+  SORF_ERR_INVALID_ARG = 1,  /* null pointer with non-zero size, bad size or flag */
+  SORF_ERR_UNSUPPORTED = 2,  /* valid request outside what the kernels implement */
+  SORF_ERR_DEVICE = 3,       /* a HIP launch or runtime call failed */
+  SORF_ERR_WORKSPACE = 4     /* workspace missing or smaller than the query returns */
+} sorf_status;
+
+typedef enum {
+  SORF_GRAM_FP32 = 0,        /* FP32 operands, FP32 MFMA, FP32 accumulation */
+  SORF_GRAM_BF16 = 1,        /* one bf16 product hi^T hi, FP32 accumulation */
+  SORF_GRAM_FP16 = 2,        /* one fp16 product hi^T hi, FP32 accumulation */
+  SORF_GRAM_BF16_HILO = 3,   /* hi^T hi + hi^T lo + lo^T hi with hi = bf16(z), lo = bf16(z - hi) */
+  SORF_GRAM_FP16_HILO = 4    /* the same with fp16 parts of 2^scale_exp * z */
+} sorf_gram_precision;
+
+/* Model parameters (host struct; the arrays it points to are device-resident).
+ * SORF subsection: per-element sign diagonals and the stacking of N_F/d blocks;
+ * RFF subsection: phases b in [0, 2 pi). */
+typedef struct {
+  int32_t d;             /* representation size, a power of two in [2, 1024]            */
+  int32_t n_stacks;      /* S >= 1; D = S * d features (D <= 2^20)                      */
+  int32_t n_transforms;  /* T in {1, 2, 3}: number of (sign, Hadamard) rounds           */
+  int32_t n_elements;    /* E >= 1                                                      */
+  float sigma;           /* kernel length scale, finite and > 0                         */
+  const uint32_t* signs; /* [E][T][S][W] with W = ceil(d / 32) words per vector; bit j of
+                            word j/32 set means entry j of D_t is -1. t = 0 is applied first. */
+  const float* bias;     /* [E][D] phases in radians                                     */
+} sorf_model;
+
+/* A batch of molecules in CSR form (host struct, device arrays). */
+typedef struct {
+  const float* x;          /* [n_atoms][d] row-major projected representations          */
+  const int32_t* element;  /* [n_atoms] element ids                                      */
+  const int64_t* mol_ptr;  /* [n_mols + 1] atom offsets of each molecule                 */
+  int64_t n_atoms;         /* >= 0; may be 0 (outputs are then zeroed)                   */
+  int64_t n_mols;          /* >= 0; molecules with zero atoms give zero rows / energies  */
+} sorf_batch;
+
+/* ABI version of the loaded library (compare with SORF_ABI_VERSION). */
+int32_t sorf_abi_version(void);
+
+/* Human-readable name of a status code (static storage, never NULL). */
+const char* sorf_status_string(sorf_status s);
+
+/* Feature matrix. RFF feature map summed over each molecule's atoms (atomic
+ * energy decomposition); SORF operator applied with the fast Walsh-Hadamard
+ * transform in O(T * D * log d) per atom (SORF subsection).
+ *   Z: [n_mols][D] row-major FP32, overwritten (rows of empty molecules = 0). */
+sorf_status sorf_forward(const sorf_model* model, const sorf_batch* batch, float* Z,
+                         sorf_stream_t stream);
+
+/* Adjoint of the energy E_m = Z_m alpha with respect to the inputs x (the
+ * derivative features of the force-trained normal equation, contracted with
+ * alpha): for atom i of molecule m,
+ *   grad_x[i] = dE[m] * sum_s c * D_0 H D_1 ... D_{T-1} H g_{i,s},
+ *   g_{i,f} = -sqrt(2/D) * alpha_f * sin(c * v_{i,f} + b_{e,f}).
+ *   alpha:  [D] FP32;  dE: [n_mols] upstream weights or NULL for all ones;
+ *   grad_x: [n_atoms][d] FP32, overwritten. */
+sorf_status sorf_backward(const sorf_model* model, const sorf_batch* batch, const float* alpha,
+                          const float* dE, float* grad_x, sorf_stream_t stream);
+
+/* Normal-equation accumulation (regularised normal equation):
+ *   G[i][j] += sum_m Z[m][i] * Z[m][j]   for i >= j only (the strict upper triangle of G is
+ *                                         neither read nor written),
+ *   Zty[i]  += sum_m Z[m][i] * y[m]       (FP32, skipped when y is NULL).
+ *   Z: [n_rows][D] row-major; G: [D][D] row-major. scale_exp: the FP16 modes split
+ *   2^scale_exp * Z into parts and scale G back by 2^(-2*scale_exp) exactly (keeps the
+ *   low part out of the fp16 subnormal range); must be 0 for the other modes, |scale_exp| <= 60. */
+sorf_status sorf_gram_accumulate(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                                 sorf_gram_precision precision, int32_t scale_exp, float* G,
+                                 float* Zty, sorf_stream_t stream);
+
+/* Bytes of workspace sorf_solve needs for a D x D system, 1 <= D <= 32768
+ * (host-only query; returns 0 for an unsupported D). */
+size_t sorf_solve_workspace_bytes(int32_t D);
+
+/* Ridge solve of the regularised normal equation (LU in the paper; the matrix
+ * is symmetric positive definite for lambda > 0, so Cholesky gives the same alpha):
+ *   A = G + lambda I (G: lower triangle of an FP32 [D][D] row-major matrix, promoted to FP64),
+ *   FP64 Cholesky A = L L^T, alpha = A^{-1} Zty, then n_refine steps of iterative
+ *   refinement alpha += A^{-1} (Zty - A alpha) with the residual in FP64.
+ *   alpha: [D] FP64 out. info: device int32, written 0 on success or k > 0 when the
+ *   leading minor of order k is not positive definite (LAPACK convention; alpha is then
+ *   undefined). workspace: device memory of at least sorf_solve_workspace_bytes(D),
+ *   256-byte aligned. 0 <= n_refine <= 16, lambda >= 0 and finite. */
+sorf_status sorf_solve(int32_t D, const float* G, const float* Zty, double lambda,
+                       int32_t n_refine, double* alpha, int32_t* info, void* workspace,
+                       size_t workspace_bytes, sorf_stream_t stream);
+
+/* Bytes of workspace sorf_predict needs (host-only query). */
+size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, int64_t n_mols);
+
+/* Prediction of energies (E = Z alpha, without forming Z) and, when J is given,
+ * forces F = -sum_{i in m} J_i^T dE/dx_i.
+ *   alpha: [D] FP32.  E: [n_mols] FP32 out.
+ *   J: concatenated per-molecule blocks, block m is [N_m][d][3 N_m] row-major
+ *      (J_i = dx_i/dr_m, coordinates ordered [atom][xyz]) starting at float offset
+ *      J_ptr[m]; J_ptr: [n_mols + 1] int64 device array. Both NULL for energies only.
+ *   F: [3 n_atoms] FP32 out ([atom][xyz]), required iff J is given.
+ *   workspace: device memory of at least sorf_predict_workspace_bytes(), 256-byte aligned. */
+sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const float* alpha,
+                         const float* J, const int64_t* J_ptr, float* E, float* F,
+                         void* workspace, size_t workspace_bytes, sorf_stream_t stream);
+
+/* Opt-in debug check of the device-side preconditions of a batch. Writes to
+ * *result (device int32) a bit mask: 0 if mol_ptr is a valid CSR over n_atoms atoms
+ * and every element id is in [0, n_elements); otherwise bit 0: mol_ptr[0] != 0,
+ * bit 1: some offset decreases, bit 2: mol_ptr[n_mols] != n_atoms,
+ * bit 3: an element id is out of range. */
+sorf_status sorf_validate_batch(const sorf_batch* batch, int32_t n_elements, int32_t* result,
+                                sorf_stream_t stream);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* SORF_H */

@@ -1,0 +1,103 @@
+"""ctypes binding of ``libsorf.so`` (the C ABI in ``include/sorf.h``).
+
+Argument marshalling only: every computation runs in the HIP library. Loading
+fails loudly when the library has not been built; there is no fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsorf.so")
+
+SORF_OK = 0
+SORF_ERR_INVALID_ARG = 1
+SORF_ERR_UNSUPPORTED = 2
+SORF_ERR_DEVICE = 3
+SORF_ERR_WORKSPACE = 4
+
+GRAM_MODES = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16_hilo": 3, "fp16_hilo": 4}
+
+# every function the header declares; the load test checks each is exported
+EXPORTS = (
+    "sorf_abi_version", "sorf_status_string", "sorf_forward", "sorf_backward",
+    "sorf_gram_accumulate", "sorf_solve_workspace_bytes", "sorf_solve",
+    "sorf_predict_workspace_bytes", "sorf_predict", "sorf_validate_batch",
+)
+
+
+class SorfModel(ctypes.Structure):
+    _fields_ = [
+        ("d", ctypes.c_int32),
+        ("n_stacks", ctypes.c_int32),
+        ("n_transforms", ctypes.c_int32),
+        ("n_elements", ctypes.c_int32),
+        ("sigma", ctypes.c_float),
+        ("signs", ctypes.c_void_p),
+        ("bias", ctypes.c_void_p),
+    ]
+
+
+class SorfBatch(ctypes.Structure):
+    _fields_ = [
+        ("x", ctypes.c_void_p),
+        ("element", ctypes.c_void_p),
+        ("mol_ptr", ctypes.c_void_p),
+        ("n_atoms", ctypes.c_int64),
+        ("n_mols", ctypes.c_int64),
+    ]
+
+
+class SorfError(RuntimeError):
+    def __init__(self, fn: str, code: int):
+        super().__init__(f"{fn} failed: {status_string(code)} ({code})")
+        self.code = code
+
+
+_lib = None
+
+
+def load() -> ctypes.CDLL:
+    """Load the built library (once). Raises if it is missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise RuntimeError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -m paper_2206_01580_amd.build); there is no CPU fallback")
+    lib = ctypes.CDLL(LIB_PATH)
+    P = ctypes.c_void_p
+    i32, i64, f64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
+    MP, BP = ctypes.POINTER(SorfModel), ctypes.POINTER(SorfBatch)
+    sig = {
+        "sorf_abi_version": (i32, []),
+        "sorf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+        "sorf_forward": (ctypes.c_int, [MP, BP, P, P]),
+        "sorf_backward": (ctypes.c_int, [MP, BP, P, P, P, P]),
+        "sorf_gram_accumulate": (ctypes.c_int, [i64, i32, P, P, ctypes.c_int, i32, P, P, P]),
+        "sorf_solve_workspace_bytes": (sz, [i32]),
+        "sorf_solve": (ctypes.c_int, [i32, P, P, f64, i32, P, P, P, sz, P]),
+        "sorf_predict_workspace_bytes": (sz, [MP, i64, i64]),
+        "sorf_predict": (ctypes.c_int, [MP, BP, P, P, P, P, P, P, sz, P]),
+        "sorf_validate_batch": (ctypes.c_int, [BP, i32, P, P]),
+    }
+    for name, (res, args) in sig.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def status_string(code: int) -> str:
+    try:
+        return load().sorf_status_string(code).decode()
+    except Exception:  # pragma: no cover - only used for messages
+        return str(code)
+
+
+def check(fn: str, code: int) -> None:
+    if code != SORF_OK:
+        raise SorfError(fn, code)

@@ -1,0 +1,190 @@
+// C ABI entry points: host-side argument validation, then kernel launches on
+// the caller's stream. Nothing here allocates device memory or synchronises.
+#include <cmath>
+#include <cstring>
+
+#include "../../include/sorf.h"
+#include "sorf_internal.h"
+
+namespace {
+
+bool is_pow2(int64_t v) { return v > 0 && (v & (v - 1)) == 0; }
+
+// float4 loads and stores need 16-byte aligned rows
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+constexpr int32_t kMaxSolveD = 32768;
+
+sorf_status check_model(const sorf_model* m) {
+  if (m == nullptr) return SORF_ERR_INVALID_ARG;
+  if (m->d < 2 || m->d > 1024 || !is_pow2(m->d)) return SORF_ERR_INVALID_ARG;
+  if (m->n_stacks < 1 || m->n_elements < 1) return SORF_ERR_INVALID_ARG;
+  if (m->n_transforms < 1 || m->n_transforms > 3) return SORF_ERR_INVALID_ARG;
+  if (!(m->sigma > 0.0f) || !std::isfinite(m->sigma)) return SORF_ERR_INVALID_ARG;
+  if (int64_t(m->d) * m->n_stacks > (int64_t(1) << 20)) return SORF_ERR_INVALID_ARG;
+  if (m->signs == nullptr || m->bias == nullptr) return SORF_ERR_INVALID_ARG;
+  if (!aligned16(m->bias) || (reinterpret_cast<uintptr_t>(m->signs) & 3u)) return SORF_ERR_INVALID_ARG;
+  return SORF_OK;
+}
+
+sorf_status check_batch(const sorf_batch* b) {
+  if (b == nullptr) return SORF_ERR_INVALID_ARG;
+  if (b->n_atoms < 0 || b->n_mols < 0) return SORF_ERR_INVALID_ARG;
+  if (b->n_atoms > (int64_t(1) << 40) || b->n_mols > (int64_t(1) << 31) - 1) return SORF_ERR_INVALID_ARG;
+  if (b->mol_ptr == nullptr) return SORF_ERR_INVALID_ARG;
+  if (b->n_atoms > 0 && (b->x == nullptr || b->element == nullptr)) return SORF_ERR_INVALID_ARG;
+  if (!aligned16(b->x)) return SORF_ERR_INVALID_ARG;
+  return SORF_OK;
+}
+
+SorfFeatureArgs pack(const sorf_model* m, const sorf_batch* b) {
+  SorfFeatureArgs a;
+  a.d = m->d;
+  a.n_stacks = m->n_stacks;
+  a.n_transforms = m->n_transforms;
+  a.n_elements = m->n_elements;
+  a.sigma = m->sigma;
+  a.signs = m->signs;
+  a.bias = m->bias;
+  a.x = b->x;
+  a.element = b->element;
+  a.mol_ptr = b->mol_ptr;
+  a.n_atoms = b->n_atoms;
+  a.n_mols = b->n_mols;
+  return a;
+}
+
+sorf_status dev(hipError_t e) { return e == hipSuccess ? SORF_OK : SORF_ERR_DEVICE; }
+
+size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
+
+size_t predict_ws(const sorf_model* m, int64_t n_atoms) {
+  return align256(sizeof(float) * size_t(n_atoms)) +
+         align256(sizeof(float) * size_t(n_atoms) * size_t(m->d));
+}
+
+}  // namespace
+
+extern "C" {
+
+int32_t sorf_abi_version(void) { return SORF_ABI_VERSION; }
+
+const char* sorf_status_string(sorf_status s) {
+  switch (s) {
+    case SORF_OK: return "SORF_OK";
+    case SORF_ERR_INVALID_ARG: return "SORF_ERR_INVALID_ARG";
+    case SORF_ERR_UNSUPPORTED: return "SORF_ERR_UNSUPPORTED";
+    case SORF_ERR_DEVICE: return "SORF_ERR_DEVICE";
+    case SORF_ERR_WORKSPACE: return "SORF_ERR_WORKSPACE";
+  }
+  return "SORF_ERR_UNKNOWN";
+}
+
+sorf_status sorf_forward(const sorf_model* model, const sorf_batch* batch, float* Z,
+                         sorf_stream_t stream) {
+  sorf_status s = check_model(model);
+  if (s != SORF_OK) return s;
+  if ((s = check_batch(batch)) != SORF_OK) return s;
+  if (batch->n_mols > 0 && Z == nullptr) return SORF_ERR_INVALID_ARG;
+  if (!aligned16(Z)) return SORF_ERR_INVALID_ARG;
+  return dev(sorf_launch_forward(pack(model, batch), Z, hipStream_t(stream)));
+}
+
+sorf_status sorf_backward(const sorf_model* model, const sorf_batch* batch, const float* alpha,
+                          const float* dE, float* grad_x, sorf_stream_t stream) {
+  sorf_status s = check_model(model);
+  if (s != SORF_OK) return s;
+  if ((s = check_batch(batch)) != SORF_OK) return s;
+  if (batch->n_atoms > 0 && (alpha == nullptr || grad_x == nullptr)) return SORF_ERR_INVALID_ARG;
+  if (!aligned16(alpha) || !aligned16(grad_x)) return SORF_ERR_INVALID_ARG;
+  return dev(sorf_launch_atom_adjoint(pack(model, batch), alpha, dE, grad_x, nullptr,
+                                      hipStream_t(stream)));
+}
+
+sorf_status sorf_gram_accumulate(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                                 sorf_gram_precision precision, int32_t scale_exp, float* G,
+                                 float* Zty, sorf_stream_t stream) {
+  if (n_rows < 0 || D < 1 || D > (1 << 20)) return SORF_ERR_INVALID_ARG;
+  if (int(precision) < 0 || int(precision) > 4) return SORF_ERR_INVALID_ARG;
+  if (scale_exp < -60 || scale_exp > 60) return SORF_ERR_INVALID_ARG;
+  if (scale_exp != 0 && precision != SORF_GRAM_FP16 && precision != SORF_GRAM_FP16_HILO)
+    return SORF_ERR_INVALID_ARG;
+  if (G == nullptr) return SORF_ERR_INVALID_ARG;
+  if (n_rows > 0 && Z == nullptr) return SORF_ERR_INVALID_ARG;
+  if (y != nullptr && Zty == nullptr) return SORF_ERR_INVALID_ARG;
+  if (!aligned16(Z)) return SORF_ERR_INVALID_ARG;
+  if (int64_t(D) * D > (int64_t(1) << 36)) return SORF_ERR_UNSUPPORTED;
+  hipStream_t st = hipStream_t(stream);
+  if (n_rows == 0) return SORF_OK;
+  hipError_t e = sorf_launch_gram(n_rows, D, Z, int(precision), scale_exp, G, st);
+  if (e != hipSuccess) return SORF_ERR_DEVICE;
+  if (y != nullptr) e = sorf_launch_zty(n_rows, D, Z, y, Zty, st);
+  return dev(e);
+}
+
+size_t sorf_solve_workspace_bytes(int32_t D) {
+  if (D < 1 || D > kMaxSolveD) return 0;
+  return sorf_solve_ws_bytes(D);
+}
+
+sorf_status sorf_solve(int32_t D, const float* G, const float* Zty, double lambda,
+                       int32_t n_refine, double* alpha, int32_t* info, void* workspace,
+                       size_t workspace_bytes, sorf_stream_t stream) {
+  if (D < 1 || D > kMaxSolveD) return SORF_ERR_INVALID_ARG;
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return SORF_ERR_INVALID_ARG;
+  if (n_refine < 0 || n_refine > 16) return SORF_ERR_INVALID_ARG;
+  if (G == nullptr || Zty == nullptr || alpha == nullptr || info == nullptr)
+    return SORF_ERR_INVALID_ARG;
+  if (workspace == nullptr || workspace_bytes < sorf_solve_ws_bytes(D)) return SORF_ERR_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  return dev(sorf_launch_solve(D, G, Zty, lambda, n_refine, alpha, info, workspace,
+                               hipStream_t(stream)));
+}
+
+size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, int64_t n_mols) {
+  (void)n_mols;
+  if (check_model(model) != SORF_OK || n_atoms < 0) return 0;
+  return predict_ws(model, n_atoms);
+}
+
+sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const float* alpha,
+                         const float* J, const int64_t* J_ptr, float* E, float* F,
+                         void* workspace, size_t workspace_bytes, sorf_stream_t stream) {
+  sorf_status s = check_model(model);
+  if (s != SORF_OK) return s;
+  if ((s = check_batch(batch)) != SORF_OK) return s;
+  if ((J == nullptr) != (J_ptr == nullptr)) return SORF_ERR_INVALID_ARG;
+  if ((J == nullptr) != (F == nullptr)) return SORF_ERR_INVALID_ARG;
+  if (batch->n_mols > 0 && E == nullptr) return SORF_ERR_INVALID_ARG;
+  if (batch->n_atoms > 0 && alpha == nullptr) return SORF_ERR_INVALID_ARG;
+  if (!aligned16(alpha)) return SORF_ERR_INVALID_ARG;
+  const size_t need = predict_ws(model, batch->n_atoms);
+  if (batch->n_atoms > 0) {
+    if (workspace == nullptr || workspace_bytes < need) return SORF_ERR_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  }
+  hipStream_t st = hipStream_t(stream);
+  const SorfFeatureArgs a = pack(model, batch);
+  float* e_atom = static_cast<float*>(workspace);
+  float* grad = reinterpret_cast<float*>(static_cast<char*>(workspace) +
+                                         align256(sizeof(float) * size_t(batch->n_atoms)));
+  hipError_t e = sorf_launch_atom_adjoint(a, alpha, nullptr, J ? grad : nullptr, e_atom, st);
+  if (e != hipSuccess) return SORF_ERR_DEVICE;
+  return dev(sorf_launch_molecule_reduce(a, e_atom, grad, J, J_ptr, E, F, st));
+}
+
+sorf_status sorf_validate_batch(const sorf_batch* batch, int32_t n_elements, int32_t* result,
+                                sorf_stream_t stream) {
+  sorf_status s = check_batch(batch);
+  if (s != SORF_OK) return s;
+  if (n_elements < 1 || result == nullptr) return SORF_ERR_INVALID_ARG;
+  SorfFeatureArgs a{};
+  a.element = batch->element;
+  a.mol_ptr = batch->mol_ptr;
+  a.n_atoms = batch->n_atoms;
+  a.n_mols = batch->n_mols;
+  a.n_elements = n_elements;
+  return dev(sorf_launch_validate(a, result, hipStream_t(stream)));
+}
+
+}  // extern "C"

@@ -1,0 +1,219 @@
+// Internal device helpers and launcher declarations of the SORF library.
+//
+// Data layout of one SORF vector (one atom, one stack) inside a wave64:
+// the d entries are split over K = d / EPL consecutive lanes ("a lane group"),
+// lane q of the group holding entries j = q * EPL + r, r = 0 .. EPL-1, in
+// registers. A wave therefore carries 64 / K vectors at once. The fast
+// Walsh-Hadamard transform (SORF subsection: O(d log d) in-place butterflies)
+// runs its first log2(EPL) stages inside each lane and the last log2(K)
+// stages across the lanes of the group with DPP / swizzle exchanges.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace sorf {
+
+constexpr float kInv2Pi = 0.159154943091895336f;
+
+__device__ __forceinline__ uint32_t lane_id() { return __lane_id(); }
+
+// Value of `x` held by lane (lane ^ (1 << BIT)) of the same wave.
+template <int BIT>
+__device__ __forceinline__ float lane_xor(float x) {
+  int i = __float_as_int(x);
+  if constexpr (BIT == 0) {
+    i = __builtin_amdgcn_mov_dpp(i, 0xB1, 0xF, 0xF, false);   // quad_perm [1,0,3,2]
+  } else if constexpr (BIT == 1) {
+    i = __builtin_amdgcn_mov_dpp(i, 0x4E, 0xF, 0xF, false);   // quad_perm [2,3,0,1]
+  } else if constexpr (BIT <= 4) {
+    // bitmask swizzle inside 32 lanes: and = 0x1f, or = 0, xor = 1 << BIT
+    i = __builtin_amdgcn_ds_swizzle(i, 0x1F | ((1 << BIT) << 10));
+  } else {
+    i = __builtin_amdgcn_ds_bpermute(int((lane_id() ^ 32u) << 2), i);
+  }
+  return __int_as_float(i);
+}
+
+// Butterfly stages of the Hadamard transform over the EPL entries of a lane
+// (index bits 0 .. log2(EPL)-1): (a, b) -> (a + b, a - b), natural order.
+template <int EPL>
+__device__ __forceinline__ void fwht_in_lane(float (&v)[EPL]) {
+#pragma unroll
+  for (int h = 1; h < EPL; h <<= 1) {
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) {
+      if ((i & h) == 0) {
+        const float a = v[i];
+        const float b = v[i + h];
+        v[i] = a + b;
+        v[i + h] = a - b;
+      }
+    }
+  }
+}
+
+// Butterfly stages over the lane bits of the group (index bits log2(EPL) ..).
+// Every lane computes v + m * partner with m = +1 on the low lane of a pair and
+// m = -1 on the high lane. The low lane gets a + b; the high lane gets
+// b - a = -(a - b): its value is carried with a pending sign. After all stages
+// lane q holds (-1)^popcount(q) times the true entries; the caller folds that
+// sign into the next sign diagonal or into the final scale.
+//
+// Inside a quad (lane bits 0 and 1) the exchange and the multiply-add are one
+// v_fmac_f32 with a DPP quad_perm on src0 (v += dpp(v) * m). The compiler does
+// not fuse a separate DPP move into the FMA, hence the inline assembly. The
+// leading s_nop covers the 2 wait states required between a VALU write of a
+// VGPR and a DPP read of it; inside a block every instruction reads a
+// different register than the previous one wrote.
+#define SORF_DPP_FMAC(CTRL, R) \
+  "v_fmac_f32_dpp %" #R ", %" #R ", %16 " CTRL " row_mask:0xf bank_mask:0xf\n\t"
+#define SORF_DPP_BLOCK16(CTRL)                                                                  \
+  "s_nop 1\n\t" SORF_DPP_FMAC(CTRL, 0) SORF_DPP_FMAC(CTRL, 1) SORF_DPP_FMAC(CTRL, 2)           \
+      SORF_DPP_FMAC(CTRL, 3) SORF_DPP_FMAC(CTRL, 4) SORF_DPP_FMAC(CTRL, 5)                      \
+          SORF_DPP_FMAC(CTRL, 6) SORF_DPP_FMAC(CTRL, 7) SORF_DPP_FMAC(CTRL, 8)                  \
+              SORF_DPP_FMAC(CTRL, 9) SORF_DPP_FMAC(CTRL, 10) SORF_DPP_FMAC(CTRL, 11)            \
+                  SORF_DPP_FMAC(CTRL, 12) SORF_DPP_FMAC(CTRL, 13) SORF_DPP_FMAC(CTRL, 14)       \
+                      SORF_DPP_FMAC(CTRL, 15)
+
+template <int BIT>
+__device__ __forceinline__ void dpp_fmac16(float* v, float m) {
+  if constexpr (BIT == 0) {
+    asm volatile(SORF_DPP_BLOCK16("quad_perm:[1,0,3,2]")
+                 : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]),
+                   "+v"(v[6]), "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]),
+                   "+v"(v[12]), "+v"(v[13]), "+v"(v[14]), "+v"(v[15])
+                 : "v"(m));
+  } else {
+    asm volatile(SORF_DPP_BLOCK16("quad_perm:[2,3,0,1]")
+                 : "+v"(v[0]), "+v"(v[1]), "+v"(v[2]), "+v"(v[3]), "+v"(v[4]), "+v"(v[5]),
+                   "+v"(v[6]), "+v"(v[7]), "+v"(v[8]), "+v"(v[9]), "+v"(v[10]), "+v"(v[11]),
+                   "+v"(v[12]), "+v"(v[13]), "+v"(v[14]), "+v"(v[15])
+                 : "v"(m));
+  }
+}
+
+template <int BIT, int LOGK, int EPL>
+__device__ __forceinline__ void fwht_across_lanes(float (&v)[EPL], uint32_t q) {
+  if constexpr (BIT < LOGK) {
+    const float m = ((q >> BIT) & 1u) ? -1.0f : 1.0f;
+    if constexpr (BIT <= 1 && EPL % 16 == 0) {
+#pragma unroll
+      for (int r = 0; r < EPL; r += 16) dpp_fmac16<BIT>(v + r, m);
+    } else {
+#pragma unroll
+      for (int r = 0; r < EPL; ++r) v[r] = __builtin_fmaf(m, lane_xor<BIT>(v[r]), v[r]);
+    }
+    fwht_across_lanes<BIT + 1, LOGK, EPL>(v, q);
+  }
+}
+
+template <int LOGK, int EPL>
+__device__ __forceinline__ void fwht(float (&v)[EPL], uint32_t q) {
+  fwht_in_lane<EPL>(v);
+  fwht_across_lanes<0, LOGK, EPL>(v, q);
+}
+
+// Multiply entry r by -1 when bit r of the lane's sign words is set.
+template <int EPL>
+__device__ __forceinline__ void apply_signs(float (&v)[EPL], const uint32_t* w) {
+#pragma unroll
+  for (int r = 0; r < EPL; ++r) {
+    // shift bit r to bit 31 and xor it into the sign (one shift + one v_bitop3)
+    const uint32_t mask = (w[r >> 5] << (31 - (r & 31))) & 0x80000000u;
+    v[r] = __uint_as_float(__float_as_uint(v[r]) ^ mask);
+  }
+}
+
+// Sign words of one lane for one (element, transform, stack) vector.
+// `vec` points at the W = ceil(d/32) words of the vector.
+template <int EPL>
+__device__ __forceinline__ void load_sign_words(uint32_t (&w)[EPL >= 32 ? EPL / 32 : 1],
+                                                const uint32_t* __restrict__ vec, uint32_t q,
+                                                uint32_t flip) {
+  if constexpr (EPL >= 32) {
+#pragma unroll
+    for (int i = 0; i < EPL / 32; ++i) w[i] = vec[q * (EPL / 32) + i] ^ flip;
+  } else {
+    const uint32_t bit0 = q * EPL;
+    w[0] = (vec[bit0 >> 5] >> (bit0 & 31)) ^ flip;
+  }
+}
+
+template <int EPL>
+__device__ __forceinline__ void load_vec(float (&v)[EPL], const float* __restrict__ p) {
+  if constexpr (EPL % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < EPL / 4; ++i) {
+      const float4 t = reinterpret_cast<const float4*>(p)[i];
+      v[4 * i + 0] = t.x;
+      v[4 * i + 1] = t.y;
+      v[4 * i + 2] = t.z;
+      v[4 * i + 3] = t.w;
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) v[i] = p[i];
+  }
+}
+
+template <int EPL>
+__device__ __forceinline__ void store_vec(float* __restrict__ p, const float (&v)[EPL], float s) {
+  if constexpr (EPL % 4 == 0) {
+#pragma unroll
+    for (int i = 0; i < EPL / 4; ++i) {
+      reinterpret_cast<float4*>(p)[i] =
+          make_float4(v[4 * i] * s, v[4 * i + 1] * s, v[4 * i + 2] * s, v[4 * i + 3] * s);
+    }
+  } else {
+#pragma unroll
+    for (int i = 0; i < EPL; ++i) p[i] = v[i] * s;
+  }
+}
+
+__device__ __forceinline__ int64_t molecule_of(const int64_t* __restrict__ mol_ptr, int64_t n_mols,
+                                               int64_t atom) {
+  // largest m with mol_ptr[m] <= atom (skips empty molecules)
+  int64_t lo = 0, hi = n_mols;  // invariant: mol_ptr[lo] <= atom < mol_ptr[hi]
+  while (hi - lo > 1) {
+    const int64_t mid = (lo + hi) >> 1;
+    if (mol_ptr[mid] <= atom) lo = mid; else hi = mid;
+  }
+  return lo;
+}
+
+}  // namespace sorf
+
+// ---------------------------------------------------------------------------
+// Launchers (host side), implemented in the kernel translation units. Each
+// returns a hipError_t from the launch.
+// ---------------------------------------------------------------------------
+struct SorfFeatureArgs {
+  int32_t d, n_stacks, n_transforms, n_elements;
+  float sigma;
+  const uint32_t* signs;
+  const float* bias;
+  const float* x;
+  const int32_t* element;
+  const int64_t* mol_ptr;
+  int64_t n_atoms, n_mols;
+};
+
+hipError_t sorf_launch_forward(const SorfFeatureArgs& a, float* Z, hipStream_t s);
+hipError_t sorf_launch_atom_adjoint(const SorfFeatureArgs& a, const float* alpha, const float* dE,
+                                    float* grad_x, float* e_atom, hipStream_t s);
+hipError_t sorf_launch_molecule_reduce(const SorfFeatureArgs& a, const float* e_atom,
+                                       const float* grad, const float* J, const int64_t* J_ptr,
+                                       float* E, float* F, hipStream_t s);
+hipError_t sorf_launch_validate(const SorfFeatureArgs& a, int32_t* result, hipStream_t s);
+hipError_t sorf_launch_fill(float* p, int64_t n, float v, hipStream_t s);
+
+hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, int mode, int32_t scale_exp,
+                            float* G, hipStream_t s);
+hipError_t sorf_launch_zty(int64_t n_rows, int32_t D, const float* Z, const float* y, float* Zty,
+                           hipStream_t s);
+
+size_t sorf_solve_ws_bytes(int32_t D);
+hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double lambda,
+                             int32_t n_refine, double* alpha, int32_t* info, void* ws,
+                             hipStream_t s);

@@ -1,0 +1,302 @@
+"""Python layer over the SORF C ABI.
+
+PyTorch supplies device memory and the current HIP stream; every step of the
+computation runs in the HIP library (``libsorf.so``). Tensors passed in must
+already live on the GPU with the documented dtype and be contiguous.
+
+Paper: arXiv 2206.01580, Theory section -- RFF feature map and atomic energy
+decomposition (``forward``/``predict``), regularised normal equation
+(``gram_accumulate``/``solve``), derivative features for forces
+(``backward``/``predict`` with Jacobians), SORF operator with per-element
+sign diagonals and stacking (``Model``).
+"""
+from __future__ import annotations
+
+import ctypes
+import math
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+import torch
+
+from . import _lib
+
+
+def pack_signs(signs_pm1: np.ndarray) -> np.ndarray:
+    """+-1 entries [E, T, S, d] -> uint32 words [E, T, S, ceil(d/32)], bit j of
+    word j // 32 set when entry j is -1."""
+    s = np.asarray(signs_pm1)
+    E, T, S, d = s.shape
+    W = (d + 31) // 32
+    bits = np.zeros((E, T, S, W * 32), dtype=np.uint64)
+    bits[..., :d] = (s < 0)
+    weights = (np.uint64(1) << np.arange(32, dtype=np.uint64))
+    words = (bits.reshape(E, T, S, W, 32) * weights).sum(axis=-1)
+    return words.astype(np.uint32)
+
+
+def _ptr(t: Optional[torch.Tensor]) -> Optional[int]:
+    return None if t is None else t.data_ptr()
+
+
+def _stream() -> int:
+    return torch.cuda.current_stream().cuda_stream
+
+
+def _need(t: torch.Tensor, dtype, name: str, numel: Optional[int] = None):
+    if not isinstance(t, torch.Tensor) or t.device.type != "cuda":
+        raise TypeError(f"{name} must be a GPU tensor")
+    if t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}, got {t.dtype}")
+    if not t.is_contiguous():
+        raise ValueError(f"{name} must be contiguous")
+    if numel is not None and t.numel() != numel:
+        raise ValueError(f"{name} must have {numel} elements, got {t.numel()}")
+
+
+@dataclass
+class Model:
+    """Resident SORF parameters: packed sign diagonals and phases on the GPU."""
+
+    d: int
+    n_stacks: int
+    n_transforms: int
+    n_elements: int
+    sigma: float
+    signs: torch.Tensor   # int32 view of the packed uint32 words
+    bias: torch.Tensor    # float32 [E, D]
+
+    @property
+    def n_features(self) -> int:
+        return self.d * self.n_stacks
+
+    @classmethod
+    def from_arrays(cls, signs_pm1: np.ndarray, bias: np.ndarray, sigma: float,
+                    device="cuda") -> "Model":
+        E, T, S, d = signs_pm1.shape
+        packed = pack_signs(signs_pm1)
+        return cls(d, S, T, E, float(sigma),
+                   torch.from_numpy(packed.view(np.int32)).to(device).contiguous(),
+                   torch.from_numpy(np.ascontiguousarray(bias, dtype=np.float32)).to(device))
+
+    @classmethod
+    def from_problem(cls, p, device="cuda") -> "Model":
+        return cls.from_arrays(p.signs, p.bias, p.sigma, device)
+
+    def c_struct(self) -> _lib.SorfModel:
+        return _lib.SorfModel(self.d, self.n_stacks, self.n_transforms, self.n_elements,
+                              self.sigma, self.signs.data_ptr(), self.bias.data_ptr())
+
+
+@dataclass
+class Batch:
+    """Molecules in CSR form on the GPU."""
+
+    x: torch.Tensor         # float32 [A, d]
+    element: torch.Tensor   # int32 [A]
+    mol_ptr: torch.Tensor   # int64 [M + 1]
+
+    @property
+    def n_atoms(self) -> int:
+        return int(self.x.shape[0])
+
+    @property
+    def n_mols(self) -> int:
+        return int(self.mol_ptr.shape[0] - 1)
+
+    @classmethod
+    def from_arrays(cls, x, element, mol_ptr, device="cuda") -> "Batch":
+        return cls(torch.as_tensor(np.ascontiguousarray(x, dtype=np.float32)).to(device),
+                   torch.as_tensor(np.ascontiguousarray(element, dtype=np.int32)).to(device),
+                   torch.as_tensor(np.ascontiguousarray(mol_ptr, dtype=np.int64)).to(device))
+
+    @classmethod
+    def from_problem(cls, p, device="cuda") -> "Batch":
+        return cls.from_arrays(p.x, p.element, p.mol_ptr, device)
+
+    def c_struct(self, x: Optional[torch.Tensor] = None) -> _lib.SorfBatch:
+        xx = self.x if x is None else x
+        return _lib.SorfBatch(xx.data_ptr() if xx.numel() else None,
+                              self.element.data_ptr() if self.element.numel() else None,
+                              self.mol_ptr.data_ptr(), self.n_atoms, self.n_mols)
+
+    def check(self, model: Model):
+        _need(self.x, torch.float32, "x", self.n_atoms * model.d)
+        _need(self.element, torch.int32, "element", self.n_atoms)
+        _need(self.mol_ptr, torch.int64, "mol_ptr")
+
+
+def forward(model: Model, batch: Batch, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """Z [n_mols, D] (sorf_forward)."""
+    batch.check(model)
+    D = model.n_features
+    if out is None:
+        out = torch.empty((batch.n_mols, D), dtype=torch.float32, device=batch.x.device)
+    _need(out, torch.float32, "Z", batch.n_mols * D)
+    lib = _lib.load()
+    m, b = model.c_struct(), batch.c_struct()
+    _lib.check("sorf_forward", lib.sorf_forward(ctypes.byref(m), ctypes.byref(b),
+                                                _ptr(out), _stream()))
+    return out
+
+
+def backward(model: Model, batch: Batch, alpha: torch.Tensor, dE: Optional[torch.Tensor] = None,
+             out: Optional[torch.Tensor] = None, x: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dL/dx [n_atoms, d] for L = sum_m dE_m E_m (sorf_backward)."""
+    batch.check(model)
+    _need(alpha, torch.float32, "alpha", model.n_features)
+    if dE is not None:
+        _need(dE, torch.float32, "dE", batch.n_mols)
+    xx = batch.x if x is None else x
+    _need(xx, torch.float32, "x", batch.n_atoms * model.d)
+    if out is None:
+        out = torch.empty((batch.n_atoms, model.d), dtype=torch.float32, device=xx.device)
+    _need(out, torch.float32, "grad_x", batch.n_atoms * model.d)
+    lib = _lib.load()
+    m, b = model.c_struct(), batch.c_struct(xx)
+    _lib.check("sorf_backward", lib.sorf_backward(ctypes.byref(m), ctypes.byref(b), _ptr(alpha),
+                                                  _ptr(dE), _ptr(out), _stream()))
+    return out
+
+
+def gram_accumulate(Z: torch.Tensor, G: torch.Tensor, y: Optional[torch.Tensor] = None,
+                    Zty: Optional[torch.Tensor] = None, precision: str = "fp32",
+                    scale_exp: int = 0) -> None:
+    """G += Z^T Z on the lower triangle; Zty += Z^T y (sorf_gram_accumulate)."""
+    M, D = Z.shape
+    _need(Z, torch.float32, "Z")
+    _need(G, torch.float32, "G", D * D)
+    if y is not None:
+        _need(y, torch.float32, "y", M)
+        _need(Zty, torch.float32, "Zty", D)
+    lib = _lib.load()
+    _lib.check("sorf_gram_accumulate", lib.sorf_gram_accumulate(
+        M, D, _ptr(Z), _ptr(y), _lib.GRAM_MODES[precision], scale_exp, _ptr(G), _ptr(Zty),
+        _stream()))
+
+
+def fp16_scale_exp(max_abs: float) -> int:
+    """Power-of-two exponent that brings |Z| <= max_abs to at most 2^14, so the
+    fp16 hi part stays finite and the lo part keeps its precision."""
+    if max_abs <= 0.0:
+        return 0
+    return int(max(-60, min(60, math.floor(14 - math.log2(max_abs)))))
+
+
+class Solver:
+    """Owns the FP64 workspace of sorf_solve for one system size."""
+
+    def __init__(self, D: int, device="cuda"):
+        lib = _lib.load()
+        self.D = D
+        nbytes = lib.sorf_solve_workspace_bytes(D)
+        if nbytes == 0:
+            raise ValueError(f"unsupported system size {D}")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        self.ws_off = (-self.ws.data_ptr()) % 256
+        self.nbytes = nbytes
+        self.info = torch.zeros(1, dtype=torch.int32, device=device)
+
+    def __call__(self, G: torch.Tensor, Zty: torch.Tensor, lam: float, n_refine: int = 3,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        D = self.D
+        _need(G, torch.float32, "G", D * D)
+        _need(Zty, torch.float32, "Zty", D)
+        if out is None:
+            out = torch.empty(D, dtype=torch.float64, device=G.device)
+        _need(out, torch.float64, "alpha", D)
+        lib = _lib.load()
+        _lib.check("sorf_solve", lib.sorf_solve(
+            D, _ptr(G), _ptr(Zty), float(lam), int(n_refine), _ptr(out), _ptr(self.info),
+            self.ws.data_ptr() + self.ws_off, self.nbytes, _stream()))
+        return out
+
+
+def solve(G: torch.Tensor, Zty: torch.Tensor, lam: float, n_refine: int = 3):
+    """alpha (FP64) and the LAPACK-style info flag (device tensor)."""
+    s = Solver(Zty.numel(), device=G.device)
+    a = s(G, Zty, lam, n_refine)
+    return a, s.info
+
+
+class Predictor:
+    """Energies and forces without forming Z (sorf_predict); owns its workspace."""
+
+    def __init__(self, model: Model, device="cuda"):
+        self.model = model
+        self.device = device
+        self.ws = torch.empty(0, dtype=torch.uint8, device=device)
+
+    def _workspace(self, n_atoms: int, n_mols: int):
+        lib = _lib.load()
+        m = self.model.c_struct()
+        need = lib.sorf_predict_workspace_bytes(ctypes.byref(m), n_atoms, n_mols)
+        if self.ws.numel() < need + 256:
+            self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        return self.ws.data_ptr() + off, need
+
+    def __call__(self, batch: Batch, alpha: torch.Tensor, J: Optional[torch.Tensor] = None,
+                 J_ptr: Optional[torch.Tensor] = None, E: Optional[torch.Tensor] = None,
+                 F: Optional[torch.Tensor] = None):
+        model = self.model
+        batch.check(model)
+        _need(alpha, torch.float32, "alpha", model.n_features)
+        dev = batch.x.device
+        if E is None:
+            E = torch.empty(batch.n_mols, dtype=torch.float32, device=dev)
+        _need(E, torch.float32, "E", batch.n_mols)
+        if J is not None:
+            _need(J, torch.float32, "J")
+            _need(J_ptr, torch.int64, "J_ptr", batch.n_mols + 1)
+            if F is None:
+                F = torch.empty(3 * batch.n_atoms, dtype=torch.float32, device=dev)
+            _need(F, torch.float32, "F", 3 * batch.n_atoms)
+        ws, nbytes = self._workspace(batch.n_atoms, batch.n_mols)
+        lib = _lib.load()
+        m, b = model.c_struct(), batch.c_struct()
+        _lib.check("sorf_predict", lib.sorf_predict(
+            ctypes.byref(m), ctypes.byref(b), _ptr(alpha), _ptr(J), _ptr(J_ptr), _ptr(E),
+            _ptr(F if J is not None else None), ws, nbytes, _stream()))
+        return (E, F) if J is not None else E
+
+
+def predict(model: Model, batch: Batch, alpha: torch.Tensor, J=None, J_ptr=None):
+    return Predictor(model, batch.x.device)(batch, alpha, J, J_ptr)
+
+
+def validate_batch(batch: Batch, n_elements: int) -> int:
+    """Device-side CSR / element-range check; returns the flag word (0 = valid)."""
+    res = torch.zeros(1, dtype=torch.int32, device=batch.x.device)
+    lib = _lib.load()
+    b = batch.c_struct()
+    _lib.check("sorf_validate_batch", lib.sorf_validate_batch(ctypes.byref(b), n_elements,
+                                                              _ptr(res), _stream()))
+    return int(res.item())
+
+
+class SorfEnergy(torch.autograd.Function):
+    """E = Z(x) alpha as a differentiable function of x.
+
+    forward: sorf_predict (energies, no Z materialised);
+    backward: sorf_backward with the incoming dL/dE as upstream weights."""
+
+    @staticmethod
+    def forward(ctx, x: torch.Tensor, model: Model, batch: Batch, alpha: torch.Tensor):
+        b = Batch(x.detach().contiguous(), batch.element, batch.mol_ptr)
+        E = Predictor(model, x.device)(b, alpha)
+        ctx.save_for_backward(x, alpha)
+        ctx.model, ctx.batch = model, batch
+        return E
+
+    @staticmethod
+    def backward(ctx, grad_E: torch.Tensor):
+        x, alpha = ctx.saved_tensors
+        b = Batch(x.detach().contiguous(), ctx.batch.element, ctx.batch.mol_ptr)
+        g = backward(ctx.model, b, alpha, dE=grad_E.contiguous().float())
+        return g, None, None, None
+
+
+def energy(x: torch.Tensor, model: Model, batch: Batch, alpha: torch.Tensor) -> torch.Tensor:
+    return SorfEnergy.apply(x, model, batch, alpha)

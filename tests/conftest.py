@@ -13,6 +13,11 @@ def pytest_configure(config):
     config.addinivalue_line("markers", "slow: long-running CPU test")
 
 
-def pytest_collection_modifyitems(config, items):
-    # GPU tests need a device; fail loudly instead of silently falling back.
-    pass
+@pytest.fixture(autouse=True)
+def _announce_gpu_case(request):
+    """Name each GPU test on the real stderr before it runs, so that a run that
+    dies inside a kernel still says which case it was in."""
+    if request.node.get_closest_marker("gpu") is not None:
+        sys.__stderr__.write(f"[gpu-case] {request.node.nodeid}\n")
+        sys.__stderr__.flush()
+    yield

@@ -1,0 +1,325 @@
+"""GPU parity: the HIP path (through the C ABI) against the FP64 oracle.
+
+Tolerances (FP32 kernels vs FP64 oracle):
+  Z      per molecule row, max_f |dZ| <= 1e-5 * max_f |Z_ora| (rows of empty molecules exactly 0)
+  grad   per atom, max_j |dg| <= 1e-5 * max_j |g_ora|
+  E      |dE_m| <= 1e-5 * sum_f |alpha_f Z_ora[m, f]|
+  F      per molecule, max |dF| <= 1e-5 * max |F_ora|
+  G      ||dG||_F / ||G||_F <= 1e-6 against the oracle's emulation of the same precision mode
+The normwise reading of the feature tolerance: FP32 cos near its zeros makes
+elementwise relative error meaningless, while the row max sets the scale the
+features are used at.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sorf_oracle as O
+from paper_2206_01580_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2206_01580_amd import _lib
+    _lib.load()  # fails loudly if the HIP library is not built
+    yield
+
+
+def S():
+    from paper_2206_01580_amd import sorf
+    return sorf
+
+
+def dev_problem(p):
+    s = S()
+    return s.Model.from_problem(p), s.Batch.from_problem(p)
+
+
+def check_rows(Zg, Zo, tol=1e-5):
+    Zg = np.asarray(Zg, dtype=np.float64)
+    scale = np.abs(Zo).max(axis=1)
+    err = np.abs(Zg - Zo).max(axis=1) if Zo.shape[1] else np.zeros(len(Zo))
+    empty = scale == 0
+    assert np.all(Zg[empty] == 0.0)
+    bad = err[~empty] > tol * scale[~empty]
+    assert not bad.any(), f"max rel row err {np.max(err[~empty] / scale[~empty]):.3e}"
+    return float(np.max(err[~empty] / scale[~empty])) if (~empty).any() else 0.0
+
+
+def gpu_forward(p):
+    model, batch = dev_problem(p)
+    Z = S().forward(model, batch)
+    torch.cuda.synchronize()
+    return Z.cpu().numpy()
+
+
+def oracle_forward(p, mols=None):
+    return O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, mols)
+
+
+# ------------------------------------------------------------------ forward
+def test_forward_config1():
+    p = W.config1()
+    rel = check_rows(gpu_forward(p), oracle_forward(p))
+    print(f"config1 forward max normwise row error {rel:.2e}")
+
+
+SHAPES = [  # (d, n_stacks, T, n_elements, n_mols, min_atoms, max_atoms)
+    (2, 3, 1, 2, 9, 0, 5), (4, 5, 2, 3, 11, 0, 7), (8, 7, 3, 2, 6, 1, 9), (16, 3, 3, 4, 13, 0, 6),
+    (32, 9, 2, 3, 7, 0, 8), (64, 4, 3, 4, 10, 1, 12), (64, 33, 1, 2, 5, 0, 9),
+    (128, 16, 3, 5, 9, 0, 14), (128, 21, 2, 3, 6, 1, 30), (256, 6, 3, 3, 5, 0, 9),
+    (512, 3, 3, 2, 4, 1, 5), (1024, 2, 2, 2, 3, 1, 4),
+]
+
+
+@pytest.mark.parametrize("shape", SHAPES, ids=lambda s: "d{}-S{}-T{}-E{}-M{}".format(*s[:5]))
+def test_forward_random_shapes(shape):
+    d, S_, T, E, M, lo, hi = shape
+    p = W.random_problem(1000 + d + S_ + T, d, S_, T, E, M, hi, lo)
+    check_rows(gpu_forward(p), oracle_forward(p))
+
+
+def test_forward_all_empty_and_no_molecules():
+    p = W.random_problem(5, 64, 2, 3, 2, 4, 0, 0)
+    assert p.n_atoms == 0
+    Z = gpu_forward(p)
+    assert Z.shape == (4, 128) and np.all(Z == 0.0)
+    q = p.subset([])
+    assert gpu_forward(q).shape == (0, 128)
+
+
+def test_forward_large_phases():
+    # big |x| / small sigma: phases of many revolutions
+    p = W.random_problem(77, 128, 4, 3, 3, 5, 6, 1, sigma=0.05, x_scale=3.0)
+    check_rows(gpu_forward(p), oracle_forward(p), tol=2e-5)
+
+
+def test_forward_deterministic():
+    p = W.random_problem(8, 128, 8, 3, 3, 20, 12, 1)
+    model, batch = dev_problem(p)
+    a = S().forward(model, batch)
+    b = S().forward(model, batch)
+    torch.cuda.synchronize()
+    assert torch.equal(a, b)
+
+
+# ------------------------------------------------------------------ backward
+@pytest.mark.parametrize("shape", [(4, 3, 2, 2, 5, 0, 4), (32, 5, 3, 3, 6, 1, 6),
+                                   (64, 7, 1, 2, 4, 1, 5), (128, 20, 3, 4, 5, 0, 7),
+                                   (256, 4, 3, 2, 3, 1, 4), (1024, 2, 3, 2, 2, 1, 3)],
+                         ids=lambda s: "d{}-S{}-T{}".format(*s[:3]))
+def test_backward_random_shapes(shape):
+    d, S_, T, E, M, lo, hi = shape
+    p = W.random_problem(2000 + d + S_, d, S_, T, E, M, hi, lo)
+    model, batch = dev_problem(p)
+    alpha = torch.from_numpy(p.alpha).cuda()
+    dE = np.random.default_rng(d).standard_normal(M).astype(np.float32)
+    g = S().backward(model, batch, alpha, torch.from_numpy(dE).cuda())
+    torch.cuda.synchronize()
+    go = O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.alpha, dE)
+    check_rows(g.cpu().numpy(), go)
+
+
+def test_backward_config3_subset():
+    p = W.config3(n_conf=24, with_J=False)
+    model, batch = dev_problem(p)
+    alpha = torch.from_numpy(p.alpha).cuda()
+    g = S().backward(model, batch, alpha)
+    torch.cuda.synchronize()
+    go = O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.alpha)
+    rel = check_rows(g.cpu().numpy(), go)
+    print(f"config3 grad max normwise atom error {rel:.2e}")
+
+
+# ------------------------------------------------------------------ predict
+def _check_energy(Eg, p, alpha):
+    Zo = oracle_forward(p)
+    Eo = Zo @ alpha.astype(np.float64)
+    scale = np.abs(Zo * alpha[None, :]).sum(axis=1)
+    err = np.abs(np.asarray(Eg, np.float64) - Eo)
+    assert np.all(err <= 1e-5 * np.maximum(scale, 1e-30)), float(np.max(err / np.maximum(scale, 1e-30)))
+
+
+@pytest.mark.parametrize("shape", [(8, 3, 3, 2, 7, 0, 5), (64, 4, 3, 3, 9, 1, 10),
+                                   (128, 16, 3, 5, 6, 0, 9), (256, 3, 2, 2, 4, 1, 6)],
+                         ids=lambda s: "d{}-S{}-T{}".format(*s[:3]))
+def test_predict_energies_and_forces(shape):
+    d, S_, T, E, M, lo, hi = shape
+    p = W.random_problem(3000 + d, d, S_, T, E, M, hi, lo, with_J=True)
+    model, batch = dev_problem(p)
+    alpha = torch.from_numpy(p.alpha).cuda()
+    En = S().predict(model, batch, alpha)
+    Ef, F = S().predict(model, batch, alpha, torch.from_numpy(p.J).cuda(),
+                        torch.from_numpy(p.J_ptr).cuda())
+    torch.cuda.synchronize()
+    _check_energy(En.cpu().numpy(), p, p.alpha)
+    assert torch.equal(En, Ef)
+    go = O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.alpha)
+    Fo = O.forces(go, p.J, p.J_ptr, p.mol_ptr)
+    Fg = F.cpu().numpy().astype(np.float64)
+    for m in range(p.n_mols):
+        a0, a1 = 3 * p.mol_ptr[m], 3 * p.mol_ptr[m + 1]
+        if a1 > a0:
+            assert np.abs(Fg[a0:a1] - Fo[a0:a1]).max() <= 1e-5 * np.abs(Fo[a0:a1]).max()
+
+
+def test_predict_config3_subset_with_jacobians():
+    p = W.config3(n_conf=6)
+    model, batch = dev_problem(p)
+    alpha = torch.from_numpy(p.alpha).cuda()
+    E, F = S().predict(model, batch, alpha, torch.from_numpy(p.J).cuda(), torch.from_numpy(p.J_ptr).cuda())
+    torch.cuda.synchronize()
+    _check_energy(E.cpu().numpy(), p, p.alpha)
+    go = O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.alpha)
+    Fo = O.forces(go, p.J, p.J_ptr, p.mol_ptr)
+    Fg = F.cpu().numpy()
+    for m in range(p.n_mols):
+        sl = slice(3 * p.mol_ptr[m], 3 * p.mol_ptr[m + 1])
+        assert np.abs(Fg[sl] - Fo[sl]).max() <= 1e-5 * np.abs(Fo[sl]).max()
+
+
+def test_autograd_function_matches_central_differences():
+    """SorfEnergy backward vs FP64 central differences of the oracle energy."""
+    p = W.random_problem(4242, 16, 3, 3, 2, 2, 3, 2)
+    model, batch = dev_problem(p)
+    alpha = torch.from_numpy(p.alpha).cuda()
+    x = batch.x.clone().requires_grad_(True)
+    w = torch.tensor([0.7, -1.3], device="cuda")
+    E = S().energy(x, model, batch, alpha)
+    (E * w).sum().backward()
+    g = x.grad.cpu().numpy().astype(np.float64)
+    h = 1e-4
+    xs = p.x.astype(np.float64)
+    fd = np.zeros_like(xs)
+    for i in range(xs.shape[0]):
+        for j in range(xs.shape[1]):
+            for sgn in (1, -1):
+                xx = xs.copy()
+                xx[i, j] += sgn * h
+                Z = O.molecule_features(xx, p.element, p.mol_ptr, p.signs, p.bias, p.sigma)
+                fd[i, j] += sgn * float(np.array([0.7, -1.3]) @ (Z @ p.alpha.astype(np.float64))) / (2 * h)
+    assert np.abs(g - fd).max() <= 1e-5 * np.abs(fd).max()
+
+
+# ------------------------------------------------------------------ Gram
+@pytest.mark.parametrize("mode", ["fp32", "bf16", "fp16", "bf16_hilo", "fp16_hilo"])
+@pytest.mark.parametrize("MD", [(333, 300), (64, 128), (1000, 37), (5, 257)], ids=lambda t: f"M{t[0]}-D{t[1]}")
+def test_gram_against_emulated_modes(mode, MD):
+    M, D = MD
+    rng = np.random.default_rng(M + D)
+    Z = (rng.standard_normal((M, D)) * 0.05).astype(np.float32)
+    y = rng.standard_normal(M).astype(np.float32)
+    k = S().fp16_scale_exp(float(np.abs(Z).max())) if mode.startswith("fp16") else 0
+    G0 = rng.standard_normal((D, D)).astype(np.float32)  # accumulate onto existing values
+    Zt, Gt = torch.from_numpy(Z).cuda(), torch.from_numpy(G0.copy()).cuda()
+    Zty = torch.zeros(D, device="cuda")
+    S().gram_accumulate(Zt, Gt, torch.from_numpy(y).cuda(), Zty, precision=mode, scale_exp=k)
+    torch.cuda.synchronize()
+    Gg = Gt.cpu().numpy().astype(np.float64)
+    upper = np.triu_indices(D, 1)
+    assert np.array_equal(Gg[upper], G0[upper].astype(np.float64)), "upper triangle touched"
+    Ge = O.gram_emulated(Z, mode, k)
+    low = np.tril_indices(D)
+    diff = (Gg - G0.astype(np.float64))[low] - Ge[low]
+    assert np.linalg.norm(diff) <= 1e-6 * np.linalg.norm(Ge[low]) + 1e-6 * np.linalg.norm(G0)
+    _, r = O.gram(Z, y)
+    assert np.abs(Zty.cpu().numpy() - r).max() <= 1e-6 * np.abs(Z).sum(axis=0).max() * np.abs(y).max()
+
+
+def test_gram_deterministic():
+    rng = np.random.default_rng(1)
+    Z = torch.from_numpy((rng.standard_normal((700, 384)) * 0.1).astype(np.float32)).cuda()
+    outs = []
+    for _ in range(2):
+        G = torch.zeros(384, 384, device="cuda")
+        S().gram_accumulate(Z, G, precision="bf16_hilo")
+        outs.append(G)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+
+
+# ------------------------------------------------------------------ solve
+@pytest.mark.parametrize("D", [1, 50, 64, 200, 513])
+def test_solve_matches_oracle(D):
+    rng = np.random.default_rng(D)
+    Z = rng.standard_normal((2 * D + 10, D)).astype(np.float32)
+    G = (Z.astype(np.float64).T @ Z.astype(np.float64)).astype(np.float32)
+    rhs = rng.standard_normal(D).astype(np.float32)
+    lam = 1e-3
+    a, info = S().solve(torch.from_numpy(G).cuda(), torch.from_numpy(rhs).cuda(), lam, 3)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    ao = O.solve(np.tril(G) + np.tril(G, -1).T, rhs, lam)
+    assert np.abs(a.cpu().numpy() - ao).max() <= 1e-10 * np.abs(ao).max()
+
+
+def test_solve_reads_only_lower_triangle():
+    D = 130
+    rng = np.random.default_rng(3)
+    Z = rng.standard_normal((300, D)).astype(np.float32)
+    G = (Z.T.astype(np.float64) @ Z).astype(np.float32)
+    junk = G.copy()
+    junk[np.triu_indices(D, 1)] = np.nan
+    rhs = rng.standard_normal(D).astype(np.float32)
+    a1, i1 = S().solve(torch.from_numpy(G).cuda(), torch.from_numpy(rhs).cuda(), 1e-2, 2)
+    a2, i2 = S().solve(torch.from_numpy(junk).cuda(), torch.from_numpy(rhs).cuda(), 1e-2, 2)
+    torch.cuda.synchronize()
+    assert int(i1.item()) == 0 and int(i2.item()) == 0
+    assert torch.equal(a1, a2)
+
+
+def test_solve_reports_non_spd():
+    D = 100
+    G = np.eye(D, dtype=np.float32)
+    G[70, 70] = -5.0
+    a, info = S().solve(torch.from_numpy(G).cuda(), torch.ones(D, device="cuda"), 0.0, 0)
+    torch.cuda.synchronize()
+    assert int(info.item()) == 71
+
+
+# ------------------------------------------------------------------ end to end
+def test_end_to_end_config1_energies():
+    """forward -> Gram (FP32) -> FP64 solve -> predict, against the oracle
+    pipeline; judged on energies (config 1 is rank deficient: N=200 < D=256)."""
+    p = W.config1()
+    s = S()
+    model, batch = dev_problem(p)
+    D = p.n_features
+    Z = s.forward(model, batch)
+    G = torch.zeros(D, D, device="cuda")
+    Zty = torch.zeros(D, device="cuda")
+    y = torch.from_numpy(p.y).cuda()
+    s.gram_accumulate(Z, G, y, Zty, "fp32")
+    a, info = s.solve(G, Zty, p.lam, 3)
+    E = s.predict(model, batch, a.float())
+    torch.cuda.synchronize()
+    assert int(info.item()) == 0
+    Zo = oracle_forward(p)
+    Go, ro = O.gram(Zo, p.y)
+    ao = O.solve(Go, ro, p.lam)
+    Eo = Zo @ ao
+    Eg = E.cpu().numpy().astype(np.float64)
+    rel = np.abs(Eg - Eo).max() / np.abs(Eo).max()
+    print(f"config1 end-to-end energy max rel error {rel:.2e}; fit rmse {np.sqrt(np.mean((Eo - p.y) ** 2)):.3e}")
+    assert rel <= 1e-3
+
+
+# ------------------------------------------------------------------ validation kernel
+def test_validate_batch_flags():
+    s = S()
+    p = W.random_problem(9, 8, 2, 3, 3, 5, 4, 1)
+    _, batch = dev_problem(p)
+    assert s.validate_batch(batch, 3) == 0
+    assert s.validate_batch(batch, 2) & 8 or (p.element < 2).all()
+    bad_ptr = p.mol_ptr.copy()
+    bad_ptr[2] = bad_ptr[3] + 1          # offsets decrease from index 2 to 3
+    b2 = s.Batch.from_arrays(p.x, p.element, bad_ptr)
+    assert s.validate_batch(b2, 3) & 2
+    b3 = s.Batch.from_arrays(p.x, p.element, p.mol_ptr + 1)
+    assert s.validate_batch(b3, 3) & 1
