@@ -1,0 +1,228 @@
+"""Benchmark of the SORF hot path on one MI355X.
+
+One step = one pass of the whole training + inference path over the QM9-like
+workload (20,000 molecules of 3..29 atoms, d = 128, 64 stacks -> D = 8192,
+sigma = 4): features Z (sorf_forward), normal equations G += Z^T Z, Zty += Z^T y
+(sorf_gram_accumulate), FP64 ridge solve with 3 refinement steps (sorf_solve),
+energies E = Z alpha without forming Z (sorf_predict) and dE/dx for every atom
+(sorf_backward). Inputs are synthetic, seeded, and resident in HBM before the
+clock starts.
+
+Prints one JSON line (rank 0, N = 1 only).
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+if ROOT not in sys.path:
+    sys.path.insert(0, ROOT)
+
+# MI355X published peaks
+PEAK_HBM_GBS = 8000.0
+PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16_hilo": 2500.0,
+                    "fp16_hilo": 2500.0, "fp64": 78.6}
+# VALU issue ceiling derived from unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
+# = 39.3 T lane-instructions/s (packed FP32, which would double it, is disabled in this build)
+PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
+
+
+def valu_slots_per_feature(d: int, T: int, backward: bool = False) -> float:
+    """Algorithmic VALU issue slots per atom-feature. Forward: T log2(d)
+    butterfly add/subs + T sign flips + 1 phase FMA + 1 accumulate + one
+    transcendental (quarter rate = 4 slots). Fused forward+backward: twice the
+    transform work, cos and sin, and 2 more FMAs (alpha weighting)."""
+    lg = math.log2(d)
+    fwd = T * lg + T + 1 + 4 + 1
+    if not backward:
+        return fwd
+    return 2 * (T * lg + T) + 1 + 8 + 3
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=2)
+    ap.add_argument("--gram", default="fp32", choices=list(PEAK_MFMA_TFLOPS))
+    ap.add_argument("--n-mols", type=int, default=20000)
+    ap.add_argument("--n-refine", type=int, default=3)
+    ap.add_argument("--lam", type=float, default=1e-6)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-sample-mols", type=int, default=64)
+    return ap.parse_args()
+
+
+def cpu_baseline(p, D, n_sample, lam):
+    """The FP64 oracle (dense W) on the host cores: per-molecule work (features,
+    Gram rows, energies, dE/dx) timed on a sample of molecules and scaled to the
+    full batch, plus one full-size FP64 solve. Returns atom-features/s."""
+    from oracle import sorf_oracle as O
+    threads = len(os.sched_getaffinity(0))
+    rng = np.random.default_rng(0)
+    mols = np.sort(rng.choice(p.n_mols, size=n_sample, replace=False))
+    q = p.subset(mols)
+    alpha = rng.standard_normal(D)
+    t0 = time.perf_counter()
+    Z = O.molecule_features(q.x, q.element, q.mol_ptr, q.signs, q.bias, q.sigma)
+    G, r = O.gram(Z, q.y)
+    O.predict_energies(Z, alpha)
+    O.grad_x(q.x, q.element, q.mol_ptr, q.signs, q.bias, q.sigma, alpha)
+    t_mol = time.perf_counter() - t0
+    # one full-size solve on a well-conditioned SPD matrix of the same size
+    A = G + (np.abs(G).max() + 1.0) * np.eye(D)
+    t1 = time.perf_counter()
+    O.solve(A, r, lam)
+    t_solve = time.perf_counter() - t1
+    t_step = t_mol * (p.n_mols / n_sample) + t_solve
+    af = float(p.n_atoms) * D
+    return {"value": af / t_step, "unit": "atom-features/s", "cores": threads, "kind": "oracle",
+            "sample": (f"FP64 dense-W oracle on {n_sample} of {p.n_mols} molecules "
+                       f"({q.n_atoms} atoms; features, Gram rows, energies, dE/dx: {t_mol:.2f} s, "
+                       f"scaled x{p.n_mols / n_sample:.1f}) + one full D={D} Cholesky solve "
+                       f"({t_solve:.2f} s)")}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py: this build runs on one GPU only (the sharded design is described in "
+              "DESIGN.md); use --gpus 1", file=sys.stderr)
+        sys.exit(2)
+    import torch
+
+    from paper_2206_01580_amd import sorf, workloads
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    t_gen = time.perf_counter()
+    p = workloads.config2(n_mols=args.n_mols)
+    gen_s = time.perf_counter() - t_gen
+    D, A, M = p.n_features, p.n_atoms, p.n_mols
+    model, batch = sorf.Model.from_problem(p), sorf.Batch.from_problem(p)
+    y = torch.from_numpy(p.y).to(dev)
+    acc_t = torch.float64 if args.gram == "fp64" else torch.float32
+    Z = torch.empty(M, D, device=dev)
+    G = torch.empty(D, D, device=dev, dtype=acc_t)
+    Zty = torch.empty(D, device=dev, dtype=acc_t)
+    solver = sorf.Solver(D, device=dev)
+    alpha = torch.empty(D, device=dev, dtype=torch.float64)
+    predictor = sorf.Predictor(model, dev)
+    E = torch.empty(M, device=dev)
+    grad = torch.empty(A, p.d, device=dev)
+    scale_exp = sorf.fp16_scale_exp(29 * math.sqrt(2.0 / D)) if args.gram.startswith("fp16") else 0
+    torch.cuda.synchronize()
+
+    phases = ["forward", "gram", "solve", "predict", "backward"]
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in phases}
+    times = {k: [] for k in phases}
+
+    def step(record: bool):
+        def mark(k, i):
+            if record:
+                ev[k][i].record()
+        mark("forward", 0)
+        sorf.forward(model, batch, out=Z)
+        mark("forward", 1)
+        G.zero_()
+        Zty.zero_()
+        mark("gram", 0)
+        sorf.gram_accumulate(Z, G, y, Zty, precision=args.gram, scale_exp=scale_exp)
+        mark("gram", 1)
+        mark("solve", 0)
+        solver(G, Zty, args.lam, args.n_refine, out=alpha)
+        mark("solve", 1)
+        a32 = alpha.float()
+        mark("predict", 0)
+        predictor(batch, a32, E=E)
+        mark("predict", 1)
+        mark("backward", 0)
+        sorf.backward(model, batch, a32, out=grad)
+        mark("backward", 1)
+
+    for _ in range(args.warmup):
+        step(False)
+    torch.cuda.synchronize()
+    info = int(solver.info.item())
+
+    t0 = time.perf_counter()
+    for _ in range(args.steps):
+        step(True)
+        torch.cuda.synchronize()
+        for k in phases:
+            times[k].append(ev[k][0].elapsed_time(ev[k][1]))
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ms_step = wall * 1e3 / args.steps
+    af = float(A) * D
+    med = {k: float(np.median(v)) for k, v in times.items()}
+
+    # rooflines of the main kernels from their HIP-event times
+    gram_flop = float(M) * D * (D + 1)
+    gram_tf = gram_flop / (med["gram"] * 1e-3) / 1e12
+    fwd_slots = valu_slots_per_feature(p.d, p.n_transforms) * af
+    fwd_tops = fwd_slots / (med["forward"] * 1e-3) / 1e12
+    bwd_slots = valu_slots_per_feature(p.d, p.n_transforms, backward=True) * af
+    bwd_tops = bwd_slots / (med["backward"] * 1e-3) / 1e12
+    chol_flop = D ** 3 / 3.0
+    rooflines = {
+        "gram": {"bound": "mfma", "achieved": gram_tf, "peak": PEAK_MFMA_TFLOPS[args.gram],
+                 "unit": "TFLOP/s", "frac": gram_tf / PEAK_MFMA_TFLOPS[args.gram], "traffic": None,
+                 "ms": med["gram"]},
+        "forward": {"bound": "alu", "achieved": fwd_tops, "peak": PEAK_VALU_TOPS,
+                    "unit": "T VALU-slots/s", "frac": fwd_tops / PEAK_VALU_TOPS, "traffic": None,
+                    "ms": med["forward"]},
+        "backward": {"bound": "alu", "achieved": bwd_tops, "peak": PEAK_VALU_TOPS,
+                     "unit": "T VALU-slots/s", "frac": bwd_tops / PEAK_VALU_TOPS, "traffic": None,
+                     "ms": med["backward"]},
+        "solve": {"bound": "mfma", "achieved": chol_flop / (med["solve"] * 1e-3) / 1e12,
+                  "peak": PEAK_MFMA_TFLOPS["fp64"], "unit": "TFLOP/s",
+                  "frac": chol_flop / (med["solve"] * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS["fp64"],
+                  "traffic": None, "ms": med["solve"]},
+    }
+    dominant = max(("gram", "forward", "backward", "solve"), key=lambda k: med[k])
+    roof = {k: v for k, v in rooflines[dominant].items() if k != "ms"}
+    roof["kernel"] = dominant
+
+    out = {
+        "metric": "SORF atom-features/s fwd+bwd; Gram TFLOP/s; force-request p50/p99 vs plain",
+        "value": af / (ms_step * 1e-3),
+        "unit": "atom-features/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": ms_step,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": "qm9-like train+infer step: 20000 molecules (3..29 atoms), d=128, "
+                               "64 stacks (D=8192), 3 transforms, sigma=4; forward, Gram, FP64 "
+                               "solve, energies, dE/dx",
+                   "n_mols": M, "n_atoms": A, "D": D, "gram": args.gram, "lambda": args.lam,
+                   "n_refine": args.n_refine},
+        "roofline": roof,
+        "phase_ms": med,
+        "rooflines": rooflines,
+        "fwd_bwd_atom_features_per_s": af / ((med["forward"] + med["backward"]) * 1e-3),
+        "forward_atom_features_per_s": af / (med["forward"] * 1e-3),
+        "gram_tflops": gram_tf,
+        "solve_info": info,
+        "gen_s": gen_s,
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(p, D, args.cpu_sample_mols, args.lam)
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

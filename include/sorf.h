@@ -122,6 +122,15 @@ sorf_status sorf_gram_accumulate(int64_t n_rows, int32_t D, const float* Z, cons
                                  sorf_gram_precision precision, int32_t scale_exp, float* G,
                                  float* Zty, sorf_stream_t stream);
 
+/* Double-precision normal equations (the paper's DP training mode; FP32 storage of
+ * G cannot hold a ridge lambda far below 2^-24 * ||G|| -- e.g. lambda = 1e-6 on a
+ * rank-deficient Gram -- because rounding G to FP32 already moves its eigenvalues
+ * by more than lambda):
+ *   G[i][j] += sum_m Z[m][i] Z[m][j] (i >= j, FP64 products and sums of the FP32 Z),
+ *   Zty[i]  += sum_m Z[m][i] y[m] (FP64).   G: [D][D] FP64 row-major, Zty: [D] FP64. */
+sorf_status sorf_gram_accumulate_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                                     double* G, double* Zty, sorf_stream_t stream);
+
 /* Bytes of workspace sorf_solve needs for a D x D system, 1 <= D <= 32768
  * (host-only query; returns 0 for an unsupported D). */
 size_t sorf_solve_workspace_bytes(int32_t D);
@@ -138,6 +147,12 @@ size_t sorf_solve_workspace_bytes(int32_t D);
 sorf_status sorf_solve(int32_t D, const float* G, const float* Zty, double lambda,
                        int32_t n_refine, double* alpha, int32_t* info, void* workspace,
                        size_t workspace_bytes, sorf_stream_t stream);
+
+/* sorf_solve for an FP64 lower-triangular G and FP64 Zty (from sorf_gram_accumulate_f64);
+ * same workspace, outputs and error behaviour. */
+sorf_status sorf_solve_f64(int32_t D, const double* G, const double* Zty, double lambda,
+                           int32_t n_refine, double* alpha, int32_t* info, void* workspace,
+                           size_t workspace_bytes, sorf_stream_t stream);
 
 /* Bytes of workspace sorf_predict needs (host-only query). */
 size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, int64_t n_mols);

@@ -122,6 +122,22 @@ sorf_status sorf_gram_accumulate(int64_t n_rows, int32_t D, const float* Z, cons
   return dev(e);
 }
 
+sorf_status sorf_gram_accumulate_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                                     double* G, double* Zty, sorf_stream_t stream) {
+  if (n_rows < 0 || D < 1 || D > (1 << 20)) return SORF_ERR_INVALID_ARG;
+  if (G == nullptr) return SORF_ERR_INVALID_ARG;
+  if (n_rows > 0 && Z == nullptr) return SORF_ERR_INVALID_ARG;
+  if (y != nullptr && Zty == nullptr) return SORF_ERR_INVALID_ARG;
+  if (!aligned16(Z)) return SORF_ERR_INVALID_ARG;
+  if (int64_t(D) * D > (int64_t(1) << 35)) return SORF_ERR_UNSUPPORTED;
+  hipStream_t st = hipStream_t(stream);
+  if (n_rows == 0) return SORF_OK;
+  hipError_t e = sorf_launch_gram_f64(n_rows, D, Z, G, st);
+  if (e != hipSuccess) return SORF_ERR_DEVICE;
+  if (y != nullptr) e = sorf_launch_zty_f64(n_rows, D, Z, y, Zty, st);
+  return dev(e);
+}
+
 size_t sorf_solve_workspace_bytes(int32_t D) {
   if (D < 1 || D > kMaxSolveD) return 0;
   return sorf_solve_ws_bytes(D);
@@ -139,6 +155,20 @@ sorf_status sorf_solve(int32_t D, const float* G, const float* Zty, double lambd
   if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
   return dev(sorf_launch_solve(D, G, Zty, lambda, n_refine, alpha, info, workspace,
                                hipStream_t(stream)));
+}
+
+sorf_status sorf_solve_f64(int32_t D, const double* G, const double* Zty, double lambda,
+                           int32_t n_refine, double* alpha, int32_t* info, void* workspace,
+                           size_t workspace_bytes, sorf_stream_t stream) {
+  if (D < 1 || D > kMaxSolveD) return SORF_ERR_INVALID_ARG;
+  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return SORF_ERR_INVALID_ARG;
+  if (n_refine < 0 || n_refine > 16) return SORF_ERR_INVALID_ARG;
+  if (G == nullptr || Zty == nullptr || alpha == nullptr || info == nullptr)
+    return SORF_ERR_INVALID_ARG;
+  if (workspace == nullptr || workspace_bytes < sorf_solve_ws_bytes(D)) return SORF_ERR_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  return dev(sorf_launch_solve_f64(D, G, Zty, lambda, n_refine, alpha, info, workspace,
+                                   hipStream_t(stream)));
 }
 
 size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, int64_t n_mols) {

@@ -244,12 +244,79 @@ __global__ __launch_bounds__(256) void gram_half_kernel(const float* __restrict_
       }
 }
 
+// ----------------------------------------------------------------- FP64 mode
+// The paper's double-precision training: Z (FP32) promoted to FP64 in LDS and
+// multiplied on the FP64 matrix cores; G is FP64. 64 x 64 tiles, 4 waves of
+// 32 x 32 (2 x 2 blocks of v_mfma_f64_16x16x4f64).
+typedef double f64x4 __attribute__((ext_vector_type(4)));
+
+__global__ __launch_bounds__(256) void gram_fp64_kernel(const float* __restrict__ Z, int64_t M,
+                                                       int32_t D, double* __restrict__ G) {
+  constexpr int T64 = 64;
+  __shared__ double sA[KB][T64 + 1];
+  __shared__ double sB[KB][T64 + 1];
+  int64_t I, J;
+  tile_of(blockIdx.x, I, J);
+  const bool diag = (I == J);
+  const int64_t I0 = I * T64, J0 = J * T64;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int wy = wv >> 1, wx = wv & 1;
+  f64x4 acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int lk = tid >> 4;        // slab row 0..15
+  const int li = (tid & 15) * 4;  // 4 consecutive columns
+  for (int64_t m0 = 0; m0 < M; m0 += KB) {
+    const int64_t m = m0 + lk;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t ci = I0 + li + c, cj = J0 + li + c;
+      sA[lk][li + c] = (m < M && ci < D) ? double(Z[m * D + ci]) : 0.0;
+      if (!diag) sB[lk][li + c] = (m < M && cj < D) ? double(Z[m * D + cj]) : 0.0;
+    }
+    __syncthreads();
+    const double (*sb)[T64 + 1] = diag ? sA : sB;
+#pragma unroll
+    for (int kk = 0; kk < KB; kk += 4) {
+      const int k = kk + (lane >> 4);
+      double av[2], bv[2];
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        av[b] = sA[k][wy * 32 + b * 16 + (lane & 15)];
+        bv[b] = sb[k][wx * 32 + b * 16 + (lane & 15)];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        // v_mfma_f64_16x16x4f64: lane l, register r holds row l/16 + 4 r, column l%16
+        const int64_t gi = I0 + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int64_t gj = J0 + wx * 32 + b * 16 + (lane & 15);
+        if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += acc[a][b][r];
+      }
+}
+
 // ----------------------------------------------------------------- Z^T y
 // one workgroup per 64 columns; the four waves take every fourth row; FP64
 // partial sums, combined in a fixed order and added to Zty in FP32.
+template <typename TOUT>
 __global__ __launch_bounds__(256) void zty_kernel(const float* __restrict__ Z,
                                                  const float* __restrict__ y, int64_t M, int32_t D,
-                                                 float* __restrict__ Zty) {
+                                                 TOUT* __restrict__ Zty) {
   __shared__ double red[4][64];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
@@ -261,7 +328,7 @@ __global__ __launch_bounds__(256) void zty_kernel(const float* __restrict__ Z,
   red[wv][lane] = acc;
   __syncthreads();
   if (wv == 0 && col < D)
-    Zty[col] += float(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
+    Zty[col] += TOUT(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
 }
 
 }  // namespace sorf
@@ -303,7 +370,24 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, int mode,
 hipError_t sorf_launch_zty(int64_t n_rows, int32_t D, const float* Z, const float* y, float* Zty,
                            hipStream_t st) {
   if (D == 0) return hipSuccess;
-  hipLaunchKernelGGL(zty_kernel, dim3(unsigned((D + 63) / 64)), dim3(256), 0, st, Z, y, n_rows, D,
-                     Zty);
+  hipLaunchKernelGGL(zty_kernel<float>, dim3(unsigned((D + 63) / 64)), dim3(256), 0, st, Z, y,
+                     n_rows, D, Zty);
+  return hipGetLastError();
+}
+
+hipError_t sorf_launch_gram_f64(int64_t n_rows, int32_t D, const float* Z, double* G,
+                                hipStream_t st) {
+  if (n_rows == 0 || D == 0) return hipSuccess;
+  const int64_t nt = (D + 63) / 64;
+  hipLaunchKernelGGL(gram_fp64_kernel, dim3(unsigned(nt * (nt + 1) / 2)), dim3(256), 0, st, Z,
+                     n_rows, D, G);
+  return hipGetLastError();
+}
+
+hipError_t sorf_launch_zty_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                               double* Zty, hipStream_t st) {
+  if (D == 0) return hipSuccess;
+  hipLaunchKernelGGL(zty_kernel<double>, dim3(unsigned((D + 63) / 64)), dim3(256), 0, st, Z, y,
+                     n_rows, D, Zty);
   return hipGetLastError();
 }

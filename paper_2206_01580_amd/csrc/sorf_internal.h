@@ -213,7 +213,15 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, int mode,
 hipError_t sorf_launch_zty(int64_t n_rows, int32_t D, const float* Z, const float* y, float* Zty,
                            hipStream_t s);
 
+hipError_t sorf_launch_gram_f64(int64_t n_rows, int32_t D, const float* Z, double* G,
+                                hipStream_t s);
+hipError_t sorf_launch_zty_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                               double* Zty, hipStream_t s);
+
 size_t sorf_solve_ws_bytes(int32_t D);
 hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double lambda,
                              int32_t n_refine, double* alpha, int32_t* info, void* ws,
                              hipStream_t s);
+hipError_t sorf_launch_solve_f64(int32_t D, const double* G, const double* Zty, double lambda,
+                                 int32_t n_refine, double* alpha, int32_t* info, void* ws,
+                                 hipStream_t s);

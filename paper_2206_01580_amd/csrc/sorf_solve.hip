@@ -56,7 +56,8 @@ static SolveWs carve(void* ws, int32_t D) {
 }
 
 // A = G + lambda I on the lower triangle, promoted to FP64; clears info.
-__global__ __launch_bounds__(256) void promote_kernel(const float* __restrict__ G, int32_t D,
+template <typename TG>
+__global__ __launch_bounds__(256) void promote_kernel(const TG* __restrict__ G, int32_t D,
                                                      double lambda, double* __restrict__ A,
                                                      int32_t* __restrict__ info) {
   const int64_t i = blockIdx.y;
@@ -189,7 +190,8 @@ __global__ __launch_bounds__(256) void syrk_kernel(double* __restrict__ A, int32
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gi = I0 + wy * 32 + a * 16 + 4 * (lane >> 4) + r;
+        // v_mfma_f64_16x16x4f64: lane l, register r holds row l/16 + 4 r, column l%16
+        const int64_t gi = I0 + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
         const int64_t gj = J0 + wx * 32 + b * 16 + (lane & 15);
         if (gi < D && gj < D && gi >= gj) A[gi * D + gj] -= acc[a][b][r];
       }
@@ -246,7 +248,8 @@ __global__ __launch_bounds__(256) void trsv_bwd_kernel(const double* __restrict_
 
 // Partial sums of (lower-stored symmetric G) x over 64 x 64 tiles:
 // part[X][Y][.] = contribution to rows of block X from the tile pairing X and Y.
-__global__ __launch_bounds__(256) void symv_tiles_kernel(const float* __restrict__ G, int32_t D,
+template <typename TG>
+__global__ __launch_bounds__(256) void symv_tiles_kernel(const TG* __restrict__ G, int32_t D,
                                                         const double* __restrict__ x,
                                                         double* __restrict__ part) {
   __shared__ double T[64][65];
@@ -287,8 +290,9 @@ __global__ __launch_bounds__(256) void symv_tiles_kernel(const float* __restrict
 }
 
 // r = Zty - lambda x - sum_Y part[X][Y] (fixed order)
+template <typename TG>
 __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict__ part, int32_t D,
-                                                      double lambda, const float* __restrict__ rhs,
+                                                      double lambda, const TG* __restrict__ rhs,
                                                       const double* __restrict__ x,
                                                       double* __restrict__ r) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
@@ -300,7 +304,8 @@ __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict_
   r[i] = (double(rhs[i]) - lambda * x[i]) - s;
 }
 
-__global__ void to_double_kernel(const float* __restrict__ a, double* __restrict__ b, int32_t n) {
+template <typename TG>
+__global__ void to_double_kernel(const TG* __restrict__ a, double* __restrict__ b, int32_t n) {
   const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i < n) b[i] = double(a[i]);
 }
@@ -338,12 +343,14 @@ size_t sorf_solve_ws_bytes(int32_t D) {
          3 * align256(sizeof(double) * D) + align256(sizeof(double) * nt * nt * 64);
 }
 
-hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double lambda,
-                             int32_t n_refine, double* alpha, int32_t* info, void* ws,
-                             hipStream_t st) {
+template <typename TG>
+static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lambda,
+                               int32_t n_refine, double* alpha, int32_t* info, void* ws,
+                               hipStream_t st) {
   const SolveWs w = carve(ws, D);
   const unsigned vg = unsigned((D + 255) / 256);
-  hipLaunchKernelGGL(promote_kernel, dim3(vg, unsigned(D)), dim3(256), 0, st, G, D, lambda, w.A, info);
+  hipLaunchKernelGGL(promote_kernel<TG>, dim3(vg, unsigned(D)), dim3(256), 0, st, G, D, lambda,
+                     w.A, info);
   for (int32_t k = 0; k < D; k += NB) {
     hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, k, info, w.Linv);
     const int64_t rest = int64_t(D) - k - NB;
@@ -355,17 +362,30 @@ hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double
   }
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(to_double_kernel, dim3(vg), dim3(256), 0, st, Zty, w.b, D);
+  hipLaunchKernelGGL(to_double_kernel<TG>, dim3(vg), dim3(256), 0, st, Zty, w.b, D);
   e = solve_triangular(w, D, w.b, w.y, alpha, st);
   if (e != hipSuccess) return e;
   const int64_t nt = (int64_t(D) + 63) / 64;
   for (int32_t it = 0; it < n_refine; ++it) {
-    hipLaunchKernelGGL(symv_tiles_kernel, dim3(unsigned(nt * (nt + 1) / 2)), dim3(256), 0, st, G, D,
-                       alpha, w.part);
-    hipLaunchKernelGGL(residual_kernel, dim3(vg), dim3(256), 0, st, w.part, D, lambda, Zty, alpha, w.b);
+    hipLaunchKernelGGL(symv_tiles_kernel<TG>, dim3(unsigned(nt * (nt + 1) / 2)), dim3(256), 0, st,
+                       G, D, alpha, w.part);
+    hipLaunchKernelGGL(residual_kernel<TG>, dim3(vg), dim3(256), 0, st, w.part, D, lambda, Zty,
+                       alpha, w.b);
     e = solve_triangular(w, D, w.b, w.y, w.dx, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(axpy_kernel, dim3(vg), dim3(256), 0, st, alpha, w.dx, D);
   }
   return hipGetLastError();
+}
+
+hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double lambda,
+                             int32_t n_refine, double* alpha, int32_t* info, void* ws,
+                             hipStream_t st) {
+  return launch_solve<float>(D, G, Zty, lambda, n_refine, alpha, info, ws, st);
+}
+
+hipError_t sorf_launch_solve_f64(int32_t D, const double* G, const double* Zty, double lambda,
+                                 int32_t n_refine, double* alpha, int32_t* info, void* ws,
+                                 hipStream_t st) {
+  return launch_solve<double>(D, G, Zty, lambda, n_refine, alpha, info, ws, st);
 }

@@ -163,14 +163,20 @@ def backward(model: Model, batch: Batch, alpha: torch.Tensor, dE: Optional[torch
 def gram_accumulate(Z: torch.Tensor, G: torch.Tensor, y: Optional[torch.Tensor] = None,
                     Zty: Optional[torch.Tensor] = None, precision: str = "fp32",
                     scale_exp: int = 0) -> None:
-    """G += Z^T Z on the lower triangle; Zty += Z^T y (sorf_gram_accumulate)."""
+    """G += Z^T Z on the lower triangle; Zty += Z^T y (sorf_gram_accumulate, or
+    sorf_gram_accumulate_f64 for precision 'fp64', where G and Zty are float64)."""
     M, D = Z.shape
     _need(Z, torch.float32, "Z")
-    _need(G, torch.float32, "G", D * D)
+    acc_t = torch.float64 if precision == "fp64" else torch.float32
+    _need(G, acc_t, "G", D * D)
     if y is not None:
         _need(y, torch.float32, "y", M)
-        _need(Zty, torch.float32, "Zty", D)
+        _need(Zty, acc_t, "Zty", D)
     lib = _lib.load()
+    if precision == "fp64":
+        _lib.check("sorf_gram_accumulate_f64", lib.sorf_gram_accumulate_f64(
+            M, D, _ptr(Z), _ptr(y), _ptr(G), _ptr(Zty), _stream()))
+        return
     _lib.check("sorf_gram_accumulate", lib.sorf_gram_accumulate(
         M, D, _ptr(Z), _ptr(y), _lib.GRAM_MODES[precision], scale_exp, _ptr(G), _ptr(Zty),
         _stream()))
@@ -201,15 +207,17 @@ class Solver:
     def __call__(self, G: torch.Tensor, Zty: torch.Tensor, lam: float, n_refine: int = 3,
                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
         D = self.D
-        _need(G, torch.float32, "G", D * D)
-        _need(Zty, torch.float32, "Zty", D)
+        f64 = G.dtype == torch.float64
+        _need(G, G.dtype if f64 else torch.float32, "G", D * D)
+        _need(Zty, torch.float64 if f64 else torch.float32, "Zty", D)
         if out is None:
             out = torch.empty(D, dtype=torch.float64, device=G.device)
         _need(out, torch.float64, "alpha", D)
         lib = _lib.load()
-        _lib.check("sorf_solve", lib.sorf_solve(
-            D, _ptr(G), _ptr(Zty), float(lam), int(n_refine), _ptr(out), _ptr(self.info),
-            self.ws.data_ptr() + self.ws_off, self.nbytes, _stream()))
+        fn, name = (lib.sorf_solve_f64, "sorf_solve_f64") if f64 else (lib.sorf_solve, "sorf_solve")
+        _lib.check(name, fn(D, _ptr(G), _ptr(Zty), float(lam), int(n_refine), _ptr(out),
+                            _ptr(self.info), self.ws.data_ptr() + self.ws_off, self.nbytes,
+                            _stream()))
         return out
 
 
