@@ -61,7 +61,8 @@ typedef enum {
   SORF_GRAM_FP32 = 0,        /* FP32 operands, FP32 MFMA, FP32 accumulation */
   SORF_GRAM_BF16 = 1,        /* one bf16 product hi^T hi, FP32 accumulation */
   SORF_GRAM_FP16 = 2,        /* one fp16 product hi^T hi, FP32 accumulation */
-  SORF_GRAM_BF16_HILO = 3,   /* hi^T hi + hi^T lo + lo^T hi with hi = bf16(z), lo = bf16(z - hi) */
+  SORF_GRAM_BF16_HILO = 3,   /* (hi + lo)^T (hi + lo), four bf16 products, hi = bf16(z),
+                                lo = bf16(z - hi); the Gram of hi + lo, so it stays PSD */
   SORF_GRAM_FP16_HILO = 4    /* the same with fp16 parts of 2^scale_exp * z */
 } sorf_gram_precision;
 

@@ -262,9 +262,11 @@ def gram_emulated(Z, mode: str, scale_exp: int = 0) -> np.ndarray:
 
     * 'fp32'       Z^T Z of the float32 values
     * 'bf16'/'fp16'      hi^T hi
-    * 'bf16_hilo'/'fp16_hilo'  hi^T hi + hi^T lo + lo^T hi  (lo^T lo dropped)
+    * 'bf16_hilo'/'fp16_hilo'  (hi + lo)^T (hi + lo), all four products
 
-    scaled back by 2**(-2*scale_exp)."""
+    scaled back by 2**(-2*scale_exp). The split modes keep lo^T lo so that
+    the result is the Gram matrix of the two-term approximation hi + lo and
+    stays positive semidefinite, as the normal equations require."""
     Z32 = np.asarray(Z, dtype=np.float32)
     if mode == "fp32":
         Zd = Z32.astype(np.float64)
@@ -273,8 +275,9 @@ def gram_emulated(Z, mode: str, scale_exp: int = 0) -> np.ndarray:
     hi, lo = split_hilo(Z32, kind, scale_exp)
     hi = hi.astype(np.float64)
     lo = lo.astype(np.float64)
-    G = hi.T @ hi
     if mode.endswith("hilo"):
-        cross = hi.T @ lo
-        G = G + cross + cross.T
+        z2 = hi + lo          # exact in float64
+        G = z2.T @ z2
+    else:
+        G = hi.T @ hi
     return G * 2.0 ** (-2 * scale_exp)

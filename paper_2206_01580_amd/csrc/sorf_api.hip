@@ -116,10 +116,7 @@ sorf_status sorf_gram_accumulate(int64_t n_rows, int32_t D, const float* Z, cons
   if (int64_t(D) * D > (int64_t(1) << 36)) return SORF_ERR_UNSUPPORTED;
   hipStream_t st = hipStream_t(stream);
   if (n_rows == 0) return SORF_OK;
-  hipError_t e = sorf_launch_gram(n_rows, D, Z, int(precision), scale_exp, G, st);
-  if (e != hipSuccess) return SORF_ERR_DEVICE;
-  if (y != nullptr) e = sorf_launch_zty(n_rows, D, Z, y, Zty, st);
-  return dev(e);
+  return dev(sorf_launch_gram(n_rows, D, Z, y, int(precision), scale_exp, G, Zty, st));
 }
 
 sorf_status sorf_gram_accumulate_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
@@ -132,10 +129,7 @@ sorf_status sorf_gram_accumulate_f64(int64_t n_rows, int32_t D, const float* Z, 
   if (int64_t(D) * D > (int64_t(1) << 35)) return SORF_ERR_UNSUPPORTED;
   hipStream_t st = hipStream_t(stream);
   if (n_rows == 0) return SORF_OK;
-  hipError_t e = sorf_launch_gram_f64(n_rows, D, Z, G, st);
-  if (e != hipSuccess) return SORF_ERR_DEVICE;
-  if (y != nullptr) e = sorf_launch_zty_f64(n_rows, D, Z, y, Zty, st);
-  return dev(e);
+  return dev(sorf_launch_gram_f64(n_rows, D, Z, y, G, Zty, st));
 }
 
 size_t sorf_solve_workspace_bytes(int32_t D) {

@@ -4,12 +4,17 @@
 // Z^T Z product dominates training) and Training-time discussion (FP32 Z^T Z
 // suffers cumulative round-off; the paper uses Kahan summation). Here the
 // reduced-precision modes split each FP32 value z into hi = round(z) and
-// lo = round(z - hi) in bf16 or fp16 and accumulate hi^T hi + hi^T lo + lo^T hi
-// in FP32 on the matrix cores.
+// lo = round(z - hi) in bf16 or fp16 and accumulate (hi + lo)^T (hi + lo) =
+// hi^T hi + hi^T lo + lo^T hi + lo^T lo in FP32 on the matrix cores. All four
+// products are kept: without lo^T lo the result is G - lo^T lo, which is not
+// positive semidefinite, and on the QM9-like workload its smallest
+// eigenvalues fall below zero by more than any useful ridge term.
 //
 // Tiling: one workgroup (4 waves) per 128 x 128 tile (I, J) of the lower
 // triangle of G; the tile walks all rows of Z in slabs of 16 rows staged
 // through LDS; each wave owns a 64 x 64 quadrant = 2 x 2 MFMA 32x32 blocks.
+// Z^T y is accumulated (in FP64) by the diagonal tiles, which already read
+// every row of their column block, and added once per call in FP32.
 #include <cmath>
 
 #include "sorf_internal.h"
@@ -61,9 +66,12 @@ __device__ __forceinline__ void split(float z, unsigned short& hi, unsigned shor
 // ----------------------------------------------------------------- FP32 mode
 template <bool VEC4>
 __global__ __launch_bounds__(256) void gram_fp32_kernel(const float* __restrict__ Z, int64_t M,
-                                                       int32_t D, float* __restrict__ G) {
+                                                       int32_t D, float* __restrict__ G,
+                                                       const float* __restrict__ y,
+                                                       float* __restrict__ Zty) {
   __shared__ float sA[KB][TILE + 4];
   __shared__ float sB[KB][TILE + 4];
+  __shared__ double zred[KB][TILE];
   int64_t I, J;
   tile_of(blockIdx.x, I, J);
   const bool diag = (I == J);
@@ -83,6 +91,11 @@ __global__ __launch_bounds__(256) void gram_fp32_kernel(const float* __restrict_
 
   const int lk = tid >> 4;         // slab row 0..15
   const int li = (tid & 15) * 8;   // 8 consecutive columns
+  // Z^T y rides on the diagonal tiles, which stream every row of their columns
+  const bool want_zty = diag && y != nullptr;
+  double zacc[8];
+#pragma unroll
+  for (int c = 0; c < 8; ++c) zacc[c] = 0.0;
   for (int64_t m0 = 0; m0 < M; m0 += KB) {
     const int64_t m = m0 + lk;
     const bool mok = m < M;
@@ -102,7 +115,14 @@ __global__ __launch_bounds__(256) void gram_fp32_kernel(const float* __restrict_
       float* dst = (h == 0 ? &sA[lk][li] : &sB[lk][li]);
 #pragma unroll
       for (int c = 0; c < 8; ++c) dst[c] = v[c];
-      if (diag) break;
+      if (diag) {
+        if (want_zty && mok) {
+          const double ym = double(y[m]);
+#pragma unroll
+          for (int c = 0; c < 8; ++c) zacc[c] += double(v[c]) * ym;
+        }
+        break;
+      }
     }
     __syncthreads();
     const float (*sb)[TILE + 4] = diag ? sA : sB;
@@ -134,13 +154,26 @@ __global__ __launch_bounds__(256) void gram_fp32_kernel(const float* __restrict_
         const int64_t gj = J0 + wx * 64 + b * 32 + (lane & 31);
         if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += acc[a][b][r];
       }
+  if (want_zty) {
+#pragma unroll
+    for (int c = 0; c < 8; ++c) zred[lk][li + c] = zacc[c];
+    __syncthreads();
+    if (tid < TILE && I0 + tid < D) {
+      double t = 0.0;
+      for (int r = 0; r < KB; ++r) t += zred[r][tid];
+      Zty[I0 + tid] += float(t);
+    }
+  }
 }
 
 // ------------------------------------------------- bf16 / fp16 (x1 and hi+lo)
 template <int MODE>
 __global__ __launch_bounds__(256) void gram_half_kernel(const float* __restrict__ Z, int64_t M,
                                                        int32_t D, float zscale, float gscale,
-                                                       float* __restrict__ G) {
+                                                       float* __restrict__ G,
+                                                       const float* __restrict__ y,
+                                                       float* __restrict__ Zty) {
+  __shared__ double zred[2][TILE];
   constexpr bool HILO = (MODE == kBF16HiLo || MODE == kFP16HiLo);
   constexpr int KP = KB + 8;  // padded k stride (in 16-bit elements)
   __shared__ __attribute__((aligned(16))) unsigned short sAh[TILE][KP];
@@ -166,6 +199,8 @@ __global__ __launch_bounds__(256) void gram_half_kernel(const float* __restrict_
 
   const int li = tid & (TILE - 1);  // column within the tile
   const int lk = (tid >> 7) * 8;    // 8 consecutive slab rows
+  const bool want_zty = diag && y != nullptr;
+  double zacc = 0.0;
   for (int64_t m0 = 0; m0 < M; m0 += KB) {
 #pragma unroll
     for (int h = 0; h < 2; ++h) {
@@ -174,9 +209,11 @@ __global__ __launch_bounds__(256) void gram_half_kernel(const float* __restrict_
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int64_t m = m0 + lk + c;
-        const float z = (m < M && col < D) ? Z[m * D + col] * zscale : 0.0f;
+        const bool ok = m < M && col < D;
+        const float zr = ok ? Z[m * D + col] : 0.0f;
+        if (h == 0 && want_zty && ok) zacc += double(zr) * double(y[m]);
         unsigned short a, b;
-        split<MODE>(z, a, b);
+        split<MODE>(zr * zscale, a, b);
         hi[c] = a;
         lo[c] = b;
       }
@@ -217,6 +254,8 @@ __global__ __launch_bounds__(256) void gram_half_kernel(const float* __restrict_
                 __builtin_bit_cast(bf16x8, ah[a]), __builtin_bit_cast(bf16x8, blv[b]), acc[a][b], 0, 0, 0);
             acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
                 __builtin_bit_cast(bf16x8, al[a]), __builtin_bit_cast(bf16x8, bhv[b]), acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
+                __builtin_bit_cast(bf16x8, al[a]), __builtin_bit_cast(bf16x8, blv[b]), acc[a][b], 0, 0, 0);
           }
         } else {
           acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
@@ -226,6 +265,8 @@ __global__ __launch_bounds__(256) void gram_half_kernel(const float* __restrict_
                 __builtin_bit_cast(f16x8, ah[a]), __builtin_bit_cast(f16x8, blv[b]), acc[a][b], 0, 0, 0);
             acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
                 __builtin_bit_cast(f16x8, al[a]), __builtin_bit_cast(f16x8, bhv[b]), acc[a][b], 0, 0, 0);
+            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
+                __builtin_bit_cast(f16x8, al[a]), __builtin_bit_cast(f16x8, blv[b]), acc[a][b], 0, 0, 0);
           }
         }
       }
@@ -242,6 +283,11 @@ __global__ __launch_bounds__(256) void gram_half_kernel(const float* __restrict_
         const int64_t gj = J0 + wx * 64 + b * 32 + (lane & 31);
         if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += acc[a][b][r] * gscale;
       }
+  if (want_zty) {
+    zred[lk >> 3][li] = zacc;
+    __syncthreads();
+    if (tid < TILE && I0 + tid < D) Zty[I0 + tid] += float(zred[0][tid] + zred[1][tid]);
+  }
 }
 
 // ----------------------------------------------------------------- FP64 mode
@@ -251,10 +297,13 @@ __global__ __launch_bounds__(256) void gram_half_kernel(const float* __restrict_
 typedef double f64x4 __attribute__((ext_vector_type(4)));
 
 __global__ __launch_bounds__(256) void gram_fp64_kernel(const float* __restrict__ Z, int64_t M,
-                                                       int32_t D, double* __restrict__ G) {
+                                                       int32_t D, double* __restrict__ G,
+                                                       const float* __restrict__ y,
+                                                       double* __restrict__ Zty) {
   constexpr int T64 = 64;
   __shared__ double sA[KB][T64 + 1];
   __shared__ double sB[KB][T64 + 1];
+  __shared__ double zred[KB][T64];
   int64_t I, J;
   tile_of(blockIdx.x, I, J);
   const bool diag = (I == J);
@@ -270,12 +319,17 @@ __global__ __launch_bounds__(256) void gram_fp64_kernel(const float* __restrict_
     for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
   const int lk = tid >> 4;        // slab row 0..15
   const int li = (tid & 15) * 4;  // 4 consecutive columns
+  const bool want_zty = diag && y != nullptr;
+  double zacc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t m0 = 0; m0 < M; m0 += KB) {
     const int64_t m = m0 + lk;
+    const double ym = (want_zty && m < M) ? double(y[m]) : 0.0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int64_t ci = I0 + li + c, cj = J0 + li + c;
-      sA[lk][li + c] = (m < M && ci < D) ? double(Z[m * D + ci]) : 0.0;
+      const double zi = (m < M && ci < D) ? double(Z[m * D + ci]) : 0.0;
+      sA[lk][li + c] = zi;
+      zacc[c] += zi * ym;
       if (!diag) sB[lk][li + c] = (m < M && cj < D) ? double(Z[m * D + cj]) : 0.0;
     }
     __syncthreads();
@@ -308,35 +362,24 @@ __global__ __launch_bounds__(256) void gram_fp64_kernel(const float* __restrict_
         const int64_t gj = J0 + wx * 32 + b * 16 + (lane & 15);
         if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += acc[a][b][r];
       }
-}
-
-// ----------------------------------------------------------------- Z^T y
-// one workgroup per 64 columns; the four waves take every fourth row; FP64
-// partial sums, combined in a fixed order and added to Zty in FP32.
-template <typename TOUT>
-__global__ __launch_bounds__(256) void zty_kernel(const float* __restrict__ Z,
-                                                 const float* __restrict__ y, int64_t M, int32_t D,
-                                                 TOUT* __restrict__ Zty) {
-  __shared__ double red[4][64];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t col = int64_t(blockIdx.x) * 64 + lane;
-  double acc = 0.0;
-  if (col < D) {
-    for (int64_t m = wv; m < M; m += 4) acc += double(Z[m * D + col]) * double(y[m]);
+  if (want_zty) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) zred[lk][li + c] = zacc[c];
+    __syncthreads();
+    if (tid < T64 && I0 + tid < D) {
+      double t = 0.0;
+      for (int r = 0; r < KB; ++r) t += zred[r][tid];
+      Zty[I0 + tid] += t;
+    }
   }
-  red[wv][lane] = acc;
-  __syncthreads();
-  if (wv == 0 && col < D)
-    Zty[col] += TOUT(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
 }
 
 }  // namespace sorf
 
 using namespace sorf;
 
-hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, int mode, int32_t scale_exp,
-                            float* G, hipStream_t st) {
+hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const float* y, int mode,
+                            int32_t scale_exp, float* G, float* Zty, hipStream_t st) {
   if (n_rows == 0 || D == 0) return hipSuccess;
   const int64_t nt = (D + TILE - 1) / TILE;
   const dim3 grid{unsigned(nt * (nt + 1) / 2)}, block{256};
@@ -345,21 +388,23 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, int mode,
   switch (mode) {
     case kFP32:
       if (D % 4 == 0)
-        hipLaunchKernelGGL(gram_fp32_kernel<true>, grid, block, 0, st, Z, n_rows, D, G);
+        hipLaunchKernelGGL(gram_fp32_kernel<true>, grid, block, 0, st, Z, n_rows, D, G, y, Zty);
       else
-        hipLaunchKernelGGL(gram_fp32_kernel<false>, grid, block, 0, st, Z, n_rows, D, G);
+        hipLaunchKernelGGL(gram_fp32_kernel<false>, grid, block, 0, st, Z, n_rows, D, G, y, Zty);
       break;
     case kBF16:
-      hipLaunchKernelGGL(gram_half_kernel<kBF16>, grid, block, 0, st, Z, n_rows, D, zs, gs, G);
+      hipLaunchKernelGGL(gram_half_kernel<kBF16>, grid, block, 0, st, Z, n_rows, D, zs, gs, G, y, Zty);
       break;
     case kFP16:
-      hipLaunchKernelGGL(gram_half_kernel<kFP16>, grid, block, 0, st, Z, n_rows, D, zs, gs, G);
+      hipLaunchKernelGGL(gram_half_kernel<kFP16>, grid, block, 0, st, Z, n_rows, D, zs, gs, G, y, Zty);
       break;
     case kBF16HiLo:
-      hipLaunchKernelGGL(gram_half_kernel<kBF16HiLo>, grid, block, 0, st, Z, n_rows, D, zs, gs, G);
+      hipLaunchKernelGGL(gram_half_kernel<kBF16HiLo>, grid, block, 0, st, Z, n_rows, D, zs, gs, G,
+                         y, Zty);
       break;
     case kFP16HiLo:
-      hipLaunchKernelGGL(gram_half_kernel<kFP16HiLo>, grid, block, 0, st, Z, n_rows, D, zs, gs, G);
+      hipLaunchKernelGGL(gram_half_kernel<kFP16HiLo>, grid, block, 0, st, Z, n_rows, D, zs, gs, G,
+                         y, Zty);
       break;
     default:
       return hipErrorInvalidValue;
@@ -367,27 +412,11 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, int mode,
   return hipGetLastError();
 }
 
-hipError_t sorf_launch_zty(int64_t n_rows, int32_t D, const float* Z, const float* y, float* Zty,
-                           hipStream_t st) {
-  if (D == 0) return hipSuccess;
-  hipLaunchKernelGGL(zty_kernel<float>, dim3(unsigned((D + 63) / 64)), dim3(256), 0, st, Z, y,
-                     n_rows, D, Zty);
-  return hipGetLastError();
-}
-
-hipError_t sorf_launch_gram_f64(int64_t n_rows, int32_t D, const float* Z, double* G,
-                                hipStream_t st) {
+hipError_t sorf_launch_gram_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                                double* G, double* Zty, hipStream_t st) {
   if (n_rows == 0 || D == 0) return hipSuccess;
   const int64_t nt = (D + 63) / 64;
   hipLaunchKernelGGL(gram_fp64_kernel, dim3(unsigned(nt * (nt + 1) / 2)), dim3(256), 0, st, Z,
-                     n_rows, D, G);
-  return hipGetLastError();
-}
-
-hipError_t sorf_launch_zty_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
-                               double* Zty, hipStream_t st) {
-  if (D == 0) return hipSuccess;
-  hipLaunchKernelGGL(zty_kernel<double>, dim3(unsigned((D + 63) / 64)), dim3(256), 0, st, Z, y,
-                     n_rows, D, Zty);
+                     n_rows, D, G, y, Zty);
   return hipGetLastError();
 }

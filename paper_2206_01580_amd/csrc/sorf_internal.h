@@ -208,15 +208,10 @@ hipError_t sorf_launch_molecule_reduce(const SorfFeatureArgs& a, const float* e_
 hipError_t sorf_launch_validate(const SorfFeatureArgs& a, int32_t* result, hipStream_t s);
 hipError_t sorf_launch_fill(float* p, int64_t n, float v, hipStream_t s);
 
-hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, int mode, int32_t scale_exp,
-                            float* G, hipStream_t s);
-hipError_t sorf_launch_zty(int64_t n_rows, int32_t D, const float* Z, const float* y, float* Zty,
-                           hipStream_t s);
-
-hipError_t sorf_launch_gram_f64(int64_t n_rows, int32_t D, const float* Z, double* G,
-                                hipStream_t s);
-hipError_t sorf_launch_zty_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
-                               double* Zty, hipStream_t s);
+hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const float* y, int mode,
+                            int32_t scale_exp, float* G, float* Zty, hipStream_t s);
+hipError_t sorf_launch_gram_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                                double* G, double* Zty, hipStream_t s);
 
 size_t sorf_solve_ws_bytes(int32_t D);
 hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double lambda,

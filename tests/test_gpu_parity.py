@@ -281,7 +281,7 @@ def test_gram_deterministic():
 
 
 # ------------------------------------------------------------------ solve
-@pytest.mark.parametrize("D", [1, 50, 64, 200, 513])
+@pytest.mark.parametrize("D", [1, 50, 64, 128, 200, 256, 513, 1000])
 def test_solve_matches_oracle(D):
     rng = np.random.default_rng(D)
     Z = rng.standard_normal((2 * D + 10, D)).astype(np.float32)
