@@ -76,71 +76,239 @@ __global__ __launch_bounds__(256) void promote_kernel(const TG* __restrict__ G, 
   if (j <= i && j < D) A[i * D + j] = double(G[i * D + j]) + (i == j ? lambda : 0.0);
 }
 
-// Factor the diagonal block at (k, k) in LDS, write L back into A and the
-// inverse of L (and its transpose) into Linv / LinvT[k / NB].
-// Both sweeps are right-looking: each step is one barrier-separated rank-1
-// update spread over a 16 x 32 thread grid, with no dependent load chains.
-__global__ __launch_bounds__(512) void potrf_diag_kernel(double* __restrict__ A, int32_t D, int32_t k,
+// ---------------------------------------------------------------------------
+// Diagonal block: factor and invert a 128 x 128 block in LDS.
+//
+// The block is split into 64 x 64 halves. A single wave factors (and later
+// inverts) a half with no workgroup barriers: the LDS operations of one wave
+// execute in order, so between steps it only waits for its own LDS traffic
+// (lgkmcnt(0)) and stops the compiler from moving memory operations across
+// the step (wave barrier). The couplings between the halves are 64 x 64 x 64
+// products spread over all four waves.
+// ---------------------------------------------------------------------------
+typedef double LdsBlock[NB + 1];
+
+static __device__ __forceinline__ void wave_step_fence() {
+  __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS reads/writes are done
+  __atomic_signal_fence(__ATOMIC_SEQ_CST);  // no compiler motion of memory accesses across
+  __builtin_amdgcn_wave_barrier();
+}
+
+// In-place Cholesky of the 64 x 64 block at (o, o) by one wave. Step J is
+// unrolled at compile time: lane (ly, lx) of an 8 x 8 grid owns entries
+// (i, l) = (J+1+ly+8a, J+1+lx+8b), l <= i; it first loads all of them (at
+// clamped, always valid addresses), then updates and stores the valid ones.
+// The trailing update uses the unscaled column J; the column is scaled after.
+// Rows past the matrix were padded with the identity, so every step is
+// well defined and the padding factors to the identity.
+template <int J>
+static __device__ __forceinline__ void wave_potrf64(LdsBlock* L, int o, int ly, int lx, int lane,
+                                                    int32_t* info, int gbase, int nvalid) {
+  constexpr int NA = (63 - J + 7) / 8;
+  const double d = L[o + J][o + J];
+  const bool bad = !(d > 0.0) || !std::isfinite(d);
+  if (bad && lane == 0 && J < nvalid && *info == 0) *info = gbase + J + 1;
+  const double piv = bad ? __builtin_nan("") : std::sqrt(d);
+  if constexpr (NA > 0) {
+    const double rd = 1.0 / d;
+    double ci[NA], cl[NA], e[NA][NA];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int i = min(J + 1 + ly + 8 * a, 63), l = min(J + 1 + lx + 8 * a, 63);
+      ci[a] = L[o + i][o + J];
+      cl[a] = L[o + l][o + J];
+    }
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NA; ++b)
+        e[a][b] = L[o + min(J + 1 + ly + 8 * a, 63)][o + min(J + 1 + lx + 8 * b, 63)];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int i = J + 1 + ly + 8 * a;
+#pragma unroll
+      for (int b = 0; b < NA; ++b) {
+        const int l = J + 1 + lx + 8 * b;
+        if (i < 64 && l <= i) L[o + i][o + l] = e[a][b] - ci[a] * rd * cl[b];
+      }
+    }
+  }
+  wave_step_fence();
+  {
+    const int i = J + lane;
+    const double rpiv = 1.0 / piv;
+    const double v = L[o + min(i, 63)][o + J];
+    if (i < 64) L[o + i][o + J] = (i == J) ? piv : v * rpiv;
+  }
+  wave_step_fence();
+  if constexpr (J + 1 < 64) wave_potrf64<J + 1>(L, o, ly, lx, lane, info, gbase, nvalid);
+}
+
+// In-place inverse of the lower-triangular 64 x 64 block at (o, o) by one
+// wave: forward elimination of [L | I]. Step Q subtracts row Q (scaled by
+// 1/L[Q][Q]) from the rows below -- entries (i, c) = (Q+1+ly+8a, lx+8b), c < Q,
+// all loaded first -- then finalises column Q below the pivot and row Q.
+template <int Q>
+static __device__ __forceinline__ void wave_trtri64(LdsBlock* L, int o, int ly, int lx, int lane) {
+  constexpr int NA = (63 - Q + 7) / 8;
+  constexpr int NC = (Q + 7) / 8;
+  const double inv = 1.0 / L[o + Q][o + Q];
+  if constexpr (NA > 0 && NC > 0) {
+    double fi[NA], rq[NC], e[NA][NC];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) fi[a] = L[o + min(Q + 1 + ly + 8 * a, 63)][o + Q];
+#pragma unroll
+    for (int b = 0; b < NC; ++b) rq[b] = L[o + Q][o + min(lx + 8 * b, 63)];
+#pragma unroll
+    for (int a = 0; a < NA; ++a)
+#pragma unroll
+      for (int b = 0; b < NC; ++b)
+        e[a][b] = L[o + min(Q + 1 + ly + 8 * a, 63)][o + min(lx + 8 * b, 63)];
+#pragma unroll
+    for (int a = 0; a < NA; ++a) {
+      const int i = Q + 1 + ly + 8 * a;
+      const double f = fi[a] * inv;
+#pragma unroll
+      for (int b = 0; b < NC; ++b) {
+        const int c = lx + 8 * b;
+        if (i < 64 && c < Q) L[o + i][o + c] = e[a][b] - f * rq[b];
+      }
+    }
+  }
+  wave_step_fence();
+  {
+    const int i = Q + 1 + lane;
+    const double vi = L[o + min(i, 63)][o + Q];
+    const double vr = L[o + Q][o + min(lane, 63)];
+    if (i < 64) L[o + i][o + Q] = -vi * inv;
+    if (lane < Q) L[o + Q][o + lane] = vr * inv;
+    if (lane == 0) L[o + Q][o + Q] = inv;
+  }
+  wave_step_fence();
+  if constexpr (Q + 1 < 64) wave_trtri64<Q + 1>(L, o, ly, lx, lane);
+}
+
+// C = A B for 64 x 64 operands held in the LDS block, on FP64 MFMA: wave
+// (wy, wx) computes the 32 x 32 quadrant of C at (32 wy, 32 wx).
+// A[i][p] = L[ar + i][ac + p]; B[p][j] = L[br + p][bc + j], or with BT the
+// transposed access B[p][j] = L[br + j][bc + p].
+template <bool BT>
+static __device__ __forceinline__ void lds_mm64(LdsBlock* L, int ar, int ac, int br, int bc,
+                                                int wy, int wx, int lane, f64x4 (&acc)[2][2]) {
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y) acc[x][y] = f64x4{0.0, 0.0, 0.0, 0.0};
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll 4
+  for (int kk = 0; kk < 64; kk += 4) {
+    const int p = kk + lk;
+    double a[2], b[2];
+#pragma unroll
+    for (int x = 0; x < 2; ++x) a[x] = L[ar + 32 * wy + 16 * x + li][ac + p];
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+      b[y] = BT ? L[br + 32 * wx + 16 * y + li][bc + p] : L[br + p][bc + 32 * wx + 16 * y + li];
+#pragma unroll
+    for (int x = 0; x < 2; ++x)
+#pragma unroll
+      for (int y = 0; y < 2; ++y) acc[x][y] = mfma64(a[x], b[y], acc[x][y]);
+  }
+}
+
+// Row / column of entry r of accumulator (x, y) in lane `lane` (see mfma64).
+#define SORF_MM_ROW(wy, x, lane, r) (32 * (wy) + 16 * (x) + ((lane) >> 4) + 4 * (r))
+#define SORF_MM_COL(wx, y, lane) (32 * (wx) + 16 * (y) + ((lane) & 15))
+
+// Factor the diagonal block at (k, k), write L back into A and the inverse of
+// L (and its transpose) into Linv / LinvT[k / NB]. 256 threads.
+//   L = [L11 0; L21 L22]:  L11 = chol(A11), L21 = A21 L11^{-T},
+//   L22 = chol(A22 - L21 L21^T);  L^{-1} = [X11 0; -X22 L21 X11, X22].
+__global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A, int32_t D, int32_t k,
                                                         int32_t* __restrict__ info,
                                                         double* __restrict__ Linv,
                                                         double* __restrict__ LinvT) {
   __shared__ double L[NB][NB + 1];
-  __shared__ double col[NB];
-  __shared__ double rowk[NB];
-  __shared__ double sc[3];
   const int tid = threadIdx.x;
-  const int ty = tid >> 5, tx = tid & 31;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int wy = wv >> 1, wx = wv & 1;
+  const int ly = lane >> 3, lx = lane & 7;
   const int n = (D - k) < NB ? (D - k) : NB;
-  for (int t = tid; t < NB * NB; t += 512) {
+  // rows past the matrix are padded with the identity
+  for (int t = tid; t < NB * NB; t += 256) {
     const int i = t >> 7, j = t & (NB - 1);
-    L[i][j] = (i < n && j <= i) ? A[int64_t(k + i) * D + (k + j)] : 0.0;
+    const int64_t gi = k + min(i, n - 1), gj = k + min(j, n - 1);
+    const double a = A[gi * D + gj];
+    L[i][j] = (i < n && j <= i) ? a : ((i == j) ? 1.0 : 0.0);
   }
   __syncthreads();
-  // Cholesky: column j is scaled by 1/sqrt(d); the trailing update uses the
-  // unscaled column and 1/d
-  for (int j = 0; j < n; ++j) {
-    if (tid < n - j) col[j + tid] = L[j + tid][j];
-    if (tid == 0) {
-      const double d = L[j][j];
-      const bool bad = !(d > 0.0) || !std::isfinite(d);
-      if (bad && *info == 0) *info = k + j + 1;
-      const double piv = bad ? __builtin_nan("") : std::sqrt(d);
-      sc[0] = piv;
-      sc[1] = 1.0 / piv;
-      sc[2] = 1.0 / d;
-    }
-    __syncthreads();
-    const double rpiv = sc[1], rd = sc[2];
-    if (tid < n - j) L[j + tid][j] = (tid == 0) ? sc[0] : col[j + tid] * rpiv;
-    for (int i = j + 1 + ty; i < n; i += 16) {
-      const double ci = col[i] * rd;
-      for (int l = j + 1 + tx; l <= i; l += 32) L[i][l] -= ci * col[l];
-    }
-    __syncthreads();
-  }
-  for (int t = tid; t < NB * NB; t += 512) {
-    const int i = t >> 7, j = t & (NB - 1);
+  if (wv == 0) wave_potrf64<0>(L, 0, ly, lx, lane, info, k, n);
+  __syncthreads();
+  for (int t = tid; t < 64 * 64; t += 256) {
+    const int i = t >> 6, j = t & 63;
     if (i < n && j <= i) A[int64_t(k + i) * D + (k + j)] = L[i][j];
   }
   __syncthreads();
-  // in-place inverse by forward elimination of [L | I]: at step q row q is
-  // divided by L[q][q] and subtracted from the rows below; the storage of
-  // L[i][c] (c < i) is reused for X[i][c] once column c has been consumed
-  for (int q = 0; q < n; ++q) {
-    if (tid < n - q) col[q + tid] = L[q + tid][q];
-    if (tid < q) rowk[tid] = L[q][tid];
-    __syncthreads();
-    const double inv = 1.0 / col[q];
-    if (tid <= q) L[q][tid] = (tid == q) ? inv : rowk[tid] * inv;
-    for (int i = q + 1 + ty; i < n; i += 16) {
-      const double f = col[i] * inv;
-      for (int c = tx; c <= q; c += 32) L[i][c] = (c == q) ? -f : L[i][c] - f * rowk[c];
-    }
-    __syncthreads();
+  if (wv == 0) wave_trtri64<0>(L, 0, ly, lx, lane);   // X11 = L11^{-1} in place
+  __syncthreads();
+  f64x4 acc[2][2];
+  // L21 = A21 X11^T
+  lds_mm64<true>(L, 64, 0, 0, 0, wy, wx, lane, acc);
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        L[64 + SORF_MM_ROW(wy, x, lane, r)][SORF_MM_COL(wx, y, lane)] = acc[x][y][r];
+  __syncthreads();
+  // A22 -= L21 L21^T (lower part)
+  lds_mm64<true>(L, 64, 0, 64, 0, wy, wx, lane, acc);
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = SORF_MM_ROW(wy, x, lane, r), j = SORF_MM_COL(wx, y, lane);
+        if (j <= i) L[64 + i][64 + j] -= acc[x][y][r];
+      }
+  __syncthreads();
+  if (wv == 0) wave_potrf64<0>(L, 64, ly, lx, lane, info, k + 64, n - 64);
+  __syncthreads();
+  for (int t = tid; t < 64 * NB; t += 256) {
+    const int i = 64 + (t >> 7), j = t & (NB - 1);
+    if (i < n && j <= i) A[int64_t(k + i) * D + (k + j)] = L[i][j];
   }
+  __syncthreads();
+  if (wv == 0) wave_trtri64<0>(L, 64, ly, lx, lane);   // X22 = L22^{-1} in place
+  __syncthreads();
+  // T = L21 X11, stored over L21
+  lds_mm64<false>(L, 64, 0, 0, 0, wy, wx, lane, acc);
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        L[64 + SORF_MM_ROW(wy, x, lane, r)][SORF_MM_COL(wx, y, lane)] = acc[x][y][r];
+  __syncthreads();
+  // X21 = -X22 T, stored over T
+  lds_mm64<false>(L, 64, 64, 64, 0, wy, wx, lane, acc);
+  __syncthreads();
+#pragma unroll
+  for (int x = 0; x < 2; ++x)
+#pragma unroll
+    for (int y = 0; y < 2; ++y)
+#pragma unroll
+      for (int r = 0; r < 4; ++r)
+        L[64 + SORF_MM_ROW(wy, x, lane, r)][SORF_MM_COL(wx, y, lane)] = -acc[x][y][r];
+  __syncthreads();
   double* out = Linv + int64_t(k / NB) * NB * NB;
   double* outT = LinvT + int64_t(k / NB) * NB * NB;
-  for (int t = tid; t < NB * NB; t += 512) {
+  for (int t = tid; t < NB * NB; t += 256) {
     const int i = t >> 7, j = t & (NB - 1);
     out[t] = (i < n && j <= i) ? L[i][j] : 0.0;
     outT[t] = (j < n && i <= j) ? L[j][i] : 0.0;
@@ -167,7 +335,8 @@ __global__ __launch_bounds__(256) void trsm_kernel(double* __restrict__ A, int32
   for (int c0 = 0; c0 < NB; c0 += KC) {
     for (int t = tid; t < 64 * KC; t += 256) {
       const int i = t / KC, p = t % KC;
-      sP[i][p] = (r0 + i < D) ? A[(r0 + i) * D + k + c0 + p] : 0.0;
+      const double a = A[min(r0 + i, int64_t(D) - 1) * D + k + c0 + p];
+      sP[i][p] = (r0 + i < D) ? a : 0.0;
     }
     for (int t = tid; t < NB * KC; t += 256) {
       const int j = t / KC, p = t % KC;
@@ -227,13 +396,14 @@ __global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32
   const int lr = tid >> 2;          // row 0..127 of the slab
   const int lp = (tid & 3) * 4;     // 4 consecutive k
   const bool okI = I0 + lr < D, okJ = J0 + lr < D;
-  const double* pI = A + (I0 + lr) * D + k + lp;
-  const double* pJ = A + (J0 + lr) * D + k + lp;
+  const double* pI = A + min(I0 + lr, int64_t(D) - 1) * D + k + lp;
+  const double* pJ = A + min(J0 + lr, int64_t(D) - 1) * D + k + lp;
   double rI[4], rJ[4];
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    rI[q] = okI ? pI[q] : 0.0;
-    rJ[q] = (!diag && okJ) ? pJ[q] : 0.0;
+    const double a = pI[q], b = pJ[q];
+    rI[q] = okI ? a : 0.0;
+    rJ[q] = okJ ? b : 0.0;
   }
   for (int c0 = 0; c0 < NB; c0 += KC) {
 #pragma unroll
@@ -245,8 +415,9 @@ __global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32
     if (c0 + KC < NB) {
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        rI[q] = okI ? pI[c0 + KC + q] : 0.0;
-        rJ[q] = (!diag && okJ) ? pJ[c0 + KC + q] : 0.0;
+        const double a = pI[c0 + KC + q], b = pJ[c0 + KC + q];
+        rI[q] = okI ? a : 0.0;
+        rJ[q] = okJ ? b : 0.0;
       }
     }
     const double (*sb)[KC + 1] = diag ? sI : sJ;
@@ -280,32 +451,58 @@ __global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32
       }
 }
 
-// out[i] = sum_p M[i][p] v[p] for a 128 x 128 block M stored row-major (the
-// zero half of a triangular block contributes nothing): one wave per row,
-// lanes read the row as two coalesced 512-byte loads, wave-sum by xor shuffles.
-static __device__ void block_mv(const double* __restrict__ M, const double* v, int n,
-                                double* out_global, int tid, int nthreads) {
-  const int lane = tid & 63, wv = tid >> 6, nw = nthreads >> 6;
-  const double v0 = lane < n ? v[lane] : 0.0;
-  const double v1 = lane + 64 < n ? v[lane + 64] : 0.0;
-  for (int i = wv; i < n; i += nw) {
-    const double* row = M + i * NB;
-    double s = (lane < n ? row[lane] * v0 : 0.0) + (lane + 64 < n ? row[lane + 64] * v1 : 0.0);
+// out[i] = sum_p MT[p][i] v[p] for a 128 x 128 block MT stored row-major and
+// zero outside the block's n x n part; v (LDS) must be zero past n.
+// Thread (i, h) of 256 issues its 64 coalesced loads (lanes run over i) at
+// once and sums p in [64 h, 64 h + 64); the halves are added in a fixed order.
+// No cross-lane reductions. `part` is 128 doubles of LDS scratch.
+static __device__ __forceinline__ void block_mvT(const double* __restrict__ MT, const double* v,
+                                                 int n, double* __restrict__ out_global,
+                                                 double* part, int tid) {
+  const int i = tid & 127, h = tid >> 7;
+  double a[64];
 #pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) out_global[i] = s;
+  for (int t = 0; t < 64; ++t) a[t] = MT[(64 * h + t) * NB + i];
+  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+#pragma unroll
+  for (int t = 0; t < 64; t += 4) {
+    s0 += a[t] * v[64 * h + t];
+    s1 += a[t + 1] * v[64 * h + t + 1];
+    s2 += a[t + 2] * v[64 * h + t + 2];
+    s3 += a[t + 3] * v[64 * h + t + 3];
   }
+  const double s = (s0 + s1) + (s2 + s3);
+  if (h == 1) part[i] = s;
+  __syncthreads();
+  if (h == 0 && i < n) out_global[i] = s + part[i];
+}
+
+// Reduce-scatter of 32 per-lane partial sums over the 64 lanes of a wave:
+// afterwards lanes 2 r and 2 r + 1 both hold the full sum of row r.
+static __device__ __forceinline__ double reduce_scatter32(double (&p)[32], int lane) {
+#pragma unroll
+  for (int lvl = 0; lvl < 5; ++lvl) {
+    const int mask = 32 >> lvl, half = 16 >> lvl;
+    const bool upper = (lane & mask) != 0;
+#pragma unroll
+    for (int r = 0; r < half; ++r) {
+      const double keep = upper ? p[r + half] : p[r];
+      const double send = upper ? p[r] : p[r + half];
+      p[r] = keep + __shfl_xor(send, mask);
+    }
+  }
+  return p[0] + __shfl_xor(p[0], 1);
 }
 
 // y_0 = L_00^{-1} b_0 (first block of the forward sweep)
-__global__ __launch_bounds__(256) void trsv_fwd_first_kernel(const double* __restrict__ Linv,
+__global__ __launch_bounds__(256) void trsv_fwd_first_kernel(const double* __restrict__ LinvT,
                                                             int32_t D, const double* __restrict__ b,
                                                             double* __restrict__ y) {
-  __shared__ double v[NB];
+  __shared__ double v[NB], part[NB];
   const int n = D < NB ? D : NB;
-  if (threadIdx.x < n) v[threadIdx.x] = b[threadIdx.x];
+  if (threadIdx.x < NB) v[threadIdx.x] = threadIdx.x < n ? b[min(int(threadIdx.x), n - 1)] : 0.0;
   __syncthreads();
-  block_mv(Linv, v, n, y, threadIdx.x, 256);
+  block_mvT(LinvT, v, n, y, part, threadIdx.x);
 }
 
 // Forward sweep, block row k (y_k already in y): rows i >= k + n get
@@ -313,82 +510,91 @@ __global__ __launch_bounds__(256) void trsv_fwd_first_kernel(const double* __res
 // 512-byte row reads). Workgroup 0 owns exactly the next block, so after its
 // update it solves that block: y_{k+n} = L^{-1} b_{k+n}.
 __global__ __launch_bounds__(256) void trsv_fwd_kernel(const double* __restrict__ A,
-                                                      const double* __restrict__ Linv, int32_t D,
+                                                      const double* __restrict__ LinvT, int32_t D,
                                                       int32_t k, double* __restrict__ b,
                                                       double* __restrict__ y) {
-  __shared__ double vk[NB];
+  __shared__ double vk[NB], part[NB];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int n = (D - k) < NB ? (D - k) : NB;
-  const double y0 = lane < n ? y[k + lane] : 0.0;
-  const double y1 = lane + 64 < n ? y[k + 64 + lane] : 0.0;
-  const int64_t r0 = int64_t(k) + n + int64_t(blockIdx.x) * 128;
+  const double y0 = y[k + lane];        // this launch only runs for full blocks
+  const double y1 = y[k + 64 + lane];
+  const int64_t r0 = int64_t(k) + NB + int64_t(blockIdx.x) * 128;
+  double pr[32];
+#pragma unroll
   for (int r = 0; r < 32; ++r) {
     const int64_t i = r0 + wv * 32 + r;
-    if (i >= D) break;
-    const double* row = A + i * D + k;
-    double s = (lane < n ? row[lane] * y0 : 0.0) + (lane + 64 < n ? row[lane + 64] * y1 : 0.0);
-#pragma unroll
-    for (int o = 32; o >= 1; o >>= 1) s += __shfl_xor(s, o);
-    if (lane == 0) b[i] -= s;
+    const double* row = A + (i < D ? i : D - 1) * D + k;
+    const double v = row[lane] * y0 + row[lane + 64] * y1;
+    pr[r] = i < D ? v : 0.0;
   }
-  if (blockIdx.x != 0 || r0 >= D) return;
+  const double tot = reduce_scatter32(pr, lane);
+  {
+    const int64_t i = r0 + wv * 32 + (lane >> 1);
+    if ((lane & 1) == 0 && i < D) b[i] -= tot;
+  }
+  if (blockIdx.x != 0) return;
   __threadfence_block();
   __syncthreads();
   const int64_t kn = r0;  // next block start
   const int nn = (D - kn) < NB ? int(D - kn) : NB;
-  if (tid < nn) vk[tid] = b[kn + tid];
+  if (tid < NB) vk[tid] = tid < nn ? b[kn + min(tid, nn - 1)] : 0.0;
   __syncthreads();
-  block_mv(Linv + (kn / NB) * NB * NB, vk, nn, y + kn, tid, 256);
+  block_mvT(LinvT + (kn / NB) * NB * NB, vk, nn, y + kn, part, tid);
 }
 
 // x_last = L_last^{-T} c_last (first block of the backward sweep)
-__global__ __launch_bounds__(256) void trsv_bwd_first_kernel(const double* __restrict__ LinvT,
+__global__ __launch_bounds__(256) void trsv_bwd_first_kernel(const double* __restrict__ Linv,
                                                             int32_t D, const double* __restrict__ c,
                                                             double* __restrict__ x) {
-  __shared__ double v[NB];
+  __shared__ double v[NB], part[NB];
   const int k = ((D - 1) / NB) * NB;
   const int n = D - k;
-  if (threadIdx.x < n) v[threadIdx.x] = c[k + threadIdx.x];
+  if (threadIdx.x < NB) v[threadIdx.x] = threadIdx.x < n ? c[k + min(int(threadIdx.x), n - 1)] : 0.0;
   __syncthreads();
-  block_mv(LinvT + (k / NB) * NB * NB, v, n, x + k, threadIdx.x, 256);
+  block_mvT(Linv + (k / NB) * NB * NB, v, n, x + k, part, threadIdx.x);
 }
 
 // Backward sweep, block row k (x_k already in x): rows i < k get
-// c_i -= sum_p L[k + p][i] x_k[p] (one thread per row, coalesced over i).
-// The last workgroup owns exactly rows [k - NB, k), so after its update it
-// solves that block: x_{k-NB} = L^{-T} c_{k-NB}.
-__global__ __launch_bounds__(128) void trsv_bwd_kernel(const double* __restrict__ A,
-                                                      const double* __restrict__ LinvT, int32_t D,
+// c_i -= sum_p L[k + p][i] x_k[p]. A workgroup owns 64 rows; thread (r, q)
+// sums p in [32 q, 32 q + 32) with all 32 loads in flight (coalesced over i),
+// and the four partial sums are combined in a fixed order. The rows of the
+// next block [k - NB, k) belong to two workgroups, so that block is solved by
+// a separate small launch afterwards.
+__global__ __launch_bounds__(256) void trsv_bwd_kernel(const double* __restrict__ A, int32_t D,
                                                       int32_t k, double* __restrict__ c,
-                                                      double* __restrict__ x) {
+                                                      const double* __restrict__ x) {
   __shared__ double xk[NB];
-  __shared__ double vk[NB];
+  __shared__ double part[4][64];
   const int tid = threadIdx.x;
+  const int r = tid & 63, q = tid >> 6;
   const int n = (D - k) < NB ? (D - k) : NB;
-  if (tid < n) xk[tid] = x[k + tid];
+  if (tid < NB) xk[tid] = tid < n ? x[k + min(tid, n - 1)] : 0.0;
   __syncthreads();
-  const int64_t i = int64_t(blockIdx.x) * 128 + tid;
-  if (i < k) {
-    double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-    int p = 0;
-    for (; p + 3 < n; p += 4) {
-      s0 += A[int64_t(k + p) * D + i] * xk[p];
-      s1 += A[int64_t(k + p + 1) * D + i] * xk[p + 1];
-      s2 += A[int64_t(k + p + 2) * D + i] * xk[p + 2];
-      s3 += A[int64_t(k + p + 3) * D + i] * xk[p + 3];
-    }
-    for (; p < n; ++p) s0 += A[int64_t(k + p) * D + i] * xk[p];
-    c[i] -= (s0 + s1) + (s2 + s3);
+  const int64_t i = int64_t(blockIdx.x) * 64 + r;
+  const int64_t ic = i < k ? i : k - 1;
+  double a[32];
+#pragma unroll
+  for (int t = 0; t < 32; ++t) a[t] = A[int64_t(k + min(32 * q + t, n - 1)) * D + ic];
+  double s0 = 0.0, s1 = 0.0;
+#pragma unroll
+  for (int t = 0; t < 32; t += 2) {
+    s0 += a[t] * xk[32 * q + t];
+    s1 += a[t + 1] * xk[32 * q + t + 1];
   }
-  if (int64_t(blockIdx.x) + 1 != int64_t(gridDim.x) || k == 0) return;
-  __threadfence_block();
+  part[q][r] = s0 + s1;
   __syncthreads();
-  const int kp = k - NB;  // previous block start (full block)
-  vk[tid] = c[kp + tid];
+  if (q == 0 && i < k) c[i] -= ((part[0][r] + part[1][r]) + part[2][r]) + part[3][r];
+}
+
+// x_kp = L_kp^{-T} c_kp for the block that the previous sweep launch finished
+__global__ __launch_bounds__(256) void trsv_bwd_block_kernel(const double* __restrict__ Linv,
+                                                            int32_t kp, const double* __restrict__ c,
+                                                            double* __restrict__ x) {
+  __shared__ double v[NB], part[NB];
+  if (threadIdx.x < NB) v[threadIdx.x] = c[kp + threadIdx.x];
   __syncthreads();
-  block_mv(LinvT + (kp / NB) * NB * NB, vk, NB, x + kp, tid, 128);
+  block_mvT(Linv + (kp / NB) * NB * NB, v, NB, x + kp, part, threadIdx.x);
 }
 
 // Partial sums of (lower-stored symmetric G) x over 64 x 64 tiles:
@@ -463,17 +669,18 @@ __global__ void axpy_kernel(double* __restrict__ x, const double* __restrict__ d
 static hipError_t solve_triangular(const SolveWs& w, int32_t D, double* rhs, double* tmp,
                                    double* out, hipStream_t st) {
   // L tmp = rhs (rhs overwritten), then L^T out = tmp (tmp overwritten)
-  hipLaunchKernelGGL(trsv_fwd_first_kernel, dim3(1), dim3(256), 0, st, w.Linv, D, rhs, tmp);
+  hipLaunchKernelGGL(trsv_fwd_first_kernel, dim3(1), dim3(256), 0, st, w.LinvT, D, rhs, tmp);
   for (int32_t k = 0; k + NB < D; k += NB) {
     const int64_t rest = int64_t(D) - k - NB;
     hipLaunchKernelGGL(trsv_fwd_kernel, dim3(unsigned((rest + 127) / 128)), dim3(256), 0, st,
-                       w.A, w.Linv, D, k, rhs, tmp);
+                       w.A, w.LinvT, D, k, rhs, tmp);
   }
-  hipLaunchKernelGGL(trsv_bwd_first_kernel, dim3(1), dim3(256), 0, st, w.LinvT, D, tmp, out);
+  hipLaunchKernelGGL(trsv_bwd_first_kernel, dim3(1), dim3(256), 0, st, w.Linv, D, tmp, out);
   const int32_t last = ((D - 1) / NB) * NB;
   for (int32_t k = last; k > 0; k -= NB) {
-    hipLaunchKernelGGL(trsv_bwd_kernel, dim3(unsigned((int64_t(k) + 127) / 128)), dim3(128), 0,
-                       st, w.A, w.LinvT, D, k, tmp, out);
+    hipLaunchKernelGGL(trsv_bwd_kernel, dim3(unsigned((int64_t(k) + 63) / 64)), dim3(256), 0, st,
+                       w.A, D, k, tmp, out);
+    hipLaunchKernelGGL(trsv_bwd_block_kernel, dim3(1), dim3(256), 0, st, w.Linv, k - NB, tmp, out);
   }
   return hipGetLastError();
 }
@@ -487,7 +694,7 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
   hipLaunchKernelGGL(promote_kernel<TG>, dim3(vg, unsigned(D)), dim3(256), 0, st, G, D, lambda,
                      w.A, info);
   for (int32_t k = 0; k < D; k += NB) {
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(512), 0, st, w.A, D, k, info, w.Linv,
+    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, k, info, w.Linv,
                        w.LinvT);
     const int64_t rest = int64_t(D) - k - NB;
     if (rest > 0) {
