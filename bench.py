@@ -8,6 +8,10 @@ energies E = Z alpha without forming Z (sorf_predict) and dE/dx for every atom
 (sorf_backward). Inputs are synthetic, seeded, and resident in HBM before the
 clock starts.
 
+A serving leg follows: a Poisson trace of energy+force requests (D = 16384,
+5..300 atoms) served by continuous batching and by one molecule per launch;
+p50/p99 latency and atoms/s of both are reported under "serving".
+
 Prints one JSON line (rank 0, N = 1 only).
 """
 from __future__ import annotations
@@ -57,7 +61,60 @@ def parse():
     ap.add_argument("--lam", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-mols", type=int, default=64)
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="length of the Poisson request trace (0 skips the serving leg)")
+    ap.add_argument("--serve-rate", type=float, default=2000.0)
+    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-max-atoms", type=int, default=8192)
     return ap.parse_args()
+
+
+def serving_leg(args, dev, log):
+    """Energy+force serving on the Poisson trace (D = 16384, sizes log-uniform
+    5..300 atoms): continuous batching vs one molecule per launch, same GPU,
+    same kernels, same resident model and request pool."""
+    import torch
+
+    from paper_2206_01580_amd import serve, sorf, workloads
+    tr = workloads.config5(rate_hz=args.serve_rate, duration_s=args.serve_seconds)
+    J = workloads.device_normal(tr.J_pool_floats, tr.J_seed, 0.1, device=dev)
+    pool = serve.RequestPool(tr.x, tr.element, tr.sizes, J, tr.J_off, device=dev)
+    model = sorf.Model.from_problem(tr.model)
+    alpha = torch.from_numpy(tr.model.alpha).to(dev)
+    R = len(tr.sizes)
+    cap = max(args.serve_max_atoms, int(tr.sizes.max()))
+    exb = serve.GpuExecutor(model, alpha, pool, max_batch_atoms=cap, max_batch_reqs=cap // 5 + 1,
+                            n_slots=args.serve_slots, device=dev)
+    exp = serve.GpuExecutor(model, alpha, pool, max_batch_atoms=int(tr.sizes.max()),
+                            max_batch_reqs=1, n_slots=1, device=dev)
+    # in-flight request state (workspace, energies, forces) of all slots at capacity
+    budget = args.serve_slots * (cap * exb.ws_per_atom + 4 * (cap // 5 + 1))
+    for ex in (exb, exp):        # load the kernels and touch every buffer once
+        h = ex.submit(0, 1)
+        while not h.done():
+            pass
+        ex.results.clear()
+    torch.cuda.synchronize()
+    log(f"serving: {R} requests, {int(tr.sizes.sum())} atoms, rate {args.serve_rate}/s")
+    sb = serve.BatchingScheduler(exb, cap, args.serve_slots, budget).run(tr.arrival_s, tr.sizes)
+    torch.cuda.synchronize()
+    log(f"serving: batched done ({len(sb.batches)} launches)")
+    sp = serve.PlainRunner(exp).run(tr.arrival_s, tr.sizes)
+    torch.cuda.synchronize()
+    log("serving: plain done")
+    warm = 0.1 * args.serve_seconds
+    b, p = sb.summary(warm, tr.arrival_s), sp.summary(warm, tr.arrival_s)
+    return {
+        "workload": (f"Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s, sizes "
+                     f"log-uniform 5..300 atoms, d=128, D=16384, energies + forces "
+                     f"(J blocks N x 128 x 3N at random offsets of a "
+                     f"{tr.J_pool_floats * 4 >> 20} MiB pool)"),
+        "requests": R, "atoms": int(tr.sizes.sum()), "warmup_s": warm,
+        "batched": dict(b, slots=args.serve_slots, max_batch_atoms=cap),
+        "plain": p,
+        "p50_speedup": (p["p50_ms"] / b["p50_ms"]) if b["p50_ms"] else None,
+        "p99_speedup": (p["p99_ms"] / b["p99_ms"]) if b["p99_ms"] else None,
+    }
 
 
 def cpu_baseline(p, D, n_sample, lam):
@@ -99,6 +156,9 @@ def main():
     import torch
 
     from paper_2206_01580_amd import sorf, workloads
+
+    def log(msg):
+        print(f"[bench] {msg}", file=sys.stderr, flush=True)
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
@@ -219,7 +279,12 @@ def main():
         "solve_info": info,
         "gen_s": gen_s,
     }
+    del Z, G, model, batch, predictor, solver, grad
+    torch.cuda.empty_cache()
+    if args.serve_seconds > 0:
+        out["serving"] = serving_leg(args, dev, log)
     if not args.no_cpu_baseline:
+        log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(p, D, args.cpu_sample_mols, args.lam)
     print(json.dumps(out))
 

@@ -232,21 +232,51 @@ def config3(n_conf: int = 2000, seed_offset: int = 0, with_J: bool = True) -> Pr
 
 @dataclasses.dataclass
 class ServingTrace:
-    """Arrival trace of energy+force requests plus the resident model."""
+    """Arrival trace of energy+force requests plus the resident model.
 
-    model: Problem          # parameters only (x/element/mol_ptr hold the pool)
+    Jacobian blocks (N x d x 3N floats each, N(0, 0.1)) are taken from one
+    seeded random pool: request r uses the block starting at float offset
+    J_off[r]. Their values only feed the force contraction, so a pool of
+    bounded size stands in for per-request Jacobians (which would total about
+    17 MB per mean request)."""
+
+    model: Problem          # parameters (signs, bias, alpha, sigma)
     arrival_s: np.ndarray   # float64 [R] arrival times in seconds
     sizes: np.ndarray       # int64 [R] atoms per request
+    x: np.ndarray           # float32 [sum(sizes), d]
+    element: np.ndarray     # int32 [sum(sizes)]
+    J_off: np.ndarray       # int64 [R] float offsets into the Jacobian pool
+    J_pool_floats: int      # pool size in floats
+    J_seed: int             # seed of the pool (device_normal / host_normal)
+
+    def host_J_pool(self) -> np.ndarray:
+        return host_normal(self.J_pool_floats, self.J_seed, 0.1)
+
+
+def host_normal(n: int, seed: int, std: float) -> np.ndarray:
+    """n float32 draws of N(0, std^2) from PCG64(seed)."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    return (std * rng.standard_normal(n, dtype=np.float32)).astype(np.float32)
+
+
+def device_normal(n: int, seed: int, std: float, device="cuda"):
+    """n float32 draws of N(0, std^2) generated on the device with a seeded
+    torch generator (for large pools that only feed timing runs)."""
+    import torch
+    g = torch.Generator(device=device)
+    g.manual_seed(seed)
+    return torch.randn(n, generator=g, device=device, dtype=torch.float32).mul_(std)
 
 
 def config5(rate_hz: float = 2000.0, duration_s: float = 20.0, seed_offset: int = 0,
-            max_requests: Optional[int] = None) -> ServingTrace:
-    """Serving: Poisson arrivals, sizes round(exp(U[ln 5, ln 300])), six
-    elements uniform, x ~ N(0, 1), J ~ N(0, 0.1) of shape d x 3N per atom,
-    D = 16384, sigma = 4, alpha ~ N(0, 1)."""
+            max_requests: Optional[int] = None, j_pool_floats: int = 1 << 27,
+            d: int = 128, n_stacks: int = 128) -> ServingTrace:
+    """Serving: Poisson arrivals at ``rate_hz``, sizes round(exp(U[ln 5, ln 300])),
+    six elements uniform, x ~ N(0, 1), Jacobians N(0, 0.1) of shape d x 3N per
+    atom, D = 16384 (d = 128, 128 stacks), sigma = 4, alpha ~ N(0, 1)."""
     seed = SEED_BASE + 5 + seed_offset
     rng = np.random.Generator(np.random.PCG64(seed))
-    d, S, T = 128, 128, 3
+    S, T = n_stacks, 3
     names = ("H", "C", "N", "O", "F", "S")
     gaps = rng.exponential(1.0 / rate_hz, size=int(rate_hz * duration_s * 1.2) + 16)
     t = np.cumsum(gaps)
@@ -255,19 +285,20 @@ def config5(rate_hz: float = 2000.0, duration_s: float = 20.0, seed_offset: int 
         t = t[:max_requests]
     R = len(t)
     sizes = np.rint(np.exp(rng.uniform(math.log(5.0), math.log(300.0), size=R))).astype(np.int64)
-    ptr = _ptr_from_sizes(sizes)
-    A = int(ptr[-1])
+    A = int(sizes.sum())
     element = rng.integers(0, len(names), size=A).astype(np.int32)
     x = rng.standard_normal((A, d), dtype=np.float32)
-    jsz = sizes * d * 3 * sizes
-    J_ptr = _ptr_from_sizes(jsz)
-    J = (0.1 * _jacobian_rng(seed).standard_normal(int(J_ptr[-1]), dtype=np.float32))
+    block = sizes * d * 3 * sizes
+    pool = max(int(j_pool_floats), int(block.max()) if R else 1)
+    J_off = (rng.random(R) * (pool - block + 1)).astype(np.int64) if R else np.zeros(0, np.int64)
     signs = draw_signs(rng, len(names), T, S, d)
     bias = draw_bias(rng, len(names), S * d)
     alpha = rng.standard_normal(S * d).astype(np.float32)
-    model = Problem("config5-serving", d, S, T, 4.0, names, x, element, ptr, signs,
-                    bias, alpha=alpha, J=J, J_ptr=J_ptr, seed=seed)
-    return ServingTrace(model, t, sizes)
+    ptr = _ptr_from_sizes(sizes)
+    model = Problem("config5-serving", d, S, T, 4.0, names, x, element, ptr, signs, bias,
+                    alpha=alpha, seed=seed)
+    return ServingTrace(model, t, sizes, x, element, J_off, pool,
+                        int(np.random.SeedSequence([seed, 1]).generate_state(1)[0]))
 
 
 def random_problem(seed: int, d: int, n_stacks: int, n_transforms: int = 3,
