@@ -248,7 +248,13 @@ def main():
                   "frac": chol_flop / (med["solve"] * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS["fp64"],
                   "traffic": None, "ms": med["solve"]},
     }
-    dominant = max(("gram", "forward", "backward", "solve"), key=lambda k: med[k])
+    pred_slots = (valu_slots_per_feature(p.d, p.n_transforms) + 1) * af
+    pred_tops = pred_slots / (med["predict"] * 1e-3) / 1e12
+    rooflines["predict"] = {"bound": "alu", "achieved": pred_tops, "peak": PEAK_VALU_TOPS,
+                            "unit": "T VALU-slots/s", "frac": pred_tops / PEAK_VALU_TOPS,
+                            "traffic": None, "ms": med["predict"]}
+    # the dominant single kernel launch (the solve phase is ~1000 launches of 9 kernels)
+    dominant = max(("gram", "forward", "backward", "predict"), key=lambda k: med[k])
     roof = {k: v for k, v in rooflines[dominant].items() if k != "ms"}
     roof["kernel"] = dominant
 

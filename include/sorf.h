@@ -155,7 +155,9 @@ sorf_status sorf_solve_f64(int32_t D, const double* G, const double* Zty, double
                            int32_t n_refine, double* alpha, int32_t* info, void* workspace,
                            size_t workspace_bytes, sorf_stream_t stream);
 
-/* Bytes of workspace sorf_predict needs (host-only query). */
+/* Bytes of workspace sorf_predict needs for a batch of n_atoms atoms in n_mols molecules
+ * (host-only query; nondecreasing in both, so a buffer sized for the largest batch serves
+ * every smaller one). Returns 0 for an invalid model or negative sizes. */
 size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, int64_t n_mols);
 
 /* Prediction of energies (E = Z alpha, without forming Z) and, when J is given,
@@ -163,7 +165,11 @@ size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, in
  *   alpha: [D] FP32.  E: [n_mols] FP32 out.
  *   J: concatenated per-molecule blocks, block m is [N_m][d][3 N_m] row-major
  *      (J_i = dx_i/dr_m, coordinates ordered [atom][xyz]) starting at float offset
- *      J_ptr[m]; J_ptr: [n_mols + 1] int64 device array. Both NULL for energies only.
+ *      J_ptr[m]; J_ptr: [n_mols + 1] int64 device array. Blocks may sit anywhere in J
+ *      (no order, gaps allowed; J_ptr[n_mols] is not read) and need no alignment.
+ *      Both NULL for energies only.
+ *   Each molecule's E and F are summed in an order fixed by its own atom count, so a
+ *   molecule's results are bitwise the same in any batch.
  *   F: [3 n_atoms] FP32 out ([atom][xyz]), required iff J is given.
  *   workspace: device memory of at least sorf_predict_workspace_bytes(), 256-byte aligned. */
 sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const float* alpha,

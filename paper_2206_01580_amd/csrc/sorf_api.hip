@@ -58,9 +58,10 @@ sorf_status dev(hipError_t e) { return e == hipSuccess ? SORF_OK : SORF_ERR_DEVI
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
-size_t predict_ws(const sorf_model* m, int64_t n_atoms) {
+size_t predict_ws(const sorf_model* m, int64_t n_atoms, int64_t n_mols) {
   return align256(sizeof(float) * size_t(n_atoms)) +
-         align256(sizeof(float) * size_t(n_atoms) * size_t(m->d));
+         align256(sizeof(float) * size_t(n_atoms) * size_t(m->d)) +
+         sorf_force_plan_bytes(n_atoms, n_mols);
 }
 
 }  // namespace
@@ -166,9 +167,8 @@ sorf_status sorf_solve_f64(int32_t D, const double* G, const double* Zty, double
 }
 
 size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, int64_t n_mols) {
-  (void)n_mols;
-  if (check_model(model) != SORF_OK || n_atoms < 0) return 0;
-  return predict_ws(model, n_atoms);
+  if (check_model(model) != SORF_OK || n_atoms < 0 || n_mols < 0) return 0;
+  return predict_ws(model, n_atoms, n_mols);
 }
 
 sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const float* alpha,
@@ -182,7 +182,7 @@ sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const
   if (batch->n_mols > 0 && E == nullptr) return SORF_ERR_INVALID_ARG;
   if (batch->n_atoms > 0 && alpha == nullptr) return SORF_ERR_INVALID_ARG;
   if (!aligned16(alpha)) return SORF_ERR_INVALID_ARG;
-  const size_t need = predict_ws(model, batch->n_atoms);
+  const size_t need = predict_ws(model, batch->n_atoms, batch->n_mols);
   if (batch->n_atoms > 0) {
     if (workspace == nullptr || workspace_bytes < need) return SORF_ERR_WORKSPACE;
     if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
@@ -190,11 +190,13 @@ sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const
   hipStream_t st = hipStream_t(stream);
   const SorfFeatureArgs a = pack(model, batch);
   float* e_atom = static_cast<float*>(workspace);
-  float* grad = reinterpret_cast<float*>(static_cast<char*>(workspace) +
-                                         align256(sizeof(float) * size_t(batch->n_atoms)));
+  const size_t grad_off = align256(sizeof(float) * size_t(batch->n_atoms));
+  float* grad = reinterpret_cast<float*>(static_cast<char*>(workspace) + grad_off);
+  void* plan = static_cast<char*>(workspace) + grad_off +
+               align256(sizeof(float) * size_t(batch->n_atoms) * size_t(model->d));
   hipError_t e = sorf_launch_atom_adjoint(a, alpha, nullptr, J ? grad : nullptr, e_atom, st);
   if (e != hipSuccess) return SORF_ERR_DEVICE;
-  return dev(sorf_launch_molecule_reduce(a, e_atom, grad, J, J_ptr, E, F, st));
+  return dev(sorf_launch_molecule_reduce(a, e_atom, grad, J, J_ptr, E, F, plan, st));
 }
 
 sorf_status sorf_validate_batch(const sorf_batch* batch, int32_t n_elements, int32_t* result,

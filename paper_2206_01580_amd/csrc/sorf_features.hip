@@ -178,58 +178,171 @@ __global__ __launch_bounds__(256) void atom_adjoint_kernel(
 }
 
 // ---------------------------------------------------------------------------
-// Per-molecule reduction: E_m = sum of the atoms' shares; F = -sum_i J_i^T g_i
-// grid.x = molecule, grid.y strides over 64-column blocks of the molecule's
-// 3 N_m force components; the four waves split the N_m * d Jacobian rows.
+// Per-molecule reduction: E_m = sum of the atoms' shares; F_m = -sum_i J_i^T g_i.
+//
+// The force contraction is a transposed GEMV per molecule: J_m is
+// [N_m d rows][3 N_m columns] row-major, g_m the N_m d gradient entries. A
+// molecule is cut into tiles of (64 columns) x (row chunk); the number of
+// row chunks depends on N_m only (min(ceil(N_m d / 256), 32)), so every
+// molecule is summed in the same order whatever batch it is in: results are
+// bitwise independent of batching. Three launches:
+//   plan    one block scans the molecules' tile and partial counts;
+//   partial a persistent grid walks the tile list; in a tile the four waves
+//           take every fourth row, lanes own columns, the waves are combined
+//           through LDS in fixed order into one partial row;
+//   final   F = -(sum of a molecule's partial rows in chunk order); E_m is
+//           summed over the atoms in order.
 // ---------------------------------------------------------------------------
-__global__ __launch_bounds__(256) void molecule_reduce_kernel(
-    const int64_t* __restrict__ mol_ptr, const float* __restrict__ e_atom,
-    const float* __restrict__ grad, const float* __restrict__ J, const int64_t* __restrict__ J_ptr,
-    float* __restrict__ E, float* __restrict__ F, int32_t d) {
-  __shared__ float red[4][64];
-  const int64_t m = blockIdx.x;
-  const int64_t a0 = mol_ptr[m];
-  const int64_t n = mol_ptr[m + 1] - a0;
-  if (blockIdx.y == 0 && threadIdx.x == 0 && E != nullptr) {
-    float s = 0.0f;
-    for (int64_t i = 0; i < n; ++i) s += e_atom[a0 + i];
-    E[m] = s;
-  }
-  if (J == nullptr || n == 0) return;
-  const int64_t ncol = 3 * n;
+constexpr int64_t kForceRowChunk = 256;
+constexpr int64_t kForceMaxChunks = 32;
+
+struct ForceShape {
+  int64_t nrc;    // row chunks
+  int64_t ncb;    // 64-column blocks
+  int64_t chunk;  // rows per chunk (last may be shorter)
+};
+
+__device__ __forceinline__ ForceShape force_shape(int64_t n, int32_t d) {
+  ForceShape f;
   const int64_t rows = n * d;
-  const float* __restrict__ blk = J + J_ptr[m];
-  const float* __restrict__ g = grad + a0 * d;
+  const int64_t c = (rows + kForceRowChunk - 1) / kForceRowChunk;
+  f.nrc = c < kForceMaxChunks ? c : kForceMaxChunks;
+  f.chunk = f.nrc > 0 ? (rows + f.nrc - 1) / f.nrc : 0;
+  f.ncb = (3 * n + 63) / 64;
+  return f;
+}
+
+// Largest index m in [0, count) with ptr[m] <= v, for nondecreasing ptr with
+// ptr[0] <= v < ptr[count]: that entry has ptr[m] <= v < ptr[m + 1].
+__device__ __forceinline__ int64_t upper_segment(const int64_t* __restrict__ ptr, int64_t count,
+                                                 int64_t v) {
+  int64_t lo = 0, hi = count - 1;
+  while (lo < hi) {
+    const int64_t mid = (lo + hi + 1) >> 1;
+    if (ptr[mid] <= v) lo = mid; else hi = mid - 1;
+  }
+  return lo;
+}
+
+__global__ __launch_bounds__(1024) void force_plan_kernel(const int64_t* __restrict__ mol_ptr,
+                                                          int64_t n_mols, int32_t d,
+                                                          int64_t* __restrict__ tile_start,
+                                                          int64_t* __restrict__ part_start) {
+  __shared__ int64_t st[1024];
+  __shared__ int64_t sp[1024];
+  const int tid = threadIdx.x;
+  const int64_t per = (n_mols + 1023) / 1024;
+  const int64_t b0 = int64_t(tid) * per;
+  const int64_t m0 = b0 < n_mols ? b0 : n_mols;
+  const int64_t m1 = m0 + per < n_mols ? m0 + per : n_mols;
+  int64_t t = 0, q = 0;
+  for (int64_t m = m0; m < m1; ++m) {
+    const int64_t n = mol_ptr[m + 1] - mol_ptr[m];
+    const ForceShape f = force_shape(n, d);
+    t += f.nrc * f.ncb;
+    q += f.nrc * 3 * n;
+  }
+  st[tid] = t;
+  sp[tid] = q;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    const int64_t vt = tid >= off ? st[tid - off] : 0;
+    const int64_t vp = tid >= off ? sp[tid - off] : 0;
+    __syncthreads();
+    st[tid] += vt;
+    sp[tid] += vp;
+    __syncthreads();
+  }
+  int64_t tb = st[tid] - t, pb = sp[tid] - q;
+  for (int64_t m = m0; m < m1; ++m) {
+    const int64_t n = mol_ptr[m + 1] - mol_ptr[m];
+    const ForceShape f = force_shape(n, d);
+    tile_start[m] = tb;
+    part_start[m] = pb;
+    tb += f.nrc * f.ncb;
+    pb += f.nrc * 3 * n;
+  }
+  if (tid == 1023) {
+    tile_start[n_mols] = st[1023];
+    part_start[n_mols] = sp[1023];
+  }
+}
+
+__global__ __launch_bounds__(256) void force_partial_kernel(
+    const int64_t* __restrict__ mol_ptr, int64_t n_mols, const int64_t* __restrict__ tile_start,
+    const int64_t* __restrict__ part_start, const float* __restrict__ grad,
+    const float* __restrict__ J, const int64_t* __restrict__ J_ptr, float* __restrict__ partial,
+    int32_t d) {
+  __shared__ float red[4][64];
+  const int64_t total = tile_start[n_mols];
   const int lane = threadIdx.x & 63;
   const int wv = threadIdx.x >> 6;
-  for (int64_t cb = blockIdx.y; cb * 64 < ncol; cb += gridDim.y) {
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
+    const int64_t m = upper_segment(tile_start, n_mols, t);
+    const int64_t a0 = mol_ptr[m];
+    const int64_t n = mol_ptr[m + 1] - a0;
+    const ForceShape f = force_shape(n, d);
+    const int64_t local = t - tile_start[m];
+    const int64_t rc = local / f.ncb;
+    const int64_t cb = local - rc * f.ncb;
+    const int64_t ncol = 3 * n;
+    const int64_t rows = n * d;
+    const int64_t r0 = rc * f.chunk < rows ? rc * f.chunk : rows;
+    const int64_t r1 = r0 + f.chunk < rows ? r0 + f.chunk : rows;
     const int64_t col = cb * 64 + lane;
     const bool ok = col < ncol;
+    // out-of-range lanes read the last column (in bounds) and discard it
+    const float* __restrict__ blk = J + J_ptr[m] + (ok ? col : ncol - 1);
+    const float* __restrict__ g = grad + a0 * d;
     float acc = 0.0f;
-    int64_t r = wv;
-    for (; r + 12 < rows; r += 16) {
-      float j0 = 0, j1 = 0, j2 = 0, j3 = 0;
-      if (ok) {
-        j0 = blk[(r + 0) * ncol + col];
-        j1 = blk[(r + 4) * ncol + col];
-        j2 = blk[(r + 8) * ncol + col];
-        j3 = blk[(r + 12) * ncol + col];
+    int64_t r = r0 + wv;
+    for (; r + 28 < r1; r += 32) {
+      float jv[8], gv[8];
+#pragma unroll
+      for (int k = 0; k < 8; ++k) {
+        jv[k] = blk[(r + 4 * k) * ncol];
+        gv[k] = g[r + 4 * k];
       }
-      acc = __builtin_fmaf(j0, g[r + 0], acc);
-      acc = __builtin_fmaf(j1, g[r + 4], acc);
-      acc = __builtin_fmaf(j2, g[r + 8], acc);
-      acc = __builtin_fmaf(j3, g[r + 12], acc);
+#pragma unroll
+      for (int k = 0; k < 8; ++k) acc = __builtin_fmaf(jv[k], gv[k], acc);
     }
-    for (; r < rows; r += 4) {
-      const float jv = ok ? blk[r * ncol + col] : 0.0f;
-      acc = __builtin_fmaf(jv, g[r], acc);
-    }
+    for (; r < r1; r += 4) acc = __builtin_fmaf(blk[r * ncol], g[r], acc);
     red[wv][lane] = acc;
     __syncthreads();
-    if (wv == 0 && ok) {
-      F[3 * a0 + col] = -(((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane]);
-    }
+    if (wv == 0 && ok)
+      partial[part_start[m] + rc * ncol + col] =
+          ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
     __syncthreads();
+  }
+}
+
+__global__ __launch_bounds__(256) void molecule_final_kernel(
+    const int64_t* __restrict__ mol_ptr, int64_t n_atoms, int64_t n_mols,
+    const int64_t* __restrict__ part_start, const float* __restrict__ partial,
+    const float* __restrict__ e_atom, float* __restrict__ E, float* __restrict__ F, int32_t d) {
+  const int64_t stride = int64_t(gridDim.x) * blockDim.x;
+  const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (F != nullptr) {
+    for (int64_t k = tid; k < 3 * n_atoms; k += stride) {
+      const int64_t i = k / 3;
+      const int64_t m = upper_segment(mol_ptr, n_mols, i);
+      const int64_t a0 = mol_ptr[m];
+      const int64_t n = mol_ptr[m + 1] - a0;
+      const ForceShape f = force_shape(n, d);
+      const int64_t ncol = 3 * n;
+      const float* __restrict__ p = partial + part_start[m] + (k - 3 * a0);
+      float s = 0.0f;
+      for (int64_t rc = 0; rc < f.nrc; ++rc) s += p[rc * ncol];
+      F[k] = -s;
+    }
+  }
+  if (E != nullptr) {
+    for (int64_t m = tid; m < n_mols; m += stride) {
+      const int64_t a0 = mol_ptr[m], a1 = mol_ptr[m + 1];
+      float s = 0.0f;
+      for (int64_t i = a0; i < a1; ++i) s += e_atom[i];
+      E[m] = s;
+    }
   }
 }
 
@@ -351,17 +464,41 @@ hipError_t sorf_launch_atom_adjoint(const SorfFeatureArgs& a, const float* alpha
 #undef CALL
 }
 
+size_t sorf_force_plan_bytes(int64_t n_atoms, int64_t n_mols) {
+  auto al = [](size_t b) { return (b + 255) & ~size_t(255); };
+  return 2 * al(sizeof(int64_t) * size_t(n_mols + 1)) +
+         al(sizeof(float) * size_t(kForceMaxChunks) * 3 * size_t(n_atoms));
+}
+
 hipError_t sorf_launch_molecule_reduce(const SorfFeatureArgs& a, const float* e_atom,
                                        const float* grad, const float* J, const int64_t* J_ptr,
-                                       float* E, float* F, hipStream_t st) {
+                                       float* E, float* F, void* plan_ws, hipStream_t st) {
   if (a.n_mols == 0) return hipSuccess;
-  unsigned gy = 1;
-  if (J != nullptr) {
-    const int64_t want = 2048 / (a.n_mols > 0 ? a.n_mols : 1);
-    gy = unsigned(want < 1 ? 1 : (want > 16 ? 16 : want));
+  const float* partial = nullptr;
+  const int64_t* part_start = nullptr;
+  if (J != nullptr && a.n_atoms > 0) {
+    const size_t idx = ((sizeof(int64_t) * size_t(a.n_mols + 1)) + 255) & ~size_t(255);
+    int64_t* tile_start = static_cast<int64_t*>(plan_ws);
+    int64_t* pstart = reinterpret_cast<int64_t*>(static_cast<char*>(plan_ws) + idx);
+    float* part = reinterpret_cast<float*>(static_cast<char*>(plan_ws) + 2 * idx);
+    hipLaunchKernelGGL(force_plan_kernel, dim3(1), dim3(1024), 0, st, a.mol_ptr, a.n_mols, a.d,
+                       tile_start, pstart);
+    // tiles <= sum_m 32 (3 N_m / 64 + 1) = 1.5 A + 32 M bounds the useful grid
+    const int64_t bound = (3 * a.n_atoms) / 2 + 32 * a.n_mols + 1;
+    const unsigned grid = unsigned(bound < 4096 ? bound : 4096);
+    hipLaunchKernelGGL(force_partial_kernel, dim3(grid), dim3(256), 0, st, a.mol_ptr, a.n_mols,
+                       tile_start, pstart, grad, J, J_ptr, part, a.d);
+    partial = part;
+    part_start = pstart;
   }
-  hipLaunchKernelGGL(molecule_reduce_kernel, dim3(unsigned(a.n_mols), gy), dim3(256), 0, st,
-                     a.mol_ptr, e_atom, grad, J, J_ptr, E, F, a.d);
+  const int64_t work = (F != nullptr ? 3 * a.n_atoms : 0) > a.n_mols
+                           ? 3 * a.n_atoms : a.n_mols;
+  int64_t blocks = (work + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  if (blocks < 1) blocks = 1;
+  hipLaunchKernelGGL(molecule_final_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, a.mol_ptr,
+                     a.n_atoms, a.n_mols, part_start, partial, e_atom, E,
+                     (J != nullptr && a.n_atoms > 0) ? F : nullptr, a.d);
   return hipGetLastError();
 }
 

@@ -110,7 +110,10 @@ __global__ __launch_bounds__(256) void gram_fp32_kernel(const float* __restrict_
         v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
       } else {
 #pragma unroll
-        for (int c = 0; c < 8; ++c) v[c] = (mok && col0 + c < D) ? Z[m * D + col0 + c] : 0.0f;
+        for (int c = 0; c < 8; ++c) {
+          const float zl = Z[(mok ? m : M - 1) * D + (col0 + c < D ? col0 + c : D - 1)];
+          v[c] = (mok && col0 + c < D) ? zl : 0.0f;
+        }
       }
       float* dst = (h == 0 ? &sA[lk][li] : &sB[lk][li]);
 #pragma unroll
@@ -206,11 +209,14 @@ __global__ __launch_bounds__(256) void gram_half_kernel(const float* __restrict_
     for (int h = 0; h < 2; ++h) {
       const int64_t col = (h == 0 ? I0 : J0) + li;
       u16x8 hi, lo;
+      // clamped addresses: every load is issued unconditionally, then masked
+      const int64_t colc = col < D ? col : D - 1;
 #pragma unroll
       for (int c = 0; c < 8; ++c) {
         const int64_t m = m0 + lk + c;
         const bool ok = m < M && col < D;
-        const float zr = ok ? Z[m * D + col] : 0.0f;
+        const float zl = Z[(m < M ? m : M - 1) * D + colc];
+        const float zr = ok ? zl : 0.0f;
         if (h == 0 && want_zty && ok) zacc += double(zr) * double(y[m]);
         unsigned short a, b;
         split<MODE>(zr * zscale, a, b);
@@ -323,14 +329,18 @@ __global__ __launch_bounds__(256) void gram_fp64_kernel(const float* __restrict_
   double zacc[4] = {0.0, 0.0, 0.0, 0.0};
   for (int64_t m0 = 0; m0 < M; m0 += KB) {
     const int64_t m = m0 + lk;
-    const double ym = (want_zty && m < M) ? double(y[m]) : 0.0;
+    const double yl = want_zty ? double(y[m < M ? m : M - 1]) : 0.0;
+    const double ym = (m < M) ? yl : 0.0;
 #pragma unroll
     for (int c = 0; c < 4; ++c) {
       const int64_t ci = I0 + li + c, cj = J0 + li + c;
-      const double zi = (m < M && ci < D) ? double(Z[m * D + ci]) : 0.0;
+      const int64_t mc = m < M ? m : M - 1;
+      const float zil = Z[mc * D + (ci < D ? ci : D - 1)];
+      const float zjl = Z[mc * D + (cj < D ? cj : D - 1)];
+      const double zi = (m < M && ci < D) ? double(zil) : 0.0;
       sA[lk][li + c] = zi;
       zacc[c] += zi * ym;
-      if (!diag) sB[lk][li + c] = (m < M && cj < D) ? double(Z[m * D + cj]) : 0.0;
+      if (!diag) sB[lk][li + c] = (m < M && cj < D) ? double(zjl) : 0.0;
     }
     __syncthreads();
     const double (*sb)[T64 + 1] = diag ? sA : sB;

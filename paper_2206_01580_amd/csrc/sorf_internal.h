@@ -202,9 +202,12 @@ struct SorfFeatureArgs {
 hipError_t sorf_launch_forward(const SorfFeatureArgs& a, float* Z, hipStream_t s);
 hipError_t sorf_launch_atom_adjoint(const SorfFeatureArgs& a, const float* alpha, const float* dE,
                                     float* grad_x, float* e_atom, hipStream_t s);
+// Workspace of the force contraction: tile and partial offsets per molecule
+// plus at most 32 partial rows of 3 N_m floats per molecule.
+size_t sorf_force_plan_bytes(int64_t n_atoms, int64_t n_mols);
 hipError_t sorf_launch_molecule_reduce(const SorfFeatureArgs& a, const float* e_atom,
                                        const float* grad, const float* J, const int64_t* J_ptr,
-                                       float* E, float* F, hipStream_t s);
+                                       float* E, float* F, void* plan_ws, hipStream_t s);
 hipError_t sorf_launch_validate(const SorfFeatureArgs& a, int32_t* result, hipStream_t s);
 hipError_t sorf_launch_fill(float* p, int64_t n, float v, hipStream_t s);
 

@@ -96,27 +96,28 @@ static __device__ __forceinline__ void wave_step_fence() {
 
 // In-place Cholesky of the 64 x 64 block at (o, o) by one wave. Step J is
 // unrolled at compile time: lane (ly, lx) of an 8 x 8 grid owns entries
-// (i, l) = (J+1+ly+8a, J+1+lx+8b), l <= i; it first loads all of them (at
-// clamped, always valid addresses), then updates and stores the valid ones.
-// The trailing update uses the unscaled column J; the column is scaled after.
-// Rows past the matrix were padded with the identity, so every step is
-// well defined and the padding factors to the identity.
+// (i, l) = (J+1+ly+8a, J+1+lx+8b), l <= i; it loads all of them (at clamped,
+// always valid addresses) before storing any, and since one wave issues its
+// LDS operations in order, every lane has read before any lane writes: one
+// wait per step suffices. The update uses the unscaled column J and 1/d_J;
+// the columns are scaled by 1/sqrt(d_J) in one pass at the end (piv[] keeps
+// the pivots). Rows past the matrix are padded with the identity.
 template <int J>
-static __device__ __forceinline__ void wave_potrf64(LdsBlock* L, int o, int ly, int lx, int lane,
-                                                    int32_t* info, int gbase, int nvalid) {
+static __device__ __forceinline__ void wave_potrf64_steps(LdsBlock* L, int o, int ly, int lx,
+                                                          int lane, double* piv, int32_t* info,
+                                                          int gbase, int nvalid) {
   constexpr int NA = (63 - J + 7) / 8;
   const double d = L[o + J][o + J];
   const bool bad = !(d > 0.0) || !std::isfinite(d);
   if (bad && lane == 0 && J < nvalid && *info == 0) *info = gbase + J + 1;
-  const double piv = bad ? __builtin_nan("") : std::sqrt(d);
+  if (lane == 0) piv[J] = bad ? __builtin_nan("") : std::sqrt(d);
   if constexpr (NA > 0) {
     const double rd = 1.0 / d;
     double ci[NA], cl[NA], e[NA][NA];
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
-      const int i = min(J + 1 + ly + 8 * a, 63), l = min(J + 1 + lx + 8 * a, 63);
-      ci[a] = L[o + i][o + J];
-      cl[a] = L[o + l][o + J];
+      ci[a] = L[o + min(J + 1 + ly + 8 * a, 63)][o + J];
+      cl[a] = L[o + min(J + 1 + lx + 8 * a, 63)][o + J];
     }
 #pragma unroll
     for (int a = 0; a < NA; ++a)
@@ -126,33 +127,47 @@ static __device__ __forceinline__ void wave_potrf64(LdsBlock* L, int o, int ly, 
 #pragma unroll
     for (int a = 0; a < NA; ++a) {
       const int i = J + 1 + ly + 8 * a;
+      const double f = ci[a] * rd;
 #pragma unroll
       for (int b = 0; b < NA; ++b) {
         const int l = J + 1 + lx + 8 * b;
-        if (i < 64 && l <= i) L[o + i][o + l] = e[a][b] - ci[a] * rd * cl[b];
+        if (i < 64 && l <= i) L[o + i][o + l] = e[a][b] - f * cl[b];
       }
     }
   }
   wave_step_fence();
-  {
-    const int i = J + lane;
-    const double rpiv = 1.0 / piv;
-    const double v = L[o + min(i, 63)][o + J];
-    if (i < 64) L[o + i][o + J] = (i == J) ? piv : v * rpiv;
+  if constexpr (J + 1 < 64)
+    wave_potrf64_steps<J + 1>(L, o, ly, lx, lane, piv, info, gbase, nvalid);
+}
+
+static __device__ __forceinline__ void wave_potrf64(LdsBlock* L, int o, int ly, int lx, int lane,
+                                                    double* piv, int32_t* info, int gbase,
+                                                    int nvalid) {
+  wave_potrf64_steps<0>(L, o, ly, lx, lane, piv, info, gbase, nvalid);
+  // scale column j by 1/piv[j]; the diagonal becomes piv[j]
+  for (int j = 0; j < 64; ++j) {
+    const double p = piv[j];
+    const double v = L[o + max(lane, j)][o + j];
+    if (lane > j) L[o + lane][o + j] = v / p;
+    if (lane == j) L[o + j][o + j] = p;
   }
   wave_step_fence();
-  if constexpr (J + 1 < 64) wave_potrf64<J + 1>(L, o, ly, lx, lane, info, gbase, nvalid);
 }
 
 // In-place inverse of the lower-triangular 64 x 64 block at (o, o) by one
-// wave: forward elimination of [L | I]. Step Q subtracts row Q (scaled by
-// 1/L[Q][Q]) from the rows below -- entries (i, c) = (Q+1+ly+8a, lx+8b), c < Q,
-// all loaded first -- then finalises column Q below the pivot and row Q.
+// wave: forward elimination of [L | I]. At step Q every row i > Q loses
+// L[i][Q] / L[Q][Q] times the (still unscaled) row Q of X, and column Q of X
+// below the pivot becomes -L[i][Q] / L[Q][Q]; all loads of the step precede
+// its stores (one wave, in-order LDS), so one wait per step suffices. Row Q is
+// never read again after step Q, so the rows are scaled by 1/L[Q][Q] in one
+// pass at the end. rinv[] holds the reciprocal pivots.
 template <int Q>
-static __device__ __forceinline__ void wave_trtri64(LdsBlock* L, int o, int ly, int lx, int lane) {
+static __device__ __forceinline__ void wave_trtri64_steps(LdsBlock* L, int o, int ly, int lx,
+                                                          int lane, const double* rinv) {
   constexpr int NA = (63 - Q + 7) / 8;
   constexpr int NC = (Q + 7) / 8;
-  const double inv = 1.0 / L[o + Q][o + Q];
+  const double inv = rinv[Q];
+  const double fq = L[o + min(Q + 1 + lane, 63)][o + Q];
   if constexpr (NA > 0 && NC > 0) {
     double fi[NA], rq[NC], e[NA][NC];
 #pragma unroll
@@ -175,17 +190,24 @@ static __device__ __forceinline__ void wave_trtri64(LdsBlock* L, int o, int ly, 
       }
     }
   }
+  if (Q + 1 + lane < 64) L[o + Q + 1 + lane][o + Q] = -fq * inv;
   wave_step_fence();
-  {
-    const int i = Q + 1 + lane;
-    const double vi = L[o + min(i, 63)][o + Q];
-    const double vr = L[o + Q][o + min(lane, 63)];
-    if (i < 64) L[o + i][o + Q] = -vi * inv;
-    if (lane < Q) L[o + Q][o + lane] = vr * inv;
-    if (lane == 0) L[o + Q][o + Q] = inv;
+  if constexpr (Q + 1 < 64) wave_trtri64_steps<Q + 1>(L, o, ly, lx, lane, rinv);
+}
+
+static __device__ __forceinline__ void wave_trtri64(LdsBlock* L, int o, int ly, int lx, int lane,
+                                                    double* rinv) {
+  rinv[lane] = 1.0 / L[o + lane][o + lane];
+  wave_step_fence();
+  wave_trtri64_steps<0>(L, o, ly, lx, lane, rinv);
+  // scale row Q (columns < Q) by 1/L[Q][Q]; the diagonal becomes 1/L[Q][Q]
+  for (int q = 0; q < 64; ++q) {
+    const double r = rinv[q];
+    const double v = L[o + q][o + min(lane, q)];
+    if (lane < q) L[o + q][o + lane] = v * r;
+    if (lane == q) L[o + q][o + q] = r;
   }
   wave_step_fence();
-  if constexpr (Q + 1 < 64) wave_trtri64<Q + 1>(L, o, ly, lx, lane);
 }
 
 // C = A B for 64 x 64 operands held in the LDS block, on FP64 MFMA: wave
@@ -229,6 +251,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
                                                         double* __restrict__ Linv,
                                                         double* __restrict__ LinvT) {
   __shared__ double L[NB][NB + 1];
+  __shared__ double piv[64];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int wy = wv >> 1, wx = wv & 1;
@@ -242,14 +265,14 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
     L[i][j] = (i < n && j <= i) ? a : ((i == j) ? 1.0 : 0.0);
   }
   __syncthreads();
-  if (wv == 0) wave_potrf64<0>(L, 0, ly, lx, lane, info, k, n);
+  if (wv == 0) wave_potrf64(L, 0, ly, lx, lane, piv, info, k, n);
   __syncthreads();
   for (int t = tid; t < 64 * 64; t += 256) {
     const int i = t >> 6, j = t & 63;
     if (i < n && j <= i) A[int64_t(k + i) * D + (k + j)] = L[i][j];
   }
   __syncthreads();
-  if (wv == 0) wave_trtri64<0>(L, 0, ly, lx, lane);   // X11 = L11^{-1} in place
+  if (wv == 0) wave_trtri64(L, 0, ly, lx, lane, piv);   // X11 = L11^{-1} in place
   __syncthreads();
   f64x4 acc[2][2];
   // L21 = A21 X11^T
@@ -275,14 +298,14 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
         if (j <= i) L[64 + i][64 + j] -= acc[x][y][r];
       }
   __syncthreads();
-  if (wv == 0) wave_potrf64<0>(L, 64, ly, lx, lane, info, k + 64, n - 64);
+  if (wv == 0) wave_potrf64(L, 64, ly, lx, lane, piv, info, k + 64, n - 64);
   __syncthreads();
   for (int t = tid; t < 64 * NB; t += 256) {
     const int i = 64 + (t >> 7), j = t & (NB - 1);
     if (i < n && j <= i) A[int64_t(k + i) * D + (k + j)] = L[i][j];
   }
   __syncthreads();
-  if (wv == 0) wave_trtri64<0>(L, 64, ly, lx, lane);   // X22 = L22^{-1} in place
+  if (wv == 0) wave_trtri64(L, 64, ly, lx, lane, piv);   // X22 = L22^{-1} in place
   __syncthreads();
   // T = L21 X11, stored over L21
   lds_mm64<false>(L, 64, 0, 0, 0, wy, wx, lane, acc);

@@ -202,6 +202,46 @@ def test_predict_config3_subset_with_jacobians():
         assert np.abs(Fg[sl] - Fo[sl]).max() <= 1e-5 * np.abs(Fo[sl]).max()
 
 
+def test_predict_forces_large_and_empty_molecules():
+    """Force contraction across every tiling regime: empty molecules, a 1-atom
+    molecule (3 columns), one whose rows exceed the 32-chunk cap (257 atoms at
+    d = 128: 32896 rows, 771 columns in 13 column blocks), and blocks placed out
+    of order with gaps in the Jacobian buffer."""
+    import dataclasses
+    base = W.random_problem(3900, 128, 2, 3, 3, 1, 1, 1)
+    sizes = np.array([0, 1, 257, 3, 0, 64])
+    rng = np.random.default_rng(3901)
+    A = int(sizes.sum())
+    ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    blocks = sizes * 128 * 3 * sizes
+    order = rng.permutation(len(sizes))
+    J_off = np.zeros(len(sizes), np.int64)
+    off = 7                                        # unaligned start, gaps between blocks
+    for m in order:
+        J_off[m] = off
+        off += int(blocks[m]) + 13
+    J = (0.1 * rng.standard_normal(off)).astype(np.float32)
+    p = dataclasses.replace(base, x=rng.standard_normal((A, 128)).astype(np.float32),
+                            element=rng.integers(0, 3, A).astype(np.int32), mol_ptr=ptr,
+                            alpha=rng.standard_normal(256).astype(np.float32))
+    model, batch = dev_problem(p)
+    J_ptr = np.concatenate([J_off, [-1]]).astype(np.int64)   # J_ptr[n_mols] is not read
+    E, F = S().predict(model, batch, torch.from_numpy(p.alpha).cuda(), torch.from_numpy(J).cuda(),
+                       torch.from_numpy(J_ptr).cuda())
+    torch.cuda.synchronize()
+    _check_energy(E.cpu().numpy(), p, p.alpha)
+    go = O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.alpha)
+    Fg = F.cpu().numpy()
+    for m in range(len(sizes)):
+        n = int(sizes[m])
+        if n == 0:
+            continue
+        blk = J[J_off[m]:J_off[m] + blocks[m]]
+        Fo = O.forces(go[ptr[m]:ptr[m + 1]], blk, np.array([0, blocks[m]]), np.array([0, n]))
+        sl = slice(3 * ptr[m], 3 * ptr[m + 1])
+        assert np.abs(Fg[sl] - Fo).max() <= 1e-5 * np.abs(Fo).max(), m
+
+
 def test_autograd_function_matches_central_differences():
     """SorfEnergy backward vs FP64 central differences of the oracle energy."""
     p = W.random_problem(4242, 16, 3, 3, 2, 2, 3, 2)
