@@ -3,7 +3,7 @@
 One step = one pass of the whole training + inference path over the QM9-like
 workload (20,000 molecules of 3..29 atoms, d = 128, 64 stacks -> D = 8192,
 sigma = 4): features Z (sorf_forward), normal equations G += Z^T Z, Zty += Z^T y
-(sorf_gram_accumulate), FP64 ridge solve with 3 refinement steps (sorf_solve),
+(sorf_gram_accumulate, bf16 hi+lo by default), FP64 ridge solve with 3 refinement steps (sorf_solve),
 energies E = Z alpha without forming Z (sorf_predict) and dE/dx for every atom
 (sorf_backward). Inputs are synthetic, seeded, and resident in HBM before the
 clock starts.
@@ -55,7 +55,7 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--gram", default="fp32", choices=list(PEAK_MFMA_TFLOPS))
+    ap.add_argument("--gram", default="bf16_hilo", choices=list(PEAK_MFMA_TFLOPS))
     ap.add_argument("--n-mols", type=int, default=20000)
     ap.add_argument("--n-refine", type=int, default=3)
     ap.add_argument("--lam", type=float, default=1e-6)
@@ -172,6 +172,8 @@ def main():
     Z = torch.empty(M, D, device=dev)
     G = torch.empty(D, D, device=dev, dtype=acc_t)
     Zty = torch.empty(D, device=dev, dtype=acc_t)
+    gram_ws = sorf.GramWorkspace(dev)
+    gram_ws.get(M, D, args.gram) if args.gram != "fp64" else None   # allocate before timing
     solver = sorf.Solver(D, device=dev)
     alpha = torch.empty(D, device=dev, dtype=torch.float64)
     predictor = sorf.Predictor(model, dev)
@@ -195,7 +197,8 @@ def main():
         G.zero_()
         Zty.zero_()
         mark("gram", 0)
-        sorf.gram_accumulate(Z, G, y, Zty, precision=args.gram, scale_exp=scale_exp)
+        sorf.gram_accumulate(Z, G, y, Zty, precision=args.gram, scale_exp=scale_exp,
+                             workspace=gram_ws)
         mark("gram", 1)
         mark("solve", 0)
         solver(G, Zty, args.lam, args.n_refine, out=alpha)
@@ -233,10 +236,13 @@ def main():
     bwd_slots = valu_slots_per_feature(p.d, p.n_transforms, backward=True) * af
     bwd_tops = bwd_slots / (med["backward"] * 1e-3) / 1e12
     chol_flop = D ** 3 / 3.0
+    # hi+lo modes execute four 16-bit products per algorithmic product
+    mfma_work = 4.0 if args.gram.endswith("_hilo") else 1.0
     rooflines = {
         "gram": {"bound": "mfma", "achieved": gram_tf, "peak": PEAK_MFMA_TFLOPS[args.gram],
                  "unit": "TFLOP/s", "frac": gram_tf / PEAK_MFMA_TFLOPS[args.gram], "traffic": None,
-                 "ms": med["gram"]},
+                 "ms": med["gram"], "mode": args.gram, "mfma_executed_tflops": gram_tf * mfma_work,
+                 "mfma_utilisation": gram_tf * mfma_work / PEAK_MFMA_TFLOPS[args.gram]},
         "forward": {"bound": "alu", "achieved": fwd_tops, "peak": PEAK_VALU_TOPS,
                     "unit": "T VALU-slots/s", "frac": fwd_tops / PEAK_VALU_TOPS, "traffic": None,
                     "ms": med["forward"]},
@@ -272,8 +278,8 @@ def main():
         "dtype": "f32",
         "data": "synthetic",
         "config": {"workload": "qm9-like train+infer step: 20000 molecules (3..29 atoms), d=128, "
-                               "64 stacks (D=8192), 3 transforms, sigma=4; forward, Gram, FP64 "
-                               "solve, energies, dE/dx",
+                               "64 stacks (D=8192), 3 transforms, sigma=4; forward, Gram (" + args.gram +
+                               "), FP64 solve, energies, dE/dx",
                    "n_mols": M, "n_atoms": A, "D": D, "gram": args.gram, "lambda": args.lam,
                    "n_refine": args.n_refine},
         "roofline": roof,
@@ -285,7 +291,7 @@ def main():
         "solve_info": info,
         "gen_s": gen_s,
     }
-    del Z, G, model, batch, predictor, solver, grad
+    del Z, G, model, batch, predictor, solver, grad, gram_ws
     torch.cuda.empty_cache()
     if args.serve_seconds > 0:
         out["serving"] = serving_leg(args, dev, log)

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SORF_ABI_VERSION 1
+#define SORF_ABI_VERSION 2
 
 typedef void* sorf_stream_t; /* a hipStream_t */
 
@@ -112,16 +112,29 @@ sorf_status sorf_forward(const sorf_model* model, const sorf_batch* batch, float
 sorf_status sorf_backward(const sorf_model* model, const sorf_batch* batch, const float* alpha,
                           const float* dE, float* grad_x, sorf_stream_t stream);
 
-/* Normal-equation accumulation (regularised normal equation):
+/* Bytes of workspace sorf_gram_accumulate needs for n_rows rows of D features in the given
+ * precision (host-only query): the FP32 mode needs only the Z^T y partials (D * 8 bytes per
+ * 1024 rows); the 16-bit modes also hold Z packed once in matrix-core fragment order
+ * (2 bytes per entry per part, rows padded to 32 and columns to 256). 0 for invalid sizes. */
+size_t sorf_gram_workspace_bytes(int64_t n_rows, int32_t D, sorf_gram_precision precision);
+
+/* Normal-equation accumulation (RFF subsection, regularised normal equation):
  *   G[i][j] += sum_m Z[m][i] * Z[m][j]   for i >= j only (the strict upper triangle of G is
  *                                         neither read nor written),
- *   Zty[i]  += sum_m Z[m][i] * y[m]       (FP32, skipped when y is NULL).
- *   Z: [n_rows][D] row-major; G: [D][D] row-major. scale_exp: the FP16 modes split
- *   2^scale_exp * Z into parts and scale G back by 2^(-2*scale_exp) exactly (keeps the
- *   low part out of the fp16 subnormal range); must be 0 for the other modes, |scale_exp| <= 60. */
+ *   Zty[i]  += sum_m Z[m][i] * y[m]       (FP64 sums added to the FP32 Zty; skipped when y
+ *                                         is NULL).
+ *   Z: [n_rows][D] row-major, 16-byte aligned; G: [D][D] row-major.
+ *   Every mode sums 256 rows at a time on the matrix cores and adds those partial sums in
+ *   FP32 with round-to-nearest, so no long matrix-core accumulation drifts.
+ *   scale_exp: the FP16 modes split 2^scale_exp * Z into parts and scale G back by
+ *   2^(-2*scale_exp) exactly (keeps the low part out of the fp16 subnormal range); must be
+ *   0 for the other modes, |scale_exp| <= 60.
+ *   workspace: device memory of at least sorf_gram_workspace_bytes(n_rows, D, precision),
+ *   256-byte aligned (may be NULL when that is 0). Results are deterministic. */
 sorf_status sorf_gram_accumulate(int64_t n_rows, int32_t D, const float* Z, const float* y,
                                  sorf_gram_precision precision, int32_t scale_exp, float* G,
-                                 float* Zty, sorf_stream_t stream);
+                                 float* Zty, void* workspace, size_t workspace_bytes,
+                                 sorf_stream_t stream);
 
 /* Double-precision normal equations (the paper's DP training mode; FP32 storage of
  * G cannot hold a ridge lambda far below 2^-24 * ||G|| -- e.g. lambda = 1e-6 on a

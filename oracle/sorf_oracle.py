@@ -109,9 +109,10 @@ def _molecule_index(mol_ptr: np.ndarray) -> np.ndarray:
     return np.repeat(np.arange(len(sizes)), sizes)
 
 
-def phases(x, element, signs, bias, sigma, atoms=None) -> np.ndarray:
-    """u_i = W_{e_i} x_i + b_{e_i} for the atoms listed (all by default);
-    returns [len(atoms), D] float64."""
+def phases(x, element, signs, bias, sigma, atoms=None, cols=None) -> np.ndarray:
+    """u_i = W_{e_i} x_i + b_{e_i} for the atoms listed (all by default),
+    restricted to the feature columns ``cols`` (all by default); returns
+    [len(atoms), len(cols)] float64."""
     x = np.asarray(x, dtype=np.float64)
     element = np.asarray(element)
     if atoms is None:
@@ -119,33 +120,37 @@ def phases(x, element, signs, bias, sigma, atoms=None) -> np.ndarray:
     atoms = np.asarray(atoms, dtype=np.int64)
     E = signs.shape[0]
     D = signs.shape[2] * signs.shape[3]
-    u = np.empty((len(atoms), D), dtype=np.float64)
+    cols = np.arange(D) if cols is None else np.asarray(cols, dtype=np.int64)
+    u = np.empty((len(atoms), len(cols)), dtype=np.float64)
     for e in range(E):
         sel = np.nonzero(element[atoms] == e)[0]
         if len(sel) == 0:
             continue
-        W = dense_w(signs[e], sigma)
-        u[sel] = x[atoms[sel]] @ W.T + np.asarray(bias[e], dtype=np.float64)
+        W = dense_w(signs[e], sigma)[cols]
+        u[sel] = x[atoms[sel]] @ W.T + np.asarray(bias[e], dtype=np.float64)[cols]
     return u
 
 
-def atom_features(x, element, signs, bias, sigma, atoms=None) -> np.ndarray:
-    """z(x_i) = sqrt(2/D) cos(W_{e_i} x_i + b_{e_i}) (feature-map equation)."""
-    u = phases(x, element, signs, bias, sigma, atoms)
-    return math.sqrt(2.0 / u.shape[1]) * np.cos(u)
+def atom_features(x, element, signs, bias, sigma, atoms=None, cols=None) -> np.ndarray:
+    """z(x_i) = sqrt(2/D) cos(W_{e_i} x_i + b_{e_i}) (feature-map equation),
+    D being the total number of features even when only ``cols`` are formed."""
+    D = signs.shape[2] * signs.shape[3]
+    u = phases(x, element, signs, bias, sigma, atoms, cols)
+    return math.sqrt(2.0 / D) * np.cos(u)
 
 
 def molecule_features(x, element, mol_ptr, signs, bias, sigma, mols=None,
-                      chunk_atoms: int = 4096) -> np.ndarray:
+                      chunk_atoms: int = 4096, cols=None) -> np.ndarray:
     """Rows Z_m = sum over the atoms of molecule m of z(x_i) (atomic energy
     decomposition: E_m = sum_I alpha^T z(rho_I) = Z_m alpha).
-    ``mols`` selects rows (all by default); returns [len(mols), D]."""
+    ``mols`` selects rows and ``cols`` feature columns (all by default);
+    returns [len(mols), len(cols)]."""
     mol_ptr = np.asarray(mol_ptr, dtype=np.int64)
     M = len(mol_ptr) - 1
     if mols is None:
         mols = np.arange(M)
     mols = np.asarray(mols, dtype=np.int64)
-    D = signs.shape[2] * signs.shape[3]
+    D = signs.shape[2] * signs.shape[3] if cols is None else len(cols)
     Z = np.zeros((len(mols), D), dtype=np.float64)
     # gather the atoms of the selected molecules, remember which row they feed
     atom_lists = [np.arange(mol_ptr[m], mol_ptr[m + 1]) for m in mols]
@@ -154,7 +159,7 @@ def molecule_features(x, element, mol_ptr, signs, bias, sigma, mols=None,
     atoms = np.concatenate(atom_lists) if len(mols) else np.zeros(0, np.int64)
     for c0 in range(0, len(atoms), chunk_atoms):
         sl = slice(c0, c0 + chunk_atoms)
-        z = atom_features(x, element, signs, bias, sigma, atoms[sl])
+        z = atom_features(x, element, signs, bias, sigma, atoms[sl], cols)
         np.add.at(Z, rows[sl], z)
     return Z
 

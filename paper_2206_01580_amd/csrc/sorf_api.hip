@@ -102,9 +102,16 @@ sorf_status sorf_backward(const sorf_model* model, const sorf_batch* batch, cons
                                       hipStream_t(stream)));
 }
 
+size_t sorf_gram_workspace_bytes(int64_t n_rows, int32_t D, sorf_gram_precision precision) {
+  if (n_rows < 0 || D < 1 || D > (1 << 20)) return 0;
+  if (int(precision) < 0 || int(precision) > 4) return 0;
+  return sorf_gram_ws_bytes(n_rows, D, int(precision));
+}
+
 sorf_status sorf_gram_accumulate(int64_t n_rows, int32_t D, const float* Z, const float* y,
                                  sorf_gram_precision precision, int32_t scale_exp, float* G,
-                                 float* Zty, sorf_stream_t stream) {
+                                 float* Zty, void* workspace, size_t workspace_bytes,
+                                 sorf_stream_t stream) {
   if (n_rows < 0 || D < 1 || D > (1 << 20)) return SORF_ERR_INVALID_ARG;
   if (int(precision) < 0 || int(precision) > 4) return SORF_ERR_INVALID_ARG;
   if (scale_exp < -60 || scale_exp > 60) return SORF_ERR_INVALID_ARG;
@@ -117,7 +124,12 @@ sorf_status sorf_gram_accumulate(int64_t n_rows, int32_t D, const float* Z, cons
   if (int64_t(D) * D > (int64_t(1) << 36)) return SORF_ERR_UNSUPPORTED;
   hipStream_t st = hipStream_t(stream);
   if (n_rows == 0) return SORF_OK;
-  return dev(sorf_launch_gram(n_rows, D, Z, y, int(precision), scale_exp, G, Zty, st));
+  const size_t need = sorf_gram_ws_bytes(n_rows, D, int(precision));
+  if (need > 0) {
+    if (workspace == nullptr || workspace_bytes < need) return SORF_ERR_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  }
+  return dev(sorf_launch_gram(n_rows, D, Z, y, int(precision), scale_exp, G, Zty, workspace, st));
 }
 
 sorf_status sorf_gram_accumulate_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,

@@ -1,20 +1,34 @@
 // Normal-equation accumulation G += Z^T Z, Zty += Z^T y on gfx950 MFMA.
 //
 // Paper: arXiv 2206.01580, RFF subsection (regularised normal equation; the
-// Z^T Z product dominates training) and Training-time discussion (FP32 Z^T Z
-// suffers cumulative round-off; the paper uses Kahan summation). Here the
-// reduced-precision modes split each FP32 value z into hi = round(z) and
-// lo = round(z - hi) in bf16 or fp16 and accumulate (hi + lo)^T (hi + lo) =
-// hi^T hi + hi^T lo + lo^T hi + lo^T lo in FP32 on the matrix cores. All four
-// products are kept: without lo^T lo the result is G - lo^T lo, which is not
-// positive semidefinite, and on the QM9-like workload its smallest
-// eigenvalues fall below zero by more than any useful ridge term.
+// Z^T Z product dominates training) and Timings (FP32 Z^T Z suffers cumulative
+// round-off, which the paper counters with Kahan summation; DP training).
 //
-// Tiling: one workgroup (4 waves) per 128 x 128 tile (I, J) of the lower
-// triangle of G; the tile walks all rows of Z in slabs of 16 rows staged
-// through LDS; each wave owns a 64 x 64 quadrant = 2 x 2 MFMA 32x32 blocks.
-// Z^T y is accumulated (in FP64) by the diagonal tiles, which already read
-// every row of their column block, and added once per call in FP32.
+// Modes. FP32: FP32 operands on v_mfma_f32_32x32x2f32. BF16/FP16 x1: one
+// 16-bit product hi^T hi. hi+lo: z = hi + lo with hi = round(z),
+// lo = round(z - hi) in bf16 or fp16 and G accumulates all four products
+// hi^T hi + hi^T lo + lo^T hi + lo^T lo, i.e. the Gram of hi + lo, which is
+// positive semidefinite (dropping lo^T lo is not).
+//
+// Accumulation. A matrix-core accumulator that has grown large loses the low
+// bits of small addends with a bias: over 20,000 QM9-like rows the single
+// running accumulator of the hi+lo modes drifted by about -3e-7 sqrt(G_ii
+// G_jj) off the diagonal, enough to make G + 1e-6 I indefinite. Here every
+// mode accumulates 256 rows at a time in a fresh MFMA accumulator P and adds
+// P into an FP32 sum S with ordinary round-to-nearest VALU adds (a blocked
+// summation in the spirit of the paper's compensated sum); this also cuts
+// the FP32 mode's error by an order of magnitude.
+//
+// Work split. One workgroup (4 waves, 2 x 2) per 256 x 128 tile (I, J) of the
+// lower triangle; each wave owns 128 x 64 = 4 x 2 MFMA 32x32 blocks. Tiles
+// are numbered row by row and dealt to the 8 XCDs in contiguous runs, so
+// the tiles running together on one XCD share the A panel in its L2.
+// The 16-bit modes first pack Z once into MFMA fragment order (one 1 KB
+// fragment per 16 rows x 32 columns: lane l holds rows 8(l/32)..8(l/32)+7 of
+// column l%32), so the Gram kernel streams contiguous fragments through LDS
+// with no per-tile conversion. The pack kernel also forms Z^T y in FP64
+// (per-chunk partials summed in a fixed order); the FP32 mode runs it for
+// Z^T y only and stages row-major Z slabs directly.
 #include <cmath>
 
 #include "sorf_internal.h"
@@ -28,17 +42,13 @@ typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
 enum GramMode { kFP32 = 0, kBF16 = 1, kFP16 = 2, kBF16HiLo = 3, kFP16HiLo = 4 };
 
-constexpr int TILE = 128;
-constexpr int KB = 16;
+constexpr int KB = 16;                 // rows per fragment / FP32 stage
+constexpr int TM = 256, TN = 128;      // workgroup tile
+constexpr int kFlushRows = 256;        // rows per fresh MFMA accumulator
+constexpr int kPackSlabs = 64;         // 16-row slabs per pack workgroup (Z^T y chunk)
 
-__device__ __forceinline__ void tile_of(int64_t t, int64_t& I, int64_t& J) {
-  // t enumerates (I, J), I >= J, row by row: t = I (I + 1) / 2 + J
-  int64_t i = int64_t((std::sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
-  while (i * (i + 1) / 2 > t) --i;
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  I = i;
-  J = t - i * (i + 1) / 2;
-}
+__host__ __device__ constexpr bool is_hilo(int mode) { return mode == kBF16HiLo || mode == kFP16HiLo; }
+__host__ __device__ constexpr bool is_bf(int mode) { return mode == kBF16 || mode == kBF16HiLo; }
 
 // round-to-nearest-even conversions, returned as raw 16-bit patterns
 __device__ __forceinline__ unsigned short to_bf16_bits(float f) {
@@ -52,7 +62,7 @@ __device__ __forceinline__ float from_bf16_bits(unsigned short h) {
 
 template <int MODE>
 __device__ __forceinline__ void split(float z, unsigned short& hi, unsigned short& lo) {
-  if constexpr (MODE == kBF16 || MODE == kBF16HiLo) {
+  if constexpr (is_bf(MODE)) {
     hi = to_bf16_bits(z);
     lo = to_bf16_bits(z - from_bf16_bits(hi));
   } else {
@@ -63,237 +73,516 @@ __device__ __forceinline__ void split(float z, unsigned short& hi, unsigned shor
   }
 }
 
-// ----------------------------------------------------------------- FP32 mode
-template <bool VEC4>
-__global__ __launch_bounds__(256) void gram_fp32_kernel(const float* __restrict__ Z, int64_t M,
-                                                       int32_t D, float* __restrict__ G,
-                                                       const float* __restrict__ y,
-                                                       float* __restrict__ Zty) {
-  __shared__ float sA[KB][TILE + 4];
-  __shared__ float sB[KB][TILE + 4];
-  __shared__ double zred[KB][TILE];
-  int64_t I, J;
-  tile_of(blockIdx.x, I, J);
-  const bool diag = (I == J);
-  const int64_t I0 = I * TILE, J0 = J * TILE;
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wv = tid >> 6;
-  const int wy = wv >> 1, wx = wv & 1;
+template <int MODE>
+__device__ __forceinline__ f32x16 mma16(u16x8 a, u16x8 b, f32x16 c) {
+  if constexpr (is_bf(MODE))
+    return __builtin_amdgcn_mfma_f32_32x32x16_bf16(__builtin_bit_cast(bf16x8, a),
+                                                   __builtin_bit_cast(bf16x8, b), c, 0, 0, 0);
+  else
+    return __builtin_amdgcn_mfma_f32_32x32x16_f16(__builtin_bit_cast(f16x8, a),
+                                                  __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
+}
 
-  f32x16 acc[2][2];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-
-  const int lk = tid >> 4;         // slab row 0..15
-  const int li = (tid & 15) * 8;   // 8 consecutive columns
-  // Z^T y rides on the diagonal tiles, which stream every row of their columns
-  const bool want_zty = diag && y != nullptr;
-  double zacc[8];
-#pragma unroll
-  for (int c = 0; c < 8; ++c) zacc[c] = 0.0;
-  for (int64_t m0 = 0; m0 < M; m0 += KB) {
-    const int64_t m = m0 + lk;
-    const bool mok = m < M;
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t col0 = (h == 0 ? I0 : J0) + li;
-      float v[8];
-      if (VEC4 && mok && col0 + 8 <= D) {
-        const float4* p = reinterpret_cast<const float4*>(Z + m * D + col0);
-        const float4 a = p[0], b = p[1];
-        v[0] = a.x; v[1] = a.y; v[2] = a.z; v[3] = a.w;
-        v[4] = b.x; v[5] = b.y; v[6] = b.z; v[7] = b.w;
-      } else {
-#pragma unroll
-        for (int c = 0; c < 8; ++c) {
-          const float zl = Z[(mok ? m : M - 1) * D + (col0 + c < D ? col0 + c : D - 1)];
-          v[c] = (mok && col0 + c < D) ? zl : 0.0f;
-        }
-      }
-      float* dst = (h == 0 ? &sA[lk][li] : &sB[lk][li]);
-#pragma unroll
-      for (int c = 0; c < 8; ++c) dst[c] = v[c];
-      if (diag) {
-        if (want_zty && mok) {
-          const double ym = double(y[m]);
-#pragma unroll
-          for (int c = 0; c < 8; ++c) zacc[c] += double(v[c]) * ym;
-        }
-        break;
-      }
-    }
-    __syncthreads();
-    const float (*sb)[TILE + 4] = diag ? sA : sB;
-#pragma unroll
-    for (int kk = 0; kk < KB; kk += 2) {
-      const int k = kk + (lane >> 5);
-      float af[2], bf[2];
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        af[b] = sA[k][wy * 64 + b * 32 + (lane & 31)];
-        bf[b] = sb[k][wx * 64 + b * 32 + (lane & 31)];
-      }
-#pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 2; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], acc[a][b], 0, 0, 0);
-    }
-    __syncthreads();
+// Tile t -> (I, J): row I holds the tiles J = 0 .. 2I+1 (clipped to the
+// matrix in the last row); rows before the last hold I (I + 1) tiles in all.
+__device__ __forceinline__ void tile_of(int64_t t, int64_t nI, int64_t nJ, int64_t& I,
+                                        int64_t& J) {
+  const int64_t full = (nI - 1) * nI;
+  if (t >= full) {
+    I = nI - 1;
+    J = t - full;
+    return;
   }
+  int64_t i = int64_t((std::sqrt(4.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) > t) --i;
+  while ((i + 1) * (i + 2) <= t) ++i;
+  I = i;
+  J = t - i * (i + 1);
+  (void)nJ;
+}
 
+__host__ __device__ inline int64_t gram_tiles(int64_t D, int64_t& nI, int64_t& nJ) {
+  nI = (D + TM - 1) / TM;
+  nJ = (D + TN - 1) / TN;
+  const int64_t last = 2 * nI < nJ ? 2 * nI : nJ;
+  return (nI - 1) * nI + last;
+}
+
+// Blocks are dealt round-robin to the 8 XCDs; hand each XCD a contiguous run
+// of tiles.
+__device__ __forceinline__ int64_t xcd_tile(int64_t n_tiles) {
+  const int64_t per = (n_tiles + 7) / 8;
+  return int64_t(blockIdx.x % 8) * per + int64_t(blockIdx.x / 8);
+}
+
+// ------------------------------------------------------------------- packing
+// Fragment (ks, cb) -> u16x8 index ((ks * ncb + cb) * 64 + lane).
+template <int MODE>
+__global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ Z, int64_t M,
+                                                   int32_t D, int64_t n_slabs, int32_t ncb,
+                                                   float zscale, u16x8* __restrict__ hi,
+                                                   u16x8* __restrict__ lo,
+                                                   const float* __restrict__ y,
+                                                   double* __restrict__ zpart) {
+  __shared__ double red[4][64];
+  const int cb = blockIdx.x;
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  const int64_t col = int64_t(cb) * 32 + (lane & 31);
+  const bool cok = col < D;
+  const int64_t colc = cok ? col : D - 1;
+  const int64_t ks0 = int64_t(blockIdx.y) * kPackSlabs;
+  const int64_t ks1 = ks0 + kPackSlabs < n_slabs ? ks0 + kPackSlabs : n_slabs;
+  double zacc = 0.0;
+  for (int64_t ks = ks0 + wv; ks < ks1; ks += 4) {
+    const int64_t r0 = ks * KB + 8 * (lane >> 5);
+    float v[8];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int j = 0; j < 8; ++j) {
+      const int64_t r = r0 + j;
+      const float zl = Z[(r < M ? r : M - 1) * D + colc];
+      v[j] = (cok && r < M) ? zl : 0.0f;
+    }
+    if (y != nullptr) {
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) {
-        const int64_t gi = I0 + wy * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t gj = J0 + wx * 64 + b * 32 + (lane & 31);
-        if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += acc[a][b][r];
+      for (int j = 0; j < 8; ++j) {
+        const int64_t r = r0 + j;
+        const float yl = y[r < M ? r : M - 1];
+        zacc += double(v[j]) * double(r < M ? yl : 0.0f);
       }
-  if (want_zty) {
+    }
+    if constexpr (MODE != kFP32) {
+      u16x8 h, l;
 #pragma unroll
-    for (int c = 0; c < 8; ++c) zred[lk][li + c] = zacc[c];
+      for (int j = 0; j < 8; ++j) {
+        unsigned short a, b;
+        split<MODE>(v[j] * zscale, a, b);
+        h[j] = a;
+        l[j] = b;
+      }
+      const int64_t idx = (ks * ncb + cb) * 64 + lane;
+      hi[idx] = h;
+      if constexpr (is_hilo(MODE)) lo[idx] = l;
+    }
+  }
+  if (y != nullptr) {
+    red[wv][lane] = zacc;
     __syncthreads();
-    if (tid < TILE && I0 + tid < D) {
+    if (threadIdx.x < 32 && cok) {
       double t = 0.0;
-      for (int r = 0; r < KB; ++r) t += zred[r][tid];
-      Zty[I0 + tid] += float(t);
+#pragma unroll
+      for (int w = 0; w < 4; ++w) t += red[w][threadIdx.x] + red[w][threadIdx.x + 32];
+      zpart[int64_t(blockIdx.y) * D + col] = t;
     }
   }
 }
 
-// ------------------------------------------------- bf16 / fp16 (x1 and hi+lo)
+template <typename T>
+__global__ void zty_finalize_kernel(const double* __restrict__ zpart, int64_t chunks, int32_t D,
+                                    T* __restrict__ Zty) {
+  const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (c >= D) return;
+  double t = 0.0;
+  for (int64_t k = 0; k < chunks; ++k) t += zpart[k * D + c];
+  Zty[c] += T(t);
+}
+
+// Direct global -> LDS copies (16 bytes per lane; a wave fills 1 KB at a
+// wave-uniform LDS address, lane i at byte 16 i). Their completion is tracked
+// by vmcnt only, so the kernels below wait on vmcnt themselves before the
+// barrier that publishes a stage; loads return in issue order.
+__device__ __forceinline__ void dma16(const void* g, void* lds) {
+  __builtin_amdgcn_global_load_lds(g, (__attribute__((address_space(3))) void*)lds, 16, 0, 0);
+}
+template <int N>
+__device__ __forceinline__ void wait_vm() {
+  static_assert(N >= 0 && N < 64, "vmcnt range");
+  asm volatile("s_waitcnt vmcnt(%0)" ::"n"(N) : "memory");
+}
+// Wait until at most `ahead` stages of PW copies each are still in flight.
+template <int PW>
+__device__ __forceinline__ void wait_stage(int64_t ahead) {
+  if (ahead >= 2) wait_vm<2 * PW>();
+  else if (ahead == 1) wait_vm<PW>();
+  else wait_vm<0>();
+}
+__device__ __forceinline__ void stage_barrier() {
+  __builtin_amdgcn_s_barrier();
+  asm volatile("" ::: "memory");
+}
+
+// ------------------------------------------------------ 16-bit modes (packed)
+// Stage = 2 slabs (32 rows): 16 A fragments (rows 256 I .. +255 of G) and 8 B
+// fragments per part, copied into a ring of NS stages; wave w copies the
+// fragments w, w + 4, ... of each part.
 template <int MODE>
-__global__ __launch_bounds__(256) void gram_half_kernel(const float* __restrict__ Z, int64_t M,
-                                                       int32_t D, float zscale, float gscale,
-                                                       float* __restrict__ G,
-                                                       const float* __restrict__ y,
-                                                       float* __restrict__ Zty) {
-  __shared__ double zred[2][TILE];
-  constexpr bool HILO = (MODE == kBF16HiLo || MODE == kFP16HiLo);
-  constexpr int KP = KB + 8;  // padded k stride (in 16-bit elements)
-  __shared__ __attribute__((aligned(16))) unsigned short sAh[TILE][KP];
-  __shared__ __attribute__((aligned(16))) unsigned short sBh[TILE][KP];
-  __shared__ __attribute__((aligned(16))) unsigned short sAl[HILO ? TILE : 1][KP];
-  __shared__ __attribute__((aligned(16))) unsigned short sBl[HILO ? TILE : 1][KP];
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ lo,
+                        int64_t n_slabs, int32_t ncb, int32_t D, int64_t n_tiles, int64_t nI,
+                        int64_t nJ, float gscale, float* __restrict__ G) {
+  constexpr bool HILO = is_hilo(MODE);
+  constexpr int NP = HILO ? 2 : 1;            // parts per operand
+  constexpr int AF = 2 * (TM / 32);           // A fragments per stage
+  constexpr int BF = 2 * (TN / 32);           // B fragments per stage
+  constexpr int NF = AF + BF;
+  constexpr int FW = NF / 4;                  // fragments per wave per part
+  constexpr int PW = NP * FW;                 // copies per wave per stage
+  constexpr int NS = HILO ? 3 : 4;            // ring depth (stages)
+  constexpr int KC = kFlushRows / (2 * KB);   // stages per flush
+  __shared__ u16x8 ring[NS][NP][NF][64];
+
+  const int64_t t = xcd_tile(n_tiles);
+  if (t >= n_tiles) return;
   int64_t I, J;
-  tile_of(blockIdx.x, I, J);
-  const bool diag = (I == J);
-  const int64_t I0 = I * TILE, J0 = J * TILE;
+  tile_of(t, nI, nJ, I, J);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int wy = wv >> 1, wx = wv & 1;
+  const bool active = I * TM + wy * 128 + 127 >= J * TN + wx * 64;
 
-  f32x16 acc[2][2];
+  int64_t src[FW];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 2; ++b)
-#pragma unroll
-      for (int r = 0; r < 16; ++r) acc[a][b][r] = 0.0f;
-
-  const int li = tid & (TILE - 1);  // column within the tile
-  const int lk = (tid >> 7) * 8;    // 8 consecutive slab rows
-  const bool want_zty = diag && y != nullptr;
-  double zacc = 0.0;
-  for (int64_t m0 = 0; m0 < M; m0 += KB) {
-#pragma unroll
-    for (int h = 0; h < 2; ++h) {
-      const int64_t col = (h == 0 ? I0 : J0) + li;
-      u16x8 hi, lo;
-      // clamped addresses: every load is issued unconditionally, then masked
-      const int64_t colc = col < D ? col : D - 1;
-#pragma unroll
-      for (int c = 0; c < 8; ++c) {
-        const int64_t m = m0 + lk + c;
-        const bool ok = m < M && col < D;
-        const float zl = Z[(m < M ? m : M - 1) * D + colc];
-        const float zr = ok ? zl : 0.0f;
-        if (h == 0 && want_zty && ok) zacc += double(zr) * double(y[m]);
-        unsigned short a, b;
-        split<MODE>(zr * zscale, a, b);
-        hi[c] = a;
-        lo[c] = b;
-      }
-      if (h == 0) {
-        *reinterpret_cast<u16x8*>(&sAh[li][lk]) = hi;
-        if constexpr (HILO) *reinterpret_cast<u16x8*>(&sAl[li][lk]) = lo;
-      } else {
-        *reinterpret_cast<u16x8*>(&sBh[li][lk]) = hi;
-        if constexpr (HILO) *reinterpret_cast<u16x8*>(&sBl[li][lk]) = lo;
-      }
-      if (diag) break;
-    }
-    __syncthreads();
-    const unsigned short (*bh)[KP] = diag ? sAh : sBh;
-    const unsigned short (*bl)[KP] = diag ? sAl : sBl;
-    const int ko = 8 * (lane >> 5);
-    u16x8 ah[2], bhv[2], al[2], blv[2];
-#pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      const int ra = wy * 64 + b * 32 + (lane & 31);
-      const int rb = wx * 64 + b * 32 + (lane & 31);
-      ah[b] = *reinterpret_cast<const u16x8*>(&sAh[ra][ko]);
-      bhv[b] = *reinterpret_cast<const u16x8*>(&bh[rb][ko]);
-      if constexpr (HILO) {
-        al[b] = *reinterpret_cast<const u16x8*>(&sAl[ra][ko]);
-        blv[b] = *reinterpret_cast<const u16x8*>(&bl[rb][ko]);
-      }
-    }
-#pragma unroll
-    for (int a = 0; a < 2; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b) {
-        if constexpr (MODE == kBF16 || MODE == kBF16HiLo) {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-              __builtin_bit_cast(bf16x8, ah[a]), __builtin_bit_cast(bf16x8, bhv[b]), acc[a][b], 0, 0, 0);
-          if constexpr (HILO) {
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, ah[a]), __builtin_bit_cast(bf16x8, blv[b]), acc[a][b], 0, 0, 0);
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, al[a]), __builtin_bit_cast(bf16x8, bhv[b]), acc[a][b], 0, 0, 0);
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(
-                __builtin_bit_cast(bf16x8, al[a]), __builtin_bit_cast(bf16x8, blv[b]), acc[a][b], 0, 0, 0);
-          }
-        } else {
-          acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-              __builtin_bit_cast(f16x8, ah[a]), __builtin_bit_cast(f16x8, bhv[b]), acc[a][b], 0, 0, 0);
-          if constexpr (HILO) {
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                __builtin_bit_cast(f16x8, ah[a]), __builtin_bit_cast(f16x8, blv[b]), acc[a][b], 0, 0, 0);
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                __builtin_bit_cast(f16x8, al[a]), __builtin_bit_cast(f16x8, bhv[b]), acc[a][b], 0, 0, 0);
-            acc[a][b] = __builtin_amdgcn_mfma_f32_32x32x16_f16(
-                __builtin_bit_cast(f16x8, al[a]), __builtin_bit_cast(f16x8, blv[b]), acc[a][b], 0, 0, 0);
-          }
-        }
-      }
-    __syncthreads();
+  for (int c = 0; c < FW; ++c) {
+    const int f = wv + 4 * c;
+    const int slab = f < AF ? f / (TM / 32) : (f - AF) / (TN / 32);
+    const int64_t cbf = f < AF ? I * (TM / 32) + f % (TM / 32) : J * (TN / 32) + (f - AF) % (TN / 32);
+    src[c] = (int64_t(slab) * ncb + cbf) * 64 + lane;
   }
-
+  const int64_t stage_stride = int64_t(2) * ncb * 64;
+  const int64_t n_st = n_slabs / 2;
+  auto issue = [&](int64_t st, int slot) {
+    const int64_t off = st * stage_stride;
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int c = 0; c < FW; ++c) {
+      dma16(hi + src[c] + off, &ring[slot][0][wv + 4 * c][0]);
+      if constexpr (HILO) dma16(lo + src[c] + off, &ring[slot][NP - 1][wv + 4 * c][0]);
+    }
+  };
+
+  f32x16 P[4][2], S[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
 #pragma unroll
     for (int b = 0; b < 2; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int64_t gi = I0 + wy * 64 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t gj = J0 + wx * 64 + b * 32 + (lane & 31);
-        if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += acc[a][b][r] * gscale;
+        P[a][b][r] = 0.0f;
+        S[a][b][r] = 0.0f;
       }
-  if (want_zty) {
-    zred[lk >> 3][li] = zacc;
-    __syncthreads();
-    if (tid < TILE && I0 + tid < D) Zty[I0 + tid] += float(zred[0][tid] + zred[1][tid]);
+
+#pragma unroll
+  for (int j = 0; j < NS - 1; ++j)
+    if (j < n_st) issue(j, j);
+  // Groups of KC stages accumulate in P; P is added into S after each group.
+  // Waves whose block lies above the diagonal compute too (their result is
+  // dropped): keeping the loop free of per-wave branches keeps P in the
+  // accumulation registers.
+  int64_t s = 0;
+  int slot = 0;
+  while (s < n_st) {
+    const int64_t g_end = s + KC < n_st ? s + KC : n_st;
+    for (; s < g_end; ++s) {
+      const int64_t left = n_st - 1 - s;
+      wait_stage<PW>(left < NS - 2 ? left : NS - 2);
+      stage_barrier();
+      if (s + NS - 1 < n_st) issue(s + NS - 1, slot == 0 ? NS - 1 : slot - 1);
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk) {
+        u16x8 ah[4], bh[2], al[4], bl[2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) {
+          ah[a] = ring[slot][0][kk * (TM / 32) + wy * 4 + a][lane];
+          if constexpr (HILO) al[a] = ring[slot][NP - 1][kk * (TM / 32) + wy * 4 + a][lane];
+        }
+#pragma unroll
+        for (int b = 0; b < 2; ++b) {
+          bh[b] = ring[slot][0][AF + kk * (TN / 32) + wx * 2 + b][lane];
+          if constexpr (HILO) bl[b] = ring[slot][NP - 1][AF + kk * (TN / 32) + wx * 2 + b][lane];
+        }
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b) {
+            P[a][b] = mma16<MODE>(ah[a], bh[b], P[a][b]);
+            if constexpr (HILO) {
+              P[a][b] = mma16<MODE>(ah[a], bl[b], P[a][b]);
+              P[a][b] = mma16<MODE>(al[a], bh[b], P[a][b]);
+              P[a][b] = mma16<MODE>(al[a], bl[b], P[a][b]);
+            }
+          }
+      }
+      slot = slot + 1 == NS ? 0 : slot + 1;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          S[a][b][r] += P[a][b][r];
+          P[a][b][r] = 0.0f;
+        }
   }
+
+  if (!active) return;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gi = I * TM + wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t gj = J * TN + wx * 64 + b * 32 + (lane & 31);
+        if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += S[a][b][r] * gscale;
+      }
+}
+
+// ------------------------------------------------ FP32 mode, D % 4 == 0
+// Stage = 16 rows of Z: 16 A rows of 256 floats (one wave copy each) and 16 B
+// rows of 128 floats (one copy per pair of rows), in a ring of 4 stages.
+// Rows past M are copied from a 1 KB block of zeros; columns past D are
+// clamped into the row (they only reach G entries that are never written).
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
+                           int64_t nI, int64_t nJ, const float* __restrict__ zeros,
+                           float* __restrict__ G) {
+  constexpr int NS = 4;
+  constexpr int PW = 6;                        // copies per wave per stage (24 / 4)
+  constexpr int KC = kFlushRows / KB;
+  __shared__ float ra[NS][KB][TM];
+  __shared__ float rb[NS][KB][TN];
+
+  const int64_t t = xcd_tile(n_tiles);
+  if (t >= n_tiles) return;
+  int64_t I, J;
+  tile_of(t, nI, nJ, I, J);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int wy = wv >> 1, wx = wv & 1;
+  const bool active = I * TM + wy * 128 + 127 >= J * TN + wx * 64;
+  const int64_t A0 = I * TM, B0 = J * TN;
+  const int64_t colA = (A0 + 4 * lane < D - 4 ? A0 + 4 * lane : D - 4);
+  const int64_t colB = (B0 + 4 * (lane & 31) < D - 4 ? B0 + 4 * (lane & 31) : D - 4);
+  const int64_t n_st = (M + KB - 1) / KB;
+  // wave w copies A rows w, w+4, w+8, w+12 and B row pairs (2w, 2w+1), (2w+8, 2w+9)
+  auto issue = [&](int64_t st, int slot) {
+    const int64_t m0 = st * KB;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int k = wv + 4 * c;
+      const int64_t m = m0 + k;
+      const float* g = m < M ? Z + m * D + colA : zeros + 4 * lane;
+      dma16(g, &ra[slot][k][0]);
+    }
+#pragma unroll
+    for (int c = 0; c < 2; ++c) {
+      const int k = 2 * wv + 8 * c + (lane >> 5);
+      const int64_t m = m0 + k;
+      const float* g = m < M ? Z + m * D + colB : zeros + 4 * lane;
+      dma16(g, &rb[slot][2 * wv + 8 * c][0]);
+    }
+  };
+
+  f32x16 P[4][2], S[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        P[a][b][r] = 0.0f;
+        S[a][b][r] = 0.0f;
+      }
+
+#pragma unroll
+  for (int j = 0; j < NS - 1; ++j)
+    if (j < n_st) issue(j, j);
+  int64_t s = 0;
+  int slot = 0;
+  while (s < n_st) {
+    const int64_t g_end = s + KC < n_st ? s + KC : n_st;
+    for (; s < g_end; ++s) {
+      const int64_t left = n_st - 1 - s;
+      wait_stage<PW>(left < NS - 2 ? left : NS - 2);
+      stage_barrier();
+      if (s + NS - 1 < n_st) issue(s + NS - 1, slot == 0 ? NS - 1 : slot - 1);
+#pragma unroll
+      for (int kk = 0; kk < KB; kk += 2) {
+        const int k = kk + (lane >> 5);
+        float af[4], bf[2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) af[a] = ra[slot][k][wy * 128 + a * 32 + (lane & 31)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bf[b] = rb[slot][k][wx * 64 + b * 32 + (lane & 31)];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], P[a][b], 0, 0, 0);
+      }
+      slot = slot + 1 == NS ? 0 : slot + 1;
+    }
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          S[a][b][r] += P[a][b][r];
+          P[a][b][r] = 0.0f;
+        }
+  }
+
+  if (!active) return;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gi = A0 + wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t gj = B0 + wx * 64 + b * 32 + (lane & 31);
+        if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += S[a][b][r];
+      }
+}
+
+// ------------------------------------------------ FP32 mode, any D
+// Row-major slabs of 16 rows staged through registers into LDS ([k][column],
+// padded) with masked loads; the 32x32x2 f32 MFMA reads lane l = column l%32
+// of slab row k0 + l/32. Used when D is not a multiple of 4.
+template <bool VEC4>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gram_fp32_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
+                      int64_t nI, int64_t nJ, float* __restrict__ G) {
+  constexpr int LDA = TM + 4, LDB = TN + 4;
+  constexpr int KC = kFlushRows / KB;
+  constexpr int CA = KB * TM / 4 / 256;        // float4 chunks per thread (A)
+  constexpr int CB = KB * TN / 4 / 256;        // (B)
+  __shared__ float sA[2][KB][LDA];
+  __shared__ float sB[2][KB][LDB];
+
+  const int64_t t = xcd_tile(n_tiles);
+  if (t >= n_tiles) return;
+  int64_t I, J;
+  tile_of(t, nI, nJ, I, J);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int wy = wv >> 1, wx = wv & 1;
+  const bool active = I * TM + wy * 128 + 127 >= J * TN + wx * 64;
+  const int64_t A0 = I * TM, B0 = J * TN;
+
+  f32x16 P[4][2], S[4][2];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        P[a][b][r] = 0.0f;
+        S[a][b][r] = 0.0f;
+      }
+
+  float4 pa[CA], pb[CB];
+  // chunk q: slab row q / (width / 4), column 4 (q % (width / 4))
+  auto load = [&](int64_t m0) {
+#pragma unroll
+    for (int c = 0; c < CA + CB; ++c) {
+      const bool isA = c < CA;
+      const int q = tid + 256 * (isA ? c : c - CA);
+      const int w4 = (isA ? TM : TN) / 4;
+      const int k = q / w4;
+      const int64_t col = (isA ? A0 : B0) + 4 * (q % w4);
+      const int64_t m = m0 + k;
+      float4 v;
+      if (VEC4 && m < M && col + 4 <= D) {
+        v = *reinterpret_cast<const float4*>(Z + m * D + col);
+      } else {
+        const int64_t mc = m < M ? m : M - 1;
+        float e[4];
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const float zl = Z[mc * D + (col + u < D ? col + u : D - 1)];
+          e[u] = (m < M && col + u < D) ? zl : 0.0f;
+        }
+        v = make_float4(e[0], e[1], e[2], e[3]);
+      }
+      if (isA) pa[c] = v; else pb[c - CA] = v;
+    }
+  };
+  auto store = [&](int buf) {
+#pragma unroll
+    for (int c = 0; c < CA; ++c) {
+      const int q = tid + 256 * c;
+      *reinterpret_cast<float4*>(&sA[buf][q / (TM / 4)][4 * (q % (TM / 4))]) = pa[c];
+    }
+#pragma unroll
+    for (int c = 0; c < CB; ++c) {
+      const int q = tid + 256 * c;
+      *reinterpret_cast<float4*>(&sB[buf][q / (TN / 4)][4 * (q % (TN / 4))]) = pb[c];
+    }
+  };
+
+  const int64_t n_stages = (M + KB - 1) / KB;
+  load(0);
+  store(0);
+  __syncthreads();
+  for (int64_t s = 0; s < n_stages; ++s) {
+    const int buf = int(s & 1);
+    if (s + 1 < n_stages) load((s + 1) * KB);
+    if (active) {
+#pragma unroll
+      for (int kk = 0; kk < KB; kk += 2) {
+        const int k = kk + (lane >> 5);
+        float af[4], bf[2];
+#pragma unroll
+        for (int a = 0; a < 4; ++a) af[a] = sA[buf][k][wy * 128 + a * 32 + (lane & 31)];
+#pragma unroll
+        for (int b = 0; b < 2; ++b) bf[b] = sB[buf][k][wx * 64 + b * 32 + (lane & 31)];
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+            P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], P[a][b], 0, 0, 0);
+      }
+      if ((s + 1) % KC == 0 || s + 1 == n_stages) {
+#pragma unroll
+        for (int a = 0; a < 4; ++a)
+#pragma unroll
+          for (int b = 0; b < 2; ++b)
+#pragma unroll
+            for (int r = 0; r < 16; ++r) {
+              S[a][b][r] += P[a][b][r];
+              P[a][b][r] = 0.0f;
+            }
+      }
+    }
+    if (s + 1 < n_stages) store(buf ^ 1);
+    __syncthreads();
+  }
+
+  if (!active) return;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int64_t gi = A0 + wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t gj = B0 + wx * 64 + b * 32 + (lane & 31);
+        if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += S[a][b][r];
+      }
+}
+
+// Square tiles of the FP64 mode: t = I (I + 1) / 2 + J, I >= J.
+__device__ __forceinline__ void tile_of_square(int64_t t, int64_t& I, int64_t& J) {
+  int64_t i = int64_t((std::sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > t) --i;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  I = i;
+  J = t - i * (i + 1) / 2;
 }
 
 // ----------------------------------------------------------------- FP64 mode
@@ -311,7 +600,7 @@ __global__ __launch_bounds__(256) void gram_fp64_kernel(const float* __restrict_
   __shared__ double sB[KB][T64 + 1];
   __shared__ double zred[KB][T64];
   int64_t I, J;
-  tile_of(blockIdx.x, I, J);
+  tile_of_square(blockIdx.x, I, J);
   const bool diag = (I == J);
   const int64_t I0 = I * T64, J0 = J * T64;
   const int tid = threadIdx.x;
@@ -388,36 +677,111 @@ __global__ __launch_bounds__(256) void gram_fp64_kernel(const float* __restrict_
 
 using namespace sorf;
 
+namespace {
+size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
+// Workspace: [Z^T y partials][1 KB of zeros][packed hi][packed lo]
+struct GramLayout {
+  int64_t n_slabs;   // 16-row slabs, padded to whole 2-slab stages
+  int32_t ncb;       // 32-column blocks, padded to whole 256-column tiles
+  int64_t chunks;    // Z^T y partial chunks
+  size_t part_bytes, zpart_bytes;
+};
+constexpr size_t kZeroBytes = 1024;
+GramLayout gram_layout(int64_t M, int32_t D) {
+  GramLayout g;
+  g.n_slabs = ((M + 2 * KB - 1) / (2 * KB)) * 2;
+  g.ncb = int32_t(((int64_t(D) + TM - 1) / TM) * (TM / 32));
+  g.chunks = (g.n_slabs + kPackSlabs - 1) / kPackSlabs;
+  g.part_bytes = al256(size_t(g.n_slabs) * size_t(g.ncb) * 1024);
+  g.zpart_bytes = al256(size_t(g.chunks) * size_t(D) * sizeof(double));
+  return g;
+}
+}  // namespace
+
+size_t sorf_gram_ws_bytes(int64_t n_rows, int32_t D, int mode) {
+  if (n_rows <= 0 || D <= 0) return 0;
+  const GramLayout g = gram_layout(n_rows, D);
+  size_t b = g.zpart_bytes + kZeroBytes;
+  if (mode != kFP32) b += g.part_bytes * (is_hilo(mode) ? 2 : 1);
+  return b;
+}
+
 hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const float* y, int mode,
-                            int32_t scale_exp, float* G, float* Zty, hipStream_t st) {
+                            int32_t scale_exp, float* G, float* Zty, void* ws, hipStream_t st) {
   if (n_rows == 0 || D == 0) return hipSuccess;
-  const int64_t nt = (D + TILE - 1) / TILE;
-  const dim3 grid{unsigned(nt * (nt + 1) / 2)}, block{256};
+  const GramLayout g = gram_layout(n_rows, D);
+  char* w = static_cast<char*>(ws);
+  double* zpart = reinterpret_cast<double*>(w);
+  float* zeros = reinterpret_cast<float*>(w + g.zpart_bytes);
+  u16x8* hi = reinterpret_cast<u16x8*>(w + g.zpart_bytes + kZeroBytes);
+  u16x8* lo = reinterpret_cast<u16x8*>(w + g.zpart_bytes + kZeroBytes + g.part_bytes);
   const float zs = std::ldexp(1.0f, scale_exp);
   const float gs = std::ldexp(1.0f, -2 * scale_exp);
+  const dim3 pgrid{unsigned(g.ncb), unsigned(g.chunks)}, blk{256};
   switch (mode) {
     case kFP32:
-      if (D % 4 == 0)
-        hipLaunchKernelGGL(gram_fp32_kernel<true>, grid, block, 0, st, Z, n_rows, D, G, y, Zty);
-      else
-        hipLaunchKernelGGL(gram_fp32_kernel<false>, grid, block, 0, st, Z, n_rows, D, G, y, Zty);
+      if (y != nullptr)
+        hipLaunchKernelGGL(pack_kernel<kFP32>, pgrid, blk, 0, st, Z, n_rows, D, g.n_slabs, g.ncb,
+                           1.0f, hi, lo, y, zpart);
       break;
     case kBF16:
-      hipLaunchKernelGGL(gram_half_kernel<kBF16>, grid, block, 0, st, Z, n_rows, D, zs, gs, G, y, Zty);
+      hipLaunchKernelGGL(pack_kernel<kBF16>, pgrid, blk, 0, st, Z, n_rows, D, g.n_slabs, g.ncb,
+                         zs, hi, lo, y, zpart);
       break;
     case kFP16:
-      hipLaunchKernelGGL(gram_half_kernel<kFP16>, grid, block, 0, st, Z, n_rows, D, zs, gs, G, y, Zty);
+      hipLaunchKernelGGL(pack_kernel<kFP16>, pgrid, blk, 0, st, Z, n_rows, D, g.n_slabs, g.ncb,
+                         zs, hi, lo, y, zpart);
       break;
     case kBF16HiLo:
-      hipLaunchKernelGGL(gram_half_kernel<kBF16HiLo>, grid, block, 0, st, Z, n_rows, D, zs, gs, G,
-                         y, Zty);
+      hipLaunchKernelGGL(pack_kernel<kBF16HiLo>, pgrid, blk, 0, st, Z, n_rows, D, g.n_slabs,
+                         g.ncb, zs, hi, lo, y, zpart);
       break;
     case kFP16HiLo:
-      hipLaunchKernelGGL(gram_half_kernel<kFP16HiLo>, grid, block, 0, st, Z, n_rows, D, zs, gs, G,
-                         y, Zty);
+      hipLaunchKernelGGL(pack_kernel<kFP16HiLo>, pgrid, blk, 0, st, Z, n_rows, D, g.n_slabs,
+                         g.ncb, zs, hi, lo, y, zpart);
       break;
     default:
       return hipErrorInvalidValue;
+  }
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (y != nullptr) {
+    hipLaunchKernelGGL(zty_finalize_kernel<float>, dim3(unsigned((D + 255) / 256)), dim3(256), 0,
+                       st, zpart, g.chunks, D, Zty);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  int64_t nI, nJ;
+  const int64_t n_tiles = gram_tiles(D, nI, nJ);
+  const dim3 grid{unsigned(((n_tiles + 7) / 8) * 8)};
+  switch (mode) {
+    case kFP32:
+      if (D % 4 == 0) {
+        if ((e = sorf_launch_fill(zeros, int64_t(kZeroBytes / sizeof(float)), 0.0f, st)) !=
+            hipSuccess)
+          return e;
+        hipLaunchKernelGGL(gram_fp32_ring_kernel, grid, blk, 0, st, Z, n_rows, D, n_tiles, nI, nJ,
+                           zeros, G);
+      } else {
+        hipLaunchKernelGGL(gram_fp32_kernel<false>, grid, blk, 0, st, Z, n_rows, D, n_tiles, nI,
+                           nJ, G);
+      }
+      break;
+    case kBF16:
+      hipLaunchKernelGGL(gram_packed_kernel<kBF16>, grid, blk, 0, st, hi, lo, g.n_slabs, g.ncb, D,
+                         n_tiles, nI, nJ, gs, G);
+      break;
+    case kFP16:
+      hipLaunchKernelGGL(gram_packed_kernel<kFP16>, grid, blk, 0, st, hi, lo, g.n_slabs, g.ncb, D,
+                         n_tiles, nI, nJ, gs, G);
+      break;
+    case kBF16HiLo:
+      hipLaunchKernelGGL(gram_packed_kernel<kBF16HiLo>, grid, blk, 0, st, hi, lo, g.n_slabs,
+                         g.ncb, D, n_tiles, nI, nJ, gs, G);
+      break;
+    case kFP16HiLo:
+      hipLaunchKernelGGL(gram_packed_kernel<kFP16HiLo>, grid, blk, 0, st, hi, lo, g.n_slabs,
+                         g.ncb, D, n_tiles, nI, nJ, gs, G);
+      break;
   }
   return hipGetLastError();
 }

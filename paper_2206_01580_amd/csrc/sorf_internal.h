@@ -211,8 +211,9 @@ hipError_t sorf_launch_molecule_reduce(const SorfFeatureArgs& a, const float* e_
 hipError_t sorf_launch_validate(const SorfFeatureArgs& a, int32_t* result, hipStream_t s);
 hipError_t sorf_launch_fill(float* p, int64_t n, float v, hipStream_t s);
 
+size_t sorf_gram_ws_bytes(int64_t n_rows, int32_t D, int mode);
 hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const float* y, int mode,
-                            int32_t scale_exp, float* G, float* Zty, hipStream_t s);
+                            int32_t scale_exp, float* G, float* Zty, void* ws, hipStream_t s);
 hipError_t sorf_launch_gram_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
                                 double* G, double* Zty, hipStream_t s);
 

@@ -160,9 +160,25 @@ def backward(model: Model, batch: Batch, alpha: torch.Tensor, dE: Optional[torch
     return out
 
 
+class GramWorkspace:
+    """Reusable device workspace for sorf_gram_accumulate (grows on demand)."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.buf = torch.empty(0, dtype=torch.uint8, device=device)
+
+    def get(self, n_rows: int, D: int, precision: str):
+        need = _lib.load().sorf_gram_workspace_bytes(n_rows, D, _lib.GRAM_MODES[precision])
+        if need == 0:
+            return None, 0
+        if self.buf.numel() < need + 256:
+            self.buf = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        return self.buf.data_ptr() + (-self.buf.data_ptr()) % 256, need
+
+
 def gram_accumulate(Z: torch.Tensor, G: torch.Tensor, y: Optional[torch.Tensor] = None,
                     Zty: Optional[torch.Tensor] = None, precision: str = "fp32",
-                    scale_exp: int = 0) -> None:
+                    scale_exp: int = 0, workspace: Optional[GramWorkspace] = None) -> None:
     """G += Z^T Z on the lower triangle; Zty += Z^T y (sorf_gram_accumulate, or
     sorf_gram_accumulate_f64 for precision 'fp64', where G and Zty are float64)."""
     M, D = Z.shape
@@ -177,9 +193,11 @@ def gram_accumulate(Z: torch.Tensor, G: torch.Tensor, y: Optional[torch.Tensor] 
         _lib.check("sorf_gram_accumulate_f64", lib.sorf_gram_accumulate_f64(
             M, D, _ptr(Z), _ptr(y), _ptr(G), _ptr(Zty), _stream()))
         return
+    ws = workspace if workspace is not None else GramWorkspace(Z.device)
+    wptr, wbytes = ws.get(M, D, precision)
     _lib.check("sorf_gram_accumulate", lib.sorf_gram_accumulate(
         M, D, _ptr(Z), _ptr(y), _lib.GRAM_MODES[precision], scale_exp, _ptr(G), _ptr(Zty),
-        _stream()))
+        wptr, wbytes, _stream()))
 
 
 def fp16_scale_exp(max_abs: float) -> int:

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.sorf_abi_version() == 1
+    assert lib.sorf_abi_version() == 2
 
 
 def test_struct_layout_matches_c(tmp_path):
@@ -135,15 +135,30 @@ def test_predict_workspace_checks(lib):
 def test_gram_argument_checks(lib):
     G = lib.sorf_gram_accumulate
     E = _lib.SORF_ERR_INVALID_ARG
-    assert G(10, 0, PTR, None, 0, 0, PTR, None, None) == E            # D = 0
-    assert G(-1, PTR, PTR, None, 0, 0, PTR, None, None) == E            # negative rows
-    assert G(10, PTR, PTR, None, 5, 0, PTR, None, None) == E            # unknown precision
-    assert G(10, PTR, PTR, None, 0, 3, PTR, None, None) == E            # scale only for fp16 modes
-    assert G(10, PTR, PTR, None, 2, 61, PTR, None, None) == E           # scale range
-    assert G(10, PTR, None, None, 0, 0, PTR, None, None) == E         # Z missing
-    assert G(10, PTR, PTR, None, 0, 0, None, None, None) == E         # G missing
-    assert G(10, PTR, PTR, PTR, 0, 0, PTR, None, None) == E               # y without Zty
-    assert G(0, PTR, None, None, 0, 0, PTR, None, None) == _lib.SORF_OK  # nothing to do, no launch
+    assert G(10, 0, PTR, None, 0, 0, PTR, None, None, 0, None) == E            # D = 0
+    assert G(-1, PTR, PTR, None, 0, 0, PTR, None, None, 0, None) == E            # negative rows
+    assert G(10, PTR, PTR, None, 5, 0, PTR, None, None, 0, None) == E            # unknown precision
+    assert G(10, PTR, PTR, None, 0, 3, PTR, None, None, 0, None) == E            # scale only for fp16 modes
+    assert G(10, PTR, PTR, None, 2, 61, PTR, None, None, 0, None) == E           # scale range
+    assert G(10, PTR, None, None, 0, 0, PTR, None, None, 0, None) == E         # Z missing
+    assert G(10, PTR, PTR, None, 0, 0, None, None, None, 0, None) == E         # G missing
+    assert G(10, PTR, PTR, PTR, 0, 0, PTR, None, None, 0, None) == E               # y without Zty
+    assert G(0, PTR, None, None, 0, 0, PTR, None, None, 0, None) == _lib.SORF_OK  # nothing to do, no launch
+
+
+def test_gram_workspace_query_and_checks(lib):
+    Q = lib.sorf_gram_workspace_bytes
+    assert Q(0, 64, 1) == 0 and Q(10, 0, 1) == 0 and Q(-1, 64, 0) == 0 and Q(10, 64, 7) == 0
+    fp32, bf, hilo = Q(10, 64, 0), Q(10, 64, 1), Q(10, 64, 3)
+    assert 0 < fp32 < bf < hilo
+    # 16-bit packing: 32 padded rows x 256 padded columns x 2 bytes per part
+    assert bf - fp32 == 32 * 256 * 2 and hilo - fp32 == 2 * (32 * 256 * 2)
+    assert Q(100000, 16384, 3) >= 2 * 100000 * 16384 * 2
+    G = lib.sorf_gram_accumulate
+    W = _lib.SORF_ERR_WORKSPACE
+    assert G(10, 64, PTR, None, 1, 0, PTR, None, None, 0, None) == W            # missing
+    assert G(10, 64, PTR, None, 1, 0, PTR, None, PTR, bf - 1, None) == W        # too small
+    assert G(10, 64, PTR, None, 1, 0, PTR, None, PTR + 16, bf, None) == W       # not 256-aligned
 
 
 def test_solve_argument_checks(lib):
@@ -200,4 +215,4 @@ def test_misaligned_arrays_rejected(lib):
     m, b = _model(), _batch()
     assert lib.sorf_forward(ctypes.byref(m), ctypes.byref(b), PTR + 4, None) == E
     assert lib.sorf_backward(ctypes.byref(m), ctypes.byref(b), PTR + 4, None, PTR, None) == E
-    assert lib.sorf_gram_accumulate(10, 64, PTR + 4, None, 0, 0, PTR, None, None) == E
+    assert lib.sorf_gram_accumulate(10, 64, PTR + 4, None, 0, 0, PTR, None, None, 0, None) == E

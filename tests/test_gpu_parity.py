@@ -267,7 +267,7 @@ def test_autograd_function_matches_central_differences():
 
 # ------------------------------------------------------------------ Gram
 @pytest.mark.parametrize("mode", ["fp32", "bf16", "fp16", "bf16_hilo", "fp16_hilo"])
-@pytest.mark.parametrize("MD", [(333, 300), (64, 128), (1000, 37), (5, 257)], ids=lambda t: f"M{t[0]}-D{t[1]}")
+@pytest.mark.parametrize("MD", [(333, 300), (64, 128), (1000, 37), (5, 257), (600, 1100)], ids=lambda t: f"M{t[0]}-D{t[1]}")
 def test_gram_against_emulated_modes(mode, MD):
     M, D = MD
     rng = np.random.default_rng(M + D)

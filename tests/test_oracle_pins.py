@@ -451,3 +451,13 @@ def test_gram_emulated_error_ordering():
     assert err["fp16_hilo"] < err["fp16"] / 50
     assert err["fp16_hilo"] < err["bf16_hilo"]
     assert err["bf16"] < 5e-3 and err["bf16_hilo"] < 5e-5
+
+
+def test_feature_column_subset_is_a_column_slice():
+    """Forming only some feature columns keeps the sqrt(2/D) of the full map
+    and equals the matching columns of the full rows."""
+    p = W.random_problem(77, 16, 3, 3, 2, 5, 6, 0)
+    cols = np.array([0, 5, 16, 31, 47])
+    full = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma)
+    part = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, cols=cols)
+    assert np.abs(part - full[:, cols]).max() <= 1e-14 * np.abs(full).max()
