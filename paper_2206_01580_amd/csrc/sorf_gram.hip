@@ -287,31 +287,37 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
       wait_stage<PW>(left < NS - 2 ? left : NS - 2);
       stage_barrier();
       if (s + NS - 1 < n_st) issue(s + NS - 1, slot == 0 ? NS - 1 : slot - 1);
+      // all of the stage's fragments are read before the first product, so
+      // the LDS latency is paid once per stage rather than per fragment
+      u16x8 ah[2][4], bh[2][2], al[2][4], bl[2][2];
 #pragma unroll
       for (int kk = 0; kk < 2; ++kk) {
-        u16x8 ah[4], bh[2], al[4], bl[2];
 #pragma unroll
         for (int a = 0; a < 4; ++a) {
-          ah[a] = ring[slot][0][kk * (TM / 32) + wy * 4 + a][lane];
-          if constexpr (HILO) al[a] = ring[slot][NP - 1][kk * (TM / 32) + wy * 4 + a][lane];
+          ah[kk][a] = ring[slot][0][kk * (TM / 32) + wy * 4 + a][lane];
+          if constexpr (HILO) al[kk][a] = ring[slot][NP - 1][kk * (TM / 32) + wy * 4 + a][lane];
         }
 #pragma unroll
         for (int b = 0; b < 2; ++b) {
-          bh[b] = ring[slot][0][AF + kk * (TN / 32) + wx * 2 + b][lane];
-          if constexpr (HILO) bl[b] = ring[slot][NP - 1][AF + kk * (TN / 32) + wx * 2 + b][lane];
+          bh[kk][b] = ring[slot][0][AF + kk * (TN / 32) + wx * 2 + b][lane];
+          if constexpr (HILO)
+            bl[kk][b] = ring[slot][NP - 1][AF + kk * (TN / 32) + wx * 2 + b][lane];
         }
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int kk = 0; kk < 2; ++kk)
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b) {
-            P[a][b] = mma16<MODE>(ah[a], bh[b], P[a][b]);
+            P[a][b] = mma16<MODE>(ah[kk][a], bh[kk][b], P[a][b]);
             if constexpr (HILO) {
-              P[a][b] = mma16<MODE>(ah[a], bl[b], P[a][b]);
-              P[a][b] = mma16<MODE>(al[a], bh[b], P[a][b]);
-              P[a][b] = mma16<MODE>(al[a], bl[b], P[a][b]);
+              P[a][b] = mma16<MODE>(ah[kk][a], bl[kk][b], P[a][b]);
+              P[a][b] = mma16<MODE>(al[kk][a], bh[kk][b], P[a][b]);
+              P[a][b] = mma16<MODE>(al[kk][a], bl[kk][b], P[a][b]);
             }
           }
-      }
       slot = slot + 1 == NS ? 0 : slot + 1;
     }
 #pragma unroll
@@ -408,20 +414,23 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
       wait_stage<PW>(left < NS - 2 ? left : NS - 2);
       stage_barrier();
       if (s + NS - 1 < n_st) issue(s + NS - 1, slot == 0 ? NS - 1 : slot - 1);
+      float af[KB / 2][4], bf[KB / 2][2];
 #pragma unroll
-      for (int kk = 0; kk < KB; kk += 2) {
-        const int k = kk + (lane >> 5);
-        float af[4], bf[2];
+      for (int kk = 0; kk < KB / 2; ++kk) {
+        const int k = 2 * kk + (lane >> 5);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) af[a] = ra[slot][k][wy * 128 + a * 32 + (lane & 31)];
+        for (int a = 0; a < 4; ++a) af[kk][a] = ra[slot][k][wy * 128 + a * 32 + (lane & 31)];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bf[b] = rb[slot][k][wx * 64 + b * 32 + (lane & 31)];
+        for (int b = 0; b < 2; ++b) bf[kk][b] = rb[slot][k][wx * 64 + b * 32 + (lane & 31)];
+      }
+      __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+      for (int kk = 0; kk < KB / 2; ++kk)
 #pragma unroll
         for (int a = 0; a < 4; ++a)
 #pragma unroll
           for (int b = 0; b < 2; ++b)
-            P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], P[a][b], 0, 0, 0);
-      }
+            P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][a], bf[kk][b], P[a][b], 0, 0, 0);
       slot = slot + 1 == NS ? 0 : slot + 1;
     }
 #pragma unroll

@@ -17,6 +17,7 @@
 // row updates the remaining right-hand side with coalesced reads of L, and
 // the workgroup that finishes the next block's rows also solves that block.
 #include <cmath>
+#include <mutex>
 
 #include "sorf_internal.h"
 
@@ -86,7 +87,18 @@ __global__ __launch_bounds__(256) void promote_kernel(const TG* __restrict__ G, 
 // the step (wave barrier). The couplings between the halves are 64 x 64 x 64
 // products spread over all four waves.
 // ---------------------------------------------------------------------------
-typedef double LdsBlock[NB + 1];
+// Row stride NB + 8 doubles: the 8 x 8 lane grids of the one-wave steps
+// (rows ly + 8a, columns lx + 8b) then fall on distinct LDS banks.
+constexpr int LDL = NB + 8;
+typedef double LdsBlock[LDL];
+
+// 1 / d to full double precision: hardware reciprocal plus one Newton step
+// (the exact IEEE division is a longer dependent chain on the critical path).
+static __device__ __forceinline__ double recip(double d) {
+  double r = __builtin_amdgcn_rcp(d);
+  const double e = __builtin_fma(-d, r, 1.0);
+  return __builtin_fma(r, e, r);
+}
 
 static __device__ __forceinline__ void wave_step_fence() {
   __builtin_amdgcn_s_waitcnt(0xc07f);  // lgkmcnt(0): this wave's LDS reads/writes are done
@@ -94,118 +106,149 @@ static __device__ __forceinline__ void wave_step_fence() {
   __builtin_amdgcn_wave_barrier();
 }
 
-// In-place Cholesky of the 64 x 64 block at (o, o) by one wave. Step J is
-// unrolled at compile time: lane (ly, lx) of an 8 x 8 grid owns entries
-// (i, l) = (J+1+ly+8a, J+1+lx+8b), l <= i; it loads all of them (at clamped,
-// always valid addresses) before storing any, and since one wave issues its
-// LDS operations in order, every lane has read before any lane writes: one
-// wait per step suffices. The update uses the unscaled column J and 1/d_J;
-// the columns are scaled by 1/sqrt(d_J) in one pass at the end (piv[] keeps
-// the pivots). Rows past the matrix are padded with the identity.
-template <int J>
-static __device__ __forceinline__ void wave_potrf64_steps(LdsBlock* L, int o, int ly, int lx,
-                                                          int lane, double* piv, int32_t* info,
-                                                          int gbase, int nvalid) {
-  constexpr int NA = (63 - J + 7) / 8;
-  const double d = L[o + J][o + J];
-  const bool bad = !(d > 0.0) || !std::isfinite(d);
-  if (bad && lane == 0 && J < nvalid && *info == 0) *info = gbase + J + 1;
-  if (lane == 0) piv[J] = bad ? __builtin_nan("") : std::sqrt(d);
-  if constexpr (NA > 0) {
-    const double rd = 1.0 / d;
-    double ci[NA], cl[NA], e[NA][NA];
+// One wave factors (and later inverts) a 64 x 64 half with the matrix held in
+// registers: lane (ly, lx) of an 8 x 8 grid owns the entries
+// (ly + 8a, lx + 8b), a, b = 0..7, for the whole factorisation. A step only
+// publishes one column (and, for the inverse, one row) through a 64-entry
+// LDS buffer; since one wave issues its LDS operations in order, the reads
+// that follow see the published values. Step J = 8 JB + jr runs with JB
+// fixed at compile time, so every register index is static; the masks that
+// select the updated entries split into a factor per row block and a
+// factor per column block, so the update is one FMA per entry.
+
+// Cholesky, unscaled right-looking form: at step J every entry (i, l) with
+// i >= l > J loses A[i][J] A[l][J] / A[J][J]; the columns are scaled by
+// 1/sqrt(A[J][J]) after the last step (piv[] keeps the square roots).
+template <int JB>
+static __device__ __forceinline__ void rpotrf_block(double (&R)[8][8], double* col, double* piv,
+                                                    double* dummy, int ly, int lx, int lane,
+                                                    int32_t* info, int gbase, int nvalid) {
+  const bool lower = ly >= lx;
+  for (int jr = 0; jr < 8; ++jr) {
+    const int J = 8 * JB + jr;
 #pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      ci[a] = L[o + min(J + 1 + ly + 8 * a, 63)][o + J];
-      cl[a] = L[o + min(J + 1 + lx + 8 * a, 63)][o + J];
+    for (int a = JB; a < 8; ++a) *(lx == jr ? &col[ly + 8 * a] : &dummy[lane]) = R[a][JB];
+    wave_step_fence();
+    const double d = col[J];
+    const bool bad = !(d > 0.0) || !std::isfinite(d);
+    if (bad && lane == 0 && J < nvalid && *info == 0) *info = gbase + J + 1;
+    *(lane == 0 ? &piv[J] : &dummy[lane]) = bad ? __builtin_nan("") : std::sqrt(d);
+    const double rd = recip(d);
+    double f[8], c[8];
+#pragma unroll
+    for (int a = JB; a < 8; ++a) f[a] = col[ly + 8 * a] * rd;
+#pragma unroll
+    for (int b = JB; b < 8; ++b) {
+      const double cl = col[lx + 8 * b];
+      c[b] = lx + 8 * b > J ? cl : 0.0;
     }
 #pragma unroll
-    for (int a = 0; a < NA; ++a)
+    for (int a = JB; a < 8; ++a) {
 #pragma unroll
-      for (int b = 0; b < NA; ++b)
-        e[a][b] = L[o + min(J + 1 + ly + 8 * a, 63)][o + min(J + 1 + lx + 8 * b, 63)];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      const int i = J + 1 + ly + 8 * a;
-      const double f = ci[a] * rd;
-#pragma unroll
-      for (int b = 0; b < NA; ++b) {
-        const int l = J + 1 + lx + 8 * b;
-        if (i < 64 && l <= i) L[o + i][o + l] = e[a][b] - f * cl[b];
-      }
+      for (int b = JB; b < a; ++b) R[a][b] = __builtin_fma(-f[a], c[b], R[a][b]);
+      R[a][a] = __builtin_fma(-f[a], lower ? c[a] : 0.0, R[a][a]);
     }
+    wave_step_fence();
   }
-  wave_step_fence();
-  if constexpr (J + 1 < 64)
-    wave_potrf64_steps<J + 1>(L, o, ly, lx, lane, piv, info, gbase, nvalid);
 }
 
 static __device__ __forceinline__ void wave_potrf64(LdsBlock* L, int o, int ly, int lx, int lane,
-                                                    double* piv, int32_t* info, int gbase,
-                                                    int nvalid) {
-  wave_potrf64_steps<0>(L, o, ly, lx, lane, piv, info, gbase, nvalid);
-  // scale column j by 1/piv[j]; the diagonal becomes piv[j]
-  for (int j = 0; j < 64; ++j) {
-    const double p = piv[j];
-    const double v = L[o + max(lane, j)][o + j];
-    if (lane > j) L[o + lane][o + j] = v / p;
-    if (lane == j) L[o + j][o + j] = p;
+                                                    double* piv, double* col, double* dummy,
+                                                    int32_t* info, int gbase, int nvalid) {
+  double R[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) R[a][b] = L[o + ly + 8 * a][o + lx + 8 * b];
+  rpotrf_block<0>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
+  rpotrf_block<1>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
+  rpotrf_block<2>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
+  rpotrf_block<3>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
+  rpotrf_block<4>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
+  rpotrf_block<5>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
+  rpotrf_block<6>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
+  rpotrf_block<7>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
+  // L[i][l] = A[i][l] / piv[l] below the diagonal, piv[l] on it, 0 above
+#pragma unroll
+  for (int b = 0; b < 8; ++b) {
+    const int l = lx + 8 * b;
+    const double p = piv[l];
+    const double rp = recip(p);
+#pragma unroll
+    for (int a = 0; a < 8; ++a) {
+      const int i = ly + 8 * a;
+      L[o + i][o + l] = i > l ? R[a][b] * rp : (i == l ? p : 0.0);
+    }
   }
   wave_step_fence();
 }
 
-// In-place inverse of the lower-triangular 64 x 64 block at (o, o) by one
-// wave: forward elimination of [L | I]. At step Q every row i > Q loses
-// L[i][Q] / L[Q][Q] times the (still unscaled) row Q of X, and column Q of X
-// below the pivot becomes -L[i][Q] / L[Q][Q]; all loads of the step precede
-// its stores (one wave, in-order LDS), so one wait per step suffices. Row Q is
-// never read again after step Q, so the rows are scaled by 1/L[Q][Q] in one
-// pass at the end. rinv[] holds the reciprocal pivots.
-template <int Q>
-static __device__ __forceinline__ void wave_trtri64_steps(LdsBlock* L, int o, int ly, int lx,
-                                                          int lane, const double* rinv) {
-  constexpr int NA = (63 - Q + 7) / 8;
-  constexpr int NC = (Q + 7) / 8;
-  const double inv = rinv[Q];
-  const double fq = L[o + min(Q + 1 + lane, 63)][o + Q];
-  if constexpr (NA > 0 && NC > 0) {
-    double fi[NA], rq[NC], e[NA][NC];
+// Inverse of the lower-triangular 64 x 64 half by forward elimination of
+// [L | I] in place: at step Q every row i > Q loses L[i][Q] / L[Q][Q] times
+// the (still unscaled) row Q of X on the columns c < Q, and X[i][Q] becomes
+// -L[i][Q] / L[Q][Q]. Row Q is final after step Q except for the scale
+// 1/L[Q][Q], applied at the end (rinv[] holds the reciprocal pivots).
+template <int QB>
+static __device__ __forceinline__ void rtrtri_block(double (&R)[8][8], double* colv,
+                                                    double* rowv, const double* rinv,
+                                                    double* dummy, int ly, int lx, int lane) {
+  for (int qr = 0; qr < 8; ++qr) {
+    const int Q = 8 * QB + qr;
 #pragma unroll
-    for (int a = 0; a < NA; ++a) fi[a] = L[o + min(Q + 1 + ly + 8 * a, 63)][o + Q];
+    for (int b = 0; b <= QB; ++b) *(ly == qr ? &rowv[lx + 8 * b] : &dummy[lane]) = R[QB][b];
 #pragma unroll
-    for (int b = 0; b < NC; ++b) rq[b] = L[o + Q][o + min(lx + 8 * b, 63)];
+    for (int a = QB; a < 8; ++a) *(lx == qr ? &colv[ly + 8 * a] : &dummy[lane]) = R[a][QB];
+    wave_step_fence();
+    const double inv = rinv[Q];
+    double f[8], r[8];
 #pragma unroll
-    for (int a = 0; a < NA; ++a)
-#pragma unroll
-      for (int b = 0; b < NC; ++b)
-        e[a][b] = L[o + min(Q + 1 + ly + 8 * a, 63)][o + min(lx + 8 * b, 63)];
-#pragma unroll
-    for (int a = 0; a < NA; ++a) {
-      const int i = Q + 1 + ly + 8 * a;
-      const double f = fi[a] * inv;
-#pragma unroll
-      for (int b = 0; b < NC; ++b) {
-        const int c = lx + 8 * b;
-        if (i < 64 && c < Q) L[o + i][o + c] = e[a][b] - f * rq[b];
-      }
+    for (int a = QB; a < 8; ++a) {
+      const double v = colv[ly + 8 * a];
+      f[a] = ly + 8 * a > Q ? v * inv : 0.0;
     }
+#pragma unroll
+    for (int b = 0; b <= QB; ++b) {
+      const double v = rowv[lx + 8 * b];
+      r[b] = lx + 8 * b < Q ? v : 0.0;
+    }
+#pragma unroll
+    for (int a = QB; a < 8; ++a)
+#pragma unroll
+      for (int b = 0; b <= QB; ++b) R[a][b] = __builtin_fma(-f[a], r[b], R[a][b]);
+#pragma unroll
+    for (int a = QB; a < 8; ++a) R[a][QB] = (lx == qr && ly + 8 * a > Q) ? -f[a] : R[a][QB];
+    wave_step_fence();
   }
-  if (Q + 1 + lane < 64) L[o + Q + 1 + lane][o + Q] = -fq * inv;
-  wave_step_fence();
-  if constexpr (Q + 1 < 64) wave_trtri64_steps<Q + 1>(L, o, ly, lx, lane, rinv);
 }
 
 static __device__ __forceinline__ void wave_trtri64(LdsBlock* L, int o, int ly, int lx, int lane,
-                                                    double* rinv) {
-  rinv[lane] = 1.0 / L[o + lane][o + lane];
+                                                    double* rinv, double* colv, double* rowv,
+                                                    double* dummy) {
+  rinv[lane] = recip(L[o + lane][o + lane]);
+  double R[8][8];
+#pragma unroll
+  for (int a = 0; a < 8; ++a)
+#pragma unroll
+    for (int b = 0; b < 8; ++b) R[a][b] = L[o + ly + 8 * a][o + lx + 8 * b];
   wave_step_fence();
-  wave_trtri64_steps<0>(L, o, ly, lx, lane, rinv);
-  // scale row Q (columns < Q) by 1/L[Q][Q]; the diagonal becomes 1/L[Q][Q]
-  for (int q = 0; q < 64; ++q) {
-    const double r = rinv[q];
-    const double v = L[o + q][o + min(lane, q)];
-    if (lane < q) L[o + q][o + lane] = v * r;
-    if (lane == q) L[o + q][o + q] = r;
+  rtrtri_block<0>(R, colv, rowv, rinv, dummy, ly, lx, lane);
+  rtrtri_block<1>(R, colv, rowv, rinv, dummy, ly, lx, lane);
+  rtrtri_block<2>(R, colv, rowv, rinv, dummy, ly, lx, lane);
+  rtrtri_block<3>(R, colv, rowv, rinv, dummy, ly, lx, lane);
+  rtrtri_block<4>(R, colv, rowv, rinv, dummy, ly, lx, lane);
+  rtrtri_block<5>(R, colv, rowv, rinv, dummy, ly, lx, lane);
+  rtrtri_block<6>(R, colv, rowv, rinv, dummy, ly, lx, lane);
+  rtrtri_block<7>(R, colv, rowv, rinv, dummy, ly, lx, lane);
+  // row i scaled by 1/L[i][i] below the diagonal; the diagonal becomes 1/L[i][i]
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    const int i = ly + 8 * a;
+    const double ri = rinv[i];
+#pragma unroll
+    for (int b = 0; b < 8; ++b) {
+      const int c = lx + 8 * b;
+      L[o + i][o + c] = c < i ? R[a][b] * ri : (c == i ? ri : 0.0);
+    }
   }
   wave_step_fence();
 }
@@ -250,29 +293,45 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
                                                         int32_t* __restrict__ info,
                                                         double* __restrict__ Linv,
                                                         double* __restrict__ LinvT) {
-  __shared__ double L[NB][NB + 1];
+  __shared__ double L[NB][LDL];
   __shared__ double piv[64];
+  __shared__ double dummy[64];
+  __shared__ double colv[64], rowv[64];
   const int tid = threadIdx.x;
   const int lane = tid & 63, wv = tid >> 6;
   const int wy = wv >> 1, wx = wv & 1;
   const int ly = lane >> 3, lx = lane & 7;
   const int n = (D - k) < NB ? (D - k) : NB;
-  // rows past the matrix are padded with the identity
-  for (int t = tid; t < NB * NB; t += 256) {
-    const int i = t >> 7, j = t & (NB - 1);
-    const int64_t gi = k + min(i, n - 1), gj = k + min(j, n - 1);
-    const double a = A[gi * D + gj];
-    L[i][j] = (i < n && j <= i) ? a : ((i == j) ? 1.0 : 0.0);
+  // rows past the matrix are padded with the identity; every thread issues
+  // its 64 loads (column lane, rows wv + 4 m) before it stores any
+  {
+    const int64_t gj0 = k + min(lane, n - 1), gj1 = k + min(lane + 64, n - 1);
+#pragma unroll
+    for (int m0 = 0; m0 < 32; m0 += 16) {
+      double v0[16], v1[16];
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int64_t gi = k + min(wv + 4 * (m0 + m), n - 1);
+        v0[m] = A[gi * D + gj0];
+        v1[m] = A[gi * D + gj1];
+      }
+#pragma unroll
+      for (int m = 0; m < 16; ++m) {
+        const int i = wv + 4 * (m0 + m);
+        L[i][lane] = (i < n && lane <= i) ? v0[m] : (i == lane ? 1.0 : 0.0);
+        L[i][lane + 64] = (i < n && lane + 64 <= i) ? v1[m] : (i == lane + 64 ? 1.0 : 0.0);
+      }
+    }
   }
   __syncthreads();
-  if (wv == 0) wave_potrf64(L, 0, ly, lx, lane, piv, info, k, n);
+  if (wv == 0) wave_potrf64(L, 0, ly, lx, lane, piv, colv, dummy, info, k, n);
   __syncthreads();
   for (int t = tid; t < 64 * 64; t += 256) {
     const int i = t >> 6, j = t & 63;
     if (i < n && j <= i) A[int64_t(k + i) * D + (k + j)] = L[i][j];
   }
   __syncthreads();
-  if (wv == 0) wave_trtri64(L, 0, ly, lx, lane, piv);   // X11 = L11^{-1} in place
+  if (wv == 0) wave_trtri64(L, 0, ly, lx, lane, piv, colv, rowv, dummy);   // X11 = L11^{-1} in place
   __syncthreads();
   f64x4 acc[2][2];
   // L21 = A21 X11^T
@@ -298,14 +357,14 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
         if (j <= i) L[64 + i][64 + j] -= acc[x][y][r];
       }
   __syncthreads();
-  if (wv == 0) wave_potrf64(L, 64, ly, lx, lane, piv, info, k + 64, n - 64);
+  if (wv == 0) wave_potrf64(L, 64, ly, lx, lane, piv, colv, dummy, info, k + 64, n - 64);
   __syncthreads();
   for (int t = tid; t < 64 * NB; t += 256) {
     const int i = 64 + (t >> 7), j = t & (NB - 1);
     if (i < n && j <= i) A[int64_t(k + i) * D + (k + j)] = L[i][j];
   }
   __syncthreads();
-  if (wv == 0) wave_trtri64(L, 64, ly, lx, lane, piv);   // X22 = L22^{-1} in place
+  if (wv == 0) wave_trtri64(L, 64, ly, lx, lane, piv, colv, rowv, dummy);   // X22 = L22^{-1} in place
   __syncthreads();
   // T = L21 X11, stored over L21
   lds_mm64<false>(L, 64, 0, 0, 0, wy, wx, lane, acc);
@@ -331,10 +390,15 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
   __syncthreads();
   double* out = Linv + int64_t(k / NB) * NB * NB;
   double* outT = LinvT + int64_t(k / NB) * NB * NB;
-  for (int t = tid; t < NB * NB; t += 256) {
-    const int i = t >> 7, j = t & (NB - 1);
-    out[t] = (i < n && j <= i) ? L[i][j] : 0.0;
-    outT[t] = (j < n && i <= j) ? L[j][i] : 0.0;
+#pragma unroll 8
+  for (int m = 0; m < 32; ++m) {
+    const int i = wv + 4 * m;
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int j = lane + 64 * h;
+      out[i * NB + j] = (i < n && j <= i) ? L[i][j] : 0.0;
+      outT[i * NB + j] = (j < n && i <= j) ? L[j][i] : 0.0;
+    }
   }
 }
 
@@ -397,12 +461,13 @@ __global__ __launch_bounds__(256) void trsm_kernel(double* __restrict__ A, int32
 // 8 waves of 32 x 64 (2 x 4 MFMA blocks), K = NB in chunks of 16 via LDS with
 // a register double buffer. On a diagonal tile the waves whose block lies
 // above the diagonal only help with the loads.
-__global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32_t D, int32_t k) {
+__global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32_t D, int32_t k,
+                                                  int32_t tile0) {
   constexpr int T = 128, KC = 16;
   __shared__ double sI[T][KC + 1];
   __shared__ double sJ[T][KC + 1];
   int64_t I, J;
-  tri_tile(blockIdx.x, I, J);
+  tri_tile(int64_t(blockIdx.x) + tile0, I, J);
   const bool diag = (I == J);
   const int64_t s0 = int64_t(k) + NB;
   const int64_t I0 = s0 + I * T, J0 = s0 + J * T;
@@ -479,13 +544,16 @@ __global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32
 // Thread (i, h) of 256 issues its 64 coalesced loads (lanes run over i) at
 // once and sums p in [64 h, 64 h + 64); the halves are added in a fixed order.
 // No cross-lane reductions. `part` is 128 doubles of LDS scratch.
-static __device__ __forceinline__ void block_mvT(const double* __restrict__ MT, const double* v,
-                                                 int n, double* __restrict__ out_global,
-                                                 double* part, int tid) {
+static __device__ __forceinline__ void block_mvT_load(const double* __restrict__ MT, double (&a)[64],
+                                                      int tid) {
   const int i = tid & 127, h = tid >> 7;
-  double a[64];
 #pragma unroll
   for (int t = 0; t < 64; ++t) a[t] = MT[(64 * h + t) * NB + i];
+}
+static __device__ __forceinline__ void block_mvT_finish(const double (&a)[64], const double* v,
+                                                        int n, double* __restrict__ out_global,
+                                                        double* part, int tid) {
+  const int i = tid & 127, h = tid >> 7;
   double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
 #pragma unroll
   for (int t = 0; t < 64; t += 4) {
@@ -498,6 +566,13 @@ static __device__ __forceinline__ void block_mvT(const double* __restrict__ MT, 
   if (h == 1) part[i] = s;
   __syncthreads();
   if (h == 0 && i < n) out_global[i] = s + part[i];
+}
+static __device__ __forceinline__ void block_mvT(const double* __restrict__ MT, const double* v,
+                                                 int n, double* __restrict__ out_global,
+                                                 double* part, int tid) {
+  double a[64];
+  block_mvT_load(MT, a, tid);
+  block_mvT_finish(a, v, n, out_global, part, tid);
 }
 
 // Reduce-scatter of 32 per-lane partial sums over the 64 lanes of a wave:
@@ -540,9 +615,12 @@ __global__ __launch_bounds__(256) void trsv_fwd_kernel(const double* __restrict_
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
+  const int64_t r0 = int64_t(k) + NB + int64_t(blockIdx.x) * 128;
+  const bool solver = blockIdx.x == 0;   // owns the next block and solves it
+  double inv[64];
+  if (solver) block_mvT_load(LinvT + (r0 / NB) * NB * NB, inv, tid);   // does not depend on y
   const double y0 = y[k + lane];        // this launch only runs for full blocks
   const double y1 = y[k + 64 + lane];
-  const int64_t r0 = int64_t(k) + NB + int64_t(blockIdx.x) * 128;
   double pr[32];
 #pragma unroll
   for (int r = 0; r < 32; ++r) {
@@ -552,18 +630,19 @@ __global__ __launch_bounds__(256) void trsv_fwd_kernel(const double* __restrict_
     pr[r] = i < D ? v : 0.0;
   }
   const double tot = reduce_scatter32(pr, lane);
-  {
-    const int64_t i = r0 + wv * 32 + (lane >> 1);
-    if ((lane & 1) == 0 && i < D) b[i] -= tot;
+  const int li = wv * 32 + (lane >> 1);
+  const int64_t i = r0 + li;
+  const double bi = b[i < D ? i : D - 1];
+  const double nb = bi - tot;
+  if (!solver) {
+    if ((lane & 1) == 0 && i < D) b[i] = nb;
+    return;
   }
-  if (blockIdx.x != 0) return;
-  __threadfence_block();
+  // the next block's right-hand side never leaves the workgroup
+  if ((lane & 1) == 0) vk[li] = i < D ? nb : 0.0;
   __syncthreads();
-  const int64_t kn = r0;  // next block start
-  const int nn = (D - kn) < NB ? int(D - kn) : NB;
-  if (tid < NB) vk[tid] = tid < nn ? b[kn + min(tid, nn - 1)] : 0.0;
-  __syncthreads();
-  block_mvT(LinvT + (kn / NB) * NB * NB, vk, nn, y + kn, part, tid);
+  const int nn = (D - r0) < NB ? int(D - r0) : NB;
+  block_mvT_finish(inv, vk, nn, y + r0, part, tid);
 }
 
 // x_last = L_last^{-T} c_last (first block of the backward sweep)
@@ -579,45 +658,43 @@ __global__ __launch_bounds__(256) void trsv_bwd_first_kernel(const double* __res
 }
 
 // Backward sweep, block row k (x_k already in x): rows i < k get
-// c_i -= sum_p L[k + p][i] x_k[p]. A workgroup owns 64 rows; thread (r, q)
-// sums p in [32 q, 32 q + 32) with all 32 loads in flight (coalesced over i),
-// and the four partial sums are combined in a fixed order. The rows of the
-// next block [k - NB, k) belong to two workgroups, so that block is solved by
-// a separate small launch afterwards.
-__global__ __launch_bounds__(256) void trsv_bwd_kernel(const double* __restrict__ A, int32_t D,
+// c_i -= sum_p L[k + p][i] x_k[p]. A workgroup owns 128 rows; thread (r, h)
+// sums p in [64 h, 64 h + 64) with all 64 loads in flight (coalesced over
+// i), and the halves are combined in a fixed order. The last workgroup owns
+// the next block [k - NB, k) and solves it: x = L^{-T} c on that block, with
+// the inverse block loaded before the update.
+__global__ __launch_bounds__(256) void trsv_bwd_kernel(const double* __restrict__ A,
+                                                      const double* __restrict__ Linv, int32_t D,
                                                       int32_t k, double* __restrict__ c,
-                                                      const double* __restrict__ x) {
-  __shared__ double xk[NB];
-  __shared__ double part[4][64];
+                                                      double* __restrict__ x) {
+  __shared__ double xk[NB], vk[NB], part[NB];
   const int tid = threadIdx.x;
-  const int r = tid & 63, q = tid >> 6;
+  const int r = tid & 127, h = tid >> 7;
   const int n = (D - k) < NB ? (D - k) : NB;
+  const bool solver = int64_t(blockIdx.x) + 1 == gridDim.x;
+  const int64_t i = int64_t(blockIdx.x) * 128 + r;     // i < k: k is a multiple of NB
+  double inv[64];
+  if (solver) block_mvT_load(Linv + int64_t(k / NB - 1) * NB * NB, inv, tid);
   if (tid < NB) xk[tid] = tid < n ? x[k + min(tid, n - 1)] : 0.0;
   __syncthreads();
-  const int64_t i = int64_t(blockIdx.x) * 64 + r;
-  const int64_t ic = i < k ? i : k - 1;
-  double a[32];
+  double a[64];
 #pragma unroll
-  for (int t = 0; t < 32; ++t) a[t] = A[int64_t(k + min(32 * q + t, n - 1)) * D + ic];
+  for (int t = 0; t < 64; ++t) a[t] = A[int64_t(k + min(64 * h + t, n - 1)) * D + i];
   double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-  for (int t = 0; t < 32; t += 2) {
-    s0 += a[t] * xk[32 * q + t];
-    s1 += a[t + 1] * xk[32 * q + t + 1];
+  for (int t = 0; t < 64; t += 2) {
+    s0 += a[t] * xk[64 * h + t];
+    s1 += a[t + 1] * xk[64 * h + t + 1];
   }
-  part[q][r] = s0 + s1;
+  if (h == 1) part[r] = s0 + s1;
   __syncthreads();
-  if (q == 0 && i < k) c[i] -= ((part[0][r] + part[1][r]) + part[2][r]) + part[3][r];
-}
-
-// x_kp = L_kp^{-T} c_kp for the block that the previous sweep launch finished
-__global__ __launch_bounds__(256) void trsv_bwd_block_kernel(const double* __restrict__ Linv,
-                                                            int32_t kp, const double* __restrict__ c,
-                                                            double* __restrict__ x) {
-  __shared__ double v[NB], part[NB];
-  if (threadIdx.x < NB) v[threadIdx.x] = c[kp + threadIdx.x];
+  if (h == 0) {
+    const double nc = c[i] - ((s0 + s1) + part[r]);
+    if (solver) vk[r] = nc; else c[i] = nc;
+  }
+  if (!solver) return;
   __syncthreads();
-  block_mvT(Linv + (kp / NB) * NB * NB, v, NB, x + kp, part, threadIdx.x);
+  block_mvT_finish(inv, vk, NB, x + (k - NB), part, tid);
 }
 
 // Partial sums of (lower-stored symmetric G) x over 64 x 64 tiles:
@@ -700,12 +777,36 @@ static hipError_t solve_triangular(const SolveWs& w, int32_t D, double* rhs, dou
   }
   hipLaunchKernelGGL(trsv_bwd_first_kernel, dim3(1), dim3(256), 0, st, w.Linv, D, tmp, out);
   const int32_t last = ((D - 1) / NB) * NB;
-  for (int32_t k = last; k > 0; k -= NB) {
-    hipLaunchKernelGGL(trsv_bwd_kernel, dim3(unsigned((int64_t(k) + 63) / 64)), dim3(256), 0, st,
-                       w.A, D, k, tmp, out);
-    hipLaunchKernelGGL(trsv_bwd_block_kernel, dim3(1), dim3(256), 0, st, w.Linv, k - NB, tmp, out);
-  }
+  for (int32_t k = last; k > 0; k -= NB)
+    hipLaunchKernelGGL(trsv_bwd_kernel, dim3(unsigned(k / NB)), dim3(256), 0, st, w.A, w.Linv,
+                       D, k, tmp, out);
   return hipGetLastError();
+}
+
+// Per-device side stream (default priority, non-blocking) and two events for
+// the factorisation lookahead, created on first use and kept for the process.
+static hipError_t lookahead_resources(hipStream_t* side, hipEvent_t* fork, hipEvent_t* join) {
+  struct Res {
+    hipStream_t s = nullptr;
+    hipEvent_t a = nullptr, b = nullptr;
+  };
+  static std::mutex mu;
+  static Res res[64];
+  int dev = 0;
+  hipError_t e = hipGetDevice(&dev);
+  if (e != hipSuccess) return e;
+  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
+  std::lock_guard<std::mutex> lock(mu);
+  Res& r = res[dev];
+  if (r.s == nullptr) {
+    if ((e = hipStreamCreateWithFlags(&r.s, hipStreamNonBlocking)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&r.a, hipEventDisableTiming)) != hipSuccess) return e;
+    if ((e = hipEventCreateWithFlags(&r.b, hipEventDisableTiming)) != hipSuccess) return e;
+  }
+  *side = r.s;
+  *fork = r.a;
+  *join = r.b;
+  return hipSuccess;
 }
 
 template <typename TG>
@@ -716,19 +817,38 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
   const unsigned vg = unsigned((D + 255) / 256);
   hipLaunchKernelGGL(promote_kernel<TG>, dim3(vg, unsigned(D)), dim3(256), 0, st, G, D, lambda,
                      w.A, info);
-  for (int32_t k = 0; k < D; k += NB) {
-    hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, k, info, w.Linv,
-                       w.LinvT);
+  // Right-looking blocked Cholesky with a one-block lookahead: after the
+  // panel solve of block k, the trailing tile that becomes the next diagonal
+  // block is updated first; that block is then factored on a second stream
+  // (one workgroup) while the rest of the trailing update runs on the
+  // caller's stream across the other compute units.
+  hipStream_t side = nullptr;
+  hipEvent_t ev_fork = nullptr, ev_join = nullptr;
+  hipError_t e = lookahead_resources(&side, &ev_fork, &ev_join);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, 0, info, w.Linv,
+                     w.LinvT);
+  for (int32_t k = 0; k + NB < D; k += NB) {
     const int64_t rest = int64_t(D) - k - NB;
-    if (rest > 0) {
-      hipLaunchKernelGGL(trsm_kernel, dim3(unsigned((rest + 63) / 64)), dim3(256), 0, st, w.A, D,
-                         k, w.Linv);
-      const int64_t nt = (rest + 127) / 128;
-      hipLaunchKernelGGL(syrk_kernel, dim3(unsigned(nt * (nt + 1) / 2)), dim3(512), 0, st, w.A,
-                         D, k);
+    hipLaunchKernelGGL(trsm_kernel, dim3(unsigned((rest + 63) / 64)), dim3(256), 0, st, w.A, D, k,
+                       w.Linv);
+    const int64_t nt = (rest + 127) / 128;
+    const int64_t tiles = nt * (nt + 1) / 2;
+    hipLaunchKernelGGL(syrk_kernel, dim3(1), dim3(512), 0, st, w.A, D, k, 0);
+    if (tiles > 1) {
+      if ((e = hipEventRecord(ev_fork, st)) != hipSuccess) return e;
+      if ((e = hipStreamWaitEvent(side, ev_fork, 0)) != hipSuccess) return e;
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, side, w.A, D, k + NB, info,
+                         w.Linv, w.LinvT);
+      if ((e = hipEventRecord(ev_join, side)) != hipSuccess) return e;
+      hipLaunchKernelGGL(syrk_kernel, dim3(unsigned(tiles - 1)), dim3(512), 0, st, w.A, D, k, 1);
+      if ((e = hipStreamWaitEvent(st, ev_join, 0)) != hipSuccess) return e;
+    } else {
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, k + NB, info,
+                         w.Linv, w.LinvT);
     }
   }
-  hipError_t e = hipGetLastError();
+  e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(to_double_kernel<TG>, dim3(vg), dim3(256), 0, st, Zty, w.b, D);
   e = solve_triangular(w, D, w.b, w.y, alpha, st);
