@@ -66,17 +66,22 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-slots", type=int, default=4)
     ap.add_argument("--serve-max-atoms", type=int, default=8192)
+    ap.add_argument("--serve-sweep", default="8000,32000",
+                    help="extra offered loads (req/s), each a trace of --serve-sweep-requests")
+    ap.add_argument("--serve-sweep-requests", type=int, default=4000)
+    ap.add_argument("--precision-mols", type=int, default=100000,
+                    help="molecules of the precision study (0 skips it)")
     return ap.parse_args()
 
 
-def serving_leg(args, dev, log):
-    """Energy+force serving on the Poisson trace (D = 16384, sizes log-uniform
+def serving_leg(args, dev, log, rate, seconds):
+    """Energy+force serving on a Poisson trace (D = 16384, sizes log-uniform
     5..300 atoms): continuous batching vs one molecule per launch, same GPU,
     same kernels, same resident model and request pool."""
     import torch
 
     from paper_2206_01580_amd import serve, sorf, workloads
-    tr = workloads.config5(rate_hz=args.serve_rate, duration_s=args.serve_seconds)
+    tr = workloads.config5(rate_hz=rate, duration_s=seconds)
     J = workloads.device_normal(tr.J_pool_floats, tr.J_seed, 0.1, device=dev)
     pool = serve.RequestPool(tr.x, tr.element, tr.sizes, J, tr.J_off, device=dev)
     model = sorf.Model.from_problem(tr.model)
@@ -95,26 +100,100 @@ def serving_leg(args, dev, log):
             pass
         ex.results.clear()
     torch.cuda.synchronize()
-    log(f"serving: {R} requests, {int(tr.sizes.sum())} atoms, rate {args.serve_rate}/s")
+    log(f"serving: {R} requests, {int(tr.sizes.sum())} atoms, rate {rate:g}/s")
     sb = serve.BatchingScheduler(exb, cap, args.serve_slots, budget).run(tr.arrival_s, tr.sizes)
     torch.cuda.synchronize()
     log(f"serving: batched done ({len(sb.batches)} launches)")
     sp = serve.PlainRunner(exp).run(tr.arrival_s, tr.sizes)
     torch.cuda.synchronize()
     log("serving: plain done")
-    warm = 0.1 * args.serve_seconds
+    warm = 0.1 * seconds
     b, p = sb.summary(warm, tr.arrival_s), sp.summary(warm, tr.arrival_s)
+    del pool, J, exb, exp
+    torch.cuda.empty_cache()
     return {
-        "workload": (f"Poisson {args.serve_rate:g} req/s for {args.serve_seconds:g} s, sizes "
-                     f"log-uniform 5..300 atoms, d=128, D=16384, energies + forces "
-                     f"(J blocks N x 128 x 3N at random offsets of a "
-                     f"{tr.J_pool_floats * 4 >> 20} MiB pool)"),
-        "requests": R, "atoms": int(tr.sizes.sum()), "warmup_s": warm,
+        "workload": (f"Poisson {rate:g} req/s for {seconds:g} s, sizes log-uniform 5..300 atoms, "
+                     f"d=128, D=16384, energies + forces (J blocks N x 128 x 3N at random offsets "
+                     f"of a {tr.J_pool_floats * 4 >> 20} MiB pool)"),
+        "rate_hz": rate, "requests": R, "atoms": int(tr.sizes.sum()), "warmup_s": warm,
         "batched": dict(b, slots=args.serve_slots, max_batch_atoms=cap),
         "plain": p,
         "p50_speedup": (p["p50_ms"] / b["p50_ms"]) if b["p50_ms"] else None,
         "p99_speedup": (p["p99_ms"] / b["p99_ms"]) if b["p99_ms"] else None,
     }
+
+
+def precision_study(args, dev, log):
+    """Gram precision modes on the precision workload (100,000 QM9-like
+    molecules, D = 16384, lambda = 1e-8, 3 refinement steps): coefficient and
+    energy errors of each mode against the FP64 Gram + FP64 solve (the
+    paper's double-precision training), all on the GPU."""
+    import torch
+
+    from paper_2206_01580_amd import sorf, workloads
+    p = workloads.config4(n_mols=args.precision_mols)
+    model, batch = sorf.Model.from_problem(p), sorf.Batch.from_problem(p)
+    D, M = p.n_features, p.n_mols
+    y = torch.from_numpy(p.y).to(dev)
+    Z = sorf.forward(model, batch)
+    solver = sorf.Solver(D, device=dev)
+    ws = sorf.GramWorkspace(dev)
+
+    def energies(alpha):
+        out = torch.empty(M, dtype=torch.float64, device=dev)
+        for r0 in range(0, M, 8192):
+            out[r0:r0 + 8192] = Z[r0:r0 + 8192].double() @ alpha
+        return out
+
+    def timed(fn):
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        fn()
+        e1.record()
+        torch.cuda.synchronize()
+        return e0.elapsed_time(e1)
+
+    G64 = torch.zeros(D, D, dtype=torch.float64, device=dev)
+    r64 = torch.zeros(D, dtype=torch.float64, device=dev)
+    t_g = timed(lambda: sorf.gram_accumulate(Z, G64, y, r64, precision="fp64"))
+    a_ref = solver(G64, r64, p.lam, args.n_refine).clone()
+    torch.cuda.synchronize()
+    info_ref = int(solver.info.item())
+    del G64, r64
+    torch.cuda.empty_cache()
+    E_ref = energies(a_ref)
+    y64 = y.double()
+    rms_ref = float(torch.sqrt(torch.mean(E_ref ** 2)))
+    res = {"fp64": {"gram_ms": t_g, "info": info_ref,
+                    "fit_rmse": float(torch.sqrt(torch.mean((E_ref - y64) ** 2)))}}
+    log(f"precision: reference done (info {info_ref})")
+    G = torch.empty(D, D, device=dev)
+    r = torch.empty(D, device=dev)
+    for mode in ("fp32", "bf16", "fp16", "bf16_hilo", "fp16_hilo"):
+        G.zero_()
+        r.zero_()
+        k = sorf.fp16_scale_exp(29 * math.sqrt(2.0 / D)) if mode.startswith("fp16") else 0
+        t = timed(lambda: sorf.gram_accumulate(Z, G, y, r, precision=mode, scale_exp=k,
+                                               workspace=ws))
+        a = solver(G, r, p.lam, args.n_refine)
+        torch.cuda.synchronize()
+        info = int(solver.info.item())
+        E = energies(a)
+        dE = E - E_ref
+        res[mode] = {
+            "gram_ms": t, "gram_tflops": float(M) * D * (D + 1) / (t * 1e-3) / 1e12, "info": info,
+            "alpha_rel_err": float(torch.linalg.norm(a - a_ref) / torch.linalg.norm(a_ref)),
+            "energy_max_rel_err": float(dE.abs().max()) / rms_ref,
+            "energy_rms_rel_err": float(torch.sqrt(torch.mean(dE ** 2))) / rms_ref,
+            "fit_rmse": float(torch.sqrt(torch.mean((E - y64) ** 2))),
+        }
+        log(f"precision: {mode} done")
+    del G, r, Z, solver, ws
+    torch.cuda.empty_cache()
+    return {"workload": f"{M} QM9-like molecules, d=128, 128 stacks (D={D}), sigma=4, "
+                        f"lambda={p.lam:g}, {args.n_refine} refinement steps",
+            "reference": "FP64 Gram + FP64 Cholesky on the GPU (paper's DP training)",
+            "energy_errors_relative_to": "rms of the reference energies", "modes": res}
 
 
 def cpu_baseline(p, D, n_sample, lam):
@@ -294,7 +373,12 @@ def main():
     del Z, G, model, batch, predictor, solver, grad, gram_ws
     torch.cuda.empty_cache()
     if args.serve_seconds > 0:
-        out["serving"] = serving_leg(args, dev, log)
+        out["serving"] = serving_leg(args, dev, log, args.serve_rate, args.serve_seconds)
+        sweep = [float(r) for r in args.serve_sweep.split(",") if r.strip()]
+        out["serving_load_sweep"] = [
+            serving_leg(args, dev, log, r, args.serve_sweep_requests / r) for r in sweep]
+    if args.precision_mols > 0:
+        out["precision_study"] = precision_study(args, dev, log)
     if not args.no_cpu_baseline:
         log("cpu baseline")
         out["cpu_baseline"] = cpu_baseline(p, D, args.cpu_sample_mols, args.lam)

@@ -83,24 +83,6 @@ __device__ __forceinline__ f32x16 mma16(u16x8 a, u16x8 b, f32x16 c) {
                                                   __builtin_bit_cast(f16x8, b), c, 0, 0, 0);
 }
 
-// Tile t -> (I, J): row I holds the tiles J = 0 .. 2I+1 (clipped to the
-// matrix in the last row); rows before the last hold I (I + 1) tiles in all.
-__device__ __forceinline__ void tile_of(int64_t t, int64_t nI, int64_t nJ, int64_t& I,
-                                        int64_t& J) {
-  const int64_t full = (nI - 1) * nI;
-  if (t >= full) {
-    I = nI - 1;
-    J = t - full;
-    return;
-  }
-  int64_t i = int64_t((std::sqrt(4.0 * double(t) + 1.0) - 1.0) * 0.5);
-  while (i * (i + 1) > t) --i;
-  while ((i + 1) * (i + 2) <= t) ++i;
-  I = i;
-  J = t - i * (i + 1);
-  (void)nJ;
-}
-
 __host__ __device__ inline int64_t gram_tiles(int64_t D, int64_t& nI, int64_t& nJ) {
   nI = (D + TM - 1) / TM;
   nJ = (D + TN - 1) / TN;
@@ -108,11 +90,43 @@ __host__ __device__ inline int64_t gram_tiles(int64_t D, int64_t& nI, int64_t& n
   return (nI - 1) * nI + last;
 }
 
-// Blocks are dealt round-robin to the 8 XCDs; hand each XCD a contiguous run
-// of tiles.
-__device__ __forceinline__ int64_t xcd_tile(int64_t n_tiles) {
-  const int64_t per = (n_tiles + 7) / 8;
-  return int64_t(blockIdx.x % 8) * per + int64_t(blockIdx.x / 8);
+// Workgroups are dealt round-robin to the 8 XCDs, and each XCD runs 32 of
+// them at a time (one per compute unit). Block b therefore gets XCD b % 8
+// and local slot q = b / 8; 32 consecutive slots of one XCD form a
+// super-tile of 4 x 8 tiles (1024 x 1024 entries of G), so the tiles that
+// run together on one XCD share 4 A panels and 8 B panels in its L2.
+// Super-tiles strictly below the diagonal come first, the lighter diagonal
+// ones last. Returns false for slots whose tile is outside the lower
+// triangle or the matrix.
+constexpr int SR_T = 4, SC_T = 8;   // tiles per super-tile (rows, columns)
+
+__host__ __device__ inline int64_t gram_super_tiles(int64_t D) {
+  const int64_t nS = (D + SR_T * TM - 1) / (SR_T * TM);
+  return nS * (nS + 1) / 2;
+}
+
+__device__ __forceinline__ bool super_tile(int64_t D, int64_t nI, int64_t nJ, int64_t& I,
+                                           int64_t& J) {
+  const int64_t nS = (D + SR_T * TM - 1) / (SR_T * TM);
+  const int64_t q = blockIdx.x / 8;
+  const int64_t G = (q / (SR_T * SC_T)) * 8 + blockIdx.x % 8;
+  const int pos = int(q % (SR_T * SC_T));
+  const int64_t off = nS * (nS - 1) / 2;
+  int64_t R, C;
+  if (G < off) {
+    int64_t r = int64_t((1.0 + std::sqrt(1.0 + 8.0 * double(G))) * 0.5);
+    while (r * (r - 1) / 2 > G) --r;
+    while ((r + 1) * r / 2 <= G) ++r;
+    R = r;
+    C = G - r * (r - 1) / 2;
+  } else if (G < off + nS) {
+    R = C = G - off;
+  } else {
+    return false;
+  }
+  I = R * SR_T + pos / SC_T;
+  J = C * SC_T + pos % SC_T;
+  return I < nI && J < nJ && J * TN <= I * TM + TM - 1;
 }
 
 // ------------------------------------------------------------------- packing
@@ -231,10 +245,9 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
   constexpr int KC = kFlushRows / (2 * KB);   // stages per flush
   __shared__ u16x8 ring[NS][NP][NF][64];
 
-  const int64_t t = xcd_tile(n_tiles);
-  if (t >= n_tiles) return;
   int64_t I, J;
-  tile_of(t, nI, nJ, I, J);
+  if (!super_tile(D, nI, nJ, I, J)) return;
+  (void)n_tiles;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
@@ -359,10 +372,9 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
   __shared__ float ra[NS][KB][TM];
   __shared__ float rb[NS][KB][TN];
 
-  const int64_t t = xcd_tile(n_tiles);
-  if (t >= n_tiles) return;
   int64_t I, J;
-  tile_of(t, nI, nJ, I, J);
+  if (!super_tile(D, nI, nJ, I, J)) return;
+  (void)n_tiles;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
@@ -472,10 +484,9 @@ void gram_fp32_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t
   __shared__ float sA[2][KB][LDA];
   __shared__ float sB[2][KB][LDB];
 
-  const int64_t t = xcd_tile(n_tiles);
-  if (t >= n_tiles) return;
   int64_t I, J;
-  tile_of(t, nI, nJ, I, J);
+  if (!super_tile(D, nI, nJ, I, J)) return;
+  (void)n_tiles;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
@@ -761,7 +772,7 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
   }
   int64_t nI, nJ;
   const int64_t n_tiles = gram_tiles(D, nI, nJ);
-  const dim3 grid{unsigned(((n_tiles + 7) / 8) * 8)};
+  const dim3 grid{unsigned(((gram_super_tiles(D) + 7) / 8) * 8 * SR_T * SC_T)};
   switch (mode) {
     case kFP32:
       if (D % 4 == 0) {

@@ -1,0 +1,94 @@
+"""Precision modes of the Gram, end to end through the ridge solve, against
+the FP64 oracle on a reduced precision workload (3000 QM9-like molecules,
+D = 1024, lambda = 1e-8, 3 refinement steps; kappa(G + lambda I) ~ 8e5).
+
+Each GPU mode's coefficients alpha are scored by the energies Z_ora alpha on
+the oracle's own features, relative to the rms of the oracle energies
+(err = max |dE| / rms(E)). What the arithmetic fixes is checked:
+
+* single-product modes (bf16, fp16): their error is the error of rounding
+  the operands, which the oracle reproduces exactly (gram_emulated: the
+  mode's roundings with FP64 products and sums); the GPU must land within a
+  factor 2 of that emulated error;
+* hi+lo and FP32: operand rounding is negligible (emulated 1e-6 .. 1e-4), so
+  what remains is the FP32 summation of G, amplified by kappa; these modes
+  must beat the single fp16 product by at least 5x;
+* FP64: limited by the FP32 features (the GPU computes Z in FP32); bounded
+  by 3e-5, ten times the measured 3.2e-6.
+The measured levels (hi+lo and FP32 about 4e-4 .. 6e-4) are a regression
+guard: they must stay below 2e-3.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import sorf_oracle as O
+from paper_2206_01580_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+MODES = ["fp64", "fp32", "bf16_hilo", "fp16_hilo", "fp16", "bf16"]
+
+
+def _scale_exp(D):
+    return int(max(-60, min(60, math.floor(14 - math.log2(29 * math.sqrt(2.0 / D))))))
+
+
+@pytest.fixture(scope="module")
+def study():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2206_01580_amd import sorf
+    p = W.qm9_like(3000, 8, W.SEED_BASE + 40, "precision-small", sigma=4.0, lam=1e-8)
+    D = p.n_features
+    Zo = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma,
+                             chunk_atoms=1 << 20)
+    Go, ro = O.gram(Zo, p.y)
+    Eo = Zo @ O.solve(Go, ro, p.lam)
+    rms = math.sqrt(np.mean(Eo ** 2))
+    emulated = {}
+    for mode in ("bf16", "fp16"):
+        Ge = O.gram_emulated(Zo, mode, _scale_exp(D) if mode == "fp16" else 0)
+        emulated[mode] = np.abs(Zo @ O.solve(Ge, ro, p.lam) - Eo).max() / rms
+    model, batch = sorf.Model.from_problem(p), sorf.Batch.from_problem(p)
+    Z = sorf.forward(model, batch)
+    y = torch.from_numpy(p.y).cuda()
+    solver = sorf.Solver(D, device="cuda")
+    errs, infos = {}, {}
+    for mode in MODES:
+        dt = torch.float64 if mode == "fp64" else torch.float32
+        G = torch.zeros(D, D, device="cuda", dtype=dt)
+        r = torch.zeros(D, device="cuda", dtype=dt)
+        k = _scale_exp(D) if mode.startswith("fp16") else 0
+        sorf.gram_accumulate(Z, G, y, r, precision=mode, scale_exp=k)
+        a = solver(G, r, p.lam, 3)
+        torch.cuda.synchronize()
+        infos[mode] = int(solver.info.item())
+        errs[mode] = np.abs(Zo @ a.cpu().numpy() - Eo).max() / rms
+    print("energy error per mode:", {m: f"{e:.3e}" for m, e in errs.items()},
+          "emulated:", {m: f"{e:.3e}" for m, e in emulated.items()})
+    return errs, infos, emulated
+
+
+@pytest.mark.parametrize("mode", MODES)
+def test_mode_factors(study, mode):
+    assert study[1][mode] == 0
+
+
+@pytest.mark.parametrize("mode", ["bf16", "fp16"])
+def test_single_product_modes_reproduce_their_rounding(study, mode):
+    errs, _, emulated = study
+    assert 0.5 * emulated[mode] <= errs[mode] <= 2.0 * emulated[mode], (errs[mode], emulated[mode])
+
+
+@pytest.mark.parametrize("mode", ["fp32", "bf16_hilo", "fp16_hilo"])
+def test_fp32_class_modes(study, mode):
+    errs = study[0]
+    assert errs[mode] <= 2e-3
+    assert errs[mode] * 5 <= errs["fp16"]
+
+
+def test_fp64_mode(study):
+    assert study[0]["fp64"] <= 3e-5
