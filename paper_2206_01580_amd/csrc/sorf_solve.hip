@@ -43,7 +43,7 @@ static __device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
 struct SolveWs {
   double* A;     // [D][D], lower triangle used
   double* Linv;  // [nblk][NB][NB] inverses of the diagonal blocks
-  double* LinvT; // [nblk][NB][NB] their transposes (row access for the backward sweep)
+  double* LinvT; // [nblk][NB][NB] their transposes (row access in the forward sweep)
   double* b;     // [D]
   double* y;     // [D]
   double* dx;    // [D]
@@ -119,36 +119,66 @@ static __device__ __forceinline__ void wave_step_fence() {
 // Cholesky, unscaled right-looking form: at step J every entry (i, l) with
 // i >= l > J loses A[i][J] A[l][J] / A[J][J]; the columns are scaled by
 // 1/sqrt(A[J][J]) after the last step (piv[] keeps the square roots).
+// Software-pipelined: a step first updates the block column that holds
+// column J + 1, publishes that column and issues the reads the next step
+// needs (fr, cr, dJ), and only then updates the remaining block columns, so
+// the LDS round trip overlaps the bulk of the FMAs.
+static __device__ __forceinline__ void order_fence() { __atomic_signal_fence(__ATOMIC_SEQ_CST); }
+
+template <int JB, int BC>
+static __device__ __forceinline__ void rpotrf_col(double (&R)[8][8], const double (&f)[8],
+                                                  const double (&c)[8], bool lower) {
+#pragma unroll
+  for (int a = BC; a < 8; ++a)
+    R[a][BC] = __builtin_fma(-f[a], a == BC ? (lower ? c[BC] : 0.0) : c[BC], R[a][BC]);
+}
+
 template <int JB>
 static __device__ __forceinline__ void rpotrf_block(double (&R)[8][8], double* col, double* piv,
                                                     double* dummy, int ly, int lx, int lane,
-                                                    int32_t* info, int gbase, int nvalid) {
+                                                    double (&fr)[8], double (&cr)[8],
+                                                    double& dJ) {
   const bool lower = ly >= lx;
   for (int jr = 0; jr < 8; ++jr) {
     const int J = 8 * JB + jr;
-#pragma unroll
-    for (int a = JB; a < 8; ++a) *(lx == jr ? &col[ly + 8 * a] : &dummy[lane]) = R[a][JB];
-    wave_step_fence();
-    const double d = col[J];
-    const bool bad = !(d > 0.0) || !std::isfinite(d);
-    if (bad && lane == 0 && J < nvalid && *info == 0) *info = gbase + J + 1;
-    *(lane == 0 ? &piv[J] : &dummy[lane]) = bad ? __builtin_nan("") : std::sqrt(d);
+    const double d = dJ;
+    *(lane == 0 ? &piv[J] : &dummy[lane]) = d;   // checked and rooted after the last step
     const double rd = recip(d);
     double f[8], c[8];
 #pragma unroll
-    for (int a = JB; a < 8; ++a) f[a] = col[ly + 8 * a] * rd;
+    for (int a = 0; a < 8; ++a) f[a] = a >= JB ? fr[a] * rd : 0.0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) c[b] = (b >= JB && lx + 8 * b > J) ? cr[b] : 0.0;
+    // 1. the block column of column J + 1, then publish column J + 1
+    if (jr < 7) {
+      rpotrf_col<JB, JB>(R, f, c, lower);
+#pragma unroll
+      for (int a = JB; a < 8; ++a) *(lx == jr + 1 ? &col[ly + 8 * a] : &dummy[lane]) = R[a][JB];
+    } else if constexpr (JB < 7) {
+      rpotrf_col<JB, JB + 1>(R, f, c, lower);
+#pragma unroll
+      for (int a = JB + 1; a < 8; ++a) *(lx == 0 ? &col[ly + 8 * a] : &dummy[lane]) = R[a][JB + 1];
+    }
+    order_fence();
+    // 2. the next step's reads
+    if (J + 1 < 64) {
+#pragma unroll
+      for (int a = JB; a < 8; ++a) {
+        fr[a] = col[ly + 8 * a];
+        cr[a] = col[lx + 8 * a];
+      }
+      dJ = col[J + 1];
+    }
+    order_fence();
+    // 3. the remaining block columns
 #pragma unroll
     for (int b = JB; b < 8; ++b) {
-      const double cl = col[lx + 8 * b];
-      c[b] = lx + 8 * b > J ? cl : 0.0;
-    }
+      if (b == JB && jr < 7) continue;
+      if (b == JB + 1 && jr == 7) continue;
 #pragma unroll
-    for (int a = JB; a < 8; ++a) {
-#pragma unroll
-      for (int b = JB; b < a; ++b) R[a][b] = __builtin_fma(-f[a], c[b], R[a][b]);
-      R[a][a] = __builtin_fma(-f[a], lower ? c[a] : 0.0, R[a][a]);
+      for (int a = b; a < 8; ++a)
+        R[a][b] = __builtin_fma(-f[a], a == b ? (lower ? c[b] : 0.0) : c[b], R[a][b]);
     }
-    wave_step_fence();
   }
 }
 
@@ -160,14 +190,36 @@ static __device__ __forceinline__ void wave_potrf64(LdsBlock* L, int o, int ly, 
   for (int a = 0; a < 8; ++a)
 #pragma unroll
     for (int b = 0; b < 8; ++b) R[a][b] = L[o + ly + 8 * a][o + lx + 8 * b];
-  rpotrf_block<0>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
-  rpotrf_block<1>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
-  rpotrf_block<2>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
-  rpotrf_block<3>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
-  rpotrf_block<4>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
-  rpotrf_block<5>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
-  rpotrf_block<6>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
-  rpotrf_block<7>(R, col, piv, dummy, ly, lx, lane, info, gbase, nvalid);
+  // publish column 0 and read it for the first step
+#pragma unroll
+  for (int a = 0; a < 8; ++a) *(lx == 0 ? &col[ly + 8 * a] : &dummy[lane]) = R[a][0];
+  wave_step_fence();
+  double fr[8], cr[8], dJ;
+#pragma unroll
+  for (int a = 0; a < 8; ++a) {
+    fr[a] = col[ly + 8 * a];
+    cr[a] = col[lx + 8 * a];
+  }
+  dJ = col[0];
+  order_fence();
+  rpotrf_block<0>(R, col, piv, dummy, ly, lx, lane, fr, cr, dJ);
+  rpotrf_block<1>(R, col, piv, dummy, ly, lx, lane, fr, cr, dJ);
+  rpotrf_block<2>(R, col, piv, dummy, ly, lx, lane, fr, cr, dJ);
+  rpotrf_block<3>(R, col, piv, dummy, ly, lx, lane, fr, cr, dJ);
+  rpotrf_block<4>(R, col, piv, dummy, ly, lx, lane, fr, cr, dJ);
+  rpotrf_block<5>(R, col, piv, dummy, ly, lx, lane, fr, cr, dJ);
+  rpotrf_block<6>(R, col, piv, dummy, ly, lx, lane, fr, cr, dJ);
+  rpotrf_block<7>(R, col, piv, dummy, ly, lx, lane, fr, cr, dJ);
+  wave_step_fence();
+  // pivots: the first one that is not positive and finite sets info
+  {
+    const double d = piv[lane];
+    const bool bad = !(d > 0.0) || !std::isfinite(d);
+    const unsigned long long m = __ballot(bad && lane < nvalid);
+    if (m != 0ull && lane == 0 && *info == 0) *info = gbase + __ffsll((long long)m);
+    piv[lane] = bad ? __builtin_nan("") : std::sqrt(d);
+  }
+  wave_step_fence();
   // L[i][l] = A[i][l] / piv[l] below the diagonal, piv[l] on it, 0 above
 #pragma unroll
   for (int b = 0; b < 8; ++b) {
@@ -187,43 +239,68 @@ static __device__ __forceinline__ void wave_potrf64(LdsBlock* L, int o, int ly, 
 // [L | I] in place: at step Q every row i > Q loses L[i][Q] / L[Q][Q] times
 // the (still unscaled) row Q of X on the columns c < Q, and X[i][Q] becomes
 // -L[i][Q] / L[Q][Q]. Row Q is final after step Q except for the scale
-// 1/L[Q][Q], applied at the end (rinv[] holds the reciprocal pivots).
+// 1/L[Q][Q], applied at the end (rinv[] holds the reciprocal pivots). The
+// columns of L are read from the untouched LDS copy; a step first finishes
+// row Q + 1, publishes it and issues the next step's reads, then updates the
+// remaining block rows.
+template <int QB, int BR>
+static __device__ __forceinline__ void rtrtri_row(double (&R)[8][8], const double (&f)[8],
+                                                  const double (&r)[8], bool colq) {
+#pragma unroll
+  for (int b = 0; b <= QB; ++b) R[BR][b] = __builtin_fma(-f[BR], r[b], R[BR][b]);
+  R[BR][QB] = colq ? -f[BR] : R[BR][QB];
+}
+
 template <int QB>
-static __device__ __forceinline__ void rtrtri_block(double (&R)[8][8], double* colv,
+static __device__ __forceinline__ void rtrtri_block(double (&R)[8][8], const LdsBlock* L, int o,
                                                     double* rowv, const double* rinv,
-                                                    double* dummy, int ly, int lx, int lane) {
+                                                    double* dummy, int ly, int lx, int lane,
+                                                    double (&rowr)[8], double (&coll)[8],
+                                                    double& inv) {
   for (int qr = 0; qr < 8; ++qr) {
     const int Q = 8 * QB + qr;
-#pragma unroll
-    for (int b = 0; b <= QB; ++b) *(ly == qr ? &rowv[lx + 8 * b] : &dummy[lane]) = R[QB][b];
-#pragma unroll
-    for (int a = QB; a < 8; ++a) *(lx == qr ? &colv[ly + 8 * a] : &dummy[lane]) = R[a][QB];
-    wave_step_fence();
-    const double inv = rinv[Q];
     double f[8], r[8];
 #pragma unroll
+    for (int a = 0; a < 8; ++a) f[a] = (a >= QB && ly + 8 * a > Q) ? coll[a] * inv : 0.0;
+#pragma unroll
+    for (int b = 0; b < 8; ++b) r[b] = (b <= QB && lx + 8 * b < Q) ? rowr[b] : 0.0;
+    const bool mine = lx == qr;   // this lane holds column Q in block column QB
+    // 1. row Q + 1, then publish it (entries at columns <= Q)
+    if (qr < 7) {
+      rtrtri_row<QB, QB>(R, f, r, mine && ly + 8 * QB > Q);
+#pragma unroll
+      for (int b = 0; b <= QB; ++b) *(ly == qr + 1 ? &rowv[lx + 8 * b] : &dummy[lane]) = R[QB][b];
+    } else if constexpr (QB < 7) {
+      rtrtri_row<QB, QB + 1>(R, f, r, mine);
+#pragma unroll
+      for (int b = 0; b <= QB; ++b) *(ly == 0 ? &rowv[lx + 8 * b] : &dummy[lane]) = R[QB + 1][b];
+    }
+    order_fence();
+    // 2. the next step's reads
+    if (Q + 1 < 64) {
+#pragma unroll
+      for (int b = 0; b < 8; ++b) rowr[b] = rowv[min(lx + 8 * b, 63)];
+#pragma unroll
+      for (int a = 0; a < 8; ++a) coll[a] = L[o + ly + 8 * a][o + Q + 1];
+      inv = rinv[Q + 1];
+    }
+    order_fence();
+    // 3. the remaining block rows
+#pragma unroll
     for (int a = QB; a < 8; ++a) {
-      const double v = colv[ly + 8 * a];
-      f[a] = ly + 8 * a > Q ? v * inv : 0.0;
-    }
-#pragma unroll
-    for (int b = 0; b <= QB; ++b) {
-      const double v = rowv[lx + 8 * b];
-      r[b] = lx + 8 * b < Q ? v : 0.0;
-    }
-#pragma unroll
-    for (int a = QB; a < 8; ++a)
+      if (a == QB && qr < 7) continue;
+      if (a == QB + 1 && qr == 7) continue;
 #pragma unroll
       for (int b = 0; b <= QB; ++b) R[a][b] = __builtin_fma(-f[a], r[b], R[a][b]);
-#pragma unroll
-    for (int a = QB; a < 8; ++a) R[a][QB] = (lx == qr && ly + 8 * a > Q) ? -f[a] : R[a][QB];
-    wave_step_fence();
+      R[a][QB] = (mine && ly + 8 * a > Q) ? -f[a] : R[a][QB];
+    }
   }
 }
 
 static __device__ __forceinline__ void wave_trtri64(LdsBlock* L, int o, int ly, int lx, int lane,
                                                     double* rinv, double* colv, double* rowv,
                                                     double* dummy) {
+  (void)colv;
   rinv[lane] = recip(L[o + lane][o + lane]);
   double R[8][8];
 #pragma unroll
@@ -231,14 +308,22 @@ static __device__ __forceinline__ void wave_trtri64(LdsBlock* L, int o, int ly, 
 #pragma unroll
     for (int b = 0; b < 8; ++b) R[a][b] = L[o + ly + 8 * a][o + lx + 8 * b];
   wave_step_fence();
-  rtrtri_block<0>(R, colv, rowv, rinv, dummy, ly, lx, lane);
-  rtrtri_block<1>(R, colv, rowv, rinv, dummy, ly, lx, lane);
-  rtrtri_block<2>(R, colv, rowv, rinv, dummy, ly, lx, lane);
-  rtrtri_block<3>(R, colv, rowv, rinv, dummy, ly, lx, lane);
-  rtrtri_block<4>(R, colv, rowv, rinv, dummy, ly, lx, lane);
-  rtrtri_block<5>(R, colv, rowv, rinv, dummy, ly, lx, lane);
-  rtrtri_block<6>(R, colv, rowv, rinv, dummy, ly, lx, lane);
-  rtrtri_block<7>(R, colv, rowv, rinv, dummy, ly, lx, lane);
+  double rowr[8], coll[8], inv;
+#pragma unroll
+  for (int b = 0; b < 8; ++b) rowr[b] = 0.0;   // row 0 has no entries left of the diagonal
+#pragma unroll
+  for (int a = 0; a < 8; ++a) coll[a] = L[o + ly + 8 * a][o];
+  inv = rinv[0];
+  order_fence();
+  rtrtri_block<0>(R, L, o, rowv, rinv, dummy, ly, lx, lane, rowr, coll, inv);
+  rtrtri_block<1>(R, L, o, rowv, rinv, dummy, ly, lx, lane, rowr, coll, inv);
+  rtrtri_block<2>(R, L, o, rowv, rinv, dummy, ly, lx, lane, rowr, coll, inv);
+  rtrtri_block<3>(R, L, o, rowv, rinv, dummy, ly, lx, lane, rowr, coll, inv);
+  rtrtri_block<4>(R, L, o, rowv, rinv, dummy, ly, lx, lane, rowr, coll, inv);
+  rtrtri_block<5>(R, L, o, rowv, rinv, dummy, ly, lx, lane, rowr, coll, inv);
+  rtrtri_block<6>(R, L, o, rowv, rinv, dummy, ly, lx, lane, rowr, coll, inv);
+  rtrtri_block<7>(R, L, o, rowv, rinv, dummy, ly, lx, lane, rowr, coll, inv);
+  wave_step_fence();
   // row i scaled by 1/L[i][i] below the diagonal; the diagonal becomes 1/L[i][i]
 #pragma unroll
   for (int a = 0; a < 8; ++a) {
@@ -285,8 +370,9 @@ static __device__ __forceinline__ void lds_mm64(LdsBlock* L, int ar, int ac, int
 #define SORF_MM_ROW(wy, x, lane, r) (32 * (wy) + 16 * (x) + ((lane) >> 4) + 4 * (r))
 #define SORF_MM_COL(wx, y, lane) (32 * (wx) + 16 * (y) + ((lane) & 15))
 
-// Factor the diagonal block at (k, k), write L back into A and the inverse of
-// L (and its transpose) into Linv / LinvT[k / NB]. 256 threads.
+// Factor the diagonal block at (k, k) and write the inverse of
+// L into Linv[k / NB] (the diagonal block of L itself is not needed again:
+// the panel solve and the sweeps use the inverse). 256 threads.
 //   L = [L11 0; L21 L22]:  L11 = chol(A11), L21 = A21 L11^{-T},
 //   L22 = chol(A22 - L21 L21^T);  L^{-1} = [X11 0; -X22 L21 X11, X22].
 __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A, int32_t D, int32_t k,
@@ -326,11 +412,6 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
   __syncthreads();
   if (wv == 0) wave_potrf64(L, 0, ly, lx, lane, piv, colv, dummy, info, k, n);
   __syncthreads();
-  for (int t = tid; t < 64 * 64; t += 256) {
-    const int i = t >> 6, j = t & 63;
-    if (i < n && j <= i) A[int64_t(k + i) * D + (k + j)] = L[i][j];
-  }
-  __syncthreads();
   if (wv == 0) wave_trtri64(L, 0, ly, lx, lane, piv, colv, rowv, dummy);   // X11 = L11^{-1} in place
   __syncthreads();
   f64x4 acc[2][2];
@@ -359,11 +440,6 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
   __syncthreads();
   if (wv == 0) wave_potrf64(L, 64, ly, lx, lane, piv, colv, dummy, info, k + 64, n - 64);
   __syncthreads();
-  for (int t = tid; t < 64 * NB; t += 256) {
-    const int i = 64 + (t >> 7), j = t & (NB - 1);
-    if (i < n && j <= i) A[int64_t(k + i) * D + (k + j)] = L[i][j];
-  }
-  __syncthreads();
   if (wv == 0) wave_trtri64(L, 64, ly, lx, lane, piv, colv, rowv, dummy);   // X22 = L22^{-1} in place
   __syncthreads();
   // T = L21 X11, stored over L21
@@ -389,7 +465,7 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
         L[64 + SORF_MM_ROW(wy, x, lane, r)][SORF_MM_COL(wx, y, lane)] = -acc[x][y][r];
   __syncthreads();
   double* out = Linv + int64_t(k / NB) * NB * NB;
-  double* outT = LinvT + int64_t(k / NB) * NB * NB;
+  (void)LinvT;   // transposed by transpose_blocks_kernel after the factorisation
 #pragma unroll 8
   for (int m = 0; m < 32; ++m) {
     const int i = wv + 4 * m;
@@ -397,9 +473,28 @@ __global__ __launch_bounds__(256) void potrf_diag_kernel(double* __restrict__ A,
     for (int h = 0; h < 2; ++h) {
       const int j = lane + 64 * h;
       out[i * NB + j] = (i < n && j <= i) ? L[i][j] : 0.0;
-      outT[i * NB + j] = (j < n && i <= j) ? L[j][i] : 0.0;
     }
   }
+}
+
+// LinvT[b] = Linv[b]^T for every diagonal block (the backward sweeps read
+// rows of the transposed inverses). One workgroup per block, 32 x 32 tiles
+// through LDS.
+__global__ __launch_bounds__(256) void transpose_blocks_kernel(const double* __restrict__ Linv,
+                                                              double* __restrict__ LinvT) {
+  __shared__ double t[32][33];
+  const double* src = Linv + int64_t(blockIdx.x) * NB * NB;
+  double* dst = LinvT + int64_t(blockIdx.x) * NB * NB;
+  const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;   // 32 x 8
+  for (int bi = 0; bi < NB; bi += 32)
+    for (int bj = 0; bj < NB; bj += 32) {
+#pragma unroll
+      for (int r = 0; r < 32; r += 8) t[ty + r][tx] = src[(bi + ty + r) * NB + bj + tx];
+      __syncthreads();
+#pragma unroll
+      for (int r = 0; r < 32; r += 8) dst[(bj + ty + r) * NB + bi + tx] = t[tx][ty + r];
+      __syncthreads();
+    }
 }
 
 // Panel below the diagonal block: L21 = A21 (L11^{-1})^T, in place.
@@ -848,6 +943,8 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
                          w.Linv, w.LinvT);
     }
   }
+  hipLaunchKernelGGL(transpose_blocks_kernel, dim3(unsigned((D + NB - 1) / NB)), dim3(256), 0, st,
+                     w.Linv, w.LinvT);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(to_double_kernel<TG>, dim3(vg), dim3(256), 0, st, Zty, w.b, D);
