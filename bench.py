@@ -50,6 +50,26 @@ def valu_slots_per_feature(d: int, T: int, backward: bool = False) -> float:
     return 2 * (T * lg + T) + 1 + 8 + 3
 
 
+def measured_traffic(mode, M, D):
+    """HBM bytes per Gram call (pack + products) from the committed PMC
+    measurement, valid only for the same mode and size and while the Gram
+    source is unchanged since the counters were taken; else None."""
+    import hashlib
+    path = os.path.join(ROOT, "profiles", "gram_traffic.json")
+    src = os.path.join(ROOT, "paper_2206_01580_amd", "csrc", "sorf_gram.hip")
+    try:
+        with open(path) as f:
+            rec = json.load(f)
+        with open(src, "rb") as f:
+            h = hashlib.sha256(f.read()).hexdigest()
+    except OSError:
+        return None
+    if rec.get("source_sha256") != h or rec.get("mode") != mode or rec.get("M") != M \
+            or rec.get("D") != D:
+        return None
+    return rec.get("traffic_bytes")
+
+
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -71,6 +91,9 @@ def parse():
     ap.add_argument("--serve-sweep-requests", type=int, default=4000)
     ap.add_argument("--precision-mols", type=int, default=100000,
                     help="molecules of the precision study (0 skips it)")
+    ap.add_argument("--copy-probe-mib", type=int, default=0,
+                    help="run one device copy of this many MiB first (scale reference for "
+                         "the FETCH_SIZE / WRITE_SIZE counters)")
     return ap.parse_args()
 
 
@@ -241,6 +264,15 @@ def main():
 
     dev = torch.device("cuda:0")
     torch.cuda.set_device(dev)
+    if args.copy_probe_mib > 0:
+        n = args.copy_probe_mib << 18                    # floats
+        src = torch.ones(n, device=dev)
+        dst = torch.empty(n, device=dev)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
+        torch.cuda.empty_cache()
     t_gen = time.perf_counter()
     p = workloads.config2(n_mols=args.n_mols)
     gen_s = time.perf_counter() - t_gen
@@ -339,6 +371,9 @@ def main():
                             "unit": "T VALU-slots/s", "frac": pred_tops / PEAK_VALU_TOPS,
                             "traffic": None, "ms": med["predict"]}
     # the dominant single kernel launch (the solve phase is ~1000 launches of 9 kernels)
+    tr = measured_traffic(args.gram, M, D)
+    if tr is not None:
+        rooflines["gram"]["traffic"] = tr
     dominant = max(("gram", "forward", "backward", "predict"), key=lambda k: med[k])
     roof = {k: v for k, v in rooflines[dominant].items() if k != "ms"}
     roof["kernel"] = dominant
