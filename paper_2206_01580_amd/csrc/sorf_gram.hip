@@ -357,6 +357,174 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
       }
 }
 
+// ------------------------------------------ 16-bit single-product modes
+// One workgroup (4 waves, 2 x 2) per 256 x 256 square tile of the lower
+// triangle and one slice of the rows; each wave owns 128 x 128 (4 x 4
+// blocks of 32 x 32), which halves the LDS bytes per product against the
+// 128 x 64 waves of the hi+lo kernel. The single accumulator is kept for
+// the whole slice: its drift is orders of magnitude below the rounding of
+// the 16-bit operands. With more than one slice, each slice writes its
+// partial tile and gram_combine_kernel adds the partials to G in a fixed
+// order, so results stay deterministic.
+constexpr int TX = 256;   // square tile of the single-product kernel
+
+__host__ __device__ inline int64_t x1_tiles(int64_t D) {
+  const int64_t n = (D + TX - 1) / TX;
+  return n * (n + 1) / 2;
+}
+
+__device__ __forceinline__ void x1_tile_of(int64_t t, int64_t& I, int64_t& J) {
+  int64_t i = int64_t((std::sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while (i * (i + 1) / 2 > t) --i;
+  while ((i + 1) * (i + 2) / 2 <= t) ++i;
+  I = i;
+  J = t - i * (i + 1) / 2;
+}
+
+template <int MODE>
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t n_slabs, int32_t ncb, int32_t D,
+                    int64_t n_tiles, int32_t n_split, float gscale, float* __restrict__ G,
+                    float* __restrict__ part) {
+  constexpr int AF = 2 * (TX / 32);   // A fragments per stage (2 slabs)
+  constexpr int NF = 2 * AF;          // A and B
+  constexpr int FW = NF / 4;          // copies per wave per stage
+  constexpr int NS = 4;
+  __shared__ u16x8 ring[NS][NF][64];
+
+  // items are (split, tile), split-major; each XCD gets a contiguous run
+  const int64_t n_items = n_tiles * n_split;
+  const int64_t per = (n_items + 7) / 8;
+  const int64_t item = int64_t(blockIdx.x % 8) * per + int64_t(blockIdx.x / 8);
+  if (item >= n_items) return;
+  const int64_t t = item % n_tiles;
+  const int sp = int(item / n_tiles);
+  int64_t I, J;
+  x1_tile_of(t, I, J);
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int wy = wv >> 1, wx = wv & 1;
+  const bool active = I * TX + wy * 128 + 127 >= J * TX + wx * 128;
+
+  // the slice of 2-slab stages this item accumulates
+  const int64_t n_st_all = n_slabs / 2;
+  const int64_t s0 = n_st_all * sp / n_split, s1 = n_st_all * (sp + 1) / n_split;
+  const int64_t n_st = s1 - s0;
+
+  int64_t src[FW];
+#pragma unroll
+  for (int c = 0; c < FW; ++c) {
+    const int f = wv + 4 * c;
+    const int slab = (f % AF) / (TX / 32);
+    const int64_t cbf = (f < AF ? I : J) * (TX / 32) + (f % AF) % (TX / 32);
+    src[c] = ((2 * s0 + slab) * int64_t(ncb) + cbf) * 64 + lane;
+  }
+  const int64_t stage_stride = int64_t(2) * ncb * 64;
+  auto issue = [&](int64_t st, int slot) {
+    const int64_t off = st * stage_stride;
+#pragma unroll
+    for (int c = 0; c < FW; ++c) dma16(hi + src[c] + off, &ring[slot][wv + 4 * c][0]);
+  };
+
+  f32x16 P[4][4];
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) P[a][b][r] = 0.0f;
+
+#pragma unroll
+  for (int j = 0; j < NS - 1; ++j)
+    if (j < n_st) issue(j, j);
+  int slot = 0;
+  for (int64_t st = 0; st < n_st; ++st) {
+    const int64_t left = n_st - 1 - st;
+    wait_stage<FW>(left < NS - 2 ? left : NS - 2);
+    stage_barrier();
+    if (st + NS - 1 < n_st) issue(st + NS - 1, slot == 0 ? NS - 1 : slot - 1);
+    u16x8 af[2][4], bf[2][4];
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        af[kk][q] = ring[slot][kk * (TX / 32) + wy * 4 + q][lane];
+        bf[kk][q] = ring[slot][AF + kk * (TX / 32) + wx * 4 + q][lane];
+      }
+    __builtin_amdgcn_sched_barrier(0);
+#pragma unroll
+    for (int kk = 0; kk < 2; ++kk)
+#pragma unroll
+      for (int a = 0; a < 4; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) P[a][b] = mma16<MODE>(af[kk][a], bf[kk][b], P[a][b]);
+    slot = slot + 1 == NS ? 0 : slot + 1;
+  }
+
+  if (!active) return;
+  if (n_split == 1) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int64_t gi = I * TX + wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int64_t gj = J * TX + wx * 128 + b * 32 + (lane & 31);
+          if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += P[a][b][r] * gscale;
+        }
+    return;
+  }
+  float* out = part + (int64_t(sp) * n_tiles + t) * TX * TX;
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        const int i = wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int j = wx * 128 + b * 32 + (lane & 31);
+        out[i * TX + j] = P[a][b][r];
+      }
+}
+
+// G += sum over the slices of the partial tiles, slice 0 first. Partial
+// entries of waves above the diagonal are never written and never read.
+__global__ __launch_bounds__(256) void gram_combine_kernel(const float* __restrict__ part,
+                                                          int64_t n_tiles, int32_t n_split,
+                                                          int32_t D, float gscale,
+                                                          float* __restrict__ G) {
+  const int64_t t = blockIdx.x;
+  int64_t I, J;
+  x1_tile_of(t, I, J);
+  for (int e = threadIdx.x; e < TX * TX; e += 256) {
+    const int i = e / TX, j = e % TX;
+    const int64_t gi = I * TX + i, gj = J * TX + j;
+    if (gi >= D || gj >= D || gi < gj) continue;
+    float acc = 0.0f;
+    for (int sp = 0; sp < n_split; ++sp) acc += part[(int64_t(sp) * n_tiles + t) * TX * TX + e];
+    G[gi * D + gj] += acc * gscale;
+  }
+}
+
+// Slices of rows for the single-product kernel: the count (1, 2 or 4) that
+// minimises whole rounds of 256 workgroups times the work per item.
+static int x1_splits(int64_t D, int64_t n_stages) {
+  const int64_t nt = x1_tiles(D);
+  int best = 1;
+  double best_cost = 1e300;
+  for (int sk = 1; sk <= 4; sk *= 2) {
+    if (sk > 1 && n_stages < 8 * sk) break;
+    const double cost = double((nt * sk + 255) / 256) / sk;
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = sk;
+    }
+  }
+  return best;
+}
+
 // ------------------------------------------------ FP32 mode, D % 4 == 0
 // Stage = 16 rows of Z: 16 A rows of 256 floats (one wave copy each) and 16 B
 // rows of 128 floats (one copy per pair of rows), in a ring of 4 stages.
@@ -718,11 +886,18 @@ GramLayout gram_layout(int64_t M, int32_t D) {
 }
 }  // namespace
 
+size_t x1_partial_bytes(int64_t n_rows, int32_t D) {
+  const GramLayout g = gram_layout(n_rows, D);
+  const int sk = x1_splits(D, g.n_slabs / 2);
+  return sk > 1 ? al256(size_t(sk) * size_t(x1_tiles(D)) * TX * TX * sizeof(float)) : 0;
+}
+
 size_t sorf_gram_ws_bytes(int64_t n_rows, int32_t D, int mode) {
   if (n_rows <= 0 || D <= 0) return 0;
   const GramLayout g = gram_layout(n_rows, D);
   size_t b = g.zpart_bytes + kZeroBytes;
   if (mode != kFP32) b += g.part_bytes * (is_hilo(mode) ? 2 : 1);
+  if (mode == kBF16 || mode == kFP16) b += x1_partial_bytes(n_rows, D);
   return b;
 }
 
@@ -787,13 +962,24 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
       }
       break;
     case kBF16:
-      hipLaunchKernelGGL(gram_packed_kernel<kBF16>, grid, blk, 0, st, hi, lo, g.n_slabs, g.ncb, D,
-                         n_tiles, nI, nJ, gs, G);
+    case kFP16: {
+      const int sk = x1_splits(D, g.n_slabs / 2);
+      const int64_t nt = x1_tiles(D);
+      float* part = reinterpret_cast<float*>(w + g.zpart_bytes + kZeroBytes + g.part_bytes);
+      const dim3 xg{unsigned(((nt * sk + 7) / 8) * 8)};
+      if (mode == kBF16)
+        hipLaunchKernelGGL(gram_x1_kernel<kBF16>, xg, blk, 0, st, hi, g.n_slabs, g.ncb, D, nt, sk,
+                           gs, G, part);
+      else
+        hipLaunchKernelGGL(gram_x1_kernel<kFP16>, xg, blk, 0, st, hi, g.n_slabs, g.ncb, D, nt, sk,
+                           gs, G, part);
+      if (sk > 1) {
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        hipLaunchKernelGGL(gram_combine_kernel, dim3(unsigned(nt)), blk, 0, st, part, nt, sk, D, gs,
+                           G);
+      }
       break;
-    case kFP16:
-      hipLaunchKernelGGL(gram_packed_kernel<kFP16>, grid, blk, 0, st, hi, lo, g.n_slabs, g.ncb, D,
-                         n_tiles, nI, nJ, gs, G);
-      break;
+    }
     case kBF16HiLo:
       hipLaunchKernelGGL(gram_packed_kernel<kBF16HiLo>, grid, blk, 0, st, hi, lo, g.n_slabs,
                          g.ncb, D, n_tiles, nI, nJ, gs, G);
