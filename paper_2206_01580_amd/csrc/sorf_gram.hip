@@ -216,7 +216,8 @@ __device__ __forceinline__ void wait_vm() {
 // Wait until at most `ahead` stages of PW copies each are still in flight.
 template <int PW>
 __device__ __forceinline__ void wait_stage(int64_t ahead) {
-  if (ahead >= 2) wait_vm<2 * PW>();
+  if (ahead >= 3) wait_vm<3 * PW>();
+  else if (ahead == 2) wait_vm<2 * PW>();
   else if (ahead == 1) wait_vm<PW>();
   else wait_vm<0>();
 }
@@ -359,14 +360,21 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
 
 // ------------------------------------------ 16-bit single-product modes
 // One workgroup (4 waves, 2 x 2) per 256 x 256 square tile of the lower
-// triangle and one slice of the rows; each wave owns 128 x 128 (4 x 4
-// blocks of 32 x 32), which halves the LDS bytes per product against the
-// 128 x 64 waves of the hi+lo kernel. The single accumulator is kept for
-// the whole slice: its drift is orders of magnitude below the rounding of
-// the 16-bit operands. With more than one slice, each slice writes its
-// partial tile and gram_combine_kernel adds the partials to G in a fixed
-// order, so results stay deterministic.
-constexpr int TX = 256;   // square tile of the single-product kernel
+// triangle; each wave owns 128 x 128 (4 x 4 blocks of 32 x 32), which halves
+// the LDS bytes per product against the 128 x 64 waves of the hi+lo kernel.
+// The single accumulator is kept for the whole row range: its drift is
+// orders of magnitude below the rounding of the 16-bit operands.
+//
+// Scheduling: with one 128 KB workgroup per CU, the tiles run in rounds of
+// kX1Slots. The first n_whole tiles (whole rounds) are computed over all rows
+// and added to G directly; each remaining tail tile is split into n_split
+// slices of the rows so that the last round is filled with short items.
+// Slices write partial tiles and gram_combine_kernel adds them to G in a
+// fixed order, so results stay deterministic. Every XCD receives a
+// contiguous run of whole tiles (neighbouring tiles share operand blocks in
+// its L2) followed by a contiguous run of slices.
+constexpr int TX = 256;        // square tile of the single-product kernel
+constexpr int kX1Slots = 256;  // concurrent workgroups: one per CU of the chip
 
 __host__ __device__ inline int64_t x1_tiles(int64_t D) {
   const int64_t n = (D + TX - 1) / TX;
@@ -381,24 +389,43 @@ __device__ __forceinline__ void x1_tile_of(int64_t t, int64_t& I, int64_t& J) {
   J = t - i * (i + 1) / 2;
 }
 
+struct X1Plan {
+  int64_t n_tiles;   // tiles of the lower triangle
+  int64_t n_whole;   // tiles computed over all rows
+  int32_t n_split;   // row slices per tail tile (1: no tail)
+};
+
+// Items of XCD x: its whole tiles, then its slices (both contiguous runs).
+__host__ __device__ inline void x1_xcd_items(const X1Plan& p, int x, int64_t& w0, int64_t& nw,
+                                             int64_t& q0, int64_t& nq) {
+  const int64_t n_pieces = (p.n_tiles - p.n_whole) * p.n_split;
+  w0 = p.n_whole * x / 8;
+  nw = p.n_whole * (x + 1) / 8 - w0;
+  q0 = n_pieces * x / 8;
+  nq = n_pieces * (x + 1) / 8 - q0;
+}
+
 template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t n_slabs, int32_t ncb, int32_t D,
-                    int64_t n_tiles, int32_t n_split, float gscale, float* __restrict__ G,
-                    float* __restrict__ part) {
+                    X1Plan plan, float gscale, float* __restrict__ G, float* __restrict__ part) {
   constexpr int AF = 2 * (TX / 32);   // A fragments per stage (2 slabs)
   constexpr int NF = 2 * AF;          // A and B
   constexpr int FW = NF / 4;          // copies per wave per stage
   constexpr int NS = 4;
   __shared__ u16x8 ring[NS][NF][64];
 
-  // items are (split, tile), split-major; each XCD gets a contiguous run
-  const int64_t n_items = n_tiles * n_split;
-  const int64_t per = (n_items + 7) / 8;
-  const int64_t item = int64_t(blockIdx.x % 8) * per + int64_t(blockIdx.x / 8);
-  if (item >= n_items) return;
-  const int64_t t = item % n_tiles;
-  const int sp = int(item / n_tiles);
+  int64_t w0, nw, q0, nq;
+  x1_xcd_items(plan, int(blockIdx.x % 8), w0, nw, q0, nq);
+  const int64_t k = blockIdx.x / 8;
+  if (k >= nw + nq) return;
+  const int64_t n_tail = plan.n_tiles - plan.n_whole;
+  const bool whole = k < nw;
+  // slices are split-major: concurrent slices of one XCD share their rows
+  const int64_t piece = whole ? 0 : q0 + (k - nw);
+  const int64_t t = whole ? w0 + k : plan.n_whole + piece % n_tail;
+  const int sp = whole ? 0 : int(piece / n_tail);
+  const int n_split = whole ? 1 : plan.n_split;
   int64_t I, J;
   x1_tile_of(t, I, J);
   const int tid = threadIdx.x;
@@ -435,35 +462,67 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t n_slabs, int32_t ncb, 
 #pragma unroll
       for (int r = 0; r < 16; ++r) P[a][b][r] = 0.0f;
 
+  // Software pipeline over half-stages: the fragments of one half-stage are
+  // read from LDS while the MFMAs of the previous half-stage run. All NS
+  // slots are filled up front; after the barrier that publishes stage st + 1
+  // every wave has read all of stage st, so its slot takes stage st + NS.
+  u16x8 a0[4], b0[4], a1[4], b1[4];
+  auto read_half = [&](int slot, int kk, u16x8 (&af)[4], u16x8 (&bf)[4]) {
 #pragma unroll
-  for (int j = 0; j < NS - 1; ++j)
+    for (int q = 0; q < 4; ++q) {
+      af[q] = ring[slot][kk * (TX / 32) + wy * 4 + q][lane];
+      bf[q] = ring[slot][AF + kk * (TX / 32) + wx * 4 + q][lane];
+    }
+  };
+  auto mma_half = [&](const u16x8 (&af)[4], const u16x8 (&bf)[4]) {
+#pragma unroll
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 4; ++b) P[a][b] = mma16<MODE>(af[a], bf[b], P[a][b]);
+  };
+  // 8 LDS reads interleaved with the first 8 of 16 MFMAs
+  auto interleave = [] {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+  };
+
+#pragma unroll
+  for (int j = 0; j < NS; ++j)
     if (j < n_st) issue(j, j);
-  int slot = 0;
-  for (int64_t st = 0; st < n_st; ++st) {
-    const int64_t left = n_st - 1 - st;
-    wait_stage<FW>(left < NS - 2 ? left : NS - 2);
+  if (n_st > 0) {
+    wait_stage<FW>(n_st - 1 < NS - 1 ? n_st - 1 : NS - 1);
     stage_barrier();
-    if (st + NS - 1 < n_st) issue(st + NS - 1, slot == 0 ? NS - 1 : slot - 1);
-    u16x8 af[2][4], bf[2][4];
-#pragma unroll
-    for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        af[kk][q] = ring[slot][kk * (TX / 32) + wy * 4 + q][lane];
-        bf[kk][q] = ring[slot][AF + kk * (TX / 32) + wx * 4 + q][lane];
-      }
-    __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-    for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-      for (int a = 0; a < 4; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) P[a][b] = mma16<MODE>(af[kk][a], bf[kk][b], P[a][b]);
-    slot = slot + 1 == NS ? 0 : slot + 1;
+    read_half(0, 0, a0, b0);
+  }
+  int slot = 0;
+  for (int64_t st = 0; st + 1 < n_st; ++st) {
+    const int nslot = slot + 1 == NS ? 0 : slot + 1;
+    read_half(slot, 1, a1, b1);
+    mma_half(a0, b0);
+    interleave();
+    const int64_t ahead = n_st - 2 - st;
+    wait_stage<FW>(ahead < NS - 2 ? ahead : NS - 2);
+    // this wave's reads of stage st have landed before its slot is reused
+    asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+    stage_barrier();
+    if (st + NS < n_st) issue(st + NS, slot);
+    read_half(nslot, 0, a0, b0);
+    mma_half(a1, b1);
+    interleave();
+    slot = nslot;
+  }
+  if (n_st > 0) {
+    read_half(slot, 1, a1, b1);
+    mma_half(a0, b0);
+    mma_half(a1, b1);
   }
 
   if (!active) return;
-  if (n_split == 1) {
+  if (whole) {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -476,7 +535,7 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t n_slabs, int32_t ncb, 
         }
     return;
   }
-  float* out = part + (int64_t(sp) * n_tiles + t) * TX * TX;
+  float* out = part + (int64_t(sp) * n_tail + (t - plan.n_whole)) * TX * TX;
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -489,40 +548,70 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t n_slabs, int32_t ncb, 
       }
 }
 
-// G += sum over the slices of the partial tiles, slice 0 first. Partial
-// entries of waves above the diagonal are never written and never read.
+// G += sum over the slices of a tail tile's partials, slice 0 first. One
+// workgroup per 4 rows of a tile, 4 columns per thread. Partial entries of
+// waves above the diagonal are never written; they are read but discarded.
 __global__ __launch_bounds__(256) void gram_combine_kernel(const float* __restrict__ part,
-                                                          int64_t n_tiles, int32_t n_split,
-                                                          int32_t D, float gscale,
+                                                          X1Plan plan, int32_t D, float gscale,
                                                           float* __restrict__ G) {
-  const int64_t t = blockIdx.x;
+  const int64_t n_tail = plan.n_tiles - plan.n_whole;
+  const int64_t tt = blockIdx.x;
   int64_t I, J;
-  x1_tile_of(t, I, J);
-  for (int e = threadIdx.x; e < TX * TX; e += 256) {
-    const int i = e / TX, j = e % TX;
-    const int64_t gi = I * TX + i, gj = J * TX + j;
-    if (gi >= D || gj >= D || gi < gj) continue;
-    float acc = 0.0f;
-    for (int sp = 0; sp < n_split; ++sp) acc += part[(int64_t(sp) * n_tiles + t) * TX * TX + e];
-    G[gi * D + gj] += acc * gscale;
+  x1_tile_of(plan.n_whole + tt, I, J);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int j = (threadIdx.x & 63) * 4;
+  const int64_t gi = I * TX + i;
+  if (gi >= D) return;
+  float4 acc = make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  for (int sp = 0; sp < plan.n_split; ++sp) {
+    const float4 v = *reinterpret_cast<const float4*>(
+        part + (int64_t(sp) * n_tail + tt) * TX * TX + int64_t(i) * TX + j);
+    acc.x += v.x;
+    acc.y += v.y;
+    acc.z += v.z;
+    acc.w += v.w;
+  }
+  const float a4[4] = {acc.x, acc.y, acc.z, acc.w};
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t gj = J * TX + j + c;
+    if (gj < D && gi >= gj) G[gi * D + gj] += a4[c] * gscale;
   }
 }
 
-// Slices of rows for the single-product kernel: the count (1, 2 or 4) that
-// minimises whole rounds of 256 workgroups times the work per item.
-static int x1_splits(int64_t D, int64_t n_stages) {
-  const int64_t nt = x1_tiles(D);
-  int best = 1;
-  double best_cost = 1e300;
-  for (int sk = 1; sk <= 4; sk *= 2) {
-    if (sk > 1 && n_stages < 8 * sk) break;
-    const double cost = double((nt * sk + 255) / 256) / sk;
-    if (cost < best_cost - 1e-9) {
-      best_cost = cost;
-      best = sk;
+// Tail split of the single-product kernel: keep whole rounds of kX1Slots
+// tiles (all of them, or all but one round) and split the remaining tiles
+// into the slice count that minimises the rounds of work, in units of one
+// whole tile. Slices keep at least 8 stages of rows, and at most 1024
+// partial tiles (256 MB) are written.
+static X1Plan x1_plan(int64_t D, int64_t n_stages) {
+  X1Plan best{x1_tiles(D), x1_tiles(D), 1};
+  const int64_t nt = best.n_tiles;
+  const int64_t q = nt / kX1Slots;
+  if (nt % kX1Slots == 0) return best;
+  double best_cost = double(q + 1);
+  for (int64_t k = q; k >= 0 && k >= q - 1; --k) {
+    const int64_t tail = nt - k * kX1Slots;
+    for (int st = 2; st <= 16; ++st) {
+      if (n_stages < 8 * int64_t(st) || tail * st > 1024) break;
+      const double cost = double(k) + double((tail * st + kX1Slots - 1) / kX1Slots) / st;
+      if (cost < best_cost - 1e-9) {
+        best_cost = cost;
+        best = X1Plan{nt, nt - tail, st};
+      }
     }
   }
   return best;
+}
+
+static int64_t x1_grid(const X1Plan& p) {
+  int64_t m = 0;
+  for (int x = 0; x < 8; ++x) {
+    int64_t w0, nw, q0, nq;
+    x1_xcd_items(p, x, w0, nw, q0, nq);
+    m = std::max(m, nw + nq);
+  }
+  return 8 * m;
 }
 
 // ------------------------------------------------ FP32 mode, D % 4 == 0
@@ -888,8 +977,9 @@ GramLayout gram_layout(int64_t M, int32_t D) {
 
 size_t x1_partial_bytes(int64_t n_rows, int32_t D) {
   const GramLayout g = gram_layout(n_rows, D);
-  const int sk = x1_splits(D, g.n_slabs / 2);
-  return sk > 1 ? al256(size_t(sk) * size_t(x1_tiles(D)) * TX * TX * sizeof(float)) : 0;
+  const X1Plan p = x1_plan(D, g.n_slabs / 2);
+  return al256(size_t(p.n_split > 1 ? p.n_split : 0) * size_t(p.n_tiles - p.n_whole) * TX * TX *
+               sizeof(float));
 }
 
 size_t sorf_gram_ws_bytes(int64_t n_rows, int32_t D, int mode) {
@@ -963,20 +1053,19 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
       break;
     case kBF16:
     case kFP16: {
-      const int sk = x1_splits(D, g.n_slabs / 2);
-      const int64_t nt = x1_tiles(D);
+      const X1Plan plan = x1_plan(D, g.n_slabs / 2);
       float* part = reinterpret_cast<float*>(w + g.zpart_bytes + kZeroBytes + g.part_bytes);
-      const dim3 xg{unsigned(((nt * sk + 7) / 8) * 8)};
+      const dim3 xg{unsigned(x1_grid(plan))};
       if (mode == kBF16)
-        hipLaunchKernelGGL(gram_x1_kernel<kBF16>, xg, blk, 0, st, hi, g.n_slabs, g.ncb, D, nt, sk,
+        hipLaunchKernelGGL(gram_x1_kernel<kBF16>, xg, blk, 0, st, hi, g.n_slabs, g.ncb, D, plan,
                            gs, G, part);
       else
-        hipLaunchKernelGGL(gram_x1_kernel<kFP16>, xg, blk, 0, st, hi, g.n_slabs, g.ncb, D, nt, sk,
+        hipLaunchKernelGGL(gram_x1_kernel<kFP16>, xg, blk, 0, st, hi, g.n_slabs, g.ncb, D, plan,
                            gs, G, part);
-      if (sk > 1) {
+      if (plan.n_split > 1) {
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        hipLaunchKernelGGL(gram_combine_kernel, dim3(unsigned(nt)), blk, 0, st, part, nt, sk, D, gs,
-                           G);
+        const dim3 cg{unsigned(plan.n_tiles - plan.n_whole), unsigned(TX / 4)};
+        hipLaunchKernelGGL(gram_combine_kernel, cg, blk, 0, st, part, plan, D, gs, G);
       }
       break;
     }

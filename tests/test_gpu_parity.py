@@ -308,13 +308,32 @@ def test_gram_fp64(MD):
     assert np.abs(Zty.cpu().numpy() - ro).max() <= 1e-13 * np.abs(ro).max()
 
 
-def test_gram_deterministic():
+@pytest.mark.parametrize("mode", ["bf16", "fp16"])
+def test_gram_single_product_whole_and_sliced_tiles(mode):
+    # D = 5900: 300 tiles of 256 x 256, so one whole round of 256 tiles plus
+    # 44 tail tiles whose rows are split into slices and combined
+    M, D = 1100, 5900
+    rng = np.random.default_rng(5)
+    Z = (rng.standard_normal((M, D)) * 0.05).astype(np.float32)
+    k = S().fp16_scale_exp(float(np.abs(Z).max())) if mode == "fp16" else 0
+    G = torch.zeros(D, D, device="cuda")
+    S().gram_accumulate(torch.from_numpy(Z).cuda(), G, precision=mode, scale_exp=k)
+    torch.cuda.synchronize()
+    Gg = G.cpu().numpy().astype(np.float64)
+    assert np.all(Gg[np.triu_indices(D, 1)] == 0.0)
+    Ge = O.gram_emulated(Z, mode, k)
+    low = np.tril_indices(D)
+    assert np.linalg.norm(Gg[low] - Ge[low]) <= 1e-6 * np.linalg.norm(Ge[low])
+
+
+@pytest.mark.parametrize("mode", ["bf16_hilo", "bf16"])
+def test_gram_deterministic(mode):
     rng = np.random.default_rng(1)
     Z = torch.from_numpy((rng.standard_normal((700, 384)) * 0.1).astype(np.float32)).cuda()
     outs = []
     for _ in range(2):
         G = torch.zeros(384, 384, device="cuda")
-        S().gram_accumulate(Z, G, precision="bf16_hilo")
+        S().gram_accumulate(Z, G, precision=mode)
         outs.append(G)
     torch.cuda.synchronize()
     assert torch.equal(outs[0], outs[1])
