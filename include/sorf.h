@@ -156,7 +156,8 @@ size_t sorf_solve_workspace_bytes(int32_t D);
  *   refinement alpha += A^{-1} (Zty - A alpha) with the residual in FP64.
  *   alpha: [D] FP64 out. info: device int32, written 0 on success or k > 0 when the
  *   leading minor of order k is not positive definite (LAPACK convention; alpha is then
- *   undefined). workspace: device memory of at least sorf_solve_workspace_bytes(D),
+ *   undefined), or -1 if a triangular sweep gave up waiting for a block (an internal
+ *   fault, reported instead of hanging; alpha is then undefined). workspace: device memory of at least sorf_solve_workspace_bytes(D),
  *   256-byte aligned. 0 <= n_refine <= 16, lambda >= 0 and finite. */
 sorf_status sorf_solve(int32_t D, const float* G, const float* Zty, double lambda,
                        int32_t n_refine, double* alpha, int32_t* info, void* workspace,

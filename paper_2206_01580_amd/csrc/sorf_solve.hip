@@ -8,14 +8,13 @@
 // of the iterative refinement are all FP64).
 //
 // Blocked right-looking Cholesky with panel width NB = 128:
-//   1. factor the NB x NB diagonal block in LDS (right-looking, 512 threads)
-//      and invert it in place (column sweep from the right),
+//   1. factor the NB x NB diagonal block in LDS and invert it (one workgroup;
+//      the 64 x 64 halves are factored and inverted by one wave in registers),
 //   2. panel below: L21 = A21 L11^{-T} = A21 (L11^{-1})^T as an FP64 MFMA GEMM,
 //   3. trailing update A22 -= L21 L21^T on the lower triangle, 128 x 128
-//      tiles of FP64 MFMA.
-// Triangular solves use the inverted diagonal blocks: one launch per block
-// row updates the remaining right-hand side with coalesced reads of L, and
-// the workgroup that finishes the next block's rows also solves that block.
+//      tiles of FP64 MFMA, the tile of the next diagonal block first.
+// Triangular solves use the inverted diagonal blocks: one launch per sweep,
+// one workgroup per block row, ordered by per-block ready flags.
 #include <cmath>
 #include <mutex>
 
@@ -48,6 +47,7 @@ struct SolveWs {
   double* y;     // [D]
   double* dx;    // [D]
   double* part;  // [nt][nt][64] partial sums of the symmetric product
+  int32_t* flags;  // [2][nblk] block-ready flags of the forward and backward sweeps
 };
 
 static size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
@@ -63,6 +63,9 @@ static SolveWs carve(void* ws, int32_t D) {
   w.y = reinterpret_cast<double*>(p);      p += align256(sizeof(double) * D);
   w.dx = reinterpret_cast<double*>(p);     p += align256(sizeof(double) * D);
   w.part = reinterpret_cast<double*>(p);
+  const size_t nt = (size_t(D) + 63) / 64;
+  p += align256(sizeof(double) * nt * nt * 64);
+  w.flags = reinterpret_cast<int32_t*>(p);
   return w;
 }
 
@@ -70,10 +73,12 @@ static SolveWs carve(void* ws, int32_t D) {
 template <typename TG>
 __global__ __launch_bounds__(256) void promote_kernel(const TG* __restrict__ G, int32_t D,
                                                      double lambda, double* __restrict__ A,
-                                                     int32_t* __restrict__ info) {
+                                                     int32_t* __restrict__ info,
+                                                     int32_t* __restrict__ flags) {
   const int64_t i = blockIdx.y;
   const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i == 0 && j == 0) *info = 0;
+  if (i == 0 && j < 2 * ((int64_t(D) + NB - 1) / NB)) flags[j] = 0;
   if (j <= i && j < D) A[i * D + j] = double(G[i * D + j]) + (i == j ? lambda : 0.0);
 }
 
@@ -634,48 +639,52 @@ __global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32
       }
 }
 
-// out[i] = sum_p MT[p][i] v[p] for a 128 x 128 block MT stored row-major and
-// zero outside the block's n x n part; v (LDS) must be zero past n.
-// Thread (i, h) of 256 issues its 64 coalesced loads (lanes run over i) at
-// once and sums p in [64 h, 64 h + 64); the halves are added in a fixed order.
-// No cross-lane reductions. `part` is 128 doubles of LDS scratch.
-static __device__ __forceinline__ void block_mvT_load(const double* __restrict__ MT, double (&a)[64],
-                                                      int tid) {
-  const int i = tid & 127, h = tid >> 7;
-#pragma unroll
-  for (int t = 0; t < 64; ++t) a[t] = MT[(64 * h + t) * NB + i];
-}
-static __device__ __forceinline__ void block_mvT_finish(const double (&a)[64], const double* v,
-                                                        int n, double* __restrict__ out_global,
-                                                        double* part, int tid) {
-  const int i = tid & 127, h = tid >> 7;
-  double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-#pragma unroll
-  for (int t = 0; t < 64; t += 4) {
-    s0 += a[t] * v[64 * h + t];
-    s1 += a[t + 1] * v[64 * h + t + 1];
-    s2 += a[t + 2] * v[64 * h + t + 2];
-    s3 += a[t + 3] * v[64 * h + t + 3];
+// ---------------------------------------------------------------------------
+// Triangular sweeps: one launch per sweep, one workgroup (512 threads) per
+// block row, in dependency order: a workgroup only waits for blocks owned by
+// workgroups with a lower index, which are dispatched before it, so the
+// waits always end. A finished block is published by a flag (agent-scope
+// release after the block's values are written); a consumer's first thread
+// polls it and every thread then issues an agent-scope fence before reading.
+// Loads of L that do not depend on the awaited block are issued before the
+// wait. A wait that exceeds
+// kSweepWaitTicks of the 100 MHz real-time counter sets *info = -1 (when it
+// is still 0) and stops waiting in that workgroup, so every wave exits.
+// The forward sweep clears the backward flags and vice versa; the promote
+// kernel clears both at the start of a solve.
+constexpr uint64_t kSweepWaitTicks = uint64_t(1) << 28;   // about 2.7 s
+
+static __device__ __forceinline__ void sweep_wait(const int32_t* flag, int32_t* info,
+                                                  bool& failed) {
+  if (threadIdx.x == 0 && !failed) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
+      if (__builtin_amdgcn_s_memrealtime() - t0 > kSweepWaitTicks) {
+        int32_t expect = 0;
+        __hip_atomic_compare_exchange_strong(info, &expect, -1, __ATOMIC_RELAXED,
+                                             __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        failed = true;
+        break;
+      }
+      __builtin_amdgcn_s_sleep(1);
+    }
   }
-  const double s = (s0 + s1) + (s2 + s3);
-  if (h == 1) part[i] = s;
   __syncthreads();
-  if (h == 0 && i < n) out_global[i] = s + part[i];
-}
-static __device__ __forceinline__ void block_mvT(const double* __restrict__ MT, const double* v,
-                                                 int n, double* __restrict__ out_global,
-                                                 double* part, int tid) {
-  double a[64];
-  block_mvT_load(MT, a, tid);
-  block_mvT_finish(a, v, n, out_global, part, tid);
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the block's values are read after this
 }
 
-// Reduce-scatter of 32 per-lane partial sums over the 64 lanes of a wave:
-// afterwards lanes 2 r and 2 r + 1 both hold the full sum of row r.
-static __device__ __forceinline__ double reduce_scatter32(double (&p)[32], int lane) {
+static __device__ __forceinline__ void sweep_publish(int32_t* flag) {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+  __syncthreads();
+  if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Sums 16 per-lane partials over the 64 lanes of a wave: afterwards every
+// lane with (lane >> 2) & 15 == r holds the full sum of partial r.
+static __device__ __forceinline__ double wave_sum16(double (&p)[16], int lane) {
 #pragma unroll
-  for (int lvl = 0; lvl < 5; ++lvl) {
-    const int mask = 32 >> lvl, half = 16 >> lvl;
+  for (int lvl = 0; lvl < 4; ++lvl) {
+    const int mask = 32 >> lvl, half = 8 >> lvl;
     const bool upper = (lane & mask) != 0;
 #pragma unroll
     for (int r = 0; r < half; ++r) {
@@ -684,112 +693,136 @@ static __device__ __forceinline__ double reduce_scatter32(double (&p)[32], int l
       p[r] = keep + __shfl_xor(send, mask);
     }
   }
-  return p[0] + __shfl_xor(p[0], 1);
+  const double t = p[0] + __shfl_xor(p[0], 2);
+  return t + __shfl_xor(t, 1);
 }
 
-// y_0 = L_00^{-1} b_0 (first block of the forward sweep)
-__global__ __launch_bounds__(256) void trsv_fwd_first_kernel(const double* __restrict__ LinvT,
-                                                            int32_t D, const double* __restrict__ b,
-                                                            double* __restrict__ y) {
-  __shared__ double v[NB], part[NB];
-  const int n = D < NB ? D : NB;
-  if (threadIdx.x < NB) v[threadIdx.x] = threadIdx.x < n ? b[min(int(threadIdx.x), n - 1)] : 0.0;
-  __syncthreads();
-  block_mvT(LinvT, v, n, y, part, threadIdx.x);
-}
-
-// Forward sweep, block row k (y_k already in y): rows i >= k + n get
-// b_i -= L_ik y_k. Each workgroup owns 128 rows (16 per wave, coalesced
-// 512-byte row reads). Workgroup 0 owns exactly the next block, so after its
-// update it solves that block: y_{k+n} = L^{-1} b_{k+n}.
-__global__ __launch_bounds__(256) void trsv_fwd_kernel(const double* __restrict__ A,
-                                                      const double* __restrict__ LinvT, int32_t D,
-                                                      int32_t k, double* __restrict__ b,
-                                                      double* __restrict__ y) {
-  __shared__ double vk[NB], part[NB];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wv = tid >> 6;
-  const int64_t r0 = int64_t(k) + NB + int64_t(blockIdx.x) * 128;
-  const bool solver = blockIdx.x == 0;   // owns the next block and solves it
-  double inv[64];
-  if (solver) block_mvT_load(LinvT + (r0 / NB) * NB * NB, inv, tid);   // does not depend on y
-  const double y0 = y[k + lane];        // this launch only runs for full blocks
-  const double y1 = y[k + 64 + lane];
-  double pr[32];
+// out[i] = sum_c M[c][i] v[c] for a 128 x 128 block stored row-major (c rows);
+// thread (i, q) holds M[32 q + m][i], m < 32, and the four quarters are added
+// in a fixed order. v and red are LDS; red holds 4 x 128 doubles.
+static __device__ __forceinline__ void block_mvT_load(const double* __restrict__ M, double (&a)[32],
+                                                      int tid) {
+  const int i = tid & 127, q = tid >> 7;
 #pragma unroll
-  for (int r = 0; r < 32; ++r) {
-    const int64_t i = r0 + wv * 32 + r;
-    const double* row = A + (i < D ? i : D - 1) * D + k;
-    const double v = row[lane] * y0 + row[lane + 64] * y1;
-    pr[r] = i < D ? v : 0.0;
-  }
-  const double tot = reduce_scatter32(pr, lane);
-  const int li = wv * 32 + (lane >> 1);
-  const int64_t i = r0 + li;
-  const double bi = b[i < D ? i : D - 1];
-  const double nb = bi - tot;
-  if (!solver) {
-    if ((lane & 1) == 0 && i < D) b[i] = nb;
-    return;
-  }
-  // the next block's right-hand side never leaves the workgroup
-  if ((lane & 1) == 0) vk[li] = i < D ? nb : 0.0;
-  __syncthreads();
-  const int nn = (D - r0) < NB ? int(D - r0) : NB;
-  block_mvT_finish(inv, vk, nn, y + r0, part, tid);
+  for (int m = 0; m < 32; ++m) a[m] = M[(32 * q + m) * NB + i];
 }
-
-// x_last = L_last^{-T} c_last (first block of the backward sweep)
-__global__ __launch_bounds__(256) void trsv_bwd_first_kernel(const double* __restrict__ Linv,
-                                                            int32_t D, const double* __restrict__ c,
-                                                            double* __restrict__ x) {
-  __shared__ double v[NB], part[NB];
-  const int k = ((D - 1) / NB) * NB;
-  const int n = D - k;
-  if (threadIdx.x < NB) v[threadIdx.x] = threadIdx.x < n ? c[k + min(int(threadIdx.x), n - 1)] : 0.0;
-  __syncthreads();
-  block_mvT(Linv + (k / NB) * NB * NB, v, n, x + k, part, threadIdx.x);
-}
-
-// Backward sweep, block row k (x_k already in x): rows i < k get
-// c_i -= sum_p L[k + p][i] x_k[p]. A workgroup owns 128 rows; thread (r, h)
-// sums p in [64 h, 64 h + 64) with all 64 loads in flight (coalesced over
-// i), and the halves are combined in a fixed order. The last workgroup owns
-// the next block [k - NB, k) and solves it: x = L^{-T} c on that block, with
-// the inverse block loaded before the update.
-__global__ __launch_bounds__(256) void trsv_bwd_kernel(const double* __restrict__ A,
-                                                      const double* __restrict__ Linv, int32_t D,
-                                                      int32_t k, double* __restrict__ c,
-                                                      double* __restrict__ x) {
-  __shared__ double xk[NB], vk[NB], part[NB];
-  const int tid = threadIdx.x;
-  const int r = tid & 127, h = tid >> 7;
-  const int n = (D - k) < NB ? (D - k) : NB;
-  const bool solver = int64_t(blockIdx.x) + 1 == gridDim.x;
-  const int64_t i = int64_t(blockIdx.x) * 128 + r;     // i < k: k is a multiple of NB
-  double inv[64];
-  if (solver) block_mvT_load(Linv + int64_t(k / NB - 1) * NB * NB, inv, tid);
-  if (tid < NB) xk[tid] = tid < n ? x[k + min(tid, n - 1)] : 0.0;
-  __syncthreads();
-  double a[64];
-#pragma unroll
-  for (int t = 0; t < 64; ++t) a[t] = A[int64_t(k + min(64 * h + t, n - 1)) * D + i];
+static __device__ __forceinline__ void block_mvT_finish(const double (&a)[32], const double* v,
+                                                        int n, double* __restrict__ out,
+                                                        double (*red)[NB], int tid) {
+  const int i = tid & 127, q = tid >> 7;
   double s0 = 0.0, s1 = 0.0;
 #pragma unroll
-  for (int t = 0; t < 64; t += 2) {
-    s0 += a[t] * xk[64 * h + t];
-    s1 += a[t + 1] * xk[64 * h + t + 1];
+  for (int m = 0; m < 32; m += 2) {
+    s0 = __builtin_fma(a[m], v[32 * q + m], s0);
+    s1 = __builtin_fma(a[m + 1], v[32 * q + m + 1], s1);
   }
-  if (h == 1) part[r] = s0 + s1;
+  red[q][i] = s0 + s1;
   __syncthreads();
-  if (h == 0) {
-    const double nc = c[i] - ((s0 + s1) + part[r]);
-    if (solver) vk[r] = nc; else c[i] = nc;
+  if (q == 0 && i < n) out[i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+}
+
+// Forward sweep L y = b, left-looking by block rows:
+//   y_k = L_kk^{-1} (b_k - sum_{j<k} L_kj y_j).
+// Workgroup k: wave w owns rows 16 w .. 16 w + 15 of the block; lane l holds
+// columns l and l + 64 of each block L_kj (coalesced 512-byte row reads) and
+// keeps per-lane partial sums over all j, reduced across lanes once.
+__global__ __launch_bounds__(512) void sweep_fwd_kernel(const double* __restrict__ A,
+                                                       const double* __restrict__ LinvT, int32_t D,
+                                                       const double* __restrict__ b,
+                                                       double* __restrict__ y,
+                                                       int32_t* __restrict__ flags,
+                                                       int32_t* __restrict__ info) {
+  __shared__ double rv[NB];
+  __shared__ double red[4][NB];
+  bool failed = false;   // used by thread 0 only
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int nblk = (D + NB - 1) / NB;
+  const int k = blockIdx.x;
+  const int64_t r0 = int64_t(k) * NB;
+  const int n = (D - r0) < NB ? int(D - r0) : NB;
+  if (tid == 0) flags[nblk + k] = 0;   // backward flag of this block, for the sweep that follows
+  double inv[32];
+  block_mvT_load(LinvT + int64_t(k) * NB * NB, inv, tid);
+  double acc[16][2];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) acc[r][0] = acc[r][1] = 0.0;
+  for (int j = 0; j < k; ++j) {
+    double lb[16][2];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      const int64_t row = r0 + 16 * wv + r;
+      const double* p = A + (row < D ? row : D - 1) * D + int64_t(j) * NB;
+      lb[r][0] = p[lane];
+      lb[r][1] = p[lane + 64];
+    }
+    sweep_wait(flags + j, info, failed);
+    const double y0 = y[int64_t(j) * NB + lane], y1 = y[int64_t(j) * NB + 64 + lane];
+#pragma unroll
+    for (int r = 0; r < 16; ++r) {
+      acc[r][0] = __builtin_fma(lb[r][0], y0, acc[r][0]);
+      acc[r][1] = __builtin_fma(lb[r][1], y1, acc[r][1]);
+    }
   }
-  if (!solver) return;
+  double ps[16];
+#pragma unroll
+  for (int r = 0; r < 16; ++r) ps[r] = acc[r][0] + acc[r][1];
+  const double s = wave_sum16(ps, lane);
+  if ((lane & 3) == 0) {
+    const int i = 16 * wv + ((lane >> 2) & 15);
+    rv[i] = i < n ? b[r0 + i] - s : 0.0;
+  }
   __syncthreads();
-  block_mvT_finish(inv, vk, NB, x + (k - NB), part, tid);
+  block_mvT_finish(inv, rv, n, y + r0, red, tid);
+  sweep_publish(flags + k);
+}
+
+// Backward sweep L^T x = y, by block rows of L^T from the last:
+//   x_k = L_kk^{-T} (y_k - sum_{j>k} L_jk^T x_j).
+// Workgroup g owns block k = nblk - 1 - g. Thread (c, q) holds column c of
+// the block and rows 32 q .. 32 q + 31 of each block L_jk (coalesced over c),
+// so the products need no cross-lane sums; the quarters are added once.
+__global__ __launch_bounds__(512) void sweep_bwd_kernel(const double* __restrict__ A,
+                                                       const double* __restrict__ Linv, int32_t D,
+                                                       const double* __restrict__ y,
+                                                       double* __restrict__ x,
+                                                       int32_t* __restrict__ flags,
+                                                       int32_t* __restrict__ info) {
+  __shared__ double rv[NB];
+  __shared__ double red[4][NB];
+  bool failed = false;   // used by thread 0 only
+  const int tid = threadIdx.x;
+  const int c = tid & 127, q = tid >> 7;
+  const int nblk = (D + NB - 1) / NB;
+  const int k = nblk - 1 - int(blockIdx.x);
+  const int64_t c0 = int64_t(k) * NB;
+  const int n = (D - c0) < NB ? int(D - c0) : NB;
+  if (tid == 0) flags[k] = 0;   // forward flag of this block, for the next solve
+  double inv[32];
+  block_mvT_load(Linv + int64_t(k) * NB * NB, inv, tid);
+  const int64_t col = c0 + (c < n ? c : n - 1);
+  double acc = 0.0;
+  for (int j = nblk - 1; j > k; --j) {
+    const int64_t rj = int64_t(j) * NB + 32 * q;
+    double lb[32];
+#pragma unroll
+    for (int m = 0; m < 32; ++m) {
+      const int64_t row = rj + m;
+      lb[m] = A[(row < D ? row : D - 1) * D + col];
+    }
+    sweep_wait(flags + nblk + j, info, failed);
+#pragma unroll
+    for (int m = 0; m < 32; ++m) {
+      const int64_t row = rj + m;
+      const double xv = x[row < D ? row : D - 1];
+      acc = __builtin_fma(row < D ? lb[m] : 0.0, xv, acc);
+    }
+  }
+  red[q][c] = acc;
+  __syncthreads();
+  if (q == 0) rv[c] = c < n ? y[c0 + c] - ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) : 0.0;
+  __syncthreads();
+  block_mvT_finish(inv, rv, n, x + c0, red, tid);
+  sweep_publish(flags + nblk + k);
 }
 
 // Partial sums of (lower-stored symmetric G) x over 64 x 64 tiles:
@@ -861,20 +894,14 @@ __global__ void axpy_kernel(double* __restrict__ x, const double* __restrict__ d
   if (i < n) x[i] += d[i];
 }
 
-static hipError_t solve_triangular(const SolveWs& w, int32_t D, double* rhs, double* tmp,
-                                   double* out, hipStream_t st) {
-  // L tmp = rhs (rhs overwritten), then L^T out = tmp (tmp overwritten)
-  hipLaunchKernelGGL(trsv_fwd_first_kernel, dim3(1), dim3(256), 0, st, w.LinvT, D, rhs, tmp);
-  for (int32_t k = 0; k + NB < D; k += NB) {
-    const int64_t rest = int64_t(D) - k - NB;
-    hipLaunchKernelGGL(trsv_fwd_kernel, dim3(unsigned((rest + 127) / 128)), dim3(256), 0, st,
-                       w.A, w.LinvT, D, k, rhs, tmp);
-  }
-  hipLaunchKernelGGL(trsv_bwd_first_kernel, dim3(1), dim3(256), 0, st, w.Linv, D, tmp, out);
-  const int32_t last = ((D - 1) / NB) * NB;
-  for (int32_t k = last; k > 0; k -= NB)
-    hipLaunchKernelGGL(trsv_bwd_kernel, dim3(unsigned(k / NB)), dim3(256), 0, st, w.A, w.Linv,
-                       D, k, tmp, out);
+static hipError_t solve_triangular(const SolveWs& w, int32_t D, const double* rhs, double* tmp,
+                                   double* out, int32_t* info, hipStream_t st) {
+  // L tmp = rhs, then L^T out = tmp: one launch per sweep, one workgroup per block
+  const unsigned nblk = unsigned((D + NB - 1) / NB);
+  hipLaunchKernelGGL(sweep_fwd_kernel, dim3(nblk), dim3(512), 0, st, w.A, w.LinvT, D, rhs, tmp,
+                     w.flags, info);
+  hipLaunchKernelGGL(sweep_bwd_kernel, dim3(nblk), dim3(512), 0, st, w.A, w.Linv, D, tmp, out,
+                     w.flags, info);
   return hipGetLastError();
 }
 
@@ -911,12 +938,13 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
   const SolveWs w = carve(ws, D);
   const unsigned vg = unsigned((D + 255) / 256);
   hipLaunchKernelGGL(promote_kernel<TG>, dim3(vg, unsigned(D)), dim3(256), 0, st, G, D, lambda,
-                     w.A, info);
+                     w.A, info, w.flags);
   // Right-looking blocked Cholesky with a one-block lookahead: after the
   // panel solve of block k, the trailing tile that becomes the next diagonal
-  // block is updated first; that block is then factored on a second stream
-  // (one workgroup) while the rest of the trailing update runs on the
-  // caller's stream across the other compute units.
+  // block is updated first; that block is then factored (one workgroup) on
+  // the caller's stream while the rest of the trailing update runs on a
+  // second stream across the other compute units. The factorisation is
+  // queued first, so it takes a compute unit before the update fills them.
   hipStream_t side = nullptr;
   hipEvent_t ev_fork = nullptr, ev_join = nullptr;
   hipError_t e = lookahead_resources(&side, &ev_fork, &ev_join);
@@ -932,11 +960,11 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
     hipLaunchKernelGGL(syrk_kernel, dim3(1), dim3(512), 0, st, w.A, D, k, 0);
     if (tiles > 1) {
       if ((e = hipEventRecord(ev_fork, st)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(side, ev_fork, 0)) != hipSuccess) return e;
-      hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, side, w.A, D, k + NB, info,
+      hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, k + NB, info,
                          w.Linv, w.LinvT);
+      if ((e = hipStreamWaitEvent(side, ev_fork, 0)) != hipSuccess) return e;
+      hipLaunchKernelGGL(syrk_kernel, dim3(unsigned(tiles - 1)), dim3(512), 0, side, w.A, D, k, 1);
       if ((e = hipEventRecord(ev_join, side)) != hipSuccess) return e;
-      hipLaunchKernelGGL(syrk_kernel, dim3(unsigned(tiles - 1)), dim3(512), 0, st, w.A, D, k, 1);
       if ((e = hipStreamWaitEvent(st, ev_join, 0)) != hipSuccess) return e;
     } else {
       hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, k + NB, info,
@@ -948,7 +976,7 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(to_double_kernel<TG>, dim3(vg), dim3(256), 0, st, Zty, w.b, D);
-  e = solve_triangular(w, D, w.b, w.y, alpha, st);
+  e = solve_triangular(w, D, w.b, w.y, alpha, info, st);
   if (e != hipSuccess) return e;
   const int64_t nt = (int64_t(D) + 63) / 64;
   for (int32_t it = 0; it < n_refine; ++it) {
@@ -956,7 +984,7 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
                        G, D, alpha, w.part);
     hipLaunchKernelGGL(residual_kernel<TG>, dim3(vg), dim3(256), 0, st, w.part, D, lambda, Zty,
                        alpha, w.b);
-    e = solve_triangular(w, D, w.b, w.y, w.dx, st);
+    e = solve_triangular(w, D, w.b, w.y, w.dx, info, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(axpy_kernel, dim3(vg), dim3(256), 0, st, alpha, w.dx, D);
   }
@@ -971,7 +999,8 @@ size_t sorf_solve_ws_bytes(int32_t D) {
   const size_t nblk = (size_t(D) + NB - 1) / NB;
   const size_t nt = (size_t(D) + 63) / 64;
   return align256(sizeof(double) * size_t(D) * D) + 2 * align256(sizeof(double) * nblk * NB * NB) +
-         3 * align256(sizeof(double) * D) + align256(sizeof(double) * nt * nt * 64);
+         3 * align256(sizeof(double) * D) + align256(sizeof(double) * nt * nt * 64) +
+         align256(sizeof(int32_t) * 2 * nblk);
 }
 
 hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double lambda,
