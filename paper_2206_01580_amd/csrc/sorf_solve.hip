@@ -14,7 +14,7 @@
 //   3. trailing update A22 -= L21 L21^T on the lower triangle, 128 x 128
 //      tiles of FP64 MFMA, the tile of the next diagonal block first.
 // Triangular solves use the inverted diagonal blocks: one launch per sweep,
-// one workgroup per block row, ordered by per-block ready flags.
+// one workgroup per block row, each waiting for the solved values it needs.
 #include <cmath>
 #include <mutex>
 
@@ -39,6 +39,23 @@ static __device__ __forceinline__ f64x4 mfma64(double a, double b, f64x4 c) {
   return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
 }
 
+// Values of the triangular sweeps' outputs are their own ready signals: a
+// slot holds the signalling-NaN pattern kNotReady (never produced by
+// arithmetic) until its value is stored; stores and polls are agent-scope
+// atomics, so they are seen across the XCDs' L2 caches.
+constexpr long long kNotReady = 0x7FF4534457454550ll;
+
+static __device__ __forceinline__ double not_ready() { return __longlong_as_double(kNotReady); }
+static __device__ __forceinline__ bool is_not_ready(double v) {
+  return __double_as_longlong(v) == kNotReady;
+}
+static __device__ __forceinline__ double poll_load(const double* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+static __device__ __forceinline__ void signal_store(double* p, double v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+}
+
 struct SolveWs {
   double* A;     // [D][D], lower triangle used
   double* Linv;  // [nblk][NB][NB] inverses of the diagonal blocks
@@ -47,7 +64,6 @@ struct SolveWs {
   double* y;     // [D]
   double* dx;    // [D]
   double* part;  // [nt][nt][64] partial sums of the symmetric product
-  int32_t* flags;  // [2][nblk] block-ready flags of the forward and backward sweeps
 };
 
 static size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
@@ -63,9 +79,6 @@ static SolveWs carve(void* ws, int32_t D) {
   w.y = reinterpret_cast<double*>(p);      p += align256(sizeof(double) * D);
   w.dx = reinterpret_cast<double*>(p);     p += align256(sizeof(double) * D);
   w.part = reinterpret_cast<double*>(p);
-  const size_t nt = (size_t(D) + 63) / 64;
-  p += align256(sizeof(double) * nt * nt * 64);
-  w.flags = reinterpret_cast<int32_t*>(p);
   return w;
 }
 
@@ -74,11 +87,11 @@ template <typename TG>
 __global__ __launch_bounds__(256) void promote_kernel(const TG* __restrict__ G, int32_t D,
                                                      double lambda, double* __restrict__ A,
                                                      int32_t* __restrict__ info,
-                                                     int32_t* __restrict__ flags) {
+                                                     double* y) {
   const int64_t i = blockIdx.y;
   const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i == 0 && j == 0) *info = 0;
-  if (i == 0 && j < 2 * ((int64_t(D) + NB - 1) / NB)) flags[j] = 0;
+  if (i == 0 && j < D) signal_store(y + j, not_ready());   // output of the first forward sweep
   if (j <= i && j < D) A[i * D + j] = double(G[i * D + j]) + (i == j ? lambda : 0.0);
 }
 
@@ -643,40 +656,49 @@ __global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32
 // Triangular sweeps: one launch per sweep, one workgroup (512 threads) per
 // block row, in dependency order: a workgroup only waits for blocks owned by
 // workgroups with a lower index, which are dispatched before it, so the
-// waits always end. A finished block is published by a flag (agent-scope
-// release after the block's values are written); a consumer's first thread
-// polls it and every thread then issues an agent-scope fence before reading.
-// Loads of L that do not depend on the awaited block are issued before the
-// wait. A wait that exceeds
-// kSweepWaitTicks of the 100 MHz real-time counter sets *info = -1 (when it
-// is still 0) and stops waiting in that workgroup, so every wave exits.
-// The forward sweep clears the backward flags and vice versa; the promote
-// kernel clears both at the start of a solve.
+// waits always end. Every solved value is its own ready signal: the output
+// vectors hold a signalling-NaN pattern (kNotReady, which arithmetic never
+// produces) until the value is stored, and consumers poll the values they
+// need with agent-scope atomic loads, each wave on its own (no workgroup
+// barrier and no separate flag round trip on the dependency chain). Loads of
+// L that do not depend on the awaited block are issued before the wait. A
+// wait that exceeds kSweepWaitTicks of the 100 MHz real-time counter sets
+// *info = -1 (when it is still 0) and stops waiting in that wave, so every
+// wave exits. The forward sweep marks its output of the backward sweep not
+// ready; the backward sweep marks each block of its input not ready once it
+// has read it, ready for the next forward sweep; the promote kernel marks
+// the forward output not ready at the start of a solve.
 constexpr uint64_t kSweepWaitTicks = uint64_t(1) << 28;   // about 2.7 s
 
-static __device__ __forceinline__ void sweep_wait(const int32_t* flag, int32_t* info,
-                                                  bool& failed) {
-  if (threadIdx.x == 0 && !failed) {
-    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-    while (__hip_atomic_load(flag, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) == 0) {
-      if (__builtin_amdgcn_s_memrealtime() - t0 > kSweepWaitTicks) {
+// Re-polls until no lane of the wave holds a not-ready value (or the wait
+// times out); v[] are the values at p[], reloaded where still not ready.
+template <int N>
+static __device__ __forceinline__ void wave_wait(const double* const (&p)[N], double (&v)[N],
+                                                 int32_t* info, bool& failed) {
+  bool pending = false;
+#pragma unroll
+  for (int t = 0; t < N; ++t) pending |= is_not_ready(v[t]);
+  if (!__any(pending) || failed) return;
+  const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+  while (true) {
+    __builtin_amdgcn_s_sleep(1);
+    pending = false;
+#pragma unroll
+    for (int t = 0; t < N; ++t) {
+      if (is_not_ready(v[t])) v[t] = poll_load(p[t]);
+      pending |= is_not_ready(v[t]);
+    }
+    if (!__any(pending)) return;
+    if (__builtin_amdgcn_s_memrealtime() - t0 > kSweepWaitTicks) {
+      if ((threadIdx.x & 63) == 0) {
         int32_t expect = 0;
         __hip_atomic_compare_exchange_strong(info, &expect, -1, __ATOMIC_RELAXED,
                                              __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-        failed = true;
-        break;
       }
-      __builtin_amdgcn_s_sleep(1);
+      failed = true;
+      return;
     }
   }
-  __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the block's values are read after this
-}
-
-static __device__ __forceinline__ void sweep_publish(int32_t* flag) {
-  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-  __syncthreads();
-  if (threadIdx.x == 0) __hip_atomic_store(flag, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
 }
 
 // Sums 16 per-lane partials over the 64 lanes of a wave: afterwards every
@@ -699,7 +721,8 @@ static __device__ __forceinline__ double wave_sum16(double (&p)[16], int lane) {
 
 // out[i] = sum_c M[c][i] v[c] for a 128 x 128 block stored row-major (c rows);
 // thread (i, q) holds M[32 q + m][i], m < 32, and the four quarters are added
-// in a fixed order. v and red are LDS; red holds 4 x 128 doubles.
+// in a fixed order. v and red are LDS; red holds 4 x 128 doubles. The results
+// are stored as ready signals.
 static __device__ __forceinline__ void block_mvT_load(const double* __restrict__ M, double (&a)[32],
                                                       int tid) {
   const int i = tid & 127, q = tid >> 7;
@@ -707,8 +730,8 @@ static __device__ __forceinline__ void block_mvT_load(const double* __restrict__
   for (int m = 0; m < 32; ++m) a[m] = M[(32 * q + m) * NB + i];
 }
 static __device__ __forceinline__ void block_mvT_finish(const double (&a)[32], const double* v,
-                                                        int n, double* __restrict__ out,
-                                                        double (*red)[NB], int tid) {
+                                                        int n, double* out, double (*red)[NB],
+                                                        int tid) {
   const int i = tid & 127, q = tid >> 7;
   double s0 = 0.0, s1 = 0.0;
 #pragma unroll
@@ -718,29 +741,27 @@ static __device__ __forceinline__ void block_mvT_finish(const double (&a)[32], c
   }
   red[q][i] = s0 + s1;
   __syncthreads();
-  if (q == 0 && i < n) out[i] = (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]);
+  if (q == 0 && i < n) signal_store(out + i, (red[0][i] + red[1][i]) + (red[2][i] + red[3][i]));
 }
 
 // Forward sweep L y = b, left-looking by block rows:
 //   y_k = L_kk^{-1} (b_k - sum_{j<k} L_kj y_j).
 // Workgroup k: wave w owns rows 16 w .. 16 w + 15 of the block; lane l holds
 // columns l and l + 64 of each block L_kj (coalesced 512-byte row reads) and
-// keeps per-lane partial sums over all j, reduced across lanes once.
+// keeps per-lane partial sums over all j, reduced across lanes once. y must
+// be not ready on entry; x (the backward sweep's output) is marked not ready.
 __global__ __launch_bounds__(512) void sweep_fwd_kernel(const double* __restrict__ A,
                                                        const double* __restrict__ LinvT, int32_t D,
-                                                       const double* __restrict__ b,
-                                                       double* __restrict__ y,
-                                                       int32_t* __restrict__ flags,
-                                                       int32_t* __restrict__ info) {
+                                                       const double* __restrict__ b, double* y,
+                                                       double* x, int32_t* __restrict__ info) {
   __shared__ double rv[NB];
   __shared__ double red[4][NB];
-  bool failed = false;   // used by thread 0 only
+  bool failed = false;
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int nblk = (D + NB - 1) / NB;
   const int k = blockIdx.x;
   const int64_t r0 = int64_t(k) * NB;
   const int n = (D - r0) < NB ? int(D - r0) : NB;
-  if (tid == 0) flags[nblk + k] = 0;   // backward flag of this block, for the sweep that follows
+  if (tid < n) signal_store(x + r0 + tid, not_ready());
   double inv[32];
   block_mvT_load(LinvT + int64_t(k) * NB * NB, inv, tid);
   double acc[16][2];
@@ -755,12 +776,13 @@ __global__ __launch_bounds__(512) void sweep_fwd_kernel(const double* __restrict
       lb[r][0] = p[lane];
       lb[r][1] = p[lane + 64];
     }
-    sweep_wait(flags + j, info, failed);
-    const double y0 = y[int64_t(j) * NB + lane], y1 = y[int64_t(j) * NB + 64 + lane];
+    const double* const yp[2] = {y + int64_t(j) * NB + lane, y + int64_t(j) * NB + 64 + lane};
+    double yv[2] = {poll_load(yp[0]), poll_load(yp[1])};
+    wave_wait<2>(yp, yv, info, failed);
 #pragma unroll
     for (int r = 0; r < 16; ++r) {
-      acc[r][0] = __builtin_fma(lb[r][0], y0, acc[r][0]);
-      acc[r][1] = __builtin_fma(lb[r][1], y1, acc[r][1]);
+      acc[r][0] = __builtin_fma(lb[r][0], yv[0], acc[r][0]);
+      acc[r][1] = __builtin_fma(lb[r][1], yv[1], acc[r][1]);
     }
   }
   double ps[16];
@@ -773,7 +795,6 @@ __global__ __launch_bounds__(512) void sweep_fwd_kernel(const double* __restrict
   }
   __syncthreads();
   block_mvT_finish(inv, rv, n, y + r0, red, tid);
-  sweep_publish(flags + k);
 }
 
 // Backward sweep L^T x = y, by block rows of L^T from the last:
@@ -781,22 +802,22 @@ __global__ __launch_bounds__(512) void sweep_fwd_kernel(const double* __restrict
 // Workgroup g owns block k = nblk - 1 - g. Thread (c, q) holds column c of
 // the block and rows 32 q .. 32 q + 31 of each block L_jk (coalesced over c),
 // so the products need no cross-lane sums; the quarters are added once.
+// Lane m < 32 of a wave polls x_j[32 q + m]; the values reach the other
+// lanes by shuffles. x must be not ready on entry; y_k is marked not ready
+// after it is read.
 __global__ __launch_bounds__(512) void sweep_bwd_kernel(const double* __restrict__ A,
                                                        const double* __restrict__ Linv, int32_t D,
-                                                       const double* __restrict__ y,
-                                                       double* __restrict__ x,
-                                                       int32_t* __restrict__ flags,
+                                                       double* y, double* x,
                                                        int32_t* __restrict__ info) {
   __shared__ double rv[NB];
   __shared__ double red[4][NB];
-  bool failed = false;   // used by thread 0 only
-  const int tid = threadIdx.x;
+  bool failed = false;
+  const int tid = threadIdx.x, lane = tid & 63;
   const int c = tid & 127, q = tid >> 7;
   const int nblk = (D + NB - 1) / NB;
   const int k = nblk - 1 - int(blockIdx.x);
   const int64_t c0 = int64_t(k) * NB;
   const int n = (D - c0) < NB ? int(D - c0) : NB;
-  if (tid == 0) flags[k] = 0;   // forward flag of this block, for the next solve
   double inv[32];
   block_mvT_load(Linv + int64_t(k) * NB * NB, inv, tid);
   const int64_t col = c0 + (c < n ? c : n - 1);
@@ -807,22 +828,25 @@ __global__ __launch_bounds__(512) void sweep_bwd_kernel(const double* __restrict
 #pragma unroll
     for (int m = 0; m < 32; ++m) {
       const int64_t row = rj + m;
-      lb[m] = A[(row < D ? row : D - 1) * D + col];
+      lb[m] = row < D ? A[row * D + col] : 0.0;
     }
-    sweep_wait(flags + nblk + j, info, failed);
+    const int64_t mine = rj + (lane & 31);
+    const double* const xp[1] = {x + (mine < D ? mine : D - 1)};
+    double xv[1] = {poll_load(xp[0])};
+    wave_wait<1>(xp, xv, info, failed);
 #pragma unroll
-    for (int m = 0; m < 32; ++m) {
-      const int64_t row = rj + m;
-      const double xv = x[row < D ? row : D - 1];
-      acc = __builtin_fma(row < D ? lb[m] : 0.0, xv, acc);
-    }
+    for (int m = 0; m < 32; ++m) acc = __builtin_fma(lb[m], __shfl(xv[0], m), acc);
   }
   red[q][c] = acc;
   __syncthreads();
-  if (q == 0) rv[c] = c < n ? y[c0 + c] - ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c])) : 0.0;
+  if (q == 0 && c < n) {
+    rv[c] = y[c0 + c] - ((red[0][c] + red[1][c]) + (red[2][c] + red[3][c]));
+    signal_store(y + c0 + c, not_ready());   // for the next forward sweep
+  } else if (q == 0) {
+    rv[c] = 0.0;
+  }
   __syncthreads();
   block_mvT_finish(inv, rv, n, x + c0, red, tid);
-  sweep_publish(flags + nblk + k);
 }
 
 // Partial sums of (lower-stored symmetric G) x over 64 x 64 tiles:
@@ -899,9 +923,9 @@ static hipError_t solve_triangular(const SolveWs& w, int32_t D, const double* rh
   // L tmp = rhs, then L^T out = tmp: one launch per sweep, one workgroup per block
   const unsigned nblk = unsigned((D + NB - 1) / NB);
   hipLaunchKernelGGL(sweep_fwd_kernel, dim3(nblk), dim3(512), 0, st, w.A, w.LinvT, D, rhs, tmp,
-                     w.flags, info);
+                     out, info);
   hipLaunchKernelGGL(sweep_bwd_kernel, dim3(nblk), dim3(512), 0, st, w.A, w.Linv, D, tmp, out,
-                     w.flags, info);
+                     info);
   return hipGetLastError();
 }
 
@@ -938,7 +962,7 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
   const SolveWs w = carve(ws, D);
   const unsigned vg = unsigned((D + 255) / 256);
   hipLaunchKernelGGL(promote_kernel<TG>, dim3(vg, unsigned(D)), dim3(256), 0, st, G, D, lambda,
-                     w.A, info, w.flags);
+                     w.A, info, w.y);
   // Right-looking blocked Cholesky with a one-block lookahead: after the
   // panel solve of block k, the trailing tile that becomes the next diagonal
   // block is updated first; that block is then factored (one workgroup) on
@@ -999,8 +1023,7 @@ size_t sorf_solve_ws_bytes(int32_t D) {
   const size_t nblk = (size_t(D) + NB - 1) / NB;
   const size_t nt = (size_t(D) + 63) / 64;
   return align256(sizeof(double) * size_t(D) * D) + 2 * align256(sizeof(double) * nblk * NB * NB) +
-         3 * align256(sizeof(double) * D) + align256(sizeof(double) * nt * nt * 64) +
-         align256(sizeof(int32_t) * 2 * nblk);
+         3 * align256(sizeof(double) * D) + align256(sizeof(double) * nt * nt * 64);
 }
 
 hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double lambda,
