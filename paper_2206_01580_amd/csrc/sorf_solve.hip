@@ -11,8 +11,9 @@
 //   1. factor the NB x NB diagonal block in LDS and invert it (one workgroup;
 //      the 64 x 64 halves are factored and inverted by one wave in registers),
 //   2. panel below: L21 = A21 L11^{-T} = A21 (L11^{-1})^T as an FP64 MFMA GEMM,
-//   3. trailing update A22 -= L21 L21^T on the lower triangle, 128 x 128
-//      tiles of FP64 MFMA, the tile of the next diagonal block first.
+//      fused with the update of the next diagonal tile,
+//   3. trailing update A22 -= L21 L21^T on the rest of the lower triangle,
+//      128 x 128 tiles of FP64 MFMA.
 // Triangular solves use the inverted diagonal blocks: one launch per sweep,
 // one workgroup per block row, each waiting for the solved values it needs.
 #include <cmath>
@@ -515,58 +516,119 @@ __global__ __launch_bounds__(256) void transpose_blocks_kernel(const double* __r
     }
 }
 
-// Panel below the diagonal block: L21 = A21 (L11^{-1})^T, in place.
-// 64 rows x 128 columns per workgroup, K = 128 in chunks of 32 through LDS.
-__global__ __launch_bounds__(256) void trsm_kernel(double* __restrict__ A, int32_t D, int32_t k,
-                                                  const double* __restrict__ Linv) {
-  constexpr int KC = 32;
-  __shared__ double sP[64][KC + 1];
-  __shared__ double sV[NB][KC + 1];
-  const int tid = threadIdx.x;
-  const int lane = tid & 63;
-  const int wv = tid >> 6;  // wave owns output columns [32 wv, 32 wv + 32)
-  const int64_t r0 = int64_t(k) + NB + int64_t(blockIdx.x) * 64;
+// Panel below the diagonal block, fused with the update of the next diagonal
+// tile: workgroup b computes the 128 rows L21 = A21 (L11^{-1})^T starting at
+// k + NB + 128 b; workgroup 0, which owns the next block row, then applies
+// A[k+NB.., k+NB..] -= L21 L21^T to that 128 x 128 tile (lower part), so the
+// next diagonal block is ready for its factorisation when this kernel ends.
+// 8 waves of 32 x 64 (2 x 4 FP64 MFMA blocks). The inverse block sits in LDS;
+// each lane loads its A operands for all of K at once (four consecutive k per
+// row: the MFMA's k index t = lane / 16 stands for k = kb + 4 t + s in step
+// s, and the B operands use the same order).
+constexpr int PLD = NB + 4;   // LDS row stride of the panel kernel (doubles)
+
+__global__ __launch_bounds__(512) void panel_kernel(double* __restrict__ A, int32_t D, int32_t k,
+                                                   const double* __restrict__ Linv) {
+  __shared__ double sL[NB][PLD];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int wy = wv >> 1, wx = wv & 1;   // rows [32 wy, +32), columns [64 wx, +64)
+  const int li = lane & 15, lt = lane >> 4;
+  const int64_t r0 = int64_t(k) + NB + int64_t(blockIdx.x) * NB;
   const double* inv = Linv + int64_t(k / NB) * NB * NB;
-  f64x4 acc[4][2];
+  for (int t = tid; t < NB * NB / 2; t += 512) {
+    const int j = t >> 6, p = (t & 63) * 2;
+    const double2 v = *reinterpret_cast<const double2*>(inv + j * NB + p);
+    sL[j][p] = v.x;
+    sL[j][p + 1] = v.y;
+  }
+  double ar[2][8][4];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a) {
+    const int64_t row = r0 + 32 * wy + 16 * a + li;
+    const bool ok = row < D;
+    const double* src = A + (ok ? row : int64_t(D) - 1) * D + k + 4 * lt;
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  for (int c0 = 0; c0 < NB; c0 += KC) {
-    for (int t = tid; t < 64 * KC; t += 256) {
-      const int i = t / KC, p = t % KC;
-      const double a = A[min(r0 + i, int64_t(D) - 1) * D + k + c0 + p];
-      sP[i][p] = (r0 + i < D) ? a : 0.0;
-    }
-    for (int t = tid; t < NB * KC; t += 256) {
-      const int j = t / KC, p = t % KC;
-      sV[j][p] = inv[j * NB + c0 + p];
-    }
-    __syncthreads();
+    for (int kb = 0; kb < 8; ++kb)
 #pragma unroll
-    for (int kk = 0; kk < KC; kk += 4) {
-      const int p = kk + (lane >> 4);
-      double av[4], bv[2];
+      for (int s = 0; s < 4; ++s) {
+        const double v = src[16 * kb + s];   // rows of A need not be 16-byte aligned
+        ar[a][kb][s] = ok ? v : 0.0;
+      }
+  }
+  __syncthreads();
+  f64x4 acc[2][4];
 #pragma unroll
-      for (int a = 0; a < 4; ++a) av[a] = sP[a * 16 + (lane & 15)][p];
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) bv[b] = sV[wv * 32 + b * 16 + (lane & 15)][p];
+    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
-      for (int a = 0; a < 4; ++a)
+  for (int kb = 0; kb < 8; ++kb) {
+    double br[4][4];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) acc[a][b] = mfma64(av[a], bv[b], acc[a][b]);
-    }
-    __syncthreads();
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int s = 0; s < 4; ++s) br[b][s] = sL[64 * wx + 16 * b + li][16 * kb + 4 * lt + s];
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) acc[a][b] = mfma64(ar[a][kb][s], br[b][s], acc[a][b]);
   }
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < 2; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < 4; ++b)
 #pragma unroll
       for (int r = 0; r < 4; ++r) {
-        const int64_t gi = r0 + a * 16 + (lane >> 4) + 4 * r;
-        const int64_t gj = k + wv * 32 + b * 16 + (lane & 15);
-        if (gi < D) A[gi * D + gj] = acc[a][b][r];
+        const int64_t row = r0 + 32 * wy + 16 * a + lt + 4 * r;
+        if (row < D) A[row * D + k + 64 * wx + 16 * b + li] = acc[a][b][r];
+      }
+  if (blockIdx.x != 0) return;
+  // the next diagonal tile: stage L21 (this workgroup's rows) in LDS
+  __syncthreads();
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 32 * wy + 16 * a + lt + 4 * r;
+        sL[i][64 * wx + 16 * b + li] = r0 + i < D ? acc[a][b][r] : 0.0;
+      }
+  __syncthreads();
+  if (32 * wy + 31 < 64 * wx) return;   // block entirely above the diagonal
+  f64x4 cc[2][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b) cc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+#pragma unroll 2
+  for (int kb = 0; kb < 8; ++kb) {
+    double pa[2][4], pb[4][4];
+#pragma unroll
+    for (int s = 0; s < 4; ++s) {
+#pragma unroll
+      for (int a = 0; a < 2; ++a) pa[a][s] = sL[32 * wy + 16 * a + li][16 * kb + 4 * lt + s];
+#pragma unroll
+      for (int b = 0; b < 4; ++b) pb[b][s] = sL[64 * wx + 16 * b + li][16 * kb + 4 * lt + s];
+    }
+#pragma unroll
+    for (int s = 0; s < 4; ++s)
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 4; ++b) cc[a][b] = mfma64(pa[a][s], pb[b][s], cc[a][b]);
+  }
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = 32 * wy + 16 * a + lt + 4 * r, j = 64 * wx + 16 * b + li;
+        const int64_t gi = r0 + i, gj = r0 + j;
+        if (gi < D && i >= j) A[gi * D + gj] -= cc[a][b][r];
       }
 }
 
@@ -977,11 +1039,9 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
                      w.LinvT);
   for (int32_t k = 0; k + NB < D; k += NB) {
     const int64_t rest = int64_t(D) - k - NB;
-    hipLaunchKernelGGL(trsm_kernel, dim3(unsigned((rest + 63) / 64)), dim3(256), 0, st, w.A, D, k,
-                       w.Linv);
     const int64_t nt = (rest + 127) / 128;
     const int64_t tiles = nt * (nt + 1) / 2;
-    hipLaunchKernelGGL(syrk_kernel, dim3(1), dim3(512), 0, st, w.A, D, k, 0);
+    hipLaunchKernelGGL(panel_kernel, dim3(unsigned(nt)), dim3(512), 0, st, w.A, D, k, w.Linv);
     if (tiles > 1) {
       if ((e = hipEventRecord(ev_fork, st)) != hipSuccess) return e;
       hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, k + NB, info,
