@@ -285,55 +285,53 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
         S[a][b][r] = 0.0f;
       }
 
-#pragma unroll
-  for (int j = 0; j < NS - 1; ++j)
-    if (j < n_st) issue(j, j);
   // Groups of KC stages accumulate in P; P is added into S after each group.
   // Waves whose block lies above the diagonal compute too (their result is
   // dropped): keeping the loop free of per-wave branches keeps P in the
-  // accumulation registers.
-  int64_t s = 0;
-  int slot = 0;
-  while (s < n_st) {
-    const int64_t g_end = s + KC < n_st ? s + KC : n_st;
-    for (; s < g_end; ++s) {
-      const int64_t left = n_st - 1 - s;
-      wait_stage<PW>(left < NS - 2 ? left : NS - 2);
-      stage_barrier();
-      if (s + NS - 1 < n_st) issue(s + NS - 1, slot == 0 ? NS - 1 : slot - 1);
-      // all of the stage's fragments are read before the first product, so
-      // the LDS latency is paid once per stage rather than per fragment
-      u16x8 ah[2][4], bh[2][2], al[2][4], bl[2][2];
+  // accumulation registers. Software pipeline over half-stages as in the
+  // single-product kernel: the fragments of one half-stage are read from LDS
+  // while the products of the previous half-stage run; all NS slots are
+  // filled up front and the slot of stage s takes stage s + NS after the
+  // barrier that publishes stage s + 1.
+  u16x8 ah0[4], al0[4], bh0[2], bl0[2], ah1[4], al1[4], bh1[2], bl1[2];
+  auto read_half = [&](int sl, int kk, u16x8 (&ah)[4], u16x8 (&al)[4], u16x8 (&bh)[2],
+                       u16x8 (&bl)[2]) {
 #pragma unroll
-      for (int kk = 0; kk < 2; ++kk) {
+    for (int a = 0; a < 4; ++a) {
+      ah[a] = ring[sl][0][kk * (TM / 32) + wy * 4 + a][lane];
+      if constexpr (HILO) al[a] = ring[sl][NP - 1][kk * (TM / 32) + wy * 4 + a][lane];
+    }
 #pragma unroll
-        for (int a = 0; a < 4; ++a) {
-          ah[kk][a] = ring[slot][0][kk * (TM / 32) + wy * 4 + a][lane];
-          if constexpr (HILO) al[kk][a] = ring[slot][NP - 1][kk * (TM / 32) + wy * 4 + a][lane];
-        }
+    for (int b = 0; b < 2; ++b) {
+      bh[b] = ring[sl][0][AF + kk * (TN / 32) + wx * 2 + b][lane];
+      if constexpr (HILO) bl[b] = ring[sl][NP - 1][AF + kk * (TN / 32) + wx * 2 + b][lane];
+    }
+  };
+  auto mma_half = [&](const u16x8 (&ah)[4], const u16x8 (&al)[4], const u16x8 (&bh)[2],
+                      const u16x8 (&bl)[2]) {
 #pragma unroll
-        for (int b = 0; b < 2; ++b) {
-          bh[kk][b] = ring[slot][0][AF + kk * (TN / 32) + wx * 2 + b][lane];
-          if constexpr (HILO)
-            bl[kk][b] = ring[slot][NP - 1][AF + kk * (TN / 32) + wx * 2 + b][lane];
+    for (int a = 0; a < 4; ++a)
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        P[a][b] = mma16<MODE>(ah[a], bh[b], P[a][b]);
+        if constexpr (HILO) {
+          P[a][b] = mma16<MODE>(ah[a], bl[b], P[a][b]);
+          P[a][b] = mma16<MODE>(al[a], bh[b], P[a][b]);
+          P[a][b] = mma16<MODE>(al[a], bl[b], P[a][b]);
         }
       }
-      __builtin_amdgcn_sched_barrier(0);
+  };
+  // the next half-stage's LDS reads interleaved with the first products
+  auto interleave = [] {
+    constexpr int NR = 6 * NP, NM = 8 * (HILO ? 4 : 1);
 #pragma unroll
-      for (int kk = 0; kk < 2; ++kk)
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b) {
-            P[a][b] = mma16<MODE>(ah[kk][a], bh[kk][b], P[a][b]);
-            if constexpr (HILO) {
-              P[a][b] = mma16<MODE>(ah[kk][a], bl[kk][b], P[a][b]);
-              P[a][b] = mma16<MODE>(al[kk][a], bh[kk][b], P[a][b]);
-              P[a][b] = mma16<MODE>(al[kk][a], bl[kk][b], P[a][b]);
-            }
-          }
-      slot = slot + 1 == NS ? 0 : slot + 1;
+    for (int i = 0; i < NR; ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
+    __builtin_amdgcn_sched_group_barrier(0x008, NM - NR, 0);
+  };
+  auto flush = [&] {
 #pragma unroll
     for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -343,6 +341,43 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
           S[a][b][r] += P[a][b][r];
           P[a][b][r] = 0.0f;
         }
+  };
+
+#pragma unroll
+  for (int j = 0; j < NS; ++j)
+    if (j < n_st) issue(j, j);
+  if (n_st > 0) {
+    wait_stage<PW>(n_st - 1 < NS - 1 ? n_st - 1 : NS - 1);
+    stage_barrier();
+    read_half(0, 0, ah0, al0, bh0, bl0);
+  }
+  int64_t s = 0;
+  int slot = 0;
+  while (s + 1 < n_st) {
+    const int64_t g_end = (s / KC + 1) * KC < n_st - 1 ? (s / KC + 1) * KC : n_st - 1;
+    for (; s < g_end; ++s) {
+      const int nslot = slot + 1 == NS ? 0 : slot + 1;
+      read_half(slot, 1, ah1, al1, bh1, bl1);
+      mma_half(ah0, al0, bh0, bl0);
+      interleave();
+      const int64_t ahead = n_st - 2 - s;
+      wait_stage<PW>(ahead < NS - 2 ? ahead : NS - 2);
+      // this wave's reads of stage s have landed before its slot is reused
+      asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+      stage_barrier();
+      if (s + NS < n_st) issue(s + NS, slot);
+      read_half(nslot, 0, ah0, al0, bh0, bl0);
+      mma_half(ah1, al1, bh1, bl1);
+      interleave();
+      slot = nslot;
+    }
+    if (s % KC == 0) flush();
+  }
+  if (n_st > 0) {
+    read_half(slot, 1, ah1, al1, bh1, bl1);
+    mma_half(ah0, al0, bh0, bl0);
+    mma_half(ah1, al1, bh1, bl1);
+    flush();
   }
 
   if (!active) return;
