@@ -182,8 +182,10 @@ size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, in
  *      J_ptr[m]; J_ptr: [n_mols + 1] int64 device array. Blocks may sit anywhere in J
  *      (no order, gaps allowed; J_ptr[n_mols] is not read) and need no alignment.
  *      Both NULL for energies only.
- *   Each molecule's E and F are summed in an order fixed by its own atom count, so a
- *   molecule's results are bitwise the same in any batch.
+ *   Each molecule's E and F are summed in an order fixed by its own atoms, so a
+ *   molecule's results are bitwise the same in any batch. Without J, E is summed per
+ *   (molecule, stack) over the atoms and then over the stacks; with J, per atom over the
+ *   features and then over the atoms: the two E agree to FP32 rounding, not bitwise.
  *   F: [3 n_atoms] FP32 out ([atom][xyz]), required iff J is given.
  *   workspace: device memory of at least sorf_predict_workspace_bytes(), 256-byte aligned. */
 sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const float* alpha,

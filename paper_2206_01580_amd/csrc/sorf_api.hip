@@ -61,7 +61,8 @@ size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 size_t predict_ws(const sorf_model* m, int64_t n_atoms, int64_t n_mols) {
   return align256(sizeof(float) * size_t(n_atoms)) +
          align256(sizeof(float) * size_t(n_atoms) * size_t(m->d)) +
-         sorf_force_plan_bytes(n_atoms, n_mols);
+         sorf_force_plan_bytes(n_atoms, n_mols) +
+         align256(sizeof(float) * size_t(n_mols) * size_t(m->n_stacks));
 }
 
 }  // namespace
@@ -201,6 +202,14 @@ sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const
   }
   hipStream_t st = hipStream_t(stream);
   const SorfFeatureArgs a = pack(model, batch);
+  if (J == nullptr) {
+    // energies only: per (molecule, stack) partials, summed in stack order
+    if (batch->n_atoms == 0) return dev(sorf_launch_fill(E, batch->n_mols, 0.0f, st));
+    float* part = reinterpret_cast<float*>(static_cast<char*>(workspace) + need -
+                                           align256(sizeof(float) * size_t(batch->n_mols) *
+                                                    size_t(model->n_stacks)));
+    return dev(sorf_launch_energies(a, alpha, part, E, st));
+  }
   float* e_atom = static_cast<float*>(workspace);
   const size_t grad_off = align256(sizeof(float) * size_t(batch->n_atoms));
   float* grad = reinterpret_cast<float*>(static_cast<char*>(workspace) + grad_off);

@@ -9,7 +9,9 @@
 // Work split. sorf_forward: one lane group per (molecule, stack); the group
 // walks the molecule's atoms and keeps the stack's d running sums of cos in
 // registers, so the atom->molecule sum needs no atomics and no second pass and
-// Z is written once, coalesced per lane (EPL contiguous floats).
+// Z is written once, coalesced per lane (EPL contiguous floats). Energies
+// without forces use the same kernel with the dot product against alpha in
+// place of the store (one partial per molecule and stack).
 // Adjoint: one wave per atom; its lane groups cover the stacks in passes and
 // the stack sum is a wave reduction at the end.
 #include <cmath>
@@ -21,12 +23,15 @@ namespace sorf {
 // ---------------------------------------------------------------------------
 // Forward features
 // ---------------------------------------------------------------------------
-template <int LOG_D, int LOG_EPL>
+// With DOT, the group does not store its features: it writes the stack's
+// share of the molecule's energy, part[m S + s] = sum_f alpha_f z_f over the
+// stack's features, summed over the group's lanes in a fixed order.
+template <int LOG_D, int LOG_EPL, bool DOT>
 __global__ __launch_bounds__(256) void forward_kernel(
     const float* __restrict__ x, const int32_t* __restrict__ element,
     const int64_t* __restrict__ mol_ptr, const uint32_t* __restrict__ signs,
-    const float* __restrict__ bias, float* __restrict__ Z, int64_t n_mols, int32_t S, int32_t T,
-    float c_rev, float out_scale) {
+    const float* __restrict__ bias, float* __restrict__ Z, const float* __restrict__ alpha,
+    int64_t n_mols, int32_t S, int32_t T, float c_rev, float out_scale) {
   constexpr int DV = 1 << LOG_D;
   constexpr int EPL = 1 << LOG_EPL;
   constexpr int LOGK = LOG_D - LOG_EPL;
@@ -74,7 +79,33 @@ __global__ __launch_bounds__(256) void forward_kernel(
       acc[r] += __builtin_amdgcn_cosf(u);
     }
   }
-  store_vec<EPL>(Z + m * Dtot + int64_t(s) * DV + q * EPL, acc, out_scale);
+  if constexpr (DOT) {
+    float al[EPL];
+    load_vec<EPL>(al, alpha + int64_t(s) * DV + q * EPL);
+    float p = 0.0f;
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) p = __builtin_fmaf(al[r], acc[r], p);
+    if constexpr (LOGK > 0) p += lane_xor<0>(p);
+    if constexpr (LOGK > 1) p += lane_xor<1>(p);
+    if constexpr (LOGK > 2) p += lane_xor<2>(p);
+    if constexpr (LOGK > 3) p += lane_xor<3>(p);
+    if constexpr (LOGK > 4) p += lane_xor<4>(p);
+    if constexpr (LOGK > 5) p += lane_xor<5>(p);
+    if (q == 0) Z[m * S + s] = p * out_scale;
+  } else {
+    store_vec<EPL>(Z + m * Dtot + int64_t(s) * DV + q * EPL, acc, out_scale);
+  }
+}
+
+// E[m] = sum over the stacks of part[m S + s], in stack order.
+__global__ __launch_bounds__(256) void energy_sum_kernel(const float* __restrict__ part,
+                                                        int64_t n_mols, int32_t S,
+                                                        float* __restrict__ E) {
+  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+  if (m >= n_mols) return;
+  float e = 0.0f;
+  for (int32_t s = 0; s < S; ++s) e += part[m * S + s];
+  E[m] = e;
 }
 
 // ---------------------------------------------------------------------------
@@ -388,7 +419,8 @@ inline float sorf_c(const SorfFeatureArgs& a) {
 }
 
 template <int LOG_D>
-static hipError_t forward_dispatch(const SorfFeatureArgs& a, float* Z, hipStream_t st) {
+static hipError_t forward_dispatch(const SorfFeatureArgs& a, float* Z, const float* alpha,
+                                   hipStream_t st) {
   constexpr int LOG_EPL = default_log_epl<LOG_D>();
   constexpr int VPW = 64 >> (LOG_D - LOG_EPL);
   const int64_t items = a.n_mols * int64_t(a.n_stacks);
@@ -396,9 +428,14 @@ static hipError_t forward_dispatch(const SorfFeatureArgs& a, float* Z, hipStream
   const int64_t blocks = (waves + 3) / 4;
   const double D = double(a.d) * a.n_stacks;
   const float c_rev = float(double(sorf_c(a)) * (1.0 / (2.0 * M_PI)));
-  hipLaunchKernelGGL((forward_kernel<LOG_D, LOG_EPL>), dim3(unsigned(blocks)), dim3(256), 0, st,
-                     a.x, a.element, a.mol_ptr, a.signs, a.bias, Z, a.n_mols, a.n_stacks,
-                     a.n_transforms, c_rev, float(std::sqrt(2.0 / D)));
+  if (alpha == nullptr)
+    hipLaunchKernelGGL((forward_kernel<LOG_D, LOG_EPL, false>), dim3(unsigned(blocks)), dim3(256),
+                       0, st, a.x, a.element, a.mol_ptr, a.signs, a.bias, Z, nullptr, a.n_mols,
+                       a.n_stacks, a.n_transforms, c_rev, float(std::sqrt(2.0 / D)));
+  else
+    hipLaunchKernelGGL((forward_kernel<LOG_D, LOG_EPL, true>), dim3(unsigned(blocks)), dim3(256),
+                       0, st, a.x, a.element, a.mol_ptr, a.signs, a.bias, Z, alpha, a.n_mols,
+                       a.n_stacks, a.n_transforms, c_rev, float(std::sqrt(2.0 / D)));
   return hipGetLastError();
 }
 
@@ -451,9 +488,26 @@ static int log2i(int d) {
 
 hipError_t sorf_launch_forward(const SorfFeatureArgs& a, float* Z, hipStream_t st) {
   if (a.n_mols == 0) return hipSuccess;
-#define CALL(L) forward_dispatch<L>(a, Z, st)
+#define CALL(L) forward_dispatch<L>(a, Z, nullptr, st)
   SORF_LOGD_SWITCH(log2i(a.d), CALL)
 #undef CALL
+}
+
+static hipError_t energy_parts(const SorfFeatureArgs& a, const float* alpha, float* part,
+                               hipStream_t st) {
+#define CALL(L) forward_dispatch<L>(a, part, alpha, st)
+  SORF_LOGD_SWITCH(log2i(a.d), CALL)
+#undef CALL
+}
+
+hipError_t sorf_launch_energies(const SorfFeatureArgs& a, const float* alpha, float* part,
+                                float* E, hipStream_t st) {
+  if (a.n_mols == 0) return hipSuccess;
+  hipError_t e = energy_parts(a, alpha, part, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(energy_sum_kernel, dim3(unsigned((a.n_mols + 255) / 256)), dim3(256), 0, st,
+                     part, a.n_mols, a.n_stacks, E);
+  return hipGetLastError();
 }
 
 hipError_t sorf_launch_atom_adjoint(const SorfFeatureArgs& a, const float* alpha, const float* dE,

@@ -200,6 +200,9 @@ struct SorfFeatureArgs {
 };
 
 hipError_t sorf_launch_forward(const SorfFeatureArgs& a, float* Z, hipStream_t s);
+// E[m] = sum_f alpha_f Z[m][f] without storing Z; part: n_mols * n_stacks floats.
+hipError_t sorf_launch_energies(const SorfFeatureArgs& a, const float* alpha, float* part,
+                                float* E, hipStream_t s);
 hipError_t sorf_launch_atom_adjoint(const SorfFeatureArgs& a, const float* alpha, const float* dE,
                                     float* grad_x, float* e_atom, hipStream_t s);
 // Workspace of the force contraction: tile and partial offsets per molecule

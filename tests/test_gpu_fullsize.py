@@ -2,7 +2,7 @@
 benchmark times, on outputs the oracle can afford one by one.
 
 * QM9-like training set (20,000 molecules, D = 8192): Z rows of 200 sampled
-  molecules; G and Z^T y on a 48-column sample (every Gram mode) against the
+  molecules; energies Z alpha of 64 sampled molecules; G and Z^T y on a 48-column sample (every Gram mode) against the
   FP64 oracle's columns of Z; the ridge solve through its residual.
 * Differentiation set (2000 conformations of a 21-atom molecule, D = 8192,
   1.36 GB of Jacobians): energies, dE/dx and forces of 8 sampled conformations.
@@ -60,6 +60,26 @@ def test_qm9_forward_sampled_rows(qm9):
     Zo = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, mols=mols)
     Zg = Z[torch.from_numpy(mols).cuda()].cpu().numpy().astype(np.float64)
     err = np.abs(Zg - Zo).max(axis=1) / np.abs(Zo).max(axis=1)
+    assert err.max() <= 1e-5, err.max()
+
+
+def test_qm9_energies_sampled(qm9):
+    """Energies without forces over the whole training set (the launch the
+    benchmark's energy phase times), sampled molecules against Z_oracle alpha."""
+    p, _, _, _ = qm9
+    s = S()
+    model, batch = s.Model.from_problem(p), s.Batch.from_problem(p)
+    rng = np.random.default_rng(13)
+    alpha = rng.standard_normal(p.n_features).astype(np.float32)
+    E = s.Predictor(model)(batch, torch.from_numpy(alpha).cuda())
+    torch.cuda.synchronize()
+    sizes = p.mol_sizes()
+    mols = np.unique(np.concatenate([[0, p.n_mols - 1, int(np.argmax(sizes))],
+                                     rng.choice(p.n_mols, 61, replace=False)]))
+    Zo = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, mols=mols)
+    Eo = Zo @ alpha.astype(np.float64)
+    scale = np.abs(Zo * alpha[None, :]).sum(axis=1)
+    err = np.abs(E.cpu().numpy()[mols].astype(np.float64) - Eo) / scale
     assert err.max() <= 1e-5, err.max()
 
 
