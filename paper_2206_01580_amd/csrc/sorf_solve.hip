@@ -633,12 +633,13 @@ __global__ __launch_bounds__(512) void panel_kernel(double* __restrict__ A, int3
 }
 
 // Trailing update A22 -= L21 L21^T on the lower triangle: 128 x 128 tiles,
-// 8 waves of 32 x 64 (2 x 4 MFMA blocks), K = NB in chunks of 16 via LDS with
-// a register double buffer. On a diagonal tile the waves whose block lies
-// above the diagonal only help with the loads.
+// 8 waves of 32 x 64 (2 x 4 MFMA blocks), K = NB in chunks of 32 via LDS with
+// a register double buffer. Each wave loads its entries of the tile before
+// the products, so the read of A22 overlaps them. On a diagonal tile the
+// waves whose block lies above the diagonal only help with the loads.
 __global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32_t D, int32_t k,
                                                   int32_t tile0) {
-  constexpr int T = 128, KC = 16;
+  constexpr int T = 128, KC = 32;
   __shared__ double sI[T][KC + 1];
   __shared__ double sJ[T][KC + 1];
   int64_t I, J;
@@ -651,33 +652,46 @@ __global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32
   const int wv = tid >> 6;
   const int wy = wv >> 1, wx = wv & 1;  // rows [32 wy, +32), columns [64 wx, +64)
   const bool idle = diag && (32 * wy + 31 < 64 * wx);
+  const int lr = tid >> 2;          // row 0..127 of the slab
+  const int lp = (tid & 3) * 8;     // 8 consecutive k
+  const bool okI = I0 + lr < D, okJ = J0 + lr < D;
+  const double* pI = A + min(I0 + lr, int64_t(D) - 1) * D + k + lp;
+  const double* pJ = A + min(J0 + lr, int64_t(D) - 1) * D + k + lp;
+  double rI[8], rJ[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double a = pI[q], b = pJ[q];
+    rI[q] = okI ? a : 0.0;
+    rJ[q] = okJ ? b : 0.0;
+  }
+  // this wave's entries of the tile (lower part inside the matrix)
+  double c[2][4][4];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 4; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int64_t gi = I0 + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
+        const int64_t gj = J0 + wx * 64 + b * 16 + (lane & 15);
+        const bool ok = !idle && gi < D && gj < D && gi >= gj;
+        c[a][b][r] = ok ? A[gi * D + gj] : 0.0;
+      }
   f64x4 acc[2][4];
 #pragma unroll
   for (int a = 0; a < 2; ++a)
 #pragma unroll
     for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
-  const int lr = tid >> 2;          // row 0..127 of the slab
-  const int lp = (tid & 3) * 4;     // 4 consecutive k
-  const bool okI = I0 + lr < D, okJ = J0 + lr < D;
-  const double* pI = A + min(I0 + lr, int64_t(D) - 1) * D + k + lp;
-  const double* pJ = A + min(J0 + lr, int64_t(D) - 1) * D + k + lp;
-  double rI[4], rJ[4];
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    const double a = pI[q], b = pJ[q];
-    rI[q] = okI ? a : 0.0;
-    rJ[q] = okJ ? b : 0.0;
-  }
   for (int c0 = 0; c0 < NB; c0 += KC) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
+    for (int q = 0; q < 8; ++q) {
       sI[lr][lp + q] = rI[q];
       if (!diag) sJ[lr][lp + q] = rJ[q];
     }
     __syncthreads();
     if (c0 + KC < NB) {
 #pragma unroll
-      for (int q = 0; q < 4; ++q) {
+      for (int q = 0; q < 8; ++q) {
         const double a = pI[c0 + KC + q], b = pJ[c0 + KC + q];
         rI[q] = okI ? a : 0.0;
         rJ[q] = okJ ? b : 0.0;
@@ -710,7 +724,7 @@ __global__ __launch_bounds__(512) void syrk_kernel(double* __restrict__ A, int32
       for (int r = 0; r < 4; ++r) {
         const int64_t gi = I0 + wy * 32 + a * 16 + (lane >> 4) + 4 * r;
         const int64_t gj = J0 + wx * 64 + b * 16 + (lane & 15);
-        if (gi < D && gj < D && gi >= gj) A[gi * D + gj] -= acc[a][b][r];
+        if (gi < D && gj < D && gi >= gj) A[gi * D + gj] = c[a][b][r] - acc[a][b][r];
       }
 }
 
