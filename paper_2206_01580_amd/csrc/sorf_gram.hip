@@ -29,6 +29,7 @@
 // with no per-tile conversion. The pack kernel also forms Z^T y in FP64
 // (per-chunk partials summed in a fixed order); the FP32 mode runs it for
 // Z^T y only and stages row-major Z slabs directly.
+#include <algorithm>
 #include <cmath>
 
 #include "sorf_internal.h"
@@ -397,8 +398,11 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
 // One workgroup (4 waves, 2 x 2) per 256 x 256 square tile of the lower
 // triangle; each wave owns 128 x 128 (4 x 4 blocks of 32 x 32), which halves
 // the LDS bytes per product against the 128 x 64 waves of the hi+lo kernel.
-// The single accumulator is kept for the whole row range: its drift is
-// orders of magnitude below the rounding of the 16-bit operands.
+// A launch covers at most kX1LaunchStages stages (32 rows each) and adds its
+// tiles to G, so the matrix-core accumulators never run over more rows than
+// that: a single accumulator over a long row range drifts enough to make
+// G + lambda I indefinite (100,000 rows, lambda = 1e-8); G itself is summed
+// in FP32 with round-to-nearest.
 //
 // Scheduling: with one 128 KB workgroup per CU, the tiles run in rounds of
 // kX1Slots. The first n_whole tiles (whole rounds) are computed over all rows
@@ -410,6 +414,7 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
 // its L2) followed by a contiguous run of slices.
 constexpr int TX = 256;        // square tile of the single-product kernel
 constexpr int kX1Slots = 256;  // concurrent workgroups: one per CU of the chip
+constexpr int64_t kX1LaunchStages = 256;   // 8192 rows per launch
 
 __host__ __device__ inline int64_t x1_tiles(int64_t D) {
   const int64_t n = (D + TX - 1) / TX;
@@ -442,8 +447,9 @@ __host__ __device__ inline void x1_xcd_items(const X1Plan& p, int x, int64_t& w0
 
 template <int MODE>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
-void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t n_slabs, int32_t ncb, int32_t D,
-                    X1Plan plan, float gscale, float* __restrict__ G, float* __restrict__ part) {
+void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_count,
+                    int32_t ncb, int32_t D, X1Plan plan, float gscale, float* __restrict__ G,
+                    float* __restrict__ part) {
   constexpr int AF = 2 * (TX / 32);   // A fragments per stage (2 slabs)
   constexpr int NF = 2 * AF;          // A and B
   constexpr int FW = NF / 4;          // copies per wave per stage
@@ -470,9 +476,8 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t n_slabs, int32_t ncb, 
   const bool active = I * TX + wy * 128 + 127 >= J * TX + wx * 128;
 
   // the slice of 2-slab stages this item accumulates
-  const int64_t n_st_all = n_slabs / 2;
-  const int64_t s0 = n_st_all * sp / n_split, s1 = n_st_all * (sp + 1) / n_split;
-  const int64_t n_st = s1 - s0;
+  const int64_t s0 = st_begin + st_count * sp / n_split;
+  const int64_t n_st = st_begin + st_count * (sp + 1) / n_split - s0;
 
   int64_t src[FW];
 #pragma unroll
@@ -1010,11 +1015,20 @@ GramLayout gram_layout(int64_t M, int32_t D) {
 }
 }  // namespace
 
+// Row ranges of the single-product launches: [k R, min((k + 1) R, n)).
+static size_t x1_plan_partial_bytes(const X1Plan& p) {
+  return size_t(p.n_split > 1 ? p.n_split : 0) * size_t(p.n_tiles - p.n_whole) * TX * TX *
+         sizeof(float);
+}
+
 size_t x1_partial_bytes(int64_t n_rows, int32_t D) {
   const GramLayout g = gram_layout(n_rows, D);
-  const X1Plan p = x1_plan(D, g.n_slabs / 2);
-  return al256(size_t(p.n_split > 1 ? p.n_split : 0) * size_t(p.n_tiles - p.n_whole) * TX * TX *
-               sizeof(float));
+  const int64_t n_st = g.n_slabs / 2;
+  const int64_t full = n_st < kX1LaunchStages ? n_st : kX1LaunchStages;
+  const int64_t last = n_st % kX1LaunchStages;
+  size_t b = x1_plan_partial_bytes(x1_plan(D, full));
+  if (last > 0) b = std::max(b, x1_plan_partial_bytes(x1_plan(D, last)));
+  return al256(b);
 }
 
 size_t sorf_gram_ws_bytes(int64_t n_rows, int32_t D, int mode) {
@@ -1088,19 +1102,24 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
       break;
     case kBF16:
     case kFP16: {
-      const X1Plan plan = x1_plan(D, g.n_slabs / 2);
       float* part = reinterpret_cast<float*>(w + g.zpart_bytes + kZeroBytes + g.part_bytes);
-      const dim3 xg{unsigned(x1_grid(plan))};
-      if (mode == kBF16)
-        hipLaunchKernelGGL(gram_x1_kernel<kBF16>, xg, blk, 0, st, hi, g.n_slabs, g.ncb, D, plan,
-                           gs, G, part);
-      else
-        hipLaunchKernelGGL(gram_x1_kernel<kFP16>, xg, blk, 0, st, hi, g.n_slabs, g.ncb, D, plan,
-                           gs, G, part);
-      if (plan.n_split > 1) {
+      const int64_t n_st = g.n_slabs / 2;
+      for (int64_t s0 = 0; s0 < n_st; s0 += kX1LaunchStages) {
+        const int64_t cnt = n_st - s0 < kX1LaunchStages ? n_st - s0 : kX1LaunchStages;
+        const X1Plan plan = x1_plan(D, cnt);
+        const dim3 xg{unsigned(x1_grid(plan))};
+        if (mode == kBF16)
+          hipLaunchKernelGGL(gram_x1_kernel<kBF16>, xg, blk, 0, st, hi, s0, cnt, g.ncb, D, plan,
+                             gs, G, part);
+        else
+          hipLaunchKernelGGL(gram_x1_kernel<kFP16>, xg, blk, 0, st, hi, s0, cnt, g.ncb, D, plan,
+                             gs, G, part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        const dim3 cg{unsigned(plan.n_tiles - plan.n_whole), unsigned(TX / 4)};
-        hipLaunchKernelGGL(gram_combine_kernel, cg, blk, 0, st, part, plan, D, gs, G);
+        if (plan.n_split > 1) {
+          const dim3 cg{unsigned(plan.n_tiles - plan.n_whole), unsigned(TX / 4)};
+          hipLaunchKernelGGL(gram_combine_kernel, cg, blk, 0, st, part, plan, D, gs, G);
+          if ((e = hipGetLastError()) != hipSuccess) return e;
+        }
       }
       break;
     }
