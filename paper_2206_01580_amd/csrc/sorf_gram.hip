@@ -132,6 +132,15 @@ __device__ __forceinline__ bool super_tile(int64_t D, int64_t nI, int64_t nJ, in
 
 // ------------------------------------------------------------------- packing
 // Fragment (ks, cb) -> u16x8 index ((ks * ncb + cb) * 64 + lane).
+// One workgroup per 128 columns (4 column blocks) x kPackSlabs slabs. Row
+// tiles of 4 slabs x 128 columns are read with coalesced 16-byte loads (the
+// next tile's loads are issued before the current one is processed), staged
+// in LDS and re-read by column: wave w forms the fragments of slab w, lane l
+// holding column 32 cb + l % 32 and rows 8 (l / 32) .. + 7 of each block. Z^T y
+// is summed per lane in FP64 and combined over the 8 partial sums of a column
+// in a fixed order.
+constexpr int kPackLds = 128 + 4;   // LDS row stride (floats): conflict-free column reads
+
 template <int MODE>
 __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ Z, int64_t M,
                                                    int32_t D, int64_t n_slabs, int32_t ncb,
@@ -139,55 +148,92 @@ __global__ __launch_bounds__(256) void pack_kernel(const float* __restrict__ Z, 
                                                    u16x8* __restrict__ lo,
                                                    const float* __restrict__ y,
                                                    double* __restrict__ zpart) {
-  __shared__ double red[4][64];
-  const int cb = blockIdx.x;
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  const int64_t col = int64_t(cb) * 32 + (lane & 31);
-  const bool cok = col < D;
-  const int64_t colc = cok ? col : D - 1;
+  __shared__ float tile[64][kPackLds];
+  __shared__ double red[8][128];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int64_t c0 = int64_t(blockIdx.x) * 128;
   const int64_t ks0 = int64_t(blockIdx.y) * kPackSlabs;
   const int64_t ks1 = ks0 + kPackSlabs < n_slabs ? ks0 + kPackSlabs : n_slabs;
-  double zacc = 0.0;
-  for (int64_t ks = ks0 + wv; ks < ks1; ks += 4) {
-    const int64_t r0 = ks * KB + 8 * (lane >> 5);
-    float v[8];
+  const bool vec = (D % 4 == 0) && (c0 + 128 <= D);
+  // loader role: float4 f = tid + 256 i of the tile: row tid / 32 + 8 i, columns 4 (tid % 32)
+  const int lrow = tid >> 5, lcol = (tid & 31) * 4;
+  float4 buf[8];
+  auto load = [&](int64_t ks) {
 #pragma unroll
-    for (int j = 0; j < 8; ++j) {
-      const int64_t r = r0 + j;
-      const float zl = Z[(r < M ? r : M - 1) * D + colc];
-      v[j] = (cok && r < M) ? zl : 0.0f;
+    for (int i = 0; i < 8; ++i) {
+      const int64_t r = ks * KB + lrow + 8 * i;
+      const int64_t rc = r < M ? r : M - 1;
+      const float* src = Z + rc * D + c0 + lcol;
+      float4 v;
+      if (vec) {
+        v = *reinterpret_cast<const float4*>(src);
+      } else {
+        v.x = c0 + lcol + 0 < D ? src[0] : 0.0f;
+        v.y = c0 + lcol + 1 < D ? src[1] : 0.0f;
+        v.z = c0 + lcol + 2 < D ? src[2] : 0.0f;
+        v.w = c0 + lcol + 3 < D ? src[3] : 0.0f;
+      }
+      buf[i] = r < M ? v : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
     }
-    if (y != nullptr) {
+  };
+  double zacc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (ks0 < ks1) load(ks0);
+  for (int64_t ks = ks0; ks < ks1; ks += 4) {
 #pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        const int64_t r = r0 + j;
-        const float yl = y[r < M ? r : M - 1];
-        zacc += double(v[j]) * double(r < M ? yl : 0.0f);
+    for (int i = 0; i < 8; ++i)
+      *reinterpret_cast<float4*>(&tile[lrow + 8 * i][lcol]) = buf[i];
+    __syncthreads();
+    if (ks + 4 < ks1) load(ks + 4);
+    const int64_t slab = ks + wv;
+    if (slab < ks1) {
+      const int rr = 16 * wv + 8 * (lane >> 5);
+      float yv[8];
+      if (y != nullptr) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int64_t r = slab * KB + 8 * (lane >> 5) + j;
+          const float t = y[r < M ? r : M - 1];
+          yv[j] = r < M ? t : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int c = cb * 32 + (lane & 31);
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = tile[rr + j][c];
+        if (y != nullptr) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) zacc[cb] += double(v[j]) * double(yv[j]);
+        }
+        if constexpr (MODE != kFP32) {
+          u16x8 h, l;
+#pragma unroll
+          for (int j = 0; j < 8; ++j) {
+            unsigned short a, b;
+            split<MODE>(v[j] * zscale, a, b);
+            h[j] = a;
+            l[j] = b;
+          }
+          const int64_t idx = (slab * ncb + blockIdx.x * 4 + cb) * 64 + lane;
+          hi[idx] = h;
+          if constexpr (is_hilo(MODE)) lo[idx] = l;
+        }
       }
     }
-    if constexpr (MODE != kFP32) {
-      u16x8 h, l;
-#pragma unroll
-      for (int j = 0; j < 8; ++j) {
-        unsigned short a, b;
-        split<MODE>(v[j] * zscale, a, b);
-        h[j] = a;
-        l[j] = b;
-      }
-      const int64_t idx = (ks * ncb + cb) * 64 + lane;
-      hi[idx] = h;
-      if constexpr (is_hilo(MODE)) lo[idx] = l;
-    }
+    __syncthreads();
   }
   if (y != nullptr) {
-    red[wv][lane] = zacc;
+    // partial of column 32 cb + l % 32 from wave w, half l / 32 -> red[2 w + half][col]
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) red[2 * wv + (lane >> 5)][cb * 32 + (lane & 31)] = zacc[cb];
     __syncthreads();
-    if (threadIdx.x < 32 && cok) {
+    if (tid < 128 && c0 + tid < D) {
       double t = 0.0;
 #pragma unroll
-      for (int w = 0; w < 4; ++w) t += red[w][threadIdx.x] + red[w][threadIdx.x + 32];
-      zpart[int64_t(blockIdx.y) * D + col] = t;
+      for (int p = 0; p < 8; ++p) t += red[p][tid];
+      zpart[int64_t(blockIdx.y) * D + c0 + tid] = t;
     }
   }
 }
@@ -1051,7 +1097,7 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
   u16x8* lo = reinterpret_cast<u16x8*>(w + g.zpart_bytes + kZeroBytes + g.part_bytes);
   const float zs = std::ldexp(1.0f, scale_exp);
   const float gs = std::ldexp(1.0f, -2 * scale_exp);
-  const dim3 pgrid{unsigned(g.ncb), unsigned(g.chunks)}, blk{256};
+  const dim3 pgrid{unsigned(g.ncb / 4), unsigned(g.chunks)}, blk{256};
   switch (mode) {
     case kFP32:
       if (y != nullptr)
