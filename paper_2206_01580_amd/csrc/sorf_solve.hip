@@ -65,6 +65,7 @@ struct SolveWs {
   double* y;     // [D]
   double* dx;    // [D]
   double* part;  // [nt][nt][64] partial sums of the symmetric product
+  int32_t* pflags;  // [4] strip flags of the panel kernel (epoch = block index + 1)
 };
 
 static size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
@@ -80,6 +81,8 @@ static SolveWs carve(void* ws, int32_t D) {
   w.y = reinterpret_cast<double*>(p);      p += align256(sizeof(double) * D);
   w.dx = reinterpret_cast<double*>(p);     p += align256(sizeof(double) * D);
   w.part = reinterpret_cast<double*>(p);
+  p += align256(sizeof(double) * ((size_t(D) + 63) / 64) * ((size_t(D) + 63) / 64) * 64);
+  w.pflags = reinterpret_cast<int32_t*>(p);
   return w;
 }
 
@@ -88,10 +91,11 @@ template <typename TG>
 __global__ __launch_bounds__(256) void promote_kernel(const TG* __restrict__ G, int32_t D,
                                                      double lambda, double* __restrict__ A,
                                                      int32_t* __restrict__ info,
-                                                     double* y) {
+                                                     double* y, int32_t* __restrict__ pflags) {
   const int64_t i = blockIdx.y;
   const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i == 0 && j == 0) *info = 0;
+  if (i == 0 && j < 4) pflags[j] = 0;
   if (i == 0 && j < D) signal_store(y + j, not_ready());   // output of the first forward sweep
   if (j <= i && j < D) A[i * D + j] = double(G[i * D + j]) + (i == j ? lambda : 0.0);
 }
@@ -517,23 +521,33 @@ __global__ __launch_bounds__(256) void transpose_blocks_kernel(const double* __r
 }
 
 // Panel below the diagonal block, fused with the update of the next diagonal
-// tile: workgroup b computes the 128 rows L21 = A21 (L11^{-1})^T starting at
-// k + NB + 128 b; workgroup 0, which owns the next block row, then applies
-// A[k+NB.., k+NB..] -= L21 L21^T to that 128 x 128 tile (lower part), so the
-// next diagonal block is ready for its factorisation when this kernel ends.
-// 8 waves of 32 x 64 (2 x 4 FP64 MFMA blocks). The inverse block sits in LDS;
-// each lane loads its A operands for all of K at once (four consecutive k per
-// row: the MFMA's k index t = lane / 16 stands for k = kb + 4 t + s in step
-// s, and the B operands use the same order).
+// tile: workgroup b computes the 32 rows L21 = A21 (L11^{-1})^T starting at
+// k + NB + 32 b (8 waves of 16 x 32, 1 x 2 FP64 MFMA blocks; the inverse
+// block sits in LDS; each lane loads its A operands for all of K at once,
+// four consecutive k per row: the MFMA's k index t = lane / 16 stands for
+// k = kb + 4 t + s in step s, and the B operands use the same order).
+// Workgroups 0..3 own the next block row. Each publishes its rows (agent
+// release, then flags[b] = epoch), waits for the lower-numbered ones (which
+// are dispatched first, so the waits end), and then applies
+//   A[r][c] -= sum_p L21[r][p] L21[c][p]
+// to its 32 rows r of the next diagonal tile and the columns c <= r. The
+// next diagonal block is therefore updated when the kernel ends, with the
+// tile work spread over four compute units. A wait longer than
+// kPanelWaitTicks (100 MHz counter) sets *info = -1 and stops waiting.
 constexpr int PLD = NB + 4;   // LDS row stride of the panel kernel (doubles)
+constexpr int PR = 32;        // rows per panel workgroup
+constexpr uint64_t kPanelWaitTicks = uint64_t(1) << 28;   // about 2.7 s
 
 __global__ __launch_bounds__(512) void panel_kernel(double* __restrict__ A, int32_t D, int32_t k,
-                                                   const double* __restrict__ Linv) {
+                                                   const double* __restrict__ Linv,
+                                                   int32_t* __restrict__ flags,
+                                                   int32_t* __restrict__ info) {
   __shared__ double sL[NB][PLD];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int wy = wv >> 1, wx = wv & 1;   // rows [32 wy, +32), columns [64 wx, +64)
+  const int wy = wv >> 2, wx = wv & 3;   // rows [16 wy, +16), columns [32 wx, +32)
   const int li = lane & 15, lt = lane >> 4;
-  const int64_t r0 = int64_t(k) + NB + int64_t(blockIdx.x) * NB;
+  const int b = blockIdx.x;
+  const int64_t r0 = int64_t(k) + NB + int64_t(b) * PR;
   const double* inv = Linv + int64_t(k / NB) * NB * NB;
   for (int t = tid; t < NB * NB / 2; t += 512) {
     const int j = t >> 6, p = (t & 63) * 2;
@@ -541,10 +555,9 @@ __global__ __launch_bounds__(512) void panel_kernel(double* __restrict__ A, int3
     sL[j][p] = v.x;
     sL[j][p + 1] = v.y;
   }
-  double ar[2][8][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a) {
-    const int64_t row = r0 + 32 * wy + 16 * a + li;
+  double ar[8][4];
+  {
+    const int64_t row = r0 + 16 * wy + li;
     const bool ok = row < D;
     const double* src = A + (ok ? row : int64_t(D) - 1) * D + k + 4 * lt;
 #pragma unroll
@@ -552,84 +565,94 @@ __global__ __launch_bounds__(512) void panel_kernel(double* __restrict__ A, int3
 #pragma unroll
       for (int s = 0; s < 4; ++s) {
         const double v = src[16 * kb + s];   // rows of A need not be 16-byte aligned
-        ar[a][kb][s] = ok ? v : 0.0;
+        ar[kb][s] = ok ? v : 0.0;
       }
   }
   __syncthreads();
-  f64x4 acc[2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) acc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  f64x4 acc[2];
+  acc[0] = acc[1] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll
   for (int kb = 0; kb < 8; ++kb) {
-    double br[4][4];
+    double br[2][4];
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int c = 0; c < 2; ++c)
 #pragma unroll
-      for (int s = 0; s < 4; ++s) br[b][s] = sL[64 * wx + 16 * b + li][16 * kb + 4 * lt + s];
+      for (int s = 0; s < 4; ++s) br[c][s] = sL[32 * wx + 16 * c + li][16 * kb + 4 * lt + s];
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) acc[a][b] = mfma64(ar[a][kb][s], br[b][s], acc[a][b]);
+      for (int c = 0; c < 2; ++c) acc[c] = mfma64(ar[kb][s], br[c][s], acc[c]);
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int64_t row = r0 + 32 * wy + 16 * a + lt + 4 * r;
-        if (row < D) A[row * D + k + 64 * wx + 16 * b + li] = acc[a][b][r];
-      }
-  if (blockIdx.x != 0) return;
-  // the next diagonal tile: stage L21 (this workgroup's rows) in LDS
+    for (int r = 0; r < 4; ++r) {
+      const int64_t row = r0 + 16 * wy + lt + 4 * r;
+      if (row < D) A[row * D + k + 32 * wx + 16 * c + li] = acc[c][r];
+    }
+  if (b >= NB / PR) return;
+  // publish this strip of the next block row
+  const int32_t epoch = k / NB + 1;
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
   __syncthreads();
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 32 * wy + 16 * a + lt + 4 * r;
-        sL[i][64 * wx + 16 * b + li] = r0 + i < D ? acc[a][b][r] : 0.0;
+  if (tid == 0) __hip_atomic_store(flags + b, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  // wait for the strips above it
+  if (tid == 0) {
+    const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+    for (int q = 0; q < b; ++q) {
+      while (__hip_atomic_load(flags + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < epoch) {
+        if (__builtin_amdgcn_s_memrealtime() - t0 > kPanelWaitTicks) {
+          int32_t expect = 0;
+          __hip_atomic_compare_exchange_strong(info, &expect, -1, __ATOMIC_RELAXED,
+                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+          break;
+        }
+        __builtin_amdgcn_s_sleep(1);
       }
+    }
+  }
   __syncthreads();
-  if (32 * wy + 31 < 64 * wx) return;   // block entirely above the diagonal
-  f64x4 cc[2][4];
-#pragma unroll
-  for (int a = 0; a < 2; ++a)
-#pragma unroll
-    for (int b = 0; b < 4; ++b) cc[a][b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  // rows 0 .. 32 (b + 1) - 1 of the next block row of L, into LDS
+  const int nrow = PR * (b + 1);
+  const int64_t rb = int64_t(k) + NB;
+  for (int t = tid; t < nrow * (NB / 2); t += 512) {
+    const int i = t >> 6, p = (t & 63) * 2;
+    const int64_t row = rb + i;
+    const bool ok = row < D;
+    const double* src = A + (ok ? row : int64_t(D) - 1) * D + k + p;
+    const double v0 = src[0], v1 = src[1];
+    sL[i][p] = ok ? v0 : 0.0;
+    sL[i][p + 1] = ok ? v1 : 0.0;
+  }
+  __syncthreads();
+  // rows 32 b + 16 wy + [0, 16), columns 32 wx + [0, 32): only blocks that reach the lower part
+  const int ib = PR * b + 16 * wy;
+  if (32 * wx > ib + 15) return;
+  f64x4 cc[2];
+  cc[0] = cc[1] = f64x4{0.0, 0.0, 0.0, 0.0};
 #pragma unroll 2
   for (int kb = 0; kb < 8; ++kb) {
-    double pa[2][4], pb[4][4];
+    double pa[4], pb[2][4];
 #pragma unroll
     for (int s = 0; s < 4; ++s) {
+      pa[s] = sL[ib + li][16 * kb + 4 * lt + s];
 #pragma unroll
-      for (int a = 0; a < 2; ++a) pa[a][s] = sL[32 * wy + 16 * a + li][16 * kb + 4 * lt + s];
-#pragma unroll
-      for (int b = 0; b < 4; ++b) pb[b][s] = sL[64 * wx + 16 * b + li][16 * kb + 4 * lt + s];
+      for (int c = 0; c < 2; ++c) pb[c][s] = sL[32 * wx + 16 * c + li][16 * kb + 4 * lt + s];
     }
 #pragma unroll
     for (int s = 0; s < 4; ++s)
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
-#pragma unroll
-        for (int b = 0; b < 4; ++b) cc[a][b] = mfma64(pa[a][s], pb[b][s], cc[a][b]);
+      for (int c = 0; c < 2; ++c) cc[c] = mfma64(pa[s], pb[c][s], cc[c]);
   }
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+  for (int c = 0; c < 2; ++c)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
-#pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int i = 32 * wy + 16 * a + lt + 4 * r, j = 64 * wx + 16 * b + li;
-        const int64_t gi = r0 + i, gj = r0 + j;
-        if (gi < D && i >= j) A[gi * D + gj] -= cc[a][b][r];
-      }
+    for (int r = 0; r < 4; ++r) {
+      const int i = ib + lt + 4 * r, j = 32 * wx + 16 * c + li;
+      const int64_t gi = rb + i, gj = rb + j;
+      if (gi < D && i >= j) A[gi * D + gj] -= cc[c][r];
+    }
 }
 
 // Trailing update A22 -= L21 L21^T on the lower triangle: 128 x 128 tiles,
@@ -1038,7 +1061,7 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
   const SolveWs w = carve(ws, D);
   const unsigned vg = unsigned((D + 255) / 256);
   hipLaunchKernelGGL(promote_kernel<TG>, dim3(vg, unsigned(D)), dim3(256), 0, st, G, D, lambda,
-                     w.A, info, w.y);
+                     w.A, info, w.y, w.pflags);
   // Right-looking blocked Cholesky with a one-block lookahead: after the
   // panel solve of block k, the trailing tile that becomes the next diagonal
   // block is updated first; that block is then factored (one workgroup) on
@@ -1055,7 +1078,8 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
     const int64_t rest = int64_t(D) - k - NB;
     const int64_t nt = (rest + 127) / 128;
     const int64_t tiles = nt * (nt + 1) / 2;
-    hipLaunchKernelGGL(panel_kernel, dim3(unsigned(nt)), dim3(512), 0, st, w.A, D, k, w.Linv);
+    hipLaunchKernelGGL(panel_kernel, dim3(unsigned((rest + PR - 1) / PR)), dim3(512), 0, st, w.A,
+                       D, k, w.Linv, w.pflags, info);
     if (tiles > 1) {
       if ((e = hipEventRecord(ev_fork, st)) != hipSuccess) return e;
       hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, k + NB, info,
@@ -1097,7 +1121,7 @@ size_t sorf_solve_ws_bytes(int32_t D) {
   const size_t nblk = (size_t(D) + NB - 1) / NB;
   const size_t nt = (size_t(D) + 63) / 64;
   return align256(sizeof(double) * size_t(D) * D) + 2 * align256(sizeof(double) * nblk * NB * NB) +
-         3 * align256(sizeof(double) * D) + align256(sizeof(double) * nt * nt * 64);
+         3 * align256(sizeof(double) * D) + align256(sizeof(double) * nt * nt * 64) + 256;
 }
 
 hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double lambda,
