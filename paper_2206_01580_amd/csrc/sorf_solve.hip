@@ -65,8 +65,7 @@ struct SolveWs {
   double* y;     // [D]
   double* dx;    // [D]
   double* part;  // [nt][nt][64] partial sums of the symmetric product
-  int32_t* pflags;  // [4] strip flags of the panel kernel (epoch = block index + 1), then
-                    // [1] count of finished next-panel tiles of the trailing updates
+  int32_t* pflags;  // [4] strip flags of the panel kernel (epoch = block index + 1)
 };
 
 static size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
@@ -96,7 +95,7 @@ __global__ __launch_bounds__(256) void promote_kernel(const TG* __restrict__ G, 
   const int64_t i = blockIdx.y;
   const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i == 0 && j == 0) *info = 0;
-  if (i == 0 && j < 5) pflags[j] = 0;
+  if (i == 0 && j < 4) pflags[j] = 0;
   if (i == 0 && j < D) signal_store(y + j, not_ready());   // output of the first forward sweep
   if (j <= i && j < D) A[i * D + j] = double(G[i * D + j]) + (i == j ? lambda : 0.0);
 }
@@ -533,9 +532,7 @@ __global__ __launch_bounds__(256) void transpose_blocks_kernel(const double* __r
 //   A[r][c] -= sum_p L21[r][p] L21[c][p]
 // to its 32 rows r of the next diagonal tile and the columns c <= r. The
 // next diagonal block is therefore updated when the kernel ends, with the
-// tile work spread over four compute units. With need > 0 the workgroups
-// first wait until flags[4] (the count of finished next-panel tiles of the
-// trailing updates, see syrk_rest_kernel) reaches need. A wait longer than
+// tile work spread over four compute units. A wait longer than
 // kPanelWaitTicks (100 MHz counter) sets *info = -1 and stops waiting.
 constexpr int PLD = NB + 4;   // LDS row stride of the panel kernel (doubles)
 constexpr int kSyrkGrid = 248;   // 8 of the 256 compute units stay free for the chain
@@ -545,29 +542,12 @@ constexpr uint64_t kPanelWaitTicks = uint64_t(1) << 28;   // about 2.7 s
 __global__ __launch_bounds__(512) void panel_kernel(double* __restrict__ A, int32_t D, int32_t k,
                                                    int32_t wg0, const double* __restrict__ Linv,
                                                    int32_t* __restrict__ flags,
-                                                   int32_t need, int32_t* __restrict__ info) {
+                                                   int32_t* __restrict__ info) {
   __shared__ double sL[NB][PLD];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wy = wv >> 2, wx = wv & 3;   // rows [16 wy, +16), columns [32 wx, +32)
   const int li = lane & 15, lt = lane >> 4;
   const int b = int(blockIdx.x) + wg0;
-  if (need > 0) {
-    // the previous step's trailing update of the tiles this panel reads
-    if (tid == 0) {
-      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
-      while (__hip_atomic_load(flags + 4, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) < need) {
-        if (__builtin_amdgcn_s_memrealtime() - t0 > kPanelWaitTicks) {
-          int32_t expect = 0;
-          __hip_atomic_compare_exchange_strong(info, &expect, -1, __ATOMIC_RELAXED,
-                                               __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
-          break;
-        }
-        __builtin_amdgcn_s_sleep(1);
-      }
-    }
-    __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-  }
   const int64_t r0 = int64_t(k) + NB + int64_t(b) * PR;
   const double* inv = Linv + int64_t(k / NB) * NB * NB;
   for (int t = tid; t < NB * NB / 2; t += 512) {
@@ -773,39 +753,30 @@ static __device__ __forceinline__ void syrk_tile(double* __restrict__ A, int32_t
       }
 }
 
-// The trailing update outside the tile (0, 0) (which the panel kernel
-// updates), in a persistent grid of at most kSyrkGrid workgroups: item i
-// of the list [(1, 0), (2, 0), ..., (nt - 1, 0), (1, 1), then the other
-// tiles (I, J), 1 <= J <= I, in row-major order] goes to workgroup
-// i mod G. The first nt items are what the next panel reads (the first block
-// column and the next diagonal tile but one); after each of them the
-// workgroup releases its writes and adds 1 to *done, which the next panel's
-// workgroups wait for. The grid stays below the number of compute units so
-// that the panel and diagonal kernels of the next steps find free units.
-__global__ __launch_bounds__(512) void syrk_rest_kernel(double* __restrict__ A, int32_t D,
-                                                       int32_t k, int32_t nt,
-                                                       int32_t* __restrict__ done) {
+// The part of the trailing update that the next panel reads: the tiles of the
+// trailing matrix's first block column below its diagonal, (I, 0) for
+// I >= 1, and the diagonal tile (1, 1) of the block after next (the tile
+// (0, 0) is updated by the panel kernel).
+__global__ __launch_bounds__(512) void syrk_next_kernel(double* __restrict__ A, int32_t D,
+                                                       int32_t k, int32_t nt) {
   __shared__ SyrkSlab sI, sJ;
-  const int64_t n_items = int64_t(nt) + int64_t(nt - 1) * nt / 2 - 1;
-  for (int64_t i = blockIdx.x; i < n_items; i += gridDim.x) {
+  const int64_t t = blockIdx.x;
+  if (t + 1 < nt) syrk_tile(A, D, k, t + 1, 0, sI, sJ);
+  else syrk_tile(A, D, k, 1, 1, sI, sJ);
+}
+
+// The rest of the trailing update, tiles (I, J) with 1 <= J <= I other than
+// (1, 1), in a persistent grid of at most kSyrkGrid workgroups: workgroup w
+// takes the tiles w, w + G, ... of the sub-triangle's row-major order after
+// (1, 1). The grid stays below the number of compute units so that the panel
+// and diagonal kernels of the next steps find free units while it runs.
+__global__ __launch_bounds__(512) void syrk_far_kernel(double* __restrict__ A, int32_t D,
+                                                      int32_t k, int64_t n_sub) {
+  __shared__ SyrkSlab sI, sJ;
+  for (int64_t t = 1 + int64_t(blockIdx.x); t < n_sub; t += gridDim.x) {
     int64_t I, J;
-    if (i + 1 < nt) {
-      I = i + 1;
-      J = 0;
-    } else if (i + 1 == nt) {
-      I = J = 1;
-    } else {
-      tri_tile(i - nt + 1, I, J);
-      ++I;
-      ++J;
-    }
-    syrk_tile(A, D, k, I, J, sI, sJ);
-    if (i < nt) {
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-      __syncthreads();
-      if (threadIdx.x == 0)
-        __hip_atomic_fetch_add(done, 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-    }
+    tri_tile(t, I, J);
+    syrk_tile(A, D, k, I + 1, J + 1, sI, sJ);
     __syncthreads();   // the next tile reuses the LDS slabs
   }
 }
@@ -1124,50 +1095,53 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
   // Right-looking blocked Cholesky with lookahead over two streams. Caller's
   // stream (the chain of dependent steps): the panel rows of the next block
   // row, fused with the update of the next diagonal tile (4 workgroups), then
-  // the factorisation of that block. Second stream: the other panel rows and
-  // the rest of the trailing update in a persistent grid that leaves
-  // compute units free. The tiles the next panel reads come first in that
-  // grid and are counted as they finish; the next panel's workgroups wait
-  // for the count, so the chain of the following steps runs beside the far
-  // part of the update. Every tile is updated by the steps in order (the
-  // second stream runs the updates of successive steps one after another).
+  // the factorisation of that block. Second stream: the other panel rows, the
+  // trailing tiles the next panel reads (first block column and the next
+  // diagonal tile but one), then the rest of the trailing update in a
+  // persistent grid that leaves compute units free, so the chain's kernels of
+  // the following steps run beside it. The chain waits for the next-panel
+  // tiles through an event. Every tile is updated by the steps in order: the
+  // second stream runs the far update of step k before the next-panel tiles
+  // of step k + 1. Only stream events order kernels of different streams, so
+  // the schedule stays correct when a tool serialises the launches.
   hipStream_t side = nullptr;
-  hipEvent_t ev_panel = nullptr, ev_done = nullptr;
-  hipError_t e = lookahead_resources(&side, &ev_panel, &ev_done);
+  hipEvent_t ev_panel = nullptr, ev_next = nullptr;
+  hipError_t e = lookahead_resources(&side, &ev_panel, &ev_next);
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, 0, info, w.Linv,
                      w.LinvT);
-  bool side_used = false;
-  int32_t need = 0;   // next-panel tiles finished by the updates so far
   for (int32_t k = 0; k + NB < D; k += NB) {
     const int64_t rest = int64_t(D) - k - NB;
     const int64_t nt = (rest + 127) / 128;
     const int64_t nwg = (rest + PR - 1) / PR;
     const int64_t strips = nwg < NB / PR ? nwg : NB / PR;
     hipLaunchKernelGGL(panel_kernel, dim3(unsigned(strips)), dim3(512), 0, st, w.A, D, k, 0,
-                       w.Linv, w.pflags, need, info);
-    if (nwg > strips || nt > 1) {
+                       w.Linv, w.pflags, info);
+    const bool side_work = nwg > strips || nt > 1;
+    if (side_work) {
       if ((e = hipEventRecord(ev_panel, st)) != hipSuccess) return e;
       if ((e = hipStreamWaitEvent(side, ev_panel, 0)) != hipSuccess) return e;
       if (nwg > strips)
         hipLaunchKernelGGL(panel_kernel, dim3(unsigned(nwg - strips)), dim3(512), 0, side, w.A,
-                           D, k, int32_t(strips), w.Linv, w.pflags, 0, info);
-      if (nt > 1) {
-        const int64_t items = nt + (nt - 1) * nt / 2 - 1;
-        const int64_t g = items < kSyrkGrid ? items : kSyrkGrid;
-        hipLaunchKernelGGL(syrk_rest_kernel, dim3(unsigned(g)), dim3(512), 0, side, w.A, D, k,
-                           int32_t(nt), w.pflags + 4);
-        need += int32_t(nt);
+                           D, k, int32_t(strips), w.Linv, w.pflags, info);
+      if (nt > 1)
+        hipLaunchKernelGGL(syrk_next_kernel, dim3(unsigned(nt)), dim3(512), 0, side, w.A, D, k,
+                           int32_t(nt));
+      if ((e = hipEventRecord(ev_next, side)) != hipSuccess) return e;
+      const int64_t n_sub = (nt - 1) * nt / 2;   // sub-triangle from (1, 1)
+      if (n_sub > 1) {
+        const int64_t g = n_sub - 1 < kSyrkGrid ? n_sub - 1 : kSyrkGrid;
+        hipLaunchKernelGGL(syrk_far_kernel, dim3(unsigned(g)), dim3(512), 0, side, w.A, D, k,
+                           n_sub);
       }
-      side_used = true;
     }
     hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, k + NB, info,
                        w.Linv, w.LinvT);
+    if (side_work && (e = hipStreamWaitEvent(st, ev_next, 0)) != hipSuccess) return e;
   }
-  if (side_used) {
-    if ((e = hipEventRecord(ev_done, side)) != hipSuccess) return e;
-    if ((e = hipStreamWaitEvent(st, ev_done, 0)) != hipSuccess) return e;
-  }
+  // the last far update (if any) before the sweeps read L
+  if ((e = hipEventRecord(ev_next, side)) != hipSuccess) return e;
+  if ((e = hipStreamWaitEvent(st, ev_next, 0)) != hipSuccess) return e;
   hipLaunchKernelGGL(transpose_blocks_kernel, dim3(unsigned((D + NB - 1) / NB)), dim3(256), 0, st,
                      w.Linv, w.LinvT);
   e = hipGetLastError();
