@@ -276,9 +276,12 @@ __device__ __forceinline__ void stage_barrier() {
 // ------------------------------------------------------ 16-bit modes (packed)
 // Stage = 2 slabs (32 rows): 16 A fragments (rows 256 I .. +255 of G) and 8 B
 // fragments per part, copied into a ring of NS stages; wave w copies the
-// fragments w, w + 4, ... of each part.
+// fragments w, w + 8, ... of each part. Eight waves (4 x 2), two per SIMD,
+// each owning 64 x 64 of the 256 x 128 tile: while one wave of a SIMD waits
+// on a barrier, a copy or LDS, the other keeps the matrix core busy.
+constexpr int kPackedWaves = 8;
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(64 * kPackedWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ lo,
                         int64_t n_slabs, int32_t ncb, int32_t D, int64_t n_tiles, int64_t nI,
                         int64_t nJ, float gscale, float* __restrict__ G) {
@@ -287,7 +290,10 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
   constexpr int AF = 2 * (TM / 32);           // A fragments per stage
   constexpr int BF = 2 * (TN / 32);           // B fragments per stage
   constexpr int NF = AF + BF;
-  constexpr int FW = NF / 4;                  // fragments per wave per part
+  constexpr int NW = kPackedWaves;
+  constexpr int WR = TM / (NW / 2), WC = TN / 2;   // wave tile: 64 x 64
+  constexpr int BA = WR / 32, BB = WC / 32;        // 32 x 32 blocks per wave
+  constexpr int FW = NF / NW;                 // fragments per wave per part
   constexpr int PW = NP * FW;                 // copies per wave per stage
   constexpr int NS = HILO ? 3 : 4;            // ring depth (stages)
   constexpr int KC = kFlushRows / (2 * KB);   // stages per flush
@@ -300,12 +306,12 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int wy = wv >> 1, wx = wv & 1;
-  const bool active = I * TM + wy * 128 + 127 >= J * TN + wx * 64;
+  const bool active = I * TM + wy * WR + WR - 1 >= J * TN + wx * WC;
 
   int64_t src[FW];
 #pragma unroll
   for (int c = 0; c < FW; ++c) {
-    const int f = wv + 4 * c;
+    const int f = wv + NW * c;
     const int slab = f < AF ? f / (TM / 32) : (f - AF) / (TN / 32);
     const int64_t cbf = f < AF ? I * (TM / 32) + f % (TM / 32) : J * (TN / 32) + (f - AF) % (TN / 32);
     src[c] = (int64_t(slab) * ncb + cbf) * 64 + lane;
@@ -316,16 +322,16 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
     const int64_t off = st * stage_stride;
 #pragma unroll
     for (int c = 0; c < FW; ++c) {
-      dma16(hi + src[c] + off, &ring[slot][0][wv + 4 * c][0]);
-      if constexpr (HILO) dma16(lo + src[c] + off, &ring[slot][NP - 1][wv + 4 * c][0]);
+      dma16(hi + src[c] + off, &ring[slot][0][wv + NW * c][0]);
+      if constexpr (HILO) dma16(lo + src[c] + off, &ring[slot][NP - 1][wv + NW * c][0]);
     }
   };
 
-  f32x16 P[4][2], S[4][2];
+  f32x16 P[BA][BB], S[BA][BB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < BA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         P[a][b][r] = 0.0f;
@@ -340,26 +346,26 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
   // while the products of the previous half-stage run; all NS slots are
   // filled up front and the slot of stage s takes stage s + NS after the
   // barrier that publishes stage s + 1.
-  u16x8 ah0[4], al0[4], bh0[2], bl0[2], ah1[4], al1[4], bh1[2], bl1[2];
-  auto read_half = [&](int sl, int kk, u16x8 (&ah)[4], u16x8 (&al)[4], u16x8 (&bh)[2],
-                       u16x8 (&bl)[2]) {
+  u16x8 ah0[BA], al0[BA], bh0[BB], bl0[BB], ah1[BA], al1[BA], bh1[BB], bl1[BB];
+  auto read_half = [&](int sl, int kk, u16x8 (&ah)[BA], u16x8 (&al)[BA], u16x8 (&bh)[BB],
+                       u16x8 (&bl)[BB]) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a) {
-      ah[a] = ring[sl][0][kk * (TM / 32) + wy * 4 + a][lane];
-      if constexpr (HILO) al[a] = ring[sl][NP - 1][kk * (TM / 32) + wy * 4 + a][lane];
+    for (int a = 0; a < BA; ++a) {
+      ah[a] = ring[sl][0][kk * (TM / 32) + wy * BA + a][lane];
+      if constexpr (HILO) al[a] = ring[sl][NP - 1][kk * (TM / 32) + wy * BA + a][lane];
     }
 #pragma unroll
-    for (int b = 0; b < 2; ++b) {
-      bh[b] = ring[sl][0][AF + kk * (TN / 32) + wx * 2 + b][lane];
-      if constexpr (HILO) bl[b] = ring[sl][NP - 1][AF + kk * (TN / 32) + wx * 2 + b][lane];
+    for (int b = 0; b < BB; ++b) {
+      bh[b] = ring[sl][0][AF + kk * (TN / 32) + wx * BB + b][lane];
+      if constexpr (HILO) bl[b] = ring[sl][NP - 1][AF + kk * (TN / 32) + wx * BB + b][lane];
     }
   };
-  auto mma_half = [&](const u16x8 (&ah)[4], const u16x8 (&al)[4], const u16x8 (&bh)[2],
-                      const u16x8 (&bl)[2]) {
+  auto mma_half = [&](const u16x8 (&ah)[BA], const u16x8 (&al)[BA], const u16x8 (&bh)[BB],
+                      const u16x8 (&bl)[BB]) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < BA; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < BB; ++b) {
         P[a][b] = mma16<MODE>(ah[a], bh[b], P[a][b]);
         if constexpr (HILO) {
           P[a][b] = mma16<MODE>(ah[a], bl[b], P[a][b]);
@@ -370,7 +376,7 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
   };
   // the next half-stage's LDS reads interleaved with the first products
   auto interleave = [] {
-    constexpr int NR = 6 * NP, NM = 8 * (HILO ? 4 : 1);
+    constexpr int NR = (BA + BB) * NP, NM = BA * BB * (HILO ? 4 : 1);
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -380,9 +386,9 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
   };
   auto flush = [&] {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < BA; ++a)
 #pragma unroll
-      for (int b = 0; b < 2; ++b)
+      for (int b = 0; b < BB; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           S[a][b][r] += P[a][b][r];
@@ -429,13 +435,13 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
 
   if (!active) return;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < BA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int64_t gi = I * TM + wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t gj = J * TN + wx * 64 + b * 32 + (lane & 31);
+        const int64_t gi = I * TM + wy * WR + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t gj = J * TN + wx * WC + b * 32 + (lane & 31);
         if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += S[a][b][r] * gscale;
       }
 }
@@ -1170,12 +1176,12 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
       break;
     }
     case kBF16HiLo:
-      hipLaunchKernelGGL(gram_packed_kernel<kBF16HiLo>, grid, blk, 0, st, hi, lo, g.n_slabs,
-                         g.ncb, D, n_tiles, nI, nJ, gs, G);
+      hipLaunchKernelGGL(gram_packed_kernel<kBF16HiLo>, grid, dim3(64 * kPackedWaves), 0, st, hi,
+                         lo, g.n_slabs, g.ncb, D, n_tiles, nI, nJ, gs, G);
       break;
     case kFP16HiLo:
-      hipLaunchKernelGGL(gram_packed_kernel<kFP16HiLo>, grid, blk, 0, st, hi, lo, g.n_slabs,
-                         g.ncb, D, n_tiles, nI, nJ, gs, G);
+      hipLaunchKernelGGL(gram_packed_kernel<kFP16HiLo>, grid, dim3(64 * kPackedWaves), 0, st, hi,
+                         lo, g.n_slabs, g.ncb, D, n_tiles, nI, nJ, gs, G);
       break;
   }
   return hipGetLastError();
