@@ -71,12 +71,18 @@ __global__ __launch_bounds__(256) void forward_kernel(
       apply_signs<EPL>(v, w);
       fwht<LOGK, EPL>(v, q);
     }
-    float b[EPL];
-    load_vec<EPL>(b, bias + int64_t(e) * Dtot + int64_t(s) * DV + q * EPL);
+    // bias in chunks of (at most) 8 entries, so that few of them are live at once
+    constexpr int CH = EPL < 8 ? EPL : 8;
+    const float* bp = bias + int64_t(e) * Dtot + int64_t(s) * DV + q * EPL;
 #pragma unroll
-    for (int r = 0; r < EPL; ++r) {
-      const float u = __builtin_fmaf(v[r], c_lane, b[r] * kInv2Pi);  // phase in revolutions
-      acc[r] += __builtin_amdgcn_cosf(u);
+    for (int r0 = 0; r0 < EPL; r0 += CH) {
+      float b[CH];
+      load_vec<CH>(b, bp + r0);
+#pragma unroll
+      for (int r = 0; r < CH; ++r) {
+        const float u = __builtin_fmaf(v[r0 + r], c_lane, b[r] * kInv2Pi);  // phase in revolutions
+        acc[r0 + r] += __builtin_amdgcn_cosf(u);
+      }
     }
   }
   if constexpr (DOT) {
@@ -139,8 +145,10 @@ __global__ __launch_bounds__(256) void atom_adjoint_kernel(
   const float c_lane = odd ? -c_rev : c_rev;
   const int64_t tstride = int64_t(S) * W;
 
-  float xin[EPL];
-  load_vec<EPL>(xin, x + a * DV + q * EPL);
+  // x is re-read (from cache) for every stack pass rather than held: with
+  // the gradient sums live, fewer registers per lane let more waves share a
+  // SIMD
+  const float* xrow = x + a * DV + q * EPL;
 
   float gacc[EPL];
 #pragma unroll
@@ -151,8 +159,7 @@ __global__ __launch_bounds__(256) void atom_adjoint_kernel(
     const int32_t s = s0 + int32_t(grp);
     if (s < S) {
       float v[EPL];
-#pragma unroll
-      for (int r = 0; r < EPL; ++r) v[r] = xin[r];
+      load_vec<EPL>(v, xrow);
       const uint32_t* sv = signs + (int64_t(e) * T * S + s) * W;
       for (int t = 0; t < T; ++t) {
         uint32_t w[LW];
@@ -160,14 +167,22 @@ __global__ __launch_bounds__(256) void atom_adjoint_kernel(
         apply_signs<EPL>(v, w);
         fwht<LOGK, EPL>(v, q);
       }
-      float b[EPL], al[EPL];
-      load_vec<EPL>(b, bias + int64_t(e) * Dtot + int64_t(s) * DV + q * EPL);
-      load_vec<EPL>(al, alpha + int64_t(s) * DV + q * EPL);
+      // bias and alpha in chunks of (at most) 8 entries, so that few of them
+      // are live at once
+      constexpr int CH = EPL < 8 ? EPL : 8;
+      const float* bp = bias + int64_t(e) * Dtot + int64_t(s) * DV + q * EPL;
+      const float* ap = alpha + int64_t(s) * DV + q * EPL;
 #pragma unroll
-      for (int r = 0; r < EPL; ++r) {
-        const float u = __builtin_fmaf(v[r], c_lane, b[r] * kInv2Pi);
-        if constexpr (WANT_E) eacc = __builtin_fmaf(al[r], __builtin_amdgcn_cosf(u), eacc);
-        if constexpr (WANT_G) v[r] = al[r] * __builtin_amdgcn_sinf(u);
+      for (int r0 = 0; r0 < EPL; r0 += CH) {
+        float b[CH], al[CH];
+        load_vec<CH>(b, bp + r0);
+        load_vec<CH>(al, ap + r0);
+#pragma unroll
+        for (int r = 0; r < CH; ++r) {
+          const float u = __builtin_fmaf(v[r0 + r], c_lane, b[r] * kInv2Pi);
+          if constexpr (WANT_E) eacc = __builtin_fmaf(al[r], __builtin_amdgcn_cosf(u), eacc);
+          if constexpr (WANT_G) v[r0 + r] = al[r] * __builtin_amdgcn_sinf(u);
+        }
       }
       if constexpr (WANT_G) {
         // transposed chain: H first, then D_{T-1}, ..., H, then D_0
