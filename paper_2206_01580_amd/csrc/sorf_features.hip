@@ -27,7 +27,7 @@ namespace sorf {
 // share of the molecule's energy, part[m S + s] = sum_f alpha_f z_f over the
 // stack's features, summed over the group's lanes in a fixed order.
 template <int LOG_D, int LOG_EPL, bool DOT>
-__global__ __launch_bounds__(256) void forward_kernel(
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void forward_kernel(
     const float* __restrict__ x, const int32_t* __restrict__ element,
     const int64_t* __restrict__ mol_ptr, const uint32_t* __restrict__ signs,
     const float* __restrict__ bias, float* __restrict__ Z, const float* __restrict__ alpha,
@@ -60,16 +60,25 @@ __global__ __launch_bounds__(256) void forward_kernel(
 #pragma unroll
   for (int r = 0; r < EPL; ++r) acc[r] = 0.0f;
 
+  // the next atom's element is read one atom ahead, and all T sign words of
+  // an atom are requested before its first transform
+  int32_t e_next = a0 < a1 ? element[a0] : 0;
   for (int64_t a = a0; a < a1; ++a) {
-    const int32_t e = element[a];
+    const int32_t e = e_next;
+    if (a + 1 < a1) e_next = element[a + 1];
     float v[EPL];
     load_vec<EPL>(v, x + a * DV + q * EPL);
     const uint32_t* sv = signs + (int64_t(e) * T * S + s) * W;
-    for (int t = 0; t < T; ++t) {
-      uint32_t w[LW];
-      load_sign_words<EPL>(w, sv + t * tstride, q, t > 0 ? flip : 0u);
-      apply_signs<EPL>(v, w);
-      fwht<LOGK, EPL>(v, q);
+    uint32_t w[3][LW];
+#pragma unroll
+    for (int t = 0; t < 3; ++t)
+      if (t < T) load_sign_words<EPL>(w[t], sv + t * tstride, q, t > 0 ? flip : 0u);
+#pragma unroll
+    for (int t = 0; t < 3; ++t) {
+      if (t < T) {
+        apply_signs<EPL>(v, w[t]);
+        fwht<LOGK, EPL>(v, q);
+      }
     }
     // bias in chunks of (at most) 8 entries, so that few of them are live at once
     constexpr int CH = EPL < 8 ? EPL : 8;
