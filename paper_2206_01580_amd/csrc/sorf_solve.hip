@@ -980,60 +980,103 @@ __global__ __launch_bounds__(512) void sweep_bwd_kernel(const double* __restrict
 
 // Partial sums of (lower-stored symmetric G) x over 64 x 64 tiles:
 // part[X][Y][.] = contribution to rows of block X from the tile pairing X and Y.
+// Thread t holds 4 x 4 entries of the tile (rows t / 16 + 16 m, columns
+// 4 (t % 16) + c); row sums reduce over the 16 lanes of a row group, column
+// sums over the 4 row groups of a wave and then the 4 waves, all in a fixed
+// order.
 template <typename TG>
 __global__ __launch_bounds__(256) void symv_tiles_kernel(const TG* __restrict__ G, int32_t D,
                                                         const double* __restrict__ x,
                                                         double* __restrict__ part) {
-  __shared__ double T[64][65];
-  __shared__ double xi[64], xj[64];
+  __shared__ double csum[4][64];
+  __shared__ double rsum[64];
   int64_t I, J;
   tri_tile(blockIdx.x, I, J);
   const int64_t nt = (int64_t(D) + 63) / 64;
   const int64_t I0 = I * 64, J0 = J * 64;
-  const int tid = threadIdx.x;
-  for (int t = tid; t < 64 * 64; t += 256) {
-    const int i = t / 64, j = t % 64;
-    const int64_t gi = I0 + i, gj = J0 + j;
-    T[i][j] = (gi < D && gj < D && gj <= gi) ? double(G[gi * D + gj]) : 0.0;
+  const bool diag = I == J;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int c0 = 4 * (tid & 15), r0 = tid >> 4;   // rows r0 + 16 m
+  double g[4][4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int64_t gi = I0 + r0 + 16 * m;
+    const int64_t gic = gi < D ? gi : int64_t(D) - 1;
+#pragma unroll
+    for (int c = 0; c < 4; ++c) {
+      const int64_t gj = J0 + c0 + c;
+      const TG v = G[gic * D + (gj < D ? gj : int64_t(D) - 1)];
+      g[m][c] = (gi < D && gj < D && gj <= gi) ? double(v) : 0.0;
+    }
   }
-  if (tid < 64) {
-    xi[tid] = (I0 + tid < D) ? x[I0 + tid] : 0.0;
-    xj[tid] = (J0 + tid < D) ? x[J0 + tid] : 0.0;
+  double xj[4], xi[4];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) xj[c] = J0 + c0 + c < D ? x[J0 + c0 + c] : 0.0;
+#pragma unroll
+  for (int m = 0; m < 4; ++m) xi[m] = I0 + r0 + 16 * m < D ? x[I0 + r0 + 16 * m] : 0.0;
+  // rows: G x over this tile's columns; columns: G^T x over its rows (strictly
+  // below the diagonal on a diagonal tile, where the row sums already hold it)
+  double rs[4], cs[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) rs[m] = ((g[m][0] * xj[0] + g[m][1] * xj[1]) + g[m][2] * xj[2]) + g[m][3] * xj[3];
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    cs[c] = 0.0;
+#pragma unroll
+    for (int m = 0; m < 4; ++m) {
+      const bool strict = !diag || (r0 + 16 * m > c0 + c);
+      cs[c] += strict ? g[m][c] * xi[m] : 0.0;
+    }
+  }
+#pragma unroll
+  for (int m = 0; m < 4; ++m)
+#pragma unroll
+    for (int o = 1; o < 16; o <<= 1) rs[m] += __shfl_xor(rs[m], o);
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    cs[c] += __shfl_xor(cs[c], 16);
+    cs[c] += __shfl_xor(cs[c], 32);
+  }
+  if ((tid & 15) == 0) {
+#pragma unroll
+    for (int m = 0; m < 4; ++m) rsum[r0 + 16 * m] = rs[m];
+  }
+  if (lane < 16) {
+#pragma unroll
+    for (int c = 0; c < 4; ++c) csum[wv][c0 + c] = cs[c];
   }
   __syncthreads();
-  if (I != J) {
-    if (tid < 64) {
-      double s = 0.0;
-      for (int j = 0; j < 64; ++j) s += T[tid][j] * xj[j];
-      part[(I * nt + J) * 64 + tid] = s;
-    } else if (tid < 128) {
-      const int j = tid - 64;
-      double s = 0.0;
-      for (int i = 0; i < 64; ++i) s += T[i][j] * xi[i];
-      part[(J * nt + I) * 64 + j] = s;
+  if (tid < 64) {
+    const double col = (csum[0][tid] + csum[1][tid]) + (csum[2][tid] + csum[3][tid]);
+    if (diag) {
+      part[(I * nt + I) * 64 + tid] = rsum[tid] + col;
+    } else {
+      part[(I * nt + J) * 64 + tid] = rsum[tid];
+      part[(J * nt + I) * 64 + tid] = col;
     }
-  } else if (tid < 64) {
-    const int i = tid;
-    double s = 0.0;
-    for (int j = 0; j <= i; ++j) s += T[i][j] * xi[j];
-    for (int j = i + 1; j < 64; ++j) s += T[j][i] * xi[j];
-    part[(I * nt + I) * 64 + i] = s;
   }
 }
 
-// r = Zty - lambda x - sum_Y part[X][Y] (fixed order)
+// r = Zty - lambda x - sum_Y part[X][Y]: one workgroup per 64-row block X;
+// thread (i, q) sums Y in [q nt / 4, (q + 1) nt / 4) in order and the four
+// quarters are added in a fixed order.
 template <typename TG>
 __global__ __launch_bounds__(256) void residual_kernel(const double* __restrict__ part, int32_t D,
                                                       double lambda, const TG* __restrict__ rhs,
                                                       const double* __restrict__ x,
                                                       double* __restrict__ r) {
-  const int64_t i = int64_t(blockIdx.x) * 256 + threadIdx.x;
-  if (i >= D) return;
+  __shared__ double qs[4][64];
   const int64_t nt = (int64_t(D) + 63) / 64;
-  const int64_t X = i / 64;
+  const int64_t X = blockIdx.x;
+  const int i = threadIdx.x & 63, q = threadIdx.x >> 6;
+  const int64_t y0 = nt * q / 4, y1 = nt * (q + 1) / 4;
   double s = 0.0;
-  for (int64_t Y = 0; Y < nt; ++Y) s += part[(X * nt + Y) * 64 + (i & 63)];
-  r[i] = (double(rhs[i]) - lambda * x[i]) - s;
+  for (int64_t Y = y0; Y < y1; ++Y) s += part[(X * nt + Y) * 64 + i];
+  qs[q][i] = s;
+  __syncthreads();
+  const int64_t gi = X * 64 + i;
+  if (q == 0 && gi < D)
+    r[gi] = (double(rhs[gi]) - lambda * x[gi]) - ((qs[0][i] + qs[1][i]) + (qs[2][i] + qs[3][i]));
 }
 
 template <typename TG>
@@ -1153,8 +1196,8 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
   for (int32_t it = 0; it < n_refine; ++it) {
     hipLaunchKernelGGL(symv_tiles_kernel<TG>, dim3(unsigned(nt * (nt + 1) / 2)), dim3(256), 0, st,
                        G, D, alpha, w.part);
-    hipLaunchKernelGGL(residual_kernel<TG>, dim3(vg), dim3(256), 0, st, w.part, D, lambda, Zty,
-                       alpha, w.b);
+    hipLaunchKernelGGL(residual_kernel<TG>, dim3(unsigned(nt)), dim3(256), 0, st, w.part, D,
+                       lambda, Zty, alpha, w.b);
     e = solve_triangular(w, D, w.b, w.y, w.dx, info, st);
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(axpy_kernel, dim3(vg), dim3(256), 0, st, alpha, w.dx, D);
