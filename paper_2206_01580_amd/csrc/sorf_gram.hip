@@ -447,9 +447,10 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
 }
 
 // ------------------------------------------ 16-bit single-product modes
-// One workgroup (4 waves, 2 x 2) per 256 x 256 square tile of the lower
-// triangle; each wave owns 128 x 128 (4 x 4 blocks of 32 x 32), which halves
-// the LDS bytes per product against the 128 x 64 waves of the hi+lo kernel.
+// One workgroup (8 waves, 2 x 4, two per SIMD) per 256 x 256 square tile of
+// the lower triangle; each wave owns 128 x 64 (4 x 2 blocks of 32 x 32), so
+// while one wave of a SIMD waits on a barrier or a copy the other keeps the
+// matrix core busy.
 // A launch covers at most kX1LaunchStages stages (32 rows each) and adds its
 // tiles to G, so the matrix-core accumulators never run over more rows than
 // that: a single accumulator over a long row range drifts enough to make
@@ -466,6 +467,7 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
 // its L2) followed by a contiguous run of slices.
 constexpr int TX = 256;        // square tile of the single-product kernel
 constexpr int kX1Slots = 256;  // concurrent workgroups: one per CU of the chip
+constexpr int kX1Waves = 8;    // 2 x 4 waves of 128 x 64, two per SIMD
 constexpr int64_t kX1LaunchStages = 256;   // 8192 rows per launch
 
 __host__ __device__ inline int64_t x1_tiles(int64_t D) {
@@ -498,13 +500,15 @@ __host__ __device__ inline void x1_xcd_items(const X1Plan& p, int x, int64_t& w0
 }
 
 template <int MODE>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+__global__ __launch_bounds__(64 * kX1Waves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_count,
                     int32_t ncb, int32_t D, X1Plan plan, float gscale, float* __restrict__ G,
                     float* __restrict__ part) {
   constexpr int AF = 2 * (TX / 32);   // A fragments per stage (2 slabs)
   constexpr int NF = 2 * AF;          // A and B
-  constexpr int FW = NF / 4;          // copies per wave per stage
+  constexpr int NW = kX1Waves;
+  constexpr int BA = 4, BB = 2;       // 32 x 32 blocks per wave: 128 x 64
+  constexpr int FW = NF / NW;         // copies per wave per stage
   constexpr int NS = 4;
   __shared__ u16x8 ring[NS][NF][64];
 
@@ -524,8 +528,8 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int wy = wv >> 1, wx = wv & 1;
-  const bool active = I * TX + wy * 128 + 127 >= J * TX + wx * 128;
+  const int wy = wv >> 2, wx = wv & 3;   // rows [128 wy, +128), columns [64 wx, +64)
+  const bool active = I * TX + wy * 128 + 127 >= J * TX + wx * 64;
 
   // the slice of 2-slab stages this item accumulates
   const int64_t s0 = st_begin + st_count * sp / n_split;
@@ -534,7 +538,7 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   int64_t src[FW];
 #pragma unroll
   for (int c = 0; c < FW; ++c) {
-    const int f = wv + 4 * c;
+    const int f = wv + NW * c;
     const int slab = (f % AF) / (TX / 32);
     const int64_t cbf = (f < AF ? I : J) * (TX / 32) + (f % AF) % (TX / 32);
     src[c] = ((2 * s0 + slab) * int64_t(ncb) + cbf) * 64 + lane;
@@ -543,14 +547,14 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   auto issue = [&](int64_t st, int slot) {
     const int64_t off = st * stage_stride;
 #pragma unroll
-    for (int c = 0; c < FW; ++c) dma16(hi + src[c] + off, &ring[slot][wv + 4 * c][0]);
+    for (int c = 0; c < FW; ++c) dma16(hi + src[c] + off, &ring[slot][wv + NW * c][0]);
   };
 
-  f32x16 P[4][4];
+  f32x16 P[BA][BB];
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < BA; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < BB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) P[a][b][r] = 0.0f;
 
@@ -558,28 +562,27 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   // read from LDS while the MFMAs of the previous half-stage run. All NS
   // slots are filled up front; after the barrier that publishes stage st + 1
   // every wave has read all of stage st, so its slot takes stage st + NS.
-  u16x8 a0[4], b0[4], a1[4], b1[4];
-  auto read_half = [&](int slot, int kk, u16x8 (&af)[4], u16x8 (&bf)[4]) {
+  u16x8 a0[BA], b0[BB], a1[BA], b1[BB];
+  auto read_half = [&](int slot, int kk, u16x8 (&af)[BA], u16x8 (&bf)[BB]) {
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      af[q] = ring[slot][kk * (TX / 32) + wy * 4 + q][lane];
-      bf[q] = ring[slot][AF + kk * (TX / 32) + wx * 4 + q][lane];
-    }
+    for (int q = 0; q < BA; ++q) af[q] = ring[slot][kk * (TX / 32) + wy * BA + q][lane];
+#pragma unroll
+    for (int q = 0; q < BB; ++q) bf[q] = ring[slot][AF + kk * (TX / 32) + wx * BB + q][lane];
   };
-  auto mma_half = [&](const u16x8 (&af)[4], const u16x8 (&bf)[4]) {
+  auto mma_half = [&](const u16x8 (&af)[BA], const u16x8 (&bf)[BB]) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < BA; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b) P[a][b] = mma16<MODE>(af[a], bf[b], P[a][b]);
+      for (int b = 0; b < BB; ++b) P[a][b] = mma16<MODE>(af[a], bf[b], P[a][b]);
   };
-  // 8 LDS reads interleaved with the first 8 of 16 MFMAs
+  // the next half-stage's 6 LDS reads interleaved with the first 6 of 8 MFMAs
   auto interleave = [] {
 #pragma unroll
-    for (int i = 0; i < 8; ++i) {
+    for (int i = 0; i < BA + BB; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, 8, 0);
+    __builtin_amdgcn_sched_group_barrier(0x008, BA * BB - (BA + BB), 0);
   };
 
 #pragma unroll
@@ -616,26 +619,26 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   if (!active) return;
   if (whole) {
 #pragma unroll
-    for (int a = 0; a < 4; ++a)
+    for (int a = 0; a < BA; ++a)
 #pragma unroll
-      for (int b = 0; b < 4; ++b)
+      for (int b = 0; b < BB; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
           const int64_t gi = I * TX + wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          const int64_t gj = J * TX + wx * 128 + b * 32 + (lane & 31);
+          const int64_t gj = J * TX + wx * 64 + b * 32 + (lane & 31);
           if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += P[a][b][r] * gscale;
         }
     return;
   }
   float* out = part + (int64_t(sp) * n_tail + (t - plan.n_whole)) * TX * TX;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < BA; ++a)
 #pragma unroll
-    for (int b = 0; b < 4; ++b)
+    for (int b = 0; b < BB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         const int i = wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int j = wx * 128 + b * 32 + (lane & 31);
+        const int j = wx * 64 + b * 32 + (lane & 31);
         out[i * TX + j] = P[a][b][r];
       }
 }
@@ -1161,11 +1164,11 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
         const X1Plan plan = x1_plan(D, cnt);
         const dim3 xg{unsigned(x1_grid(plan))};
         if (mode == kBF16)
-          hipLaunchKernelGGL(gram_x1_kernel<kBF16>, xg, blk, 0, st, hi, s0, cnt, g.ncb, D, plan,
-                             gs, G, part);
+          hipLaunchKernelGGL(gram_x1_kernel<kBF16>, xg, dim3(64 * kX1Waves), 0, st, hi, s0, cnt,
+                             g.ncb, D, plan, gs, G, part);
         else
-          hipLaunchKernelGGL(gram_x1_kernel<kFP16>, xg, blk, 0, st, hi, s0, cnt, g.ncb, D, plan,
-                             gs, G, part);
+          hipLaunchKernelGGL(gram_x1_kernel<kFP16>, xg, dim3(64 * kX1Waves), 0, st, hi, s0, cnt,
+                             g.ncb, D, plan, gs, G, part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (plan.n_split > 1) {
           const dim3 cg{unsigned(plan.n_tiles - plan.n_whole), unsigned(TX / 4)};
