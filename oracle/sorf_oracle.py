@@ -20,6 +20,9 @@ Paper passages followed (arXiv 2206.01580, Theory section):
 * RFF subsection, regularised normal equation: (Z^T Z + lambda I) alpha = Z^T E.
 * RFF subsection, force derivatives dZ (derivative features); forces are the
   negative coordinate gradient of the energy.
+* RFF subsection, force-trained normal equation:
+  ((Z, dZ)^T (Z, dZ) + lambda I) alpha = (Z, dZ)^T (E, F), dZ with one row
+  per atomic coordinate (3 N_atom rows).
 * SORF subsection, W_ORF ~ (sqrt(d)/sigma) [H_i D_i]_{N_transform}; the
   Sylvester recursion for H; stacking of N_F/d independent blocks.
 
@@ -36,6 +39,8 @@ design notes of the repository):
 * No intercept; lambda is added to the diagonal unscaled.
 * Forces F = -dE/dr; with Jacobian blocks J_i = dx_i/dr (d x 3N) this is
   F = -sum_i J_i^T (dE/dx_i).
+* The rows of dZ hold the NEGATIVE coordinate derivatives of Z, so that
+  dZ alpha = F and the stacked system pairs dZ with F as printed.
 
 Pins: each function is checked in ``tests/test_oracle_pins.py`` against
 closed forms, invariants, exact enumeration, brute force and independent
@@ -51,7 +56,7 @@ import scipy.linalg
 __all__ = [
     "hadamard", "sorf_scale", "dense_block", "dense_w", "phases", "atom_features",
     "molecule_features", "gram", "solve", "predict_energies", "grad_x", "forces",
-    "round_bf16", "round_fp16", "split_hilo", "gram_emulated",
+    "derivative_features", "force_normal_equations", "round_bf16", "round_fp16", "split_hilo", "gram_emulated",
 ]
 
 
@@ -229,6 +234,58 @@ def forces(grad, J, J_ptr, mol_ptr) -> np.ndarray:
         blk = np.asarray(J[J_ptr[m]:J_ptr[m + 1]], dtype=np.float64).reshape(n, d, 3 * n)
         F[3 * a0:3 * a1] = -np.einsum("ijk,ij->k", blk, grad[a0:a1])
     return F
+
+
+def derivative_features(x, element, mol_ptr, signs, bias, sigma, J, J_ptr,
+                        mols=None, cols=None) -> np.ndarray:
+    """Derivative feature matrix dZ of the force-trained normal equation
+    (RFF subsection): one row per atomic coordinate, rows ordered like the
+    coordinates ([atom][xyz]), holding the negative derivative of the
+    molecule's feature row with respect to that coordinate,
+
+        dZ[3 a + k] = -dZ_m / dr_{a,k}
+                    = sqrt(2/D) sum_{i in m} sin(u_i) * (W_{e_i} J_i)[:, 3 (a - a0) + k],
+
+    so that dZ alpha = -dE/dr = F and (Z, dZ)^T (E, F) pairs energies with Z
+    and forces with dZ. J_i = dx_i/dr_m (d x 3 N_m) is block m of J as in
+    ``forces``. ``mols`` selects molecules (all by default; their rows are
+    concatenated in the given order) and ``cols`` feature columns.
+    Returns [3 * (atoms of mols), len(cols)] float64."""
+    x = np.asarray(x, dtype=np.float64)
+    element = np.asarray(element)
+    mol_ptr = np.asarray(mol_ptr, dtype=np.int64)
+    A, d = x.shape
+    D = signs.shape[2] * signs.shape[3]
+    cols = np.arange(D) if cols is None else np.asarray(cols, dtype=np.int64)
+    if mols is None:
+        mols = np.arange(len(mol_ptr) - 1)
+    Ws = [dense_w(signs[e], sigma)[cols] for e in range(signs.shape[0])]
+    blocks = []
+    for m in np.asarray(mols, dtype=np.int64):
+        a0, a1 = int(mol_ptr[m]), int(mol_ptr[m + 1])
+        n = a1 - a0
+        out = np.zeros((3 * n, len(cols)), dtype=np.float64)
+        if n:
+            blk = np.asarray(J[J_ptr[m]:J_ptr[m] + n * d * 3 * n],
+                             dtype=np.float64).reshape(n, d, 3 * n)
+            s = np.sin(phases(x, element, signs, bias, sigma, np.arange(a0, a1), cols))
+            for i in range(n):
+                WJ = Ws[element[a0 + i]] @ blk[i]          # [len(cols), 3 n]
+                out += (s[i][:, None] * WJ).T
+            out *= math.sqrt(2.0 / D)
+        blocks.append(out)
+    if not blocks:
+        return np.zeros((0, len(cols)), dtype=np.float64)
+    return np.concatenate(blocks, axis=0)
+
+
+def force_normal_equations(Z, dZ, E, F):
+    """(Z, dZ)^T (Z, dZ) and (Z, dZ)^T (E, F) of the force-trained normal
+    equation: the energy rows and the coordinate rows stacked into one
+    least-squares system. float64."""
+    A = np.concatenate([np.asarray(Z, dtype=np.float64), np.asarray(dZ, dtype=np.float64)])
+    b = np.concatenate([np.asarray(E, dtype=np.float64), np.asarray(F, dtype=np.float64)])
+    return A.T @ A, A.T @ b
 
 
 # --------------------------------------------------------------------------

@@ -461,3 +461,94 @@ def test_feature_column_subset_is_a_column_slice():
     full = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma)
     part = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, cols=cols)
     assert np.abs(part - full[:, cols]).max() <= 1e-14 * np.abs(full).max()
+
+
+# ---------------------------------------------------------------- derivative features (force training)
+def _dz_problem(seed, **kw):
+    base = dict(d=8, n_stacks=2, n_mols=4, min_atoms=0, max_atoms=3, with_J=True)
+    base.update(kw)
+    return W.random_problem(seed, **base)
+
+
+def test_f1_derivative_features_central_differences():
+    """Each row of dZ is minus the derivative of its molecule's feature row
+    along one coordinate, taken through the linearised x(r + h e_k) = x + h J_k."""
+    p = _dz_problem(71)
+    dZ = O.derivative_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.J, p.J_ptr)
+    assert dZ.shape == (3 * p.n_atoms, p.n_features)
+    x = p.x.astype(np.float64)
+    d, h = p.d, 1e-4
+    checked = 0
+    for m in range(p.n_mols):
+        a0, a1 = int(p.mol_ptr[m]), int(p.mol_ptr[m + 1])
+        n = a1 - a0
+        if n == 0:
+            continue
+        blk = p.J[p.J_ptr[m]:p.J_ptr[m + 1]].astype(np.float64).reshape(n, d, 3 * n)
+        for k in range(3 * n):
+            xp = x.copy(); xp[a0:a1] += h * blk[:, :, k]
+            xm = x.copy(); xm[a0:a1] -= h * blk[:, :, k]
+            Zp = O.molecule_features(xp, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, mols=[m])
+            Zm = O.molecule_features(xm, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, mols=[m])
+            fd = -(Zp[0] - Zm[0]) / (2 * h)
+            row = dZ[3 * a0 + k]
+            assert np.abs(row - fd).max() < 1e-7 * max(1.0, np.abs(fd).max())
+            checked += 1
+    assert checked > 0
+
+
+def test_f1_dz_alpha_is_the_force():
+    """dZ alpha equals the forces of the energy model, computed by the
+    independent route grad_x -> J^T contraction."""
+    p = _dz_problem(72, d=16, n_stacks=3, n_mols=5, max_atoms=4)
+    alpha = p.alpha.astype(np.float64)
+    dZ = O.derivative_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.J, p.J_ptr)
+    g = O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, alpha)
+    F = O.forces(g, p.J, p.J_ptr, p.mol_ptr)
+    assert np.abs(dZ @ alpha - F).max() < 1e-10 * max(1.0, np.abs(F).max())
+
+
+def test_f1_selected_molecules_and_columns_are_slices():
+    p = _dz_problem(73, n_mols=6)
+    full = O.derivative_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.J, p.J_ptr)
+    mols = [4, 1]
+    cols = np.array([0, 5, 9, 15])
+    part = O.derivative_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.J,
+                                 p.J_ptr, mols=mols, cols=cols)
+    rows = np.concatenate([np.arange(3 * p.mol_ptr[m], 3 * p.mol_ptr[m + 1]) for m in mols])
+    assert part.shape == (len(rows), len(cols))
+    assert np.abs(part - full[np.ix_(rows, cols)]).max() < 1e-13
+
+
+def test_f1_force_normal_equations_are_the_stacked_least_squares():
+    """((Z, dZ)^T (Z, dZ) + lam I) a = (Z, dZ)^T (E, F) is the ridge
+    least-squares problem over the stacked energy and coordinate rows
+    (independent route: lstsq on the system augmented with sqrt(lam) I)."""
+    rng = np.random.default_rng(74)
+    Z = rng.standard_normal((12, 10))
+    dZ = rng.standard_normal((30, 10))
+    E = rng.standard_normal(12)
+    F = rng.standard_normal(30)
+    lam = 0.3
+    G, r = O.force_normal_equations(Z, dZ, E, F)
+    a = O.solve(G, r, lam)
+    Aug = np.concatenate([Z, dZ, math.sqrt(lam) * np.eye(10)])
+    b = np.concatenate([E, F, np.zeros(10)])
+    ls = np.linalg.lstsq(Aug, b, rcond=None)[0]
+    assert np.abs(a - ls).max() < 1e-10
+
+
+def test_f1_planted_coefficients_recovered_from_energies_and_forces():
+    """Energies from Z alpha* and forces from the grad_x route: the force-trained
+    normal equation recovers alpha* even with fewer molecules than features."""
+    p = _dz_problem(75, d=4, n_stacks=3, n_mols=2, min_atoms=2, max_atoms=3)
+    a_star = np.random.default_rng(1).standard_normal(p.n_features)
+    Z = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma)
+    dZ = O.derivative_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.J, p.J_ptr)
+    E = Z @ a_star
+    F = O.forces(O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, a_star),
+                 p.J, p.J_ptr, p.mol_ptr)
+    assert Z.shape[0] < p.n_features <= Z.shape[0] + dZ.shape[0]
+    G, r = O.force_normal_equations(Z, dZ, E, F)
+    a = O.solve(G, r, 1e-12)
+    assert np.abs(a - a_star).max() < 1e-5
