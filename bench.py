@@ -50,6 +50,13 @@ def valu_slots_per_feature(d: int, T: int, backward: bool = False) -> float:
     return 2 * (T * lg + T) + 1 + 8 + 3
 
 
+def dz_slots_per_unit(d: int, T: int) -> float:
+    """Algorithmic VALU issue slots per (atom, coordinate column, feature) of
+    the derivative features: T log2(d) butterfly add/subs + T sign flips of
+    the Jacobian column's transform + 1 FMA of sin(u) times it into the row."""
+    return T * math.log2(d) + T + 1
+
+
 def measured_traffic(mode, M, D):
     """HBM bytes per Gram call (pack + products) from the committed PMC
     measurement, valid only for the same mode and size and while the Gram
@@ -89,6 +96,9 @@ def parse():
     ap.add_argument("--serve-sweep", default="8000,32000",
                     help="extra offered loads (req/s), each a trace of --serve-sweep-requests")
     ap.add_argument("--serve-sweep-requests", type=int, default=4000)
+    ap.add_argument("--force-confs", type=int, default=2000,
+                    help="conformations of the force-training leg (0 skips it)")
+    ap.add_argument("--force-steps", type=int, default=3)
     ap.add_argument("--precision-mols", type=int, default=100000,
                     help="molecules of the precision study (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -144,6 +154,111 @@ def serving_leg(args, dev, log, rate, seconds):
         "p50_speedup": (p["p50_ms"] / b["p50_ms"]) if b["p50_ms"] else None,
         "p99_speedup": (p["p99_ms"] / b["p99_ms"]) if b["p99_ms"] else None,
     }
+
+
+def force_training_leg(args, dev, log):
+    """Force-trained normal equations on the differentiation workload (one
+    21-atom molecule in 2,000 conformations, d = 128, D = 8192, Jacobians
+    d x 63 per atom): features Z, derivative features dZ (3 rows per atom),
+    G = Z^T Z + dZ^T dZ and Zty = Z^T E + dZ^T F in the bench's Gram mode, and
+    the FP64 solve. Energy and force targets are seeded N(0, 1) (the timing
+    does not depend on them)."""
+    import torch
+
+    from paper_2206_01580_amd import sorf, workloads
+    p = workloads.config3(n_conf=args.force_confs, with_J=False)
+    D, A, M = p.n_features, p.n_atoms, p.n_mols
+    model, batch = sorf.Model.from_problem(p), sorf.Batch.from_problem(p)
+    n_j = A * p.d * 3 * int(p.mol_sizes()[0])
+    J = workloads.device_normal(n_j, p.seed + 1, 0.1, device=dev)
+    J_ptr = torch.arange(M + 1, dtype=torch.int64, device=dev) * (n_j // M)
+    E_t = workloads.device_normal(M, p.seed + 2, 1.0, device=dev)
+    F_t = workloads.device_normal(3 * A, p.seed + 3, 1.0, device=dev)
+    Z = torch.empty(M, D, device=dev)
+    dZ = torch.empty(3 * A, D, device=dev)
+    acc_t = torch.float64 if args.gram == "fp64" else torch.float32
+    G = torch.empty(D, D, device=dev, dtype=acc_t)
+    r = torch.empty(D, device=dev, dtype=acc_t)
+    ws = sorf.GramWorkspace(dev)
+    if args.gram != "fp64":
+        ws.get(3 * A, D, args.gram)             # allocate before timing
+    solver = sorf.Solver(D, device=dev)
+    alpha = torch.empty(D, device=dev, dtype=torch.float64)
+    scale_exp = 0
+    if args.gram.startswith("fp16"):
+        torch.cuda.synchronize()
+        sorf.derivative_features(model, batch, J, J_ptr, out=dZ)
+        sorf.forward(model, batch, out=Z)
+        mx = max(float(Z.abs().max()), float(dZ.abs().max()))
+        scale_exp = sorf.fp16_scale_exp(mx)
+    phases = ["forward", "dz", "gram", "solve"]
+    ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+          for k in phases}
+    times = {k: [] for k in phases}
+
+    def step(record):
+        def mark(k, i):
+            if record:
+                ev[k][i].record()
+        mark("forward", 0)
+        sorf.forward(model, batch, out=Z)
+        mark("forward", 1)
+        mark("dz", 0)
+        sorf.derivative_features(model, batch, J, J_ptr, out=dZ)
+        mark("dz", 1)
+        G.zero_()
+        r.zero_()
+        mark("gram", 0)
+        sorf.gram_accumulate(Z, G, E_t, r, precision=args.gram, scale_exp=scale_exp, workspace=ws)
+        sorf.gram_accumulate(dZ, G, F_t, r, precision=args.gram, scale_exp=scale_exp, workspace=ws)
+        mark("gram", 1)
+        mark("solve", 0)
+        solver(G, r, args.lam, args.n_refine, out=alpha)
+        mark("solve", 1)
+
+    step(False)
+    torch.cuda.synchronize()
+    info = int(solver.info.item())
+    log(f"force training: {M} conformations, dZ {3 * A} x {D}, info {info}")
+    t0 = time.perf_counter()
+    for _ in range(args.force_steps):
+        step(True)
+        torch.cuda.synchronize()
+        for k in phases:
+            times[k].append(ev[k][0].elapsed_time(ev[k][1]))
+    wall_ms = (time.perf_counter() - t0) * 1e3 / args.force_steps
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    units = float(A) * 3 * int(p.mol_sizes()[0]) * D          # (atom, column, feature)
+    dz_tops = units * dz_slots_per_unit(p.d, p.n_transforms) / (med["dz"] * 1e-3) / 1e12
+    rows = M + 3 * A
+    gram_tf = float(rows) * D * (D + 1) / (med["gram"] * 1e-3) / 1e12
+    out = {
+        "workload": (f"{M} conformations of a 21-atom molecule, d={p.d}, {p.n_stacks} stacks "
+                     f"(D={D}), sigma={p.sigma:g}, Jacobians d x 63 per atom N(0, 0.1); "
+                     f"(Z, dZ) has {rows} rows; Gram {args.gram}, lambda={args.lam:g}"),
+        "ms_per_step": wall_ms, "phase_ms": med, "solve_info": info,
+        "dz_rows_per_s": 3.0 * A / (med["dz"] * 1e-3),
+        "roofline_dz": {"bound": "alu", "achieved": dz_tops, "peak": PEAK_VALU_TOPS,
+                        "unit": "T VALU-slots/s", "frac": dz_tops / PEAK_VALU_TOPS,
+                        "traffic": None,
+                        "slots_per_unit": dz_slots_per_unit(p.d, p.n_transforms),
+                        "units_per_launch": units},
+        "gram_tflops": gram_tf,
+        "gram_frac": gram_tf / PEAK_MFMA_TFLOPS[args.gram],
+    }
+    if not args.no_cpu_baseline:
+        from oracle import sorf_oracle as O
+        q = workloads.config3(n_conf=4)
+        t1 = time.perf_counter()
+        O.derivative_features(q.x, q.element, q.mol_ptr, q.signs, q.bias, q.sigma, q.J, q.J_ptr)
+        t_o = time.perf_counter() - t1
+        out["cpu_baseline_dz"] = {
+            "value": 3.0 * q.n_atoms / t_o, "unit": "dZ rows/s",
+            "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+            "sample": f"FP64 dense-W oracle, dZ of 4 conformations ({3 * q.n_atoms} rows), {t_o:.2f} s"}
+    del Z, dZ, G, r, ws, solver, J
+    torch.cuda.empty_cache()
+    return out
 
 
 def precision_study(args, dev, log):
@@ -412,6 +527,8 @@ def main():
         sweep = [float(r) for r in args.serve_sweep.split(",") if r.strip()]
         out["serving_load_sweep"] = [
             serving_leg(args, dev, log, r, args.serve_sweep_requests / r) for r in sweep]
+    if args.force_confs > 0:
+        out["force_training"] = force_training_leg(args, dev, log)
     if args.precision_mols > 0:
         out["precision_study"] = precision_study(args, dev, log)
     if not args.no_cpu_baseline:

@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SORF_ABI_VERSION 2
+#define SORF_ABI_VERSION 3
 
 typedef void* sorf_stream_t; /* a hipStream_t */
 
@@ -111,6 +111,24 @@ sorf_status sorf_forward(const sorf_model* model, const sorf_batch* batch, float
  *   grad_x: [n_atoms][d] FP32, overwritten. */
 sorf_status sorf_backward(const sorf_model* model, const sorf_batch* batch, const float* alpha,
                           const float* dE, float* grad_x, sorf_stream_t stream);
+
+/* Derivative feature matrix of the force-trained normal equation (RFF subsection:
+ * ((Z, dZ)^T (Z, dZ) + lambda I) alpha = (Z, dZ)^T (E, F), dZ with one row per atomic
+ * coordinate). Row 3 a + k (atom a of molecule m, coordinate k in [0, 3)) is minus the
+ * derivative of the molecule's feature row with respect to that coordinate:
+ *   dZ[3 a + k][f] = sqrt(2/D) sum_{i in m} sin(u_{i,f}) (W_{e_i} J_i)[f][3 (a - a0) + k],
+ *   u_i = W_{e_i} x_i + b_{e_i},  a0 = mol_ptr[m],
+ * so that dZ alpha = F = -dE/dr. Accumulating (Z, E) and then (dZ, F) with
+ * sorf_gram_accumulate into the same G and Zty forms the force-trained system.
+ *   J, J_ptr: the per-molecule Jacobian blocks exactly as sorf_predict takes them
+ *     (block m is [N_m][d][3 N_m] row-major at float offset J_ptr[m]; no alignment).
+ *   dZ: [3 n_atoms][D] row-major FP32, 16-byte aligned, overwritten (molecules with no
+ *     atoms own no rows). Each row is summed over its molecule's atoms in atom order,
+ *     so a molecule's rows are bitwise the same in any batch.
+ *   Required non-NULL when n_atoms > 0. Needs no workspace. */
+sorf_status sorf_derivative_features(const sorf_model* model, const sorf_batch* batch,
+                                     const float* J, const int64_t* J_ptr, float* dZ,
+                                     sorf_stream_t stream);
 
 /* Bytes of workspace sorf_gram_accumulate needs for n_rows rows of D features in the given
  * precision (host-only query): the FP32 mode needs only the Z^T y partials (D * 8 bytes per

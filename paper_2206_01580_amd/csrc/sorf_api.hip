@@ -103,6 +103,18 @@ sorf_status sorf_backward(const sorf_model* model, const sorf_batch* batch, cons
                                       hipStream_t(stream)));
 }
 
+sorf_status sorf_derivative_features(const sorf_model* model, const sorf_batch* batch,
+                                     const float* J, const int64_t* J_ptr, float* dZ,
+                                     sorf_stream_t stream) {
+  sorf_status s = check_model(model);
+  if (s != SORF_OK) return s;
+  if ((s = check_batch(batch)) != SORF_OK) return s;
+  if (batch->n_atoms > 0 && (J == nullptr || J_ptr == nullptr || dZ == nullptr))
+    return SORF_ERR_INVALID_ARG;
+  if (!aligned16(dZ)) return SORF_ERR_INVALID_ARG;
+  return dev(sorf_launch_dz(pack(model, batch), J, J_ptr, dZ, hipStream_t(stream)));
+}
+
 size_t sorf_gram_workspace_bytes(int64_t n_rows, int32_t D, sorf_gram_precision precision) {
   if (n_rows < 0 || D < 1 || D > (1 << 20)) return 0;
   if (int(precision) < 0 || int(precision) > 4) return 0;

@@ -211,6 +211,9 @@ size_t sorf_force_plan_bytes(int64_t n_atoms, int64_t n_mols);
 hipError_t sorf_launch_molecule_reduce(const SorfFeatureArgs& a, const float* e_atom,
                                        const float* grad, const float* J, const int64_t* J_ptr,
                                        float* E, float* F, void* plan_ws, hipStream_t s);
+// Derivative features dZ [3 n_atoms][D] (rows of the force-trained normal equation).
+hipError_t sorf_launch_dz(const SorfFeatureArgs& a, const float* J, const int64_t* J_ptr,
+                          float* dZ, hipStream_t s);
 hipError_t sorf_launch_validate(const SorfFeatureArgs& a, int32_t* result, hipStream_t s);
 hipError_t sorf_launch_fill(float* p, int64_t n, float v, hipStream_t s);
 

@@ -160,6 +160,24 @@ def backward(model: Model, batch: Batch, alpha: torch.Tensor, dE: Optional[torch
     return out
 
 
+def derivative_features(model: Model, batch: Batch, J: torch.Tensor, J_ptr: torch.Tensor,
+                        out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dZ [3 n_atoms, D]: minus the coordinate derivatives of the molecules'
+    feature rows, one row per atomic coordinate (sorf_derivative_features)."""
+    batch.check(model)
+    D = model.n_features
+    _need(J, torch.float32, "J")
+    _need(J_ptr, torch.int64, "J_ptr", batch.n_mols + 1)
+    if out is None:
+        out = torch.empty((3 * batch.n_atoms, D), dtype=torch.float32, device=batch.x.device)
+    _need(out, torch.float32, "dZ", 3 * batch.n_atoms * D)
+    lib = _lib.load()
+    m, b = model.c_struct(), batch.c_struct()
+    _lib.check("sorf_derivative_features", lib.sorf_derivative_features(
+        ctypes.byref(m), ctypes.byref(b), _ptr(J), _ptr(J_ptr), _ptr(out), _stream()))
+    return out
+
+
 class GramWorkspace:
     """Reusable device workspace for sorf_gram_accumulate (grows on demand)."""
 
