@@ -33,6 +33,65 @@
 
 namespace sorf {
 
+// Lane layout of this kernel: entry j of a d-vector sits in lane q = j % K of
+// its group, register r = j / K (K = d / EPL lanes per vector). The butterfly
+// stages over the register bits run in registers and those over the lane bits
+// across lanes, as in the other feature kernels; the Hadamard matrix in
+// natural order is unchanged by this relabelling of the index bits, since it
+// relabels rows and columns alike. The point of the layout: the K sign bits
+// of register r of a group are one K-bit chunk of the sign vector, and when
+// every group of a wave transforms a column of the same atom (same element
+// and stack), the sign mask of register r across the wave is that chunk
+// repeated 64 / K times: a wave-uniform value in scalar registers, applied
+// with one v_cndmask per entry.
+
+template <int K>
+__host__ __device__ constexpr uint32_t lane_repeat() {  // sum over k < 32/K of 2^(kK)
+  uint32_t v = 0;
+  for (int k = 0; k < 32 / K; ++k) v |= 1u << (k * K);
+  return v;
+}
+
+template <int K>
+__host__ __device__ constexpr uint32_t odd_lanes() {    // bit q set iff popcount(q) is odd, q < K
+  uint32_t v = 0;
+  for (int q = 0; q < K && q < 32; ++q)
+    if (__builtin_popcount(q) & 1) v |= 1u << q;
+  return v;
+}
+
+// v[r] = -v[r] where the sign bit of entry r K + q is set; `pending` also
+// flips the lanes that carry the pending sign of the previous transform's
+// cross-lane stages. `sw` points at the W sign words of the vector and must
+// be the same for the whole wave.
+template <int EPL, int K>
+__device__ __forceinline__ void apply_signs_wave(float (&v)[EPL], const uint32_t* __restrict__ sw,
+                                                 bool pending) {
+  constexpr uint32_t KMASK = K >= 32 ? 0xFFFFFFFFu : ((1u << K) - 1u);
+  constexpr uint32_t REP = lane_repeat<K>();
+  constexpr uint32_t FLIP = odd_lanes<K>() * REP;
+#pragma unroll
+  for (int r = 0; r < EPL; ++r) {
+    const uint32_t word = __builtin_amdgcn_readfirstlane(sw[(r * K) >> 5]);
+    uint32_t m32 = ((word >> ((r * K) & 31)) & KMASK) * REP;
+    if (pending) m32 ^= FLIP;
+    const uint64_t m = (uint64_t(m32) << 32) | m32;
+    asm("v_cndmask_b32_e64 %0, %1, -%1, %2" : "=v"(v[r]) : "v"(v[r]), "s"(m));
+  }
+}
+
+// The same for a lane group whose vector differs from the other groups'.
+// `flip` is 0x80000000 on lanes that carry a pending sign, else 0.
+template <int EPL, int K>
+__device__ __forceinline__ void apply_signs_group(float (&v)[EPL], const uint32_t* __restrict__ sw,
+                                                  uint32_t q, uint32_t flip) {
+#pragma unroll
+  for (int r = 0; r < EPL; ++r) {
+    const uint32_t bit = (sw[(r * K) >> 5] >> (((r * K) & 31) + q)) << 31;
+    v[r] = __uint_as_float(__float_as_uint(v[r]) ^ bit ^ flip);
+  }
+}
+
 template <int LOG_D, int LOG_EPL>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void dz_kernel(
     const float* __restrict__ x, const int32_t* __restrict__ element,
@@ -43,19 +102,19 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
   constexpr int DV = 1 << LOG_D;
   constexpr int EPL = 1 << LOG_EPL;
   constexpr int LOGK = LOG_D - LOG_EPL;
+  constexpr int K = 1 << LOGK;                       // lanes per vector
   constexpr int VPW = 64 >> LOGK;                    // column vectors per wave
   constexpr int W = (DV + 31) / 32;                  // sign words per vector
-  constexpr int LW = EPL >= 32 ? EPL / 32 : 1;       // sign words per lane
   constexpr int PADL = EPL % 4 == 0 ? EPL + 4 : EPL; // LDS stride of one lane's share
-  constexpr int ROW = (1 << LOGK) * PADL;            // LDS floats per atom
+  constexpr int ROW = K * PADL;                      // LDS floats per atom
   constexpr int CH = 4 * VPW;                        // atoms per LDS chunk
   __shared__ __attribute__((aligned(16))) float sinbuf[CH * ROW];
 
   // block -> (molecule, stack): the S blocks of a molecule share blockIdx.x % 8
   const int64_t b = blockIdx.x;
-  const int64_t r = b >> 3;
-  const int64_t m = m_begin + (r / S) * 8 + (b & 7);
-  const int32_t s = int32_t(r % S);
+  const int64_t rr = b >> 3;
+  const int64_t m = m_begin + (rr / S) * 8 + (b & 7);
+  const int32_t s = int32_t(rr % S);
   if (m >= m_end) return;
   const int64_t a0 = mol_ptr[m];
   const int64_t n = mol_ptr[m + 1] - a0;
@@ -63,10 +122,10 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
 
   const int wv = int(threadIdx.x >> 6);
   const uint32_t lane = lane_id();
-  const uint32_t q = lane & ((1u << LOGK) - 1u);
+  const uint32_t q = lane & (K - 1u);
   const int g = int(lane >> LOGK);
   const bool odd = (__builtin_popcount(q) & 1) != 0;
-  const uint32_t flip = odd ? 0xFFFFFFFFu : 0u;  // pending sign after cross-lane stages
+  const uint32_t flip = odd ? 0x80000000u : 0u;  // pending sign after cross-lane stages
   const float c_lane = odd ? -c_rev : c_rev;
   const float o_lane = odd ? -out_scale : out_scale;
   const int64_t Dtot = int64_t(S) * DV;
@@ -81,77 +140,83 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
     const int64_t i = i0 + wv * VPW + g;
     const int64_t a = a0 + (i < n ? i : n - 1);
     const int32_t e = element[a];
+    const float* xa = x + a * DV + q;
     float v[EPL];
-    load_vec<EPL>(v, x + a * DV + q * EPL);
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) v[r] = xa[r * K];
     const uint32_t* sv = signs + (int64_t(e) * T * S + s) * W;
     for (int t = 0; t < T; ++t) {
-      uint32_t w[LW];
-      load_sign_words<EPL>(w, sv + t * tstride, q, t > 0 ? flip : 0u);
-      apply_signs<EPL>(v, w);
+      apply_signs_group<EPL, K>(v, sv + t * tstride, q, t > 0 ? flip : 0u);
       fwht<LOGK, EPL>(v, q);
     }
-    const float* bp = bias + int64_t(e) * Dtot + int64_t(s) * DV + q * EPL;
-    float bb[EPL];
-    load_vec<EPL>(bb, bp);
+    const float* bp = bias + int64_t(e) * Dtot + int64_t(s) * DV + q;
 #pragma unroll
-    for (int j = 0; j < EPL; ++j)
-      v[j] = __builtin_amdgcn_sinf(__builtin_fmaf(v[j], c_lane, bb[j] * kInv2Pi));
+    for (int r = 0; r < EPL; ++r)
+      v[r] = __builtin_amdgcn_sinf(__builtin_fmaf(v[r], c_lane, bp[r * K] * kInv2Pi));
     if (i < n) {
       float* dst = sinbuf + (wv * VPW + g) * ROW + q * PADL;
       if constexpr (EPL % 4 == 0) {
 #pragma unroll
-        for (int j = 0; j < EPL; j += 4)
-          *reinterpret_cast<float4*>(dst + j) = make_float4(v[j], v[j + 1], v[j + 2], v[j + 3]);
+        for (int r = 0; r < EPL; r += 4)
+          *reinterpret_cast<float4*>(dst + r) = make_float4(v[r], v[r + 1], v[r + 2], v[r + 3]);
       } else {
 #pragma unroll
-        for (int j = 0; j < EPL; ++j) dst[j] = v[j];
+        for (int r = 0; r < EPL; ++r) dst[r] = v[r];
       }
     }
   };
 
-  // acc += sin(u_i) * (W_{e_i,s} J_i[:, col]) over atoms i0 .. i1 - 1 (LDS chunk at i0)
+  // acc += sin(u_i) * (W_{e_i,s} J_i[:, col]) over atoms i0 .. i1 - 1 (LDS chunk at i0).
+  // Every group of the wave takes the same atom, so the sign masks and the row
+  // base of each J load are wave-uniform; only the lane's row and column vary.
   auto col_pass = [&](int64_t cg, int64_t i0, int64_t i1, float (&acc)[EPL]) {
     const int64_t col = cg * VPW + g;
     const int64_t colc = col < ncol ? col : ncol - 1;
+    // the atom's block through a buffer descriptor: the wave-uniform row offset
+    // of each load goes in a scalar register, so loads need no address VALU
+    const uint32_t vofs = uint32_t((int64_t(q) * ncol + colc) * 4);   // bytes
+    const uint32_t blk_bytes = uint32_t(int64_t(DV) * ncol * 4);
+    const uint32_t row_bytes = uint32_t(int64_t(K) * ncol * 4);
     for (int64_t i = i0; i < i1; ++i) {
-      const int32_t e = element[a0 + i];
-      const float* __restrict__ jp = jm + (i * DV + q * EPL) * ncol + colc;
+      const int32_t e = __builtin_amdgcn_readfirstlane(element[a0 + i]);
+      const __amdgpu_buffer_rsrc_t rsrc = __builtin_amdgcn_make_buffer_rsrc(
+          const_cast<float*>(jm + i * DV * ncol), int16_t(0), int32_t(blk_bytes), 0x00020000);
       float v[EPL];
 #pragma unroll
-      for (int j = 0; j < EPL; ++j) v[j] = jp[j * ncol];
+      for (int r = 0; r < EPL; ++r)
+        v[r] = __uint_as_float(__builtin_amdgcn_raw_buffer_load_b32(rsrc, vofs, r * row_bytes, 0));
       const uint32_t* sv = signs + (int64_t(e) * T * S + s) * W;
-      uint32_t w[3][LW];
-#pragma unroll
-      for (int t = 0; t < 3; ++t)
-        if (t < T) load_sign_words<EPL>(w[t], sv + t * tstride, q, t > 0 ? flip : 0u);
 #pragma unroll
       for (int t = 0; t < 3; ++t) {
         if (t < T) {
-          apply_signs<EPL>(v, w[t]);
+          apply_signs_wave<EPL, K>(v, sv + t * tstride, t > 0);
           fwht<LOGK, EPL>(v, q);
         }
       }
       const float* sp = sinbuf + (i - i0) * ROW + q * PADL;
       if constexpr (EPL % 4 == 0) {
 #pragma unroll
-        for (int j = 0; j < EPL; j += 4) {
-          const float4 sn = *reinterpret_cast<const float4*>(sp + j);
-          acc[j] = __builtin_fmaf(sn.x, v[j], acc[j]);
-          acc[j + 1] = __builtin_fmaf(sn.y, v[j + 1], acc[j + 1]);
-          acc[j + 2] = __builtin_fmaf(sn.z, v[j + 2], acc[j + 2]);
-          acc[j + 3] = __builtin_fmaf(sn.w, v[j + 3], acc[j + 3]);
+        for (int r = 0; r < EPL; r += 4) {
+          const float4 sn = *reinterpret_cast<const float4*>(sp + r);
+          acc[r] = __builtin_fmaf(sn.x, v[r], acc[r]);
+          acc[r + 1] = __builtin_fmaf(sn.y, v[r + 1], acc[r + 1]);
+          acc[r + 2] = __builtin_fmaf(sn.z, v[r + 2], acc[r + 2]);
+          acc[r + 3] = __builtin_fmaf(sn.w, v[r + 3], acc[r + 3]);
         }
       } else {
 #pragma unroll
-        for (int j = 0; j < EPL; ++j) acc[j] = __builtin_fmaf(sp[j], v[j], acc[j]);
+        for (int r = 0; r < EPL; ++r) acc[r] = __builtin_fmaf(sp[r], v[r], acc[r]);
       }
     }
   };
 
   auto store_row = [&](int64_t cg, const float (&acc)[EPL]) {
     const int64_t col = cg * VPW + g;
-    if (col < ncol)
-      store_vec<EPL>(dZ + (3 * a0 + col) * Dtot + int64_t(s) * DV + q * EPL, acc, o_lane);
+    if (col < ncol) {
+      float* out = dZ + (3 * a0 + col) * Dtot + int64_t(s) * DV + q;
+#pragma unroll
+      for (int r = 0; r < EPL; ++r) out[r * K] = acc[r] * o_lane;
+    }
   };
 
   if (n <= CH) {
@@ -160,7 +225,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
     for (int64_t cg = wv; cg < n_cg; cg += 4) {
       float acc[EPL];
 #pragma unroll
-      for (int j = 0; j < EPL; ++j) acc[j] = 0.0f;
+      for (int r = 0; r < EPL; ++r) acc[r] = 0.0f;
       col_pass(cg, 0, n, acc);
       store_row(cg, acc);
     }
@@ -169,7 +234,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
       const int64_t cg = cg0 + wv;
       float acc[EPL];
 #pragma unroll
-      for (int j = 0; j < EPL; ++j) acc[j] = 0.0f;
+      for (int r = 0; r < EPL; ++r) acc[r] = 0.0f;
       for (int64_t i0 = 0; i0 < n; i0 += CH) {
         __syncthreads();  // the previous chunk's sin values are no longer read
         sin_chunk(i0);
