@@ -122,6 +122,8 @@ sorf_status sorf_backward(const sorf_model* model, const sorf_batch* batch, cons
  * sorf_gram_accumulate into the same G and Zty forms the force-trained system.
  *   J, J_ptr: the per-molecule Jacobian blocks exactly as sorf_predict takes them
  *     (block m is [N_m][d][3 N_m] row-major at float offset J_ptr[m]; no alignment).
+ *     One atom's part of a block, d * 3 N_m floats, must stay below 2^32 bytes
+ *     (N_m < 2^30 / (3 d) atoms in one molecule; not checked, as N_m lives in device memory).
  *   dZ: [3 n_atoms][D] row-major FP32, 16-byte aligned, overwritten (molecules with no
  *     atoms own no rows). Each row is summed over its molecule's atoms in atom order,
  *     so a molecule's rows are bitwise the same in any batch.

@@ -175,6 +175,7 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void d
     // the atom's block through a buffer descriptor: the wave-uniform row offset
     // of each load goes in a scalar register, so loads need no address VALU
     const uint32_t vofs = uint32_t((int64_t(q) * ncol + colc) * 4);   // bytes
+    // (a block below 2^32 bytes, d * 3 N_m * 4, as the interface requires)
     const uint32_t blk_bytes = uint32_t(int64_t(DV) * ncol * 4);
     const uint32_t row_bytes = uint32_t(int64_t(K) * ncol * 4);
     for (int64_t i = i0; i < i1; ++i) {
