@@ -25,6 +25,8 @@ Paper passages followed (arXiv 2206.01580, Theory section):
   per atomic coordinate (3 N_atom rows).
 * SORF subsection, W_ORF ~ (sqrt(d)/sigma) [H_i D_i]_{N_transform}; the
   Sylvester recursion for H; stacking of N_F/d independent blocks.
+* SORF subsection, projection to 2^n dimensions: per element, the SVD
+  Z~_e = U_e S_e V_e^T of sampled representations and rho_proj = rho^T U_e^{N_PCA}.
 
 Readings taken where the paper is silent or ambiguous (all listed in the
 design notes of the repository):
@@ -41,6 +43,10 @@ design notes of the repository):
   F = -sum_i J_i^T (dE/dx_i).
 * The rows of dZ hold the NEGATIVE coordinate derivatives of Z, so that
   dZ alpha = F and the stacked system pairs dZ with F as printed.
+* Projection: the representations are the COLUMNS of Z~_e (so U_e acts on
+  representation space), the SVD is of the raw matrix (no centring; the
+  paper names an SVD, not a covariance), and each singular vector's sign is
+  fixed by its largest-magnitude entry.
 
 Pins: each function is checked in ``tests/test_oracle_pins.py`` against
 closed forms, invariants, exact enumeration, brute force and independent
@@ -56,7 +62,8 @@ import scipy.linalg
 __all__ = [
     "hadamard", "sorf_scale", "dense_block", "dense_w", "phases", "atom_features",
     "molecule_features", "gram", "solve", "predict_energies", "grad_x", "forces",
-    "derivative_features", "force_normal_equations", "round_bf16", "round_fp16", "split_hilo", "gram_emulated",
+    "derivative_features", "force_normal_equations", "projection_fit", "project",
+    "round_bf16", "round_fp16", "split_hilo", "gram_emulated",
 ]
 
 
@@ -286,6 +293,39 @@ def force_normal_equations(Z, dZ, E, F):
     A = np.concatenate([np.asarray(Z, dtype=np.float64), np.asarray(dZ, dtype=np.float64)])
     b = np.concatenate([np.asarray(E, dtype=np.float64), np.asarray(F, dtype=np.float64)])
     return A.T @ A, A.T @ b
+
+
+# --------------------------------------------------------------------------
+# Per-element projection of the representation to d = 2^n (SORF subsection)
+# --------------------------------------------------------------------------
+
+def projection_fit(rho_sample, n_pca: int):
+    """U_e^{N_PCA} of one element: the first ``n_pca`` left singular vectors of
+    the matrix whose columns are the sampled representations of that element
+    (Z~_e = U_e S_e V_e^T, SORF subsection), each column's sign fixed so that
+    its entry of largest magnitude is positive (the SVD leaves the sign free).
+    rho_sample: [n_samples, d_rep]. Returns (U [d_rep, n_pca], s [n_pca]) in
+    float64; the singular values come in decreasing order."""
+    Zt = np.asarray(rho_sample, dtype=np.float64).T
+    U, s, _ = np.linalg.svd(Zt, full_matrices=False)
+    U = U[:, :n_pca].copy()
+    piv = np.argmax(np.abs(U), axis=0)
+    U *= np.sign(U[piv, np.arange(U.shape[1])])[None, :]
+    return U, s[:n_pca]
+
+
+def project(rho, element, U):
+    """x_i = rho_i^T U_{e_i}: the projected representation of every atom with
+    its own element's matrix. rho: [A, d_rep]; U: [E, d_rep, d]. float64."""
+    rho = np.asarray(rho, dtype=np.float64)
+    element = np.asarray(element)
+    U = np.asarray(U, dtype=np.float64)
+    x = np.zeros((rho.shape[0], U.shape[2]), dtype=np.float64)
+    for e in range(U.shape[0]):
+        sel = np.nonzero(element == e)[0]
+        if len(sel):
+            x[sel] = rho[sel] @ U[e]
+    return x
 
 
 # --------------------------------------------------------------------------

@@ -552,3 +552,70 @@ def test_f1_planted_coefficients_recovered_from_energies_and_forces():
     G, r = O.force_normal_equations(Z, dZ, E, F)
     a = O.solve(G, r, 1e-12)
     assert np.abs(a - a_star).max() < 1e-5
+
+
+# ---------------------------------------------------------------- per-element projection
+def _lowrank_sample(seed, n, d_rep, spectrum):
+    """Rows rho = sum_j g_j sqrt(spectrum_j) b_j with orthonormal b_j: the
+    left singular vectors are known (the b_j) and the squared singular values
+    are close to n * spectrum."""
+    rng = np.random.default_rng(seed)
+    B, _ = np.linalg.qr(rng.standard_normal((d_rep, len(spectrum))))
+    g = rng.standard_normal((n, len(spectrum))) * np.sqrt(spectrum)[None, :]
+    return g @ B.T, B
+
+
+def test_f2_fit_matches_eigenvectors_of_the_gram():
+    """Independent route: eigenvectors of Z~ Z~^T (symmetric eigensolver) are the
+    left singular vectors, eigenvalues the squared singular values."""
+    rho, _ = _lowrank_sample(81, 400, 40, 2.0 ** -np.arange(40) * 10)
+    U, s = O.projection_fit(rho, 16)
+    w, V = np.linalg.eigh(rho.T @ rho)
+    order = np.argsort(w)[::-1][:16]
+    V = V[:, order]
+    V *= np.sign(V[np.argmax(np.abs(V), axis=0), np.arange(16)])[None, :]
+    assert np.abs(U - V).max() < 1e-8
+    assert np.abs(s ** 2 - w[order]).max() < 1e-9 * w.max()
+    assert np.abs(U.T @ U - np.eye(16)).max() < 1e-12
+
+
+def test_f2_fit_recovers_a_planted_subspace_and_eckart_young():
+    rho, B = _lowrank_sample(82, 600, 32, np.linspace(9.0, 5.0, 8))
+    # a rank-8 sample: its top-8 span is exactly the planted span
+    U, s = O.projection_fit(rho, 8)
+    P_fit, P_true = U @ U.T, B @ B.T
+    assert np.abs(P_fit - P_true).max() < 1e-10
+    # with noise in the other directions, the best rank-8 approximation
+    rho = rho + 1e-3 * np.random.default_rng(0).standard_normal(rho.shape)
+    U, s = O.projection_fit(rho, 8)
+    # best rank-8 approximation error equals the dropped singular values
+    Zt = rho.T
+    full = np.linalg.svd(Zt, compute_uv=False)
+    resid = Zt - U @ (U.T @ Zt)
+    assert abs(np.sum(resid ** 2) - np.sum(full[8:] ** 2)) < 1e-9 * np.sum(full ** 2)
+
+
+def test_f2_sign_convention_and_no_centring():
+    """Each column's largest entry is positive; a constant offset of all
+    representations moves the leading vector towards that offset (the SVD is of
+    the raw matrix, not of centred data)."""
+    rng = np.random.default_rng(83)
+    rho = rng.standard_normal((300, 12)) * 0.1 + 5.0 * np.eye(12)[3]
+    U, _ = O.projection_fit(rho, 4)
+    piv = np.argmax(np.abs(U), axis=0)
+    assert np.all(U[piv, np.arange(4)] > 0)
+    assert abs(U[3, 0]) > 0.99
+
+
+def test_f2_projection_brute_force_and_per_element():
+    rng = np.random.default_rng(84)
+    rho = rng.standard_normal((7, 5))
+    element = np.array([0, 1, 1, 0, 2, 2, 1])
+    U = rng.standard_normal((3, 5, 4))
+    x = O.project(rho, element, U)
+    for i in range(7):
+        for j in range(4):
+            ref = sum(rho[i, k] * U[element[i], k, j] for k in range(5))
+            assert abs(x[i, j] - ref) < 1e-13
+    # another element's matrix gives another answer
+    assert np.abs(O.project(rho, (element + 1) % 3, U) - x).max() > 1e-3
