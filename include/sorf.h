@@ -132,6 +132,49 @@ sorf_status sorf_derivative_features(const sorf_model* model, const sorf_batch* 
                                      const float* J, const int64_t* J_ptr, float* dZ,
                                      sorf_stream_t stream);
 
+/* Bytes of workspace sorf_projection_fit needs for representations of d_rep entries
+ * (host-only query): about 4 d_rep^2 doubles. 0 unless 1 <= d_rep <= 4096. */
+size_t sorf_projection_fit_workspace_bytes(int32_t d_rep);
+
+/* Fit of one element's projection matrix (SORF subsection: the SVD Z~_e = U_e S_e V_e^T of
+ * the matrix whose columns are sampled representations of element e; U_e^{N_PCA} is its
+ * first N_PCA columns). Computed as the eigenvectors of Z~_e Z~_e^T = sum_rows rho^T rho,
+ * formed in FP64, by the cyclic Jacobi method in FP64 (at most 15 sweeps).
+ *   sample: [n_samples][d_rep] FP32 rows (any alignment).
+ *   U: [d_rep][n_pca] row-major FP32 out; column r is the left singular vector of the
+ *     r-th largest singular value (equal values: lower eigenvector index first), its sign
+ *     chosen so that its entry of largest magnitude (ties: lowest row) is positive. Writing
+ *     element e's result at U_all + e * d_rep * d with n_pca = d builds the [E][d_rep][d]
+ *     array sorf_project takes.
+ *   singular_values: [n_pca] FP64 out (sqrt of the eigenvalues, negatives clamped to 0), or NULL.
+ *   1 <= n_pca <= d_rep <= 4096 (larger d_rep: SORF_ERR_UNSUPPORTED). The columns are
+ *   determined only for distinct, nonzero singular values: the sample needs rank >= n_pca
+ *   (columns past its rank are arbitrary unit vectors of the null space).
+ *   workspace: at least sorf_projection_fit_workspace_bytes(d_rep), 256-byte aligned.
+ *   About 15 (d_rep + 1) kernel launches; deterministic. */
+sorf_status sorf_projection_fit(int64_t n_samples, int32_t d_rep, const float* sample,
+                                int32_t n_pca, float* U, double* singular_values,
+                                void* workspace, size_t workspace_bytes, sorf_stream_t stream);
+
+/* Bytes of workspace sorf_project needs (host-only query; nondecreasing in n_atoms).
+ * 0 for invalid sizes (n_atoms < 0, n_elements outside [1, 256]). */
+size_t sorf_project_workspace_bytes(int64_t n_atoms, int32_t n_elements);
+
+/* Per-element projection of the atomic representation to the transform size (SORF
+ * subsection: rho_proj = rho^T U_e^{N_PCA}, U_e^{N_PCA} the first N_PCA left singular
+ * vectors of element e's sampled representations, one matrix per element):
+ *   x[i][j] = sum_k rho[i][k] U[e_i][k][j]   (FP32 matrix-core products and sums).
+ *   rho: [n_atoms][d_rep] row-major FP32 (any alignment; 16-byte aligned rows with d_rep and
+ *   d multiples of 4 take the vector path); element: [n_atoms] int32 in [0, n_elements)
+ *   (atoms with other ids are skipped and their x rows left as they were);
+ *   U: [n_elements][d_rep][d] row-major FP32; x: [n_atoms][d] FP32 out.
+ *   1 <= n_elements <= 256 (else SORF_ERR_UNSUPPORTED), d_rep >= 1, 1 <= d <= 2^20.
+ *   workspace: at least sorf_project_workspace_bytes(n_atoms, n_elements), 256-byte aligned.
+ *   x is deterministic: every row depends on its own rho row only. */
+sorf_status sorf_project(int64_t n_atoms, int32_t d_rep, const float* rho, const int32_t* element,
+                         int32_t n_elements, const float* U, int32_t d, float* x,
+                         void* workspace, size_t workspace_bytes, sorf_stream_t stream);
+
 /* Bytes of workspace sorf_gram_accumulate needs for n_rows rows of D features in the given
  * precision (host-only query): the FP32 mode needs only the Z^T y partials (D * 8 bytes per
  * 1024 rows); the 16-bit modes also hold Z packed once in matrix-core fragment order

@@ -305,7 +305,10 @@ def projection_fit(rho_sample, n_pca: int):
     (Z~_e = U_e S_e V_e^T, SORF subsection), each column's sign fixed so that
     its entry of largest magnitude is positive (the SVD leaves the sign free).
     rho_sample: [n_samples, d_rep]. Returns (U [d_rep, n_pca], s [n_pca]) in
-    float64; the singular values come in decreasing order."""
+    float64; the singular values come in decreasing order. The columns are
+    unique (up to the sign fixed here) only where the singular values are
+    distinct and nonzero, so the sample needs at least n_pca rows of rank
+    n_pca."""
     Zt = np.asarray(rho_sample, dtype=np.float64).T
     U, s, _ = np.linalg.svd(Zt, full_matrices=False)
     U = U[:, :n_pca].copy()

@@ -22,7 +22,8 @@ GRAM_MODES = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16_hilo": 3, "fp16_hilo": 4}
 # every function the header declares; the load test checks each is exported
 EXPORTS = (
     "sorf_abi_version", "sorf_status_string", "sorf_forward", "sorf_backward",
-    "sorf_derivative_features",
+    "sorf_derivative_features", "sorf_project_workspace_bytes", "sorf_project",
+    "sorf_projection_fit_workspace_bytes", "sorf_projection_fit",
     "sorf_gram_workspace_bytes", "sorf_gram_accumulate", "sorf_gram_accumulate_f64",
     "sorf_solve_workspace_bytes",
     "sorf_solve", "sorf_solve_f64",
@@ -80,6 +81,10 @@ def load() -> ctypes.CDLL:
         "sorf_forward": (ctypes.c_int, [MP, BP, P, P]),
         "sorf_backward": (ctypes.c_int, [MP, BP, P, P, P, P]),
         "sorf_derivative_features": (ctypes.c_int, [MP, BP, P, P, P, P]),
+        "sorf_project_workspace_bytes": (sz, [i64, i32]),
+        "sorf_project": (ctypes.c_int, [i64, i32, P, P, i32, P, i32, P, P, sz, P]),
+        "sorf_projection_fit_workspace_bytes": (sz, [i32]),
+        "sorf_projection_fit": (ctypes.c_int, [i64, i32, P, i32, P, P, P, sz, P]),
         "sorf_gram_workspace_bytes": (sz, [i64, i32, ctypes.c_int]),
         "sorf_gram_accumulate": (ctypes.c_int, [i64, i32, P, P, ctypes.c_int, i32, P, P, P, sz,
                                                 P]),

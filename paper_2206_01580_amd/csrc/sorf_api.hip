@@ -115,6 +115,47 @@ sorf_status sorf_derivative_features(const sorf_model* model, const sorf_batch* 
   return dev(sorf_launch_dz(pack(model, batch), J, J_ptr, dZ, hipStream_t(stream)));
 }
 
+size_t sorf_project_workspace_bytes(int64_t n_atoms, int32_t n_elements) {
+  if (n_atoms < 0 || n_atoms > (int64_t(1) << 40) || n_elements < 1 || n_elements > 256) return 0;
+  return sorf_project_ws_bytes(n_atoms, n_elements);
+}
+
+sorf_status sorf_project(int64_t n_atoms, int32_t d_rep, const float* rho, const int32_t* element,
+                         int32_t n_elements, const float* U, int32_t d, float* x,
+                         void* workspace, size_t workspace_bytes, sorf_stream_t stream) {
+  if (n_atoms < 0 || n_atoms > (int64_t(1) << 40)) return SORF_ERR_INVALID_ARG;
+  if (d_rep < 1 || d < 1 || d > (1 << 20) || n_elements < 1) return SORF_ERR_INVALID_ARG;
+  if (n_elements > 256) return SORF_ERR_UNSUPPORTED;
+  if (int64_t(d_rep) * d * n_elements > (int64_t(1) << 40)) return SORF_ERR_INVALID_ARG;
+  if (n_atoms == 0) return SORF_OK;
+  if (rho == nullptr || element == nullptr || U == nullptr || x == nullptr)
+    return SORF_ERR_INVALID_ARG;
+  const size_t need = sorf_project_ws_bytes(n_atoms, n_elements);
+  if (workspace == nullptr || workspace_bytes < need) return SORF_ERR_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  return dev(sorf_launch_project(n_atoms, d_rep, rho, element, n_elements, U, d, x, workspace,
+                                 hipStream_t(stream)));
+}
+
+size_t sorf_projection_fit_workspace_bytes(int32_t d_rep) {
+  if (d_rep < 1 || d_rep > 4096) return 0;
+  return sorf_fit_ws_bytes(d_rep);
+}
+
+sorf_status sorf_projection_fit(int64_t n_samples, int32_t d_rep, const float* sample,
+                                int32_t n_pca, float* U, double* singular_values,
+                                void* workspace, size_t workspace_bytes, sorf_stream_t stream) {
+  if (d_rep < 1 || n_pca < 1 || n_pca > d_rep || n_samples < 0) return SORF_ERR_INVALID_ARG;
+  if (d_rep > 4096) return SORF_ERR_UNSUPPORTED;
+  if (n_samples > (int64_t(1) << 40)) return SORF_ERR_INVALID_ARG;
+  if (U == nullptr || (n_samples > 0 && sample == nullptr)) return SORF_ERR_INVALID_ARG;
+  const size_t need = sorf_fit_ws_bytes(d_rep);
+  if (workspace == nullptr || workspace_bytes < need) return SORF_ERR_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  return dev(sorf_launch_projection_fit(n_samples, d_rep, sample, n_pca, U, singular_values,
+                                        workspace, hipStream_t(stream)));
+}
+
 size_t sorf_gram_workspace_bytes(int64_t n_rows, int32_t D, sorf_gram_precision precision) {
   if (n_rows < 0 || D < 1 || D > (1 << 20)) return 0;
   if (int(precision) < 0 || int(precision) > 4) return 0;

@@ -214,6 +214,15 @@ hipError_t sorf_launch_molecule_reduce(const SorfFeatureArgs& a, const float* e_
 // Derivative features dZ [3 n_atoms][D] (rows of the force-trained normal equation).
 hipError_t sorf_launch_dz(const SorfFeatureArgs& a, const float* J, const int64_t* J_ptr,
                           float* dZ, hipStream_t s);
+// Per-element projection x_i = rho_i^T U_{e_i}; workspace: bucket counts, offsets and list.
+size_t sorf_project_ws_bytes(int64_t n_atoms, int32_t n_elements);
+hipError_t sorf_launch_project(int64_t n_atoms, int32_t d_rep, const float* rho,
+                               const int32_t* element, int32_t n_elements, const float* U,
+                               int32_t d, float* x, void* ws, hipStream_t s);
+// Fit of one element's projection: top n_pca eigenvectors of sum rho^T rho (FP64 Jacobi).
+size_t sorf_fit_ws_bytes(int32_t d_rep);
+hipError_t sorf_launch_projection_fit(int64_t n_samples, int32_t d_rep, const float* sample,
+                                      int32_t n_pca, float* U, double* sv, void* ws, hipStream_t s);
 hipError_t sorf_launch_validate(const SorfFeatureArgs& a, int32_t* result, hipStream_t s);
 hipError_t sorf_launch_fill(float* p, int64_t n, float v, hipStream_t s);
 

@@ -178,6 +178,65 @@ def derivative_features(model: Model, batch: Batch, J: torch.Tensor, J_ptr: torc
     return out
 
 
+class Projector:
+    """Per-element projection x_i = rho_i^T U_{e_i} (sorf_project); owns its
+    workspace. U: [n_elements, d_rep, d] float32 on the device."""
+
+    def __init__(self, U: torch.Tensor):
+        _need(U, torch.float32, "U")
+        if U.dim() != 3:
+            raise ValueError("U must be [n_elements, d_rep, d]")
+        self.U = U
+        self.ws = torch.empty(0, dtype=torch.uint8, device=U.device)
+
+    def __call__(self, rho: torch.Tensor, element: torch.Tensor,
+                 out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        E, d_rep, d = self.U.shape
+        A = element.numel()
+        _need(rho, torch.float32, "rho", A * d_rep)
+        _need(element, torch.int32, "element", A)
+        if out is None:
+            out = torch.empty((A, d), dtype=torch.float32, device=rho.device)
+        _need(out, torch.float32, "x", A * d)
+        lib = _lib.load()
+        need = lib.sorf_project_workspace_bytes(A, E)
+        if self.ws.numel() < need + 256:
+            self.ws = torch.empty(need + 256, dtype=torch.uint8, device=rho.device)
+        wptr = self.ws.data_ptr() + (-self.ws.data_ptr()) % 256
+        _lib.check("sorf_project", lib.sorf_project(
+            A, d_rep, _ptr(rho), _ptr(element), E, _ptr(self.U), d, _ptr(out), wptr, need,
+            _stream()))
+        return out
+
+
+def projection_fit(sample: torch.Tensor, n_pca: int, out: Optional[torch.Tensor] = None,
+                   singular_values: Optional[torch.Tensor] = None):
+    """U [d_rep, n_pca] (FP32) and the singular values [n_pca] (FP64) of one
+    element's sampled representations [n_samples, d_rep] (sorf_projection_fit)."""
+    _need(sample, torch.float32, "sample")
+    n, d_rep = sample.shape
+    dev = sample.device
+    if out is None:
+        out = torch.empty((d_rep, n_pca), dtype=torch.float32, device=dev)
+    _need(out, torch.float32, "U", d_rep * n_pca)
+    if singular_values is None:
+        singular_values = torch.empty(n_pca, dtype=torch.float64, device=dev)
+    _need(singular_values, torch.float64, "singular_values", n_pca)
+    lib = _lib.load()
+    need = lib.sorf_projection_fit_workspace_bytes(d_rep)
+    ws = torch.empty(need + 256, dtype=torch.uint8, device=dev)
+    wptr = ws.data_ptr() + (-ws.data_ptr()) % 256
+    _lib.check("sorf_projection_fit", lib.sorf_projection_fit(
+        n, d_rep, _ptr(sample), n_pca, _ptr(out), _ptr(singular_values), wptr, need, _stream()))
+    return out, singular_values
+
+
+def project(rho: torch.Tensor, element: torch.Tensor, U: torch.Tensor,
+            out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """x [n_atoms, d] = rho_i^T U_{e_i} (sorf_project)."""
+    return Projector(U)(rho, element, out)
+
+
 class GramWorkspace:
     """Reusable device workspace for sorf_gram_accumulate (grows on demand)."""
 

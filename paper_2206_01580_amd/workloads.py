@@ -253,6 +253,64 @@ class ServingTrace:
         return host_normal(self.J_pool_floats, self.J_seed, 0.1)
 
 
+# Representation vectors ahead of the projection. The FCHL19 representation
+# with the energy+force parameters (n2 = 24 two-body bins per element, n3 = 20
+# three-body radial bins times the cosine and sine terms per element pair)
+# has 5 * 24 + 15 * 20 * 2 = 720 entries for five elements. Synthetic stand-in:
+# per element a nonnegative mean plus a rank-256 Gaussian part with a decaying
+# spectrum (scale 2^(-j/32) along direction j), so that a few hundred
+# directions carry the variance, as in a real representation set.
+FCHL19_EF_SIZE = 720
+
+
+def representation_model(seed: int, n_elements: int, d_rep: int, rank: int = 256):
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 2])))
+    mu = np.abs(rng.standard_normal((n_elements, d_rep)))
+    L = rng.standard_normal((n_elements, d_rep, rank)) / math.sqrt(rank)
+    scale = 2.0 ** (-np.arange(rank) / 32.0)
+    return mu, L, scale
+
+
+def host_representations(element: np.ndarray, n_elements: int, d_rep: int, seed: int,
+                         rank: int = 256) -> np.ndarray:
+    """rho [A, d_rep] float32 for the atoms' elements (host, for tests)."""
+    mu, L, scale = representation_model(seed, n_elements, d_rep, rank)
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 3])))
+    g = rng.standard_normal((len(element), rank)) * scale[None, :]
+    rho = np.empty((len(element), d_rep), dtype=np.float64)
+    for e in range(n_elements):
+        sel = np.nonzero(np.asarray(element) == e)[0]
+        rho[sel] = mu[e][None, :] + g[sel] @ L[e].T
+    return rho.astype(np.float32)
+
+
+def device_representations(element, n_elements: int, d_rep: int, seed: int, rank: int = 256,
+                           device="cuda"):
+    """The same distribution drawn on the device (for the benchmark's sizes)."""
+    import torch
+    mu, L, scale = representation_model(seed, n_elements, d_rep, rank)
+    el = torch.as_tensor(np.asarray(element), device=device)
+    g = device_normal(len(element) * rank, seed + 3, 1.0, device).view(len(element), rank)
+    g.mul_(torch.as_tensor(scale, dtype=torch.float32, device=device))
+    rho = torch.empty((len(element), d_rep), dtype=torch.float32, device=device)
+    for e in range(n_elements):
+        sel = torch.nonzero(el == e).flatten()
+        Le = torch.as_tensor(L[e].T.copy(), dtype=torch.float32, device=device)
+        rho[sel] = torch.as_tensor(mu[e], dtype=torch.float32, device=device) + g[sel] @ Le
+    return rho
+
+
+def random_projection(seed: int, n_elements: int, d_rep: int, d: int) -> np.ndarray:
+    """U [E, d_rep, d] float32 with orthonormal columns (Q of a Gaussian matrix):
+    a stand-in for fitted projections where only their shape matters."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 4])))
+    U = np.empty((n_elements, d_rep, d), dtype=np.float32)
+    for e in range(n_elements):
+        q, _ = np.linalg.qr(rng.standard_normal((d_rep, d)))
+        U[e] = q.astype(np.float32)
+    return U
+
+
 def host_normal(n: int, seed: int, std: float) -> np.ndarray:
     """n float32 draws of N(0, std^2) from PCG64(seed)."""
     rng = np.random.Generator(np.random.PCG64(seed))
