@@ -99,6 +99,8 @@ def parse():
     ap.add_argument("--force-confs", type=int, default=2000,
                     help="conformations of the force-training leg (0 skips it)")
     ap.add_argument("--force-steps", type=int, default=3)
+    ap.add_argument("--projection", type=int, default=1,
+                    help="run the per-element projection leg (0 skips it)")
     ap.add_argument("--precision-mols", type=int, default=100000,
                     help="molecules of the precision study (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -257,6 +259,69 @@ def force_training_leg(args, dev, log):
             "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
             "sample": f"FP64 dense-W oracle, dZ of 4 conformations ({3 * q.n_atoms} rows), {t_o:.2f} s"}
     del Z, dZ, G, r, ws, solver, J
+    torch.cuda.empty_cache()
+    return out
+
+
+def projection_leg(args, p, dev, log):
+    """Per-element projection on the QM9-like batch: every atom's 720-entry
+    representation (the FCHL19 size for five elements with the energy+force
+    parameters; synthetic, drawn on the device) projected to d = 128 with a
+    matrix per element, fitted on the GPU from 1000 sampled atoms of that
+    element."""
+    import torch
+
+    from paper_2206_01580_amd import sorf, workloads
+    d_rep, d, E = workloads.FCHL19_EF_SIZE, p.d, p.n_elements
+    el = torch.from_numpy(p.element).to(dev)
+    rho = workloads.device_representations(p.element, E, d_rep, seed=p.seed + 5, device=dev)
+    U = torch.empty((E, d_rep, d), dtype=torch.float32, device=dev)
+    rng = np.random.default_rng(p.seed + 6)
+    fit_ms = []
+    for e in range(E):
+        rows = np.nonzero(p.element == e)[0]
+        rows = np.sort(rng.choice(rows, size=min(len(rows), 1000), replace=False))
+        sample = rho.index_select(0, torch.from_numpy(rows).to(dev)).contiguous()
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        sorf.projection_fit(sample, d, out=U[e])
+        e1.record()
+        torch.cuda.synchronize()
+        fit_ms.append(e0.elapsed_time(e1))
+    proj = sorf.Projector(U)
+    x = torch.empty((p.n_atoms, d), dtype=torch.float32, device=dev)
+    proj(rho, el, x)
+    torch.cuda.synchronize()
+    e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    n = max(3, args.steps)
+    e0.record()
+    for _ in range(n):
+        proj(rho, el, x)
+    e1.record()
+    torch.cuda.synchronize()
+    ms = e0.elapsed_time(e1) / n
+    flop = 2.0 * p.n_atoms * d_rep * d
+    tf = flop / (ms * 1e-3) / 1e12
+    out = {
+        "workload": (f"{p.n_atoms} atoms of the QM9-like batch, representations of {d_rep} entries "
+                     f"-> d={d}, {E} elements, projections fitted from 1000 atoms per element"),
+        "project_ms": ms, "fit_ms_per_element": fit_ms,
+        "roofline": {"bound": "mfma", "achieved": tf, "peak": PEAK_MFMA_TFLOPS["fp32"],
+                     "unit": "TFLOP/s", "frac": tf / PEAK_MFMA_TFLOPS["fp32"], "traffic": None,
+                     "algorithmic_bytes": 4.0 * p.n_atoms * (d_rep + d)},
+    }
+    if not args.no_cpu_baseline:
+        from oracle import sorf_oracle as O
+        k = min(100000, p.n_atoms)
+        rows = np.arange(k)
+        rho_h = rho[:k].cpu().numpy()
+        Uh = U.cpu().numpy()
+        t0 = time.perf_counter()
+        O.project(rho_h, p.element[rows], Uh)
+        t = time.perf_counter() - t0
+        out["cpu_baseline"] = {"value": k / t, "unit": "atoms/s", "cores": len(os.sched_getaffinity(0)),
+                               "kind": "oracle", "sample": f"FP64 oracle projection of {k} atoms, {t:.2f} s"}
+    del rho, x, U, proj
     torch.cuda.empty_cache()
     return out
 
@@ -529,6 +594,9 @@ def main():
             serving_leg(args, dev, log, r, args.serve_sweep_requests / r) for r in sweep]
     if args.force_confs > 0:
         out["force_training"] = force_training_leg(args, dev, log)
+    if args.projection:
+        log("projection")
+        out["projection"] = projection_leg(args, p, dev, log)
     if args.precision_mols > 0:
         out["precision_study"] = precision_study(args, dev, log)
     if not args.no_cpu_baseline:
