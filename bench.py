@@ -101,6 +101,8 @@ def parse():
     ap.add_argument("--force-steps", type=int, default=3)
     ap.add_argument("--projection", type=int, default=1,
                     help="run the per-element projection leg (0 skips it)")
+    ap.add_argument("--ntransform-study", type=int, default=1,
+                    help="run the N_transform study (0 skips it)")
     ap.add_argument("--precision-mols", type=int, default=100000,
                     help="molecules of the precision study (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -324,6 +326,65 @@ def projection_leg(args, p, dev, log):
     del rho, x, U, proj
     torch.cuda.empty_cache()
     return out
+
+
+def ntransform_study(args, p, dev, log):
+    """N_transform in {1, 2, 3} on the QM9-like batch (the paper runs T = 2,
+    the main step T = 3): forward and dE/dx times at full size, and the
+    kernel-approximation error of the features: over 256 carbon atoms,
+    ||Zhat Zhat^T - K||_F / ||K||_F against the Gaussian kernel
+    K_ij = exp(-|x_i - x_j|^2 / (2 sigma^2)) the estimator approximates,
+    using the first N_F features (N_F = 1024 .. 8192). The feature map keeps
+    its sqrt(2/N_F) normaliser for each N_F."""
+    import torch
+
+    from paper_2206_01580_amd import sorf, workloads
+    C = p.element_names.index("C")
+    rows = np.nonzero(p.element == C)[0][:256]
+    xs = p.x[rows].astype(np.float64)
+    sq = np.sum((xs[:, None, :] - xs[None, :, :]) ** 2, axis=2)
+    K = np.exp(-sq / (2.0 * p.sigma ** 2))
+    res = {}
+    for T in (1, 2, 3):
+        q = workloads.with_transforms(p, T)
+        model, batch = sorf.Model.from_problem(q), sorf.Batch.from_problem(q)
+        alpha = torch.from_numpy(q.alpha if q.alpha is not None else
+                                 np.ones(q.n_features, np.float32)).to(dev)
+        Z = torch.empty(q.n_mols, q.n_features, device=dev)
+        g = torch.empty(q.n_atoms, q.d, device=dev)
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(4)]
+        sorf.forward(model, batch, out=Z)
+        sorf.backward(model, batch, alpha, out=g)
+        torch.cuda.synchronize()
+        n = 3
+        ev[0].record()
+        for _ in range(n):
+            sorf.forward(model, batch, out=Z)
+        ev[1].record()
+        for _ in range(n):
+            sorf.backward(model, batch, alpha, out=g)
+        ev[2].record()
+        torch.cuda.synchronize()
+        f_ms, b_ms = ev[0].elapsed_time(ev[1]) / n, ev[1].elapsed_time(ev[2]) / n
+        # single-atom molecules of the 256 carbon atoms
+        a = workloads.Problem(q.name, q.d, q.n_stacks, T, q.sigma, q.element_names,
+                              np.ascontiguousarray(q.x[rows]), np.full(len(rows), C, np.int32),
+                              np.arange(len(rows) + 1, dtype=np.int64), q.signs, q.bias)
+        Za = sorf.forward(sorf.Model.from_problem(a), sorf.Batch.from_problem(a)).double()
+        err = {}
+        for nf in (1024, 2048, 4096, 8192):
+            Zs = Za[:, :nf] * math.sqrt(q.n_features / nf)
+            Kh = (Zs @ Zs.T).cpu().numpy()
+            err[str(nf)] = float(np.linalg.norm(Kh - K) / np.linalg.norm(K))
+        res[f"T{T}"] = {"forward_ms": f_ms, "backward_ms": b_ms,
+                        "forward_atom_features_per_s": q.n_atoms * q.n_features / (f_ms * 1e-3),
+                        "kernel_rel_err_by_nf": err}
+        del Z, g, model, batch
+        torch.cuda.empty_cache()
+        log(f"ntransform: T={T} done")
+    return {"workload": (f"{p.n_atoms} atoms of the QM9-like batch, D={p.n_features}; kernel error over "
+                         f"{len(rows)} carbon atoms against exp(-|dx|^2/(2 sigma^2)), sigma={p.sigma:g}"),
+            "by_T": res}
 
 
 def precision_study(args, dev, log):
@@ -597,6 +658,8 @@ def main():
     if args.projection:
         log("projection")
         out["projection"] = projection_leg(args, p, dev, log)
+    if args.ntransform_study:
+        out["ntransform_study"] = ntransform_study(args, p, dev, log)
     if args.precision_mols > 0:
         out["precision_study"] = precision_study(args, dev, log)
     if not args.no_cpu_baseline:

@@ -230,6 +230,16 @@ def config3(n_conf: int = 2000, seed_offset: int = 0, with_J: bool = True) -> Pr
                    signs, bias, alpha=alpha, J=J, J_ptr=J_ptr, seed=seed)
 
 
+def with_transforms(p: Problem, T: int) -> Problem:
+    """The same workload with N_transform = T: the first T sign diagonals of
+    every element and stack (the paper's runs use T = 2; the studies compare
+    T = 1, 2, 3 on otherwise identical inputs)."""
+    if not 1 <= T <= p.signs.shape[1]:
+        raise ValueError(f"T must be in [1, {p.signs.shape[1]}]")
+    return dataclasses.replace(p, name=f"{p.name}-T{T}", n_transforms=T,
+                               signs=np.ascontiguousarray(p.signs[:, :T]))
+
+
 @dataclasses.dataclass
 class ServingTrace:
     """Arrival trace of energy+force requests plus the resident model.
