@@ -32,7 +32,7 @@ if ROOT not in sys.path:
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16_hilo": 2500.0,
-                    "fp16_hilo": 2500.0, "fp64": 78.6}
+                    "fp16_hilo": 2500.0, "fp64": 78.6, "fp32_kahan": 157.3}
 # VALU issue ceiling derived from unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 39.3 T lane-instructions/s (packed FP32, which would double it, is disabled in this build)
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -433,7 +433,7 @@ def precision_study(args, dev, log):
     log(f"precision: reference done (info {info_ref})")
     G = torch.empty(D, D, device=dev)
     r = torch.empty(D, device=dev)
-    for mode in ("fp32", "bf16", "fp16", "bf16_hilo", "fp16_hilo"):
+    for mode in ("fp32", "fp32_kahan", "bf16", "fp16", "bf16_hilo", "fp16_hilo"):
         G.zero_()
         r.zero_()
         k = sorf.fp16_scale_exp(29 * math.sqrt(2.0 / D)) if mode.startswith("fp16") else 0

@@ -63,7 +63,10 @@ typedef enum {
   SORF_GRAM_FP16 = 2,        /* one fp16 product hi^T hi, FP32 accumulation */
   SORF_GRAM_BF16_HILO = 3,   /* (hi + lo)^T (hi + lo), four bf16 products, hi = bf16(z),
                                 lo = bf16(z - hi); the Gram of hi + lo, so it stays PSD */
-  SORF_GRAM_FP16_HILO = 4    /* the same with fp16 parts of 2^scale_exp * z */
+  SORF_GRAM_FP16_HILO = 4,   /* the same with fp16 parts of 2^scale_exp * z */
+  SORF_GRAM_FP32_KAHAN = 5   /* FP32 as mode 0, with each 256-row block sum added into the
+                                running FP32 sum by Kahan's compensated summation (the
+                                paper's FP32 training mode, Timings subsection) */
 } sorf_gram_precision;
 
 /* Model parameters (host struct; the arrays it points to are device-resident).

@@ -365,7 +365,8 @@ def gram_emulated(Z, mode: str, scale_exp: int = 0) -> np.ndarray:
     """The Gram matrix each reduced-precision mode must produce when its
     products are exact and accumulation error is ignored (float64 sums):
 
-    * 'fp32'       Z^T Z of the float32 values
+    * 'fp32', 'fp32_kahan'  Z^T Z of the float32 values (the modes differ
+                   only in how their accumulation rounds)
     * 'bf16'/'fp16'      hi^T hi
     * 'bf16_hilo'/'fp16_hilo'  (hi + lo)^T (hi + lo), all four products
 
@@ -373,7 +374,7 @@ def gram_emulated(Z, mode: str, scale_exp: int = 0) -> np.ndarray:
     the result is the Gram matrix of the two-term approximation hi + lo and
     stays positive semidefinite, as the normal equations require."""
     Z32 = np.asarray(Z, dtype=np.float32)
-    if mode == "fp32":
+    if mode in ("fp32", "fp32_kahan"):
         Zd = Z32.astype(np.float64)
         return Zd.T @ Zd
     kind = mode.split("_")[0]

@@ -17,7 +17,8 @@ SORF_ERR_UNSUPPORTED = 2
 SORF_ERR_DEVICE = 3
 SORF_ERR_WORKSPACE = 4
 
-GRAM_MODES = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16_hilo": 3, "fp16_hilo": 4}
+GRAM_MODES = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16_hilo": 3, "fp16_hilo": 4,
+              "fp32_kahan": 5}
 
 # every function the header declares; the load test checks each is exported
 EXPORTS = (

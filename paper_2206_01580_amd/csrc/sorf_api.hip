@@ -158,7 +158,7 @@ sorf_status sorf_projection_fit(int64_t n_samples, int32_t d_rep, const float* s
 
 size_t sorf_gram_workspace_bytes(int64_t n_rows, int32_t D, sorf_gram_precision precision) {
   if (n_rows < 0 || D < 1 || D > (1 << 20)) return 0;
-  if (int(precision) < 0 || int(precision) > 4) return 0;
+  if (int(precision) < 0 || int(precision) > 5) return 0;
   return sorf_gram_ws_bytes(n_rows, D, int(precision));
 }
 
@@ -167,7 +167,7 @@ sorf_status sorf_gram_accumulate(int64_t n_rows, int32_t D, const float* Z, cons
                                  float* Zty, void* workspace, size_t workspace_bytes,
                                  sorf_stream_t stream) {
   if (n_rows < 0 || D < 1 || D > (1 << 20)) return SORF_ERR_INVALID_ARG;
-  if (int(precision) < 0 || int(precision) > 4) return SORF_ERR_INVALID_ARG;
+  if (int(precision) < 0 || int(precision) > 5) return SORF_ERR_INVALID_ARG;
   if (scale_exp < -60 || scale_exp > 60) return SORF_ERR_INVALID_ARG;
   if (scale_exp != 0 && precision != SORF_GRAM_FP16 && precision != SORF_GRAM_FP16_HILO)
     return SORF_ERR_INVALID_ARG;

@@ -41,7 +41,7 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
 
-enum GramMode { kFP32 = 0, kBF16 = 1, kFP16 = 2, kBF16HiLo = 3, kFP16HiLo = 4 };
+enum GramMode { kFP32 = 0, kBF16 = 1, kFP16 = 2, kBF16HiLo = 3, kFP16HiLo = 4, kFP32Kahan = 5 };
 
 constexpr int KB = 16;                 // rows per fragment / FP32 stage
 constexpr int TM = 256, TN = 128;      // workgroup tile
@@ -709,11 +709,37 @@ static int64_t x1_grid(const X1Plan& p) {
   return 8 * m;
 }
 
+// Flush of the block sum P (kFlushRows rows on the matrix cores) into the
+// running FP32 sum S. With KAHAN (the paper's FP32 training mode) the flush is
+// compensated: the rounding error of each S += P is carried in C and
+// subtracted from the next block (y = P - C; t = S + y; C = (t - S) - y; S = t).
+template <bool KAHAN, int NA>
+__device__ __forceinline__ void flush_sum(f32x16 (&P)[4][2], f32x16 (&S)[4][2],
+                                          f32x16 (&C)[NA][2]) {
+#pragma unroll
+  for (int a = 0; a < 4; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) {
+        if constexpr (KAHAN) {
+          const float y = P[a][b][r] - C[a][b][r];
+          const float t = S[a][b][r] + y;
+          C[a][b][r] = (t - S[a][b][r]) - y;
+          S[a][b][r] = t;
+        } else {
+          S[a][b][r] += P[a][b][r];
+        }
+        P[a][b][r] = 0.0f;
+      }
+}
+
 // ------------------------------------------------ FP32 mode, D % 4 == 0
 // Stage = 16 rows of Z: 16 A rows of 256 floats (one wave copy each) and 16 B
 // rows of 128 floats (one copy per pair of rows), in a ring of 4 stages.
 // Rows past M are copied from a 1 KB block of zeros; columns past D are
 // clamped into the row (they only reach G entries that are never written).
+template <bool KAHAN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
                            int64_t nI, int64_t nJ, const float* __restrict__ zeros,
@@ -756,6 +782,7 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
   };
 
   f32x16 P[4][2], S[4][2];
+  f32x16 Cc[KAHAN ? 4 : 1][2];   // Kahan compensation of S (mode 5 only)
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -764,6 +791,7 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
       for (int r = 0; r < 16; ++r) {
         P[a][b][r] = 0.0f;
         S[a][b][r] = 0.0f;
+        if (KAHAN) Cc[KAHAN ? a : 0][b][r] = 0.0f;
       }
 
 #pragma unroll
@@ -797,15 +825,7 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
             P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][a], bf[kk][b], P[a][b], 0, 0, 0);
       slot = slot + 1 == NS ? 0 : slot + 1;
     }
-#pragma unroll
-    for (int a = 0; a < 4; ++a)
-#pragma unroll
-      for (int b = 0; b < 2; ++b)
-#pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          S[a][b][r] += P[a][b][r];
-          P[a][b][r] = 0.0f;
-        }
+    flush_sum<KAHAN>(P, S, Cc);
   }
 
   if (!active) return;
@@ -825,7 +845,7 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
 // Row-major slabs of 16 rows staged through registers into LDS ([k][column],
 // padded) with masked loads; the 32x32x2 f32 MFMA reads lane l = column l%32
 // of slab row k0 + l/32. Used when D is not a multiple of 4.
-template <bool VEC4>
+template <bool VEC4, bool KAHAN>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
 void gram_fp32_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
                       int64_t nI, int64_t nJ, float* __restrict__ G) {
@@ -847,6 +867,7 @@ void gram_fp32_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t
   const int64_t A0 = I * TM, B0 = J * TN;
 
   f32x16 P[4][2], S[4][2];
+  f32x16 Cc[KAHAN ? 4 : 1][2];   // Kahan compensation of S (mode 5 only)
 #pragma unroll
   for (int a = 0; a < 4; ++a)
 #pragma unroll
@@ -855,6 +876,7 @@ void gram_fp32_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t
       for (int r = 0; r < 16; ++r) {
         P[a][b][r] = 0.0f;
         S[a][b][r] = 0.0f;
+        if (KAHAN) Cc[KAHAN ? a : 0][b][r] = 0.0f;
       }
 
   float4 pa[CA], pb[CB];
@@ -919,17 +941,7 @@ void gram_fp32_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t
           for (int b = 0; b < 2; ++b)
             P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[a], bf[b], P[a][b], 0, 0, 0);
       }
-      if ((s + 1) % KC == 0 || s + 1 == n_stages) {
-#pragma unroll
-        for (int a = 0; a < 4; ++a)
-#pragma unroll
-          for (int b = 0; b < 2; ++b)
-#pragma unroll
-            for (int r = 0; r < 16; ++r) {
-              S[a][b][r] += P[a][b][r];
-              P[a][b][r] = 0.0f;
-            }
-      }
+      if ((s + 1) % KC == 0 || s + 1 == n_stages) flush_sum<KAHAN>(P, S, Cc);
     }
     if (s + 1 < n_stages) store(buf ^ 1);
     __syncthreads();
@@ -1090,7 +1102,7 @@ size_t sorf_gram_ws_bytes(int64_t n_rows, int32_t D, int mode) {
   if (n_rows <= 0 || D <= 0) return 0;
   const GramLayout g = gram_layout(n_rows, D);
   size_t b = g.zpart_bytes + kZeroBytes;
-  if (mode != kFP32) b += g.part_bytes * (is_hilo(mode) ? 2 : 1);
+  if (mode != kFP32 && mode != kFP32Kahan) b += g.part_bytes * (is_hilo(mode) ? 2 : 1);
   if (mode == kBF16 || mode == kFP16) b += x1_partial_bytes(n_rows, D);
   return b;
 }
@@ -1109,6 +1121,7 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
   const dim3 pgrid{unsigned(g.ncb / 4), unsigned(g.chunks)}, blk{256};
   switch (mode) {
     case kFP32:
+    case kFP32Kahan:
       if (y != nullptr)
         hipLaunchKernelGGL(pack_kernel<kFP32>, pgrid, blk, 0, st, Z, n_rows, D, g.n_slabs, g.ncb,
                            1.0f, hi, lo, y, zpart);
@@ -1144,15 +1157,23 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
   const dim3 grid{unsigned(((gram_super_tiles(D) + 7) / 8) * 8 * SR_T * SC_T)};
   switch (mode) {
     case kFP32:
+    case kFP32Kahan:
       if (D % 4 == 0) {
         if ((e = sorf_launch_fill(zeros, int64_t(kZeroBytes / sizeof(float)), 0.0f, st)) !=
             hipSuccess)
           return e;
-        hipLaunchKernelGGL(gram_fp32_ring_kernel, grid, blk, 0, st, Z, n_rows, D, n_tiles, nI, nJ,
-                           zeros, G);
+        if (mode == kFP32Kahan)
+          hipLaunchKernelGGL(gram_fp32_ring_kernel<true>, grid, blk, 0, st, Z, n_rows, D, n_tiles,
+                             nI, nJ, zeros, G);
+        else
+          hipLaunchKernelGGL(gram_fp32_ring_kernel<false>, grid, blk, 0, st, Z, n_rows, D, n_tiles,
+                             nI, nJ, zeros, G);
+      } else if (mode == kFP32Kahan) {
+        hipLaunchKernelGGL((gram_fp32_kernel<false, true>), grid, blk, 0, st, Z, n_rows, D,
+                           n_tiles, nI, nJ, G);
       } else {
-        hipLaunchKernelGGL(gram_fp32_kernel<false>, grid, blk, 0, st, Z, n_rows, D, n_tiles, nI,
-                           nJ, G);
+        hipLaunchKernelGGL((gram_fp32_kernel<false, false>), grid, blk, 0, st, Z, n_rows, D,
+                           n_tiles, nI, nJ, G);
       }
       break;
     case kBF16:

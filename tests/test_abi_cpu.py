@@ -137,7 +137,8 @@ def test_gram_argument_checks(lib):
     E = _lib.SORF_ERR_INVALID_ARG
     assert G(10, 0, PTR, None, 0, 0, PTR, None, None, 0, None) == E            # D = 0
     assert G(-1, PTR, PTR, None, 0, 0, PTR, None, None, 0, None) == E            # negative rows
-    assert G(10, PTR, PTR, None, 5, 0, PTR, None, None, 0, None) == E            # unknown precision
+    assert G(10, PTR, PTR, None, 6, 0, PTR, None, None, 0, None) == E            # unknown precision
+    assert G(10, PTR, PTR, None, 5, 3, PTR, None, None, 0, None) == E            # no scale for fp32 Kahan
     assert G(10, PTR, PTR, None, 0, 3, PTR, None, None, 0, None) == E            # scale only for fp16 modes
     assert G(10, PTR, PTR, None, 2, 61, PTR, None, None, 0, None) == E           # scale range
     assert G(10, PTR, None, None, 0, 0, PTR, None, None, 0, None) == E         # Z missing

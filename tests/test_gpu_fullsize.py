@@ -24,7 +24,7 @@ from paper_2206_01580_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-UNIT = {"fp32": 0.0, "bf16": 2.0 ** -9, "fp16": 2.0 ** -12, "bf16_hilo": 2.0 ** -17,
+UNIT = {"fp32": 0.0, "fp32_kahan": 0.0, "bf16": 2.0 ** -9, "fp16": 2.0 ** -12, "bf16_hilo": 2.0 ** -17,
         "fp16_hilo": 2.0 ** -23}
 
 
@@ -91,7 +91,7 @@ def test_qm9_feature_columns(qm9):
     assert (np.abs(Zg - Zc) / row_scale).max() <= 1e-5
 
 
-@pytest.mark.parametrize("mode", ["fp32", "bf16", "fp16", "bf16_hilo", "fp16_hilo"])
+@pytest.mark.parametrize("mode", ["fp32", "fp32_kahan", "bf16", "fp16", "bf16_hilo", "fp16_hilo"])
 def test_qm9_gram_sampled(qm9, mode):
     p, Z, cols, Zc = qm9
     s = S()

@@ -270,7 +270,7 @@ def test_autograd_function_matches_central_differences():
 
 
 # ------------------------------------------------------------------ Gram
-@pytest.mark.parametrize("mode", ["fp32", "bf16", "fp16", "bf16_hilo", "fp16_hilo"])
+@pytest.mark.parametrize("mode", ["fp32", "fp32_kahan", "bf16", "fp16", "bf16_hilo", "fp16_hilo"])
 @pytest.mark.parametrize("MD", [(333, 300), (64, 128), (1000, 37), (5, 257), (600, 1100)], ids=lambda t: f"M{t[0]}-D{t[1]}")
 def test_gram_against_emulated_modes(mode, MD):
     M, D = MD
@@ -292,6 +292,30 @@ def test_gram_against_emulated_modes(mode, MD):
     assert np.linalg.norm(diff) <= 1e-6 * np.linalg.norm(Ge[low]) + 1e-6 * np.linalg.norm(G0)
     _, r = O.gram(Z, y)
     assert np.abs(Zty.cpu().numpy() - r).max() <= 1e-6 * np.abs(Z).sum(axis=0).max() * np.abs(y).max()
+
+
+@pytest.mark.parametrize("D", [64, 30], ids=["ring-D64", "slab-D30"])
+def test_kahan_flush_beats_plain_fp32_on_a_long_sum(D):
+    """131,072 rows of positive entries near 1: the running FP32 sum grows to
+    1.3e5 while each 256-row block adds ~256, so plain FP32 flushes lose low
+    bits at every add; the compensated flush keeps them (both against FP64
+    sums of the same FP32 rows)."""
+    M = 1 << 17
+    rng = np.random.default_rng(D)
+    Z = (1.0 + 0.01 * rng.standard_normal((M, D))).astype(np.float32)
+    Zd = Z.astype(np.float64)
+    Ge = Zd.T @ Zd
+    low = np.tril_indices(D)
+    errs = {}
+    for mode in ("fp32", "fp32_kahan"):
+        G = torch.zeros(D, D, device="cuda")
+        S().gram_accumulate(torch.from_numpy(Z).cuda(), G, precision=mode)
+        torch.cuda.synchronize()
+        errs[mode] = float(np.linalg.norm(G.double().cpu().numpy()[low] - Ge[low]) /
+                           np.linalg.norm(Ge[low]))
+    print("relative Frobenius errors:", errs)
+    assert errs["fp32_kahan"] <= 0.2 * errs["fp32"], errs
+    assert errs["fp32_kahan"] <= 1e-6
 
 
 @pytest.mark.parametrize("MD", [(333, 300), (17, 64), (5, 129)], ids=lambda t: f"M{t[0]}-D{t[1]}")

@@ -31,7 +31,7 @@ from paper_2206_01580_amd import workloads as W
 torch = pytest.importorskip("torch")
 pytestmark = pytest.mark.gpu
 
-MODES = ["fp64", "fp32", "bf16_hilo", "fp16_hilo", "fp16", "bf16"]
+MODES = ["fp64", "fp32", "fp32_kahan", "bf16_hilo", "fp16_hilo", "fp16", "bf16"]
 
 
 def _scale_exp(D):
@@ -85,7 +85,7 @@ def test_single_product_modes_reproduce_their_rounding(study, mode):
     assert 0.5 * emulated[mode] <= errs[mode] <= 2.0 * emulated[mode], (errs[mode], emulated[mode])
 
 
-@pytest.mark.parametrize("mode", ["fp32", "bf16_hilo", "fp16_hilo"])
+@pytest.mark.parametrize("mode", ["fp32", "fp32_kahan", "bf16_hilo", "fp16_hilo"])
 def test_fp32_class_modes(study, mode):
     errs = study[0]
     assert errs[mode] <= 2e-3
