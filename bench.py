@@ -103,6 +103,8 @@ def parse():
                     help="run the per-element projection leg (0 skips it)")
     ap.add_argument("--ntransform-study", type=int, default=1,
                     help="run the N_transform study (0 skips it)")
+    ap.add_argument("--roundoff-study", type=int, default=1,
+                    help="run the FP32 round-off study of dense-W RFF vs SORF phases (0 skips it)")
     ap.add_argument("--precision-mols", type=int, default=100000,
                     help="molecules of the precision study (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -387,6 +389,63 @@ def ntransform_study(args, p, dev, log):
             "by_T": res}
 
 
+def roundoff_study(args, p, dev, log):
+    """FP32 round-off of the phases W x: dense Gaussian W (RFF, entries
+    N(0, 1/sigma^2)) against the SORF transform, both in FP32 on the GPU, on
+    the x of 256 carbon atoms of the QM9-like batch (d = 128, sigma = 4). RFF
+    phases come from the FP32 matrix-core product of sorf_project (W^T as a
+    one-element projection); SORF features from sorf_forward on single-atom
+    molecules. Errors against FP64 on the host: the RFF phase error itself, and
+    for both the feature error |dz| in units of sqrt(2/N_F) (for RFF, cos of the
+    FP32 phases taken in FP64, so only the phase round-off counts)."""
+    import torch
+
+    from oracle import sorf_oracle as O
+    from paper_2206_01580_amd import sorf, workloads
+    C = p.element_names.index("C")
+    rows = np.nonzero(p.element == C)[0][:256]
+    x = np.ascontiguousarray(p.x[rows])
+    x64 = x.astype(np.float64)
+    rng = np.random.default_rng(p.seed + 7)
+    out = {}
+    for S in (8, 32, 128):
+        D = S * p.d
+        W = (rng.standard_normal((D, p.d)) / p.sigma).astype(np.float32)
+        b = rng.uniform(0.0, 2.0 * math.pi, D)
+        Ut = torch.from_numpy(np.ascontiguousarray(W.T)[None]).to(dev)
+        u32 = sorf.project(torch.from_numpy(x).to(dev),
+                           torch.zeros(len(rows), dtype=torch.int32, device=dev), Ut)
+        u32 = u32.double().cpu().numpy()
+        u64 = x64 @ W.astype(np.float64).T
+        rff_dz = np.abs(np.cos(u32 + b) - np.cos(u64 + b))
+        # SORF: the same atoms as single-atom molecules, D features of the batch's model
+        signs = p.signs[C:C + 1, :, :S] if S <= p.n_stacks else None
+        if signs is None:
+            rs = np.random.default_rng(p.seed + 8 + S)
+            signs = (1 - 2 * rs.integers(0, 2, size=(1, p.n_transforms, S, p.d))).astype(np.int8)
+        bias = np.ascontiguousarray(b[None].astype(np.float32))
+        a = workloads.Problem("roundoff", p.d, S, p.n_transforms, p.sigma, ("C",), x,
+                              np.zeros(len(rows), np.int32), np.arange(len(rows) + 1, dtype=np.int64),
+                              np.ascontiguousarray(signs), bias)
+        Zs = sorf.forward(sorf.Model.from_problem(a), sorf.Batch.from_problem(a)).double().cpu().numpy()
+        Zo = O.molecule_features(a.x, a.element, a.mol_ptr, a.signs, a.bias, a.sigma)
+        sorf_dz = np.abs(Zs - Zo) / math.sqrt(2.0 / D)
+        uo = O.phases(a.x, a.element, a.signs, a.bias, a.sigma)
+        out[str(D)] = {
+            "rff_phase_err_max": float(np.abs(u32 - u64).max()),
+            "rff_phase_err_rms": float(np.sqrt(np.mean((u32 - u64) ** 2))),
+            "rff_phase_abs_max": float(np.abs(u64).max()),
+            "sorf_phase_abs_max": float(np.abs(uo - a.bias[0].astype(np.float64)).max()),
+            "rff_feature_err_max": float(rff_dz.max()), "rff_feature_err_rms": float(np.sqrt(np.mean(rff_dz ** 2))),
+            "sorf_feature_err_max": float(sorf_dz.max()),
+            "sorf_feature_err_rms": float(np.sqrt(np.mean(sorf_dz ** 2))),
+        }
+        log(f"roundoff: N_F={D} done")
+    return {"workload": (f"x of {len(rows)} carbon atoms of the QM9-like batch (d={p.d}, sigma={p.sigma:g}); "
+                         "errors against FP64, feature errors in units of sqrt(2/N_F)"),
+            "by_nf": out}
+
+
 def precision_study(args, dev, log):
     """Gram precision modes on the precision workload (100,000 QM9-like
     molecules, D = 16384, lambda = 1e-8, 3 refinement steps): coefficient and
@@ -660,6 +719,8 @@ def main():
         out["projection"] = projection_leg(args, p, dev, log)
     if args.ntransform_study:
         out["ntransform_study"] = ntransform_study(args, p, dev, log)
+    if args.roundoff_study:
+        out["roundoff_study"] = roundoff_study(args, p, dev, log)
     if args.precision_mols > 0:
         out["precision_study"] = precision_study(args, dev, log)
     if not args.no_cpu_baseline:
