@@ -321,6 +321,39 @@ def random_projection(seed: int, n_elements: int, d_rep: int, d: int) -> np.ndar
     return U
 
 
+# FCHL19 parameters of the energy+force column of the paper's table (n2, n3,
+# eta2, eta3, N2, N3, c3, zeta, r_cut in Angstrom), and an element list of
+# nuclear charges in the order the representation's bins use.
+FCHL19_EF = dict(n2=24, n3=20, eta2=0.32, eta3=2.7, N2=1.8, N3=0.57, c3=13.4,
+                 zeta=math.pi, rcut=6.0)
+QM9_CHARGES = (1, 6, 7, 8, 9)
+
+
+def molecule_geometry(rng, n: int, bond=(1.0, 1.6), min_dist=0.95) -> np.ndarray:
+    """Coordinates [n, 3] (Angstrom) of a molecule-like cluster: every atom
+    after the first sits at a bond length U[1.0, 1.6] from a random earlier
+    atom, in a random direction, and no two atoms come closer than 0.95."""
+    R = np.zeros((n, 3))
+    for a in range(1, n):
+        for _ in range(1000):
+            base = R[rng.integers(0, a)]
+            v = rng.standard_normal(3)
+            cand = base + rng.uniform(*bond) * v / np.linalg.norm(v)
+            if np.min(np.linalg.norm(R[:a] - cand, axis=1)) >= min_dist:
+                R[a] = cand
+                break
+        else:
+            raise RuntimeError("could not place an atom")
+    return R
+
+
+def host_geometries(sizes, seed: int) -> np.ndarray:
+    """Concatenated coordinates [sum(sizes), 3] float32 of molecules of the given sizes."""
+    rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([seed, 5])))
+    parts = [molecule_geometry(rng, int(n)) for n in sizes]
+    return (np.concatenate(parts) if parts else np.zeros((0, 3))).astype(np.float32)
+
+
 def host_normal(n: int, seed: int, std: float) -> np.ndarray:
     """n float32 draws of N(0, std^2) from PCG64(seed)."""
     rng = np.random.Generator(np.random.PCG64(seed))
