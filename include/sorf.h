@@ -92,6 +92,21 @@ typedef struct {
   int64_t n_mols;          /* >= 0; molecules with zero atoms give zero rows / energies  */
 } sorf_batch;
 
+/* FCHL19 representation parameters (Representation subsection and the parameter table
+ * of Computational Details; the energy+force column is n2 = 24, n3 = 20, eta2 = 0.32,
+ * eta3 = 2.7, N2 = 1.8, N3 = 0.57, c3 = 13.4, zeta = pi, rcut = 6.0 Angstrom). Host struct. */
+typedef struct {
+  int32_t n2;    /* two-body radial bins, centres rcut (k + 1) / n2                       */
+  int32_t n3;    /* three-body radial bins (>= 2), centres rcut k / (n3 - 1)                */
+  float eta2;    /* log-normal width parameter of the two-body term                         */
+  float eta3;    /* width of the three-body radial Gaussians                                */
+  float N2;      /* two-body distance exponent                                              */
+  float N3;      /* three-body (Axilrod-Teller-Muto) distance exponent                      */
+  float c3;      /* three-body weight                                                       */
+  float zeta;    /* angular Gaussian width                                                  */
+  float rcut;    /* cutoff radius                                                           */
+} sorf_fchl19_params;
+
 /* ABI version of the loaded library (compare with SORF_ABI_VERSION). */
 int32_t sorf_abi_version(void);
 
@@ -177,6 +192,29 @@ size_t sorf_project_workspace_bytes(int64_t n_atoms, int32_t n_elements);
 sorf_status sorf_project(int64_t n_atoms, int32_t d_rep, const float* rho, const int32_t* element,
                          int32_t n_elements, const float* U, int32_t d, float* x,
                          void* workspace, size_t workspace_bytes, sorf_stream_t stream);
+
+/* Length of the FCHL19 representation for n_elements elements:
+ * n_elements n2 + n_elements (n_elements + 1) / 2 n3 2 (720 for five elements with the
+ * energy+force parameters). Host-only; 0 for invalid arguments. */
+int64_t sorf_fchl19_length(int32_t n_elements, const sorf_fchl19_params* params);
+
+/* FCHL19 representation of every atom (Representation subsection):
+ *   rho_i = [G2_X for each element X] ++ [G3_XY for each element pair X <= Y, lexicographic],
+ *   G2_X[k] = sum_{j of element X} f_cut(r_ij) r_ij^-N2 LN(R_k; mu(r_ij), sigma(r_ij)),
+ *     LN the log-normal density with mu = ln(r / sqrt(1 + eta2/r^2)), sigma^2 = ln(1 + eta2/r^2);
+ *   G3_XY[k][t] = sum over unordered neighbour pairs {j, l} of elements {X, Y} of
+ *     xi3 f_cut(r_ij) f_cut(r_jl) f_cut(r_il) sqrt(eta3/pi) exp(-eta3 ((r_ij + r_il)/2 - R_k)^2) A_t,
+ *     xi3 = c3 (1 + 3 cos_i cos_j cos_l) / (r_ij r_jl r_il)^N3, A_cos = 2 e^(-zeta^2/2) cos(theta_i),
+ *     A_sin = 2 e^(-zeta^2/2) sin(theta_i), theta_i the angle at i; f_cut(r) = (cos(pi r/rcut)+1)/2
+ *     for r < rcut, else 0. Neighbours: other atoms of the same molecule closer than rcut.
+ *   R: [n_atoms][3] FP32 coordinates (Angstrom); element: [n_atoms] int32 in [0, n_elements);
+ *   mol_ptr: [n_mols + 1] CSR atom offsets; rho: [n_atoms][length] FP32 out.
+ *   1 <= n_elements <= 16; at most 512 neighbours per atom (an atom with more gets a row of
+ *   NaN). Each entry is summed in a fixed order (deterministic). No workspace. */
+sorf_status sorf_fchl19_forward(const float* R, const int32_t* element, const int64_t* mol_ptr,
+                                int64_t n_atoms, int64_t n_mols, int32_t n_elements,
+                                const sorf_fchl19_params* params, float* rho,
+                                sorf_stream_t stream);
 
 /* Bytes of workspace sorf_gram_accumulate needs for n_rows rows of D features in the given
  * precision (host-only query): the FP32 mode needs only the Z^T y partials (D * 8 bytes per

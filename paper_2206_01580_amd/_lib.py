@@ -25,6 +25,7 @@ EXPORTS = (
     "sorf_abi_version", "sorf_status_string", "sorf_forward", "sorf_backward",
     "sorf_derivative_features", "sorf_project_workspace_bytes", "sorf_project",
     "sorf_projection_fit_workspace_bytes", "sorf_projection_fit",
+    "sorf_fchl19_length", "sorf_fchl19_forward",
     "sorf_gram_workspace_bytes", "sorf_gram_accumulate", "sorf_gram_accumulate_f64",
     "sorf_solve_workspace_bytes",
     "sorf_solve", "sorf_solve_f64",
@@ -51,6 +52,20 @@ class SorfBatch(ctypes.Structure):
         ("mol_ptr", ctypes.c_void_p),
         ("n_atoms", ctypes.c_int64),
         ("n_mols", ctypes.c_int64),
+    ]
+
+
+class SorfFchl19Params(ctypes.Structure):
+    _fields_ = [
+        ("n2", ctypes.c_int32),
+        ("n3", ctypes.c_int32),
+        ("eta2", ctypes.c_float),
+        ("eta3", ctypes.c_float),
+        ("N2", ctypes.c_float),
+        ("N3", ctypes.c_float),
+        ("c3", ctypes.c_float),
+        ("zeta", ctypes.c_float),
+        ("rcut", ctypes.c_float),
     ]
 
 
@@ -86,6 +101,9 @@ def load() -> ctypes.CDLL:
         "sorf_project": (ctypes.c_int, [i64, i32, P, P, i32, P, i32, P, P, sz, P]),
         "sorf_projection_fit_workspace_bytes": (sz, [i32]),
         "sorf_projection_fit": (ctypes.c_int, [i64, i32, P, i32, P, P, P, sz, P]),
+        "sorf_fchl19_length": (i64, [i32, ctypes.POINTER(SorfFchl19Params)]),
+        "sorf_fchl19_forward": (ctypes.c_int, [P, P, P, i64, i64, i32,
+                                               ctypes.POINTER(SorfFchl19Params), P, P]),
         "sorf_gram_workspace_bytes": (sz, [i64, i32, ctypes.c_int]),
         "sorf_gram_accumulate": (ctypes.c_int, [i64, i32, P, P, ctypes.c_int, i32, P, P, P, sz,
                                                 P]),

@@ -156,6 +156,35 @@ sorf_status sorf_projection_fit(int64_t n_samples, int32_t d_rep, const float* s
                                         workspace, hipStream_t(stream)));
 }
 
+static bool fchl_params_ok(const sorf_fchl19_params* p) {
+  if (p == nullptr || p->n2 < 1 || p->n3 < 2 || p->n2 > 4096 || p->n3 > 4096) return false;
+  const float v[] = {p->eta2, p->eta3, p->N2, p->N3, p->c3, p->zeta, p->rcut};
+  for (float x : v)
+    if (!std::isfinite(x)) return false;
+  return p->eta2 > 0.0f && p->eta3 > 0.0f && p->rcut > 0.0f;
+}
+
+int64_t sorf_fchl19_length(int32_t n_elements, const sorf_fchl19_params* params) {
+  if (n_elements < 1 || n_elements > 16 || !fchl_params_ok(params)) return 0;
+  return sorf_fchl19_len(n_elements, params->n2, params->n3);
+}
+
+sorf_status sorf_fchl19_forward(const float* R, const int32_t* element, const int64_t* mol_ptr,
+                                int64_t n_atoms, int64_t n_mols, int32_t n_elements,
+                                const sorf_fchl19_params* params, float* rho,
+                                sorf_stream_t stream) {
+  if (n_atoms < 0 || n_mols < 0 || n_atoms > (int64_t(1) << 40)) return SORF_ERR_INVALID_ARG;
+  if (n_elements < 1 || !fchl_params_ok(params)) return SORF_ERR_INVALID_ARG;
+  if (n_elements > 16) return SORF_ERR_UNSUPPORTED;
+  if (n_atoms == 0) return SORF_OK;
+  if (R == nullptr || element == nullptr || mol_ptr == nullptr || rho == nullptr || n_mols == 0)
+    return SORF_ERR_INVALID_ARG;
+  const FchlParamsHost p{params->n2, params->n3, params->eta2, params->eta3, params->N2,
+                         params->N3, params->c3, params->zeta, params->rcut};
+  return dev(sorf_launch_fchl19_forward(R, element, mol_ptr, n_atoms, n_mols, n_elements, p, rho,
+                                        hipStream_t(stream)));
+}
+
 size_t sorf_gram_workspace_bytes(int64_t n_rows, int32_t D, sorf_gram_precision precision) {
   if (n_rows < 0 || D < 1 || D > (1 << 20)) return 0;
   if (int(precision) < 0 || int(precision) > 5) return 0;

@@ -1,0 +1,248 @@
+// FCHL19 atomic representation (arXiv 2206.01580, Theory section,
+// Representation subsection; parameters from the Computational Details
+// table): for every atom i,
+//   rho_i = [G2_X for every element X] ++ [G3_XY for every element pair X <= Y],
+//   G2_X[k]     = sum_{j in X} f_cut(r_ij) r_ij^-N2 LN(R_k; mu(r_ij), sigma(r_ij)),
+//                 LN the log-normal density, mu = ln(r / sqrt(1 + eta2/r^2)),
+//                 sigma^2 = ln(1 + eta2/r^2), R_k = r_cut (k + 1) / n2;
+//   G3_XY[k][t] = sum over unordered neighbour pairs {j, k'} of elements {X, Y} of
+//                 xi3 f_cut(r_ij) f_cut(r_jk') f_cut(r_ik') sqrt(eta3/pi)
+//                 exp(-eta3 ((r_ij + r_ik')/2 - R_k)^2) A_t(theta),
+//                 xi3 = c3 (1 + 3 cos_i cos_j cos_k') / (r_ij r_jk' r_ik')^N3 (Axilrod-Teller-Muto),
+//                 A_cos = 2 e^(-zeta^2/2) cos(theta), A_sin = 2 e^(-zeta^2/2) sin(theta),
+//                 theta the angle at i, R_k = r_cut k / (n3 - 1); f_cut(r) = (cos(pi r/r_cut) + 1)/2
+//                 below r_cut and 0 beyond.
+//
+// One workgroup (4 waves) per atom. The atom's neighbours (same molecule,
+// closer than r_cut) are gathered into LDS grouped by element, in atom order
+// inside each group (ballot compaction, no atomics), with their per-neighbour
+// two-body factors. Two-body bins: one thread per (element, bin) sums its
+// element's neighbours in order. Three-body: the unordered pairs are numbered
+// by element pair (X <= Y), then by position; chunks of pairs get their
+// radial-independent weight (xi3, cutoffs, angle) computed by all threads
+// into LDS, and one thread per (element pair, radial bin) sums its pairs of
+// the chunk in order. Every entry of rho is therefore summed in a fixed order.
+#include <cmath>
+
+#include "sorf_internal.h"
+
+namespace sorf {
+
+constexpr int kFchlMaxNb = 512;        // neighbours of one atom held in LDS
+constexpr int kFchlPairChunk = 2048;   // three-body pairs per LDS chunk
+constexpr int kFchlMaxElements = 16;
+
+struct FchlParams {
+  int32_t n2, n3;
+  float eta2, eta3, N2, N3, c3, zeta, rcut;
+};
+
+__device__ __forceinline__ float fchl_fcut(float r, float rc) {
+  return r < rc ? 0.5f * (cosf(3.14159265358979f * r / rc) + 1.0f) : 0.0f;
+}
+
+// element pair (a <= b) -> position in the lexicographic list of pairs
+__device__ __forceinline__ int fchl_pair(int a, int b, int E) { return a * E - a * (a - 1) / 2 + (b - a); }
+
+__global__ __launch_bounds__(256) void fchl19_forward_kernel(
+    const float* __restrict__ R, const int32_t* __restrict__ element,
+    const int64_t* __restrict__ mol_ptr, int64_t atom0, int64_t n_atoms, int64_t n_mols,
+    int32_t E, FchlParams p, int64_t size, float* __restrict__ rho) {
+  __shared__ float nx[kFchlMaxNb], ny[kFchlMaxNb], nz[kFchlMaxNb], nr[kFchlMaxNb];
+  __shared__ float c2[kFchlMaxNb], mu2[kFchlMaxNb], inv2s2[kFchlMaxNb];
+  __shared__ int32_t grp[kFchlMaxElements + 1];     // neighbour offsets per element
+  __shared__ int32_t wcount[4];
+  __shared__ int64_t seg[kFchlMaxElements * (kFchlMaxElements + 1) / 2 + 1];
+  __shared__ float pw_c[kFchlPairChunk], pw_s[kFchlPairChunk], pmid[kFchlPairChunk];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t i = atom0 + blockIdx.x;
+  if (i >= n_atoms) return;
+  const int64_t m = molecule_of(mol_ptr, n_mols, i);
+  const int64_t a0 = mol_ptr[m], a1 = mol_ptr[m + 1];
+  const float rc = p.rcut;
+  const float xi = R[3 * i], yi = R[3 * i + 1], zi = R[3 * i + 2];
+  float* __restrict__ out = rho + i * size;
+
+  // neighbours grouped by element, atom order inside a group
+  int total = 0;
+  bool overflow = false;
+  for (int X = 0; X < E; ++X) {
+    if (tid == 0) grp[X] = total;
+    for (int64_t j0 = a0; j0 < a1; j0 += 256) {
+      const int64_t j = j0 + tid;
+      float dx = 0.f, dy = 0.f, dz = 0.f, r = 0.f;
+      bool f = false;
+      if (j < a1 && j != i && element[j] == X) {
+        dx = R[3 * j] - xi;
+        dy = R[3 * j + 1] - yi;
+        dz = R[3 * j + 2] - zi;
+        r = sqrtf(dx * dx + dy * dy + dz * dz);
+        f = r < rc;
+      }
+      const uint64_t mask = __ballot(f);
+      const int before = __popcll(mask & ((uint64_t(1) << lane) - 1));
+      if (lane == 0) wcount[wv] = __popcll(mask);
+      __syncthreads();
+      int off = total;
+      for (int w = 0; w < wv; ++w) off += wcount[w];
+      const int chunk = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+      if (f) {
+        const int slot = off + before;
+        if (slot < kFchlMaxNb) {
+          nx[slot] = dx;
+          ny[slot] = dy;
+          nz[slot] = dz;
+          nr[slot] = r;
+          // two-body factors: f_cut r^-N2 / (sigma sqrt(2 pi)), mu, 1 / (2 sigma^2)
+          const float q = 1.0f + p.eta2 / (r * r);
+          const float s2 = logf(q);
+          c2[slot] = fchl_fcut(r, rc) * powf(r, -p.N2) / (sqrtf(s2) * 2.50662827463100f);
+          mu2[slot] = logf(r / sqrtf(q));
+          inv2s2[slot] = 0.5f / s2;
+        }
+      }
+      total += chunk;
+      __syncthreads();
+    }
+  }
+  if (tid == 0) grp[E] = total;
+  overflow = total > kFchlMaxNb;
+  if (overflow) {   // more neighbours than the LDS list holds: mark the row, do not guess
+    for (int64_t t = tid; t < size; t += 256) out[t] = __builtin_nanf("");
+    return;
+  }
+  __syncthreads();
+
+  // two-body bins
+  for (int t = tid; t < E * p.n2; t += 256) {
+    const int X = t / p.n2, k = t % p.n2;
+    const float Rk = rc * float(k + 1) / float(p.n2);
+    const float lnR = logf(Rk);
+    float acc = 0.0f;
+    for (int s = grp[X]; s < grp[X + 1]; ++s) {
+      const float d = lnR - mu2[s];
+      acc += c2[s] * expf(-d * d * inv2s2[s]);
+    }
+    out[t] = acc / Rk;
+  }
+
+  // three-body: pair numbering by element pair X <= Y
+  const int NP = E * (E + 1) / 2;
+  if (tid == 0) {
+    int64_t o = 0;
+    for (int X = 0; X < E; ++X)
+      for (int Y = X; Y < E; ++Y) {
+        seg[fchl_pair(X, Y, E)] = o;
+        const int64_t cx = grp[X + 1] - grp[X], cy = grp[Y + 1] - grp[Y];
+        o += X == Y ? cx * (cx - 1) / 2 : cx * cy;
+      }
+    seg[NP] = o;
+  }
+  __syncthreads();
+  const int64_t n_pairs = seg[NP];
+  const float angw = 2.0f * expf(-0.5f * p.zeta * p.zeta) * sqrtf(p.eta3 / 3.14159265358979f);
+  const int nbins = NP * p.n3;
+  // rounds of 512 (element pair, radial bin) outputs, two per thread
+  for (int t0 = 0; t0 < nbins; t0 += 512) {
+    float acc_c[2] = {0.f, 0.f}, acc_s[2] = {0.f, 0.f};
+    for (int64_t q0 = 0; q0 < n_pairs; q0 += kFchlPairChunk) {
+      const int64_t q1 = q0 + kFchlPairChunk < n_pairs ? q0 + kFchlPairChunk : n_pairs;
+      for (int64_t q = q0 + tid; q < q1; q += 256) {
+        // pair q -> element pair P (row X, column Y) -> neighbours (a, b)
+        int P = 0;
+        while (q >= seg[P + 1]) ++P;
+        int X = 0;
+        while (fchl_pair(X, X, E) + (E - X) <= P) ++X;
+        const int Y = X + (P - fchl_pair(X, X, E));
+        const int64_t loc = q - seg[P];
+        int a, b;
+        if (X != Y) {
+          const int cy = grp[Y + 1] - grp[Y];
+          a = grp[X] + int(loc / cy);
+          b = grp[Y] + int(loc % cy);
+        } else {
+          // loc -> (u, v), u < v; row u starts at u (2 cx - u - 1) / 2
+          const int cx = grp[X + 1] - grp[X];
+          const double c2x = 2.0 * cx - 1.0;
+          int u = int((c2x - sqrt(c2x * c2x - 8.0 * double(loc))) * 0.5);
+          if (u < 0) u = 0;
+          while (u > 0 && int64_t(u) * (2 * cx - u - 1) / 2 > loc) --u;
+          while (int64_t(u + 1) * (2 * cx - u - 2) / 2 <= loc) ++u;
+          a = grp[X] + u;
+          b = grp[X] + u + 1 + int(loc - int64_t(u) * (2 * cx - u - 1) / 2);
+        }
+        const float rij = nr[a], rik = nr[b];
+        const float jx = nx[b] - nx[a], jy = ny[b] - ny[a], jz = nz[b] - nz[a];
+        const float rjk = sqrtf(jx * jx + jy * jy + jz * jz);
+        const float cos_i = (nx[a] * nx[b] + ny[a] * ny[b] + nz[a] * nz[b]) / (rij * rik);
+        const float cos_j = -(nx[a] * jx + ny[a] * jy + nz[a] * jz) / (rij * rjk);
+        const float cos_k = (nx[b] * jx + ny[b] * jy + nz[b] * jz) / (rik * rjk);
+        const float sin_i = sqrtf(fmaxf(0.0f, 1.0f - cos_i * cos_i));
+        const float xi3 = p.c3 * (1.0f + 3.0f * cos_i * cos_j * cos_k) / powf(rij * rjk * rik, p.N3);
+        const float w = xi3 * fchl_fcut(rij, rc) * fchl_fcut(rjk, rc) * fchl_fcut(rik, rc) * angw;
+        const int sl = int(q - q0);
+        pw_c[sl] = w * cos_i;
+        pw_s[sl] = w * sin_i;
+        pmid[sl] = 0.5f * (rij + rik);
+      }
+      __syncthreads();
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const int t = t0 + tid + 256 * h;
+        if (t < nbins) {
+          const int P = t / p.n3, k = t % p.n3;
+          const float Rk = rc * float(k) / float(p.n3 - 1);
+          const int64_t lo = seg[P] > q0 ? seg[P] : q0;
+          const int64_t hi = seg[P + 1] < q1 ? seg[P + 1] : q1;
+          float c = acc_c[h], sn = acc_s[h];
+          for (int64_t q = lo; q < hi; ++q) {
+            const int sl = int(q - q0);
+            const float d = pmid[sl] - Rk;
+            const float g = expf(-p.eta3 * d * d);
+            c += pw_c[sl] * g;
+            sn += pw_s[sl] * g;
+          }
+          acc_c[h] = c;
+          acc_s[h] = sn;
+        }
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int h = 0; h < 2; ++h) {
+      const int t = t0 + tid + 256 * h;
+      if (t < nbins) {
+        float* o = out + int64_t(E) * p.n2 + 2 * int64_t(t);
+        o[0] = acc_c[h];
+        o[1] = acc_s[h];
+      }
+    }
+  }
+}
+
+}  // namespace sorf
+
+using namespace sorf;
+
+int64_t sorf_fchl19_len(int32_t E, int32_t n2, int32_t n3) {
+  return int64_t(E) * n2 + int64_t(E) * (E + 1) / 2 * n3 * 2;
+}
+
+hipError_t sorf_launch_fchl19_forward(const float* R, const int32_t* element,
+                                      const int64_t* mol_ptr, int64_t n_atoms, int64_t n_mols,
+                                      int32_t E, const FchlParamsHost& ph, float* rho,
+                                      hipStream_t st) {
+  if (n_atoms == 0) return hipSuccess;
+  const FchlParams p{ph.n2, ph.n3, ph.eta2, ph.eta3, ph.N2, ph.N3, ph.c3, ph.zeta, ph.rcut};
+  const int64_t size = sorf_fchl19_len(E, ph.n2, ph.n3);
+  constexpr int64_t kPerLaunch = int64_t(1) << 30;
+  for (int64_t a0 = 0; a0 < n_atoms; a0 += kPerLaunch) {
+    const int64_t cnt = n_atoms - a0 < kPerLaunch ? n_atoms - a0 : kPerLaunch;
+    hipLaunchKernelGGL(fchl19_forward_kernel, dim3(unsigned(cnt)), dim3(256), 0, st, R, element,
+                       mol_ptr, a0, n_atoms, n_mols, E, p, size, rho);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}

@@ -223,6 +223,16 @@ hipError_t sorf_launch_project(int64_t n_atoms, int32_t d_rep, const float* rho,
 size_t sorf_fit_ws_bytes(int32_t d_rep);
 hipError_t sorf_launch_projection_fit(int64_t n_samples, int32_t d_rep, const float* sample,
                                       int32_t n_pca, float* U, double* sv, void* ws, hipStream_t s);
+// FCHL19 representation (parameters as in the paper's table).
+struct FchlParamsHost {
+  int32_t n2, n3;
+  float eta2, eta3, N2, N3, c3, zeta, rcut;
+};
+int64_t sorf_fchl19_len(int32_t n_elements, int32_t n2, int32_t n3);
+hipError_t sorf_launch_fchl19_forward(const float* R, const int32_t* element,
+                                      const int64_t* mol_ptr, int64_t n_atoms, int64_t n_mols,
+                                      int32_t n_elements, const FchlParamsHost& p, float* rho,
+                                      hipStream_t s);
 hipError_t sorf_launch_validate(const SorfFeatureArgs& a, int32_t* result, hipStream_t s);
 hipError_t sorf_launch_fill(float* p, int64_t n, float v, hipStream_t s);
 

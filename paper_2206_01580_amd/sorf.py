@@ -237,6 +237,34 @@ def project(rho: torch.Tensor, element: torch.Tensor, U: torch.Tensor,
     return Projector(U)(rho, element, out)
 
 
+def fchl19_params(n2=24, n3=20, eta2=0.32, eta3=2.7, N2=1.8, N3=0.57, c3=13.4, zeta=math.pi,
+                  rcut=6.0) -> "_lib.SorfFchl19Params":
+    """FCHL19 parameters; the defaults are the paper's energy+force column."""
+    return _lib.SorfFchl19Params(int(n2), int(n3), float(eta2), float(eta3), float(N2),
+                                 float(N3), float(c3), float(zeta), float(rcut))
+
+
+def fchl19(R: torch.Tensor, element: torch.Tensor, mol_ptr: torch.Tensor, n_elements: int,
+           params=None, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """rho [n_atoms, length] FCHL19 representation (sorf_fchl19_forward)."""
+    prm = params if params is not None else fchl19_params()
+    A = element.numel()
+    _need(R, torch.float32, "R", 3 * A)
+    _need(element, torch.int32, "element", A)
+    _need(mol_ptr, torch.int64, "mol_ptr")
+    lib = _lib.load()
+    L = lib.sorf_fchl19_length(n_elements, ctypes.byref(prm))
+    if L <= 0:
+        raise ValueError("invalid FCHL19 parameters or element count")
+    if out is None:
+        out = torch.empty((A, L), dtype=torch.float32, device=R.device)
+    _need(out, torch.float32, "rho", A * L)
+    _lib.check("sorf_fchl19_forward", lib.sorf_fchl19_forward(
+        _ptr(R), _ptr(element), _ptr(mol_ptr), A, mol_ptr.numel() - 1, n_elements,
+        ctypes.byref(prm), _ptr(out), _stream()))
+    return out
+
+
 class GramWorkspace:
     """Reusable device workspace for sorf_gram_accumulate (grows on demand)."""
 

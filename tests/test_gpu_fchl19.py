@@ -1,0 +1,124 @@
+"""GPU parity of the FCHL19 representation against the FP64 oracle.
+
+Tolerance: per atom row, max |d rho| <= 2e-5 max |rho_oracle| (normwise, as
+for the features: FP32 transcendental functions of arguments up to ~50 in
+magnitude carry relative errors of a few 1e-6); rows of atoms without
+neighbours are exactly 0.
+"""
+import math
+
+import numpy as np
+import pytest
+
+from oracle import fchl19_oracle as F
+from paper_2206_01580_amd import workloads as W
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+PRM = dict(W.FCHL19_EF)
+PRM_E = dict(n2=23, n3=22, eta2=0.27, eta3=5.6, N2=2.78, N3=2.1, c3=60.1, zeta=math.pi, rcut=6.0)
+
+
+@pytest.fixture(scope="module", autouse=True)
+def _gpu():
+    if not torch.cuda.is_available():
+        pytest.fail("GPU tests need a GPU")
+    from paper_2206_01580_amd import _lib
+    _lib.load()  # fails loudly if the HIP library is not built
+    yield
+
+
+def S():
+    from paper_2206_01580_amd import sorf
+    return sorf
+
+
+def gpu_rho(R, el, ptr, E, prm):
+    s = S()
+    return s.fchl19(torch.from_numpy(np.ascontiguousarray(R, np.float32)).cuda(),
+                    torch.from_numpy(np.ascontiguousarray(el, np.int32)).cuda(),
+                    torch.from_numpy(np.asarray(ptr, np.int64)).cuda(), E,
+                    s.fchl19_params(**prm)).cpu().numpy()
+
+
+def check(R, el, ptr, E, prm):
+    got = gpu_rho(R, el, ptr, E, prm).astype(np.float64)
+    ref, _ = F.fchl19(np.asarray(R, np.float32).astype(np.float64), el, ptr, E, prm)
+    ref = ref.numpy()
+    assert got.shape == ref.shape
+    scale = np.abs(ref).max(axis=1)
+    err = np.abs(got - ref).max(axis=1)
+    empty = scale == 0
+    assert np.all(got[empty] == 0.0)
+    assert np.all(err[~empty] <= 2e-5 * scale[~empty]), float(np.max(err[~empty] / scale[~empty]))
+    return float(np.max(err[~empty] / scale[~empty])) if (~empty).any() else 0.0
+
+
+# (molecule sizes, elements, parameter set, coordinate stretch)
+CASES = {
+    "qm9-sizes-E5": ([29, 3, 18, 1, 2, 11, 25], 5, PRM, 1.0),
+    "energy-params-E5": ([20, 9, 14], 5, PRM_E, 1.0),
+    "stretched-cutoff-E3": ([24, 16], 3, PRM, 2.5),      # many pairs beyond r_cut
+    "one-element": ([12, 7], 1, PRM, 1.0),
+    "eight-elements-two-rounds": ([26, 19], 8, PRM, 1.0),  # 36 pairs x 20 bins > 512
+    "large-molecule-chunks": ([120], 5, PRM, 1.0),          # > 2048 pairs per atom
+}
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_fchl19_matches_oracle(case):
+    sizes, E, prm, stretch = CASES[case]
+    rng = np.random.default_rng(len(case))
+    R = W.host_geometries(sizes, seed=sum(sizes) + E) * stretch
+    el = rng.integers(0, E, size=sum(sizes)).astype(np.int32)
+    ptr = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    rel = check(R, el, ptr, E, prm)
+    print(f"{case}: max row error / row scale {rel:.2e}")
+
+
+def test_fchl19_deterministic_and_empty():
+    sizes = [29, 17, 0, 5]
+    rng = np.random.default_rng(1)
+    R = W.host_geometries(sizes, seed=2)
+    el = rng.integers(0, 5, size=sum(sizes)).astype(np.int32)
+    ptr = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    a = gpu_rho(R, el, ptr, 5, PRM)
+    b = gpu_rho(R, el, ptr, 5, PRM)
+    assert np.array_equal(a, b)
+    # no atoms: nothing to do
+    s = S()
+    out = torch.empty((0, 720), device="cuda")
+    s.fchl19(torch.empty((0, 3), device="cuda"), torch.empty(0, dtype=torch.int32, device="cuda"),
+             torch.zeros(1, dtype=torch.int64, device="cuda"), 5, out=out)
+    torch.cuda.synchronize()
+
+
+def test_fchl19_too_many_neighbours_gives_nan_rows():
+    """600 atoms in a 3 A box: every atom has 599 neighbours, more than the 512
+    the kernel holds, so its row is NaN (a visible refusal, not a guess)."""
+    rng = np.random.default_rng(3)
+    R = rng.uniform(0.0, 3.0, size=(600, 3)).astype(np.float32)
+    el = np.zeros(600, np.int32)
+    rho = gpu_rho(R, el, np.array([0, 600]), 1, PRM)
+    assert np.all(np.isnan(rho))
+
+
+def test_fchl19_qm9_like_full_size_sampled():
+    """Every atom of 20,000 QM9-like molecules (the benchmark's batch), sampled
+    molecules against the oracle."""
+    p = W.config2()
+    sizes = p.mol_sizes()
+    R = W.host_geometries(sizes, seed=7)
+    s = S()
+    rho = s.fchl19(torch.from_numpy(R).cuda(), torch.from_numpy(p.element).cuda(),
+                   torch.from_numpy(p.mol_ptr).cuda(), 5, s.fchl19_params(**PRM))
+    torch.cuda.synchronize()
+    mols = np.random.default_rng(8).choice(p.n_mols, size=12, replace=False)
+    for m in mols:
+        a0, a1 = int(p.mol_ptr[m]), int(p.mol_ptr[m + 1])
+        ref, _ = F.fchl19(R[a0:a1].astype(np.float64), p.element[a0:a1], [0, a1 - a0], 5, PRM)
+        ref = ref.numpy()
+        got = rho[a0:a1].double().cpu().numpy()
+        scale = np.abs(ref).max(axis=1)
+        assert np.all(np.abs(got - ref).max(axis=1) <= 2e-5 * scale)
