@@ -216,6 +216,18 @@ sorf_status sorf_fchl19_forward(const float* R, const int32_t* element, const in
                                 const sorf_fchl19_params* params, float* rho,
                                 sorf_stream_t stream);
 
+/* Coordinate gradient of the FCHL19 representation contracted with an upstream gradient:
+ *   dR[a] = d(sum_i g_i . rho_i) / dR_a,  so that for g = dE/drho the forces are -dR
+ * (the representation's backward pass, GPU impl. of the Representation subsection).
+ *   g: [n_atoms][length] FP32 (dE/drho); dR: [n_atoms][3] FP32 out; other arguments as
+ *   sorf_fchl19_forward. At most 1024 atoms per molecule and 512 neighbours per atom (the
+ *   molecule's rows are NaN otherwise). Each molecule is summed in a fixed order
+ *   (deterministic). No workspace. */
+sorf_status sorf_fchl19_backward(const float* R, const int32_t* element, const int64_t* mol_ptr,
+                                 int64_t n_atoms, int64_t n_mols, int32_t n_elements,
+                                 const sorf_fchl19_params* params, const float* g, float* dR,
+                                 sorf_stream_t stream);
+
 /* Bytes of workspace sorf_gram_accumulate needs for n_rows rows of D features in the given
  * precision (host-only query): the FP32 mode needs only the Z^T y partials (D * 8 bytes per
  * 1024 rows); the 16-bit modes also hold Z packed once in matrix-core fragment order

@@ -25,7 +25,7 @@ EXPORTS = (
     "sorf_abi_version", "sorf_status_string", "sorf_forward", "sorf_backward",
     "sorf_derivative_features", "sorf_project_workspace_bytes", "sorf_project",
     "sorf_projection_fit_workspace_bytes", "sorf_projection_fit",
-    "sorf_fchl19_length", "sorf_fchl19_forward",
+    "sorf_fchl19_length", "sorf_fchl19_forward", "sorf_fchl19_backward",
     "sorf_gram_workspace_bytes", "sorf_gram_accumulate", "sorf_gram_accumulate_f64",
     "sorf_solve_workspace_bytes",
     "sorf_solve", "sorf_solve_f64",
@@ -104,6 +104,8 @@ def load() -> ctypes.CDLL:
         "sorf_fchl19_length": (i64, [i32, ctypes.POINTER(SorfFchl19Params)]),
         "sorf_fchl19_forward": (ctypes.c_int, [P, P, P, i64, i64, i32,
                                                ctypes.POINTER(SorfFchl19Params), P, P]),
+        "sorf_fchl19_backward": (ctypes.c_int, [P, P, P, i64, i64, i32,
+                                                ctypes.POINTER(SorfFchl19Params), P, P, P]),
         "sorf_gram_workspace_bytes": (sz, [i64, i32, ctypes.c_int]),
         "sorf_gram_accumulate": (ctypes.c_int, [i64, i32, P, P, ctypes.c_int, i32, P, P, P, sz,
                                                 P]),

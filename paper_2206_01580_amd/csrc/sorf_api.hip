@@ -185,6 +185,24 @@ sorf_status sorf_fchl19_forward(const float* R, const int32_t* element, const in
                                         hipStream_t(stream)));
 }
 
+sorf_status sorf_fchl19_backward(const float* R, const int32_t* element, const int64_t* mol_ptr,
+                                 int64_t n_atoms, int64_t n_mols, int32_t n_elements,
+                                 const sorf_fchl19_params* params, const float* g, float* dR,
+                                 sorf_stream_t stream) {
+  if (n_atoms < 0 || n_mols < 0 || n_atoms > (int64_t(1) << 40)) return SORF_ERR_INVALID_ARG;
+  if (n_mols > (int64_t(1) << 31) - 1) return SORF_ERR_INVALID_ARG;
+  if (n_elements < 1 || !fchl_params_ok(params)) return SORF_ERR_INVALID_ARG;
+  if (n_elements > 16) return SORF_ERR_UNSUPPORTED;
+  if (n_atoms == 0) return SORF_OK;
+  if (R == nullptr || element == nullptr || mol_ptr == nullptr || g == nullptr || dR == nullptr ||
+      n_mols == 0)
+    return SORF_ERR_INVALID_ARG;
+  const FchlParamsHost p{params->n2, params->n3, params->eta2, params->eta3, params->N2,
+                         params->N3, params->c3, params->zeta, params->rcut};
+  return dev(sorf_launch_fchl19_backward(R, element, mol_ptr, n_mols, n_elements, p, g, dR,
+                                         hipStream_t(stream)));
+}
+
 size_t sorf_gram_workspace_bytes(int64_t n_rows, int32_t D, sorf_gram_precision precision) {
   if (n_rows < 0 || D < 1 || D > (1 << 20)) return 0;
   if (int(precision) < 0 || int(precision) > 5) return 0;

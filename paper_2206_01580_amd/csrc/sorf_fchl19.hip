@@ -221,6 +221,294 @@ __global__ __launch_bounds__(256) void fchl19_forward_kernel(
   }
 }
 
+// ---------------------------------------------------------------------------
+// Coordinate gradient: dR = d(sum_i g_i . rho_i)/dR for an upstream g = dE/drho
+// (the forces are -dR). Every three-body term of a centre i and its pair of
+// neighbours (j, l) depends on the positions only through the three sides
+// a = r_ij, b = r_il, c = r_jl (the cosines follow by the law of cosines), so
+// its gradient is dL/da u_ij + dL/db u_il + dL/dc u_jl distributed to the
+// three atoms; a two-body term gives dL/dr u_ij to j and minus that to i.
+//
+// One workgroup per molecule, holding the molecule's atoms and its gradient
+// in LDS and walking the centres in order. For each centre the neighbours are
+// gathered as in the forward kernel; one thread per neighbour forms its
+// two-body contribution, one thread per pair its three-body contributions,
+// and then one thread per neighbour adds, in pair order, the contributions
+// that land on its atom, while thread 0 adds the centre's: every gradient
+// entry is summed in a fixed order (deterministic, no atomics).
+// ---------------------------------------------------------------------------
+constexpr int kFchlBwdMaxAtoms = 1024;   // atoms of one molecule held in LDS
+constexpr int kFchlBwdPairChunk = 1024;
+
+__global__ __launch_bounds__(256) void fchl19_backward_kernel(
+    const float* __restrict__ R, const int32_t* __restrict__ element,
+    const int64_t* __restrict__ mol_ptr, int64_t m0, int64_t n_mols, int32_t E, FchlParams p,
+    int64_t size, const float* __restrict__ g, float* __restrict__ dR) {
+  __shared__ float ax[kFchlBwdMaxAtoms], ay[kFchlBwdMaxAtoms], az[kFchlBwdMaxAtoms];
+  __shared__ float gx[kFchlBwdMaxAtoms], gy[kFchlBwdMaxAtoms], gz[kFchlBwdMaxAtoms];
+  __shared__ int32_t ael[kFchlBwdMaxAtoms];
+  __shared__ int32_t nidx[kFchlMaxNb];
+  __shared__ float nx[kFchlMaxNb], ny[kFchlMaxNb], nz[kFchlMaxNb], nr[kFchlMaxNb];
+  __shared__ float sacc[3][kFchlMaxNb];
+  __shared__ int32_t grp[kFchlMaxElements + 1];
+  __shared__ int32_t wcount[4];
+  __shared__ int64_t seg[kFchlMaxElements * (kFchlMaxElements + 1) / 2 + 1];
+  __shared__ float fi[3][kFchlBwdPairChunk], fj[3][kFchlBwdPairChunk], fl[3][kFchlBwdPairChunk];
+  __shared__ int32_t qa[kFchlBwdPairChunk], qb[kFchlBwdPairChunk];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t m = m0 + blockIdx.x;
+  if (m >= n_mols) return;
+  const int64_t a0 = mol_ptr[m];
+  const int N = int(mol_ptr[m + 1] - a0);
+  if (N <= 0) return;
+  if (N > kFchlBwdMaxAtoms) {   // more atoms than the LDS holds: mark the rows, do not guess
+    for (int t = tid; t < 3 * N; t += 256) dR[3 * a0 + t] = __builtin_nanf("");
+    return;
+  }
+  const float rc = p.rcut;
+  const float kPi = 3.14159265358979f;
+  for (int t = tid; t < N; t += 256) {
+    ax[t] = R[3 * (a0 + t)];
+    ay[t] = R[3 * (a0 + t) + 1];
+    az[t] = R[3 * (a0 + t) + 2];
+    ael[t] = element[a0 + t];
+    gx[t] = gy[t] = gz[t] = 0.0f;
+  }
+  __syncthreads();
+  const float angw = 2.0f * expf(-0.5f * p.zeta * p.zeta) * sqrtf(p.eta3 / kPi);
+  const int NP = E * (E + 1) / 2;
+  bool bad = false;
+
+  for (int ci = 0; ci < N; ++ci) {
+    const float* __restrict__ gi = g + (a0 + ci) * size;
+    // neighbours grouped by element, atom order inside a group
+    int total = 0;
+    for (int X = 0; X < E; ++X) {
+      if (tid == 0) grp[X] = total;
+      for (int j0 = 0; j0 < N; j0 += 256) {
+        const int j = j0 + tid;
+        float dx = 0.f, dy = 0.f, dz = 0.f, r = 0.f;
+        bool f = false;
+        if (j < N && j != ci && ael[j] == X) {
+          dx = ax[j] - ax[ci];
+          dy = ay[j] - ay[ci];
+          dz = az[j] - az[ci];
+          r = sqrtf(dx * dx + dy * dy + dz * dz);
+          f = r < rc;
+        }
+        const uint64_t mask = __ballot(f);
+        const int before = __popcll(mask & ((uint64_t(1) << lane) - 1));
+        if (lane == 0) wcount[wv] = __popcll(mask);
+        __syncthreads();
+        int off = total;
+        for (int w = 0; w < wv; ++w) off += wcount[w];
+        const int chunk = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+        if (f && off + before < kFchlMaxNb) {
+          const int sl = off + before;
+          nidx[sl] = j;
+          nx[sl] = dx;
+          ny[sl] = dy;
+          nz[sl] = dz;
+          nr[sl] = r;
+        }
+        total += chunk;
+        __syncthreads();
+      }
+    }
+    if (total > kFchlMaxNb) {
+      bad = true;
+      break;
+    }
+    if (tid == 0) {
+      grp[E] = total;
+      int64_t o = 0;
+      for (int X = 0; X < E; ++X)
+        for (int Y = X; Y < E; ++Y) {
+          seg[fchl_pair(X, Y, E)] = o;
+          const int64_t cx = grp[X + 1] - grp[X], cy = grp[Y + 1] - grp[Y];
+          o += X == Y ? cx * (cx - 1) / 2 : cx * cy;
+        }
+      seg[NP] = o;
+    }
+    __syncthreads();
+
+    // two-body: d/dr of f_cut(r) r^-N2 LN(R_k; mu(r), sigma(r)), summed against g
+    for (int sl = tid; sl < total; sl += 256) {
+      int X = 0;
+      while (sl >= grp[X + 1]) ++X;
+      const float r = nr[sl];
+      const float q = 1.0f + p.eta2 / (r * r);
+      const float s2 = logf(q);
+      const float ds2 = -2.0f * p.eta2 / (r * r * r * q);
+      const float mu = logf(r / sqrtf(q));
+      const float dmu = 1.0f / r + p.eta2 / (r * r * r * q);
+      const float fcv = fchl_fcut(r, rc);
+      const float dfc = r < rc ? -0.5f * (kPi / rc) * sinf(kPi * r / rc) : 0.0f;
+      const float pref = powf(r, -p.N2) / (sqrtf(s2) * 2.50662827463100f);
+      float dL = 0.0f;
+      for (int k = 0; k < p.n2; ++k) {
+        const float Rk = rc * float(k + 1) / float(p.n2);
+        const float Lk = logf(Rk) - mu;
+        const float B = pref * expf(-Lk * Lk / (2.0f * s2)) / Rk;
+        const float D = -p.N2 / r - 0.5f * ds2 / s2 + Lk * dmu / s2 + Lk * Lk * ds2 / (2.0f * s2 * s2);
+        dL += gi[X * p.n2 + k] * (dfc + fcv * D) * B;
+      }
+      const float inv = dL / r;
+      sacc[0][sl] = nx[sl] * inv;
+      sacc[1][sl] = ny[sl] * inv;
+      sacc[2][sl] = nz[sl] * inv;
+    }
+    __syncthreads();
+    float cx_acc = 0.f, cy_acc = 0.f, cz_acc = 0.f;   // centre's gradient (thread 0)
+    if (tid == 0)
+      for (int sl = 0; sl < total; ++sl) {
+        cx_acc -= sacc[0][sl];
+        cy_acc -= sacc[1][sl];
+        cz_acc -= sacc[2][sl];
+      }
+
+    // three-body over unordered pairs, in chunks
+    const int64_t n_pairs = seg[NP];
+    for (int64_t q0 = 0; q0 < n_pairs; q0 += kFchlBwdPairChunk) {
+      const int64_t q1 = q0 + kFchlBwdPairChunk < n_pairs ? q0 + kFchlBwdPairChunk : n_pairs;
+      for (int64_t q = q0 + tid; q < q1; q += 256) {
+        int P = 0;
+        while (q >= seg[P + 1]) ++P;
+        int X = 0;
+        while (fchl_pair(X, X, E) + (E - X) <= P) ++X;
+        const int Y = X + (P - fchl_pair(X, X, E));
+        const int64_t loc = q - seg[P];
+        int sa, sb;
+        if (X != Y) {
+          const int cy = grp[Y + 1] - grp[Y];
+          sa = grp[X] + int(loc / cy);
+          sb = grp[Y] + int(loc % cy);
+        } else {
+          const int cxn = grp[X + 1] - grp[X];
+          const double c2x = 2.0 * cxn - 1.0;
+          int u = int((c2x - sqrt(c2x * c2x - 8.0 * double(loc))) * 0.5);
+          if (u < 0) u = 0;
+          while (u > 0 && int64_t(u) * (2 * cxn - u - 1) / 2 > loc) --u;
+          while (int64_t(u + 1) * (2 * cxn - u - 2) / 2 <= loc) ++u;
+          sa = grp[X] + u;
+          sb = grp[X] + u + 1 + int(loc - int64_t(u) * (2 * cxn - u - 1) / 2);
+        }
+        // sides a = r_ij, b = r_il, c = r_jl and unit vectors i->j, i->l, j->l
+        const float a = nr[sa], b = nr[sb];
+        const float wx = nx[sb] - nx[sa], wy = ny[sb] - ny[sa], wz = nz[sb] - nz[sa];
+        const float c = sqrtf(wx * wx + wy * wy + wz * wz);
+        const float ci_ = (a * a + b * b - c * c) / (2.0f * a * b);
+        const float cj_ = (a * a + c * c - b * b) / (2.0f * a * c);
+        const float cl_ = (b * b + c * c - a * a) / (2.0f * b * c);
+        const float dci[3] = {(a * a - b * b + c * c) / (2.0f * a * a * b),
+                              (b * b - a * a + c * c) / (2.0f * a * b * b), -c / (a * b)};
+        const float dcj[3] = {(a * a - c * c + b * b) / (2.0f * a * a * c), -b / (a * c),
+                              (c * c - a * a + b * b) / (2.0f * a * c * c)};
+        const float dcl[3] = {-a / (b * c), (b * b - c * c + a * a) / (2.0f * b * b * c),
+                              (c * c - b * b + a * a) / (2.0f * b * c * c)};
+        const float si = sqrtf(fmaxf(0.0f, 1.0f - ci_ * ci_));
+        const float dsi_dc = si > 1e-12f ? -ci_ / si : 0.0f;
+        const float C = ci_ * cj_ * cl_;
+        const float P3 = powf(a * b * c, p.N3);
+        const float xi3 = p.c3 * (1.0f + 3.0f * C) / P3;
+        const float fa = fchl_fcut(a, rc), fb = fchl_fcut(b, rc), fcc = fchl_fcut(c, rc);
+        const float dfa = a < rc ? -0.5f * (kPi / rc) * sinf(kPi * a / rc) : 0.0f;
+        const float dfb = b < rc ? -0.5f * (kPi / rc) * sinf(kPi * b / rc) : 0.0f;
+        const float dfcc = c < rc ? -0.5f * (kPi / rc) * sinf(kPi * c / rc) : 0.0f;
+        const float Fc = fa * fb * fcc;
+        const float dF[3] = {dfa * fb * fcc, fa * dfb * fcc, fa * fb * dfcc};
+        const float side[3] = {a, b, c};
+        const float A = angw * xi3 * Fc;
+        const float wc = A * ci_, ws = A * si;
+        // radial sums against this centre's g for the pair's element pair
+        const float mid = 0.5f * (a + b);
+        const float* __restrict__ gp = gi + int64_t(E) * p.n2 + int64_t(P) * p.n3 * 2;
+        float Gc = 0.f, Gs = 0.f, Gcp = 0.f, Gsp = 0.f;
+        for (int k = 0; k < p.n3; ++k) {
+          const float Rk = rc * float(k) / float(p.n3 - 1);
+          const float d = mid - Rk;
+          const float rad = expf(-p.eta3 * d * d);
+          const float drad = -2.0f * p.eta3 * d * rad;
+          Gc += gp[2 * k] * rad;
+          Gs += gp[2 * k + 1] * rad;
+          Gcp += gp[2 * k] * drad;
+          Gsp += gp[2 * k + 1] * drad;
+        }
+        float dL[3];
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          const float dC = dci[v] * cj_ * cl_ + ci_ * dcj[v] * cl_ + ci_ * cj_ * dcl[v];
+          const float dxi = p.c3 * 3.0f * dC / P3 - p.N3 * xi3 / side[v];
+          const float dA = angw * (dxi * Fc + xi3 * dF[v]);
+          const float dwc = dA * ci_ + A * dci[v];
+          const float dws = dA * si + A * dsi_dc * dci[v];
+          const float dmid = v < 2 ? 0.5f : 0.0f;
+          dL[v] = Gc * dwc + Gs * dws + (wc * Gcp + ws * Gsp) * dmid;
+        }
+        const float ua[3] = {nx[sa] / a, ny[sa] / a, nz[sa] / a};
+        const float ub[3] = {nx[sb] / b, ny[sb] / b, nz[sb] / b};
+        const float uc[3] = {wx / c, wy / c, wz / c};
+        const int sl = int(q - q0);
+#pragma unroll
+        for (int v = 0; v < 3; ++v) {
+          fi[v][sl] = -dL[0] * ua[v] - dL[1] * ub[v];
+          fj[v][sl] = dL[0] * ua[v] - dL[2] * uc[v];
+          fl[v][sl] = dL[1] * ub[v] + dL[2] * uc[v];
+        }
+        qa[sl] = sa;
+        qb[sl] = sb;
+      }
+      __syncthreads();
+      // each neighbour adds the contributions landing on it, in pair order
+      const int cnt = int(q1 - q0);
+      for (int sl = tid; sl < total; sl += 256) {
+        float sx = sacc[0][sl], sy = sacc[1][sl], sz = sacc[2][sl];
+        for (int t = 0; t < cnt; ++t) {
+          if (qa[t] == sl) {
+            sx += fj[0][t];
+            sy += fj[1][t];
+            sz += fj[2][t];
+          } else if (qb[t] == sl) {
+            sx += fl[0][t];
+            sy += fl[1][t];
+            sz += fl[2][t];
+          }
+        }
+        sacc[0][sl] = sx;
+        sacc[1][sl] = sy;
+        sacc[2][sl] = sz;
+      }
+      if (tid == 0)
+        for (int t = 0; t < cnt; ++t) {
+          cx_acc += fi[0][t];
+          cy_acc += fi[1][t];
+          cz_acc += fi[2][t];
+        }
+      __syncthreads();
+    }
+    // add this centre's contributions to the molecule's gradient
+    for (int sl = tid; sl < total; sl += 256) {
+      const int j = nidx[sl];
+      gx[j] += sacc[0][sl];
+      gy[j] += sacc[1][sl];
+      gz[j] += sacc[2][sl];
+    }
+    __syncthreads();
+    if (tid == 0) {
+      gx[ci] += cx_acc;
+      gy[ci] += cy_acc;
+      gz[ci] += cz_acc;
+    }
+    __syncthreads();
+  }
+  for (int t = tid; t < N; t += 256) {
+    dR[3 * (a0 + t)] = bad ? __builtin_nanf("") : gx[t];
+    dR[3 * (a0 + t) + 1] = bad ? __builtin_nanf("") : gy[t];
+    dR[3 * (a0 + t) + 2] = bad ? __builtin_nanf("") : gz[t];
+  }
+}
+
 }  // namespace sorf
 
 using namespace sorf;
@@ -241,6 +529,24 @@ hipError_t sorf_launch_fchl19_forward(const float* R, const int32_t* element,
     const int64_t cnt = n_atoms - a0 < kPerLaunch ? n_atoms - a0 : kPerLaunch;
     hipLaunchKernelGGL(fchl19_forward_kernel, dim3(unsigned(cnt)), dim3(256), 0, st, R, element,
                        mol_ptr, a0, n_atoms, n_mols, E, p, size, rho);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  return hipSuccess;
+}
+
+hipError_t sorf_launch_fchl19_backward(const float* R, const int32_t* element,
+                                       const int64_t* mol_ptr, int64_t n_mols, int32_t E,
+                                       const FchlParamsHost& ph, const float* g, float* dR,
+                                       hipStream_t st) {
+  if (n_mols == 0) return hipSuccess;
+  const FchlParams p{ph.n2, ph.n3, ph.eta2, ph.eta3, ph.N2, ph.N3, ph.c3, ph.zeta, ph.rcut};
+  const int64_t size = sorf_fchl19_len(E, ph.n2, ph.n3);
+  constexpr int64_t kPerLaunch = int64_t(1) << 30;
+  for (int64_t m0 = 0; m0 < n_mols; m0 += kPerLaunch) {
+    const int64_t cnt = n_mols - m0 < kPerLaunch ? n_mols - m0 : kPerLaunch;
+    hipLaunchKernelGGL(fchl19_backward_kernel, dim3(unsigned(cnt)), dim3(256), 0, st, R, element,
+                       mol_ptr, m0, n_mols, E, p, size, g, dR);
     const hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }

@@ -233,6 +233,10 @@ hipError_t sorf_launch_fchl19_forward(const float* R, const int32_t* element,
                                       const int64_t* mol_ptr, int64_t n_atoms, int64_t n_mols,
                                       int32_t n_elements, const FchlParamsHost& p, float* rho,
                                       hipStream_t s);
+hipError_t sorf_launch_fchl19_backward(const float* R, const int32_t* element,
+                                       const int64_t* mol_ptr, int64_t n_mols, int32_t n_elements,
+                                       const FchlParamsHost& p, const float* g, float* dR,
+                                       hipStream_t s);
 hipError_t sorf_launch_validate(const SorfFeatureArgs& a, int32_t* result, hipStream_t s);
 hipError_t sorf_launch_fill(float* p, int64_t n, float v, hipStream_t s);
 

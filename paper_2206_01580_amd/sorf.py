@@ -265,6 +265,27 @@ def fchl19(R: torch.Tensor, element: torch.Tensor, mol_ptr: torch.Tensor, n_elem
     return out
 
 
+def fchl19_backward(R: torch.Tensor, element: torch.Tensor, mol_ptr: torch.Tensor,
+                    n_elements: int, g: torch.Tensor, params=None,
+                    out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    """dR [n_atoms, 3] = d(sum_i g_i . rho_i)/dR (sorf_fchl19_backward); forces are -dR."""
+    prm = params if params is not None else fchl19_params()
+    A = element.numel()
+    _need(R, torch.float32, "R", 3 * A)
+    _need(element, torch.int32, "element", A)
+    _need(mol_ptr, torch.int64, "mol_ptr")
+    lib = _lib.load()
+    L = lib.sorf_fchl19_length(n_elements, ctypes.byref(prm))
+    _need(g, torch.float32, "g", A * L)
+    if out is None:
+        out = torch.empty((A, 3), dtype=torch.float32, device=R.device)
+    _need(out, torch.float32, "dR", 3 * A)
+    _lib.check("sorf_fchl19_backward", lib.sorf_fchl19_backward(
+        _ptr(R), _ptr(element), _ptr(mol_ptr), A, mol_ptr.numel() - 1, n_elements,
+        ctypes.byref(prm), _ptr(g), _ptr(out), _stream()))
+    return out
+
+
 class GramWorkspace:
     """Reusable device workspace for sorf_gram_accumulate (grows on demand)."""
 

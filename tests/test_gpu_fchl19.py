@@ -122,3 +122,65 @@ def test_fchl19_qm9_like_full_size_sampled():
         got = rho[a0:a1].double().cpu().numpy()
         scale = np.abs(ref).max(axis=1)
         assert np.all(np.abs(got - ref).max(axis=1) <= 2e-5 * scale)
+
+
+# ------------------------------------------------------------------ backward
+def gpu_grad(R, el, ptr, E, prm, g):
+    s = S()
+    return s.fchl19_backward(torch.from_numpy(np.ascontiguousarray(R, np.float32)).cuda(),
+                             torch.from_numpy(np.ascontiguousarray(el, np.int32)).cuda(),
+                             torch.from_numpy(np.asarray(ptr, np.int64)).cuda(), E,
+                             torch.from_numpy(np.ascontiguousarray(g, np.float32)).cuda(),
+                             s.fchl19_params(**prm)).cpu().numpy()
+
+
+@pytest.mark.parametrize("case", list(CASES))
+def test_fchl19_backward_matches_oracle(case):
+    """Per molecule, max |d dR| <= 2e-5 max |dR_oracle|: the row tolerance of the
+    forward, for FP32 derivatives of the same terms."""
+    sizes, E, prm, stretch = CASES[case]
+    rng = np.random.default_rng(len(case) + 100)
+    R = (W.host_geometries(sizes, seed=sum(sizes) + E) * stretch).astype(np.float32)
+    el = rng.integers(0, E, size=sum(sizes)).astype(np.int32)
+    ptr = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    L = F.fchl19_size(E, prm["n2"], prm["n3"])
+    g = rng.standard_normal((sum(sizes), L)).astype(np.float32)
+    got = gpu_grad(R, el, ptr, E, prm, g).astype(np.float64)
+    ref = F.fchl19_grad(R.astype(np.float64), el, ptr, E, prm, g.astype(np.float64))
+    worst = 0.0
+    for m in range(len(sizes)):
+        r = slice(ptr[m], ptr[m + 1])
+        if ptr[m] == ptr[m + 1]:
+            continue
+        scale = np.abs(ref[r]).max()
+        err = np.abs(got[r] - ref[r]).max()
+        if scale == 0:
+            assert err == 0
+            continue
+        worst = max(worst, err / scale)
+        assert err <= 2e-5 * scale, (m, err / scale)
+    print(f"{case}: max gradient error / molecule scale {worst:.2e}")
+
+
+def test_fchl19_backward_deterministic_and_forces_through_the_model():
+    """Forces of E = sum_i w . rho_i equal -dR for g = w, and two runs agree bitwise."""
+    sizes = [21, 9, 1]
+    rng = np.random.default_rng(9)
+    R = W.host_geometries(sizes, seed=10)
+    el = rng.integers(0, 5, size=sum(sizes)).astype(np.int32)
+    ptr = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    g = np.tile(rng.standard_normal(720).astype(np.float32), (sum(sizes), 1))
+    a = gpu_grad(R, el, ptr, 5, PRM, g)
+    b = gpu_grad(R, el, ptr, 5, PRM, g)
+    assert np.array_equal(a, b)
+    assert np.all(a[30] == 0)   # the one-atom molecule (atom 30) feels no force
+    # central differences of the GPU forward itself (FP32; loose, a cross-check only)
+    h = 2e-3
+    Rd = R.astype(np.float64)
+    for atom, c in [(0, 0), (5, 2), (24, 1)]:
+        Rp = Rd.copy(); Rp[atom, c] += h
+        Rm = Rd.copy(); Rm[atom, c] -= h
+        fp = float(np.sum(gpu_rho(Rp, el, ptr, 5, PRM).astype(np.float64) * g))
+        fm = float(np.sum(gpu_rho(Rm, el, ptr, 5, PRM).astype(np.float64) * g))
+        fd = (fp - fm) / (2 * h)
+        assert abs(a[atom, c] - fd) <= 2e-3 * max(1.0, abs(fd)), (atom, c, a[atom, c], fd)
