@@ -105,6 +105,8 @@ def parse():
                     help="run the N_transform study (0 skips it)")
     ap.add_argument("--roundoff-study", type=int, default=1,
                     help="run the FP32 round-off study of dense-W RFF vs SORF phases (0 skips it)")
+    ap.add_argument("--representation", type=int, default=1,
+                    help="run the FCHL19 representation leg (0 skips it)")
     ap.add_argument("--precision-mols", type=int, default=100000,
                     help="molecules of the precision study (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -446,6 +448,117 @@ def roundoff_study(args, p, dev, log):
             "by_nf": out}
 
 
+def fchl19_slots(R, mol_ptr, rcut, n2, n3):
+    """VALU-slot model of the FCHL19 forward: 8 slots per (neighbour, two-body bin)
+    (one exponential at quarter rate = 4, and the square, scale, multiply, add),
+    7 per (neighbour pair, three-body bin) (exponential 4, difference, square,
+    two FMAs) and 80 per neighbour pair for its geometry (a square root, divisions,
+    the power and three cutoff cosines). Returns (slots, neighbours, pairs)."""
+    nb = 0
+    pairs = 0
+    for m in range(len(mol_ptr) - 1):
+        X = R[mol_ptr[m]:mol_ptr[m + 1]].astype(np.float64)
+        d = np.sqrt(((X[:, None, :] - X[None, :, :]) ** 2).sum(-1))
+        n = (d < rcut).sum(axis=1) - 1
+        nb += int(n.sum())
+        pairs += int((n * (n - 1) // 2).sum())
+    return 8.0 * nb * n2 + 7.0 * pairs * n3 + 80.0 * pairs, nb, pairs
+
+
+def representation_leg(args, p, dev, log):
+    """FCHL19 on the QM9-like batch (20,000 molecules, 360,149 atoms on synthetic
+    molecule-like geometries, five elements, the paper's energy+force parameters,
+    720 entries per atom): the representation, its backward pass, and the whole
+    energy+force prediction chain of the paper (representation -> projection ->
+    energies; dE/dx -> dE/drho through the projection's transpose -> forces)."""
+    import torch
+
+    from paper_2206_01580_amd import sorf, workloads
+    t0 = time.perf_counter()
+    R = workloads.host_geometries(p.mol_sizes(), seed=p.seed + 9)
+    gen_s = time.perf_counter() - t0
+    prm_d = workloads.FCHL19_EF
+    prm = sorf.fchl19_params(**prm_d)
+    Rt = torch.from_numpy(R).to(dev)
+    el = torch.from_numpy(p.element).to(dev)
+    ptr = torch.from_numpy(p.mol_ptr).to(dev)
+    E, A, d = p.n_elements, p.n_atoms, p.d
+    L = workloads.FCHL19_EF_SIZE
+    rho = torch.empty((A, L), device=dev)
+    dR = torch.empty((A, 3), device=dev)
+    g = workloads.device_normal(A * L, p.seed + 10, 1.0, device=dev).view(A, L)
+    U = torch.from_numpy(workloads.random_projection(p.seed + 11, E, L, d)).to(dev)
+    Ut = U.transpose(1, 2).contiguous()
+    model, batch = sorf.Model.from_problem(p), sorf.Batch.from_problem(p)
+    alpha = torch.ones(p.n_features, device=dev)
+    predictor = sorf.Predictor(model, dev)
+    proj, projT = sorf.Projector(U), sorf.Projector(Ut)
+    x = torch.empty((A, d), device=dev)
+    Eout = torch.empty(p.n_mols, device=dev)
+    gx = torch.empty((A, d), device=dev)
+    grho = torch.empty((A, L), device=dev)
+    bx = sorf.Batch(x, el, ptr)
+
+    def chain(ev=None):
+        def mark(i):
+            if ev is not None:
+                ev[i].record()
+        mark(0)
+        sorf.fchl19(Rt, el, ptr, E, prm, out=rho)
+        mark(1)
+        proj(rho, el, x)
+        mark(2)
+        predictor(bx, alpha, E=Eout)
+        mark(3)
+        sorf.backward(model, bx, alpha, out=gx)
+        mark(4)
+        projT(gx, el, grho)
+        mark(5)
+        sorf.fchl19_backward(Rt, el, ptr, E, grho, prm, out=dR)
+        mark(6)
+
+    chain()
+    sorf.fchl19_backward(Rt, el, ptr, E, g, prm, out=dR)
+    torch.cuda.synchronize()
+    names = ["fchl19_forward", "project", "energies", "dE_dx", "project_transpose", "fchl19_backward"]
+    times = {k: [] for k in names}
+    n = 3
+    for _ in range(n):
+        ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+        chain(ev)
+        torch.cuda.synchronize()
+        for k, nm in enumerate(names):
+            times[nm].append(ev[k].elapsed_time(ev[k + 1]))
+    med = {k: float(np.median(v)) for k, v in times.items()}
+    slots, nb, pairs = fchl19_slots(R, p.mol_ptr, prm_d["rcut"], prm_d["n2"], prm_d["n3"])
+    tops = slots / (med["fchl19_forward"] * 1e-3) / 1e12
+    out = {
+        "workload": (f"{p.n_mols} QM9-like molecules, {A} atoms on synthetic geometries, {E} elements, "
+                     f"FCHL19 energy+force parameters ({L} entries), {nb} neighbour entries, "
+                     f"{pairs} neighbour pairs; projection {L} -> {d}, D={p.n_features}"),
+        "phase_ms": med,
+        "chain_ms": sum(med.values()),
+        "atoms_per_s_energy_force": A / (sum(med.values()) * 1e-3),
+        "roofline_fchl19_forward": {"bound": "alu", "achieved": tops, "peak": PEAK_VALU_TOPS,
+                                    "unit": "T VALU-slots/s", "frac": tops / PEAK_VALU_TOPS,
+                                    "traffic": None, "slots_per_launch": slots},
+        "geometry_gen_s": gen_s,
+    }
+    if not args.no_cpu_baseline:
+        from oracle import fchl19_oracle as F
+        k = 40
+        a1 = int(p.mol_ptr[k])
+        t1 = time.perf_counter()
+        F.fchl19(R[:a1].astype(np.float64), p.element[:a1], p.mol_ptr[:k + 1], E, prm_d)
+        t = time.perf_counter() - t1
+        out["cpu_baseline"] = {"value": a1 / t, "unit": "atoms/s (FCHL19 forward)",
+                               "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
+                               "sample": f"FP64 oracle FCHL19 of {k} molecules ({a1} atoms), {t:.2f} s"}
+    del rho, dR, g, U, Ut, x, gx, grho
+    torch.cuda.empty_cache()
+    return out
+
+
 def precision_study(args, dev, log):
     """Gram precision modes on the precision workload (100,000 QM9-like
     molecules, D = 16384, lambda = 1e-8, 3 refinement steps): coefficient and
@@ -721,6 +834,9 @@ def main():
         out["ntransform_study"] = ntransform_study(args, p, dev, log)
     if args.roundoff_study:
         out["roundoff_study"] = roundoff_study(args, p, dev, log)
+    if args.representation:
+        log("representation")
+        out["representation"] = representation_leg(args, p, dev, log)
     if args.precision_mols > 0:
         out["precision_study"] = precision_study(args, dev, log)
     if not args.no_cpu_baseline:

@@ -237,8 +237,8 @@ __global__ __launch_bounds__(256) void fchl19_forward_kernel(
 // that land on its atom, while thread 0 adds the centre's: every gradient
 // entry is summed in a fixed order (deterministic, no atomics).
 // ---------------------------------------------------------------------------
-constexpr int kFchlBwdMaxAtoms = 1024;   // atoms of one molecule held in LDS
-constexpr int kFchlBwdPairChunk = 1024;
+constexpr int kFchlBwdMaxAtoms = 512;    // atoms of one molecule held in LDS
+constexpr int kFchlBwdPairChunk = 512;
 
 __global__ __launch_bounds__(256) void fchl19_backward_kernel(
     const float* __restrict__ R, const int32_t* __restrict__ element,
