@@ -237,6 +237,232 @@ __global__ __launch_bounds__(256) void fchl19_forward_kernel(
 // that land on its atom, while thread 0 adds the centre's: every gradient
 // entry is summed in a fixed order (deterministic, no atomics).
 // ---------------------------------------------------------------------------
+// dL/da, dL/db, dL/dc for one centre i and neighbour pair (j, l) with sides
+// a = r_ij, b = r_il, c = r_jl, where L is the pair's three-body terms
+// contracted with the centre's upstream gradient gp (the 2 n3 entries of the
+// pair's element pair, [radial bin][cos, sin]). The cosines are functions of
+// the sides (law of cosines), so this is the whole positional dependence.
+__device__ __forceinline__ void fchl_triple_grad(float a, float b, float c,
+                                                 const float* __restrict__ gp,
+                                                 const FchlParams& p, float angw, float (&dL)[3]) {
+  const float kPi = 3.14159265358979f;
+  const float rc = p.rcut;
+  const float ci_ = (a * a + b * b - c * c) / (2.0f * a * b);
+  const float cj_ = (a * a + c * c - b * b) / (2.0f * a * c);
+  const float cl_ = (b * b + c * c - a * a) / (2.0f * b * c);
+  const float dci[3] = {(a * a - b * b + c * c) / (2.0f * a * a * b),
+                        (b * b - a * a + c * c) / (2.0f * a * b * b), -c / (a * b)};
+  const float dcj[3] = {(a * a - c * c + b * b) / (2.0f * a * a * c), -b / (a * c),
+                        (c * c - a * a + b * b) / (2.0f * a * c * c)};
+  const float dcl[3] = {-a / (b * c), (b * b - c * c + a * a) / (2.0f * b * b * c),
+                        (c * c - b * b + a * a) / (2.0f * b * c * c)};
+  const float si = sqrtf(fmaxf(0.0f, 1.0f - ci_ * ci_));
+  const float dsi_dc = si > 1e-12f ? -ci_ / si : 0.0f;
+  const float C = ci_ * cj_ * cl_;
+  const float P3 = powf(a * b * c, p.N3);
+  const float xi3 = p.c3 * (1.0f + 3.0f * C) / P3;
+  const float fa = fchl_fcut(a, rc), fb = fchl_fcut(b, rc), fcc = fchl_fcut(c, rc);
+  const float dfa = a < rc ? -0.5f * (kPi / rc) * sinf(kPi * a / rc) : 0.0f;
+  const float dfb = b < rc ? -0.5f * (kPi / rc) * sinf(kPi * b / rc) : 0.0f;
+  const float dfcc = c < rc ? -0.5f * (kPi / rc) * sinf(kPi * c / rc) : 0.0f;
+  const float Fc = fa * fb * fcc;
+  const float dF[3] = {dfa * fb * fcc, fa * dfb * fcc, fa * fb * dfcc};
+  const float side[3] = {a, b, c};
+  const float A = angw * xi3 * Fc;
+  const float wc = A * ci_, ws = A * si;
+  const float mid = 0.5f * (a + b);
+  float Gc = 0.f, Gs = 0.f, Gcp = 0.f, Gsp = 0.f;
+  for (int k = 0; k < p.n3; ++k) {
+    const float Rk = rc * float(k) / float(p.n3 - 1);
+    const float d = mid - Rk;
+    const float rad = expf(-p.eta3 * d * d);
+    const float drad = -2.0f * p.eta3 * d * rad;
+    Gc += gp[2 * k] * rad;
+    Gs += gp[2 * k + 1] * rad;
+    Gcp += gp[2 * k] * drad;
+    Gsp += gp[2 * k + 1] * drad;
+  }
+#pragma unroll
+  for (int v = 0; v < 3; ++v) {
+    const float dC = dci[v] * cj_ * cl_ + ci_ * dcj[v] * cl_ + ci_ * cj_ * dcl[v];
+    const float dxi = p.c3 * 3.0f * dC / P3 - p.N3 * xi3 / side[v];
+    const float dA = angw * (dxi * Fc + xi3 * dF[v]);
+    const float dwc = dA * ci_ + A * dci[v];
+    const float dws = dA * si + A * dsi_dc * dci[v];
+    const float dmid = v < 2 ? 0.5f : 0.0f;
+    dL[v] = Gc * dwc + Gs * dws + (wc * Gcp + ws * Gsp) * dmid;
+  }
+}
+
+// d/dr of the two-body terms of one neighbour at distance r, contracted with
+// the centre's upstream gradient gX (the n2 bins of the neighbour's element)
+__device__ __forceinline__ float fchl_pair_grad(float r, const float* __restrict__ gX,
+                                                const FchlParams& p) {
+  const float kPi = 3.14159265358979f;
+  const float rc = p.rcut;
+  const float q = 1.0f + p.eta2 / (r * r);
+  const float s2 = logf(q);
+  const float ds2 = -2.0f * p.eta2 / (r * r * r * q);
+  const float mu = logf(r / sqrtf(q));
+  const float dmu = 1.0f / r + p.eta2 / (r * r * r * q);
+  const float fcv = fchl_fcut(r, rc);
+  const float dfc = r < rc ? -0.5f * (kPi / rc) * sinf(kPi * r / rc) : 0.0f;
+  const float pref = powf(r, -p.N2) / (sqrtf(s2) * 2.50662827463100f);
+  float dL = 0.0f;
+  for (int k = 0; k < p.n2; ++k) {
+    const float Rk = rc * float(k + 1) / float(p.n2);
+    const float Lk = logf(Rk) - mu;
+    const float B = pref * expf(-Lk * Lk / (2.0f * s2)) / Rk;
+    const float D = -p.N2 / r - 0.5f * ds2 / s2 + Lk * dmu / s2 + Lk * Lk * ds2 / (2.0f * s2 * s2);
+    dL += gX[k] * (dfc + fcv * D) * B;
+  }
+  return dL;
+}
+
+// Molecules of at most kFchlSmallAtoms atoms: one workgroup per molecule,
+// its four waves take four centres at a time. A wave keeps the centre's
+// neighbours one per lane; lane s forms the two-body term of its neighbour
+// and, for every other neighbour t in order, the three-body term of the pair
+// (s, t) as it lands on s (each pair is evaluated by both of its lanes, so no
+// lane waits for another), plus the centre's share for t > s. The four
+// centres' results are merged into the molecule's gradient in centre order.
+constexpr int kFchlSmallAtoms = 64;
+
+__global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
+    const float* __restrict__ R, const int32_t* __restrict__ element,
+    const int64_t* __restrict__ mol_ptr, int64_t m0, int64_t n_mols, int32_t E, FchlParams p,
+    int64_t size, const float* __restrict__ g, float* __restrict__ dR) {
+  __shared__ float ax[kFchlSmallAtoms], ay[kFchlSmallAtoms], az[kFchlSmallAtoms];
+  __shared__ int32_t ael[kFchlSmallAtoms];
+  __shared__ float gsum[3][kFchlSmallAtoms];
+  __shared__ float res[4][3][kFchlSmallAtoms];
+  __shared__ int32_t nid[4][kFchlSmallAtoms];
+
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t m = m0 + blockIdx.x;
+  if (m >= n_mols) return;
+  const int64_t a0 = mol_ptr[m];
+  const int N = int(mol_ptr[m + 1] - a0);
+  if (N <= 0 || N > kFchlSmallAtoms) return;   // larger molecules: fchl19_backward_kernel
+  const float rc = p.rcut;
+  if (tid < N) {
+    ax[tid] = R[3 * (a0 + tid)];
+    ay[tid] = R[3 * (a0 + tid) + 1];
+    az[tid] = R[3 * (a0 + tid) + 2];
+    ael[tid] = element[a0 + tid];
+    gsum[0][tid] = gsum[1][tid] = gsum[2][tid] = 0.0f;
+  }
+  __syncthreads();
+  const float angw = 2.0f * expf(-0.5f * p.zeta * p.zeta) * sqrtf(p.eta3 / 3.14159265358979f);
+
+  for (int c0 = 0; c0 < N; c0 += 4) {
+    const int ci = c0 + wv;
+    res[wv][0][lane] = res[wv][1][lane] = res[wv][2][lane] = 0.0f;
+    if (ci < N) {   // wave-uniform
+      const float* __restrict__ gi = g + (a0 + ci) * size;
+      // this lane's candidate atom, then the neighbours in element order
+      const int t = lane;
+      float dx = 0.f, dy = 0.f, dz = 0.f, r = 0.f;
+      bool in = false;
+      if (t < N && t != ci) {
+        dx = ax[t] - ax[ci];
+        dy = ay[t] - ay[ci];
+        dz = az[t] - az[ci];
+        r = sqrtf(dx * dx + dy * dy + dz * dz);
+        in = r < rc;
+      }
+      int n = 0;
+      for (int X = 0; X < E; ++X) {
+        const bool f = in && ael[t < N ? t : 0] == X;
+        const uint64_t mask = __ballot(f);
+        if (f) nid[wv][n + __popcll(mask & ((uint64_t(1) << lane) - 1))] = t;
+        n += __popcll(mask);
+      }
+      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+      __builtin_amdgcn_wave_barrier();
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+      float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
+      if (lane < n) {
+        const int js = nid[wv][lane];
+        const float ux = ax[js] - ax[ci], uy = ay[js] - ay[ci], uz = az[js] - az[ci];
+        const float rs = sqrtf(ux * ux + uy * uy + uz * uz);
+        const int Xs = ael[js];
+        const float d2 = fchl_pair_grad(rs, gi + Xs * p.n2, p) / rs;
+        sx = ux * d2;
+        sy = uy * d2;
+        sz = uz * d2;
+        cx = -sx;
+        cy = -sy;
+        cz = -sz;
+        for (int u = 0; u < n; ++u) {
+          if (u == lane) continue;
+          const int ju = nid[wv][u];
+          const bool first = lane < u;   // the pair's j is the lower slot
+          const int ja = first ? js : ju, jb = first ? ju : js;
+          const float vax = ax[ja] - ax[ci], vay = ay[ja] - ay[ci], vaz = az[ja] - az[ci];
+          const float vbx = ax[jb] - ax[ci], vby = ay[jb] - ay[ci], vbz = az[jb] - az[ci];
+          const float a = sqrtf(vax * vax + vay * vay + vaz * vaz);
+          const float b = sqrtf(vbx * vbx + vby * vby + vbz * vbz);
+          const float wx = vbx - vax, wy = vby - vay, wz = vbz - vaz;
+          const float c = sqrtf(wx * wx + wy * wy + wz * wz);
+          const int Xa = ael[ja], Xb = ael[jb];
+          const int P = fchl_pair(Xa < Xb ? Xa : Xb, Xa < Xb ? Xb : Xa, E);
+          float dL[3];
+          fchl_triple_grad(a, b, c, gi + int64_t(E) * p.n2 + int64_t(P) * p.n3 * 2, p, angw, dL);
+          const float ua[3] = {vax / a, vay / a, vaz / a};
+          const float ub[3] = {vbx / b, vby / b, vbz / b};
+          const float uc[3] = {wx / c, wy / c, wz / c};
+          if (first) {   // this lane is j: fj, and the centre's fi once per pair
+            sx += dL[0] * ua[0] - dL[2] * uc[0];
+            sy += dL[0] * ua[1] - dL[2] * uc[1];
+            sz += dL[0] * ua[2] - dL[2] * uc[2];
+            cx += -dL[0] * ua[0] - dL[1] * ub[0];
+            cy += -dL[0] * ua[1] - dL[1] * ub[1];
+            cz += -dL[0] * ua[2] - dL[1] * ub[2];
+          } else {       // this lane is l
+            sx += dL[1] * ub[0] + dL[2] * uc[0];
+            sy += dL[1] * ub[1] + dL[2] * uc[1];
+            sz += dL[1] * ub[2] + dL[2] * uc[2];
+          }
+        }
+        res[wv][0][js] = sx;
+        res[wv][1][js] = sy;
+        res[wv][2][js] = sz;
+      }
+      // the centre's total over the lanes, in a fixed butterfly order
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) {
+        cx += __shfl_xor(cx, o);
+        cy += __shfl_xor(cy, o);
+        cz += __shfl_xor(cz, o);
+      }
+      if (lane == 0) {
+        res[wv][0][ci] = cx;
+        res[wv][1][ci] = cy;
+        res[wv][2][ci] = cz;
+      }
+    }
+    __syncthreads();
+    if (tid < N) {
+#pragma unroll
+      for (int v = 0; v < 3; ++v) {
+        float acc = gsum[v][tid];
+        acc += res[0][v][tid];
+        acc += res[1][v][tid];
+        acc += res[2][v][tid];
+        acc += res[3][v][tid];
+        gsum[v][tid] = acc;
+      }
+    }
+    __syncthreads();
+  }
+  if (tid < N) {
+    dR[3 * (a0 + tid)] = gsum[0][tid];
+    dR[3 * (a0 + tid) + 1] = gsum[1][tid];
+    dR[3 * (a0 + tid) + 2] = gsum[2][tid];
+  }
+}
+
 constexpr int kFchlBwdMaxAtoms = 512;    // atoms of one molecule held in LDS
 constexpr int kFchlBwdPairChunk = 512;
 
@@ -261,7 +487,7 @@ __global__ __launch_bounds__(256) void fchl19_backward_kernel(
   if (m >= n_mols) return;
   const int64_t a0 = mol_ptr[m];
   const int N = int(mol_ptr[m + 1] - a0);
-  if (N <= 0) return;
+  if (N <= kFchlSmallAtoms) return;   // fchl19_backward_small_kernel
   if (N > kFchlBwdMaxAtoms) {   // more atoms than the LDS holds: mark the rows, do not guess
     for (int t = tid; t < 3 * N; t += 256) dR[3 * a0 + t] = __builtin_nanf("");
     return;
@@ -338,22 +564,7 @@ __global__ __launch_bounds__(256) void fchl19_backward_kernel(
       int X = 0;
       while (sl >= grp[X + 1]) ++X;
       const float r = nr[sl];
-      const float q = 1.0f + p.eta2 / (r * r);
-      const float s2 = logf(q);
-      const float ds2 = -2.0f * p.eta2 / (r * r * r * q);
-      const float mu = logf(r / sqrtf(q));
-      const float dmu = 1.0f / r + p.eta2 / (r * r * r * q);
-      const float fcv = fchl_fcut(r, rc);
-      const float dfc = r < rc ? -0.5f * (kPi / rc) * sinf(kPi * r / rc) : 0.0f;
-      const float pref = powf(r, -p.N2) / (sqrtf(s2) * 2.50662827463100f);
-      float dL = 0.0f;
-      for (int k = 0; k < p.n2; ++k) {
-        const float Rk = rc * float(k + 1) / float(p.n2);
-        const float Lk = logf(Rk) - mu;
-        const float B = pref * expf(-Lk * Lk / (2.0f * s2)) / Rk;
-        const float D = -p.N2 / r - 0.5f * ds2 / s2 + Lk * dmu / s2 + Lk * Lk * ds2 / (2.0f * s2 * s2);
-        dL += gi[X * p.n2 + k] * (dfc + fcv * D) * B;
-      }
+      const float dL = fchl_pair_grad(r, gi + X * p.n2, p);
       const float inv = dL / r;
       sacc[0][sl] = nx[sl] * inv;
       sacc[1][sl] = ny[sl] * inv;
@@ -398,54 +609,8 @@ __global__ __launch_bounds__(256) void fchl19_backward_kernel(
         const float a = nr[sa], b = nr[sb];
         const float wx = nx[sb] - nx[sa], wy = ny[sb] - ny[sa], wz = nz[sb] - nz[sa];
         const float c = sqrtf(wx * wx + wy * wy + wz * wz);
-        const float ci_ = (a * a + b * b - c * c) / (2.0f * a * b);
-        const float cj_ = (a * a + c * c - b * b) / (2.0f * a * c);
-        const float cl_ = (b * b + c * c - a * a) / (2.0f * b * c);
-        const float dci[3] = {(a * a - b * b + c * c) / (2.0f * a * a * b),
-                              (b * b - a * a + c * c) / (2.0f * a * b * b), -c / (a * b)};
-        const float dcj[3] = {(a * a - c * c + b * b) / (2.0f * a * a * c), -b / (a * c),
-                              (c * c - a * a + b * b) / (2.0f * a * c * c)};
-        const float dcl[3] = {-a / (b * c), (b * b - c * c + a * a) / (2.0f * b * b * c),
-                              (c * c - b * b + a * a) / (2.0f * b * c * c)};
-        const float si = sqrtf(fmaxf(0.0f, 1.0f - ci_ * ci_));
-        const float dsi_dc = si > 1e-12f ? -ci_ / si : 0.0f;
-        const float C = ci_ * cj_ * cl_;
-        const float P3 = powf(a * b * c, p.N3);
-        const float xi3 = p.c3 * (1.0f + 3.0f * C) / P3;
-        const float fa = fchl_fcut(a, rc), fb = fchl_fcut(b, rc), fcc = fchl_fcut(c, rc);
-        const float dfa = a < rc ? -0.5f * (kPi / rc) * sinf(kPi * a / rc) : 0.0f;
-        const float dfb = b < rc ? -0.5f * (kPi / rc) * sinf(kPi * b / rc) : 0.0f;
-        const float dfcc = c < rc ? -0.5f * (kPi / rc) * sinf(kPi * c / rc) : 0.0f;
-        const float Fc = fa * fb * fcc;
-        const float dF[3] = {dfa * fb * fcc, fa * dfb * fcc, fa * fb * dfcc};
-        const float side[3] = {a, b, c};
-        const float A = angw * xi3 * Fc;
-        const float wc = A * ci_, ws = A * si;
-        // radial sums against this centre's g for the pair's element pair
-        const float mid = 0.5f * (a + b);
-        const float* __restrict__ gp = gi + int64_t(E) * p.n2 + int64_t(P) * p.n3 * 2;
-        float Gc = 0.f, Gs = 0.f, Gcp = 0.f, Gsp = 0.f;
-        for (int k = 0; k < p.n3; ++k) {
-          const float Rk = rc * float(k) / float(p.n3 - 1);
-          const float d = mid - Rk;
-          const float rad = expf(-p.eta3 * d * d);
-          const float drad = -2.0f * p.eta3 * d * rad;
-          Gc += gp[2 * k] * rad;
-          Gs += gp[2 * k + 1] * rad;
-          Gcp += gp[2 * k] * drad;
-          Gsp += gp[2 * k + 1] * drad;
-        }
         float dL[3];
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          const float dC = dci[v] * cj_ * cl_ + ci_ * dcj[v] * cl_ + ci_ * cj_ * dcl[v];
-          const float dxi = p.c3 * 3.0f * dC / P3 - p.N3 * xi3 / side[v];
-          const float dA = angw * (dxi * Fc + xi3 * dF[v]);
-          const float dwc = dA * ci_ + A * dci[v];
-          const float dws = dA * si + A * dsi_dc * dci[v];
-          const float dmid = v < 2 ? 0.5f : 0.0f;
-          dL[v] = Gc * dwc + Gs * dws + (wc * Gcp + ws * Gsp) * dmid;
-        }
+        fchl_triple_grad(a, b, c, gi + int64_t(E) * p.n2 + int64_t(P) * p.n3 * 2, p, angw, dL);
         const float ua[3] = {nx[sa] / a, ny[sa] / a, nz[sa] / a};
         const float ub[3] = {nx[sb] / b, ny[sb] / b, nz[sb] / b};
         const float uc[3] = {wx / c, wy / c, wz / c};
@@ -545,9 +710,13 @@ hipError_t sorf_launch_fchl19_backward(const float* R, const int32_t* element,
   constexpr int64_t kPerLaunch = int64_t(1) << 30;
   for (int64_t m0 = 0; m0 < n_mols; m0 += kPerLaunch) {
     const int64_t cnt = n_mols - m0 < kPerLaunch ? n_mols - m0 : kPerLaunch;
+    hipLaunchKernelGGL(fchl19_backward_small_kernel, dim3(unsigned(cnt)), dim3(256), 0, st, R,
+                       element, mol_ptr, m0, n_mols, E, p, size, g, dR);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fchl19_backward_kernel, dim3(unsigned(cnt)), dim3(256), 0, st, R, element,
                        mol_ptr, m0, n_mols, E, p, size, g, dR);
-    const hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
