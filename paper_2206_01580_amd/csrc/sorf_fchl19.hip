@@ -31,6 +31,7 @@ namespace sorf {
 constexpr int kFchlMaxNb = 512;        // neighbours of one atom held in LDS
 constexpr int kFchlPairChunk = 2048;   // three-body pairs per LDS chunk
 constexpr int kFchlMaxElements = 16;
+constexpr int kFchlSmallMol = 64;       // molecules up to this size take the wave-per-atom kernel
 
 struct FchlParams {
   int32_t n2, n3;
@@ -60,6 +61,7 @@ __global__ __launch_bounds__(256) void fchl19_forward_kernel(
   if (i >= n_atoms) return;
   const int64_t m = molecule_of(mol_ptr, n_mols, i);
   const int64_t a0 = mol_ptr[m], a1 = mol_ptr[m + 1];
+  if (a1 - a0 <= kFchlSmallMol) return;   // fchl19_forward_small_kernel takes this atom
   const float rc = p.rcut;
   const float xi = R[3 * i], yi = R[3 * i + 1], zi = R[3 * i + 2];
   float* __restrict__ out = rho + i * size;
@@ -218,6 +220,173 @@ __global__ __launch_bounds__(256) void fchl19_forward_kernel(
         o[1] = acc_s[h];
       }
     }
+  }
+}
+
+// Atoms of molecules of at most kFchlSmallMol atoms: one wave per atom, four
+// atoms per workgroup, no workgroup barriers. The wave's lanes take the
+// molecule's atoms, gather the neighbours by element with ballots into the
+// wave's LDS, form the two-body bins (lanes over bins), then the three-body
+// pair weights in chunks (lanes over pairs) and the three-body bins (lanes
+// over bins, each bin summing its pairs of the chunk in order and adding the
+// chunk's sum to its entry of rho, chunk by chunk). Every entry is summed in
+// the same fixed order as in the workgroup-per-atom kernel's numbering.
+constexpr int kFchlWavePairs = 512;
+
+__device__ __forceinline__ void wave_sync_lds() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
+__global__ __launch_bounds__(256) void fchl19_forward_small_kernel(
+    const float* __restrict__ R, const int32_t* __restrict__ element,
+    const int64_t* __restrict__ mol_ptr, int64_t atom0, int64_t n_atoms, int64_t n_mols,
+    int32_t E, FchlParams p, int64_t size, float* __restrict__ rho) {
+  __shared__ float nx[4][kFchlSmallMol], ny[4][kFchlSmallMol], nz[4][kFchlSmallMol];
+  __shared__ float nr[4][kFchlSmallMol], c2[4][kFchlSmallMol], mu2[4][kFchlSmallMol],
+      inv2s2[4][kFchlSmallMol];
+  __shared__ int32_t grp[4][kFchlMaxElements + 1];
+  __shared__ int64_t seg[4][kFchlMaxElements * (kFchlMaxElements + 1) / 2 + 1];
+  __shared__ float pw_c[4][kFchlWavePairs], pw_s[4][kFchlWavePairs], pmid[4][kFchlWavePairs];
+
+  const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+  const int64_t i = atom0 + int64_t(blockIdx.x) * 4 + wv;
+  if (i >= n_atoms) return;                   // whole waves leave
+  const int64_t m = molecule_of(mol_ptr, n_mols, i);
+  const int64_t a0 = mol_ptr[m];
+  const int N = int(mol_ptr[m + 1] - a0);
+  if (N > kFchlSmallMol) return;              // fchl19_forward_kernel takes this atom
+  const float rc = p.rcut;
+  float* __restrict__ out = rho + i * size;
+
+  // neighbours by element, atom order inside a group (lane = candidate atom)
+  const int64_t j = a0 + lane;
+  float dx = 0.f, dy = 0.f, dz = 0.f, r = 0.f;
+  bool in = false;
+  int ej = -1;
+  if (lane < N && j != i) {
+    dx = R[3 * j] - R[3 * i];
+    dy = R[3 * j + 1] - R[3 * i + 1];
+    dz = R[3 * j + 2] - R[3 * i + 2];
+    r = sqrtf(dx * dx + dy * dy + dz * dz);
+    in = r < rc;
+    ej = element[j];
+  }
+  int n = 0;
+  for (int X = 0; X < E; ++X) {
+    if (lane == 0) grp[wv][X] = n;
+    const bool f = in && ej == X;
+    const uint64_t mask = __ballot(f);
+    if (f) {
+      const int sl = n + __popcll(mask & ((uint64_t(1) << lane) - 1));
+      nx[wv][sl] = dx;
+      ny[wv][sl] = dy;
+      nz[wv][sl] = dz;
+      nr[wv][sl] = r;
+      const float q = 1.0f + p.eta2 / (r * r);
+      const float s2 = logf(q);
+      c2[wv][sl] = fchl_fcut(r, rc) * powf(r, -p.N2) / (sqrtf(s2) * 2.50662827463100f);
+      mu2[wv][sl] = logf(r / sqrtf(q));
+      inv2s2[wv][sl] = 0.5f / s2;
+    }
+    n += __popcll(mask);
+  }
+  if (lane == 0) grp[wv][E] = n;
+  wave_sync_lds();
+
+  // two-body bins
+  for (int t = lane; t < E * p.n2; t += 64) {
+    const int X = t / p.n2, k = t % p.n2;
+    const float Rk = rc * float(k + 1) / float(p.n2);
+    const float lnR = logf(Rk);
+    float acc = 0.0f;
+    for (int sl = grp[wv][X]; sl < grp[wv][X + 1]; ++sl) {
+      const float d = lnR - mu2[wv][sl];
+      acc += c2[wv][sl] * expf(-d * d * inv2s2[wv][sl]);
+    }
+    out[t] = acc / Rk;
+  }
+
+  // three-body
+  const int NP = E * (E + 1) / 2;
+  if (lane == 0) {
+    int64_t o = 0;
+    for (int X = 0; X < E; ++X)
+      for (int Y = X; Y < E; ++Y) {
+        seg[wv][fchl_pair(X, Y, E)] = o;
+        const int64_t cx = grp[wv][X + 1] - grp[wv][X], cy = grp[wv][Y + 1] - grp[wv][Y];
+        o += X == Y ? cx * (cx - 1) / 2 : cx * cy;
+      }
+    seg[wv][NP] = o;
+  }
+  wave_sync_lds();
+  const int64_t n_pairs = seg[wv][NP];
+  const float angw = 2.0f * expf(-0.5f * p.zeta * p.zeta) * sqrtf(p.eta3 / 3.14159265358979f);
+  const int nbins = NP * p.n3;
+  for (int64_t q0 = 0; q0 < n_pairs || q0 == 0; q0 += kFchlWavePairs) {
+    const int64_t q1 = q0 + kFchlWavePairs < n_pairs ? q0 + kFchlWavePairs : n_pairs;
+    for (int64_t q = q0 + lane; q < q1; q += 64) {
+      int P = 0;
+      while (q >= seg[wv][P + 1]) ++P;
+      int X = 0;
+      while (fchl_pair(X, X, E) + (E - X) <= P) ++X;
+      const int Y = X + (P - fchl_pair(X, X, E));
+      const int64_t loc = q - seg[wv][P];
+      int a, b;
+      if (X != Y) {
+        const int cy = grp[wv][Y + 1] - grp[wv][Y];
+        a = grp[wv][X] + int(loc / cy);
+        b = grp[wv][Y] + int(loc % cy);
+      } else {
+        const int cx = grp[wv][X + 1] - grp[wv][X];
+        const double c2x = 2.0 * cx - 1.0;
+        int u = int((c2x - sqrt(c2x * c2x - 8.0 * double(loc))) * 0.5);
+        if (u < 0) u = 0;
+        while (u > 0 && int64_t(u) * (2 * cx - u - 1) / 2 > loc) --u;
+        while (int64_t(u + 1) * (2 * cx - u - 2) / 2 <= loc) ++u;
+        a = grp[wv][X] + u;
+        b = grp[wv][X] + u + 1 + int(loc - int64_t(u) * (2 * cx - u - 1) / 2);
+      }
+      const float rij = nr[wv][a], rik = nr[wv][b];
+      const float jx = nx[wv][b] - nx[wv][a], jy = ny[wv][b] - ny[wv][a], jz = nz[wv][b] - nz[wv][a];
+      const float rjk = sqrtf(jx * jx + jy * jy + jz * jz);
+      const float cos_i = (nx[wv][a] * nx[wv][b] + ny[wv][a] * ny[wv][b] + nz[wv][a] * nz[wv][b]) / (rij * rik);
+      const float cos_j = -(nx[wv][a] * jx + ny[wv][a] * jy + nz[wv][a] * jz) / (rij * rjk);
+      const float cos_k = (nx[wv][b] * jx + ny[wv][b] * jy + nz[wv][b] * jz) / (rik * rjk);
+      const float sin_i = sqrtf(fmaxf(0.0f, 1.0f - cos_i * cos_i));
+      const float xi3 = p.c3 * (1.0f + 3.0f * cos_i * cos_j * cos_k) / powf(rij * rjk * rik, p.N3);
+      const float w = xi3 * fchl_fcut(rij, rc) * fchl_fcut(rjk, rc) * fchl_fcut(rik, rc) * angw;
+      const int sl = int(q - q0);
+      pw_c[wv][sl] = w * cos_i;
+      pw_s[wv][sl] = w * sin_i;
+      pmid[wv][sl] = 0.5f * (rij + rik);
+    }
+    wave_sync_lds();
+    for (int t = lane; t < nbins; t += 64) {
+      const int P = t / p.n3, k = t % p.n3;
+      const float Rk = rc * float(k) / float(p.n3 - 1);
+      const int64_t lo = seg[wv][P] > q0 ? seg[wv][P] : q0;
+      const int64_t hi = seg[wv][P + 1] < q1 ? seg[wv][P + 1] : q1;
+      float c = 0.f, sn = 0.f;
+      for (int64_t q = lo; q < hi; ++q) {
+        const int sl = int(q - q0);
+        const float d = pmid[wv][sl] - Rk;
+        const float gk = expf(-p.eta3 * d * d);
+        c += pw_c[wv][sl] * gk;
+        sn += pw_s[wv][sl] * gk;
+      }
+      float* o = out + int64_t(E) * p.n2 + 2 * int64_t(t);
+      if (q0 == 0) {
+        o[0] = c;
+        o[1] = sn;
+      } else {
+        o[0] += c;
+        o[1] += sn;
+      }
+    }
+    wave_sync_lds();   // the chunk's weights are no longer read
+    if (n_pairs == 0) break;
   }
 }
 
@@ -692,9 +861,13 @@ hipError_t sorf_launch_fchl19_forward(const float* R, const int32_t* element,
   constexpr int64_t kPerLaunch = int64_t(1) << 30;
   for (int64_t a0 = 0; a0 < n_atoms; a0 += kPerLaunch) {
     const int64_t cnt = n_atoms - a0 < kPerLaunch ? n_atoms - a0 : kPerLaunch;
+    hipLaunchKernelGGL(fchl19_forward_small_kernel, dim3(unsigned((cnt + 3) / 4)), dim3(256), 0, st,
+                       R, element, mol_ptr, a0, n_atoms, n_mols, E, p, size, rho);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fchl19_forward_kernel, dim3(unsigned(cnt)), dim3(256), 0, st, R, element,
                        mol_ptr, a0, n_atoms, n_mols, E, p, size, rho);
-    const hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
   return hipSuccess;
