@@ -13,7 +13,8 @@
 //                 theta the angle at i, R_k = r_cut k / (n3 - 1); f_cut(r) = (cos(pi r/r_cut) + 1)/2
 //                 below r_cut and 0 beyond.
 //
-// One workgroup (4 waves) per atom. The atom's neighbours (same molecule,
+// Atoms of molecules of up to 64 atoms take one wave each (see
+// fchl19_forward_small_kernel). Larger molecules: one workgroup (4 waves) per atom. The atom's neighbours (same molecule,
 // closer than r_cut) are gathered into LDS grouped by element, in atom order
 // inside each group (ballot compaction, no atomics), with their per-neighbour
 // two-body factors. Two-body bins: one thread per (element, bin) sums its
@@ -45,10 +46,10 @@ __device__ __forceinline__ float fchl_fcut(float r, float rc) {
 // element pair (a <= b) -> position in the lexicographic list of pairs
 __device__ __forceinline__ int fchl_pair(int a, int b, int E) { return a * E - a * (a - 1) / 2 + (b - a); }
 
-__global__ __launch_bounds__(256) void fchl19_forward_kernel(
-    const float* __restrict__ R, const int32_t* __restrict__ element,
-    const int64_t* __restrict__ mol_ptr, int64_t atom0, int64_t n_atoms, int64_t n_mols,
-    int32_t E, FchlParams p, int64_t size, float* __restrict__ rho) {
+__device__ __forceinline__ void fchl19_forward_atom(
+    int64_t i, const float* __restrict__ R, const int32_t* __restrict__ element,
+    const int64_t* __restrict__ mol_ptr, int64_t n_mols, int32_t E, const FchlParams& p,
+    int64_t size, float* __restrict__ rho) {
   __shared__ float nx[kFchlMaxNb], ny[kFchlMaxNb], nz[kFchlMaxNb], nr[kFchlMaxNb];
   __shared__ float c2[kFchlMaxNb], mu2[kFchlMaxNb], inv2s2[kFchlMaxNb];
   __shared__ int32_t grp[kFchlMaxElements + 1];     // neighbour offsets per element
@@ -57,11 +58,8 @@ __global__ __launch_bounds__(256) void fchl19_forward_kernel(
   __shared__ float pw_c[kFchlPairChunk], pw_s[kFchlPairChunk], pmid[kFchlPairChunk];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t i = atom0 + blockIdx.x;
-  if (i >= n_atoms) return;
   const int64_t m = molecule_of(mol_ptr, n_mols, i);
   const int64_t a0 = mol_ptr[m], a1 = mol_ptr[m + 1];
-  if (a1 - a0 <= kFchlSmallMol) return;   // fchl19_forward_small_kernel takes this atom
   const float rc = p.rcut;
   const float xi = R[3 * i], yi = R[3 * i + 1], zi = R[3 * i + 2];
   float* __restrict__ out = rho + i * size;
@@ -220,6 +218,21 @@ __global__ __launch_bounds__(256) void fchl19_forward_kernel(
         o[1] = acc_s[h];
       }
     }
+  }
+}
+
+// Atoms of larger molecules: a persistent grid walks all atoms and gives each
+// atom of a molecule above kFchlSmallMol atoms a whole workgroup (the small
+// molecules' atoms are skipped at the cost of one lookup).
+__global__ __launch_bounds__(256) void fchl19_forward_kernel(
+    const float* __restrict__ R, const int32_t* __restrict__ element,
+    const int64_t* __restrict__ mol_ptr, int64_t n_atoms, int64_t n_mols, int32_t E, FchlParams p,
+    int64_t size, float* __restrict__ rho) {
+  for (int64_t i = blockIdx.x; i < n_atoms; i += gridDim.x) {
+    const int64_t m = molecule_of(mol_ptr, n_mols, i);
+    if (mol_ptr[m + 1] - mol_ptr[m] <= kFchlSmallMol) continue;
+    fchl19_forward_atom(i, R, element, mol_ptr, n_mols, E, p, size, rho);
+    __syncthreads();   // the next atom reuses the LDS
   }
 }
 
@@ -865,12 +878,11 @@ hipError_t sorf_launch_fchl19_forward(const float* R, const int32_t* element,
                        R, element, mol_ptr, a0, n_atoms, n_mols, E, p, size, rho);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fchl19_forward_kernel, dim3(unsigned(cnt)), dim3(256), 0, st, R, element,
-                       mol_ptr, a0, n_atoms, n_mols, E, p, size, rho);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  const int64_t grid = n_atoms < 4096 ? n_atoms : 4096;
+  hipLaunchKernelGGL(fchl19_forward_kernel, dim3(unsigned(grid)), dim3(256), 0, st, R, element,
+                     mol_ptr, n_atoms, n_mols, E, p, size, rho);
+  return hipGetLastError();
 }
 
 hipError_t sorf_launch_fchl19_backward(const float* R, const int32_t* element,
