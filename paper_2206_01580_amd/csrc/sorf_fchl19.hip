@@ -502,12 +502,14 @@ __device__ __forceinline__ float fchl_pair_grad(float r, const float* __restrict
 }
 
 // Molecules of at most kFchlSmallAtoms atoms: one workgroup per molecule,
-// its four waves take four centres at a time. A wave keeps the centre's
-// neighbours one per lane; lane s forms the two-body term of its neighbour
-// and, for every other neighbour t in order, the three-body term of the pair
-// (s, t) as it lands on s (each pair is evaluated by both of its lanes, so no
-// lane waits for another), plus the centre's share for t > s. The four
-// centres' results are merged into the molecule's gradient in centre order.
+// its four waves take four centres at a time. A wave gives each of the
+// centre's neighbours H lanes (H = 4, 2, 1 for at most 16, 32, 63
+// neighbours); they form the two-body term of their neighbour s and, for the
+// other neighbours t in order (every H-th each), the three-body term of the
+// pair (s, t) as it lands on s (each pair is evaluated for both of its
+// neighbours, so no lane waits for another), plus the centre's share for
+// t > s. The H parts are combined by fixed shuffles and the four centres'
+// results merged into the molecule's gradient in centre order.
 constexpr int kFchlSmallAtoms = 64;
 
 __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
@@ -564,22 +566,28 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
       __builtin_amdgcn_wave_barrier();
       __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
       float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-      if (lane < n) {
-        const int js = nid[wv][lane];
+      // H lanes per neighbour slot when the neighbours are few: lane (sl, h)
+      // takes the partners u = h, h + H, ... of slot sl
+      const int H = n <= 16 ? 4 : (n <= 32 ? 2 : 1);
+      const int sl = lane / H, h = lane % H;
+      int js = 0;
+      if (sl < n) {
+        js = nid[wv][sl];
         const float ux = ax[js] - ax[ci], uy = ay[js] - ay[ci], uz = az[js] - az[ci];
-        const float rs = sqrtf(ux * ux + uy * uy + uz * uz);
-        const int Xs = ael[js];
-        const float d2 = fchl_pair_grad(rs, gi + Xs * p.n2, p) / rs;
-        sx = ux * d2;
-        sy = uy * d2;
-        sz = uz * d2;
-        cx = -sx;
-        cy = -sy;
-        cz = -sz;
-        for (int u = 0; u < n; ++u) {
-          if (u == lane) continue;
+        if (h == 0) {
+          const float rs = sqrtf(ux * ux + uy * uy + uz * uz);
+          const float d2 = fchl_pair_grad(rs, gi + ael[js] * p.n2, p) / rs;
+          sx = ux * d2;
+          sy = uy * d2;
+          sz = uz * d2;
+          cx = -sx;
+          cy = -sy;
+          cz = -sz;
+        }
+        for (int u = h; u < n; u += H) {
+          if (u == sl) continue;
           const int ju = nid[wv][u];
-          const bool first = lane < u;   // the pair's j is the lower slot
+          const bool first = sl < u;   // the pair's j is the lower slot
           const int ja = first ? js : ju, jb = first ? ju : js;
           const float vax = ax[ja] - ax[ci], vay = ay[ja] - ay[ci], vaz = az[ja] - az[ci];
           const float vbx = ax[jb] - ax[ci], vby = ay[jb] - ay[ci], vbz = az[jb] - az[ci];
@@ -594,19 +602,32 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
           const float ua[3] = {vax / a, vay / a, vaz / a};
           const float ub[3] = {vbx / b, vby / b, vbz / b};
           const float uc[3] = {wx / c, wy / c, wz / c};
-          if (first) {   // this lane is j: fj, and the centre's fi once per pair
+          if (first) {   // this slot is j: fj, and the centre's fi once per pair
             sx += dL[0] * ua[0] - dL[2] * uc[0];
             sy += dL[0] * ua[1] - dL[2] * uc[1];
             sz += dL[0] * ua[2] - dL[2] * uc[2];
             cx += -dL[0] * ua[0] - dL[1] * ub[0];
             cy += -dL[0] * ua[1] - dL[1] * ub[1];
             cz += -dL[0] * ua[2] - dL[1] * ub[2];
-          } else {       // this lane is l
+          } else {       // this slot is l
             sx += dL[1] * ub[0] + dL[2] * uc[0];
             sy += dL[1] * ub[1] + dL[2] * uc[1];
             sz += dL[1] * ub[2] + dL[2] * uc[2];
           }
         }
+      }
+      // the H parts of a slot, combined in a fixed order
+      if (H >= 2) {
+        sx += __shfl_xor(sx, 1);
+        sy += __shfl_xor(sy, 1);
+        sz += __shfl_xor(sz, 1);
+      }
+      if (H >= 4) {
+        sx += __shfl_xor(sx, 2);
+        sy += __shfl_xor(sy, 2);
+        sz += __shfl_xor(sz, 2);
+      }
+      if (sl < n && h == 0) {
         res[wv][0][js] = sx;
         res[wv][1][js] = sy;
         res[wv][2][js] = sz;
