@@ -34,7 +34,7 @@ PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16_hilo": 2500.0,
                     "fp16_hilo": 2500.0, "fp64": 78.6, "fp32_kahan": 157.3}
 # VALU issue ceiling derived from unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
-# = 39.3 T lane-instructions/s (packed FP32, which would double it, is disabled in this build)
+# = 39.3 T lane-instructions/s (packed FP32, which would double it, is disabled by the library's compile flags)
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
 
 
@@ -665,8 +665,8 @@ def cpu_baseline(p, D, n_sample, lam):
 def main():
     args = parse()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py: this build runs on one GPU only (the sharded design is described in "
-              "DESIGN.md); use --gpus 1", file=sys.stderr)
+        print("bench.py: runs on one GPU only (the multi-GPU sharding is not implemented); "
+              "use --gpus 1", file=sys.stderr)
         sys.exit(2)
     import torch
 

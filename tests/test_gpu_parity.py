@@ -409,7 +409,7 @@ def test_solve_reports_non_spd():
 # ------------------------------------------------------------------ end to end
 def test_end_to_end_config1_energies():
     """forward -> Gram (FP64, the paper's DP mode) -> FP64 solve -> predict,
-    against the oracle pipeline; judged on energies (config 1 is rank
+    against the oracle pipeline; checked on energies (config 1 is rank
     deficient: N=200 < D=256, and lambda = 1e-6 is below the FP32 rounding of G)."""
     p = W.config1()
     s = S()
