@@ -122,7 +122,7 @@ def serving_leg(args, dev, log, rate, seconds):
     import torch
 
     from paper_2206_01580_amd import serve, sorf, workloads
-    tr = workloads.config5(rate_hz=rate, duration_s=seconds)
+    tr = workloads.serving_trace(rate_hz=rate, duration_s=seconds)
     J = workloads.device_normal(tr.J_pool_floats, tr.J_seed, 0.1, device=dev)
     pool = serve.RequestPool(tr.x, tr.element, tr.sizes, J, tr.J_off, device=dev)
     model = sorf.Model.from_problem(tr.model)
@@ -174,7 +174,7 @@ def force_training_leg(args, dev, log):
     import torch
 
     from paper_2206_01580_amd import sorf, workloads
-    p = workloads.config3(n_conf=args.force_confs, with_J=False)
+    p = workloads.conformations(n_conf=args.force_confs, with_J=False)
     D, A, M = p.n_features, p.n_atoms, p.n_mols
     model, batch = sorf.Model.from_problem(p), sorf.Batch.from_problem(p)
     n_j = A * p.d * 3 * int(p.mol_sizes()[0])
@@ -256,7 +256,7 @@ def force_training_leg(args, dev, log):
     }
     if not args.no_cpu_baseline:
         from oracle import sorf_oracle as O
-        q = workloads.config3(n_conf=4)
+        q = workloads.conformations(n_conf=4)
         t1 = time.perf_counter()
         O.derivative_features(q.x, q.element, q.mol_ptr, q.signs, q.bias, q.sigma, q.J, q.J_ptr)
         t_o = time.perf_counter() - t1
@@ -567,7 +567,7 @@ def precision_study(args, dev, log):
     import torch
 
     from paper_2206_01580_amd import sorf, workloads
-    p = workloads.config4(n_mols=args.precision_mols)
+    p = workloads.precision_batch(n_mols=args.precision_mols)
     model, batch = sorf.Model.from_problem(p), sorf.Batch.from_problem(p)
     D, M = p.n_features, p.n_mols
     y = torch.from_numpy(p.y).to(dev)
@@ -687,7 +687,7 @@ def main():
         del src, dst
         torch.cuda.empty_cache()
     t_gen = time.perf_counter()
-    p = workloads.config2(n_mols=args.n_mols)
+    p = workloads.qm9_batch(n_mols=args.n_mols)
     gen_s = time.perf_counter() - t_gen
     D, A, M = p.n_features, p.n_atoms, p.n_mols
     model, batch = sorf.Model.from_problem(p), sorf.Batch.from_problem(p)

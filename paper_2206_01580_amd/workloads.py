@@ -18,7 +18,7 @@ Array conventions (shared by both sides):
 * ``signs``    int8    [n_elements, n_transforms, n_stacks, d]  entries +-1;
                                        transform index t = 0 is applied first
 * ``bias``     float32 [n_elements, n_stacks * d]  phases in [0, 2*pi)
-* ``y``        float32 [n_mols]        regression targets (energy configs)
+* ``y``        float32 [n_mols]        regression targets (energy workloads)
 * ``alpha``    float32 [n_stacks * d]  model weights (differentiation/serving)
 * ``J``        float32 concatenated per-molecule blocks [N_m, d, 3 N_m]
 * ``J_ptr``    int64   [n_mols + 1]    float offsets of each block in ``J``
@@ -152,7 +152,7 @@ def qm9_like_sizes(rng, n_mols):
     return 3 + rng.binomial(26, 15.0 / 26.0, size=n_mols)
 
 
-def config1(seed_offset: int = 0) -> Problem:
+def small_energy_batch(seed_offset: int = 0) -> Problem:
     """Small energy model: 200 molecules of 3..20 atoms, d=64, 4 stacks."""
     seed = SEED_BASE + 1 + seed_offset
     rng = np.random.Generator(np.random.PCG64(seed))
@@ -166,7 +166,7 @@ def config1(seed_offset: int = 0) -> Problem:
     signs = draw_signs(rng, len(names), T, S, d)
     bias = draw_bias(rng, len(names), S * d)
     y = _linear_targets(rng, x, ptr)
-    return Problem("config1-small-energy", d, S, T, 2.0, names, x, element, ptr,
+    return Problem("small-energy-200", d, S, T, 2.0, names, x, element, ptr,
                    signs, bias, y=y, lam=1e-6, seed=seed)
 
 
@@ -189,19 +189,19 @@ def qm9_like(n_mols: int, n_stacks: int, seed: int, name: str, sigma=4.0, lam=0.
                    y=y, lam=lam, seed=seed)
 
 
-def config2(n_mols: int = 20000, seed_offset: int = 0) -> Problem:
+def qm9_batch(n_mols: int = 20000, seed_offset: int = 0) -> Problem:
     """QM9-like forward + Gram: 20k molecules, d=128, 64 stacks (D=8192), sigma=4."""
     return qm9_like(n_mols, 64, SEED_BASE + 2 + seed_offset,
-                    "config2-qm9like-fwd-gram", sigma=4.0, lam=1e-6)
+                    "qm9like-20000", sigma=4.0, lam=1e-6)
 
 
-def config4(n_mols: int = 100000, seed_offset: int = 0) -> Problem:
+def precision_batch(n_mols: int = 100000, seed_offset: int = 0) -> Problem:
     """Precision study: 100k QM9-like molecules, d=128, 128 stacks (D=16384)."""
     return qm9_like(n_mols, 128, SEED_BASE + 4 + seed_offset,
-                    "config4-qm9like-precision", sigma=4.0, lam=1e-8)
+                    "qm9like-precision-100000", sigma=4.0, lam=1e-8)
 
 
-def config3(n_conf: int = 2000, seed_offset: int = 0, with_J: bool = True) -> Problem:
+def conformations(n_conf: int = 2000, seed_offset: int = 0, with_J: bool = True) -> Problem:
     """Differentiation: one 21-atom molecule (9 C, 8 H, 4 O) in ``n_conf``
     conformations; x = x0 + N(0, 0.05); Jacobians dx/dr of shape d x 63 per
     atom drawn N(0, 0.1); D = 8192, sigma = 8; alpha ~ N(0, 1)."""
@@ -226,7 +226,7 @@ def config3(n_conf: int = 2000, seed_offset: int = 0, with_J: bool = True) -> Pr
     signs = draw_signs(rng, len(names), T, S, d)
     bias = draw_bias(rng, len(names), S * d)
     alpha = rng.standard_normal(S * d).astype(np.float32)
-    return Problem("config3-differentiation", d, S, T, 8.0, names, x, element, ptr,
+    return Problem("conformations-21-atoms", d, S, T, 8.0, names, x, element, ptr,
                    signs, bias, alpha=alpha, J=J, J_ptr=J_ptr, seed=seed)
 
 
@@ -369,7 +369,7 @@ def device_normal(n: int, seed: int, std: float, device="cuda"):
     return torch.randn(n, generator=g, device=device, dtype=torch.float32).mul_(std)
 
 
-def config5(rate_hz: float = 2000.0, duration_s: float = 20.0, seed_offset: int = 0,
+def serving_trace(rate_hz: float = 2000.0, duration_s: float = 20.0, seed_offset: int = 0,
             max_requests: Optional[int] = None, j_pool_floats: int = 1 << 27,
             d: int = 128, n_stacks: int = 128) -> ServingTrace:
     """Serving: Poisson arrivals at ``rate_hz``, sizes round(exp(U[ln 5, ln 300])),
@@ -396,7 +396,7 @@ def config5(rate_hz: float = 2000.0, duration_s: float = 20.0, seed_offset: int 
     bias = draw_bias(rng, len(names), S * d)
     alpha = rng.standard_normal(S * d).astype(np.float32)
     ptr = _ptr_from_sizes(sizes)
-    model = Problem("config5-serving", d, S, T, 4.0, names, x, element, ptr, signs, bias,
+    model = Problem("serving-d16384", d, S, T, 4.0, names, x, element, ptr, signs, bias,
                     alpha=alpha, seed=seed)
     return ServingTrace(model, t, sizes, x, element, J_off, pool,
                         int(np.random.SeedSequence([seed, 1]).generate_state(1)[0]))
@@ -431,4 +431,5 @@ def random_problem(seed: int, d: int, n_stacks: int, n_transforms: int = 3,
                    signs, bias, y=y, alpha=alpha, J=J, J_ptr=J_ptr, lam=1e-6, seed=seed)
 
 
-CONFIGS = {1: config1, 2: config2, 3: config3, 4: config4}
+WORKLOADS = {"small-energy": small_energy_batch, "qm9-like": qm9_batch,
+             "conformations": conformations, "precision": precision_batch}

@@ -107,7 +107,7 @@ def test_fchl19_too_many_neighbours_gives_nan_rows():
 def test_fchl19_qm9_like_full_size_sampled():
     """Every atom of 20,000 QM9-like molecules (the benchmark's batch), sampled
     molecules against the oracle."""
-    p = W.config2()
+    p = W.qm9_batch()
     sizes = p.mol_sizes()
     R = W.host_geometries(sizes, seed=7)
     s = S()

@@ -156,17 +156,17 @@ def test_dz_alpha_equals_predicted_forces():
         assert np.abs(Fd[r] - Fp[r]).max() <= 1e-5 * scale[r].max()
 
 
-def test_dz_config3_sampled_molecules():
+def test_dz_conformations_sampled_molecules():
     """The full differentiation workload (2,000 conformations of a 21-atom
     molecule, D = 8192: dZ is 126,000 x 8192) in the launch configuration the
     benchmark times; sampled conformations against the oracle."""
-    p = W.config3()
+    p = W.conformations()
     dZ = gpu_dz(p)
     mols = [0, 1, 997, 1998, 1999]
     rows = torch.from_numpy(rows_of(p, mols)).cuda()
     got = dZ.index_select(0, rows).cpu().numpy()
     rel = check_dz(got, p, mols)
-    print(f"config3 dZ: max row error / row scale {rel:.2e}")
+    print(f"conformations dZ: max row error / row scale {rel:.2e}")
     # dZ alpha against the forces of the predict path on every conformation
     model, batch, J, J_ptr = device_inputs(p)
     alpha = torch.from_numpy(p.alpha).cuda()

@@ -37,7 +37,7 @@ def S():
 def qm9():
     if not torch.cuda.is_available():
         pytest.fail("GPU tests need a GPU")
-    p = W.config2()
+    p = W.qm9_batch()
     s = S()
     model, batch = s.Model.from_problem(p), s.Batch.from_problem(p)
     Z = s.forward(model, batch)
@@ -118,7 +118,7 @@ def test_qm9_gram_sampled(qm9, mode):
 def test_qm9_solve_residual():
     """Full-size ridge solve (D = 8192, lambda = 1e-6, 3 refinements) on the
     bf16 hi+lo Gram: the FP64 residual of the system it was given is small."""
-    p = W.config2()
+    p = W.qm9_batch()
     s = S()
     model, batch = s.Model.from_problem(p), s.Batch.from_problem(p)
     Z = s.forward(model, batch)
@@ -139,7 +139,7 @@ def test_qm9_solve_residual():
 
 
 def test_differentiation_set_sampled_conformations():
-    p = W.config3()
+    p = W.conformations()
     s = S()
     model, batch = s.Model.from_problem(p), s.Batch.from_problem(p)
     alpha = torch.from_numpy(p.alpha).cuda()

@@ -82,10 +82,10 @@ def oracle_forward(p, mols=None):
 
 
 # ------------------------------------------------------------------ forward
-def test_forward_config1():
-    p = W.config1()
+def test_forward_small_energy_batch():
+    p = W.small_energy_batch()
     rel = check_rows(gpu_forward(p), oracle_forward(p))
-    print(f"config1 forward max normwise row error {rel:.2e}")
+    print(f"small energy batch: forward max normwise row error {rel:.2e}")
 
 
 SHAPES = [  # (d, n_stacks, T, n_elements, n_mols, min_atoms, max_atoms)
@@ -144,15 +144,15 @@ def test_backward_random_shapes(shape):
     check_rows(g.cpu().numpy(), go)
 
 
-def test_backward_config3_subset():
-    p = W.config3(n_conf=24, with_J=False)
+def test_backward_conformations_subset():
+    p = W.conformations(n_conf=24, with_J=False)
     model, batch = dev_problem(p)
     alpha = torch.from_numpy(p.alpha).cuda()
     g = S().backward(model, batch, alpha)
     torch.cuda.synchronize()
     go = O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.alpha)
     rel = check_rows(g.cpu().numpy(), go)
-    print(f"config3 grad max normwise atom error {rel:.2e}")
+    print(f"conformations: grad max normwise atom error {rel:.2e}")
 
 
 # ------------------------------------------------------------------ predict
@@ -188,8 +188,8 @@ def test_predict_energies_and_forces(shape):
             assert np.abs(Fg[a0:a1] - Fo[a0:a1]).max() <= 1e-5 * np.abs(Fo[a0:a1]).max()
 
 
-def test_predict_config3_subset_with_jacobians():
-    p = W.config3(n_conf=6)
+def test_predict_conformations_subset_with_jacobians():
+    p = W.conformations(n_conf=6)
     model, batch = dev_problem(p)
     alpha = torch.from_numpy(p.alpha).cuda()
     E, F = S().predict(model, batch, alpha, torch.from_numpy(p.J).cuda(), torch.from_numpy(p.J_ptr).cuda())
@@ -407,11 +407,11 @@ def test_solve_reports_non_spd():
 
 
 # ------------------------------------------------------------------ end to end
-def test_end_to_end_config1_energies():
+def test_end_to_end_small_energy_batch():
     """forward -> Gram (FP64, the paper's DP mode) -> FP64 solve -> predict,
-    against the oracle pipeline; checked on energies (config 1 is rank
+    against the oracle pipeline; checked on energies (the 200-molecule batch is rank
     deficient: N=200 < D=256, and lambda = 1e-6 is below the FP32 rounding of G)."""
-    p = W.config1()
+    p = W.small_energy_batch()
     s = S()
     model, batch = dev_problem(p)
     D = p.n_features
@@ -430,7 +430,7 @@ def test_end_to_end_config1_energies():
     Eo = Zo @ ao
     Eg = E.cpu().numpy().astype(np.float64)
     rel = np.abs(Eg - Eo).max() / np.abs(Eo).max()
-    print(f"config1 end-to-end energy max rel error {rel:.2e}; fit rmse {np.sqrt(np.mean((Eo - p.y) ** 2)):.3e}")
+    print(f"small energy batch: end-to-end energy max rel error {rel:.2e}; fit rmse {np.sqrt(np.mean((Eo - p.y) ** 2)):.3e}")
     assert rel <= 1e-3
 
 

@@ -103,7 +103,7 @@ def test_precision_workload_factorises_in_every_16bit_mode():
     here can only come from the FP32 accumulation drifting over a long row
     range (a single matrix-core accumulator over all 100,000 rows did)."""
     from paper_2206_01580_amd import sorf
-    p = W.config4(n_mols=100000)
+    p = W.precision_batch(n_mols=100000)
     model, batch = sorf.Model.from_problem(p), sorf.Batch.from_problem(p)
     D = p.n_features
     Z = sorf.forward(model, batch)

@@ -115,7 +115,7 @@ def test_project_deterministic():
 def test_projected_features_match_the_oracle():
     """rho -> x (sorf_project) -> Z (sorf_forward) against the oracle's
     project -> molecule_features on a small QM9-like batch."""
-    p = W.config2(n_mols=40)
+    p = W.qm9_batch(n_mols=40)
     d_rep = W.FCHL19_EF_SIZE
     rho = W.host_representations(p.element, p.n_elements, d_rep, seed=10)
     U = W.random_projection(11, p.n_elements, d_rep, p.d)
@@ -136,7 +136,7 @@ def test_projected_features_match_the_oracle():
 def test_project_qm9_like_full_size_sampled_rows():
     """The benchmark's projection: every atom of the 20,000-molecule QM9-like
     batch (360,149 atoms, d_rep = 720 -> d = 128), sampled rows against the oracle."""
-    p = W.config2()
+    p = W.qm9_batch()
     d_rep = W.FCHL19_EF_SIZE
     el = torch.from_numpy(p.element).cuda()
     rho = W.device_representations(p.element, p.n_elements, d_rep, seed=12)
@@ -206,7 +206,7 @@ def test_projection_fit_recovers_a_planted_subspace():
 def test_fitted_projection_feeds_the_projection():
     """Fit per element on a sample of a QM9-like batch, project every atom, and
     compare with the oracle's fit + projection."""
-    p = W.config2(n_mols=2000)      # at least d atoms of every element, fluorine included
+    p = W.qm9_batch(n_mols=2000)      # at least d atoms of every element, fluorine included
     d_rep = W.FCHL19_EF_SIZE
     assert np.bincount(p.element).min() >= p.d
     rho = W.host_representations(p.element, p.n_elements, d_rep, seed=22)

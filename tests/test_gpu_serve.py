@@ -24,7 +24,7 @@ def trace():
         pytest.fail("GPU tests need a GPU")
     from paper_2206_01580_amd import _lib
     _lib.load()
-    tr = W.config5(rate_hz=20000.0, duration_s=1.0, max_requests=48, j_pool_floats=1 << 22,
+    tr = W.serving_trace(rate_hz=20000.0, duration_s=1.0, max_requests=48, j_pool_floats=1 << 22,
                    d=32, n_stacks=8)
     Jh = tr.host_J_pool()
     return tr, Jh, torch.from_numpy(Jh).cuda()

@@ -25,7 +25,7 @@ def _gpu():
 
 @pytest.fixture(scope="module")
 def qm9():
-    return W.config2()
+    return W.qm9_batch()
 
 
 @pytest.mark.parametrize("T", [1, 2])
