@@ -46,10 +46,11 @@ __device__ __forceinline__ float fchl_fcut(float r, float rc) {
 // element pair (a <= b) -> position in the lexicographic list of pairs
 __device__ __forceinline__ int fchl_pair(int a, int b, int E) { return a * E - a * (a - 1) / 2 + (b - a); }
 
+// Atom i of molecule m (atoms a0 .. a1 - 1).
 __device__ __forceinline__ void fchl19_forward_atom(
-    int64_t i, const float* __restrict__ R, const int32_t* __restrict__ element,
-    const int64_t* __restrict__ mol_ptr, int64_t n_mols, int32_t E, const FchlParams& p,
-    int64_t size, float* __restrict__ rho) {
+    int64_t i, int64_t a0, int64_t a1, const float* __restrict__ R,
+    const int32_t* __restrict__ element, int32_t E, const FchlParams& p, int64_t size,
+    float* __restrict__ rho) {
   __shared__ float nx[kFchlMaxNb], ny[kFchlMaxNb], nz[kFchlMaxNb], nr[kFchlMaxNb];
   __shared__ float c2[kFchlMaxNb], mu2[kFchlMaxNb], inv2s2[kFchlMaxNb];
   __shared__ int32_t grp[kFchlMaxElements + 1];     // neighbour offsets per element
@@ -58,8 +59,6 @@ __device__ __forceinline__ void fchl19_forward_atom(
   __shared__ float pw_c[kFchlPairChunk], pw_s[kFchlPairChunk], pmid[kFchlPairChunk];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t m = molecule_of(mol_ptr, n_mols, i);
-  const int64_t a0 = mol_ptr[m], a1 = mol_ptr[m + 1];
   const float rc = p.rcut;
   const float xi = R[3 * i], yi = R[3 * i + 1], zi = R[3 * i + 2];
   float* __restrict__ out = rho + i * size;
@@ -221,18 +220,51 @@ __device__ __forceinline__ void fchl19_forward_atom(
   }
 }
 
-// Atoms of larger molecules: a persistent grid walks all atoms and gives each
-// atom of a molecule above kFchlSmallMol atoms a whole workgroup (the small
-// molecules' atoms are skipped at the cost of one lookup).
+// Atoms of larger molecules: a persistent grid in which every workgroup reads
+// the molecule sizes 256 at a time (coalesced), collects the molecules above
+// kFchlSmallMol atoms with ballots, and gives a whole workgroup to atom j of
+// such a molecule m when (m + j) mod grid is its own index, so that the atoms
+// of one large molecule spread over consecutive workgroups.
 __global__ __launch_bounds__(256) void fchl19_forward_kernel(
     const float* __restrict__ R, const int32_t* __restrict__ element,
-    const int64_t* __restrict__ mol_ptr, int64_t n_atoms, int64_t n_mols, int32_t E, FchlParams p,
+    const int64_t* __restrict__ mol_ptr, int64_t n_mols, int32_t E, FchlParams p,
     int64_t size, float* __restrict__ rho) {
-  for (int64_t i = blockIdx.x; i < n_atoms; i += gridDim.x) {
-    const int64_t m = molecule_of(mol_ptr, n_mols, i);
-    if (mol_ptr[m + 1] - mol_ptr[m] <= kFchlSmallMol) continue;
-    fchl19_forward_atom(i, R, element, mol_ptr, n_mols, E, p, size, rho);
-    __syncthreads();   // the next atom reuses the LDS
+  __shared__ int32_t big[256];
+  __shared__ int32_t wbig[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t G = gridDim.x, b = blockIdx.x;
+  int64_t lo = 0, hi = 0;
+  if (tid < n_mols) {
+    lo = mol_ptr[tid];
+    hi = mol_ptr[tid + 1];
+  }
+  for (int64_t m0 = 0; m0 < n_mols; m0 += 256) {
+    const int64_t m = m0 + tid;
+    const bool large = m < n_mols && hi - lo > kFchlSmallMol;
+    // next group's sizes in flight while this group is processed
+    if (m + 256 < n_mols) {
+      lo = mol_ptr[m + 256];
+      hi = mol_ptr[m + 257];
+    }
+    const uint64_t mask = __ballot(large);
+    if (lane == 0) wbig[wv] = __popcll(mask);
+    __syncthreads();
+    int off = 0, nbig = 0;
+    for (int w = 0; w < 4; ++w) {
+      off += w < wv ? wbig[w] : 0;
+      nbig += wbig[w];
+    }
+    if (large) big[off + __popcll(mask & ((uint64_t(1) << lane) - 1))] = tid;
+    __syncthreads();
+    for (int t = 0; t < nbig; ++t) {
+      const int64_t mm = m0 + big[t];
+      const int64_t a0 = mol_ptr[mm], a1 = mol_ptr[mm + 1];
+      for (int64_t j = ((b - mm) % G + G) % G; j < a1 - a0; j += G) {
+        fchl19_forward_atom(a0 + j, a0, a1, R, element, E, p, size, rho);
+        __syncthreads();   // the next atom reuses the LDS
+      }
+    }
+    __syncthreads();   // big[] and wbig[] are rewritten by the next group
   }
 }
 
@@ -240,11 +272,13 @@ __global__ __launch_bounds__(256) void fchl19_forward_kernel(
 // atoms per workgroup, no workgroup barriers. The wave's lanes take the
 // molecule's atoms, gather the neighbours by element with ballots into the
 // wave's LDS, form the two-body bins (lanes over bins), then the three-body
-// pair weights in chunks (lanes over pairs) and the three-body bins (lanes
-// over bins, each bin summing its pairs of the chunk in order and adding the
-// chunk's sum to its entry of rho, chunk by chunk). Every entry is summed in
-// the same fixed order as in the workgroup-per-atom kernel's numbering.
-constexpr int kFchlWavePairs = 512;
+// pair weights in chunks (lanes over pairs) and the three-body bins: lane
+// groups of one lane per radial bin split each chunk's pairs into equal
+// parts, so that no lane walks a whole large element pair (H-C, say) while
+// the others idle. Every entry is summed in a fixed order (pairs in the
+// workgroup-per-atom kernel's numbering, parts in group order, chunks in
+// order), so results are deterministic.
+constexpr int kFchlWavePairs = 384;   // covers the 378 pairs of a centre with 28 neighbours
 
 __device__ __forceinline__ void wave_sync_lds() {
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
@@ -260,8 +294,9 @@ __global__ __launch_bounds__(256) void fchl19_forward_small_kernel(
   __shared__ float nr[4][kFchlSmallMol], c2[4][kFchlSmallMol], mu2[4][kFchlSmallMol],
       inv2s2[4][kFchlSmallMol];
   __shared__ int32_t grp[4][kFchlMaxElements + 1];
-  __shared__ int64_t seg[4][kFchlMaxElements * (kFchlMaxElements + 1) / 2 + 1];
+  __shared__ int32_t seg[4][kFchlMaxElements * (kFchlMaxElements + 1) / 2 + 1];
   __shared__ float pw_c[4][kFchlWavePairs], pw_s[4][kFchlWavePairs], pmid[4][kFchlWavePairs];
+  __shared__ float tail[4][64][2];
 
   const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
   const int64_t i = atom0 + int64_t(blockIdx.x) * 4 + wv;
@@ -321,45 +356,53 @@ __global__ __launch_bounds__(256) void fchl19_forward_small_kernel(
     out[t] = acc / Rk;
   }
 
-  // three-body
+  // three-body: pairs numbered by element pair, then by position (the
+  // workgroup-per-atom kernel's numbering)
   const int NP = E * (E + 1) / 2;
   if (lane == 0) {
-    int64_t o = 0;
+    int32_t o = 0;
     for (int X = 0; X < E; ++X)
       for (int Y = X; Y < E; ++Y) {
         seg[wv][fchl_pair(X, Y, E)] = o;
-        const int64_t cx = grp[wv][X + 1] - grp[wv][X], cy = grp[wv][Y + 1] - grp[wv][Y];
+        const int32_t cx = grp[wv][X + 1] - grp[wv][X], cy = grp[wv][Y + 1] - grp[wv][Y];
         o += X == Y ? cx * (cx - 1) / 2 : cx * cy;
       }
     seg[wv][NP] = o;
   }
   wave_sync_lds();
-  const int64_t n_pairs = seg[wv][NP];
+  const int32_t n_pairs = seg[wv][NP];
   const float angw = 2.0f * expf(-0.5f * p.zeta * p.zeta) * sqrtf(p.eta3 / 3.14159265358979f);
-  const int nbins = NP * p.n3;
-  for (int64_t q0 = 0; q0 < n_pairs || q0 == 0; q0 += kFchlWavePairs) {
-    const int64_t q1 = q0 + kFchlWavePairs < n_pairs ? q0 + kFchlWavePairs : n_pairs;
-    for (int64_t q = q0 + lane; q < q1; q += 64) {
-      int P = 0;
+  // Bins: G groups of n3 lanes, one lane per radial bin; group g walks the
+  // g-th of G equal parts of the chunk's pairs in order. An element pair
+  // whose pairs fall in several parts is finished by the group where it ends,
+  // which adds the partial sums of the earlier groups in group order. With
+  // more than 64 radial bins one group's lanes loop over them.
+  const int G = p.n3 <= 64 ? 64 / p.n3 : 1;
+  const int g = p.n3 <= 64 ? lane / p.n3 : 0;
+  const int kl = p.n3 <= 64 ? lane % p.n3 : lane;
+  float* __restrict__ out3 = out + int64_t(E) * p.n2;
+  int P = 0, X = 0;   // decode state: non-decreasing in q, kept across iterations
+  for (int32_t q0 = 0; q0 < n_pairs || q0 == 0; q0 += kFchlWavePairs) {
+    const int32_t q1 = q0 + kFchlWavePairs < n_pairs ? q0 + kFchlWavePairs : n_pairs;
+    for (int32_t q = q0 + lane; q < q1; q += 64) {
       while (q >= seg[wv][P + 1]) ++P;
-      int X = 0;
       while (fchl_pair(X, X, E) + (E - X) <= P) ++X;
       const int Y = X + (P - fchl_pair(X, X, E));
-      const int64_t loc = q - seg[wv][P];
+      const int32_t loc = q - seg[wv][P];
       int a, b;
       if (X != Y) {
         const int cy = grp[wv][Y + 1] - grp[wv][Y];
-        a = grp[wv][X] + int(loc / cy);
-        b = grp[wv][Y] + int(loc % cy);
+        a = grp[wv][X] + loc / cy;
+        b = grp[wv][Y] + loc % cy;
       } else {
         const int cx = grp[wv][X + 1] - grp[wv][X];
         const double c2x = 2.0 * cx - 1.0;
         int u = int((c2x - sqrt(c2x * c2x - 8.0 * double(loc))) * 0.5);
         if (u < 0) u = 0;
-        while (u > 0 && int64_t(u) * (2 * cx - u - 1) / 2 > loc) --u;
-        while (int64_t(u + 1) * (2 * cx - u - 2) / 2 <= loc) ++u;
+        while (u > 0 && u * (2 * cx - u - 1) / 2 > loc) --u;
+        while ((u + 1) * (2 * cx - u - 2) / 2 <= loc) ++u;
         a = grp[wv][X] + u;
-        b = grp[wv][X] + u + 1 + int(loc - int64_t(u) * (2 * cx - u - 1) / 2);
+        b = grp[wv][X] + u + 1 + (loc - u * (2 * cx - u - 1) / 2);
       }
       const float rij = nr[wv][a], rik = nr[wv][b];
       const float jx = nx[wv][b] - nx[wv][a], jy = ny[wv][b] - ny[wv][a], jz = nz[wv][b] - nz[wv][a];
@@ -370,35 +413,85 @@ __global__ __launch_bounds__(256) void fchl19_forward_small_kernel(
       const float sin_i = sqrtf(fmaxf(0.0f, 1.0f - cos_i * cos_i));
       const float xi3 = p.c3 * (1.0f + 3.0f * cos_i * cos_j * cos_k) / powf(rij * rjk * rik, p.N3);
       const float w = xi3 * fchl_fcut(rij, rc) * fchl_fcut(rjk, rc) * fchl_fcut(rik, rc) * angw;
-      const int sl = int(q - q0);
+      const int sl = q - q0;
       pw_c[wv][sl] = w * cos_i;
       pw_s[wv][sl] = w * sin_i;
       pmid[wv][sl] = 0.5f * (rij + rik);
     }
+    // element pairs without pairs in the first chunk: their bins start at 0
+    if (q0 == 0)
+      for (int Q = 0; Q < NP; ++Q) {
+        const int32_t s0 = seg[wv][Q], s1 = seg[wv][Q + 1] < q1 ? seg[wv][Q + 1] : q1;
+        if (s1 <= s0)
+          for (int k = lane; k < p.n3; k += 64) {
+            out3[2 * (int64_t(Q) * p.n3 + k)] = 0.0f;
+            out3[2 * (int64_t(Q) * p.n3 + k) + 1] = 0.0f;
+          }
+      }
     wave_sync_lds();
-    for (int t = lane; t < nbins; t += 64) {
-      const int P = t / p.n3, k = t % p.n3;
+    const int32_t L = q1 - q0;
+    int pend = -1;                      // element pair to finish after the tails are stored
+    float pc = 0.f, ps = 0.f;
+    for (int k = kl; k < p.n3 && g < G; k += 64) {
       const float Rk = rc * float(k) / float(p.n3 - 1);
-      const int64_t lo = seg[wv][P] > q0 ? seg[wv][P] : q0;
-      const int64_t hi = seg[wv][P + 1] < q1 ? seg[wv][P + 1] : q1;
+      const int32_t lo = q0 + int32_t(int64_t(L) * g / G), hi = q0 + int32_t(int64_t(L) * (g + 1) / G);
+      int Q = 0;
+      while (Q < NP && seg[wv][Q + 1] <= lo) ++Q;
+      bool started = Q < NP && (seg[wv][Q] > q0 ? seg[wv][Q] : q0) >= lo;
+      int32_t segend = Q < NP && seg[wv][Q + 1] < q1 ? seg[wv][Q + 1] : q1;
       float c = 0.f, sn = 0.f;
-      for (int64_t q = lo; q < hi; ++q) {
-        const int sl = int(q - q0);
+      for (int32_t q = lo; q < hi; ++q) {
+        const int sl = q - q0;
         const float d = pmid[wv][sl] - Rk;
         const float gk = expf(-p.eta3 * d * d);
         c += pw_c[wv][sl] * gk;
         sn += pw_s[wv][sl] * gk;
+        if (q + 1 == segend) {          // element pair Q ends in this part
+          if (started) {
+            float* o = out3 + 2 * (int64_t(Q) * p.n3 + k);
+            if (q0 == 0) {
+              o[0] = c;
+              o[1] = sn;
+            } else {
+              o[0] += c;
+              o[1] += sn;
+            }
+          } else {
+            pend = Q;
+            pc = c;
+            ps = sn;
+          }
+          c = 0.f;
+          sn = 0.f;
+          ++Q;
+          while (Q < NP && seg[wv][Q + 1] <= q + 1) ++Q;
+          started = true;
+          segend = Q < NP && seg[wv][Q + 1] < q1 ? seg[wv][Q + 1] : q1;
+        }
       }
-      float* o = out + int64_t(E) * p.n2 + 2 * int64_t(t);
+      tail[wv][lane][0] = c;            // open partial at the end of the part (0 if none)
+      tail[wv][lane][1] = sn;
+    }
+    wave_sync_lds();
+    if (pend >= 0) {
+      const int32_t st = seg[wv][pend] > q0 ? seg[wv][pend] : q0;
+      int gs = 0;
+      while (q0 + int32_t(int64_t(L) * (gs + 1) / G) <= st) ++gs;
+      float sc = 0.f, ss = 0.f;
+      for (int gg = gs; gg < g; ++gg) {
+        sc += tail[wv][gg * p.n3 + kl][0];
+        ss += tail[wv][gg * p.n3 + kl][1];
+      }
+      float* o = out3 + 2 * (int64_t(pend) * p.n3 + kl);
       if (q0 == 0) {
-        o[0] = c;
-        o[1] = sn;
+        o[0] = sc + pc;
+        o[1] = ss + ps;
       } else {
-        o[0] += c;
-        o[1] += sn;
+        o[0] += sc + pc;
+        o[1] += ss + ps;
       }
     }
-    wave_sync_lds();   // the chunk's weights are no longer read
+    wave_sync_lds();   // weights and tails are reused, and the next chunk adds to these entries
     if (n_pairs == 0) break;
   }
 }
@@ -900,9 +993,12 @@ hipError_t sorf_launch_fchl19_forward(const float* R, const int32_t* element,
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  const int64_t grid = n_atoms < 4096 ? n_atoms : 4096;
+  if (n_mols == 0) return hipSuccess;
+  // three workgroups of this kernel fit a compute unit (LDS), 256 units: the
+  // whole grid is resident, so the size scan runs once
+  const int64_t grid = n_atoms < 768 ? n_atoms : 768;
   hipLaunchKernelGGL(fchl19_forward_kernel, dim3(unsigned(grid)), dim3(256), 0, st, R, element,
-                     mol_ptr, n_atoms, n_mols, E, p, size, rho);
+                     mol_ptr, n_mols, E, p, size, rho);
   return hipGetLastError();
 }
 

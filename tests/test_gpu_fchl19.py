@@ -63,6 +63,15 @@ CASES = {
     "one-element": ([12, 7], 1, PRM, 1.0),
     "eight-elements-two-rounds": ([26, 19], 8, PRM, 1.0),  # 36 pairs x 20 bins > 512
     "large-molecule-chunks": ([120], 5, PRM, 1.0),          # > 2048 pairs per atom
+    # wave-per-atom kernel: centres with 38..59 neighbours (up to 1711 pairs,
+    # five chunks of pair weights)
+    "compact-small-chunks": ([60, 45], 5, PRM, 0.8),
+    # lane groups for the radial bins: 2 groups of 30, one of 64, one lane
+    # looping over 70 bins, 32 groups of 2
+    "radial-bins-30": ([20, 13], 3, dict(PRM, n3=30), 1.0),
+    "radial-bins-64": ([16, 11], 2, dict(PRM, n3=64), 1.0),
+    "radial-bins-70": ([18, 9], 2, dict(PRM, n3=70), 1.0),
+    "radial-bins-2": ([15, 6], 2, dict(PRM, n3=2), 1.0),
 }
 
 
