@@ -595,16 +595,22 @@ __device__ __forceinline__ float fchl_pair_grad(float r, const float* __restrict
 }
 
 // Molecules of at most kFchlSmallAtoms atoms: one workgroup per molecule,
-// its four waves take four centres at a time. A wave gives each of the
-// centre's neighbours H lanes (H = 4, 2, 1 for at most 16, 32, 63
-// neighbours); they form the two-body term of their neighbour s and, for the
-// other neighbours t in order (every H-th each), the three-body term of the
-// pair (s, t) as it lands on s (each pair is evaluated for both of its
-// neighbours, so no lane waits for another), plus the centre's share for
-// t > s. The H parts are combined by fixed shuffles and the four centres'
-// results merged into the molecule's gradient in centre order.
+// its four waves take four centres at a time. For a centre with n
+// neighbours, every unordered pair is evaluated once: lanes take the pairs
+// (in chunks of kFchlBwdPairs) and store dL/da, dL/db, dL/dc in the wave's
+// LDS. Then lane s (one per neighbour) walks its partners t in order and
+// sums T_s (dL/da where s is the pair's j, dL/db where it is l, plus its
+// two-body term) and V_s = -sum dL/dc (x_t - x_s) / r_st. Neighbour s gets
+// T_s u_s + V_s, the centre -sum_s T_s u_s (u_s the unit vector from the
+// centre to s, summed by fixed shuffles), and the four centres' results are
+// merged into the molecule's gradient in centre order.
+// STAGED: the centre's upstream gradient row (at most kFchlStage entries) is
+// copied into the wave's LDS first, so that the radial-bin loops read LDS.
 constexpr int kFchlSmallAtoms = 64;
+constexpr int kFchlStage = 1024;
+constexpr int kFchlBwdPairs = 256;
 
+template <bool STAGED>
 __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
     const float* __restrict__ R, const int32_t* __restrict__ element,
     const int64_t* __restrict__ mol_ptr, int64_t m0, int64_t n_mols, int32_t E, FchlParams p,
@@ -614,6 +620,8 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
   __shared__ float gsum[3][kFchlSmallAtoms];
   __shared__ float res[4][3][kFchlSmallAtoms];
   __shared__ int32_t nid[4][kFchlSmallAtoms];
+  __shared__ float dls[4][3][kFchlBwdPairs];
+  __shared__ float gst[4][STAGED ? kFchlStage : 1];
 
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int64_t m = m0 + blockIdx.x;
@@ -637,16 +645,17 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
     res[wv][0][lane] = res[wv][1][lane] = res[wv][2][lane] = 0.0f;
     if (ci < N) {   // wave-uniform
       const float* __restrict__ gi = g + (a0 + ci) * size;
+      if (STAGED) {
+        for (int64_t t = lane; t < size; t += 64) gst[wv][t] = gi[t];
+        gi = &gst[wv][0];   // made visible by the wave barrier below
+      }
+      const float xi = ax[ci], yi = ay[ci], zi = az[ci];
       // this lane's candidate atom, then the neighbours in element order
       const int t = lane;
-      float dx = 0.f, dy = 0.f, dz = 0.f, r = 0.f;
       bool in = false;
       if (t < N && t != ci) {
-        dx = ax[t] - ax[ci];
-        dy = ay[t] - ay[ci];
-        dz = az[t] - az[ci];
-        r = sqrtf(dx * dx + dy * dy + dz * dz);
-        in = r < rc;
+        const float dx = ax[t] - xi, dy = ay[t] - yi, dz = az[t] - zi;
+        in = sqrtf(dx * dx + dy * dy + dz * dz) < rc;
       }
       int n = 0;
       for (int X = 0; X < E; ++X) {
@@ -655,35 +664,37 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
         if (f) nid[wv][n + __popcll(mask & ((uint64_t(1) << lane) - 1))] = t;
         n += __popcll(mask);
       }
-      __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
-      __builtin_amdgcn_wave_barrier();
-      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-      float sx = 0.f, sy = 0.f, sz = 0.f, cx = 0.f, cy = 0.f, cz = 0.f;
-      // H lanes per neighbour slot when the neighbours are few: lane (sl, h)
-      // takes the partners u = h, h + H, ... of slot sl
-      const int H = n <= 16 ? 4 : (n <= 32 ? 2 : 1);
-      const int sl = lane / H, h = lane % H;
+      wave_sync_lds();
+      // lane s < n: neighbour slot s, its unit vector and two-body term
       int js = 0;
-      if (sl < n) {
-        js = nid[wv][sl];
-        const float ux = ax[js] - ax[ci], uy = ay[js] - ay[ci], uz = az[js] - az[ci];
-        if (h == 0) {
-          const float rs = sqrtf(ux * ux + uy * uy + uz * uz);
-          const float d2 = fchl_pair_grad(rs, gi + ael[js] * p.n2, p) / rs;
-          sx = ux * d2;
-          sy = uy * d2;
-          sz = uz * d2;
-          cx = -sx;
-          cy = -sy;
-          cz = -sz;
-        }
-        for (int u = h; u < n; u += H) {
-          if (u == sl) continue;
-          const int ju = nid[wv][u];
-          const bool first = sl < u;   // the pair's j is the lower slot
-          const int ja = first ? js : ju, jb = first ? ju : js;
-          const float vax = ax[ja] - ax[ci], vay = ay[ja] - ay[ci], vaz = az[ja] - az[ci];
-          const float vbx = ax[jb] - ax[ci], vby = ay[jb] - ay[ci], vbz = az[jb] - az[ci];
+      float xs = 0.f, ys = 0.f, zs = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
+      float T = 0.f, Vx = 0.f, Vy = 0.f, Vz = 0.f;
+      if (lane < n) {
+        js = nid[wv][lane];
+        xs = ax[js];
+        ys = ay[js];
+        zs = az[js];
+        const float vx = xs - xi, vy = ys - yi, vz = zs - zi;
+        const float rs = sqrtf(vx * vx + vy * vy + vz * vz);
+        ux = vx / rs;
+        uy = vy / rs;
+        uz = vz / rs;
+        T = fchl_pair_grad(rs, gi + ael[js] * p.n2, p);
+      }
+      const int32_t n_pairs = n * (n - 1) / 2;
+      for (int32_t q0 = 0; q0 < n_pairs; q0 += kFchlBwdPairs) {
+        const int32_t q1 = q0 + kFchlBwdPairs < n_pairs ? q0 + kFchlBwdPairs : n_pairs;
+        for (int32_t q = q0 + lane; q < q1; q += 64) {
+          // q -> slots (s, t), s < t; row s starts at s (2n - s - 1) / 2
+          const float c2n = 2.0f * float(n) - 1.0f;
+          int s = int((c2n - sqrtf(c2n * c2n - 8.0f * float(q))) * 0.5f);
+          s = s < 0 ? 0 : (s > n - 2 ? n - 2 : s);
+          while (s > 0 && s * (2 * n - s - 1) / 2 > q) --s;
+          while ((s + 1) * (2 * n - s - 2) / 2 <= q) ++s;
+          const int tt = s + 1 + (q - s * (2 * n - s - 1) / 2);
+          const int ja = nid[wv][s], jb = nid[wv][tt];
+          const float vax = ax[ja] - xi, vay = ay[ja] - yi, vaz = az[ja] - zi;
+          const float vbx = ax[jb] - xi, vby = ay[jb] - yi, vbz = az[jb] - zi;
           const float a = sqrtf(vax * vax + vay * vay + vaz * vaz);
           const float b = sqrtf(vbx * vbx + vby * vby + vbz * vbz);
           const float wx = vbx - vax, wy = vby - vay, wz = vbz - vaz;
@@ -692,40 +703,39 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
           const int P = fchl_pair(Xa < Xb ? Xa : Xb, Xa < Xb ? Xb : Xa, E);
           float dL[3];
           fchl_triple_grad(a, b, c, gi + int64_t(E) * p.n2 + int64_t(P) * p.n3 * 2, p, angw, dL);
-          const float ua[3] = {vax / a, vay / a, vaz / a};
-          const float ub[3] = {vbx / b, vby / b, vbz / b};
-          const float uc[3] = {wx / c, wy / c, wz / c};
-          if (first) {   // this slot is j: fj, and the centre's fi once per pair
-            sx += dL[0] * ua[0] - dL[2] * uc[0];
-            sy += dL[0] * ua[1] - dL[2] * uc[1];
-            sz += dL[0] * ua[2] - dL[2] * uc[2];
-            cx += -dL[0] * ua[0] - dL[1] * ub[0];
-            cy += -dL[0] * ua[1] - dL[1] * ub[1];
-            cz += -dL[0] * ua[2] - dL[1] * ub[2];
-          } else {       // this slot is l
-            sx += dL[1] * ub[0] + dL[2] * uc[0];
-            sy += dL[1] * ub[1] + dL[2] * uc[1];
-            sz += dL[1] * ub[2] + dL[2] * uc[2];
+          const int sl = q - q0;
+          dls[wv][0][sl] = dL[0];
+          dls[wv][1][sl] = dL[1];
+          dls[wv][2][sl] = dL[2];
+        }
+        wave_sync_lds();
+        if (lane < n) {
+          const int s = lane;
+          for (int u = 0; u < n; ++u) {
+            if (u == s) continue;
+            const int lo = s < u ? s : u, hi = s < u ? u : s;
+            const int32_t q = lo * (2 * n - lo - 1) / 2 + (hi - lo - 1);
+            if (q < q0 || q >= q1) continue;
+            const int sl = q - q0;
+            T += s < u ? dls[wv][0][sl] : dls[wv][1][sl];
+            const int ju = nid[wv][u];
+            const float wx = (ax[ju] - xi) - (xs - xi), wy = (ay[ju] - yi) - (ys - yi),
+                        wz = (az[ju] - zi) - (zs - zi);
+            const float f = dls[wv][2][sl] / sqrtf(wx * wx + wy * wy + wz * wz);
+            Vx -= f * wx;
+            Vy -= f * wy;
+            Vz -= f * wz;
           }
         }
+        wave_sync_lds();   // the chunk's derivatives are no longer read
       }
-      // the H parts of a slot, combined in a fixed order
-      if (H >= 2) {
-        sx += __shfl_xor(sx, 1);
-        sy += __shfl_xor(sy, 1);
-        sz += __shfl_xor(sz, 1);
-      }
-      if (H >= 4) {
-        sx += __shfl_xor(sx, 2);
-        sy += __shfl_xor(sy, 2);
-        sz += __shfl_xor(sz, 2);
-      }
-      if (sl < n && h == 0) {
-        res[wv][0][js] = sx;
-        res[wv][1][js] = sy;
-        res[wv][2][js] = sz;
+      if (lane < n) {
+        res[wv][0][js] = T * ux + Vx;
+        res[wv][1][js] = T * uy + Vy;
+        res[wv][2][js] = T * uz + Vz;
       }
       // the centre's total over the lanes, in a fixed butterfly order
+      float cx = -T * ux, cy = -T * uy, cz = -T * uz;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         cx += __shfl_xor(cx, o);
@@ -1012,8 +1022,12 @@ hipError_t sorf_launch_fchl19_backward(const float* R, const int32_t* element,
   constexpr int64_t kPerLaunch = int64_t(1) << 30;
   for (int64_t m0 = 0; m0 < n_mols; m0 += kPerLaunch) {
     const int64_t cnt = n_mols - m0 < kPerLaunch ? n_mols - m0 : kPerLaunch;
-    hipLaunchKernelGGL(fchl19_backward_small_kernel, dim3(unsigned(cnt)), dim3(256), 0, st, R,
-                       element, mol_ptr, m0, n_mols, E, p, size, g, dR);
+    if (size <= kFchlStage)
+      hipLaunchKernelGGL(fchl19_backward_small_kernel<true>, dim3(unsigned(cnt)), dim3(256), 0, st,
+                         R, element, mol_ptr, m0, n_mols, E, p, size, g, dR);
+    else
+      hipLaunchKernelGGL(fchl19_backward_small_kernel<false>, dim3(unsigned(cnt)), dim3(256), 0,
+                         st, R, element, mol_ptr, m0, n_mols, E, p, size, g, dR);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
     hipLaunchKernelGGL(fchl19_backward_kernel, dim3(unsigned(cnt)), dim3(256), 0, st, R, element,

@@ -72,6 +72,8 @@ CASES = {
     "radial-bins-64": ([16, 11], 2, dict(PRM, n3=64), 1.0),
     "radial-bins-70": ([18, 9], 2, dict(PRM, n3=70), 1.0),
     "radial-bins-2": ([15, 6], 2, dict(PRM, n3=2), 1.0),
+    # ten elements: 2440 entries per row, above what the backward stages in LDS
+    "ten-elements-unstaged": ([22, 14], 10, PRM, 1.0),
 }
 
 
