@@ -43,6 +43,18 @@ __device__ __forceinline__ float fchl_fcut(float r, float rc) {
   return r < rc ? 0.5f * (cosf(3.14159265358979f * r / rc) + 1.0f) : 0.0f;
 }
 
+// Hardware exp2, log2 and reciprocal (about 1 ulp each) for the radial-bin
+// loops, where the correctly rounded library sequences cost several times
+// as many instructions; arguments there are at most a few tens in magnitude,
+// so the results keep a relative accuracy of about 1e-6.
+__device__ __forceinline__ float fchl_exp(float x) {
+  return __builtin_amdgcn_exp2f(x * 1.44269504088896341f);
+}
+__device__ __forceinline__ float fchl_ln(float x) {
+  return __builtin_amdgcn_logf(x) * 0.693147180559945309f;
+}
+__device__ __forceinline__ float fchl_rcp(float x) { return __builtin_amdgcn_rcpf(x); }
+
 // element pair (a <= b) -> position in the lexicographic list of pairs
 __device__ __forceinline__ int fchl_pair(int a, int b, int E) { return a * E - a * (a - 1) / 2 + (b - a); }
 
@@ -121,7 +133,7 @@ __device__ __forceinline__ void fchl19_forward_atom(
     float acc = 0.0f;
     for (int s = grp[X]; s < grp[X + 1]; ++s) {
       const float d = lnR - mu2[s];
-      acc += c2[s] * expf(-d * d * inv2s2[s]);
+      acc += c2[s] * fchl_exp(-d * d * inv2s2[s]);
     }
     out[t] = acc / Rk;
   }
@@ -198,7 +210,7 @@ __device__ __forceinline__ void fchl19_forward_atom(
           for (int64_t q = lo; q < hi; ++q) {
             const int sl = int(q - q0);
             const float d = pmid[sl] - Rk;
-            const float g = expf(-p.eta3 * d * d);
+            const float g = fchl_exp(-p.eta3 * d * d);
             c += pw_c[sl] * g;
             sn += pw_s[sl] * g;
           }
@@ -351,7 +363,7 @@ __global__ __launch_bounds__(256) void fchl19_forward_small_kernel(
     float acc = 0.0f;
     for (int sl = grp[wv][X]; sl < grp[wv][X + 1]; ++sl) {
       const float d = lnR - mu2[wv][sl];
-      acc += c2[wv][sl] * expf(-d * d * inv2s2[wv][sl]);
+      acc += c2[wv][sl] * fchl_exp(-d * d * inv2s2[wv][sl]);
     }
     out[t] = acc / Rk;
   }
@@ -407,11 +419,13 @@ __global__ __launch_bounds__(256) void fchl19_forward_small_kernel(
       const float rij = nr[wv][a], rik = nr[wv][b];
       const float jx = nx[wv][b] - nx[wv][a], jy = ny[wv][b] - ny[wv][a], jz = nz[wv][b] - nz[wv][a];
       const float rjk = sqrtf(jx * jx + jy * jy + jz * jz);
-      const float cos_i = (nx[wv][a] * nx[wv][b] + ny[wv][a] * ny[wv][b] + nz[wv][a] * nz[wv][b]) / (rij * rik);
-      const float cos_j = -(nx[wv][a] * jx + ny[wv][a] * jy + nz[wv][a] * jz) / (rij * rjk);
-      const float cos_k = (nx[wv][b] * jx + ny[wv][b] * jy + nz[wv][b] * jz) / (rik * rjk);
+      const float iij = fchl_rcp(rij), iik = fchl_rcp(rik), ijk = fchl_rcp(rjk);
+      const float cos_i = (nx[wv][a] * nx[wv][b] + ny[wv][a] * ny[wv][b] + nz[wv][a] * nz[wv][b]) * (iij * iik);
+      const float cos_j = -(nx[wv][a] * jx + ny[wv][a] * jy + nz[wv][a] * jz) * (iij * ijk);
+      const float cos_k = (nx[wv][b] * jx + ny[wv][b] * jy + nz[wv][b] * jz) * (iik * ijk);
       const float sin_i = sqrtf(fmaxf(0.0f, 1.0f - cos_i * cos_i));
-      const float xi3 = p.c3 * (1.0f + 3.0f * cos_i * cos_j * cos_k) / powf(rij * rjk * rik, p.N3);
+      const float xi3 = p.c3 * (1.0f + 3.0f * cos_i * cos_j * cos_k) *
+                        __builtin_amdgcn_exp2f(-p.N3 * __builtin_amdgcn_logf(rij * rjk * rik));
       const float w = xi3 * fchl_fcut(rij, rc) * fchl_fcut(rjk, rc) * fchl_fcut(rik, rc) * angw;
       const int sl = q - q0;
       pw_c[wv][sl] = w * cos_i;
@@ -443,7 +457,7 @@ __global__ __launch_bounds__(256) void fchl19_forward_small_kernel(
       for (int32_t q = lo; q < hi; ++q) {
         const int sl = q - q0;
         const float d = pmid[wv][sl] - Rk;
-        const float gk = expf(-p.eta3 * d * d);
+        const float gk = fchl_exp(-p.eta3 * d * d);
         c += pw_c[wv][sl] * gk;
         sn += pw_s[wv][sl] * gk;
         if (q + 1 == segend) {          // element pair Q ends in this part
@@ -522,35 +536,44 @@ __device__ __forceinline__ void fchl_triple_grad(float a, float b, float c,
                                                  const FchlParams& p, float angw, float (&dL)[3]) {
   const float kPi = 3.14159265358979f;
   const float rc = p.rcut;
-  const float ci_ = (a * a + b * b - c * c) / (2.0f * a * b);
-  const float cj_ = (a * a + c * c - b * b) / (2.0f * a * c);
-  const float cl_ = (b * b + c * c - a * a) / (2.0f * b * c);
-  const float dci[3] = {(a * a - b * b + c * c) / (2.0f * a * a * b),
-                        (b * b - a * a + c * c) / (2.0f * a * b * b), -c / (a * b)};
-  const float dcj[3] = {(a * a - c * c + b * b) / (2.0f * a * a * c), -b / (a * c),
-                        (c * c - a * a + b * b) / (2.0f * a * c * c)};
-  const float dcl[3] = {-a / (b * c), (b * b - c * c + a * a) / (2.0f * b * b * c),
-                        (c * c - b * b + a * a) / (2.0f * b * c * c)};
+  const float ia = fchl_rcp(a), ib = fchl_rcp(b), ic = fchl_rcp(c);
+  const float a2 = a * a, b2 = b * b, c2 = c * c;
+  const float ci_ = 0.5f * (a2 + b2 - c2) * ia * ib;
+  const float cj_ = 0.5f * (a2 + c2 - b2) * ia * ic;
+  const float cl_ = 0.5f * (b2 + c2 - a2) * ib * ic;
+  const float dci[3] = {0.5f * (a2 - b2 + c2) * ia * ia * ib, 0.5f * (b2 - a2 + c2) * ia * ib * ib,
+                        -c * ia * ib};
+  const float dcj[3] = {0.5f * (a2 - c2 + b2) * ia * ia * ic, -b * ia * ic,
+                        0.5f * (c2 - a2 + b2) * ia * ic * ic};
+  const float dcl[3] = {-a * ib * ic, 0.5f * (b2 - c2 + a2) * ib * ib * ic,
+                        0.5f * (c2 - b2 + a2) * ib * ic * ic};
   const float si = sqrtf(fmaxf(0.0f, 1.0f - ci_ * ci_));
-  const float dsi_dc = si > 1e-12f ? -ci_ / si : 0.0f;
+  const float dsi_dc = si > 1e-12f ? -ci_ * fchl_rcp(si) : 0.0f;
   const float C = ci_ * cj_ * cl_;
-  const float P3 = powf(a * b * c, p.N3);
-  const float xi3 = p.c3 * (1.0f + 3.0f * C) / P3;
-  const float fa = fchl_fcut(a, rc), fb = fchl_fcut(b, rc), fcc = fchl_fcut(c, rc);
-  const float dfa = a < rc ? -0.5f * (kPi / rc) * sinf(kPi * a / rc) : 0.0f;
-  const float dfb = b < rc ? -0.5f * (kPi / rc) * sinf(kPi * b / rc) : 0.0f;
-  const float dfcc = c < rc ? -0.5f * (kPi / rc) * sinf(kPi * c / rc) : 0.0f;
+  const float invP3 = __builtin_amdgcn_exp2f(-p.N3 * __builtin_amdgcn_logf(a * b * c));
+  const float xi3 = p.c3 * (1.0f + 3.0f * C) * invP3;
+  const float w = kPi / rc;
+  float sa, ca, sb, cb, sc, cc;
+  sincosf(w * a, &sa, &ca);
+  sincosf(w * b, &sb, &cb);
+  sincosf(w * c, &sc, &cc);
+  const float fa = a < rc ? 0.5f * (ca + 1.0f) : 0.0f;
+  const float fb = b < rc ? 0.5f * (cb + 1.0f) : 0.0f;
+  const float fcc = c < rc ? 0.5f * (cc + 1.0f) : 0.0f;
+  const float dfa = a < rc ? -0.5f * w * sa : 0.0f;
+  const float dfb = b < rc ? -0.5f * w * sb : 0.0f;
+  const float dfcc = c < rc ? -0.5f * w * sc : 0.0f;
   const float Fc = fa * fb * fcc;
   const float dF[3] = {dfa * fb * fcc, fa * dfb * fcc, fa * fb * dfcc};
-  const float side[3] = {a, b, c};
+  const float inv_side[3] = {ia, ib, ic};
   const float A = angw * xi3 * Fc;
   const float wc = A * ci_, ws = A * si;
   const float mid = 0.5f * (a + b);
+  const float step = rc / float(p.n3 - 1);
   float Gc = 0.f, Gs = 0.f, Gcp = 0.f, Gsp = 0.f;
   for (int k = 0; k < p.n3; ++k) {
-    const float Rk = rc * float(k) / float(p.n3 - 1);
-    const float d = mid - Rk;
-    const float rad = expf(-p.eta3 * d * d);
+    const float d = mid - float(k) * step;
+    const float rad = fchl_exp(-p.eta3 * d * d);
     const float drad = -2.0f * p.eta3 * d * rad;
     Gc += gp[2 * k] * rad;
     Gs += gp[2 * k + 1] * rad;
@@ -560,7 +583,7 @@ __device__ __forceinline__ void fchl_triple_grad(float a, float b, float c,
 #pragma unroll
   for (int v = 0; v < 3; ++v) {
     const float dC = dci[v] * cj_ * cl_ + ci_ * dcj[v] * cl_ + ci_ * cj_ * dcl[v];
-    const float dxi = p.c3 * 3.0f * dC / P3 - p.N3 * xi3 / side[v];
+    const float dxi = p.c3 * 3.0f * dC * invP3 - p.N3 * xi3 * inv_side[v];
     const float dA = angw * (dxi * Fc + xi3 * dF[v]);
     const float dwc = dA * ci_ + A * dci[v];
     const float dws = dA * si + A * dsi_dc * dci[v];
@@ -583,12 +606,16 @@ __device__ __forceinline__ float fchl_pair_grad(float r, const float* __restrict
   const float fcv = fchl_fcut(r, rc);
   const float dfc = r < rc ? -0.5f * (kPi / rc) * sinf(kPi * r / rc) : 0.0f;
   const float pref = powf(r, -p.N2) / (sqrtf(s2) * 2.50662827463100f);
+  const float is2 = 1.0f / s2;
+  // D = D0 + Lk D1 + Lk^2 D2
+  const float D0 = -p.N2 / r - 0.5f * ds2 * is2, D1 = dmu * is2, D2 = 0.5f * ds2 * is2 * is2;
+  const float step = rc / float(p.n2);
   float dL = 0.0f;
   for (int k = 0; k < p.n2; ++k) {
-    const float Rk = rc * float(k + 1) / float(p.n2);
-    const float Lk = logf(Rk) - mu;
-    const float B = pref * expf(-Lk * Lk / (2.0f * s2)) / Rk;
-    const float D = -p.N2 / r - 0.5f * ds2 / s2 + Lk * dmu / s2 + Lk * Lk * ds2 / (2.0f * s2 * s2);
+    const float Rk = float(k + 1) * step;
+    const float Lk = fchl_ln(Rk) - mu;
+    const float B = pref * fchl_exp(-0.5f * Lk * Lk * is2) * fchl_rcp(Rk);
+    const float D = D0 + Lk * (D1 + Lk * D2);
     dL += gX[k] * (dfc + fcv * D) * B;
   }
   return dL;
