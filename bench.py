@@ -465,6 +465,17 @@ def fchl19_slots(R, mol_ptr, rcut, n2, n3):
     return 8.0 * nb * n2 + 7.0 * pairs * n3 + 80.0 * pairs, nb, pairs
 
 
+def fchl19_backward_slots(nb, pairs, n2, n3):
+    """VALU-slot model of the FCHL19 backward: 23 slots per (neighbour, two-body
+    bin) (logarithm, exponential and reciprocal at quarter rate = 12, and the
+    polynomial in the log-distance), 15 per (neighbour pair, three-body bin)
+    (exponential 5, the bin's distance and its square, the Gaussian's
+    derivative, four FMAs) and 160 per neighbour pair (three square roots,
+    reciprocals and sine/cosine pairs, the power, the cosine derivatives, and
+    the gather along the pair's direction)."""
+    return 23.0 * nb * n2 + 15.0 * pairs * n3 + 160.0 * pairs
+
+
 def representation_leg(args, p, dev, log):
     """FCHL19 on the QM9-like batch (20,000 molecules, 360,149 atoms on synthetic
     molecule-like geometries, five elements, the paper's energy+force parameters,
@@ -532,6 +543,8 @@ def representation_leg(args, p, dev, log):
     med = {k: float(np.median(v)) for k, v in times.items()}
     slots, nb, pairs = fchl19_slots(R, p.mol_ptr, prm_d["rcut"], prm_d["n2"], prm_d["n3"])
     tops = slots / (med["fchl19_forward"] * 1e-3) / 1e12
+    slots_b = fchl19_backward_slots(nb, pairs, prm_d["n2"], prm_d["n3"])
+    tops_b = slots_b / (med["fchl19_backward"] * 1e-3) / 1e12
     out = {
         "workload": (f"{p.n_mols} QM9-like molecules, {A} atoms on synthetic geometries, {E} elements, "
                      f"FCHL19 energy+force parameters ({L} entries), {nb} neighbour entries, "
@@ -542,6 +555,9 @@ def representation_leg(args, p, dev, log):
         "roofline_fchl19_forward": {"bound": "alu", "achieved": tops, "peak": PEAK_VALU_TOPS,
                                     "unit": "T VALU-slots/s", "frac": tops / PEAK_VALU_TOPS,
                                     "traffic": None, "slots_per_launch": slots},
+        "roofline_fchl19_backward": {"bound": "alu", "achieved": tops_b, "peak": PEAK_VALU_TOPS,
+                                     "unit": "T VALU-slots/s", "frac": tops_b / PEAK_VALU_TOPS,
+                                     "traffic": None, "slots_per_launch": slots_b},
         "geometry_gen_s": gen_s,
     }
     if not args.no_cpu_baseline:
