@@ -195,3 +195,27 @@ def test_fchl19_backward_deterministic_and_forces_through_the_model():
         fm = float(np.sum(gpu_rho(Rm, el, ptr, 5, PRM).astype(np.float64) * g))
         fd = (fp - fm) / (2 * h)
         assert abs(a[atom, c] - fd) <= 2e-3 * max(1.0, abs(fd)), (atom, c, a[atom, c], fd)
+
+
+def test_fchl19_backward_qm9_like_full_size_sampled():
+    """The backward over all 20,000 QM9-like molecules in one call (the
+    benchmark's launch), sampled molecules against the oracle's gradient with
+    the same per-molecule bound as above."""
+    p = W.qm9_batch()
+    sizes = p.mol_sizes()
+    R = W.host_geometries(sizes, seed=7)
+    L = F.fchl19_size(5, PRM["n2"], PRM["n3"])
+    gen = torch.Generator().manual_seed(11)
+    g = torch.randn((p.n_atoms, L), generator=gen, dtype=torch.float32)
+    s = S()
+    dR = s.fchl19_backward(torch.from_numpy(R).cuda(), torch.from_numpy(p.element).cuda(),
+                           torch.from_numpy(p.mol_ptr).cuda(), 5, g.cuda(),
+                           s.fchl19_params(**PRM)).cpu().numpy().astype(np.float64)
+    mols = np.random.default_rng(12).choice(p.n_mols, size=12, replace=False)
+    for m in mols:
+        a0, a1 = int(p.mol_ptr[m]), int(p.mol_ptr[m + 1])
+        ref = F.fchl19_grad(R[a0:a1].astype(np.float64), p.element[a0:a1], [0, a1 - a0], 5, PRM,
+                            g[a0:a1].double().numpy())
+        scale = np.abs(ref).max()
+        err = np.abs(dR[a0:a1] - ref).max()
+        assert (err == 0) if scale == 0 else (err <= 2e-5 * scale), (int(m), err, scale)
