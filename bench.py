@@ -236,6 +236,39 @@ def force_training_leg(args, dev, log):
             times[k].append(ev[k][0].elapsed_time(ev[k][1]))
     wall_ms = (time.perf_counter() - t0) * 1e3 / args.force_steps
     med = {k: float(np.median(v)) for k, v in times.items()}
+    # inference on the same conformations with the fitted alpha: energies and
+    # forces in one sorf_predict call, dE/dx alone (sorf_backward), and the force
+    # contraction alone (sorf_forces) on that gradient
+    a32 = alpha.float().contiguous()
+    pred, fcon = sorf.Predictor(model, dev), sorf.ForceContraction(dev)
+    E_p, F_p, F_c = (torch.empty(M, device=dev), torch.empty(3 * A, device=dev),
+                     torch.empty(3 * A, device=dev))
+    gx = torch.empty((A, p.d), device=dev)
+
+    def infer(e=None):
+        for k, fn in enumerate((lambda: pred(batch, a32, J, J_ptr, E=E_p, F=F_p),
+                                lambda: sorf.backward(model, batch, a32, out=gx),
+                                lambda: fcon(batch.mol_ptr, gx, J, J_ptr, out=F_c))):
+            if e is not None:
+                e[2 * k].record()
+            fn()
+            if e is not None:
+                e[2 * k + 1].record()
+
+    infer()
+    torch.cuda.synchronize()
+    inames = ["predict_energy_force", "dE_dx", "forces"]
+    itimes = {k: [] for k in inames}
+    for _ in range(max(3, args.force_steps)):
+        e = [torch.cuda.Event(enable_timing=True) for _ in range(6)]
+        infer(e)
+        torch.cuda.synchronize()
+        for k, nm in enumerate(inames):
+            itimes[nm].append(e[2 * k].elapsed_time(e[2 * k + 1]))
+    imed = {k: float(np.median(v)) for k, v in itimes.items()}
+    f_diff = float((F_c - F_p).abs().max() / F_p.abs().max().clamp_min(1e-30))
+    f_bytes = 4.0 * (n_j + A * p.d + 3 * A)                  # J, dE/dx and F, once each
+    f_gbs = f_bytes / (imed["forces"] * 1e-3) / 1e9
     units = float(A) * 3 * int(p.mol_sizes()[0]) * D          # (atom, column, feature)
     dz_tops = units * dz_slots_per_unit(p.d, p.n_transforms) / (med["dz"] * 1e-3) / 1e12
     rows = M + 3 * A
@@ -253,6 +286,14 @@ def force_training_leg(args, dev, log):
                         "units_per_launch": units},
         "gram_tflops": gram_tf,
         "gram_frac": gram_tf / PEAK_MFMA_TFLOPS[args.gram],
+        "inference": {
+            "phase_ms": imed,
+            "conformations_per_s": M / (imed["predict_energy_force"] * 1e-3),
+            "forces_call_vs_predict_max_rel_diff": f_diff,
+            "roofline_forces": {"bound": "hbm", "achieved": f_gbs, "peak": PEAK_HBM_GBS,
+                                "unit": "GB/s", "frac": f_gbs / PEAK_HBM_GBS, "traffic": None,
+                                "algorithmic_bytes": f_bytes},
+        },
     }
     if not args.no_cpu_baseline:
         from oracle import sorf_oracle as O
@@ -264,7 +305,7 @@ def force_training_leg(args, dev, log):
             "value": 3.0 * q.n_atoms / t_o, "unit": "dZ rows/s",
             "cores": len(os.sched_getaffinity(0)), "kind": "oracle",
             "sample": f"FP64 dense-W oracle, dZ of 4 conformations ({3 * q.n_atoms} rows), {t_o:.2f} s"}
-    del Z, dZ, G, r, ws, solver, J
+    del Z, dZ, G, r, ws, solver, J, gx, E_p, F_p, F_c, pred, fcon
     torch.cuda.empty_cache()
     return out
 

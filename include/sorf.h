@@ -45,7 +45,7 @@
 extern "C" {
 #endif
 
-#define SORF_ABI_VERSION 3
+#define SORF_ABI_VERSION 4
 
 typedef void* sorf_stream_t; /* a hipStream_t */
 
@@ -307,6 +307,29 @@ size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, in
 sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const float* alpha,
                          const float* J, const int64_t* J_ptr, float* E, float* F,
                          void* workspace, size_t workspace_bytes, sorf_stream_t stream);
+
+/* Bytes of workspace sorf_forces needs for n_atoms atoms in n_mols molecules (host-only
+ * query, nondecreasing in both). Returns 0 for negative sizes. */
+size_t sorf_forces_workspace_bytes(int64_t n_atoms, int64_t n_mols);
+
+/* Forces from a given coordinate-independent gradient (Theory section: the forces
+ * are minus the derivative of the energy with respect to the atomic coordinates,
+ * which the chain rule takes through the representation's Jacobians):
+ *   F[3 a + k] = -sum_{i in m} (J_i^T grad_x_i)[3 (a - a0) + k],  a0 = mol_ptr[m],
+ * for atom a of molecule m and coordinate k. With grad_x from sorf_backward (dE = NULL)
+ * this is the force part of sorf_predict, as a call of its own.
+ *   d: length of each atom's gradient row, >= 1.  mol_ptr: [n_mols + 1] int64 CSR
+ *     (same device-side preconditions as a batch).
+ *   grad_x: [n_atoms][d] FP32.  J, J_ptr: the Jacobian blocks exactly as sorf_predict
+ *     takes them.  F: [3 n_atoms] FP32 out ([atom][xyz]).
+ *   Each force is summed in an order fixed by its own molecule (row chunks of the
+ *   block, then chunks in order), so a molecule's forces are bitwise the same in any
+ *   batch and equal to sorf_predict's for the same gradient.
+ *   workspace: device memory of at least sorf_forces_workspace_bytes(), 256-byte
+ *     aligned. grad_x, J, J_ptr, F and the workspace are required when n_atoms > 0. */
+sorf_status sorf_forces(int32_t d, int64_t n_atoms, int64_t n_mols, const int64_t* mol_ptr,
+                        const float* grad_x, const float* J, const int64_t* J_ptr, float* F,
+                        void* workspace, size_t workspace_bytes, sorf_stream_t stream);
 
 /* Opt-in debug check of the device-side preconditions of a batch. Writes to
  * *result (device int32) a bit mask: 0 if mol_ptr is a valid CSR over n_atoms atoms

@@ -29,7 +29,8 @@ EXPORTS = (
     "sorf_gram_workspace_bytes", "sorf_gram_accumulate", "sorf_gram_accumulate_f64",
     "sorf_solve_workspace_bytes",
     "sorf_solve", "sorf_solve_f64",
-    "sorf_predict_workspace_bytes", "sorf_predict", "sorf_validate_batch",
+    "sorf_predict_workspace_bytes", "sorf_predict", "sorf_forces_workspace_bytes", "sorf_forces",
+    "sorf_validate_batch",
 )
 
 
@@ -115,6 +116,8 @@ def load() -> ctypes.CDLL:
         "sorf_solve": (ctypes.c_int, [i32, P, P, f64, i32, P, P, P, sz, P]),
         "sorf_predict_workspace_bytes": (sz, [MP, i64, i64]),
         "sorf_predict": (ctypes.c_int, [MP, BP, P, P, P, P, P, P, sz, P]),
+        "sorf_forces_workspace_bytes": (sz, [i64, i64]),
+        "sorf_forces": (ctypes.c_int, [i32, i64, i64, P, P, P, P, P, P, sz, P]),
         "sorf_validate_batch": (ctypes.c_int, [BP, i32, P, P]),
     }
     for name, (res, args) in sig.items():

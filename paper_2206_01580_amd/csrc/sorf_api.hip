@@ -320,6 +320,32 @@ sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const
   return dev(sorf_launch_molecule_reduce(a, e_atom, grad, J, J_ptr, E, F, plan, st));
 }
 
+size_t sorf_forces_workspace_bytes(int64_t n_atoms, int64_t n_mols) {
+  if (n_atoms < 0 || n_mols < 0) return 0;
+  return sorf_force_plan_bytes(n_atoms, n_mols);
+}
+
+sorf_status sorf_forces(int32_t d, int64_t n_atoms, int64_t n_mols, const int64_t* mol_ptr,
+                        const float* grad_x, const float* J, const int64_t* J_ptr, float* F,
+                        void* workspace, size_t workspace_bytes, sorf_stream_t stream) {
+  if (d < 1 || n_atoms < 0 || n_mols < 0 || mol_ptr == nullptr) return SORF_ERR_INVALID_ARG;
+  if (n_atoms > (int64_t(1) << 40) || n_mols > (int64_t(1) << 31) - 1) return SORF_ERR_INVALID_ARG;
+  if (n_atoms == 0) return SORF_OK;
+  if (n_mols == 0) return SORF_ERR_INVALID_ARG;   // atoms need a molecule
+  if (grad_x == nullptr || J == nullptr || J_ptr == nullptr || F == nullptr)
+    return SORF_ERR_INVALID_ARG;
+  if (workspace == nullptr || workspace_bytes < sorf_force_plan_bytes(n_atoms, n_mols))
+    return SORF_ERR_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  SorfFeatureArgs a{};
+  a.d = d;
+  a.mol_ptr = mol_ptr;
+  a.n_atoms = n_atoms;
+  a.n_mols = n_mols;
+  return dev(sorf_launch_molecule_reduce(a, nullptr, grad_x, J, J_ptr, nullptr, F, workspace,
+                                         hipStream_t(stream)));
+}
+
 sorf_status sorf_validate_batch(const sorf_batch* batch, int32_t n_elements, int32_t* result,
                                 sorf_stream_t stream) {
   sorf_status s = check_batch(batch);

@@ -414,6 +414,42 @@ class Predictor:
         return (E, F) if J is not None else E
 
 
+class ForceContraction:
+    """F = -sum_i J_i^T grad_x_i per molecule (sorf_forces); owns its workspace."""
+
+    def __init__(self, device="cuda"):
+        self.device = device
+        self.ws = torch.empty(0, dtype=torch.uint8, device=device)
+
+    def __call__(self, mol_ptr: torch.Tensor, grad_x: torch.Tensor, J: torch.Tensor,
+                 J_ptr: torch.Tensor, out: Optional[torch.Tensor] = None) -> torch.Tensor:
+        _need(mol_ptr, torch.int64, "mol_ptr")
+        _need(grad_x, torch.float32, "grad_x")
+        if grad_x.dim() != 2:
+            raise ValueError("grad_x must be [n_atoms, d]")
+        n_atoms, d = int(grad_x.shape[0]), int(grad_x.shape[1])
+        n_mols = int(mol_ptr.numel()) - 1
+        _need(J, torch.float32, "J")
+        _need(J_ptr, torch.int64, "J_ptr", n_mols + 1)
+        if out is None:
+            out = torch.empty(3 * n_atoms, dtype=torch.float32, device=grad_x.device)
+        _need(out, torch.float32, "F", 3 * n_atoms)
+        lib = _lib.load()
+        need = lib.sorf_forces_workspace_bytes(n_atoms, n_mols)
+        if self.ws.numel() < need + 256:
+            self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        ws = self.ws.data_ptr() + (-self.ws.data_ptr()) % 256
+        _lib.check("sorf_forces", lib.sorf_forces(
+            d, n_atoms, n_mols, _ptr(mol_ptr), _ptr(grad_x), _ptr(J), _ptr(J_ptr), _ptr(out), ws,
+            need, _stream()))
+        return out
+
+
+def forces(mol_ptr: torch.Tensor, grad_x: torch.Tensor, J: torch.Tensor, J_ptr: torch.Tensor,
+           out: Optional[torch.Tensor] = None) -> torch.Tensor:
+    return ForceContraction(grad_x.device)(mol_ptr, grad_x, J, J_ptr, out)
+
+
 def predict(model: Model, batch: Batch, alpha: torch.Tensor, J=None, J_ptr=None):
     return Predictor(model, batch.x.device)(batch, alpha, J, J_ptr)
 

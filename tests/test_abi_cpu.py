@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.sorf_abi_version() == 3
+    assert lib.sorf_abi_version() == 4
 
 
 def test_struct_layout_matches_c(tmp_path):
@@ -217,3 +217,23 @@ def test_misaligned_arrays_rejected(lib):
     assert lib.sorf_forward(ctypes.byref(m), ctypes.byref(b), PTR + 4, None) == E
     assert lib.sorf_backward(ctypes.byref(m), ctypes.byref(b), PTR + 4, None, PTR, None) == E
     assert lib.sorf_gram_accumulate(10, 64, PTR + 4, None, 0, 0, PTR, None, None, 0, None) == E
+
+
+def test_forces_argument_checks(lib):
+    F = lib.sorf_forces
+    need = lib.sorf_forces_workspace_bytes(5, 2)
+    assert need > 0 and lib.sorf_forces_workspace_bytes(-1, 2) == 0
+    ok = (64, 5, 2, PTR, PTR, PTR, PTR, PTR, PTR, need, None)
+    for i, bad in [(0, 0), (1, -1), (2, -1), (3, None), (2, 0), (4, None), (5, None), (6, None),
+                   (7, None)]:
+        args = list(ok)
+        args[i] = bad
+        assert F(*args) == _lib.SORF_ERR_INVALID_ARG, (i, bad)
+    args = list(ok)
+    args[9] = need - 1
+    assert F(*args) == _lib.SORF_ERR_WORKSPACE
+    args = list(ok)
+    args[8] = PTR + 16
+    assert F(*args) == _lib.SORF_ERR_WORKSPACE
+    # no atoms: nothing to do, nothing required
+    assert F(64, 0, 3, PTR, None, None, None, None, None, 0, None) == _lib.SORF_OK

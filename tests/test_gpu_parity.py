@@ -246,6 +246,60 @@ def test_predict_forces_large_and_empty_molecules():
         assert np.abs(Fg[sl] - Fo).max() <= 1e-5 * np.abs(Fo).max(), m
 
 
+def test_forces_call_matches_definition_and_predict():
+    """sorf_forces: for an arbitrary gradient, F = -sum_i J_i^T g_i per molecule
+    against the oracle's FP64 contraction (same per-molecule bound as predict),
+    over empty, 1-atom and 257-atom molecules with out-of-order, gapped,
+    unaligned Jacobian blocks; on sorf_backward's gradient it gives
+    sorf_predict's forces; no atoms is a no-op."""
+    sizes = np.array([0, 1, 257, 3, 0, 64])
+    rng = np.random.default_rng(3911)
+    A, d = int(sizes.sum()), 128
+    ptr = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    blocks = sizes * d * 3 * sizes
+    J_off = np.zeros(len(sizes), np.int64)
+    off = 5
+    for m in rng.permutation(len(sizes)):
+        J_off[m] = off
+        off += int(blocks[m]) + 11
+    J = (0.1 * rng.standard_normal(off)).astype(np.float32)
+    J_ptr = np.concatenate([J_off, [-1]]).astype(np.int64)
+    g = rng.standard_normal((A, d)).astype(np.float32)
+    Jd, Jp, Pd = (torch.from_numpy(J).cuda(), torch.from_numpy(J_ptr).cuda(),
+                  torch.from_numpy(ptr).cuda())
+    F = S().forces(Pd, torch.from_numpy(g).cuda(), Jd, Jp).cpu().numpy()
+    for m in range(len(sizes)):
+        n = int(sizes[m])
+        if n == 0:
+            continue
+        blk = J[J_off[m]:J_off[m] + blocks[m]]
+        Fo = O.forces(g[ptr[m]:ptr[m + 1]], blk, np.array([0, blocks[m]]), np.array([0, n]))
+        sl = slice(3 * ptr[m], 3 * ptr[m + 1])
+        assert np.abs(F[sl] - Fo).max() <= 1e-5 * np.abs(Fo).max(), m
+    # the force part of sorf_predict, as a call of its own
+    import dataclasses
+    base = W.random_problem(3910, d, 2, 3, 3, 1, 1, 1)
+    p = dataclasses.replace(base, x=rng.standard_normal((A, d)).astype(np.float32),
+                            element=rng.integers(0, 3, A).astype(np.int32), mol_ptr=ptr,
+                            alpha=rng.standard_normal(2 * d).astype(np.float32))
+    model, batch = dev_problem(p)
+    alpha = torch.from_numpy(p.alpha).cuda()
+    _, Fp = S().predict(model, batch, alpha, Jd, Jp)
+    gx = S().backward(model, batch, alpha)
+    Fs = S().forces(batch.mol_ptr, gx, Jd, Jp)
+    torch.cuda.synchronize()
+    Fp, Fs = Fp.cpu().numpy().astype(np.float64), Fs.cpu().numpy().astype(np.float64)
+    for m in range(len(sizes)):
+        sl = slice(3 * ptr[m], 3 * ptr[m + 1])
+        if sizes[m]:
+            assert np.abs(Fs[sl] - Fp[sl]).max() <= 1e-6 * np.abs(Fp[sl]).max(), m
+    # no atoms
+    out = torch.empty(0, device="cuda")
+    S().forces(torch.zeros(3, dtype=torch.int64, device="cuda"), torch.empty((0, d), device="cuda"),
+               Jd, torch.zeros(3, dtype=torch.int64, device="cuda"), out=out)
+    torch.cuda.synchronize()
+
+
 def test_autograd_function_matches_central_differences():
     """SorfEnergy backward vs FP64 central differences of the oracle energy."""
     p = W.random_problem(4242, 16, 3, 3, 2, 2, 3, 2)
