@@ -39,8 +39,15 @@ struct FchlParams {
   float eta2, eta3, N2, N3, c3, zeta, rcut;
 };
 
+// The argument of the cutoff's cosine, pi r / r_cut, lies in [0, pi) below
+// r_cut, so the hardware sine and cosine (argument in revolutions, here in
+// [0, 1/2)) serve without range reduction; f_cut is exactly 0 at and beyond r_cut.
 __device__ __forceinline__ float fchl_fcut(float r, float rc) {
-  return r < rc ? 0.5f * (cosf(3.14159265358979f * r / rc) + 1.0f) : 0.0f;
+  return r < rc ? 0.5f * (__builtin_amdgcn_cosf(r * (0.5f / rc)) + 1.0f) : 0.0f;
+}
+// d f_cut / dr
+__device__ __forceinline__ float fchl_dfcut(float r, float rc) {
+  return r < rc ? -0.5f * (3.14159265358979f / rc) * __builtin_amdgcn_sinf(r * (0.5f / rc)) : 0.0f;
 }
 
 // Hardware exp2, log2 and reciprocal (about 1 ulp each) for the radial-bin
@@ -408,8 +415,8 @@ __global__ __launch_bounds__(256) void fchl19_forward_small_kernel(
         b = grp[wv][Y] + loc % cy;
       } else {
         const int cx = grp[wv][X + 1] - grp[wv][X];
-        const double c2x = 2.0 * cx - 1.0;
-        int u = int((c2x - sqrt(c2x * c2x - 8.0 * double(loc))) * 0.5);
+        const float c2x = 2.0f * float(cx) - 1.0f;
+        int u = int((c2x - sqrtf(c2x * c2x - 8.0f * float(loc))) * 0.5f);
         if (u < 0) u = 0;
         while (u > 0 && u * (2 * cx - u - 1) / 2 > loc) --u;
         while ((u + 1) * (2 * cx - u - 2) / 2 <= loc) ++u;
@@ -534,7 +541,6 @@ __global__ __launch_bounds__(256) void fchl19_forward_small_kernel(
 __device__ __forceinline__ void fchl_triple_grad(float a, float b, float c,
                                                  const float* __restrict__ gp,
                                                  const FchlParams& p, float angw, float (&dL)[3]) {
-  const float kPi = 3.14159265358979f;
   const float rc = p.rcut;
   const float ia = fchl_rcp(a), ib = fchl_rcp(b), ic = fchl_rcp(c);
   const float a2 = a * a, b2 = b * b, c2 = c * c;
@@ -552,17 +558,8 @@ __device__ __forceinline__ void fchl_triple_grad(float a, float b, float c,
   const float C = ci_ * cj_ * cl_;
   const float invP3 = __builtin_amdgcn_exp2f(-p.N3 * __builtin_amdgcn_logf(a * b * c));
   const float xi3 = p.c3 * (1.0f + 3.0f * C) * invP3;
-  const float w = kPi / rc;
-  float sa, ca, sb, cb, sc, cc;
-  sincosf(w * a, &sa, &ca);
-  sincosf(w * b, &sb, &cb);
-  sincosf(w * c, &sc, &cc);
-  const float fa = a < rc ? 0.5f * (ca + 1.0f) : 0.0f;
-  const float fb = b < rc ? 0.5f * (cb + 1.0f) : 0.0f;
-  const float fcc = c < rc ? 0.5f * (cc + 1.0f) : 0.0f;
-  const float dfa = a < rc ? -0.5f * w * sa : 0.0f;
-  const float dfb = b < rc ? -0.5f * w * sb : 0.0f;
-  const float dfcc = c < rc ? -0.5f * w * sc : 0.0f;
+  const float fa = fchl_fcut(a, rc), fb = fchl_fcut(b, rc), fcc = fchl_fcut(c, rc);
+  const float dfa = fchl_dfcut(a, rc), dfb = fchl_dfcut(b, rc), dfcc = fchl_dfcut(c, rc);
   const float Fc = fa * fb * fcc;
   const float dF[3] = {dfa * fb * fcc, fa * dfb * fcc, fa * fb * dfcc};
   const float inv_side[3] = {ia, ib, ic};
@@ -596,7 +593,6 @@ __device__ __forceinline__ void fchl_triple_grad(float a, float b, float c,
 // the centre's upstream gradient gX (the n2 bins of the neighbour's element)
 __device__ __forceinline__ float fchl_pair_grad(float r, const float* __restrict__ gX,
                                                 const FchlParams& p) {
-  const float kPi = 3.14159265358979f;
   const float rc = p.rcut;
   const float q = 1.0f + p.eta2 / (r * r);
   const float s2 = logf(q);
@@ -604,7 +600,7 @@ __device__ __forceinline__ float fchl_pair_grad(float r, const float* __restrict
   const float mu = logf(r / sqrtf(q));
   const float dmu = 1.0f / r + p.eta2 / (r * r * r * q);
   const float fcv = fchl_fcut(r, rc);
-  const float dfc = r < rc ? -0.5f * (kPi / rc) * sinf(kPi * r / rc) : 0.0f;
+  const float dfc = fchl_dfcut(r, rc);
   const float pref = powf(r, -p.N2) / (sqrtf(s2) * 2.50662827463100f);
   const float is2 = 1.0f / s2;
   // D = D0 + Lk D1 + Lk^2 D2
