@@ -113,6 +113,17 @@ def test_fchl19_too_many_neighbours_gives_nan_rows():
     el = np.zeros(600, np.int32)
     rho = gpu_rho(R, el, np.array([0, 600]), 1, PRM)
     assert np.all(np.isnan(rho))
+    # the backward holds at most 512 atoms of a molecule: all 600 rows are NaN,
+    # and a small molecule in the same batch is unaffected
+    R2 = np.concatenate([R, W.host_geometries([9], seed=4)]).astype(np.float32)
+    el2 = np.zeros(609, np.int32)
+    ptr2 = np.array([0, 600, 609])
+    L = F.fchl19_size(1, PRM["n2"], PRM["n3"])
+    g = np.random.default_rng(5).standard_normal((609, L)).astype(np.float32)
+    dR = gpu_grad(R2, el2, ptr2, 1, PRM, g)
+    assert np.all(np.isnan(dR[:600]))
+    ref = F.fchl19_grad(R2[600:].astype(np.float64), el2[600:], [0, 9], 1, PRM, g[600:].astype(np.float64))
+    assert np.abs(dR[600:] - ref).max() <= 2e-5 * np.abs(ref).max()
 
 
 def test_fchl19_qm9_like_full_size_sampled():
