@@ -590,9 +590,10 @@ __device__ __forceinline__ void fchl_triple_grad(float a, float b, float c,
 }
 
 // d/dr of the two-body terms of one neighbour at distance r, contracted with
-// the centre's upstream gradient gX (the n2 bins of the neighbour's element)
+// the centre's upstream gradient gX (the n2 bins of the neighbour's element),
+// over the bins k0, k0 + kstep, ...
 __device__ __forceinline__ float fchl_pair_grad(float r, const float* __restrict__ gX,
-                                                const FchlParams& p) {
+                                                const FchlParams& p, int k0 = 0, int kstep = 1) {
   const float rc = p.rcut;
   const float q = 1.0f + p.eta2 / (r * r);
   const float s2 = logf(q);
@@ -607,7 +608,7 @@ __device__ __forceinline__ float fchl_pair_grad(float r, const float* __restrict
   const float D0 = -p.N2 / r - 0.5f * ds2 * is2, D1 = dmu * is2, D2 = 0.5f * ds2 * is2 * is2;
   const float step = rc / float(p.n2);
   float dL = 0.0f;
-  for (int k = 0; k < p.n2; ++k) {
+  for (int k = k0; k < p.n2; k += kstep) {
     const float Rk = float(k + 1) * step;
     const float Lk = fchl_ln(Rk) - mu;
     const float B = pref * fchl_exp(-0.5f * Lk * Lk * is2) * fchl_rcp(Rk);
@@ -621,10 +622,12 @@ __device__ __forceinline__ float fchl_pair_grad(float r, const float* __restrict
 // its four waves take four centres at a time. For a centre with n
 // neighbours, every unordered pair is evaluated once: lanes take the pairs
 // (in chunks of kFchlBwdPairs) and store dL/da, dL/db, dL/dc in the wave's
-// LDS. Then lane s (one per neighbour) walks its partners t in order and
-// sums T_s (dL/da where s is the pair's j, dL/db where it is l, plus its
-// two-body term) and V_s = -sum dL/dc (x_t - x_s) / r_st. Neighbour s gets
-// T_s u_s + V_s, the centre -sum_s T_s u_s (u_s the unit vector from the
+// LDS. Then each neighbour s gets H lanes (H = 4, 2, 1 for at most 16, 32,
+// 63 neighbours); lane h walks the partners t = h, h + H, ... in order (and
+// the two-body bins h, h + H, ...) and sums T_s (dL/da where s is the pair's
+// j, dL/db where it is l, plus its two-body term) and V_s = -sum dL/dc
+// (x_t - x_s) / r_st; the H parts are combined by fixed shuffles. Neighbour s
+// gets T_s u_s + V_s, the centre -sum_s T_s u_s (u_s the unit vector from the
 // centre to s, summed by fixed shuffles), and the four centres' results are
 // merged into the molecule's gradient in centre order.
 // STAGED: the centre's upstream gradient row (at most kFchlStage entries) is
@@ -688,12 +691,15 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
         n += __popcll(mask);
       }
       wave_sync_lds();
-      // lane s < n: neighbour slot s, its unit vector and two-body term
+      // H lanes per neighbour slot when the neighbours are few: lane (sl, h)
+      // takes the two-body bins and the partners h, h + H, ... of slot sl
+      const int H = n <= 16 ? 4 : (n <= 32 ? 2 : 1);
+      const int sl = lane / H, h = lane % H;
       int js = 0;
       float xs = 0.f, ys = 0.f, zs = 0.f, ux = 0.f, uy = 0.f, uz = 0.f;
       float T = 0.f, Vx = 0.f, Vy = 0.f, Vz = 0.f;
-      if (lane < n) {
-        js = nid[wv][lane];
+      if (sl < n) {
+        js = nid[wv][sl];
         xs = ax[js];
         ys = ay[js];
         zs = az[js];
@@ -702,7 +708,7 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
         ux = vx / rs;
         uy = vy / rs;
         uz = vz / rs;
-        T = fchl_pair_grad(rs, gi + ael[js] * p.n2, p);
+        T = fchl_pair_grad(rs, gi + ael[js] * p.n2, p, h, H);
       }
       const int32_t n_pairs = n * (n - 1) / 2;
       for (int32_t q0 = 0; q0 < n_pairs; q0 += kFchlBwdPairs) {
@@ -732,9 +738,9 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
           dls[wv][2][sl] = dL[2];
         }
         wave_sync_lds();
-        if (lane < n) {
-          const int s = lane;
-          for (int u = 0; u < n; ++u) {
+        if (sl < n) {
+          const int s = sl;
+          for (int u = h; u < n; u += H) {
             if (u == s) continue;
             const int lo = s < u ? s : u, hi = s < u ? u : s;
             const int32_t q = lo * (2 * n - lo - 1) / 2 + (hi - lo - 1);
@@ -752,13 +758,28 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
         }
         wave_sync_lds();   // the chunk's derivatives are no longer read
       }
-      if (lane < n) {
+      // the H parts of a slot, combined in a fixed order (every lane of the
+      // slot then holds the same sums)
+      if (H >= 2) {
+        T += __shfl_xor(T, 1);
+        Vx += __shfl_xor(Vx, 1);
+        Vy += __shfl_xor(Vy, 1);
+        Vz += __shfl_xor(Vz, 1);
+      }
+      if (H >= 4) {
+        T += __shfl_xor(T, 2);
+        Vx += __shfl_xor(Vx, 2);
+        Vy += __shfl_xor(Vy, 2);
+        Vz += __shfl_xor(Vz, 2);
+      }
+      const bool owner = sl < n && h == 0;
+      if (owner) {
         res[wv][0][js] = T * ux + Vx;
         res[wv][1][js] = T * uy + Vy;
         res[wv][2][js] = T * uz + Vz;
       }
-      // the centre's total over the lanes, in a fixed butterfly order
-      float cx = -T * ux, cy = -T * uy, cz = -T * uz;
+      // the centre's total over the slots' owner lanes, in a fixed butterfly order
+      float cx = owner ? -T * ux : 0.f, cy = owner ? -T * uy : 0.f, cz = owner ? -T * uz : 0.f;
 #pragma unroll
       for (int o = 32; o > 0; o >>= 1) {
         cx += __shfl_xor(cx, o);
