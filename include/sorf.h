@@ -312,9 +312,10 @@ sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const
  * query, nondecreasing in both). Returns 0 for negative sizes. */
 size_t sorf_forces_workspace_bytes(int64_t n_atoms, int64_t n_mols);
 
-/* Forces from a given coordinate-independent gradient (Theory section: the forces
- * are minus the derivative of the energy with respect to the atomic coordinates,
- * which the chain rule takes through the representation's Jacobians):
+/* Forces from a given gradient of the energy with respect to the atoms'
+ * representations, dE/dx (Theory section: the forces are minus the derivative of
+ * the energy with respect to the atomic coordinates, which the chain rule takes
+ * through the representation's Jacobians):
  *   F[3 a + k] = -sum_{i in m} (J_i^T grad_x_i)[3 (a - a0) + k],  a0 = mol_ptr[m],
  * for atom a of molecule m and coordinate k. With grad_x from sorf_backward (dE = NULL)
  * this is the force part of sorf_predict, as a call of its own.
