@@ -20,13 +20,24 @@
 
 namespace sorf {
 
+// LDS writes of a wave visible to all its lanes (no workgroup barrier)
+__device__ __forceinline__ void lds_wave_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+  __builtin_amdgcn_wave_barrier();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // ---------------------------------------------------------------------------
 // Forward features
 // ---------------------------------------------------------------------------
 // With DOT, the group does not store its features: it writes the stack's
 // share of the molecule's energy, part[m S + s] = sum_f alpha_f z_f over the
 // stack's features, summed over the group's lanes in a fixed order.
-template <int LOG_D, int LOG_EPL, bool DOT>
+// SHARED (the stack count a multiple of the groups per wave, so that all
+// groups of a wave walk the same molecule): the wave loads the next atom's x
+// row cooperatively (d / 64 floats per lane) while it transforms the current
+// one, and parks it in a double-buffered LDS row that the groups read from.
+template <int LOG_D, int LOG_EPL, bool DOT, bool SHARED>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void forward_kernel(
     const float* __restrict__ x, const int32_t* __restrict__ element,
     const int64_t* __restrict__ mol_ptr, const uint32_t* __restrict__ signs,
@@ -60,6 +71,16 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
 #pragma unroll
   for (int r = 0; r < EPL; ++r) acc[r] = 0.0f;
 
+  constexpr int XR = SHARED ? DV / 64 : 1;   // floats of a row per lane
+  __shared__ float xrow[SHARED ? 4 : 1][2][SHARED ? DV : 1];
+  const int wv = int(threadIdx.x >> 6);
+  if constexpr (SHARED) {
+    if (a0 < a1) {
+#pragma unroll
+      for (int i = 0; i < XR; ++i) xrow[wv][0][lane + 64 * i] = x[a0 * DV + lane + 64 * i];
+      lds_wave_sync();
+    }
+  }
   // the next atom's element is read one atom ahead, and all T sign words of
   // an atom are requested before its first transform
   int32_t e_next = a0 < a1 ? element[a0] : 0;
@@ -67,7 +88,14 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
     const int32_t e = e_next;
     if (a + 1 < a1) e_next = element[a + 1];
     float v[EPL];
-    load_vec<EPL>(v, x + a * DV + q * EPL);
+    float xn[XR];
+    const int buf = int(a - a0) & 1;
+    if constexpr (SHARED) {
+#pragma unroll
+      for (int r = 0; r < EPL; ++r) v[r] = xrow[wv][buf][q * EPL + r];
+    } else {
+      load_vec<EPL>(v, x + a * DV + q * EPL);
+    }
     const uint32_t* sv = signs + (int64_t(e) * T * S + s) * W;
     uint32_t w[3][LW];
 #pragma unroll
@@ -78,6 +106,13 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
       if (t < T) {
         apply_signs<EPL>(v, w[t]);
         fwht<LOGK, EPL>(v, q);
+      }
+    }
+    // the next atom's row is requested here, to arrive during the cosines
+    if constexpr (SHARED) {
+      if (a + 1 < a1) {
+#pragma unroll
+        for (int i = 0; i < XR; ++i) xn[i] = x[(a + 1) * DV + lane + 64 * i];
       }
     }
     // bias in chunks of (at most) 8 entries, so that few of them are live at once
@@ -92,6 +127,15 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
         const float u = __builtin_fmaf(v[r0 + r], c_lane, b[r] * kInv2Pi);  // phase in revolutions
         acc[r0 + r] += __builtin_amdgcn_cosf(u);
       }
+    }
+    if constexpr (SHARED) {
+      // the next atom's row goes to the other buffer, whose last reads (one
+      // atom ago) are behind the previous sync
+      if (a + 1 < a1) {
+#pragma unroll
+        for (int i = 0; i < XR; ++i) xrow[wv][buf ^ 1][lane + 64 * i] = xn[i];
+      }
+      lds_wave_sync();
     }
   }
   if constexpr (DOT) {
@@ -452,14 +496,23 @@ static hipError_t forward_dispatch(const SorfFeatureArgs& a, float* Z, const flo
   const int64_t blocks = (waves + 3) / 4;
   const double D = double(a.d) * a.n_stacks;
   const float c_rev = float(double(sorf_c(a)) * (1.0 / (2.0 * M_PI)));
-  if (alpha == nullptr)
-    hipLaunchKernelGGL((forward_kernel<LOG_D, LOG_EPL, false>), dim3(unsigned(blocks)), dim3(256),
-                       0, st, a.x, a.element, a.mol_ptr, a.signs, a.bias, Z, nullptr, a.n_mols,
-                       a.n_stacks, a.n_transforms, c_rev, float(std::sqrt(2.0 / D)));
-  else
-    hipLaunchKernelGGL((forward_kernel<LOG_D, LOG_EPL, true>), dim3(unsigned(blocks)), dim3(256),
-                       0, st, a.x, a.element, a.mol_ptr, a.signs, a.bias, Z, alpha, a.n_mols,
-                       a.n_stacks, a.n_transforms, c_rev, float(std::sqrt(2.0 / D)));
+  const float scale = float(std::sqrt(2.0 / D));
+  // the shared-row form needs whole rows per wave (d >= 64) and every wave's
+  // groups on one molecule (n_stacks a multiple of the groups per wave)
+  constexpr bool kCanShare = LOG_D >= 6 && LOG_D <= 8;
+  const bool share = kCanShare && a.n_stacks % VPW == 0;
+#define SORF_FWD(DOTV, SH)                                                                     \
+  hipLaunchKernelGGL((forward_kernel<LOG_D, LOG_EPL, DOTV, SH>), dim3(unsigned(blocks)),     \
+                     dim3(256), 0, st, a.x, a.element, a.mol_ptr, a.signs, a.bias, Z, alpha, \
+                     a.n_mols, a.n_stacks, a.n_transforms, c_rev, scale)
+  if (alpha == nullptr) {
+    if (share) SORF_FWD(false, kCanShare);
+    else SORF_FWD(false, false);
+  } else {
+    if (share) SORF_FWD(true, kCanShare);
+    else SORF_FWD(true, false);
+  }
+#undef SORF_FWD
   return hipGetLastError();
 }
 

@@ -93,6 +93,9 @@ SHAPES = [  # (d, n_stacks, T, n_elements, n_mols, min_atoms, max_atoms)
     (32, 9, 2, 3, 7, 0, 8), (64, 4, 3, 4, 10, 1, 12), (64, 33, 1, 2, 5, 0, 9),
     (128, 16, 3, 5, 9, 0, 14), (128, 21, 2, 3, 6, 1, 30), (256, 6, 3, 3, 5, 0, 9),
     (512, 3, 3, 2, 4, 1, 5), (1024, 2, 2, 2, 3, 1, 4),
+    # stack counts that are multiples of the lane groups per wave (32 at d = 64,
+    # 8 at d = 256): the wave-shared x-row form of the forward kernel
+    (64, 32, 3, 3, 4, 0, 11), (256, 8, 3, 3, 5, 0, 10),
 ]
 
 
@@ -165,7 +168,8 @@ def _check_energy(Eg, p, alpha):
 
 
 @pytest.mark.parametrize("shape", [(8, 3, 3, 2, 7, 0, 5), (64, 4, 3, 3, 9, 1, 10),
-                                   (128, 16, 3, 5, 6, 0, 9), (256, 3, 2, 2, 4, 1, 6)],
+                                   (128, 16, 3, 5, 6, 0, 9), (256, 3, 2, 2, 4, 1, 6),
+                                   (64, 32, 3, 3, 4, 0, 8), (256, 8, 2, 2, 4, 1, 6)],
                          ids=lambda s: "d{}-S{}-T{}".format(*s[:3]))
 def test_predict_energies_and_forces(shape):
     d, S_, T, E, M, lo, hi = shape
