@@ -230,3 +230,36 @@ def test_fchl19_backward_qm9_like_full_size_sampled():
         scale = np.abs(ref).max()
         err = np.abs(dR[a0:a1] - ref).max()
         assert (err == 0) if scale == 0 else (err <= 2e-5 * scale), (int(m), err, scale)
+
+
+def test_fchl19_cutoff_boundary():
+    """A neighbour exactly at r_cut adds nothing (f_cut is 0 there, rows and
+    gradient exactly 0); just inside r_cut the rows follow the oracle."""
+    rc = PRM["rcut"]
+    R = np.array([[0.0, 0.0, 0.0], [rc, 0.0, 0.0]], np.float32)
+    el = np.array([0, 1], np.int32)
+    rho = gpu_rho(R, el, [0, 2], 2, PRM)
+    assert np.all(rho == 0.0)
+    L = F.fchl19_size(2, PRM["n2"], PRM["n3"])
+    g = np.ones((2, L), np.float32)
+    assert np.all(gpu_grad(R, el, [0, 2], 2, PRM, g) == 0.0)
+    R[1, 0] = rc - 0.25
+    check(R, el, [0, 2], 2, PRM)
+
+
+def test_fchl19_molecule_results_independent_of_the_batch():
+    """A molecule's rows and gradient are bitwise the same alone and inside a
+    larger batch (each is summed in an order fixed by the molecule itself)."""
+    sizes = [7, 23, 1, 15]
+    rng = np.random.default_rng(21)
+    R = W.host_geometries(sizes, seed=22).astype(np.float32)
+    el = rng.integers(0, 5, size=sum(sizes)).astype(np.int32)
+    ptr = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    g = rng.standard_normal((sum(sizes), 720)).astype(np.float32)
+    rho_all = gpu_rho(R, el, ptr, 5, PRM)
+    dR_all = gpu_grad(R, el, ptr, 5, PRM, g)
+    a0, a1 = int(ptr[1]), int(ptr[2])
+    rho_one = gpu_rho(R[a0:a1], el[a0:a1], [0, a1 - a0], 5, PRM)
+    dR_one = gpu_grad(R[a0:a1], el[a0:a1], [0, a1 - a0], 5, PRM, g[a0:a1])
+    assert np.array_equal(rho_all[a0:a1], rho_one)
+    assert np.array_equal(dR_all[a0:a1], dR_one)
