@@ -3,7 +3,7 @@
 One step = one pass of the whole training + inference path over the QM9-like
 workload (20,000 molecules of 3..29 atoms, d = 128, 64 stacks -> D = 8192,
 sigma = 4): features Z (sorf_forward), normal equations G += Z^T Z, Zty += Z^T y
-(sorf_gram_accumulate, bf16 hi+lo by default), FP64 ridge solve with 3 refinement steps (sorf_solve),
+(sorf_gram_accumulate, FP32 as the workload states), FP64 ridge solve with 3 refinement steps (sorf_solve),
 energies E = Z alpha without forming Z (sorf_predict) and dE/dx for every atom
 (sorf_backward). Inputs are synthetic, seeded, and resident in HBM before the
 clock starts.
@@ -32,7 +32,10 @@ if ROOT not in sys.path:
 # MI355X published peaks
 PEAK_HBM_GBS = 8000.0
 PEAK_MFMA_TFLOPS = {"fp32": 157.3, "bf16": 2500.0, "fp16": 2500.0, "bf16_hilo": 2500.0,
-                    "fp16_hilo": 2500.0, "fp64": 78.6, "fp32_kahan": 157.3}
+                    "fp16_hilo": 2500.0, "fp64": 78.6, "fp32_kahan": 157.3, "split": 2500.0}
+# matrix-core work per algorithmic product, in units of one 16-bit product: hi+lo runs
+# four fp16/bf16 products; split runs one int8 product (double rate) and three fp16
+MFMA_WORK = {"bf16_hilo": 4.0, "fp16_hilo": 4.0, "split": 3.5}
 # VALU issue ceiling derived from unit counts: 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz
 # = 39.3 T lane-instructions/s (packed FP32, which would double it, is disabled by the library's compile flags)
 PEAK_VALU_TOPS = 256 * 4 * 16 * 2.4e9 / 1e12
@@ -82,7 +85,9 @@ def parse():
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--gram", default="bf16_hilo", choices=list(PEAK_MFMA_TFLOPS))
+    ap.add_argument("--gram", default="fp32", choices=list(PEAK_MFMA_TFLOPS))
+    ap.add_argument("--gram-modes", default="fp32_kahan,bf16,bf16_hilo,fp16_hilo,split",
+                    help="other Gram modes timed on the same Z after the step (labelled extras)")
     ap.add_argument("--n-mols", type=int, default=20000)
     ap.add_argument("--n-refine", type=int, default=3)
     ap.add_argument("--lam", type=float, default=1e-6)
@@ -184,7 +189,7 @@ def force_training_leg(args, dev, log):
     F_t = workloads.device_normal(3 * A, p.seed + 3, 1.0, device=dev)
     Z = torch.empty(M, D, device=dev)
     dZ = torch.empty(3 * A, D, device=dev)
-    acc_t = torch.float64 if args.gram == "fp64" else torch.float32
+    acc_t = torch.float64 if args.gram in ("fp64", "split") else torch.float32
     G = torch.empty(D, D, device=dev, dtype=acc_t)
     r = torch.empty(D, device=dev, dtype=acc_t)
     ws = sorf.GramWorkspace(dev)
@@ -662,7 +667,14 @@ def precision_study(args, dev, log):
     log(f"precision: reference done (info {info_ref})")
     G = torch.empty(D, D, device=dev)
     r = torch.empty(D, device=dev)
-    for mode in ("fp32", "fp32_kahan", "bf16", "fp16", "bf16_hilo", "fp16_hilo"):
+    for mode in ("split", "fp32", "fp32_kahan", "bf16", "fp16", "bf16_hilo", "fp16_hilo"):
+        if mode == "split":
+            G = torch.zeros(D, D, dtype=torch.float64, device=dev)
+            r = torch.zeros(D, dtype=torch.float64, device=dev)
+        elif G.dtype != torch.float32:
+            G = torch.empty(D, D, device=dev)
+            r = torch.empty(D, device=dev)
+            torch.cuda.empty_cache()
         G.zero_()
         r.zero_()
         k = sorf.fp16_scale_exp(29 * math.sqrt(2.0 / D)) if mode.startswith("fp16") else 0
@@ -749,7 +761,7 @@ def main():
     D, A, M = p.n_features, p.n_atoms, p.n_mols
     model, batch = sorf.Model.from_problem(p), sorf.Batch.from_problem(p)
     y = torch.from_numpy(p.y).to(dev)
-    acc_t = torch.float64 if args.gram == "fp64" else torch.float32
+    acc_t = torch.float64 if args.gram in ("fp64", "split") else torch.float32
     Z = torch.empty(M, D, device=dev)
     G = torch.empty(D, D, device=dev, dtype=acc_t)
     Zty = torch.empty(D, device=dev, dtype=acc_t)
@@ -817,8 +829,7 @@ def main():
     bwd_slots = valu_slots_per_feature(p.d, p.n_transforms, backward=True) * af
     bwd_tops = bwd_slots / (med["backward"] * 1e-3) / 1e12
     chol_flop = D ** 3 / 3.0
-    # hi+lo modes execute four 16-bit products per algorithmic product
-    mfma_work = 4.0 if args.gram.endswith("_hilo") else 1.0
+    mfma_work = MFMA_WORK.get(args.gram, 1.0)
     rooflines = {
         "gram": {"bound": "mfma", "achieved": gram_tf, "peak": PEAK_MFMA_TFLOPS[args.gram],
                  "unit": "TFLOP/s", "frac": gram_tf / PEAK_MFMA_TFLOPS[args.gram], "traffic": None,
@@ -848,6 +859,9 @@ def main():
     roof = {k: v for k, v in rooflines[dominant].items() if k != "ms"}
     roof["kernel"] = dominant
 
+    gram_dtype = {"fp32": "fp32", "fp32_kahan": "fp32 (Kahan block sums)", "fp64": "f64",
+                  "bf16": "bf16 x1", "fp16": "fp16 x1", "bf16_hilo": "bf16 hi+lo",
+                  "fp16_hilo": "fp16 hi+lo", "split": "int8 head + fp16 tail, f64 G"}[args.gram]
     out = {
         "metric": "SORF atom-features/s fwd+bwd; Gram TFLOP/s; force-request p50/p99 vs plain",
         "value": af / (ms_step * 1e-3),
@@ -859,22 +873,52 @@ def main():
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": f"f32 features / {gram_dtype} Gram / f64 solve",
         "data": "synthetic",
         "config": {"workload": "qm9-like train+infer step: 20000 molecules (3..29 atoms), d=128, "
                                "64 stacks (D=8192), 3 transforms, sigma=4; forward, Gram (" + args.gram +
                                "), FP64 solve, energies, dE/dx",
                    "n_mols": M, "n_atoms": A, "D": D, "gram": args.gram, "lambda": args.lam,
                    "n_refine": args.n_refine},
+        "fwd_bwd_atom_features_per_s": af / ((med["forward"] + med["backward"]) * 1e-3),
+        "gram_tflops": gram_tf,
         "roofline": roof,
         "phase_ms": med,
-        "rooflines": rooflines,
-        "fwd_bwd_atom_features_per_s": af / ((med["forward"] + med["backward"]) * 1e-3),
         "forward_atom_features_per_s": af / (med["forward"] * 1e-3),
-        "gram_tflops": gram_tf,
+        "rooflines": rooflines,
         "solve_info": info,
         "gen_s": gen_s,
     }
+    # other Gram modes on the same Z: labelled extras, not the step's arithmetic
+    extra = {}
+    for mode in [m.strip() for m in args.gram_modes.split(",") if m.strip()]:
+        if mode == args.gram:
+            continue
+        dt = torch.float64 if mode in ("fp64", "split") else torch.float32
+        Gm = G if dt == acc_t else torch.empty(D, D, device=dev, dtype=dt)
+        rm = torch.empty(D, device=dev, dtype=dt)
+        km = sorf.fp16_scale_exp(29 * math.sqrt(2.0 / D)) if mode.startswith("fp16") else 0
+        gram_ws.get(M, D, mode)
+        ts = []
+        for it in range(4):
+            Gm.zero_()
+            rm.zero_()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            sorf.gram_accumulate(Z, Gm, y, rm, precision=mode, scale_exp=km, workspace=gram_ws)
+            e1.record()
+            torch.cuda.synchronize()
+            if it > 0:
+                ts.append(e0.elapsed_time(e1))
+        ms = float(np.median(ts))
+        tf = gram_flop / (ms * 1e-3) / 1e12
+        work = MFMA_WORK.get(mode, 1.0)
+        extra[mode] = {"ms": ms, "algorithmic_tflops": tf, "peak": PEAK_MFMA_TFLOPS[mode],
+                       "frac": tf / PEAK_MFMA_TFLOPS[mode], "mfma_executed_tflops": tf * work,
+                       "mfma_utilisation": tf * work / PEAK_MFMA_TFLOPS[mode]}
+        del Gm, rm
+        log(f"gram {mode}: {ms:.2f} ms")
+    out["gram_modes"] = extra
     del Z, G, model, batch, predictor, solver, grad, gram_ws
     torch.cuda.empty_cache()
     if args.serve_seconds > 0:

@@ -19,7 +19,8 @@
  * Conventions shared by every call:
  *   - Pointers named in the structs and arguments are DEVICE pointers unless a
  *     comment says "host". All buffers are owned by the caller; the library
- *     keeps no state and never frees anything.
+ *     keeps no state and never frees anything. The only HIP objects it creates
+ *     are those sorf_solve_streams_create hands to the caller, who owns them.
  *   - Every compute call is asynchronous on `stream` (a hipStream_t; NULL means
  *     the default stream), returns a status immediately, never prints and never
  *     allocates device memory. Host-side validation of sizes, flags and null
@@ -45,7 +46,7 @@
 extern "C" {
 #endif
 
-#define SORF_ABI_VERSION 4
+#define SORF_ABI_VERSION 5
 
 typedef void* sorf_stream_t; /* a hipStream_t */
 
@@ -261,6 +262,31 @@ sorf_status sorf_gram_accumulate(int64_t n_rows, int32_t D, const float* Z, cons
 sorf_status sorf_gram_accumulate_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
                                      double* G, double* Zty, sorf_stream_t stream);
 
+/* Bytes of workspace sorf_gram_accumulate_split needs (host-only query): Z^T y partials,
+ * column maxima and exponents, and Z packed once as an int8 head (1 byte per entry) and
+ * fp16 head and tail (2 bytes each), rows padded to 64 and columns to 256. 0 for invalid
+ * sizes or n_rows = 0. */
+size_t sorf_gram_split_workspace_bytes(int64_t n_rows, int32_t D);
+
+/* Normal equations with an FP64 G from 8- and 16-bit matrix-core products (the RFF
+ * subsection's regularised normal equation; Timings subsection: FP32 accumulation of
+ * Z^T Z costs accuracy on ill-conditioned systems). Each column f of Z is scaled by
+ * 2^e_f, e_f the largest exponent with max_m |Z[m][f]| 2^e_f <= 127, and split into an
+ * integer head h = rint(Z 2^e_f) (|h| <= 127) and an fp16 tail t = fp16(Z 2^e_f - h):
+ *   G[i][j] += 2^-(e_i + e_j) sum_m (h + t)[m][i] (h + t)[m][j]   for i >= j,
+ * the Gram of the split representation, so G stays positive semidefinite. h^T h runs on
+ * the int8 matrix cores with exact int32 sums (up to 131,072 rows per pass, more rows
+ * take more passes); h^T t + t^T h + t^T t on the fp16 matrix cores, summed in FP32 over
+ * 256-row blocks. |Z - 2^-e_f (h + t)| <= 2^-13 2^-e_f per entry, below 2^-19 of the
+ * column's maximum (max 2^e_f > 63.5).
+ *   Z^T y is summed in FP64 (skipped when y is NULL).
+ *   Z: [n_rows][D] FP32 row-major, 16-byte aligned; G: [D][D] FP64 row-major (only the
+ *   lower triangle is read and written); Zty: [D] FP64. workspace: at least
+ *   sorf_gram_split_workspace_bytes(n_rows, D), 256-byte aligned. Deterministic. */
+sorf_status sorf_gram_accumulate_split(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                                       double* G, double* Zty, void* workspace,
+                                       size_t workspace_bytes, sorf_stream_t stream);
+
 /* Bytes of workspace sorf_solve needs for a D x D system, 1 <= D <= 32768
  * (host-only query; returns 0 for an unsupported D). */
 size_t sorf_solve_workspace_bytes(int32_t D);
@@ -273,17 +299,53 @@ size_t sorf_solve_workspace_bytes(int32_t D);
  *   alpha: [D] FP64 out. info: device int32, written 0 on success or k > 0 when the
  *   leading minor of order k is not positive definite (LAPACK convention; alpha is then
  *   undefined), or -1 if a triangular sweep gave up waiting for a block (an internal
- *   fault, reported instead of hanging; alpha is then undefined). workspace: device memory of at least sorf_solve_workspace_bytes(D),
- *   256-byte aligned. 0 <= n_refine <= 16, lambda >= 0 and finite. */
+ *   fault, reported instead of hanging; alpha is then undefined). workspace: device memory
+ *   of at least sorf_solve_workspace_bytes(D), 256-byte aligned. 0 <= n_refine <= 16,
+ *   lambda >= 0 and finite.
+ *   Every launch goes to `stream`; the call uses no other stream or event. Calls on
+ *   distinct streams with distinct workspaces and outputs are independent. */
 sorf_status sorf_solve(int32_t D, const float* G, const float* Zty, double lambda,
                        int32_t n_refine, double* alpha, int32_t* info, void* workspace,
                        size_t workspace_bytes, sorf_stream_t stream);
 
-/* sorf_solve for an FP64 lower-triangular G and FP64 Zty (from sorf_gram_accumulate_f64);
- * same workspace, outputs and error behaviour. */
+/* sorf_solve for an FP64 lower-triangular G and FP64 Zty (from sorf_gram_accumulate_f64
+ * or sorf_gram_accumulate_split); same workspace, outputs and error behaviour. */
 sorf_status sorf_solve_f64(int32_t D, const double* G, const double* Zty, double lambda,
                            int32_t n_refine, double* alpha, int32_t* info, void* workspace,
                            size_t workspace_bytes, sorf_stream_t stream);
+
+/* Caller-owned resources for the lookahead schedule of the factorisation: a second stream
+ * on which the trailing updates run beside the chain of dependent diagonal steps, and two
+ * events that order it with the call's stream. Host struct of HIP handles. */
+typedef struct {
+  sorf_stream_t side;  /* hipStream_t, must differ from the call's stream          */
+  void* event_fork;    /* hipEvent_t                                              */
+  void* event_join;    /* hipEvent_t, distinct from event_fork                    */
+} sorf_solve_streams;
+
+/* Create the resources of a sorf_solve_streams on the current device: a non-blocking
+ * stream of default priority and two events without timing. Host call; returns
+ * SORF_ERR_DEVICE (with every field NULL) if HIP refuses. The caller releases them with
+ * sorf_solve_streams_destroy, which waits for the side stream first. */
+sorf_status sorf_solve_streams_create(sorf_solve_streams* s);
+sorf_status sorf_solve_streams_destroy(sorf_solve_streams* s);
+
+/* sorf_solve / sorf_solve_f64 with the lookahead schedule: the trailing updates of step k
+ * run on streams->side beside the diagonal factorisation of step k + 1 on `stream`. The
+ * result is bitwise the one of sorf_solve (the same kernels in the same per-tile order);
+ * the call returns with all its work ordered before later work on `stream`. The events
+ * are recorded and waited for inside the call, so one sorf_solve_streams must not serve
+ * two calls at once (calls from different host threads need one each); streams == NULL
+ * is sorf_solve. Same arguments, outputs and errors otherwise; SORF_ERR_INVALID_ARG if a
+ * handle is NULL, the side stream is `stream` or the two events are the same. */
+sorf_status sorf_solve_streamed(int32_t D, const float* G, const float* Zty, double lambda,
+                                int32_t n_refine, double* alpha, int32_t* info, void* workspace,
+                                size_t workspace_bytes, const sorf_solve_streams* streams,
+                                sorf_stream_t stream);
+sorf_status sorf_solve_f64_streamed(int32_t D, const double* G, const double* Zty, double lambda,
+                                    int32_t n_refine, double* alpha, int32_t* info,
+                                    void* workspace, size_t workspace_bytes,
+                                    const sorf_solve_streams* streams, sorf_stream_t stream);
 
 /* Bytes of workspace sorf_predict needs for a batch of n_atoms atoms in n_mols molecules
  * (host-only query; nondecreasing in both, so a buffer sized for the largest batch serves

@@ -63,7 +63,7 @@ __all__ = [
     "hadamard", "sorf_scale", "dense_block", "dense_w", "phases", "atom_features",
     "molecule_features", "gram", "solve", "predict_energies", "grad_x", "forces",
     "derivative_features", "force_normal_equations", "projection_fit", "project",
-    "round_bf16", "round_fp16", "split_hilo", "gram_emulated",
+    "round_bf16", "round_fp16", "split_hilo", "gram_emulated", "split_head_tail",
 ]
 
 
@@ -361,6 +361,32 @@ def split_hilo(Z, kind: str, scale_exp: int = 0):
     return hi, lo
 
 
+def split_head_tail(Z):
+    """Per-column integer head and fp16 tail of the split Gram mode.
+
+    For column f, e_f is the largest integer with max_m |Z[m, f]| * 2**e_f <= 127
+    (0 for an all-zero column); w = Z * 2**e_f (exact); h = round-half-even(w),
+    an integer with |h| <= 127; t = fp16(w - h). Returns (h, t, e) with h and t
+    float64 arrays holding the exact values and e int64 [D]. Found here by a
+    search from a floating-point guess, checked against the defining inequality."""
+    Z32 = np.asarray(Z, dtype=np.float32)
+    m = np.abs(Z32).max(axis=0).astype(np.float64) if Z32.shape[0] else np.zeros(Z32.shape[1])
+    e = np.zeros(m.shape, dtype=np.int64)
+    for f in range(len(m)):
+        if m[f] == 0.0:
+            continue
+        k = int(math.floor(math.log2(127.0 / m[f])))
+        while math.ldexp(m[f], k) > 127.0:
+            k -= 1
+        while math.ldexp(m[f], k + 1) <= 127.0:
+            k += 1
+        e[f] = k
+    w = Z32.astype(np.float64) * np.exp2(e.astype(np.float64))[None, :]   # exact
+    h = np.rint(w)
+    t = (w - h).astype(np.float32).astype(np.float16).astype(np.float64)
+    return h, t, e
+
+
 def gram_emulated(Z, mode: str, scale_exp: int = 0) -> np.ndarray:
     """The Gram matrix each reduced-precision mode must produce when its
     products are exact and accumulation error is ignored (float64 sums):
@@ -370,10 +396,17 @@ def gram_emulated(Z, mode: str, scale_exp: int = 0) -> np.ndarray:
     * 'bf16'/'fp16'      hi^T hi
     * 'bf16_hilo'/'fp16_hilo'  (hi + lo)^T (hi + lo), all four products
 
+    * 'split'      (h + t)^T (h + t) scaled by 2**-(e_i + e_j), the head and
+                   tail of ``split_head_tail`` (``scale_exp`` unused)
+
     scaled back by 2**(-2*scale_exp). The split modes keep lo^T lo so that
     the result is the Gram matrix of the two-term approximation hi + lo and
     stays positive semidefinite, as the normal equations require."""
     Z32 = np.asarray(Z, dtype=np.float32)
+    if mode == "split":
+        h, t, e = split_head_tail(Z32)
+        v = (h + t) * np.exp2(-e.astype(np.float64))[None, :]    # exact in float64
+        return v.T @ v
     if mode in ("fp32", "fp32_kahan"):
         Zd = Z32.astype(np.float64)
         return Zd.T @ Zd

@@ -27,8 +27,10 @@ EXPORTS = (
     "sorf_projection_fit_workspace_bytes", "sorf_projection_fit",
     "sorf_fchl19_length", "sorf_fchl19_forward", "sorf_fchl19_backward",
     "sorf_gram_workspace_bytes", "sorf_gram_accumulate", "sorf_gram_accumulate_f64",
+    "sorf_gram_split_workspace_bytes", "sorf_gram_accumulate_split",
     "sorf_solve_workspace_bytes",
-    "sorf_solve", "sorf_solve_f64",
+    "sorf_solve", "sorf_solve_f64", "sorf_solve_streams_create", "sorf_solve_streams_destroy",
+    "sorf_solve_streamed", "sorf_solve_f64_streamed",
     "sorf_predict_workspace_bytes", "sorf_predict", "sorf_forces_workspace_bytes", "sorf_forces",
     "sorf_validate_batch",
 )
@@ -70,6 +72,14 @@ class SorfFchl19Params(ctypes.Structure):
     ]
 
 
+class SorfSolveStreams(ctypes.Structure):
+    _fields_ = [
+        ("side", ctypes.c_void_p),
+        ("event_fork", ctypes.c_void_p),
+        ("event_join", ctypes.c_void_p),
+    ]
+
+
 class SorfError(RuntimeError):
     def __init__(self, fn: str, code: int):
         super().__init__(f"{fn} failed: {status_string(code)} ({code})")
@@ -92,6 +102,7 @@ def load() -> ctypes.CDLL:
     P = ctypes.c_void_p
     i32, i64, f64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t
     MP, BP = ctypes.POINTER(SorfModel), ctypes.POINTER(SorfBatch)
+    SP = ctypes.POINTER(SorfSolveStreams)
     sig = {
         "sorf_abi_version": (i32, []),
         "sorf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -111,9 +122,15 @@ def load() -> ctypes.CDLL:
         "sorf_gram_accumulate": (ctypes.c_int, [i64, i32, P, P, ctypes.c_int, i32, P, P, P, sz,
                                                 P]),
         "sorf_gram_accumulate_f64": (ctypes.c_int, [i64, i32, P, P, P, P, P]),
+        "sorf_gram_split_workspace_bytes": (sz, [i64, i32]),
+        "sorf_gram_accumulate_split": (ctypes.c_int, [i64, i32, P, P, P, P, P, sz, P]),
         "sorf_solve_workspace_bytes": (sz, [i32]),
         "sorf_solve_f64": (ctypes.c_int, [i32, P, P, f64, i32, P, P, P, sz, P]),
         "sorf_solve": (ctypes.c_int, [i32, P, P, f64, i32, P, P, P, sz, P]),
+        "sorf_solve_streams_create": (ctypes.c_int, [SP]),
+        "sorf_solve_streams_destroy": (ctypes.c_int, [SP]),
+        "sorf_solve_streamed": (ctypes.c_int, [i32, P, P, f64, i32, P, P, P, sz, SP, P]),
+        "sorf_solve_f64_streamed": (ctypes.c_int, [i32, P, P, f64, i32, P, P, P, sz, SP, P]),
         "sorf_predict_workspace_bytes": (sz, [MP, i64, i64]),
         "sorf_predict": (ctypes.c_int, [MP, BP, P, P, P, P, P, P, sz, P]),
         "sorf_forces_workspace_bytes": (sz, [i64, i64]),

@@ -246,14 +246,37 @@ sorf_status sorf_gram_accumulate_f64(int64_t n_rows, int32_t D, const float* Z, 
   return dev(sorf_launch_gram_f64(n_rows, D, Z, y, G, Zty, st));
 }
 
+size_t sorf_gram_split_workspace_bytes(int64_t n_rows, int32_t D) {
+  if (n_rows < 0 || D < 1 || D > (1 << 20)) return 0;
+  return sorf_gram_split_ws_bytes(n_rows, D);
+}
+
+sorf_status sorf_gram_accumulate_split(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                                       double* G, double* Zty, void* workspace,
+                                       size_t workspace_bytes, sorf_stream_t stream) {
+  if (n_rows < 0 || D < 1 || D > (1 << 20)) return SORF_ERR_INVALID_ARG;
+  if (G == nullptr) return SORF_ERR_INVALID_ARG;
+  if (n_rows > 0 && Z == nullptr) return SORF_ERR_INVALID_ARG;
+  if (y != nullptr && Zty == nullptr) return SORF_ERR_INVALID_ARG;
+  if (!aligned16(Z)) return SORF_ERR_INVALID_ARG;
+  if (int64_t(D) * D > (int64_t(1) << 35)) return SORF_ERR_UNSUPPORTED;
+  if (n_rows == 0) return SORF_OK;
+  const size_t need = sorf_gram_split_ws_bytes(n_rows, D);
+  if (workspace == nullptr || workspace_bytes < need) return SORF_ERR_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  return dev(sorf_launch_gram_split(n_rows, D, Z, y, G, Zty, workspace, hipStream_t(stream)));
+}
+
 size_t sorf_solve_workspace_bytes(int32_t D) {
   if (D < 1 || D > kMaxSolveD) return 0;
   return sorf_solve_ws_bytes(D);
 }
 
-sorf_status sorf_solve(int32_t D, const float* G, const float* Zty, double lambda,
-                       int32_t n_refine, double* alpha, int32_t* info, void* workspace,
-                       size_t workspace_bytes, sorf_stream_t stream) {
+namespace {
+
+sorf_status check_solve(int32_t D, const void* G, const void* Zty, double lambda,
+                        int32_t n_refine, const double* alpha, const int32_t* info,
+                        const void* workspace, size_t workspace_bytes) {
   if (D < 1 || D > kMaxSolveD) return SORF_ERR_INVALID_ARG;
   if (!(lambda >= 0.0) || !std::isfinite(lambda)) return SORF_ERR_INVALID_ARG;
   if (n_refine < 0 || n_refine > 16) return SORF_ERR_INVALID_ARG;
@@ -261,22 +284,96 @@ sorf_status sorf_solve(int32_t D, const float* G, const float* Zty, double lambd
     return SORF_ERR_INVALID_ARG;
   if (workspace == nullptr || workspace_bytes < sorf_solve_ws_bytes(D)) return SORF_ERR_WORKSPACE;
   if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  return SORF_OK;
+}
+
+// the side stream must differ from the call's stream and come with both events
+sorf_status check_streams(const sorf_solve_streams* s, sorf_stream_t stream) {
+  if (s == nullptr) return SORF_OK;
+  if (s->side == nullptr || s->event_fork == nullptr || s->event_join == nullptr)
+    return SORF_ERR_INVALID_ARG;
+  if (s->side == stream || s->event_fork == s->event_join) return SORF_ERR_INVALID_ARG;
+  return SORF_OK;
+}
+
+}  // namespace
+
+sorf_status sorf_solve_streams_create(sorf_solve_streams* s) {
+  if (s == nullptr) return SORF_ERR_INVALID_ARG;
+  s->side = nullptr;
+  s->event_fork = s->event_join = nullptr;
+  hipStream_t st = nullptr;
+  hipEvent_t a = nullptr, b = nullptr;
+  if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return SORF_ERR_DEVICE;
+  if (hipEventCreateWithFlags(&a, hipEventDisableTiming) != hipSuccess) {
+    (void)hipStreamDestroy(st);
+    return SORF_ERR_DEVICE;
+  }
+  if (hipEventCreateWithFlags(&b, hipEventDisableTiming) != hipSuccess) {
+    (void)hipEventDestroy(a);
+    (void)hipStreamDestroy(st);
+    return SORF_ERR_DEVICE;
+  }
+  s->side = st;
+  s->event_fork = a;
+  s->event_join = b;
+  return SORF_OK;
+}
+
+sorf_status sorf_solve_streams_destroy(sorf_solve_streams* s) {
+  if (s == nullptr) return SORF_ERR_INVALID_ARG;
+  hipError_t e = hipSuccess, t;
+  if (s->side != nullptr && (t = hipStreamSynchronize(hipStream_t(s->side))) != hipSuccess) e = t;
+  if (s->event_fork != nullptr && (t = hipEventDestroy(hipEvent_t(s->event_fork))) != hipSuccess) e = t;
+  if (s->event_join != nullptr && (t = hipEventDestroy(hipEvent_t(s->event_join))) != hipSuccess) e = t;
+  if (s->side != nullptr && (t = hipStreamDestroy(hipStream_t(s->side))) != hipSuccess) e = t;
+  s->side = nullptr;
+  s->event_fork = s->event_join = nullptr;
+  return dev(e);
+}
+
+sorf_status sorf_solve_streamed(int32_t D, const float* G, const float* Zty, double lambda,
+                                int32_t n_refine, double* alpha, int32_t* info, void* workspace,
+                                size_t workspace_bytes, const sorf_solve_streams* streams,
+                                sorf_stream_t stream) {
+  sorf_status s = check_solve(D, G, Zty, lambda, n_refine, alpha, info, workspace,
+                              workspace_bytes);
+  if (s != SORF_OK) return s;
+  if ((s = check_streams(streams, stream)) != SORF_OK) return s;
   return dev(sorf_launch_solve(D, G, Zty, lambda, n_refine, alpha, info, workspace,
-                               hipStream_t(stream)));
+                               hipStream_t(stream),
+                               streams ? hipStream_t(streams->side) : nullptr,
+                               streams ? hipEvent_t(streams->event_fork) : nullptr,
+                               streams ? hipEvent_t(streams->event_join) : nullptr));
+}
+
+sorf_status sorf_solve_f64_streamed(int32_t D, const double* G, const double* Zty, double lambda,
+                                    int32_t n_refine, double* alpha, int32_t* info,
+                                    void* workspace, size_t workspace_bytes,
+                                    const sorf_solve_streams* streams, sorf_stream_t stream) {
+  sorf_status s = check_solve(D, G, Zty, lambda, n_refine, alpha, info, workspace,
+                              workspace_bytes);
+  if (s != SORF_OK) return s;
+  if ((s = check_streams(streams, stream)) != SORF_OK) return s;
+  return dev(sorf_launch_solve_f64(D, G, Zty, lambda, n_refine, alpha, info, workspace,
+                                   hipStream_t(stream),
+                                   streams ? hipStream_t(streams->side) : nullptr,
+                                   streams ? hipEvent_t(streams->event_fork) : nullptr,
+                                   streams ? hipEvent_t(streams->event_join) : nullptr));
+}
+
+sorf_status sorf_solve(int32_t D, const float* G, const float* Zty, double lambda,
+                       int32_t n_refine, double* alpha, int32_t* info, void* workspace,
+                       size_t workspace_bytes, sorf_stream_t stream) {
+  return sorf_solve_streamed(D, G, Zty, lambda, n_refine, alpha, info, workspace,
+                             workspace_bytes, nullptr, stream);
 }
 
 sorf_status sorf_solve_f64(int32_t D, const double* G, const double* Zty, double lambda,
                            int32_t n_refine, double* alpha, int32_t* info, void* workspace,
                            size_t workspace_bytes, sorf_stream_t stream) {
-  if (D < 1 || D > kMaxSolveD) return SORF_ERR_INVALID_ARG;
-  if (!(lambda >= 0.0) || !std::isfinite(lambda)) return SORF_ERR_INVALID_ARG;
-  if (n_refine < 0 || n_refine > 16) return SORF_ERR_INVALID_ARG;
-  if (G == nullptr || Zty == nullptr || alpha == nullptr || info == nullptr)
-    return SORF_ERR_INVALID_ARG;
-  if (workspace == nullptr || workspace_bytes < sorf_solve_ws_bytes(D)) return SORF_ERR_WORKSPACE;
-  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
-  return dev(sorf_launch_solve_f64(D, G, Zty, lambda, n_refine, alpha, info, workspace,
-                                   hipStream_t(stream)));
+  return sorf_solve_f64_streamed(D, G, Zty, lambda, n_refine, alpha, info, workspace,
+                                 workspace_bytes, nullptr, stream);
 }
 
 size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, int64_t n_mols) {

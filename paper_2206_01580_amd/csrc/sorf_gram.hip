@@ -31,6 +31,7 @@
 // Z^T y only and stages row-major Z slabs directly.
 #include <algorithm>
 #include <cmath>
+#include <type_traits>
 
 #include "sorf_internal.h"
 
@@ -40,15 +41,23 @@ typedef float f32x16 __attribute__((ext_vector_type(16)));
 typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef _Float16 f16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned short u16x8 __attribute__((ext_vector_type(8)));
+typedef int i32x4 __attribute__((ext_vector_type(4)));
+typedef int i32x16 __attribute__((ext_vector_type(16)));
 
-enum GramMode { kFP32 = 0, kBF16 = 1, kFP16 = 2, kBF16HiLo = 3, kFP16HiLo = 4, kFP32Kahan = 5 };
+// Modes 0..5 are the public precisions. The split mode (FP64 output) runs two
+// internal ones: kSplitHead, the integer head products on int8 matrix cores,
+// and kSplitCross, the three fp16 products that involve the tail.
+enum GramMode { kFP32 = 0, kBF16 = 1, kFP16 = 2, kBF16HiLo = 3, kFP16HiLo = 4, kFP32Kahan = 5,
+                kSplitCross = 6, kSplitHead = 7 };
 
 constexpr int KB = 16;                 // rows per fragment / FP32 stage
 constexpr int TM = 256, TN = 128;      // workgroup tile
 constexpr int kFlushRows = 256;        // rows per fresh MFMA accumulator
 constexpr int kPackSlabs = 64;         // 16-row slabs per pack workgroup (Z^T y chunk)
 
-__host__ __device__ constexpr bool is_hilo(int mode) { return mode == kBF16HiLo || mode == kFP16HiLo; }
+__host__ __device__ constexpr bool is_hilo(int mode) {
+  return mode == kBF16HiLo || mode == kFP16HiLo || mode == kSplitCross;
+}
 __host__ __device__ constexpr bool is_bf(int mode) { return mode == kBF16 || mode == kBF16HiLo; }
 
 // round-to-nearest-even conversions, returned as raw 16-bit patterns
@@ -248,6 +257,155 @@ __global__ void zty_finalize_kernel(const double* __restrict__ zpart, int64_t ch
   Zty[c] += T(t);
 }
 
+// ------------------------------------------------------- split mode (FP64 G)
+// Every column f of Z gets a power-of-two scale 2^e_f, e_f the largest
+// exponent with max_m |Z[m][f]| 2^e_f <= 127. The scaled value w = z 2^e_f
+// (exact) is split into an integer head h = rint(w), |h| <= 127, and a tail
+// t = w - h (exact, |t| <= 1/2) rounded to fp16. The Gram of h + t is
+//   h^T h  (int8 products, int32 sums: exact while rows * 127^2 < 2^31)
+// + h^T t + t^T h + t^T t  (fp16 products, FP32 block sums),
+// each entry scaled by 2^-(e_i + e_j) into an FP64 G. Only the tail's fp16
+// rounding (at most 2^-13 2^-e_f, below 2^-19 of the column's maximum) and the
+// FP32 sums of the tail products (2^-7 of G in size) are inexact.
+
+// Column maxima of |Z| over row chunks (a wave reads consecutive columns of
+// one row); partial maxima [chunk][D].
+__global__ __launch_bounds__(256) void colmax_kernel(const float* __restrict__ Z, int64_t M,
+                                                     int32_t D, int64_t rows_per,
+                                                     float* __restrict__ part) {
+  const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (c >= D) return;
+  const int64_t r0 = int64_t(blockIdx.y) * rows_per;
+  const int64_t r1 = r0 + rows_per < M ? r0 + rows_per : M;
+  float m = 0.0f;
+  for (int64_t r = r0; r < r1; ++r) m = fmaxf(m, fabsf(Z[r * D + c]));
+  part[int64_t(blockIdx.y) * D + c] = m;
+}
+
+// e_f from the chunk maxima: with max = mant 2^k (1 <= mant < 2), the largest
+// e with max 2^e <= 127 is 6 - k when mant * 64 <= 127, else 5 - k. An all-zero
+// column gets e = 0.
+__global__ __launch_bounds__(256) void split_exps_kernel(const float* __restrict__ part,
+                                                         int64_t chunks, int32_t D,
+                                                         int32_t* __restrict__ exps) {
+  const int64_t c = int64_t(blockIdx.x) * 256 + threadIdx.x;
+  if (c >= D) return;
+  float m = 0.0f;
+  for (int64_t k = 0; k < chunks; ++k) m = fmaxf(m, part[k * D + c]);
+  int e = 0;
+  if (m > 0.0f) {
+    const int k = ilogbf(m);
+    e = ldexpf(m, 6 - k) <= 127.0f ? 6 - k : 5 - k;
+  }
+  exps[c] = e;
+}
+
+// pack_kernel's tiling for the split mode: per 16-row slab and 32-column block
+// the fp16 head and tail fragments (lane l: column l % 32, rows 8 (l / 32)
+// .. + 7), and the int8 head in 32-row fragments of 16 bytes per lane whose
+// bytes 0..7 are the lane's rows of the first slab and bytes 8..15 those of the
+// second (the same rows as its two fp16 fragments; A and B use one layout, so
+// the order of the K index within a fragment is free). Z^T y in FP64 partials.
+__global__ __launch_bounds__(256) void pack_split_kernel(
+    const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_slabs, int32_t ncb,
+    const int32_t* __restrict__ exps, u16x8* __restrict__ hi, u16x8* __restrict__ lo,
+    uint2* __restrict__ hi8, const float* __restrict__ y, double* __restrict__ zpart) {
+  __shared__ float tile[64][kPackLds];
+  __shared__ double red[8][128];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63, wv = tid >> 6;
+  const int64_t c0 = int64_t(blockIdx.x) * 128;
+  const int64_t ks0 = int64_t(blockIdx.y) * kPackSlabs;
+  const int64_t ks1 = ks0 + kPackSlabs < n_slabs ? ks0 + kPackSlabs : n_slabs;
+  const bool vec = (D % 4 == 0) && (c0 + 128 <= D);
+  const int lrow = tid >> 5, lcol = (tid & 31) * 4;
+  int ex[4];
+#pragma unroll
+  for (int cb = 0; cb < 4; ++cb) {
+    const int64_t c = c0 + cb * 32 + (lane & 31);
+    ex[cb] = c < D ? exps[c] : 0;
+  }
+  float4 buf[8];
+  auto load = [&](int64_t ks) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) {
+      const int64_t r = ks * KB + lrow + 8 * i;
+      const int64_t rc = r < M ? r : M - 1;
+      const float* src = Z + rc * D + c0 + lcol;
+      float4 v;
+      if (vec) {
+        v = *reinterpret_cast<const float4*>(src);
+      } else {
+        v.x = c0 + lcol + 0 < D ? src[0] : 0.0f;
+        v.y = c0 + lcol + 1 < D ? src[1] : 0.0f;
+        v.z = c0 + lcol + 2 < D ? src[2] : 0.0f;
+        v.w = c0 + lcol + 3 < D ? src[3] : 0.0f;
+      }
+      buf[i] = r < M ? v : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+  };
+  double zacc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (ks0 < ks1) load(ks0);
+  for (int64_t ks = ks0; ks < ks1; ks += 4) {
+#pragma unroll
+    for (int i = 0; i < 8; ++i)
+      *reinterpret_cast<float4*>(&tile[lrow + 8 * i][lcol]) = buf[i];
+    __syncthreads();
+    if (ks + 4 < ks1) load(ks + 4);
+    const int64_t slab = ks + wv;
+    if (slab < ks1) {
+      const int rr = 16 * wv + 8 * (lane >> 5);
+      float yv[8];
+      if (y != nullptr) {
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const int64_t r = slab * KB + 8 * (lane >> 5) + j;
+          const float t = y[r < M ? r : M - 1];
+          yv[j] = r < M ? t : 0.0f;
+        }
+      }
+#pragma unroll
+      for (int cb = 0; cb < 4; ++cb) {
+        const int c = cb * 32 + (lane & 31);
+        float v[8];
+#pragma unroll
+        for (int j = 0; j < 8; ++j) v[j] = tile[rr + j][c];
+        if (y != nullptr) {
+#pragma unroll
+          for (int j = 0; j < 8; ++j) zacc[cb] += double(v[j]) * double(yv[j]);
+        }
+        u16x8 h, l;
+        uint32_t b8[2] = {0u, 0u};
+#pragma unroll
+        for (int j = 0; j < 8; ++j) {
+          const float w = ldexpf(v[j], ex[cb]);
+          const float hv = rintf(w);
+          h[j] = __builtin_bit_cast(unsigned short, (_Float16)hv);
+          l[j] = __builtin_bit_cast(unsigned short, (_Float16)(w - hv));
+          b8[j >> 2] |= (uint32_t(int32_t(hv)) & 0xFFu) << (8 * (j & 3));
+        }
+        const int64_t cbg = int64_t(blockIdx.x) * 4 + cb;
+        const int64_t idx = (slab * ncb + cbg) * 64 + lane;
+        hi[idx] = h;
+        lo[idx] = l;
+        hi8[(((slab >> 1) * ncb + cbg) * 64 + lane) * 2 + (slab & 1)] = make_uint2(b8[0], b8[1]);
+      }
+    }
+    __syncthreads();
+  }
+  if (y != nullptr) {
+#pragma unroll
+    for (int cb = 0; cb < 4; ++cb) red[2 * wv + (lane >> 5)][cb * 32 + (lane & 31)] = zacc[cb];
+    __syncthreads();
+    if (tid < 128 && c0 + tid < D) {
+      double t = 0.0;
+#pragma unroll
+      for (int p = 0; p < 8; ++p) t += red[p][tid];
+      zpart[int64_t(blockIdx.y) * D + c0 + tid] = t;
+    }
+  }
+}
+
 // Direct global -> LDS copies (16 bytes per lane; a wave fills 1 KB at a
 // wave-uniform LDS address, lane i at byte 16 i). Their completion is tracked
 // by vmcnt only, so the kernels below wait on vmcnt themselves before the
@@ -284,8 +442,10 @@ template <int MODE>
 __global__ __launch_bounds__(64 * kPackedWaves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ lo,
                         int64_t n_slabs, int32_t ncb, int32_t D, int64_t n_tiles, int64_t nI,
-                        int64_t nJ, float gscale, float* __restrict__ G) {
+                        int64_t nJ, float gscale, float* __restrict__ G,
+                        double* __restrict__ G64, const int32_t* __restrict__ exps) {
   constexpr bool HILO = is_hilo(MODE);
+  constexpr bool CROSS = MODE == kSplitCross;   // tail products only, FP64 output
   constexpr int NP = HILO ? 2 : 1;            // parts per operand
   constexpr int AF = 2 * (TM / 32);           // A fragments per stage
   constexpr int BF = 2 * (TN / 32);           // B fragments per stage
@@ -366,7 +526,7 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
     for (int a = 0; a < BA; ++a)
 #pragma unroll
       for (int b = 0; b < BB; ++b) {
-        P[a][b] = mma16<MODE>(ah[a], bh[b], P[a][b]);
+        if constexpr (!CROSS) P[a][b] = mma16<MODE>(ah[a], bh[b], P[a][b]);
         if constexpr (HILO) {
           P[a][b] = mma16<MODE>(ah[a], bl[b], P[a][b]);
           P[a][b] = mma16<MODE>(al[a], bh[b], P[a][b]);
@@ -376,7 +536,7 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
   };
   // the next half-stage's LDS reads interleaved with the first products
   auto interleave = [] {
-    constexpr int NR = (BA + BB) * NP, NM = BA * BB * (HILO ? 4 : 1);
+    constexpr int NR = (BA + BB) * NP, NM = BA * BB * (CROSS ? 3 : HILO ? 4 : 1);
 #pragma unroll
     for (int i = 0; i < NR; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
@@ -442,7 +602,12 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
       for (int r = 0; r < 16; ++r) {
         const int64_t gi = I * TM + wy * WR + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int64_t gj = J * TN + wx * WC + b * 32 + (lane & 31);
-        if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += S[a][b][r] * gscale;
+        if (gi < D && gj < D && gi >= gj) {
+          if constexpr (CROSS)
+            G64[gi * D + gj] += ldexp(double(S[a][b][r]), -(exps[gi] + exps[gj]));
+          else
+            G[gi * D + gj] += S[a][b][r] * gscale;
+        }
       }
 }
 
@@ -503,7 +668,13 @@ template <int MODE>
 __global__ __launch_bounds__(64 * kX1Waves) __attribute__((amdgpu_waves_per_eu(2, 2)))
 void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_count,
                     int32_t ncb, int32_t D, X1Plan plan, float gscale, float* __restrict__ G,
-                    float* __restrict__ part) {
+                    float* __restrict__ part, double* __restrict__ G64,
+                    const int32_t* __restrict__ exps) {
+  // kSplitHead: 16-byte lanes hold 16 int8 head values of 32 rows (one
+  // v_mfma_i32_32x32x32_i8 per 32 x 32 block and fragment row); the int32
+  // sums are exact, and the result goes to the FP64 G scaled by 2^-(e_i + e_j)
+  constexpr bool HEAD = MODE == kSplitHead;
+  using Acc = std::conditional_t<HEAD, i32x16, f32x16>;
   constexpr int AF = 2 * (TX / 32);   // A fragments per stage (2 slabs)
   constexpr int NF = 2 * AF;          // A and B
   constexpr int NW = kX1Waves;
@@ -550,13 +721,13 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
     for (int c = 0; c < FW; ++c) dma16(hi + src[c] + off, &ring[slot][wv + NW * c][0]);
   };
 
-  f32x16 P[BA][BB];
+  Acc P[BA][BB];
 #pragma unroll
   for (int a = 0; a < BA; ++a)
 #pragma unroll
     for (int b = 0; b < BB; ++b)
 #pragma unroll
-      for (int r = 0; r < 16; ++r) P[a][b][r] = 0.0f;
+      for (int r = 0; r < 16; ++r) P[a][b][r] = 0;
 
   // Software pipeline over half-stages: the fragments of one half-stage are
   // read from LDS while the MFMAs of the previous half-stage run. All NS
@@ -573,7 +744,14 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
 #pragma unroll
     for (int a = 0; a < BA; ++a)
 #pragma unroll
-      for (int b = 0; b < BB; ++b) P[a][b] = mma16<MODE>(af[a], bf[b], P[a][b]);
+      for (int b = 0; b < BB; ++b) {
+        if constexpr (HEAD)
+          P[a][b] = __builtin_amdgcn_mfma_i32_32x32x32_i8(__builtin_bit_cast(i32x4, af[a]),
+                                                          __builtin_bit_cast(i32x4, bf[b]),
+                                                          P[a][b], 0, 0, 0);
+        else
+          P[a][b] = mma16<MODE>(af[a], bf[b], P[a][b]);
+      }
   };
   // the next half-stage's 6 LDS reads interleaved with the first 6 of 8 MFMAs
   auto interleave = [] {
@@ -626,11 +804,17 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
         for (int r = 0; r < 16; ++r) {
           const int64_t gi = I * TX + wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
           const int64_t gj = J * TX + wx * 64 + b * 32 + (lane & 31);
-          if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += P[a][b][r] * gscale;
+          if (gi < D && gj < D && gi >= gj) {
+            if constexpr (HEAD)
+              G64[gi * D + gj] += ldexp(double(P[a][b][r]), -(exps[gi] + exps[gj]));
+            else
+              G[gi * D + gj] += P[a][b][r] * gscale;
+          }
         }
     return;
   }
-  float* out = part + (int64_t(sp) * n_tail + (t - plan.n_whole)) * TX * TX;
+  using Part = std::conditional_t<HEAD, int32_t, float>;
+  Part* out = reinterpret_cast<Part*>(part) + (int64_t(sp) * n_tail + (t - plan.n_whole)) * TX * TX;
 #pragma unroll
   for (int a = 0; a < BA; ++a)
 #pragma unroll
@@ -671,6 +855,36 @@ __global__ __launch_bounds__(256) void gram_combine_kernel(const float* __restri
   for (int c = 0; c < 4; ++c) {
     const int64_t gj = J * TX + j + c;
     if (gj < D && gi >= gj) G[gi * D + gj] += a4[c] * gscale;
+  }
+}
+
+// The split head's slices: exact int64 sums of the int32 partials, slice
+// order irrelevant, then scaled into the FP64 G.
+__global__ __launch_bounds__(256) void gram_combine_head_kernel(const int32_t* __restrict__ part,
+                                                               X1Plan plan, int32_t D,
+                                                               const int32_t* __restrict__ exps,
+                                                               double* __restrict__ G64) {
+  const int64_t n_tail = plan.n_tiles - plan.n_whole;
+  const int64_t tt = blockIdx.x;
+  int64_t I, J;
+  x1_tile_of(plan.n_whole + tt, I, J);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int j = (threadIdx.x & 63) * 4;
+  const int64_t gi = I * TX + i;
+  if (gi >= D) return;
+  int64_t acc[4] = {0, 0, 0, 0};
+  for (int sp = 0; sp < plan.n_split; ++sp) {
+    const int4 v = *reinterpret_cast<const int4*>(
+        part + (int64_t(sp) * n_tail + tt) * TX * TX + int64_t(i) * TX + j);
+    acc[0] += v.x;
+    acc[1] += v.y;
+    acc[2] += v.z;
+    acc[3] += v.w;
+  }
+#pragma unroll
+  for (int c = 0; c < 4; ++c) {
+    const int64_t gj = J * TX + j + c;
+    if (gj < D && gi >= gj) G64[gi * D + gj] += ldexp(double(acc[c]), -(exps[gi] + exps[gj]));
   }
 }
 
@@ -1186,10 +1400,10 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
         const dim3 xg{unsigned(x1_grid(plan))};
         if (mode == kBF16)
           hipLaunchKernelGGL(gram_x1_kernel<kBF16>, xg, dim3(64 * kX1Waves), 0, st, hi, s0, cnt,
-                             g.ncb, D, plan, gs, G, part);
+                             g.ncb, D, plan, gs, G, part, nullptr, nullptr);
         else
           hipLaunchKernelGGL(gram_x1_kernel<kFP16>, xg, dim3(64 * kX1Waves), 0, st, hi, s0, cnt,
-                             g.ncb, D, plan, gs, G, part);
+                             g.ncb, D, plan, gs, G, part, nullptr, nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (plan.n_split > 1) {
           const dim3 cg{unsigned(plan.n_tiles - plan.n_whole), unsigned(TX / 4)};
@@ -1201,13 +1415,111 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
     }
     case kBF16HiLo:
       hipLaunchKernelGGL(gram_packed_kernel<kBF16HiLo>, grid, dim3(64 * kPackedWaves), 0, st, hi,
-                         lo, g.n_slabs, g.ncb, D, n_tiles, nI, nJ, gs, G);
+                         lo, g.n_slabs, g.ncb, D, n_tiles, nI, nJ, gs, G, nullptr, nullptr);
       break;
     case kFP16HiLo:
       hipLaunchKernelGGL(gram_packed_kernel<kFP16HiLo>, grid, dim3(64 * kPackedWaves), 0, st, hi,
-                         lo, g.n_slabs, g.ncb, D, n_tiles, nI, nJ, gs, G);
+                         lo, g.n_slabs, g.ncb, D, n_tiles, nI, nJ, gs, G, nullptr, nullptr);
       break;
   }
+  return hipGetLastError();
+}
+
+// ---------------------------------------------------------- split mode launch
+namespace {
+// Head launches: 64-row stages, exact while rows * 127^2 < 2^31.
+constexpr int64_t kHeadLaunchStages = 2048;   // 131,072 rows
+// Workspace: [Z^T y partials][column maxima][exponents][fp16 head][fp16 tail]
+// [int8 head][head slice partials]
+struct SplitLayout {
+  int64_t n_slabs;   // 16-row slabs, padded to whole 64-row head stages
+  int32_t ncb;       // 32-column blocks, padded to whole 256-column tiles
+  int64_t chunks;    // Z^T y partial chunks
+  int64_t cm_chunks, cm_rows;
+  size_t zpart, cmax, exps, frag16, frag8, head_part;
+};
+SplitLayout split_layout(int64_t M, int32_t D) {
+  SplitLayout g;
+  g.n_slabs = ((M + 4 * KB - 1) / (4 * KB)) * 4;
+  g.ncb = int32_t(((int64_t(D) + TM - 1) / TM) * (TM / 32));
+  g.chunks = (g.n_slabs + kPackSlabs - 1) / kPackSlabs;
+  g.cm_chunks = std::min<int64_t>(256, (M + 511) / 512);
+  g.cm_rows = (M + g.cm_chunks - 1) / g.cm_chunks;
+  g.zpart = al256(size_t(g.chunks) * size_t(D) * sizeof(double));
+  g.cmax = al256(size_t(g.cm_chunks) * size_t(D) * sizeof(float));
+  g.exps = al256(size_t(D) * sizeof(int32_t));
+  g.frag16 = al256(size_t(g.n_slabs) * size_t(g.ncb) * 1024);
+  g.frag8 = al256(size_t(g.n_slabs / 2) * size_t(g.ncb) * 1024);
+  const int64_t n_st = g.n_slabs / 4;
+  const int64_t full = n_st < kHeadLaunchStages ? n_st : kHeadLaunchStages;
+  const int64_t last = n_st % kHeadLaunchStages;
+  size_t b = x1_plan_partial_bytes(x1_plan(D, full));
+  if (last > 0) b = std::max(b, x1_plan_partial_bytes(x1_plan(D, last)));
+  g.head_part = al256(b);
+  return g;
+}
+}  // namespace
+
+size_t sorf_gram_split_ws_bytes(int64_t n_rows, int32_t D) {
+  if (n_rows <= 0 || D <= 0) return 0;
+  const SplitLayout g = split_layout(n_rows, D);
+  return g.zpart + g.cmax + g.exps + 2 * g.frag16 + g.frag8 + g.head_part;
+}
+
+hipError_t sorf_launch_gram_split(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                                  double* G, double* Zty, void* ws, hipStream_t st) {
+  if (n_rows == 0 || D == 0) return hipSuccess;
+  const SplitLayout g = split_layout(n_rows, D);
+  char* w = static_cast<char*>(ws);
+  double* zpart = reinterpret_cast<double*>(w);
+  w += g.zpart;
+  float* cmax = reinterpret_cast<float*>(w);
+  w += g.cmax;
+  int32_t* exps = reinterpret_cast<int32_t*>(w);
+  w += g.exps;
+  u16x8* hi = reinterpret_cast<u16x8*>(w);
+  w += g.frag16;
+  u16x8* lo = reinterpret_cast<u16x8*>(w);
+  w += g.frag16;
+  u16x8* hi8 = reinterpret_cast<u16x8*>(w);
+  w += g.frag8;
+  int32_t* hpart = reinterpret_cast<int32_t*>(w);
+  const dim3 blk{256};
+  const unsigned cgrid = unsigned((D + 255) / 256);
+  hipLaunchKernelGGL(colmax_kernel, dim3(cgrid, unsigned(g.cm_chunks)), blk, 0, st, Z, n_rows, D,
+                     g.cm_rows, cmax);
+  hipLaunchKernelGGL(split_exps_kernel, dim3(cgrid), blk, 0, st, cmax, g.cm_chunks, D, exps);
+  hipLaunchKernelGGL(pack_split_kernel, dim3(unsigned(g.ncb / 4), unsigned(g.chunks)), blk, 0, st,
+                     Z, n_rows, D, g.n_slabs, g.ncb, exps, hi, lo, reinterpret_cast<uint2*>(hi8),
+                     y, zpart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  if (y != nullptr) {
+    hipLaunchKernelGGL(zty_finalize_kernel<double>, dim3(cgrid), blk, 0, st, zpart, g.chunks, D,
+                       Zty);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+  }
+  // head: h^T h on the int8 matrix cores, whole 64-row stages per launch
+  const int64_t n_st = g.n_slabs / 4;
+  for (int64_t s0 = 0; s0 < n_st; s0 += kHeadLaunchStages) {
+    const int64_t cnt = n_st - s0 < kHeadLaunchStages ? n_st - s0 : kHeadLaunchStages;
+    const X1Plan plan = x1_plan(D, cnt);
+    hipLaunchKernelGGL(gram_x1_kernel<kSplitHead>, dim3(unsigned(x1_grid(plan))),
+                       dim3(64 * kX1Waves), 0, st, hi8, s0, cnt, g.ncb, D, plan, 1.0f, nullptr,
+                       reinterpret_cast<float*>(hpart), G, exps);
+    if ((e = hipGetLastError()) != hipSuccess) return e;
+    if (plan.n_split > 1) {
+      const dim3 cg{unsigned(plan.n_tiles - plan.n_whole), unsigned(TX / 4)};
+      hipLaunchKernelGGL(gram_combine_head_kernel, cg, blk, 0, st, hpart, plan, D, exps, G);
+      if ((e = hipGetLastError()) != hipSuccess) return e;
+    }
+  }
+  // tail: h^T t + t^T h + t^T t on the fp16 matrix cores
+  int64_t nI, nJ;
+  const int64_t n_tiles = gram_tiles(D, nI, nJ);
+  const dim3 grid{unsigned(((gram_super_tiles(D) + 7) / 8) * 8 * SR_T * SC_T)};
+  hipLaunchKernelGGL(gram_packed_kernel<kSplitCross>, grid, dim3(64 * kPackedWaves), 0, st, hi, lo,
+                     g.n_slabs, g.ncb, D, n_tiles, nI, nJ, 1.0f, nullptr, G, exps);
   return hipGetLastError();
 }
 

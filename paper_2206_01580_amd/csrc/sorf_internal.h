@@ -243,13 +243,20 @@ hipError_t sorf_launch_fill(float* p, int64_t n, float v, hipStream_t s);
 size_t sorf_gram_ws_bytes(int64_t n_rows, int32_t D, int mode);
 hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const float* y, int mode,
                             int32_t scale_exp, float* G, float* Zty, void* ws, hipStream_t s);
+size_t sorf_gram_split_ws_bytes(int64_t n_rows, int32_t D);
+hipError_t sorf_launch_gram_split(int64_t n_rows, int32_t D, const float* Z, const float* y,
+                                  double* G, double* Zty, void* ws, hipStream_t s);
 hipError_t sorf_launch_gram_f64(int64_t n_rows, int32_t D, const float* Z, const float* y,
                                 double* G, double* Zty, hipStream_t s);
 
 size_t sorf_solve_ws_bytes(int32_t D);
+// side == nullptr: every launch on s; otherwise the lookahead runs on side,
+// ordered with s through the two caller-owned events
 hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double lambda,
                              int32_t n_refine, double* alpha, int32_t* info, void* ws,
-                             hipStream_t s);
+                             hipStream_t s, hipStream_t side, hipEvent_t ev_fork,
+                             hipEvent_t ev_join);
 hipError_t sorf_launch_solve_f64(int32_t D, const double* G, const double* Zty, double lambda,
                                  int32_t n_refine, double* alpha, int32_t* info, void* ws,
-                                 hipStream_t s);
+                                 hipStream_t s, hipStream_t side, hipEvent_t ev_fork,
+                                 hipEvent_t ev_join);

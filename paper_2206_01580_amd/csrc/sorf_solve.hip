@@ -17,7 +17,6 @@
 // Triangular solves use the inverted diagonal blocks: one launch per sweep,
 // one workgroup per block row, each waiting for the solved values it needs.
 #include <cmath>
-#include <mutex>
 
 #include "sorf_internal.h"
 
@@ -1101,36 +1100,11 @@ static hipError_t solve_triangular(const SolveWs& w, int32_t D, const double* rh
   return hipGetLastError();
 }
 
-// Per-device side stream (default priority, non-blocking) and two events for
-// the factorisation lookahead, created on first use and kept for the process.
-static hipError_t lookahead_resources(hipStream_t* side, hipEvent_t* fork, hipEvent_t* join) {
-  struct Res {
-    hipStream_t s = nullptr;
-    hipEvent_t a = nullptr, b = nullptr;
-  };
-  static std::mutex mu;
-  static Res res[64];
-  int dev = 0;
-  hipError_t e = hipGetDevice(&dev);
-  if (e != hipSuccess) return e;
-  if (dev < 0 || dev >= 64) return hipErrorInvalidDevice;
-  std::lock_guard<std::mutex> lock(mu);
-  Res& r = res[dev];
-  if (r.s == nullptr) {
-    if ((e = hipStreamCreateWithFlags(&r.s, hipStreamNonBlocking)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&r.a, hipEventDisableTiming)) != hipSuccess) return e;
-    if ((e = hipEventCreateWithFlags(&r.b, hipEventDisableTiming)) != hipSuccess) return e;
-  }
-  *side = r.s;
-  *fork = r.a;
-  *join = r.b;
-  return hipSuccess;
-}
-
 template <typename TG>
 static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lambda,
                                int32_t n_refine, double* alpha, int32_t* info, void* ws,
-                               hipStream_t st) {
+                               hipStream_t st, hipStream_t side, hipEvent_t ev_panel,
+                               hipEvent_t ev_next) {
   const SolveWs w = carve(ws, D);
   const unsigned vg = unsigned((D + 255) / 256);
   hipLaunchKernelGGL(promote_kernel<TG>, dim3(vg, unsigned(D)), dim3(256), 0, st, G, D, lambda,
@@ -1147,10 +1121,13 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
   // second stream runs the far update of step k before the next-panel tiles
   // of step k + 1. Only stream events order kernels of different streams, so
   // the schedule stays correct when a tool serialises the launches.
-  hipStream_t side = nullptr;
-  hipEvent_t ev_panel = nullptr, ev_next = nullptr;
-  hipError_t e = lookahead_resources(&side, &ev_panel, &ev_next);
-  if (e != hipSuccess) return e;
+  // The second stream and both events belong to the caller. Without them
+  // (side == nullptr) every launch goes to the caller's stream in the same
+  // order, which serialises the chain behind each trailing update but runs
+  // the same kernels on the same data: the result is bitwise the same.
+  const bool two = side != nullptr;
+  if (!two) side = st;
+  hipError_t e = hipSuccess;
   hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, 0, info, w.Linv,
                      w.LinvT);
   for (int32_t k = 0; k + NB < D; k += NB) {
@@ -1162,15 +1139,17 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
                        w.Linv, w.pflags, info);
     const bool side_work = nwg > strips || nt > 1;
     if (side_work) {
-      if ((e = hipEventRecord(ev_panel, st)) != hipSuccess) return e;
-      if ((e = hipStreamWaitEvent(side, ev_panel, 0)) != hipSuccess) return e;
+      if (two) {
+        if ((e = hipEventRecord(ev_panel, st)) != hipSuccess) return e;
+        if ((e = hipStreamWaitEvent(side, ev_panel, 0)) != hipSuccess) return e;
+      }
       if (nwg > strips)
         hipLaunchKernelGGL(panel_kernel, dim3(unsigned(nwg - strips)), dim3(512), 0, side, w.A,
                            D, k, int32_t(strips), w.Linv, w.pflags, info);
       if (nt > 1)
         hipLaunchKernelGGL(syrk_next_kernel, dim3(unsigned(nt)), dim3(512), 0, side, w.A, D, k,
                            int32_t(nt));
-      if ((e = hipEventRecord(ev_next, side)) != hipSuccess) return e;
+      if (two && (e = hipEventRecord(ev_next, side)) != hipSuccess) return e;
       const int64_t n_sub = (nt - 1) * nt / 2;   // sub-triangle from (1, 1)
       if (n_sub > 1) {
         const int64_t g = n_sub - 1 < kSyrkGrid ? n_sub - 1 : kSyrkGrid;
@@ -1180,11 +1159,13 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
     }
     hipLaunchKernelGGL(potrf_diag_kernel, dim3(1), dim3(256), 0, st, w.A, D, k + NB, info,
                        w.Linv, w.LinvT);
-    if (side_work && (e = hipStreamWaitEvent(st, ev_next, 0)) != hipSuccess) return e;
+    if (two && side_work && (e = hipStreamWaitEvent(st, ev_next, 0)) != hipSuccess) return e;
   }
   // the last far update (if any) before the sweeps read L
-  if ((e = hipEventRecord(ev_next, side)) != hipSuccess) return e;
-  if ((e = hipStreamWaitEvent(st, ev_next, 0)) != hipSuccess) return e;
+  if (two) {
+    if ((e = hipEventRecord(ev_next, side)) != hipSuccess) return e;
+    if ((e = hipStreamWaitEvent(st, ev_next, 0)) != hipSuccess) return e;
+  }
   hipLaunchKernelGGL(transpose_blocks_kernel, dim3(unsigned((D + NB - 1) / NB)), dim3(256), 0, st,
                      w.Linv, w.LinvT);
   e = hipGetLastError();
@@ -1218,12 +1199,16 @@ size_t sorf_solve_ws_bytes(int32_t D) {
 
 hipError_t sorf_launch_solve(int32_t D, const float* G, const float* Zty, double lambda,
                              int32_t n_refine, double* alpha, int32_t* info, void* ws,
-                             hipStream_t st) {
-  return launch_solve<float>(D, G, Zty, lambda, n_refine, alpha, info, ws, st);
+                             hipStream_t st, hipStream_t side, hipEvent_t ev_fork,
+                             hipEvent_t ev_join) {
+  return launch_solve<float>(D, G, Zty, lambda, n_refine, alpha, info, ws, st, side, ev_fork,
+                             ev_join);
 }
 
 hipError_t sorf_launch_solve_f64(int32_t D, const double* G, const double* Zty, double lambda,
                                  int32_t n_refine, double* alpha, int32_t* info, void* ws,
-                                 hipStream_t st) {
-  return launch_solve<double>(D, G, Zty, lambda, n_refine, alpha, info, ws, st);
+                                 hipStream_t st, hipStream_t side, hipEvent_t ev_fork,
+                                 hipEvent_t ev_join) {
+  return launch_solve<double>(D, G, Zty, lambda, n_refine, alpha, info, ws, st, side, ev_fork,
+                              ev_join);
 }

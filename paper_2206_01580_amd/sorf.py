@@ -294,7 +294,11 @@ class GramWorkspace:
         self.buf = torch.empty(0, dtype=torch.uint8, device=device)
 
     def get(self, n_rows: int, D: int, precision: str):
-        need = _lib.load().sorf_gram_workspace_bytes(n_rows, D, _lib.GRAM_MODES[precision])
+        lib = _lib.load()
+        if precision == "split":
+            need = lib.sorf_gram_split_workspace_bytes(n_rows, D)
+        else:
+            need = lib.sorf_gram_workspace_bytes(n_rows, D, _lib.GRAM_MODES[precision])
         if need == 0:
             return None, 0
         if self.buf.numel() < need + 256:
@@ -305,11 +309,12 @@ class GramWorkspace:
 def gram_accumulate(Z: torch.Tensor, G: torch.Tensor, y: Optional[torch.Tensor] = None,
                     Zty: Optional[torch.Tensor] = None, precision: str = "fp32",
                     scale_exp: int = 0, workspace: Optional[GramWorkspace] = None) -> None:
-    """G += Z^T Z on the lower triangle; Zty += Z^T y (sorf_gram_accumulate, or
-    sorf_gram_accumulate_f64 for precision 'fp64', where G and Zty are float64)."""
+    """G += Z^T Z on the lower triangle; Zty += Z^T y (sorf_gram_accumulate;
+    sorf_gram_accumulate_f64 for precision 'fp64' and sorf_gram_accumulate_split for
+    'split', where G and Zty are float64)."""
     M, D = Z.shape
     _need(Z, torch.float32, "Z")
-    acc_t = torch.float64 if precision == "fp64" else torch.float32
+    acc_t = torch.float64 if precision in ("fp64", "split") else torch.float32
     _need(G, acc_t, "G", D * D)
     if y is not None:
         _need(y, torch.float32, "y", M)
@@ -321,6 +326,10 @@ def gram_accumulate(Z: torch.Tensor, G: torch.Tensor, y: Optional[torch.Tensor] 
         return
     ws = workspace if workspace is not None else GramWorkspace(Z.device)
     wptr, wbytes = ws.get(M, D, precision)
+    if precision == "split":
+        _lib.check("sorf_gram_accumulate_split", lib.sorf_gram_accumulate_split(
+            M, D, _ptr(Z), _ptr(y), _ptr(G), _ptr(Zty), wptr, wbytes, _stream()))
+        return
     _lib.check("sorf_gram_accumulate", lib.sorf_gram_accumulate(
         M, D, _ptr(Z), _ptr(y), _lib.GRAM_MODES[precision], scale_exp, _ptr(G), _ptr(Zty),
         wptr, wbytes, _stream()))
@@ -335,9 +344,16 @@ def fp16_scale_exp(max_abs: float) -> int:
 
 
 class Solver:
-    """Owns the FP64 workspace of sorf_solve for one system size."""
+    """Owns the FP64 workspace of sorf_solve for one system size.
 
-    def __init__(self, D: int, device="cuda"):
+    With ``lookahead=True`` it also owns a ``sorf_solve_streams`` (a second
+    stream and two events, created by the library for this object only) and
+    runs the two-stream factorisation schedule (``sorf_solve_streamed``);
+    otherwise every launch goes to the current stream (``sorf_solve``). The
+    results are bitwise the same. One Solver must not be called from two
+    threads at once; each thread needs its own."""
+
+    def __init__(self, D: int, device="cuda", lookahead: bool = True):
         lib = _lib.load()
         self.D = D
         nbytes = lib.sorf_solve_workspace_bytes(D)
@@ -347,6 +363,25 @@ class Solver:
         self.ws_off = (-self.ws.data_ptr()) % 256
         self.nbytes = nbytes
         self.info = torch.zeros(1, dtype=torch.int32, device=device)
+        self._streams = None
+        if lookahead:
+            st = _lib.SorfSolveStreams()
+            with torch.cuda.device(self.ws.device):
+                _lib.check("sorf_solve_streams_create", lib.sorf_solve_streams_create(
+                    ctypes.byref(st)))
+            self._streams = st
+
+    def close(self) -> None:
+        """Release the side stream and events (also done on garbage collection)."""
+        if self._streams is not None:
+            st, self._streams = self._streams, None
+            _lib.load().sorf_solve_streams_destroy(ctypes.byref(st))
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:  # pragma: no cover - interpreter shutdown
+            pass
 
     def __call__(self, G: torch.Tensor, Zty: torch.Tensor, lam: float, n_refine: int = 3,
                  out: Optional[torch.Tensor] = None) -> torch.Tensor:
@@ -358,10 +393,16 @@ class Solver:
             out = torch.empty(D, dtype=torch.float64, device=G.device)
         _need(out, torch.float64, "alpha", D)
         lib = _lib.load()
-        fn, name = (lib.sorf_solve_f64, "sorf_solve_f64") if f64 else (lib.sorf_solve, "sorf_solve")
-        _lib.check(name, fn(D, _ptr(G), _ptr(Zty), float(lam), int(n_refine), _ptr(out),
-                            _ptr(self.info), self.ws.data_ptr() + self.ws_off, self.nbytes,
-                            _stream()))
+        args = (D, _ptr(G), _ptr(Zty), float(lam), int(n_refine), _ptr(out), _ptr(self.info),
+                self.ws.data_ptr() + self.ws_off, self.nbytes)
+        if self._streams is None:
+            fn, name = ((lib.sorf_solve_f64, "sorf_solve_f64") if f64
+                        else (lib.sorf_solve, "sorf_solve"))
+            _lib.check(name, fn(*args, _stream()))
+        else:
+            fn, name = ((lib.sorf_solve_f64_streamed, "sorf_solve_f64_streamed") if f64
+                        else (lib.sorf_solve_streamed, "sorf_solve_streamed"))
+            _lib.check(name, fn(*args, ctypes.byref(self._streams), _stream()))
         return out
 
 

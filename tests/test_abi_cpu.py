@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.sorf_abi_version() == 4
+    assert lib.sorf_abi_version() == 5
 
 
 def test_struct_layout_matches_c(tmp_path):
@@ -177,6 +177,67 @@ def test_solve_argument_checks(lib):
     assert S(100, PTR, PTR, 1e-3, 3, PTR, PTR, 256, need - 1, None) == _lib.SORF_ERR_WORKSPACE
     assert S(100, PTR, PTR, 1e-3, 3, PTR, PTR, None, need, None) == _lib.SORF_ERR_WORKSPACE
     assert S(100, PTR, PTR, 1e-3, 3, PTR, PTR, 264, need, None) == _lib.SORF_ERR_WORKSPACE
+
+
+def test_gram_split_argument_checks(lib):
+    G = lib.sorf_gram_accumulate_split
+    need = lib.sorf_gram_split_workspace_bytes(1000, 300)
+    # head and tail fragments (1 + 2 + 2 bytes per entry of the padded Z) at least
+    assert need >= 1024 * 512 * 5
+    assert lib.sorf_gram_split_workspace_bytes(0, 300) == 0
+    assert lib.sorf_gram_split_workspace_bytes(10, 0) == 0
+    assert lib.sorf_gram_split_workspace_bytes(-1, 300) == 0
+    E, W = _lib.SORF_ERR_INVALID_ARG, _lib.SORF_ERR_WORKSPACE
+    assert G(-1, 300, PTR, None, PTR, None, PTR, need, None) == E
+    assert G(1000, 0, PTR, None, PTR, None, PTR, need, None) == E
+    assert G(1000, 300, PTR, None, None, None, PTR, need, None) == E       # no G
+    assert G(1000, 300, None, None, PTR, None, PTR, need, None) == E       # no Z
+    assert G(1000, 300, PTR, PTR, PTR, None, PTR, need, None) == E         # y without Zty
+    assert G(1000, 300, PTR + 4, None, PTR, None, PTR, need, None) == E    # misaligned Z
+    assert G(1000, 300, PTR, None, PTR, None, None, need, None) == W
+    assert G(1000, 300, PTR, None, PTR, None, PTR, need - 1, None) == W
+    assert G(1000, 300, PTR, None, PTR, None, PTR + 16, need, None) == W
+    assert G(0, 300, None, None, PTR, None, None, 0, None) == _lib.SORF_OK  # nothing to add
+
+
+def test_solve_streamed_argument_checks(lib):
+    """The streamed solve runs the same host checks as sorf_solve, and rejects a
+    resource set with a missing handle, a side stream equal to the call's stream,
+    or one event used for both roles -- all before any HIP call."""
+    S = lib.sorf_solve_streamed
+    need = lib.sorf_solve_workspace_bytes(100)
+    E = _lib.SORF_ERR_INVALID_ARG
+    ok = _lib.SorfSolveStreams(0x1000, 0x2000, 0x3000)
+    args = (100, PTR, PTR, 1e-3, 3, PTR, PTR, 256, need)
+    assert S(0, PTR, PTR, 1e-3, 3, PTR, PTR, 256, need, ctypes.byref(ok), None) == E
+    assert S(*args[:7], 256, need - 1, ctypes.byref(ok), None) == _lib.SORF_ERR_WORKSPACE
+    for bad in (_lib.SorfSolveStreams(None, 0x2000, 0x3000),
+                _lib.SorfSolveStreams(0x1000, None, 0x3000),
+                _lib.SorfSolveStreams(0x1000, 0x2000, None),
+                _lib.SorfSolveStreams(0x1000, 0x2000, 0x2000)):
+        assert S(*args, ctypes.byref(bad), None) == E
+        assert lib.sorf_solve_f64_streamed(*args, ctypes.byref(bad), None) == E
+    # the side stream may not be the call's stream
+    assert S(*args, ctypes.byref(ok), 0x1000) == E
+    assert lib.sorf_solve_streams_create(None) == E
+    assert lib.sorf_solve_streams_destroy(None) == E
+
+
+def test_solve_streams_struct_layout(tmp_path):
+    src = tmp_path / "streams.c"
+    src.write_text(
+        '#include <stdio.h>\n#include <stddef.h>\n#include "sorf.h"\n'
+        "int main(void){\n"
+        'printf("%zu %zu %zu %zu\\n", sizeof(sorf_solve_streams), offsetof(sorf_solve_streams, side),'
+        " offsetof(sorf_solve_streams, event_fork), offsetof(sorf_solve_streams, event_join));\n"
+        "return 0;}\n")
+    exe = tmp_path / "streams"
+    subprocess.run(["gcc", "-std=c99", "-Wall", "-Werror", f"-I{ROOT}/include", str(src), "-o",
+                    str(exe)], check=True)
+    out = subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()
+    S = _lib.SorfSolveStreams
+    assert [int(v) for v in out] == [ctypes.sizeof(S), S.side.offset, S.event_fork.offset,
+                                     S.event_join.offset]
 
 
 def test_status_strings(lib):

@@ -453,6 +453,58 @@ def test_gram_emulated_error_ordering():
     assert err["bf16"] < 5e-3 and err["bf16_hilo"] < 5e-5
 
 
+def test_split_head_tail_definition():
+    """Split mode: e_f is the largest exponent with max|Z_f| 2^e_f <= 127 (checked
+    against the inequality for e_f and e_f + 1), the head is an integer of magnitude
+    <= 127 equal to the nearest integer of w = Z 2^e_f, the tail is w - h rounded to
+    fp16 (half-ulp bound 2^-13 for |w - h| <= 1/2), and an all-zero column has e = 0."""
+    rng = np.random.default_rng(12)
+    Z = (rng.standard_normal((300, 40)) * np.exp(rng.uniform(-8, 3, 40))[None, :]).astype(np.float32)
+    Z[:, 7] = 0.0
+    Z[5, 9] = -Z[:, 9].__abs__().max() * 1.0001     # negative column maximum
+    h, t, e = O.split_head_tail(Z)
+    m = np.abs(Z).max(axis=0).astype(np.float64)
+    for f in range(Z.shape[1]):
+        if m[f] == 0:
+            assert e[f] == 0 and not h[:, f].any() and not t[:, f].any()
+            continue
+        assert m[f] * 2.0 ** e[f] <= 127.0 < m[f] * 2.0 ** (e[f] + 1)
+    w = Z.astype(np.float64) * 2.0 ** e[None, :]
+    assert np.array_equal(h, np.round(h)) and np.abs(h).max() <= 127
+    assert np.abs(w - h).max() <= 0.5
+    assert np.abs(w - (h + t)).max() <= 2.0 ** -13
+    # t is exactly representable in fp16 and is the nearest such value
+    assert np.array_equal(t, t.astype(np.float16).astype(np.float64))
+    # a column that holds small integers times a power of two splits with no tail
+    Zi = (rng.integers(-127, 128, size=(64, 3)) * 2.0 ** -9).astype(np.float32)
+    Zi[0] = [127 * 2.0 ** -9, -127 * 2.0 ** -9, 64 * 2.0 ** -9]
+    hi, ti, ei = O.split_head_tail(Zi)
+    assert list(ei) == [9, 9, 9] and not ti.any()
+    assert np.array_equal(hi * 2.0 ** -9, Zi.astype(np.float64))
+
+
+def test_split_gram_is_the_gram_of_the_split_and_within_its_bound():
+    """G_split = V^T V with V = 2^-e (h + t) (positive semidefinite), and every entry
+    differs from the FP64 Z^T Z by at most sum_m (|z_i| d_j + d_i |z_j| + d_i d_j),
+    d_f = 2^-13 2^-e_f the per-entry representation bound."""
+    rng = np.random.default_rng(13)
+    Z = (rng.standard_normal((500, 30)) * 0.04).astype(np.float32)
+    G = O.gram_emulated(Z, "split")
+    h, t, e = O.split_head_tail(Z)
+    V = (h + t) * 2.0 ** -e[None, :]
+    assert np.abs(G - V.T @ V).max() <= 1e-15 * np.abs(G).max()
+    assert np.linalg.eigvalsh(G).min() >= -1e-12 * np.abs(G).max()
+    Zd = Z.astype(np.float64)
+    d = 2.0 ** -13 * 2.0 ** -e.astype(np.float64)
+    A = np.abs(Zd)
+    bound = A.T @ (np.ones_like(Zd) * d) + (np.ones_like(Zd) * d).T @ A + len(Zd) * np.outer(d, d)
+    err = np.abs(G - Zd.T @ Zd)
+    assert (err <= bound + 1e-15 * np.abs(G).max()).all()
+    # a two-part representation: far more accurate than one 16-bit product
+    exact = Zd.T @ Zd
+    assert np.linalg.norm(G - exact) < np.linalg.norm(O.gram_emulated(Z, "fp16", 10) - exact) / 50
+
+
 def test_feature_column_subset_is_a_column_slice():
     """Forming only some feature columns keeps the sqrt(2/D) of the full map
     and equals the matching columns of the full rows."""
