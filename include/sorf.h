@@ -353,7 +353,10 @@ sorf_status sorf_solve_f64_streamed(int32_t D, const double* G, const double* Zt
 size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, int64_t n_mols);
 
 /* Prediction of energies (E = Z alpha, without forming Z) and, when J is given,
- * forces F = -sum_{i in m} J_i^T dE/dx_i.
+ * forces F = -sum_{i in m} J_i^T dE/dx_i (RFF subsection: the atomic energy
+ * decomposition E = sum_I alpha^T z(rho_I) = Z alpha, and forces as minus the coordinate
+ * derivative of the energy, taken through the representations' Jacobians; Timings
+ * subsection: energies and forces of many configurations predicted in one call).
  *   alpha: [D] FP32.  E: [n_mols] FP32 out.
  *   J: concatenated per-molecule blocks, block m is [N_m][d][3 N_m] row-major
  *      (J_i = dx_i/dr_m, coordinates ordered [atom][xyz]) starting at float offset

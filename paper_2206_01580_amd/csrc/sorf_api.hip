@@ -381,9 +381,12 @@ size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, in
   return predict_ws(model, n_atoms, n_mols);
 }
 
-sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const float* alpha,
-                         const float* J, const int64_t* J_ptr, float* E, float* F,
-                         void* workspace, size_t workspace_bytes, sorf_stream_t stream) {
+}  // extern "C"
+
+namespace {
+
+sorf_status check_predict(const sorf_model* model, const sorf_batch* batch, const float* alpha,
+                          const float* J, const int64_t* J_ptr, const float* E, const float* F) {
   sorf_status s = check_model(model);
   if (s != SORF_OK) return s;
   if ((s = check_batch(batch)) != SORF_OK) return s;
@@ -392,12 +395,15 @@ sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const
   if (batch->n_mols > 0 && E == nullptr) return SORF_ERR_INVALID_ARG;
   if (batch->n_atoms > 0 && alpha == nullptr) return SORF_ERR_INVALID_ARG;
   if (!aligned16(alpha)) return SORF_ERR_INVALID_ARG;
+  return SORF_OK;
+}
+
+// The launches of sorf_predict on a checked batch and a workspace of at least
+// predict_ws() bytes, 256-byte aligned.
+sorf_status predict_launch(const sorf_model* model, const sorf_batch* batch, const float* alpha,
+                           const float* J, const int64_t* J_ptr, float* E, float* F,
+                           void* workspace, hipStream_t st) {
   const size_t need = predict_ws(model, batch->n_atoms, batch->n_mols);
-  if (batch->n_atoms > 0) {
-    if (workspace == nullptr || workspace_bytes < need) return SORF_ERR_WORKSPACE;
-    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
-  }
-  hipStream_t st = hipStream_t(stream);
   const SorfFeatureArgs a = pack(model, batch);
   if (J == nullptr) {
     // energies only: per (molecule, stack) partials, summed in stack order
@@ -415,6 +421,23 @@ sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const
   hipError_t e = sorf_launch_atom_adjoint(a, alpha, nullptr, J ? grad : nullptr, e_atom, st);
   if (e != hipSuccess) return SORF_ERR_DEVICE;
   return dev(sorf_launch_molecule_reduce(a, e_atom, grad, J, J_ptr, E, F, plan, st));
+}
+
+}  // namespace
+
+extern "C" {
+
+sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const float* alpha,
+                         const float* J, const int64_t* J_ptr, float* E, float* F,
+                         void* workspace, size_t workspace_bytes, sorf_stream_t stream) {
+  sorf_status s = check_predict(model, batch, alpha, J, J_ptr, E, F);
+  if (s != SORF_OK) return s;
+  const size_t need = predict_ws(model, batch->n_atoms, batch->n_mols);
+  if (batch->n_atoms > 0) {
+    if (workspace == nullptr || workspace_bytes < need) return SORF_ERR_WORKSPACE;
+    if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  }
+  return predict_launch(model, batch, alpha, J, J_ptr, E, F, workspace, hipStream_t(stream));
 }
 
 size_t sorf_forces_workspace_bytes(int64_t n_atoms, int64_t n_mols) {

@@ -19,10 +19,14 @@
 // summation in the spirit of the paper's compensated sum); this also cuts
 // the FP32 mode's error by an order of magnitude.
 //
-// Work split. One workgroup (4 waves, 2 x 2) per 256 x 128 tile (I, J) of the
-// lower triangle; each wave owns 128 x 64 = 4 x 2 MFMA 32x32 blocks. Tiles
-// are numbered row by row and dealt to the 8 XCDs in contiguous runs, so
-// the tiles running together on one XCD share the A panel in its L2.
+// Work split. FP32 modes: one workgroup (4 waves, 2 x 2, one per SIMD) per
+// 256 x 128 tile (I, J) of the lower triangle, each wave 128 x 64 (4 x 2 MFMA
+// 32x32 blocks). hi+lo modes (and the split mode's tail): 8 waves (4 x 2, two
+// per SIMD) per 256 x 128 tile, each wave 64 x 64 (2 x 2 blocks). Single
+// product modes (and the split mode's int8 head): 8 waves (2 x 4) per 256 x 256
+// tile, each wave 128 x 64. The 256 x 128 tiles are dealt to the XCDs in
+// super-tiles of 4 x 8 tiles, so the tiles running together on one XCD share
+// their A and B panels in its L2.
 // The 16-bit modes first pack Z once into MFMA fragment order (one 1 KB
 // fragment per 16 rows x 32 columns: lane l holds rows 8(l/32)..8(l/32)+7 of
 // column l%32), so the Gram kernel streams contiguous fragments through LDS
