@@ -58,6 +58,7 @@ constexpr int KB = 16;                 // rows per fragment / FP32 stage
 constexpr int TM = 256, TN = 128;      // workgroup tile
 constexpr int kFlushRows = 256;        // rows per fresh MFMA accumulator
 constexpr int kPackSlabs = 64;         // 16-row slabs per pack workgroup (Z^T y chunk)
+constexpr int kFP32Waves = 8;          // waves of the FP32 ring kernel (4 or 8)
 
 __host__ __device__ constexpr bool is_hilo(int mode) {
   return mode == kBF16HiLo || mode == kFP16HiLo || mode == kSplitCross;
@@ -931,13 +932,13 @@ static int64_t x1_grid(const X1Plan& p) {
 // running FP32 sum S. With KAHAN (the paper's FP32 training mode) the flush is
 // compensated: the rounding error of each S += P is carried in C and
 // subtracted from the next block (y = P - C; t = S + y; C = (t - S) - y; S = t).
-template <bool KAHAN, int NA>
-__device__ __forceinline__ void flush_sum(f32x16 (&P)[4][2], f32x16 (&S)[4][2],
-                                          f32x16 (&C)[NA][2]) {
+template <bool KAHAN, int BA, int BB, int NA>
+__device__ __forceinline__ void flush_sum(f32x16 (&P)[BA][BB], f32x16 (&S)[BA][BB],
+                                          f32x16 (&C)[NA][BB]) {
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < BA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         if constexpr (KAHAN) {
@@ -957,14 +958,20 @@ __device__ __forceinline__ void flush_sum(f32x16 (&P)[4][2], f32x16 (&S)[4][2],
 // rows of 128 floats (one copy per pair of rows), in a ring of 4 stages.
 // Rows past M are copied from a 1 KB block of zeros; columns past D are
 // clamped into the row (they only reach G entries that are never written).
-template <bool KAHAN>
-__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(1, 1)))
+// NW = 8 (used): eight waves (4 x 2, two per SIMD) of 64 x 64, so that while
+// one wave of a SIMD waits on the stage barrier or its LDS reads the other
+// keeps the matrix core busy; the Kahan mode then spills 6 registers (47 with
+// NW = 4: four waves, one per SIMD, of 128 x 64).
+template <bool KAHAN, int NW>
+__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
                            int64_t nI, int64_t nJ, const float* __restrict__ zeros,
                            float* __restrict__ G) {
   constexpr int NS = 4;
-  constexpr int PW = 6;                        // copies per wave per stage (24 / 4)
+  constexpr int PW = 24 / NW;                  // copies per wave per stage (16 A + 8 B pairs)
   constexpr int KC = kFlushRows / KB;
+  constexpr int WR = TM / (NW / 2), WC = TN / 2;   // wave tile
+  constexpr int BA = WR / 32, BB = WC / 32;
   __shared__ float ra[NS][KB][TM];
   __shared__ float rb[NS][KB][TN];
 
@@ -975,36 +982,36 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int wy = wv >> 1, wx = wv & 1;
-  const bool active = I * TM + wy * 128 + 127 >= J * TN + wx * 64;
+  const bool active = I * TM + wy * WR + WR - 1 >= J * TN + wx * WC;
   const int64_t A0 = I * TM, B0 = J * TN;
   const int64_t colA = (A0 + 4 * lane < D - 4 ? A0 + 4 * lane : D - 4);
   const int64_t colB = (B0 + 4 * (lane & 31) < D - 4 ? B0 + 4 * (lane & 31) : D - 4);
   const int64_t n_st = (M + KB - 1) / KB;
-  // wave w copies A rows w, w+4, w+8, w+12 and B row pairs (2w, 2w+1), (2w+8, 2w+9)
+  // copy c of a stage (c = wv + NW i): c < 16 is A row c, else B rows 2 (c - 16) + (0, 1)
   auto issue = [&](int64_t st, int slot) {
     const int64_t m0 = st * KB;
 #pragma unroll
-    for (int c = 0; c < 4; ++c) {
-      const int k = wv + 4 * c;
-      const int64_t m = m0 + k;
-      const float* g = m < M ? Z + m * D + colA : zeros + 4 * lane;
-      dma16(g, &ra[slot][k][0]);
-    }
-#pragma unroll
-    for (int c = 0; c < 2; ++c) {
-      const int k = 2 * wv + 8 * c + (lane >> 5);
-      const int64_t m = m0 + k;
-      const float* g = m < M ? Z + m * D + colB : zeros + 4 * lane;
-      dma16(g, &rb[slot][2 * wv + 8 * c][0]);
+    for (int i = 0; i < PW; ++i) {
+      const int c = wv + NW * i;
+      if (c < KB) {
+        const int64_t m = m0 + c;
+        const float* g = m < M ? Z + m * D + colA : zeros + 4 * lane;
+        dma16(g, &ra[slot][c][0]);
+      } else {
+        const int k = 2 * (c - KB) + (lane >> 5);
+        const int64_t m = m0 + k;
+        const float* g = m < M ? Z + m * D + colB : zeros + 4 * lane;
+        dma16(g, &rb[slot][2 * (c - KB)][0]);
+      }
     }
   };
 
-  f32x16 P[4][2], S[4][2];
-  f32x16 Cc[KAHAN ? 4 : 1][2];   // Kahan compensation of S (mode 5 only)
+  f32x16 P[BA][BB], S[BA][BB];
+  f32x16 Cc[KAHAN ? BA : 1][BB];   // Kahan compensation of S (mode 5 only)
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < BA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
         P[a][b][r] = 0.0f;
@@ -1024,22 +1031,22 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
       wait_stage<PW>(left < NS - 2 ? left : NS - 2);
       stage_barrier();
       if (s + NS - 1 < n_st) issue(s + NS - 1, slot == 0 ? NS - 1 : slot - 1);
-      float af[KB / 2][4], bf[KB / 2][2];
+      float af[KB / 2][BA], bf[KB / 2][BB];
 #pragma unroll
       for (int kk = 0; kk < KB / 2; ++kk) {
         const int k = 2 * kk + (lane >> 5);
 #pragma unroll
-        for (int a = 0; a < 4; ++a) af[kk][a] = ra[slot][k][wy * 128 + a * 32 + (lane & 31)];
+        for (int a = 0; a < BA; ++a) af[kk][a] = ra[slot][k][wy * WR + a * 32 + (lane & 31)];
 #pragma unroll
-        for (int b = 0; b < 2; ++b) bf[kk][b] = rb[slot][k][wx * 64 + b * 32 + (lane & 31)];
+        for (int b = 0; b < BB; ++b) bf[kk][b] = rb[slot][k][wx * WC + b * 32 + (lane & 31)];
       }
       __builtin_amdgcn_sched_barrier(0);
 #pragma unroll
       for (int kk = 0; kk < KB / 2; ++kk)
 #pragma unroll
-        for (int a = 0; a < 4; ++a)
+        for (int a = 0; a < BA; ++a)
 #pragma unroll
-          for (int b = 0; b < 2; ++b)
+          for (int b = 0; b < BB; ++b)
             P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][a], bf[kk][b], P[a][b], 0, 0, 0);
       slot = slot + 1 == NS ? 0 : slot + 1;
     }
@@ -1048,13 +1055,13 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
 
   if (!active) return;
 #pragma unroll
-  for (int a = 0; a < 4; ++a)
+  for (int a = 0; a < BA; ++a)
 #pragma unroll
-    for (int b = 0; b < 2; ++b)
+    for (int b = 0; b < BB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int64_t gi = A0 + wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t gj = B0 + wx * 64 + b * 32 + (lane & 31);
+        const int64_t gi = A0 + wy * WR + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int64_t gj = B0 + wx * WC + b * 32 + (lane & 31);
         if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += S[a][b][r];
       }
 }
@@ -1381,11 +1388,11 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
             hipSuccess)
           return e;
         if (mode == kFP32Kahan)
-          hipLaunchKernelGGL(gram_fp32_ring_kernel<true>, grid, blk, 0, st, Z, n_rows, D, n_tiles,
-                             nI, nJ, zeros, G);
+          hipLaunchKernelGGL((gram_fp32_ring_kernel<true, kFP32Waves>), grid,
+                             dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G);
         else
-          hipLaunchKernelGGL(gram_fp32_ring_kernel<false>, grid, blk, 0, st, Z, n_rows, D, n_tiles,
-                             nI, nJ, zeros, G);
+          hipLaunchKernelGGL((gram_fp32_ring_kernel<false, kFP32Waves>), grid,
+                             dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G);
       } else if (mode == kFP32Kahan) {
         hipLaunchKernelGGL((gram_fp32_kernel<false, true>), grid, blk, 0, st, Z, n_rows, D,
                            n_tiles, nI, nJ, G);
