@@ -93,7 +93,7 @@ def parse():
     ap.add_argument("--lam", type=float, default=1e-6)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample-mols", type=int, default=64)
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
+    ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the Poisson request trace (0 skips the serving leg)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-slots", type=int, default=4)
@@ -153,7 +153,7 @@ def serving_leg(args, dev, log, rate, seconds):
     sp = serve.PlainRunner(exp).run(tr.arrival_s, tr.sizes)
     torch.cuda.synchronize()
     log("serving: plain done")
-    warm = 0.1 * seconds
+    warm = min(1.0, 0.1 * seconds)       # the first second of the trace is warm-up
     b, p = sb.summary(warm, tr.arrival_s), sp.summary(warm, tr.arrival_s)
     del pool, J, exb, exp
     torch.cuda.empty_cache()

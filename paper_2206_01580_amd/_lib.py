@@ -98,6 +98,15 @@ def load() -> ctypes.CDLL:
         raise RuntimeError(
             f"{LIB_PATH} is missing: build the HIP library first "
             "(python -m paper_2206_01580_amd.build); there is no CPU fallback")
+    # PyTorch ships its own HIP runtime (torch/lib/libamdhip64.so, soname
+    # libamdhip64.so.7). Loaded first, it is the runtime this library binds to.
+    # Loaded after this library, torch would bring in a second runtime beside
+    # /opt/rocm's, and streams handed from one to the other make every launch
+    # fail. So torch, when installed, is imported before the library is opened.
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     lib = ctypes.CDLL(LIB_PATH)
     P = ctypes.c_void_p
     i32, i64, f64, sz = ctypes.c_int32, ctypes.c_int64, ctypes.c_double, ctypes.c_size_t

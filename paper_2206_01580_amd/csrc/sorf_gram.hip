@@ -120,11 +120,11 @@ __host__ __device__ inline int64_t gram_super_tiles(int64_t D) {
   return nS * (nS + 1) / 2;
 }
 
-__device__ __forceinline__ bool super_tile(int64_t D, int64_t nI, int64_t nJ, int64_t& I,
-                                           int64_t& J) {
+__device__ __forceinline__ bool super_tile(int64_t b, int64_t D, int64_t nI, int64_t nJ,
+                                           int64_t& I, int64_t& J) {
   const int64_t nS = (D + SR_T * TM - 1) / (SR_T * TM);
-  const int64_t q = blockIdx.x / 8;
-  const int64_t G = (q / (SR_T * SC_T)) * 8 + blockIdx.x % 8;
+  const int64_t q = b / 8;
+  const int64_t G = (q / (SR_T * SC_T)) * 8 + b % 8;
   const int pos = int(q % (SR_T * SC_T));
   const int64_t off = nS * (nS - 1) / 2;
   int64_t R, C;
@@ -143,6 +143,27 @@ __device__ __forceinline__ bool super_tile(int64_t D, int64_t nI, int64_t nJ, in
   J = C * SC_T + pos % SC_T;
   return I < nI && J < nJ && J * TN <= I * TM + TM - 1;
 }
+
+// Row slices of the 256 x 128 tile kernels. One workgroup fills a compute
+// unit, so a launch of n_tiles tiles runs in ceil(n_tiles / 256) rounds; at
+// D = 8192 (1056 tiles) the fifth round holds 32 tiles and a fifth of the
+// launch leaves most of the chip idle. Splitting the rows of every tile into
+// n_split slices makes n_split * n_tiles shorter items (8448 at D = 8192, 33
+// whole rounds). Slice sp covers rows [sp * rows_per, (sp + 1) * rows_per) and
+// is dealt blocks [sp * grid1, (sp + 1) * grid1), each slice in the super-tile
+// order, so the slices run one after another and neighbouring tiles of one
+// slice share their panels in an XCD's L2. With n_split > 1 each item writes
+// its 256 x 128 sum to a partial tile and gram_slices_combine_kernel adds the
+// n_split partials of every entry into G in slice order (deterministic).
+struct SlicePlan {
+  int32_t n_split;    // row slices per tile (1: items add into G themselves)
+  int64_t rows_per;   // rows per slice, a multiple of the flush block
+  int64_t grid1;      // blocks per slice
+};
+
+// Index of lower-triangle tile (I, J) of 256 x 128 tiles: row I holds
+// J = 0 .. 2 I + 1, so the rows before it hold I (I + 1) tiles.
+__host__ __device__ inline int64_t tile_index(int64_t I, int64_t J) { return I * (I + 1) + J; }
 
 // ------------------------------------------------------------------- packing
 // Fragment (ks, cb) -> u16x8 index ((ks * ncb + cb) * 64 + lane).
@@ -465,7 +486,7 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
   __shared__ u16x8 ring[NS][NP][NF][64];
 
   int64_t I, J;
-  if (!super_tile(D, nI, nJ, I, J)) return;
+  if (!super_tile(blockIdx.x, D, nI, nJ, I, J)) return;
   (void)n_tiles;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -645,12 +666,43 @@ __host__ __device__ inline int64_t x1_tiles(int64_t D) {
   return n * (n + 1) / 2;
 }
 
-__device__ __forceinline__ void x1_tile_of(int64_t t, int64_t& I, int64_t& J) {
-  int64_t i = int64_t((std::sqrt(8.0 * double(t) + 1.0) - 1.0) * 0.5);
-  while (i * (i + 1) / 2 > t) --i;
-  while ((i + 1) * (i + 2) / 2 <= t) ++i;
-  I = i;
-  J = t - i * (i + 1) / 2;
+// Order of the tiles (I, J), J <= I, of the n x n tile grid: bands of 4 tile
+// rows; in band b first the 8-column blocks that lie wholly below the band's
+// diagonal (b / 2 of them, 32 tiles each, row-major inside), then the band's
+// remaining tiles row by row; the last band, when n is not a multiple of 4,
+// row by row. Consecutive tiles, which run together on one XCD, then form 4 x 8
+// blocks that read 4 + 8 column panels of Z through that XCD's L2 (row-major
+// order: a run of 32 tiles of one or two rows reads about 33).
+// Band b holds 16 b + 10 tiles, so 8 b^2 + 2 b tiles precede it.
+__device__ __forceinline__ void x1_tile_of(int64_t t, int64_t n, int64_t& I, int64_t& J) {
+  const int64_t nfull = n / 4;
+  const int64_t base = 8 * nfull * nfull + 2 * nfull;
+  int64_t u, r, c0;
+  if (t >= base) {   // last, partial band
+    u = t - base;
+    r = 4 * nfull;
+    c0 = 0;
+  } else {
+    int64_t b = int64_t((std::sqrt(4.0 + 32.0 * double(t)) - 2.0) / 16.0);
+    while (8 * b * b + 2 * b > t) --b;
+    while (8 * (b + 1) * (b + 1) + 2 * (b + 1) <= t) ++b;
+    u = t - (8 * b * b + 2 * b);
+    const int64_t nf = b / 2;   // whole 8-column blocks below the band's diagonal
+    if (u < 32 * nf) {
+      I = 4 * b + (u % 32) / 8;
+      J = 8 * (u / 32) + u % 8;
+      return;
+    }
+    u -= 32 * nf;
+    r = 4 * b;
+    c0 = 8 * nf;
+  }
+  while (u >= r - c0 + 1) {   // rows of the remaining region, columns c0 .. r
+    u -= r - c0 + 1;
+    ++r;
+  }
+  I = r;
+  J = c0 + u;
 }
 
 struct X1Plan {
@@ -700,7 +752,7 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   const int sp = whole ? 0 : int(piece / n_tail);
   const int n_split = whole ? 1 : plan.n_split;
   int64_t I, J;
-  x1_tile_of(t, I, J);
+  x1_tile_of(t, (D + TX - 1) / TX, I, J);
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
@@ -841,7 +893,7 @@ __global__ __launch_bounds__(256) void gram_combine_kernel(const float* __restri
   const int64_t n_tail = plan.n_tiles - plan.n_whole;
   const int64_t tt = blockIdx.x;
   int64_t I, J;
-  x1_tile_of(plan.n_whole + tt, I, J);
+  x1_tile_of(plan.n_whole + tt, (D + TX - 1) / TX, I, J);
   const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int j = (threadIdx.x & 63) * 4;
   const int64_t gi = I * TX + i;
@@ -872,7 +924,7 @@ __global__ __launch_bounds__(256) void gram_combine_head_kernel(const int32_t* _
   const int64_t n_tail = plan.n_tiles - plan.n_whole;
   const int64_t tt = blockIdx.x;
   int64_t I, J;
-  x1_tile_of(plan.n_whole + tt, I, J);
+  x1_tile_of(plan.n_whole + tt, (D + TX - 1) / TX, I, J);
   const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
   const int j = (threadIdx.x & 63) * 4;
   const int64_t gi = I * TX + i;
@@ -966,7 +1018,7 @@ template <bool KAHAN, int NW>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
                            int64_t nI, int64_t nJ, const float* __restrict__ zeros,
-                           float* __restrict__ G) {
+                           float* __restrict__ G, SlicePlan plan, float* __restrict__ part) {
   constexpr int NS = 4;
   constexpr int PW = 24 / NW;                  // copies per wave per stage (16 A + 8 B pairs)
   constexpr int KC = kFlushRows / KB;
@@ -976,8 +1028,8 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
   __shared__ float rb[NS][KB][TN];
 
   int64_t I, J;
-  if (!super_tile(D, nI, nJ, I, J)) return;
-  (void)n_tiles;
+  const int64_t sp = blockIdx.x / plan.grid1;
+  if (!super_tile(blockIdx.x % plan.grid1, D, nI, nJ, I, J)) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
@@ -986,21 +1038,24 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
   const int64_t A0 = I * TM, B0 = J * TN;
   const int64_t colA = (A0 + 4 * lane < D - 4 ? A0 + 4 * lane : D - 4);
   const int64_t colB = (B0 + 4 * (lane & 31) < D - 4 ? B0 + 4 * (lane & 31) : D - 4);
-  const int64_t n_st = (M + KB - 1) / KB;
+  // this item's rows [r0, r1)
+  const int64_t r0 = sp * plan.rows_per;
+  const int64_t r1 = r0 + plan.rows_per < M ? r0 + plan.rows_per : M;
+  const int64_t n_st = r1 > r0 ? (r1 - r0 + KB - 1) / KB : 0;
   // copy c of a stage (c = wv + NW i): c < 16 is A row c, else B rows 2 (c - 16) + (0, 1)
   auto issue = [&](int64_t st, int slot) {
-    const int64_t m0 = st * KB;
+    const int64_t m0 = r0 + st * KB;
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
       const int c = wv + NW * i;
       if (c < KB) {
         const int64_t m = m0 + c;
-        const float* g = m < M ? Z + m * D + colA : zeros + 4 * lane;
+        const float* g = m < r1 ? Z + m * D + colA : zeros + 4 * lane;
         dma16(g, &ra[slot][c][0]);
       } else {
         const int k = 2 * (c - KB) + (lane >> 5);
         const int64_t m = m0 + k;
-        const float* g = m < M ? Z + m * D + colB : zeros + 4 * lane;
+        const float* g = m < r1 ? Z + m * D + colB : zeros + 4 * lane;
         dma16(g, &rb[slot][2 * (c - KB)][0]);
       }
     }
@@ -1019,41 +1074,96 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
         if (KAHAN) Cc[KAHAN ? a : 0][b][r] = 0.0f;
       }
 
+  // Software pipeline over half-stages (k steps 0..3 and 4..7 of a 16-row
+  // stage): the LDS reads of one half-stage are issued while the products of
+  // the previous one run, so the matrix core keeps working across the stage
+  // barrier. All NS slots are filled up front; after the barrier that
+  // publishes stage s + 1 every wave has read all of stage s, so its slot
+  // takes stage s + NS.
+  constexpr int HK = KB / 4;   // k steps (of 2 rows) per half-stage
+  float a0[HK][BA], b0[HK][BB], a1[HK][BA], b1[HK][BB];
+  auto read_half = [&](int sl, int h, float (&af)[HK][BA], float (&bf)[HK][BB]) {
 #pragma unroll
-  for (int j = 0; j < NS - 1; ++j)
+    for (int kk = 0; kk < HK; ++kk) {
+      const int k = 2 * (h * HK + kk) + (lane >> 5);
+#pragma unroll
+      for (int a = 0; a < BA; ++a) af[kk][a] = ra[sl][k][wy * WR + a * 32 + (lane & 31)];
+#pragma unroll
+      for (int b = 0; b < BB; ++b) bf[kk][b] = rb[sl][k][wx * WC + b * 32 + (lane & 31)];
+    }
+  };
+  auto mma_half = [&](const float (&af)[HK][BA], const float (&bf)[HK][BB]) {
+#pragma unroll
+    for (int kk = 0; kk < HK; ++kk)
+#pragma unroll
+      for (int a = 0; a < BA; ++a)
+#pragma unroll
+        for (int b = 0; b < BB; ++b)
+          P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][a], bf[kk][b], P[a][b], 0, 0, 0);
+  };
+  // the next half-stage's LDS reads interleaved with the first products
+  auto interleave = [] {
+    constexpr int NR = HK * (BA + BB), NM = HK * BA * BB;
+#pragma unroll
+    for (int i = 0; i < (NR < NM ? NR : NM); ++i) {
+      __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
+      __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
+    }
+    if constexpr (NM > NR) __builtin_amdgcn_sched_group_barrier(0x008, NM - NR, 0);
+    if constexpr (NR > NM) __builtin_amdgcn_sched_group_barrier(0x100, NR - NM, 0);
+  };
+
+#pragma unroll
+  for (int j = 0; j < NS; ++j)
     if (j < n_st) issue(j, j);
-  int64_t s = 0;
+  if (n_st > 0) {
+    wait_stage<PW>(n_st - 1 < NS - 1 ? n_st - 1 : NS - 1);
+    stage_barrier();
+    read_half(0, 0, a0, b0);
+  }
   int slot = 0;
+  int64_t s = 0;
   while (s < n_st) {
     const int64_t g_end = s + KC < n_st ? s + KC : n_st;
     for (; s < g_end; ++s) {
-      const int64_t left = n_st - 1 - s;
-      wait_stage<PW>(left < NS - 2 ? left : NS - 2);
-      stage_barrier();
-      if (s + NS - 1 < n_st) issue(s + NS - 1, slot == 0 ? NS - 1 : slot - 1);
-      float af[KB / 2][BA], bf[KB / 2][BB];
-#pragma unroll
-      for (int kk = 0; kk < KB / 2; ++kk) {
-        const int k = 2 * kk + (lane >> 5);
-#pragma unroll
-        for (int a = 0; a < BA; ++a) af[kk][a] = ra[slot][k][wy * WR + a * 32 + (lane & 31)];
-#pragma unroll
-        for (int b = 0; b < BB; ++b) bf[kk][b] = rb[slot][k][wx * WC + b * 32 + (lane & 31)];
+      read_half(slot, 1, a1, b1);
+      mma_half(a0, b0);
+      interleave();
+      const bool more = s + 1 < n_st;
+      const int nslot = more ? (slot + 1 == NS ? 0 : slot + 1) : slot;
+      if (more) {
+        const int64_t ahead = n_st - 2 - s;
+        wait_stage<PW>(ahead < NS - 2 ? ahead : NS - 2);
+        // this wave's reads of stage s have landed before its slot is reused
+        asm volatile("s_waitcnt lgkmcnt(0)" ::: "memory");
+        stage_barrier();
+        if (s + NS < n_st) issue(s + NS, slot);
       }
-      __builtin_amdgcn_sched_barrier(0);
-#pragma unroll
-      for (int kk = 0; kk < KB / 2; ++kk)
-#pragma unroll
-        for (int a = 0; a < BA; ++a)
-#pragma unroll
-          for (int b = 0; b < BB; ++b)
-            P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][a], bf[kk][b], P[a][b], 0, 0, 0);
-      slot = slot + 1 == NS ? 0 : slot + 1;
+      // after the last stage this re-reads a published slot with no copy in
+      // flight; the values are not used
+      read_half(nslot, 0, a0, b0);
+      mma_half(a1, b1);
+      interleave();
+      slot = nslot;
     }
     flush_sum<KAHAN>(P, S, Cc);
   }
 
   if (!active) return;
+  if (sp > 0) {
+    float* out = part + ((sp - 1) * n_tiles + tile_index(I, J)) * (TM * TN);
+#pragma unroll
+    for (int a = 0; a < BA; ++a)
+#pragma unroll
+      for (int b = 0; b < BB; ++b)
+#pragma unroll
+        for (int r = 0; r < 16; ++r) {
+          const int i = wy * WR + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int j = wx * WC + b * 32 + (lane & 31);
+          out[i * TN + j] = S[a][b][r];
+        }
+    return;
+  }
 #pragma unroll
   for (int a = 0; a < BA; ++a)
 #pragma unroll
@@ -1064,6 +1174,34 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
         const int64_t gj = B0 + wx * WC + b * 32 + (lane & 31);
         if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += S[a][b][r];
       }
+}
+
+// G += the partial tiles of slices 1 .. n_split - 1 of every 256 x 128 tile
+// (slice 0 added its sum into G itself), summed in slice order. One workgroup
+// per 4 rows of a tile, two columns per thread. Entries of waves above the
+// diagonal are never written to the partials; they are not read.
+__global__ __launch_bounds__(256) void gram_slices_combine_kernel(const float* __restrict__ part,
+                                                                 int64_t n_tiles, int32_t n_split,
+                                                                 int32_t D,
+                                                                 float* __restrict__ G) {
+  const int64_t t = blockIdx.x;
+  int64_t I = int64_t((std::sqrt(4.0 * double(t) + 1.0) - 1.0) * 0.5);
+  while (I * (I + 1) > t) --I;
+  while ((I + 1) * (I + 2) <= t) ++I;
+  const int64_t J = t - I * (I + 1);
+  const int i = blockIdx.y * 4 + (threadIdx.x >> 6);
+  const int j = (threadIdx.x & 63) * 2;
+  const int64_t gi = I * TM + i, gj = J * TN + j;
+  if (gi >= D || gj > gi) return;
+  float2 acc = make_float2(0.0f, 0.0f);
+  for (int sp = 1; sp < n_split; ++sp) {
+    const float2 v = *reinterpret_cast<const float2*>(
+        part + (int64_t(sp - 1) * n_tiles + t) * (TM * TN) + int64_t(i) * TN + j);
+    acc.x += v.x;
+    acc.y += v.y;
+  }
+  G[gi * D + gj] += acc.x;
+  if (gj + 1 < D && gj + 1 <= gi) G[gi * D + gj + 1] += acc.y;
 }
 
 // ------------------------------------------------ FP32 mode, any D
@@ -1082,7 +1220,7 @@ void gram_fp32_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t
   __shared__ float sB[2][KB][LDB];
 
   int64_t I, J;
-  if (!super_tile(D, nI, nJ, I, J)) return;
+  if (!super_tile(blockIdx.x, D, nI, nJ, I, J)) return;
   (void)n_tiles;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
@@ -1323,10 +1461,46 @@ size_t x1_partial_bytes(int64_t n_rows, int32_t D) {
   return al256(b);
 }
 
+// Row-slice plan of the FP32 tile kernel: the slice count in 1..8 with the
+// least estimated time, counted in rounds of 256 items (one per compute unit,
+// each a slice of one tile at the FP32 matrix-core rate) plus the partial
+// tiles' HBM traffic (written once, read once, at 5 TB/s). Ties: fewer
+// slices. Slices keep at least 2048 rows; the partials stay within 4 GB.
+static SlicePlan slice_plan(int64_t M, int32_t D) {
+  int64_t nI, nJ;
+  const int64_t T = gram_tiles(D, nI, nJ);
+  const int64_t grid1 = ((gram_super_tiles(D) + 7) / 8) * 8 * SR_T * SC_T;
+  const double tile_s = 2.0 * TM * TN * double(M) / (157.3e12 / kX1Slots);   // whole tile
+  const double part_s = double(TM * TN * sizeof(float)) * 2.0 / 5e12;       // per partial tile
+  SlicePlan best{1, M, grid1};
+  double best_cost = double((T + kX1Slots - 1) / kX1Slots) * tile_s;
+  for (int s = 2; s <= 8; ++s) {
+    const int64_t rows = ((M + s - 1) / s + kFlushRows - 1) / kFlushRows * kFlushRows;
+    const int64_t n = (M + rows - 1) / rows;
+    if (rows < 2048 || size_t(n - 1) * size_t(T) * TM * TN * sizeof(float) > (size_t(4) << 30))
+      break;
+    const double cost = double((T * n + kX1Slots - 1) / kX1Slots) * tile_s * double(rows) / double(M) +
+                        double((n - 1) * T) * part_s;
+    if (cost < best_cost - 1e-9) {
+      best_cost = cost;
+      best = SlicePlan{int32_t(n), rows, grid1};
+    }
+  }
+  return best;
+}
+
+static size_t slice_partial_bytes(int64_t M, int32_t D) {
+  const SlicePlan p = slice_plan(M, D);
+  if (p.n_split <= 1) return 0;
+  int64_t nI, nJ;
+  return al256(size_t(p.n_split - 1) * size_t(gram_tiles(D, nI, nJ)) * TM * TN * sizeof(float));
+}
+
 size_t sorf_gram_ws_bytes(int64_t n_rows, int32_t D, int mode) {
   if (n_rows <= 0 || D <= 0) return 0;
   const GramLayout g = gram_layout(n_rows, D);
   size_t b = g.zpart_bytes + kZeroBytes;
+  if ((mode == kFP32 || mode == kFP32Kahan) && D % 4 == 0) b += slice_partial_bytes(n_rows, D);
   if (mode != kFP32 && mode != kFP32Kahan) b += g.part_bytes * (is_hilo(mode) ? 2 : 1);
   if (mode == kBF16 || mode == kFP16) b += x1_partial_bytes(n_rows, D);
   return b;
@@ -1387,12 +1561,21 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
         if ((e = sorf_launch_fill(zeros, int64_t(kZeroBytes / sizeof(float)), 0.0f, st)) !=
             hipSuccess)
           return e;
+        const SlicePlan plan = slice_plan(n_rows, D);
+        float* part = reinterpret_cast<float*>(w + g.zpart_bytes + kZeroBytes);
+        const dim3 rgrid{unsigned(plan.grid1 * plan.n_split)};
         if (mode == kFP32Kahan)
-          hipLaunchKernelGGL((gram_fp32_ring_kernel<true, kFP32Waves>), grid,
-                             dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G);
+          hipLaunchKernelGGL((gram_fp32_ring_kernel<true, kFP32Waves>), rgrid,
+                             dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G,
+                             plan, part);
         else
-          hipLaunchKernelGGL((gram_fp32_ring_kernel<false, kFP32Waves>), grid,
-                             dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G);
+          hipLaunchKernelGGL((gram_fp32_ring_kernel<false, kFP32Waves>), rgrid,
+                             dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G,
+                             plan, part);
+        if ((e = hipGetLastError()) != hipSuccess) return e;
+        if (plan.n_split > 1)
+          hipLaunchKernelGGL(gram_slices_combine_kernel, dim3(unsigned(n_tiles), unsigned(TM / 4)),
+                             blk, 0, st, part, n_tiles, plan.n_split, D, G);
       } else if (mode == kFP32Kahan) {
         hipLaunchKernelGGL((gram_fp32_kernel<false, true>), grid, blk, 0, st, Z, n_rows, D,
                            n_tiles, nI, nJ, G);

@@ -39,6 +39,9 @@ class ServeStats:
     wall_s: float                  # trace start to last completion
     atoms: int
     rejected: List[int]            # requests that can never fit the budget
+    inflight_at_launch: List[int] = dataclasses.field(default_factory=list)
+    # batches already on the device when each launch was made (continuous
+    # batching admits new work while earlier batches run)
 
     def summary(self, warmup_s: float = 0.0, arrivals: Optional[np.ndarray] = None) -> dict:
         lat = self.latency_s
@@ -55,6 +58,7 @@ class ServeStats:
             "launches": len(self.batches),
             "mean_batch_requests": float(np.mean([b - a for a, b in self.batches])) if self.batches else 0.0,
             "rejected": len(self.rejected),
+            "launches_beside_inflight": int(sum(1 for c in self.inflight_at_launch if c > 0)),
         }
 
 
@@ -82,7 +86,7 @@ class BatchingScheduler:
         pending = collections.deque()
         inflight = collections.deque()       # (handle, first, last, bytes)
         used = 0
-        batches, rejected = [], []
+        batches, rejected, beside = [], [], []
         nxt = 0
         t0 = self.clock()
         finished = 0
@@ -125,6 +129,7 @@ class BatchingScheduler:
                     last += 1
                 if last > first:
                     nbytes = self.ex.bytes_for(first, last)
+                    beside.append(len(inflight))
                     h = self.ex.submit(first, last)
                     inflight.append((h, first, last, nbytes))
                     used += nbytes
@@ -135,7 +140,7 @@ class BatchingScheduler:
         wall = np.nanmax(completion[np.isfinite(completion)]) if np.isfinite(completion).any() else 0.0
         lat = completion - arrivals
         done_atoms = int(sizes[np.isfinite(completion)].sum())
-        return ServeStats(lat, completion, batches, float(wall), done_atoms, rejected)
+        return ServeStats(lat, completion, batches, float(wall), done_atoms, rejected, beside)
 
 
 class PlainRunner:

@@ -478,6 +478,37 @@ def test_gram_fp64(MD):
     assert np.abs(Zty.cpu().numpy() - ro).max() <= 1e-13 * np.abs(ro).max()
 
 
+@pytest.mark.parametrize("mode", ["fp32", "fp32_kahan"])
+@pytest.mark.parametrize("MD", [(20001, 256), (4100, 1000), (9000, 1536)],
+                         ids=lambda t: f"M{t[0]}-D{t[1]}")
+def test_gram_fp32_row_slices(mode, MD):
+    """Row counts at which the FP32 tile kernel splits every tile's rows into
+    slices (8 slices of 2560 rows with a last one of 2081; 2 with a ragged 1796;
+    5 with a last one of 808; D = 1000 also ends in a partial tile): slice 0 adds
+    into G, the others go through partial tiles combined in slice order. G
+    accumulates onto existing values, the upper triangle stays untouched, and the
+    result is within the FP32 bound of the FP64 Gram and bitwise repeatable."""
+    M, D = MD
+    rng = np.random.default_rng(3 * M + D)
+    Z = (rng.standard_normal((M, D)) * 0.05).astype(np.float32)
+    G0 = rng.standard_normal((D, D)).astype(np.float32)
+    Zt = torch.from_numpy(Z).cuda()
+    outs = []
+    for _ in range(2):
+        Gt = torch.from_numpy(G0.copy()).cuda()
+        S().gram_accumulate(Zt, Gt, precision=mode)
+        outs.append(Gt)
+    torch.cuda.synchronize()
+    assert torch.equal(outs[0], outs[1])
+    Gg = outs[0].cpu().numpy().astype(np.float64)
+    upper = np.triu_indices(D, 1)
+    assert np.array_equal(Gg[upper], G0[upper].astype(np.float64)), "upper triangle touched"
+    Ge = O.gram_emulated(Z, mode, 0)
+    low = np.tril_indices(D)
+    diff = (Gg - G0.astype(np.float64))[low] - Ge[low]
+    assert np.linalg.norm(diff) <= 1e-6 * np.linalg.norm(Ge[low]) + 1e-6 * np.linalg.norm(G0)
+
+
 @pytest.mark.parametrize("mode", ["bf16", "fp16"])
 def test_gram_single_product_whole_and_sliced_tiles(mode):
     # D = 5900: 300 tiles of 256 x 256, so one whole round of 256 tiles plus

@@ -81,3 +81,53 @@ def test_served_requests_match_oracle(trace, which):
     blk = Jh[tr.J_off[r]:tr.J_off[r] + nJ]
     Fo = O.forces(g, blk, np.array([0, nJ]), ptr)
     assert np.abs(Fg.astype(np.float64) - Fo).max() <= 1e-5 * np.abs(Fo).max()
+
+
+def test_staggered_arrivals_at_the_serving_shape():
+    """Requests of the serving workload's shape (d = 128, 128 stacks: D = 16384,
+    5..300 atoms, Jacobian blocks at random offsets of a pool) arrive every
+    ~50 us on the clock, so later requests are admitted while earlier batches
+    are still on the device. Every request's energy and forces equal its solo
+    launch bit for bit, and two requests match the FP64 oracle."""
+    from paper_2206_01580_amd import serve, sorf
+    tr = W.serving_trace(rate_hz=20000.0, duration_s=1.0, max_requests=64, j_pool_floats=1 << 25)
+    Jd = W.device_normal(tr.J_pool_floats, tr.J_seed, 0.1)
+    pool = serve.RequestPool(tr.x, tr.element, tr.sizes, Jd, tr.J_off)
+    model = sorf.Model.from_problem(tr.model)
+    alpha = torch.from_numpy(tr.model.alpha).cuda()
+    R = len(tr.sizes)
+    print(f"staggered serve: {R} requests, {int(tr.sizes.sum())} atoms, "
+          f"last arrival {tr.arrival_s[-1] * 1e3:.2f} ms", flush=True)
+    exb = serve.GpuExecutor(model, alpha, pool, max_batch_atoms=1024, max_batch_reqs=R, n_slots=3)
+    exp = serve.GpuExecutor(model, alpha, pool, max_batch_atoms=int(tr.sizes.max()),
+                            max_batch_reqs=1, n_slots=1)
+    for ex in (exb, exp):        # load the kernels once before the clock starts
+        h = ex.submit(0, 1)
+        while not h.done():
+            pass
+        ex.results.clear()
+    torch.cuda.synchronize()
+    st_b = serve.BatchingScheduler(exb, 1024, 3, 1 << 40).run(tr.arrival_s, tr.sizes)
+    st_p = serve.PlainRunner(exp).run(tr.arrival_s, tr.sizes)
+    torch.cuda.synchronize()
+    res_b = serve.request_results(exb, tr.sizes)
+    res_p = serve.request_results(exp, tr.sizes)
+    assert sorted(res_b) == sorted(res_p) == list(range(R))
+    assert st_b.summary()["launches_beside_inflight"] > 0, "no launch overlapped a batch in flight"
+    for r in range(R):
+        assert np.float32(res_b[r][0]).tobytes() == np.float32(res_p[r][0]).tobytes(), r
+        assert res_b[r][1].tobytes() == res_p[r][1].tobytes(), r
+    m = tr.model
+    alpha64 = m.alpha.astype(np.float64)
+    for r in (int(np.argmax(tr.sizes)), R - 1):
+        a0, n = int(np.sum(tr.sizes[:r])), int(tr.sizes[r])
+        x, el = tr.x[a0:a0 + n], tr.element[a0:a0 + n]
+        ptr = np.array([0, n], dtype=np.int64)
+        za = O.atom_features(x, el, m.signs, m.bias, m.sigma)
+        Eo = float((za @ alpha64).sum())
+        assert abs(res_b[r][0] - Eo) <= 1e-5 * float(np.abs(za * alpha64[None, :]).sum())
+        g = O.grad_x(x, el, ptr, m.signs, m.bias, m.sigma, alpha64)
+        nJ = n * m.d * 3 * n
+        blk = Jd[int(tr.J_off[r]):int(tr.J_off[r]) + nJ].cpu().numpy()
+        Fo = O.forces(g, blk, np.array([0, nJ]), ptr)
+        assert np.abs(res_b[r][1].astype(np.float64) - Fo).max() <= 1e-5 * np.abs(Fo).max()
