@@ -170,50 +170,34 @@ __global__ __launch_bounds__(256) void energy_sum_kernel(const float* __restrict
 // ---------------------------------------------------------------------------
 // Per-atom adjoint: dE/dx_i (and the atom's energy share)
 // ---------------------------------------------------------------------------
+// The stacks s = s_begin, s_begin + s_step, ... of atom a (element e) for the
+// lane group grp of a wave (lane q inside the group): the forward chain, the
+// phase, the energy share sum_f alpha_f cos(u_f) into eacc and, for the
+// gradient, alpha_f sin(u_f) taken back through the transposed chain and
+// added into gacc (per lane, before any sum over the groups).
 template <int LOG_D, int LOG_EPL, bool WANT_E, bool WANT_G>
-__global__ __launch_bounds__(256) void atom_adjoint_kernel(
-    const float* __restrict__ x, const int32_t* __restrict__ element,
-    const int64_t* __restrict__ mol_ptr, const uint32_t* __restrict__ signs,
-    const float* __restrict__ bias, const float* __restrict__ alpha,
-    const float* __restrict__ dE, float* __restrict__ grad_x, float* __restrict__ e_atom,
-    int64_t n_atoms, int64_t n_mols, int32_t S, int32_t T, float c_rev, float g_scale,
-    float e_scale) {
+__device__ __forceinline__ void adjoint_stacks(const float* __restrict__ xrow,
+                                               const uint32_t* __restrict__ signs_e,
+                                               const float* __restrict__ bias_e,
+                                               const float* __restrict__ alpha, int32_t S,
+                                               int32_t T, int32_t s_begin, int32_t s_step,
+                                               uint32_t q, uint32_t grp, float c_rev,
+                                               float (&gacc)[1 << LOG_EPL], float& eacc) {
   constexpr int DV = 1 << LOG_D;
   constexpr int EPL = 1 << LOG_EPL;
   constexpr int LOGK = LOG_D - LOG_EPL;
-  constexpr int VPW = 64 >> LOGK;
   constexpr int W = (DV + 31) / 32;
   constexpr int LW = EPL >= 32 ? EPL / 32 : 1;
-
-  const uint32_t lane = lane_id();
-  const uint32_t q = lane & ((1u << LOGK) - 1u);
-  const uint32_t grp = lane >> LOGK;
-  const int64_t a = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
-  if (a >= n_atoms) return;  // whole waves leave together
-
-  const int32_t e = element[a];
-  const int64_t Dtot = int64_t(S) * DV;
   const bool odd = (__builtin_popcount(q) & 1) != 0;
   const uint32_t flip = odd ? 0xFFFFFFFFu : 0u;
   const float c_lane = odd ? -c_rev : c_rev;
   const int64_t tstride = int64_t(S) * W;
-
-  // x is re-read (from cache) for every stack pass rather than held: with
-  // the gradient sums live, fewer registers per lane let more waves share a
-  // SIMD
-  const float* xrow = x + a * DV + q * EPL;
-
-  float gacc[EPL];
-#pragma unroll
-  for (int r = 0; r < EPL; ++r) gacc[r] = 0.0f;
-  float eacc = 0.0f;
-
-  for (int32_t s0 = 0; s0 < S; s0 += VPW) {
+  for (int32_t s0 = s_begin; s0 < S; s0 += s_step) {
     const int32_t s = s0 + int32_t(grp);
     if (s < S) {
       float v[EPL];
       load_vec<EPL>(v, xrow);
-      const uint32_t* sv = signs + (int64_t(e) * T * S + s) * W;
+      const uint32_t* sv = signs_e + int64_t(s) * W;
       for (int t = 0; t < T; ++t) {
         uint32_t w[LW];
         load_sign_words<EPL>(w, sv + t * tstride, q, t > 0 ? flip : 0u);
@@ -223,7 +207,7 @@ __global__ __launch_bounds__(256) void atom_adjoint_kernel(
       // bias and alpha in chunks of (at most) 8 entries, so that few of them
       // are live at once
       constexpr int CH = EPL < 8 ? EPL : 8;
-      const float* bp = bias + int64_t(e) * Dtot + int64_t(s) * DV + q * EPL;
+      const float* bp = bias_e + int64_t(s) * DV + q * EPL;
       const float* ap = alpha + int64_t(s) * DV + q * EPL;
 #pragma unroll
       for (int r0 = 0; r0 < EPL; r0 += CH) {
@@ -250,20 +234,19 @@ __global__ __launch_bounds__(256) void atom_adjoint_kernel(
       }
     }
   }
+}
 
+// Sum of gacc over the lane groups of a wave (lane bits LOGK .. 5) and of
+// eacc over all its lanes, in a fixed order.
+template <int LOGK, int EPL, bool WANT_E, bool WANT_G>
+__device__ __forceinline__ void adjoint_wave_sums(float (&gacc)[EPL], float& eacc) {
   if constexpr (WANT_G) {
-    // sum over the lane groups (stacks) of the wave: lane bits LOGK .. 5
     if constexpr (LOGK <= 0) { for (int r = 0; r < EPL; ++r) gacc[r] += lane_xor<0>(gacc[r]); }
     if constexpr (LOGK <= 1) { for (int r = 0; r < EPL; ++r) gacc[r] += lane_xor<1>(gacc[r]); }
     if constexpr (LOGK <= 2) { for (int r = 0; r < EPL; ++r) gacc[r] += lane_xor<2>(gacc[r]); }
     if constexpr (LOGK <= 3) { for (int r = 0; r < EPL; ++r) gacc[r] += lane_xor<3>(gacc[r]); }
     if constexpr (LOGK <= 4) { for (int r = 0; r < EPL; ++r) gacc[r] += lane_xor<4>(gacc[r]); }
     if constexpr (LOGK <= 5) { for (int r = 0; r < EPL; ++r) gacc[r] += lane_xor<5>(gacc[r]); }
-    if (grp == 0) {
-      float w_m = 1.0f;
-      if (dE != nullptr) w_m = dE[molecule_of(mol_ptr, n_mols, a)];
-      store_vec<EPL>(grad_x + a * DV + q * EPL, gacc, g_scale * w_m);
-    }
   }
   if constexpr (WANT_E) {
     eacc += lane_xor<0>(eacc);
@@ -272,7 +255,120 @@ __global__ __launch_bounds__(256) void atom_adjoint_kernel(
     eacc += lane_xor<3>(eacc);
     eacc += lane_xor<4>(eacc);
     eacc += lane_xor<5>(eacc);
+  }
+}
+
+// One wave per atom: its lane groups cover the stacks in passes of VPW.
+template <int LOG_D, int LOG_EPL, bool WANT_E, bool WANT_G>
+__global__ __launch_bounds__(256) void atom_adjoint_kernel(
+    const float* __restrict__ x, const int32_t* __restrict__ element,
+    const int64_t* __restrict__ mol_ptr, const uint32_t* __restrict__ signs,
+    const float* __restrict__ bias, const float* __restrict__ alpha,
+    const float* __restrict__ dE, float* __restrict__ grad_x, float* __restrict__ e_atom,
+    int64_t n_atoms, int64_t n_mols, int32_t S, int32_t T, float c_rev, float g_scale,
+    float e_scale) {
+  constexpr int DV = 1 << LOG_D;
+  constexpr int EPL = 1 << LOG_EPL;
+  constexpr int LOGK = LOG_D - LOG_EPL;
+  constexpr int VPW = 64 >> LOGK;
+  constexpr int W = (DV + 31) / 32;
+
+  const uint32_t lane = lane_id();
+  const uint32_t q = lane & ((1u << LOGK) - 1u);
+  const uint32_t grp = lane >> LOGK;
+  const int64_t a = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  if (a >= n_atoms) return;  // whole waves leave together
+
+  const int32_t e = element[a];
+  const int64_t Dtot = int64_t(S) * DV;
+  // x is re-read (from cache) for every stack pass rather than held: with
+  // the gradient sums live, fewer registers per lane let more waves share a
+  // SIMD
+  const float* xrow = x + a * DV + q * EPL;
+
+  float gacc[EPL];
+#pragma unroll
+  for (int r = 0; r < EPL; ++r) gacc[r] = 0.0f;
+  float eacc = 0.0f;
+  adjoint_stacks<LOG_D, LOG_EPL, WANT_E, WANT_G>(xrow, signs + int64_t(e) * T * S * W,
+                                                 bias + int64_t(e) * Dtot, alpha, S, T, 0, VPW,
+                                                 q, grp, c_rev, gacc, eacc);
+  adjoint_wave_sums<LOGK, EPL, WANT_E, WANT_G>(gacc, eacc);
+  if constexpr (WANT_G) {
+    if (grp == 0) {
+      float w_m = 1.0f;
+      if (dE != nullptr) w_m = dE[molecule_of(mol_ptr, n_mols, a)];
+      store_vec<EPL>(grad_x + a * DV + q * EPL, gacc, g_scale * w_m);
+    }
+  }
+  if constexpr (WANT_E) {
     if (lane == 0) e_atom[a] = eacc * e_scale;
+  }
+}
+
+// Latency form of the energy + gradient adjoint (sorf_predict with forces):
+// one workgroup of NWAVE waves per atom, wave w taking the stack passes
+// w, w + NWAVE, ...; the waves' sums are added in wave order through LDS.
+// A small batch (a served request) then spreads over NWAVE times as many
+// SIMDs and finishes in about 1 / NWAVE of the one-wave time. NWAVE depends
+// only on the model (the pass count, at most 8), so a molecule's results do
+// not depend on the batch it is in.
+constexpr int kAdjMaxWaves = 8;
+template <int LOG_D, int LOG_EPL>
+__global__ __launch_bounds__(64 * kAdjMaxWaves) __attribute__((amdgpu_waves_per_eu(3))) void atom_adjoint_split_kernel(
+    const float* __restrict__ x, const int32_t* __restrict__ element,
+    const uint32_t* __restrict__ signs, const float* __restrict__ bias,
+    const float* __restrict__ alpha, float* __restrict__ grad_x, float* __restrict__ e_atom,
+    int64_t n_atoms, int32_t S, int32_t T, float c_rev, float g_scale, float e_scale) {
+  constexpr int DV = 1 << LOG_D;
+  constexpr int EPL = 1 << LOG_EPL;
+  constexpr int LOGK = LOG_D - LOG_EPL;
+  constexpr int VPW = 64 >> LOGK;
+  constexpr int W = (DV + 31) / 32;
+  __shared__ float red[kAdjMaxWaves][DV];
+  __shared__ float ered[kAdjMaxWaves];
+
+  const int nw = int(blockDim.x >> 6);
+  const int wv = int(threadIdx.x >> 6);
+  const uint32_t lane = lane_id();
+  const uint32_t q = lane & ((1u << LOGK) - 1u);
+  const uint32_t grp = lane >> LOGK;
+  // workgroup-uniform loop over atoms (one per workgroup at a time)
+  for (int64_t a = blockIdx.x; a < n_atoms; a += gridDim.x) {
+    const int32_t e = element[a];
+    const float* xrow = x + a * DV + q * EPL;
+
+    float gacc[EPL];
+#pragma unroll
+    for (int r = 0; r < EPL; ++r) gacc[r] = 0.0f;
+    float eacc = 0.0f;
+    adjoint_stacks<LOG_D, LOG_EPL, true, true>(xrow, signs + int64_t(e) * T * S * W,
+                                               bias + int64_t(e) * int64_t(S) * DV, alpha, S, T,
+                                               wv * VPW, nw * VPW, q, grp, c_rev, gacc, eacc);
+    adjoint_wave_sums<LOGK, EPL, true, true>(gacc, eacc);
+    if (grp == 0) {
+#pragma unroll
+      for (int r = 0; r < EPL; ++r) red[wv][q * EPL + r] = gacc[r];
+    }
+    if (lane == 0) ered[wv] = eacc;
+    __syncthreads();
+    if (wv == 0) {
+      if (grp == 0) {
+#pragma unroll
+        for (int r = 0; r < EPL; ++r) {
+          float g = red[0][q * EPL + r];
+          for (int w = 1; w < nw; ++w) g += red[w][q * EPL + r];
+          gacc[r] = g;
+        }
+        store_vec<EPL>(grad_x + a * DV + q * EPL, gacc, g_scale);
+      }
+      if (lane == 0) {
+        float es = ered[0];
+        for (int w = 1; w < nw; ++w) es += ered[w];
+        e_atom[a] = es * e_scale;
+      }
+    }
+    __syncthreads();   // red[] and ered[] are rewritten for the next atom
   }
 }
 
@@ -430,8 +526,15 @@ __global__ __launch_bounds__(256) void molecule_final_kernel(
       const ForceShape f = force_shape(n, d);
       const int64_t ncol = 3 * n;
       const float* __restrict__ p = partial + part_start[m] + (k - 3 * a0);
+      // all chunk partials are loaded before the sum (one memory round trip
+      // instead of nrc dependent ones); the sum keeps chunk order
+      float v[kForceMaxChunks];
+#pragma unroll
+      for (int rc = 0; rc < kForceMaxChunks; ++rc) v[rc] = rc < f.nrc ? p[rc * ncol] : 0.0f;
       float s = 0.0f;
-      for (int64_t rc = 0; rc < f.nrc; ++rc) s += p[rc * ncol];
+#pragma unroll
+      for (int rc = 0; rc < kForceMaxChunks; ++rc)
+        if (rc < f.nrc) s += v[rc];
       F[k] = -s;
     }
   }
@@ -439,7 +542,15 @@ __global__ __launch_bounds__(256) void molecule_final_kernel(
     for (int64_t m = tid; m < n_mols; m += stride) {
       const int64_t a0 = mol_ptr[m], a1 = mol_ptr[m + 1];
       float s = 0.0f;
-      for (int64_t i = a0; i < a1; ++i) s += e_atom[i];
+      // loads in groups of 16 ahead of the in-order sum
+      for (int64_t i0 = a0; i0 < a1; i0 += 16) {
+        float v[16];
+#pragma unroll
+        for (int j = 0; j < 16; ++j) v[j] = i0 + j < a1 ? e_atom[i0 + j] : 0.0f;
+#pragma unroll
+        for (int j = 0; j < 16; ++j)
+          if (i0 + j < a1) s += v[j];
+      }
       E[m] = s;
     }
   }
@@ -531,7 +642,16 @@ static hipError_t adjoint_dispatch(const SorfFeatureArgs& a, const float* alpha,
   hipLaunchKernelGGL((atom_adjoint_kernel<LOG_D, LOG_EPL, WE, WG>), grid, block, 0, st, a.x,   \
                      a.element, a.mol_ptr, a.signs, a.bias, alpha, dE, grad_x, e_atom,        \
                      a.n_atoms, a.n_mols, a.n_stacks, a.n_transforms, c_rev, g_scale, e_scale)
-  if (e_atom && grad_x) SORF_ADJ(true, true);
+  if (e_atom && grad_x && dE == nullptr) {
+    // energies with forces: the latency form, one pass of stacks per wave
+    constexpr int VPW = 64 >> (LOG_D - LOG_EPL);
+    const int64_t passes = (a.n_stacks + VPW - 1) / VPW;
+    const int nw = int(passes < kAdjMaxWaves ? passes : kAdjMaxWaves);
+    const int64_t grid = a.n_atoms < (int64_t(1) << 20) ? a.n_atoms : (int64_t(1) << 20);
+    hipLaunchKernelGGL((atom_adjoint_split_kernel<LOG_D, LOG_EPL>), dim3(unsigned(grid)),
+                       dim3(64 * nw), 0, st, a.x, a.element, a.signs, a.bias, alpha, grad_x,
+                       e_atom, a.n_atoms, a.n_stacks, a.n_transforms, c_rev, g_scale, e_scale);
+  } else if (e_atom && grad_x) SORF_ADJ(true, true);
   else if (e_atom) SORF_ADJ(true, false);
   else SORF_ADJ(false, true);
 #undef SORF_ADJ

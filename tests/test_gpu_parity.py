@@ -169,11 +169,20 @@ def _check_energy(Eg, p, alpha):
 
 @pytest.mark.parametrize("shape", [(8, 3, 3, 2, 7, 0, 5), (64, 4, 3, 3, 9, 1, 10),
                                    (128, 16, 3, 5, 6, 0, 9), (256, 3, 2, 2, 4, 1, 6),
-                                   (64, 32, 3, 3, 4, 0, 8), (256, 8, 2, 2, 4, 1, 6)],
+                                   (64, 32, 3, 3, 4, 0, 8), (256, 8, 2, 2, 4, 1, 6),
+                                   # the energy + force adjoint spreads an atom's stack
+                                   # passes over up to 8 waves: 10 passes (waves 0, 1
+                                   # take two), 2 passes at d = 1024
+                                   (128, 160, 3, 3, 5, 0, 6), (1024, 3, 2, 2, 3, 1, 3)],
                          ids=lambda s: "d{}-S{}-T{}".format(*s[:3]))
 def test_predict_energies_and_forces(shape):
     d, S_, T, E, M, lo, hi = shape
-    p = W.random_problem(3000 + d, d, S_, T, E, M, hi, lo, with_J=True)
+    # at d = 1024 a random sigma down to 0.5 gives phases of up to 160 radians,
+    # whose FP32 rounding alone (eps (T log2 d + 3) |u|) exceeds the force bound
+    # (the large-phase reading of the feature tolerance); sigma = 32 keeps them
+    # below 10 radians, the bias's range
+    p = W.random_problem(3000 + d, d, S_, T, E, M, hi, lo, with_J=True,
+                         sigma=32.0 if d >= 1024 else None)
     model, batch = dev_problem(p)
     alpha = torch.from_numpy(p.alpha).cuda()
     En = S().predict(model, batch, alpha)
@@ -438,10 +447,18 @@ def test_gram_split_deterministic():
 
 @pytest.mark.parametrize("D", [64, 30], ids=["ring-D64", "slab-D30"])
 def test_kahan_flush_beats_plain_fp32_on_a_long_sum(D):
-    """131,072 rows of positive entries near 1: the running FP32 sum grows to
-    1.3e5 while each 256-row block adds ~256, so plain FP32 flushes lose low
-    bits at every add; the compensated flush keeps them (both against FP64
-    sums of the same FP32 rows)."""
+    """131,072 rows of positive entries near 1 (both modes against FP64 sums of
+    the same FP32 rows).
+
+    slab kernel (D % 4 != 0, one pass over all rows): the running FP32 sum grows
+    to 1.3e5 while each 256-row block adds ~256, so plain FP32 flushes lose low
+    bits at every add; the compensated flush keeps them (5x smaller error).
+
+    ring kernel (D % 4 == 0): the rows of a tile are split into 8 slices of
+    16,384 rows whose sums are added in slice order, so the running sums stay
+    8x shorter and plain FP32 already lands at the rounding floor of the result
+    (about half an ulp, 6e-8 relative); both modes must stay within two ulps
+    (2^-22 relative) and the compensated one no worse than the plain one."""
     M = 1 << 17
     rng = np.random.default_rng(D)
     Z = (1.0 + 0.01 * rng.standard_normal((M, D))).astype(np.float32)
@@ -456,8 +473,12 @@ def test_kahan_flush_beats_plain_fp32_on_a_long_sum(D):
         errs[mode] = float(np.linalg.norm(G.double().cpu().numpy()[low] - Ge[low]) /
                            np.linalg.norm(Ge[low]))
     print("relative Frobenius errors:", errs)
-    assert errs["fp32_kahan"] <= 0.2 * errs["fp32"], errs
-    assert errs["fp32_kahan"] <= 1e-6
+    if D % 4 != 0:
+        assert errs["fp32_kahan"] <= 0.2 * errs["fp32"], errs
+        assert errs["fp32_kahan"] <= 1e-6
+    else:
+        assert errs["fp32"] <= 2.0 ** -22 and errs["fp32_kahan"] <= 2.0 ** -22, errs
+        assert errs["fp32_kahan"] <= 1.05 * errs["fp32"], errs
 
 
 @pytest.mark.parametrize("MD", [(333, 300), (17, 64), (5, 129)], ids=lambda t: f"M{t[0]}-D{t[1]}")
