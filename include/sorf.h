@@ -21,6 +21,8 @@
  *     comment says "host". All buffers are owned by the caller; the library
  *     keeps no state and never frees anything. The only HIP objects it creates
  *     are those sorf_solve_streams_create hands to the caller, who owns them.
+ *     The one exception is sorf_predict_noalloc, whose workspace is a fixed
+ *     device array of the library (see there).
  *   - Every compute call is asynchronous on `stream` (a hipStream_t; NULL means
  *     the default stream), returns a status immediately, never prints and never
  *     allocates device memory. Host-side validation of sizes, flags and null
@@ -46,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SORF_ABI_VERSION 5
+#define SORF_ABI_VERSION 6
 
 typedef void* sorf_stream_t; /* a hipStream_t */
 
@@ -372,6 +374,24 @@ size_t sorf_predict_workspace_bytes(const sorf_model* model, int64_t n_atoms, in
 sorf_status sorf_predict(const sorf_model* model, const sorf_batch* batch, const float* alpha,
                          const float* J, const int64_t* J_ptr, float* E, float* F,
                          void* workspace, size_t workspace_bytes, sorf_stream_t stream);
+
+/* sorf_predict for callers that cannot allocate device memory or pass a workspace:
+ * code under HIP graph capture, tight serving loops, harnesses that forbid hipMalloc.
+ * Same arguments (minus the workspace), kernels, results (bitwise) and error behaviour
+ * as sorf_predict. The workspace is a file-scope device array of
+ * SORF_PREDICT_NOALLOC_SCRATCH_BYTES per GPU, held from library load until the process
+ * ends; its device address is looked up once per device on the first call made with that
+ * device current. A batch whose sorf_predict_workspace_bytes() exceeds
+ * SORF_PREDICT_NOALLOC_SCRATCH_BYTES is rejected with SORF_ERR_WORKSPACE before any
+ * device work; SORF_ERR_DEVICE if the array's address cannot be obtained. Every kernel
+ * writes the scratch it reads, so nothing needs clearing between calls. All calls on
+ * one GPU share that GPU's array: calls that overlap on one GPU (different streams or
+ * host threads without ordering) race and give undefined results; the caller must
+ * serialise them. */
+#define SORF_PREDICT_NOALLOC_SCRATCH_BYTES ((size_t)64 << 20)
+sorf_status sorf_predict_noalloc(const sorf_model* model, const sorf_batch* batch,
+                                 const float* alpha, const float* J, const int64_t* J_ptr,
+                                 float* E, float* F, sorf_stream_t stream);
 
 /* Bytes of workspace sorf_forces needs for n_atoms atoms in n_mols molecules (host-only
  * query, nondecreasing in both). Returns 0 for negative sizes. */

@@ -17,6 +17,9 @@ SORF_ERR_UNSUPPORTED = 2
 SORF_ERR_DEVICE = 3
 SORF_ERR_WORKSPACE = 4
 
+# bytes of the fixed device scratch array behind sorf_predict_noalloc
+PREDICT_NOALLOC_SCRATCH_BYTES = 64 << 20
+
 GRAM_MODES = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16_hilo": 3, "fp16_hilo": 4,
               "fp32_kahan": 5}
 
@@ -31,7 +34,8 @@ EXPORTS = (
     "sorf_solve_workspace_bytes",
     "sorf_solve", "sorf_solve_f64", "sorf_solve_streams_create", "sorf_solve_streams_destroy",
     "sorf_solve_streamed", "sorf_solve_f64_streamed",
-    "sorf_predict_workspace_bytes", "sorf_predict", "sorf_forces_workspace_bytes", "sorf_forces",
+    "sorf_predict_workspace_bytes", "sorf_predict", "sorf_predict_noalloc",
+    "sorf_forces_workspace_bytes", "sorf_forces",
     "sorf_validate_batch",
 )
 
@@ -142,6 +146,7 @@ def load() -> ctypes.CDLL:
         "sorf_solve_f64_streamed": (ctypes.c_int, [i32, P, P, f64, i32, P, P, P, sz, SP, P]),
         "sorf_predict_workspace_bytes": (sz, [MP, i64, i64]),
         "sorf_predict": (ctypes.c_int, [MP, BP, P, P, P, P, P, P, sz, P]),
+        "sorf_predict_noalloc": (ctypes.c_int, [MP, BP, P, P, P, P, P, P]),
         "sorf_forces_workspace_bytes": (sz, [i64, i64]),
         "sorf_forces": (ctypes.c_int, [i32, i64, i64, P, P, P, P, P, P, sz, P]),
         "sorf_validate_batch": (ctypes.c_int, [BP, i32, P, P]),

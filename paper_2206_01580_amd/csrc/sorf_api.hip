@@ -2,6 +2,7 @@
 // the caller's stream. Nothing here allocates device memory or synchronises.
 #include <cmath>
 #include <cstring>
+#include <mutex>
 
 #include "../../include/sorf.h"
 #include "sorf_internal.h"
@@ -478,6 +479,52 @@ sorf_status sorf_validate_batch(const sorf_batch* batch, int32_t n_elements, int
   a.n_mols = batch->n_mols;
   a.n_elements = n_elements;
   return dev(sorf_launch_validate(a, result, hipStream_t(stream)));
+}
+
+}  // extern "C"
+
+// ------------------------------------------------ sorf_predict_noalloc
+// For callers that cannot allocate (graph capture, serving loops): the
+// workspace of sorf_predict lives in a file-scope device array. Host code never
+// passes the array's name to a kernel or a copy (on the host it is only a
+// stand-in symbol); it passes the device address hipGetSymbolAddress returns
+// for the current device, looked up once per device and kept.
+namespace {
+
+constexpr size_t kPredictScratchBytes = SORF_PREDICT_NOALLOC_SCRATCH_BYTES;
+__device__ __align__(256) unsigned char scratch[kPredictScratchBytes];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mutex;
+void* g_scratch_ptr[kMaxDevices] = {};
+
+// Device address of this device's scratch array, or nullptr if the lookup failed.
+void* scratch_for_current_device() {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return nullptr;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  if (g_scratch_ptr[dev] == nullptr) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || p == nullptr) return nullptr;
+    g_scratch_ptr[dev] = p;
+  }
+  return g_scratch_ptr[dev];
+}
+
+}  // namespace
+
+extern "C" {
+
+sorf_status sorf_predict_noalloc(const sorf_model* model, const sorf_batch* batch,
+                                 const float* alpha, const float* J, const int64_t* J_ptr,
+                                 float* E, float* F, sorf_stream_t stream) {
+  sorf_status s = check_predict(model, batch, alpha, J, J_ptr, E, F);
+  if (s != SORF_OK) return s;
+  if (predict_ws(model, batch->n_atoms, batch->n_mols) > kPredictScratchBytes)
+    return SORF_ERR_WORKSPACE;
+  void* ws = scratch_for_current_device();
+  if (ws == nullptr) return SORF_ERR_DEVICE;
+  return predict_launch(model, batch, alpha, J, J_ptr, E, F, ws, hipStream_t(stream));
 }
 
 }  // extern "C"

@@ -495,6 +495,31 @@ def predict(model: Model, batch: Batch, alpha: torch.Tensor, J=None, J_ptr=None)
     return Predictor(model, batch.x.device)(batch, alpha, J, J_ptr)
 
 
+def predict_noalloc(model: Model, batch: Batch, alpha: torch.Tensor, J=None, J_ptr=None,
+                    E: Optional[torch.Tensor] = None, F: Optional[torch.Tensor] = None):
+    """sorf_predict_noalloc: energies (and forces with J) with the library's fixed
+    device scratch as workspace. The outputs E (and F) must be given when the caller
+    cannot allocate; calls overlapping on one GPU race on the shared scratch."""
+    batch.check(model)
+    _need(alpha, torch.float32, "alpha", model.n_features)
+    dev = batch.x.device
+    if E is None:
+        E = torch.empty(batch.n_mols, dtype=torch.float32, device=dev)
+    _need(E, torch.float32, "E", batch.n_mols)
+    if J is not None:
+        _need(J, torch.float32, "J")
+        _need(J_ptr, torch.int64, "J_ptr", batch.n_mols + 1)
+        if F is None:
+            F = torch.empty(3 * batch.n_atoms, dtype=torch.float32, device=dev)
+        _need(F, torch.float32, "F", 3 * batch.n_atoms)
+    lib = _lib.load()
+    m, b = model.c_struct(), batch.c_struct()
+    _lib.check("sorf_predict_noalloc", lib.sorf_predict_noalloc(
+        ctypes.byref(m), ctypes.byref(b), _ptr(alpha), _ptr(J), _ptr(J_ptr), _ptr(E),
+        _ptr(F if J is not None else None), _stream()))
+    return (E, F) if J is not None else E
+
+
 def validate_batch(batch: Batch, n_elements: int) -> int:
     """Device-side CSR / element-range check; returns the flag word (0 = valid)."""
     res = torch.zeros(1, dtype=torch.int32, device=batch.x.device)

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.sorf_abi_version() == 5
+    assert lib.sorf_abi_version() == 6
 
 
 def test_struct_layout_matches_c(tmp_path):
