@@ -60,12 +60,14 @@ def dz_slots_per_unit(d: int, T: int) -> float:
     return T * math.log2(d) + T + 1
 
 
-def measured_traffic(mode, M, D):
-    """HBM bytes per Gram call (pack + products) from the committed PMC
-    measurement, valid only for the same mode and size and while the Gram
-    source is unchanged since the counters were taken; else None."""
+def measured_gram_counters(mode, M, D):
+    """HBM bytes and matrix-core busy fraction of one Gram call from the
+    committed counter runs (profiles/gram_qm9_like_counters.json: scaled
+    FETCH_SIZE + WRITE_SIZE per call, SQ_VALU_MFMA_BUSY_CYCLES per SIMD-cycle),
+    valid only for the same mode and size and while the Gram source is
+    unchanged since the counters were taken; else None."""
     import hashlib
-    path = os.path.join(ROOT, "profiles", "gram_traffic.json")
+    path = os.path.join(ROOT, "profiles", "gram_qm9_like_counters.json")
     src = os.path.join(ROOT, "paper_2206_01580_amd", "csrc", "sorf_gram.hip")
     try:
         with open(path) as f:
@@ -74,10 +76,10 @@ def measured_traffic(mode, M, D):
             h = hashlib.sha256(f.read()).hexdigest()
     except OSError:
         return None
-    if rec.get("source_sha256") != h or rec.get("mode") != mode or rec.get("M") != M \
-            or rec.get("D") != D:
+    if rec.get("source_sha256") != h or rec.get("M") != M or rec.get("D") != D \
+            or mode not in rec.get("modes", {}):
         return None
-    return rec.get("traffic_bytes")
+    return rec["modes"][mode]
 
 
 def parse():
@@ -852,9 +854,11 @@ def main():
                             "unit": "T VALU-slots/s", "frac": pred_tops / PEAK_VALU_TOPS,
                             "traffic": None, "ms": med["predict"]}
     # the dominant single kernel launch (the solve phase is ~1000 launches of 9 kernels)
-    tr = measured_traffic(args.gram, M, D)
-    if tr is not None:
-        rooflines["gram"]["traffic"] = tr
+    cnt = measured_gram_counters(args.gram, M, D)
+    if cnt is not None:
+        rooflines["gram"]["traffic"] = cnt["hbm_bytes"]
+        rooflines["gram"]["mfma_busy_counter"] = cnt["mfma_busy"]
+        rooflines["gram"]["clock_ghz_counter"] = cnt["clock_ghz"]
     dominant = max(("gram", "forward", "backward", "predict"), key=lambda k: med[k])
     roof = {k: v for k, v in rooflines[dominant].items() if k != "ms"}
     roof["kernel"] = dominant
