@@ -98,7 +98,7 @@ def parse():
     ap.add_argument("--serve-seconds", type=float, default=20.0,
                     help="length of the Poisson request trace (0 skips the serving leg)")
     ap.add_argument("--serve-rate", type=float, default=2000.0)
-    ap.add_argument("--serve-slots", type=int, default=4)
+    ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-max-atoms", type=int, default=8192)
     ap.add_argument("--serve-sweep", default="8000,32000",
                     help="extra offered loads (req/s), each a trace of --serve-sweep-requests")
@@ -124,8 +124,13 @@ def parse():
 
 def serving_leg(args, dev, log, rate, seconds):
     """Energy+force serving on a Poisson trace (D = 16384, sizes log-uniform
-    5..300 atoms): continuous batching vs one molecule per launch, same GPU,
-    same kernels, same resident model and request pool."""
+    5..300 atoms), same GPU, same resident model and request pool:
+    - batched: continuous batching into the library's persistent serving
+      kernel (sorf_server_*: batches published through a ring in host-coherent
+      memory, no launch per batch), up to 64 requests and --serve-max-atoms
+      atoms per batch, --serve-slots batches in flight;
+    - plain: one molecule per sorf_predict launch sequence, FIFO, one stream.
+    Each request's results are bitwise the same on both paths."""
     import torch
 
     from paper_2206_01580_amd import serve, sorf, workloads
@@ -136,38 +141,50 @@ def serving_leg(args, dev, log, rate, seconds):
     alpha = torch.from_numpy(tr.model.alpha).to(dev)
     R = len(tr.sizes)
     cap = max(args.serve_max_atoms, int(tr.sizes.max()))
-    exb = serve.GpuExecutor(model, alpha, pool, max_batch_atoms=cap, max_batch_reqs=cap // 5 + 1,
-                            n_slots=args.serve_slots, device=dev)
     exp = serve.GpuExecutor(model, alpha, pool, max_batch_atoms=int(tr.sizes.max()),
                             max_batch_reqs=1, n_slots=1, device=dev)
-    # in-flight request state (workspace, energies, forces) of all slots at capacity
-    budget = args.serve_slots * (cap * exb.ws_per_atom + 4 * (cap // 5 + 1))
-    for ex in (exb, exp):        # load the kernels and touch every buffer once
-        h = ex.submit(0, 1)
-        while not h.done():
-            pass
-        ex.results.clear()
+    h = exp.submit(0, 1)         # load the kernels and touch every buffer once
+    while not h.done():
+        pass
+    exp.results.clear()
     torch.cuda.synchronize()
     log(f"serving: {R} requests, {int(tr.sizes.sum())} atoms, rate {rate:g}/s")
-    sb = serve.BatchingScheduler(exb, cap, args.serve_slots, budget).run(tr.arrival_s, tr.sizes)
+    srv = serve.NativeServer(model, alpha, pool, max_batch_atoms=cap, ring_slots=args.serve_slots,
+                             idle_timeout_s=max(30.0, 2 * seconds), device=dev)
+    # in-flight request state: the result slots of the ring
+    budget = args.serve_slots * srv.slot_bytes()
+    try:
+        h = srv.submit(0, 1)     # first batch: the kernel's code and the pool pages are warm
+        while not h.done():
+            pass
+        srv.results.clear()
+        sb = serve.BatchingScheduler(srv, cap, args.serve_slots, budget,
+                                     max_batch_requests=serve.NativeServer.MAX_REQUESTS
+                                     ).run(tr.arrival_s, tr.sizes)
+    finally:
+        state = srv.stop()
     torch.cuda.synchronize()
-    log(f"serving: batched done ({len(sb.batches)} launches)")
+    log(f"serving: batched done ({len(sb.batches)} batches, kernel exit state {state})")
     sp = serve.PlainRunner(exp).run(tr.arrival_s, tr.sizes)
     torch.cuda.synchronize()
     log("serving: plain done")
     warm = min(1.0, 0.1 * seconds)       # the first second of the trace is warm-up
     b, p = sb.summary(warm, tr.arrival_s), sp.summary(warm, tr.arrival_s)
-    del pool, J, exb, exp
+    del pool, J, exp, srv
     torch.cuda.empty_cache()
     return {
         "workload": (f"Poisson {rate:g} req/s for {seconds:g} s, sizes log-uniform 5..300 atoms, "
                      f"d=128, D=16384, energies + forces (J blocks N x 128 x 3N at random offsets "
                      f"of a {tr.J_pool_floats * 4 >> 20} MiB pool)"),
         "rate_hz": rate, "requests": R, "atoms": int(tr.sizes.sum()), "warmup_s": warm,
-        "batched": dict(b, slots=args.serve_slots, max_batch_atoms=cap),
-        "plain": p,
+        "batched": dict(b, executor="persistent serving kernel (sorf_server)",
+                        ring_slots=args.serve_slots, max_batch_atoms=cap,
+                        max_batch_requests=serve.NativeServer.MAX_REQUESTS, kernel_exit_state=state),
+        "plain": dict(p, executor="sorf_predict per request (4 kernels, 2 offset uploads, "
+                                  "2 result copies, 1 event)"),
         "p50_speedup": (p["p50_ms"] / b["p50_ms"]) if b["p50_ms"] else None,
         "p99_speedup": (p["p99_ms"] / b["p99_ms"]) if b["p99_ms"] else None,
+        "atoms_per_s_ratio": (b["atoms_per_s"] / p["atoms_per_s"]) if p["atoms_per_s"] else None,
     }
 
 

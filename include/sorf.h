@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SORF_ABI_VERSION 6
+#define SORF_ABI_VERSION 7
 
 typedef void* sorf_stream_t; /* a hipStream_t */
 
@@ -57,7 +57,8 @@ typedef enum {
   SORF_ERR_INVALID_ARG = 1,  /* null pointer with non-zero size, bad size or flag */
   SORF_ERR_UNSUPPORTED = 2,  /* valid request outside what the kernels implement */
   SORF_ERR_DEVICE = 3,       /* a HIP launch or runtime call failed */
-  SORF_ERR_WORKSPACE = 4     /* workspace missing or smaller than the query returns */
+  SORF_ERR_WORKSPACE = 4,    /* workspace missing or smaller than the query returns */
+  SORF_ERR_BUSY = 5          /* sorf_server_submit: every ring slot holds an unfinished batch */
 } sorf_status;
 
 typedef enum {
@@ -416,6 +417,73 @@ size_t sorf_forces_workspace_bytes(int64_t n_atoms, int64_t n_mols);
 sorf_status sorf_forces(int32_t d, int64_t n_atoms, int64_t n_mols, const int64_t* mol_ptr,
                         const float* grad_x, const float* J, const int64_t* J_ptr, float* F,
                         void* workspace, size_t workspace_bytes, sorf_stream_t stream);
+
+/* ---------------------------------------------------------------------------
+ * Continuous-batching server for energy + force requests (Timings subsection:
+ * predicting many configurations in one call rather than one small molecule at
+ * a time). sorf_server_start launches one persistent kernel that stays resident
+ * on every compute unit of the current device until sorf_server_stop. The host
+ * then publishes batches of requests, each a contiguous run of molecules of a
+ * device-resident request pool, with sorf_server_submit (a descriptor written into
+ * a ring in host-coherent memory: no launch, copy or event per batch). The kernel
+ * takes the batches in submission order and writes each one's energies and forces
+ * into a host-coherent result slot; sorf_server_query reports completion. Every
+ * result is summed in the order sorf_predict uses, so a request's energy and forces
+ * are bitwise those of sorf_predict with its Jacobian on that request alone,
+ * whatever batch it is served in.
+ * Exceptions to the conventions above: sorf_server_start allocates the ring,
+ * control word and result slots in pinned host memory (hipHostMalloc) and
+ * sorf_server_stop frees them; while the kernel runs, other work on the device
+ * competes with it for compute units; sorf_server_stop blocks until the kernel
+ * has exited. A server is used from one host thread at a time.
+ * --------------------------------------------------------------------------- */
+typedef struct sorf_server sorf_server;   /* opaque, owned by the caller between start and stop */
+typedef struct {
+  int64_t max_batch_atoms;   /* atoms of the largest batch, 1 .. 2^24 (sizes scratch and slots) */
+  int32_t ring_slots;        /* batches published ahead of the kernel, 1 .. 64; a batch's result
+                                slot is reused by the batch ring_slots later */
+  double idle_timeout_s;     /* the kernel exits after this long without a batch, (0, 3600] */
+} sorf_server_config;
+
+/* Bytes of device workspace a server needs (host-only query): 0 for an invalid model or
+ * configuration. */
+size_t sorf_server_workspace_bytes(const sorf_model* model, const sorf_server_config* cfg);
+
+/* Starts the server on `stream` (a stream of the current device that the caller does not
+ * use otherwise until sorf_server_stop). alpha: [D] FP32; x_pool [A][d], element_pool [A]:
+ * the request pool's atoms; J_pool: Jacobian blocks, block r at any float offset (as in
+ * sorf_predict). All device arrays must stay valid and unchanged until the server stops.
+ * workspace: device memory of at least sorf_server_workspace_bytes(), 256-byte aligned, kept
+ * by the server until stop. On success *server is the handle; on failure it is NULL and no
+ * kernel runs. */
+sorf_status sorf_server_start(const sorf_model* model, const float* alpha, const float* x_pool,
+                              const int32_t* element_pool, const float* J_pool,
+                              const sorf_server_config* cfg, void* workspace,
+                              size_t workspace_bytes, sorf_stream_t stream, sorf_server** server);
+
+/* Publishes a batch of n_requests (1 .. 64) requests: request r has atoms
+ * [atom_offsets[r], atom_offsets[r + 1]) of the pool (host array of n_requests + 1
+ * nondecreasing offsets, at most max_batch_atoms atoms in all) and its Jacobian block at
+ * float offset J_offsets[r] of J_pool (host array). *ticket receives the batch number
+ * (0, 1, 2, ... in submission order). SORF_ERR_BUSY: ring_slots batches are unfinished;
+ * SORF_ERR_DEVICE: the kernel has exited. */
+sorf_status sorf_server_submit(sorf_server* server, int32_t n_requests, const int64_t* atom_offsets,
+                               const int64_t* J_offsets, int64_t* ticket);
+
+/* 1: batch `ticket` is finished and its results readable; 0: not yet; -1: the kernel has
+ * exited without finishing it; -2: no such ticket. */
+int32_t sorf_server_query(const sorf_server* server, int64_t ticket);
+
+/* Host pointers into the result slot of a finished batch: energies [n_requests] and forces
+ * [3 x atoms of the batch] ([atom][xyz], requests in order). Valid until the batch
+ * ring_slots later is submitted or the server stops; NULL for an unknown ticket. */
+const float* sorf_server_energies(const sorf_server* server, int64_t ticket);
+const float* sorf_server_forces(const sorf_server* server, int64_t ticket);
+
+/* Asks the kernel to finish the published batches and exit, waits for it and frees the
+ * server. *state (may be NULL): 1 stopped on request, 2 had exited after idle_timeout_s,
+ * 3 had exited on a wait limit (a fault of the server, reported rather than hung). */
+sorf_status sorf_server_stop(sorf_server* server, int32_t* state);
 
 /* Opt-in debug check of the device-side preconditions of a batch. Writes to
  * *result (device int32) a bit mask: 0 if mol_ptr is a valid CSR over n_atoms atoms

@@ -16,6 +16,7 @@ SORF_ERR_INVALID_ARG = 1
 SORF_ERR_UNSUPPORTED = 2
 SORF_ERR_DEVICE = 3
 SORF_ERR_WORKSPACE = 4
+SORF_ERR_BUSY = 5
 
 # bytes of the fixed device scratch array behind sorf_predict_noalloc
 PREDICT_NOALLOC_SCRATCH_BYTES = 64 << 20
@@ -36,7 +37,8 @@ EXPORTS = (
     "sorf_solve_streamed", "sorf_solve_f64_streamed",
     "sorf_predict_workspace_bytes", "sorf_predict", "sorf_predict_noalloc",
     "sorf_forces_workspace_bytes", "sorf_forces",
-    "sorf_validate_batch",
+    "sorf_validate_batch", "sorf_server_workspace_bytes", "sorf_server_start", "sorf_server_submit",
+    "sorf_server_query", "sorf_server_energies", "sorf_server_forces", "sorf_server_stop",
 )
 
 
@@ -81,6 +83,14 @@ class SorfSolveStreams(ctypes.Structure):
         ("side", ctypes.c_void_p),
         ("event_fork", ctypes.c_void_p),
         ("event_join", ctypes.c_void_p),
+    ]
+
+
+class SorfServerConfig(ctypes.Structure):
+    _fields_ = [
+        ("max_batch_atoms", ctypes.c_int64),
+        ("ring_slots", ctypes.c_int32),
+        ("idle_timeout_s", ctypes.c_double),
     ]
 
 
@@ -150,6 +160,14 @@ def load() -> ctypes.CDLL:
         "sorf_forces_workspace_bytes": (sz, [i64, i64]),
         "sorf_forces": (ctypes.c_int, [i32, i64, i64, P, P, P, P, P, P, sz, P]),
         "sorf_validate_batch": (ctypes.c_int, [BP, i32, P, P]),
+        "sorf_server_workspace_bytes": (sz, [MP, ctypes.POINTER(SorfServerConfig)]),
+        "sorf_server_start": (ctypes.c_int, [MP, P, P, P, P, ctypes.POINTER(SorfServerConfig), P, sz,
+                                             P, ctypes.POINTER(P)]),
+        "sorf_server_submit": (ctypes.c_int, [P, i32, P, P, ctypes.POINTER(i64)]),
+        "sorf_server_query": (i32, [P, i64]),
+        "sorf_server_energies": (ctypes.POINTER(ctypes.c_float), [P, i64]),
+        "sorf_server_forces": (ctypes.POINTER(ctypes.c_float), [P, i64]),
+        "sorf_server_stop": (ctypes.c_int, [P, ctypes.POINTER(i32)]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)

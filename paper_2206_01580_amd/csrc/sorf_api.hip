@@ -79,6 +79,7 @@ const char* sorf_status_string(sorf_status s) {
     case SORF_ERR_UNSUPPORTED: return "SORF_ERR_UNSUPPORTED";
     case SORF_ERR_DEVICE: return "SORF_ERR_DEVICE";
     case SORF_ERR_WORKSPACE: return "SORF_ERR_WORKSPACE";
+    case SORF_ERR_BUSY: return "SORF_ERR_BUSY";
   }
   return "SORF_ERR_UNKNOWN";
 }

@@ -314,30 +314,27 @@ __global__ __launch_bounds__(256) void atom_adjoint_kernel(
 // only on the model (the pass count, at most 8), so a molecule's results do
 // not depend on the batch it is in.
 constexpr int kAdjMaxWaves = 8;
+// Atom a with waves 0 .. nw - 1 of the workgroup (waves at or above nw only
+// take part in the barriers); red/ered are the workgroup's LDS scratch.
 template <int LOG_D, int LOG_EPL>
-__global__ __launch_bounds__(64 * kAdjMaxWaves) __attribute__((amdgpu_waves_per_eu(3))) void atom_adjoint_split_kernel(
-    const float* __restrict__ x, const int32_t* __restrict__ element,
+__device__ __forceinline__ void adjoint_split_atom(
+    int64_t a, int nw, const float* __restrict__ x, const int32_t* __restrict__ element,
     const uint32_t* __restrict__ signs, const float* __restrict__ bias,
     const float* __restrict__ alpha, float* __restrict__ grad_x, float* __restrict__ e_atom,
-    int64_t n_atoms, int32_t S, int32_t T, float c_rev, float g_scale, float e_scale) {
+    int32_t S, int32_t T, float c_rev, float g_scale, float e_scale,
+    float (&red)[kAdjMaxWaves][1 << LOG_D], float (&ered)[kAdjMaxWaves]) {
   constexpr int DV = 1 << LOG_D;
   constexpr int EPL = 1 << LOG_EPL;
   constexpr int LOGK = LOG_D - LOG_EPL;
   constexpr int VPW = 64 >> LOGK;
   constexpr int W = (DV + 31) / 32;
-  __shared__ float red[kAdjMaxWaves][DV];
-  __shared__ float ered[kAdjMaxWaves];
-
-  const int nw = int(blockDim.x >> 6);
   const int wv = int(threadIdx.x >> 6);
   const uint32_t lane = lane_id();
   const uint32_t q = lane & ((1u << LOGK) - 1u);
   const uint32_t grp = lane >> LOGK;
-  // workgroup-uniform loop over atoms (one per workgroup at a time)
-  for (int64_t a = blockIdx.x; a < n_atoms; a += gridDim.x) {
+  if (wv < nw) {
     const int32_t e = element[a];
     const float* xrow = x + a * DV + q * EPL;
-
     float gacc[EPL];
 #pragma unroll
     for (int r = 0; r < EPL; ++r) gacc[r] = 0.0f;
@@ -351,25 +348,48 @@ __global__ __launch_bounds__(64 * kAdjMaxWaves) __attribute__((amdgpu_waves_per_
       for (int r = 0; r < EPL; ++r) red[wv][q * EPL + r] = gacc[r];
     }
     if (lane == 0) ered[wv] = eacc;
-    __syncthreads();
-    if (wv == 0) {
-      if (grp == 0) {
-#pragma unroll
-        for (int r = 0; r < EPL; ++r) {
-          float g = red[0][q * EPL + r];
-          for (int w = 1; w < nw; ++w) g += red[w][q * EPL + r];
-          gacc[r] = g;
-        }
-        store_vec<EPL>(grad_x + a * DV + q * EPL, gacc, g_scale);
-      }
-      if (lane == 0) {
-        float es = ered[0];
-        for (int w = 1; w < nw; ++w) es += ered[w];
-        e_atom[a] = es * e_scale;
-      }
-    }
-    __syncthreads();   // red[] and ered[] are rewritten for the next atom
   }
+  __syncthreads();
+  if (wv == 0) {
+    if (grp == 0) {
+      float g[EPL];
+#pragma unroll
+      for (int r = 0; r < EPL; ++r) {
+        float v = red[0][q * EPL + r];
+        for (int w = 1; w < nw; ++w) v += red[w][q * EPL + r];
+        g[r] = v;
+      }
+      store_vec<EPL>(grad_x + a * DV + q * EPL, g, g_scale);
+    }
+    if (lane == 0) {
+      float es = ered[0];
+      for (int w = 1; w < nw; ++w) es += ered[w];
+      e_atom[a] = es * e_scale;
+    }
+  }
+  __syncthreads();   // red[] and ered[] are rewritten for the next atom
+}
+
+// Latency form of the energy + gradient adjoint (sorf_predict with forces):
+// one workgroup of nw waves per atom, wave w taking the stack passes
+// w, w + nw, ...; the waves' sums are added in wave order through LDS.
+// A small batch (a served request) then spreads over nw times as many SIMDs
+// and finishes in about 1 / nw of the one-wave time. nw depends only on the
+// model (the pass count, at most 8), so a molecule's results do not depend
+// on the batch it is in.
+template <int LOG_D, int LOG_EPL>
+__global__ __launch_bounds__(64 * kAdjMaxWaves) __attribute__((amdgpu_waves_per_eu(3))) void atom_adjoint_split_kernel(
+    const float* __restrict__ x, const int32_t* __restrict__ element,
+    const uint32_t* __restrict__ signs, const float* __restrict__ bias,
+    const float* __restrict__ alpha, float* __restrict__ grad_x, float* __restrict__ e_atom,
+    int64_t n_atoms, int32_t S, int32_t T, float c_rev, float g_scale, float e_scale) {
+  __shared__ float red[kAdjMaxWaves][1 << LOG_D];
+  __shared__ float ered[kAdjMaxWaves];
+  const int nw = int(blockDim.x >> 6);
+  // workgroup-uniform loop over atoms (one per workgroup at a time)
+  for (int64_t a = blockIdx.x; a < n_atoms; a += gridDim.x)
+    adjoint_split_atom<LOG_D, LOG_EPL>(a, nw, x, element, signs, bias, alpha, grad_x, e_atom, S,
+                                       T, c_rev, g_scale, e_scale, red, ered);
 }
 
 // ---------------------------------------------------------------------------
@@ -388,24 +408,6 @@ __global__ __launch_bounds__(64 * kAdjMaxWaves) __attribute__((amdgpu_waves_per_
 //   final   F = -(sum of a molecule's partial rows in chunk order); E_m is
 //           summed over the atoms in order.
 // ---------------------------------------------------------------------------
-constexpr int64_t kForceRowChunk = 256;
-constexpr int64_t kForceMaxChunks = 32;
-
-struct ForceShape {
-  int64_t nrc;    // row chunks
-  int64_t ncb;    // 64-column blocks
-  int64_t chunk;  // rows per chunk (last may be shorter)
-};
-
-__device__ __forceinline__ ForceShape force_shape(int64_t n, int32_t d) {
-  ForceShape f;
-  const int64_t rows = n * d;
-  const int64_t c = (rows + kForceRowChunk - 1) / kForceRowChunk;
-  f.nrc = c < kForceMaxChunks ? c : kForceMaxChunks;
-  f.chunk = f.nrc > 0 ? (rows + f.nrc - 1) / f.nrc : 0;
-  f.ncb = (3 * n + 63) / 64;
-  return f;
-}
 
 // Largest index m in [0, count) with ptr[m] <= v, for nondecreasing ptr with
 // ptr[0] <= v < ptr[count]: that entry has ptr[m] <= v < ptr[m + 1].
@@ -463,34 +465,41 @@ __global__ __launch_bounds__(1024) void force_plan_kernel(const int64_t* __restr
   }
 }
 
-__global__ __launch_bounds__(256) void force_partial_kernel(
-    const int64_t* __restrict__ mol_ptr, int64_t n_mols, const int64_t* __restrict__ tile_start,
-    const int64_t* __restrict__ part_start, const float* __restrict__ grad,
-    const float* __restrict__ J, const int64_t* __restrict__ J_ptr, float* __restrict__ partial,
-    int32_t d) {
-  __shared__ float red[4][64];
-  const int64_t total = tile_start[n_mols];
-  const int lane = threadIdx.x & 63;
-  const int wv = threadIdx.x >> 6;
-  for (int64_t t = blockIdx.x; t < total; t += gridDim.x) {
-    const int64_t m = upper_segment(tile_start, n_mols, t);
+// Tile t of the force contraction by four waves (wq = 0..3, lane = 0..63)
+// sharing red[4][64]: in the tile (64 columns, one row chunk of molecule m),
+// wave wq takes rows r0 + wq, r0 + wq + 4, ..., lanes own columns, and the
+// waves are combined in fixed order into one partial row. Both barriers are
+// reached by every caller's thread, active or not.
+__device__ __forceinline__ void force_tile(bool active, int64_t t,
+                                           const int64_t* __restrict__ mol_ptr, int64_t n_mols,
+                                           const int64_t* __restrict__ tile_start,
+                                           const int64_t* __restrict__ part_start,
+                                           const float* __restrict__ grad,
+                                           const float* __restrict__ J,
+                                           const int64_t* __restrict__ J_ptr,
+                                           float* __restrict__ partial, int32_t d, int wq, int lane,
+                                           float (&red)[4][64]) {
+  int64_t m = 0, rc = 0, col = 0, ncol = 1;
+  bool ok = false;
+  if (active) {
+    m = upper_segment(tile_start, n_mols, t);
     const int64_t a0 = mol_ptr[m];
     const int64_t n = mol_ptr[m + 1] - a0;
     const ForceShape f = force_shape(n, d);
     const int64_t local = t - tile_start[m];
-    const int64_t rc = local / f.ncb;
+    rc = local / f.ncb;
     const int64_t cb = local - rc * f.ncb;
-    const int64_t ncol = 3 * n;
+    ncol = 3 * n;
     const int64_t rows = n * d;
     const int64_t r0 = rc * f.chunk < rows ? rc * f.chunk : rows;
     const int64_t r1 = r0 + f.chunk < rows ? r0 + f.chunk : rows;
-    const int64_t col = cb * 64 + lane;
-    const bool ok = col < ncol;
+    col = cb * 64 + lane;
+    ok = col < ncol;
     // out-of-range lanes read the last column (in bounds) and discard it
     const float* __restrict__ blk = J + J_ptr[m] + (ok ? col : ncol - 1);
     const float* __restrict__ g = grad + a0 * d;
     float acc = 0.0f;
-    int64_t r = r0 + wv;
+    int64_t r = r0 + wq;
     for (; r + 28 < r1; r += 32) {
       float jv[8], gv[8];
 #pragma unroll
@@ -502,13 +511,67 @@ __global__ __launch_bounds__(256) void force_partial_kernel(
       for (int k = 0; k < 8; ++k) acc = __builtin_fmaf(jv[k], gv[k], acc);
     }
     for (; r < r1; r += 4) acc = __builtin_fmaf(blk[r * ncol], g[r], acc);
-    red[wv][lane] = acc;
-    __syncthreads();
-    if (wv == 0 && ok)
-      partial[part_start[m] + rc * ncol + col] =
-          ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
-    __syncthreads();
+    red[wq][lane] = acc;
   }
+  __syncthreads();
+  if (active && wq == 0 && ok)
+    partial[part_start[m] + rc * ncol + col] =
+        ((red[0][lane] + red[1][lane]) + red[2][lane]) + red[3][lane];
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(256) void force_partial_kernel(
+    const int64_t* __restrict__ mol_ptr, int64_t n_mols, const int64_t* __restrict__ tile_start,
+    const int64_t* __restrict__ part_start, const float* __restrict__ grad,
+    const float* __restrict__ J, const int64_t* __restrict__ J_ptr, float* __restrict__ partial,
+    int32_t d) {
+  __shared__ float red[4][64];
+  const int64_t total = tile_start[n_mols];
+  const int lane = threadIdx.x & 63;
+  const int wv = threadIdx.x >> 6;
+  for (int64_t t = blockIdx.x; t < total; t += gridDim.x)
+    force_tile(true, t, mol_ptr, n_mols, tile_start, part_start, grad, J, J_ptr, partial, d, wv,
+               lane, red);
+}
+
+// F[k] = -(sum of the molecule's partial rows at column k - 3 a0, in chunk
+// order), for force entry k of atom k / 3 of the batch. All chunk partials are
+// loaded before the sum (one memory round trip instead of nrc dependent ones).
+__device__ __forceinline__ float force_entry(int64_t k, const int64_t* __restrict__ mol_ptr,
+                                             int64_t n_mols,
+                                             const int64_t* __restrict__ part_start,
+                                             const float* __restrict__ partial, int32_t d) {
+  const int64_t i = k / 3;
+  const int64_t m = upper_segment(mol_ptr, n_mols, i);
+  const int64_t a0 = mol_ptr[m];
+  const int64_t n = mol_ptr[m + 1] - a0;
+  const ForceShape f = force_shape(n, d);
+  const int64_t ncol = 3 * n;
+  const float* __restrict__ p = partial + part_start[m] + (k - 3 * a0);
+  float v[kForceMaxChunks];
+#pragma unroll
+  for (int rc = 0; rc < kForceMaxChunks; ++rc) v[rc] = rc < f.nrc ? p[rc * ncol] : 0.0f;
+  float s = 0.0f;
+#pragma unroll
+  for (int rc = 0; rc < kForceMaxChunks; ++rc)
+    if (rc < f.nrc) s += v[rc];
+  return -s;
+}
+
+// E_m = sum of the atoms' shares in atom order, loads in groups of 16 ahead
+// of the in-order sum.
+__device__ __forceinline__ float molecule_energy(int64_t a0, int64_t a1,
+                                                 const float* __restrict__ e_atom) {
+  float s = 0.0f;
+  for (int64_t i0 = a0; i0 < a1; i0 += 16) {
+    float v[16];
+#pragma unroll
+    for (int j = 0; j < 16; ++j) v[j] = i0 + j < a1 ? e_atom[i0 + j] : 0.0f;
+#pragma unroll
+    for (int j = 0; j < 16; ++j)
+      if (i0 + j < a1) s += v[j];
+  }
+  return s;
 }
 
 __global__ __launch_bounds__(256) void molecule_final_kernel(
@@ -518,41 +581,12 @@ __global__ __launch_bounds__(256) void molecule_final_kernel(
   const int64_t stride = int64_t(gridDim.x) * blockDim.x;
   const int64_t tid = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
   if (F != nullptr) {
-    for (int64_t k = tid; k < 3 * n_atoms; k += stride) {
-      const int64_t i = k / 3;
-      const int64_t m = upper_segment(mol_ptr, n_mols, i);
-      const int64_t a0 = mol_ptr[m];
-      const int64_t n = mol_ptr[m + 1] - a0;
-      const ForceShape f = force_shape(n, d);
-      const int64_t ncol = 3 * n;
-      const float* __restrict__ p = partial + part_start[m] + (k - 3 * a0);
-      // all chunk partials are loaded before the sum (one memory round trip
-      // instead of nrc dependent ones); the sum keeps chunk order
-      float v[kForceMaxChunks];
-#pragma unroll
-      for (int rc = 0; rc < kForceMaxChunks; ++rc) v[rc] = rc < f.nrc ? p[rc * ncol] : 0.0f;
-      float s = 0.0f;
-#pragma unroll
-      for (int rc = 0; rc < kForceMaxChunks; ++rc)
-        if (rc < f.nrc) s += v[rc];
-      F[k] = -s;
-    }
+    for (int64_t k = tid; k < 3 * n_atoms; k += stride)
+      F[k] = force_entry(k, mol_ptr, n_mols, part_start, partial, d);
   }
   if (E != nullptr) {
-    for (int64_t m = tid; m < n_mols; m += stride) {
-      const int64_t a0 = mol_ptr[m], a1 = mol_ptr[m + 1];
-      float s = 0.0f;
-      // loads in groups of 16 ahead of the in-order sum
-      for (int64_t i0 = a0; i0 < a1; i0 += 16) {
-        float v[16];
-#pragma unroll
-        for (int j = 0; j < 16; ++j) v[j] = i0 + j < a1 ? e_atom[i0 + j] : 0.0f;
-#pragma unroll
-        for (int j = 0; j < 16; ++j)
-          if (i0 + j < a1) s += v[j];
-      }
-      E[m] = s;
-    }
+    for (int64_t m = tid; m < n_mols; m += stride)
+      E[m] = molecule_energy(mol_ptr[m], mol_ptr[m + 1], e_atom);
   }
 }
 
@@ -632,11 +666,8 @@ static hipError_t adjoint_dispatch(const SorfFeatureArgs& a, const float* alpha,
                                    float* grad_x, float* e_atom, hipStream_t st) {
   constexpr int LOG_EPL = default_log_epl<LOG_D>();
   const int64_t blocks = (a.n_atoms + 3) / 4;
-  const double D = double(a.d) * a.n_stacks;
-  const double c = double(sorf_c(a));
-  const float c_rev = float(c * (1.0 / (2.0 * M_PI)));
-  const float g_scale = float(-std::sqrt(2.0 / D) * c);
-  const float e_scale = float(std::sqrt(2.0 / D));
+  float c_rev, g_scale, e_scale;
+  sorf_adjoint_scales(a, &c_rev, &g_scale, &e_scale);
   const dim3 grid{unsigned(blocks)}, block{256};
 #define SORF_ADJ(WE, WG)                                                                        \
   hipLaunchKernelGGL((atom_adjoint_kernel<LOG_D, LOG_EPL, WE, WG>), grid, block, 0, st, a.x,   \
@@ -644,9 +675,7 @@ static hipError_t adjoint_dispatch(const SorfFeatureArgs& a, const float* alpha,
                      a.n_atoms, a.n_mols, a.n_stacks, a.n_transforms, c_rev, g_scale, e_scale)
   if (e_atom && grad_x && dE == nullptr) {
     // energies with forces: the latency form, one pass of stacks per wave
-    constexpr int VPW = 64 >> (LOG_D - LOG_EPL);
-    const int64_t passes = (a.n_stacks + VPW - 1) / VPW;
-    const int nw = int(passes < kAdjMaxWaves ? passes : kAdjMaxWaves);
+    const int nw = sorf_adjoint_waves(a.d, a.n_stacks);
     const int64_t grid = a.n_atoms < (int64_t(1) << 20) ? a.n_atoms : (int64_t(1) << 20);
     hipLaunchKernelGGL((atom_adjoint_split_kernel<LOG_D, LOG_EPL>), dim3(unsigned(grid)),
                        dim3(64 * nw), 0, st, a.x, a.element, a.signs, a.bias, alpha, grad_x,
@@ -658,9 +687,204 @@ static hipError_t adjoint_dispatch(const SorfFeatureArgs& a, const float* alpha,
   return hipGetLastError();
 }
 
+// ---------------------------------------------------------------------------
+// Persistent serving kernel
+// ---------------------------------------------------------------------------
+// One workgroup of 8 waves per compute unit, all resident (cooperative
+// launch). Per batch, with grid-wide barriers between the phases:
+//   B0  workgroup 0 waits until every workgroup has finished the previous
+//       batch, publishes it as done, waits for the host to publish the next
+//       one and copies its descriptor into device memory;
+//   A   energy + gradient adjoint of the batch's atoms (adjoint_split_atom,
+//       the sorf_predict kernel's per-atom work);
+//   B   force tiles (force_tile, two tiles per workgroup at a time);
+//   C   forces and energies (force_entry, molecule_energy) written straight
+//       into the batch's host-coherent result slot.
+// Every result is summed in the order sorf_predict uses, so a request's
+// energy and forces are bitwise those of sorf_predict on it alone. Every wait
+// is bounded: a wait that exceeds its limit ends the kernel with state 3.
+__device__ __forceinline__ unsigned long long serve_load(unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+// constant-rate real-time counter (the device's wall clock)
+__device__ __forceinline__ int64_t serve_now() {
+  return int64_t(__builtin_amdgcn_s_memrealtime());
+}
+
+// Grid-wide barrier number `n` (counted from 0 over the kernel's life):
+// returns false when the wait limit was reached.
+// Every thread releases its own writes at device scope before the workgroup
+// arrives, and acquires after the wait.
+__device__ __forceinline__ bool serve_barrier(unsigned long long* bar, unsigned long long n,
+                                              int64_t limit, int* lds_ok) {
+  __threadfence();
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    __hip_atomic_fetch_add(&bar[0], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    const unsigned long long target = (n + 1) * gridDim.x;
+    const int64_t t0 = serve_now();
+    int ok = 1;
+    while (serve_load(&bar[0]) < target) {
+      __builtin_amdgcn_s_sleep(1);
+      if (serve_now() - t0 > limit) { ok = 0; break; }
+    }
+    *lds_ok = ok;
+  }
+  __syncthreads();
+  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+  return *lds_ok != 0;
+}
+
+template <int LOG_D, int LOG_EPL>
+__global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void serve_kernel(
+    ServeKernelArgs a) {
+  constexpr int DV = 1 << LOG_D;
+  __shared__ float red[kAdjMaxWaves][DV];
+  __shared__ float ered[kAdjMaxWaves];
+  __shared__ float fred[2][4][64];
+  __shared__ int s_ok;
+  __shared__ int64_t s_flag;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t G = gridDim.x, b = blockIdx.x;
+  unsigned long long nbar = 0;   // barriers passed
+  for (int64_t k = 0;; ++k) {
+    // ---- B0: batch boundary
+    __threadfence_system();   // this thread's result writes have reached the host
+    __syncthreads();
+    if (tid == 0)
+      __hip_atomic_fetch_add(&a.bar[0], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+    if (b == 0) {
+      if (tid == 0) {
+        int64_t flag = 1;   // 1: run, 0: exit (stop or idle), -1: exit (limit)
+        const unsigned long long target = (nbar + 1) * G;
+        int64_t t0 = serve_now();
+        while (serve_load(&a.bar[0]) < target) {
+          __builtin_amdgcn_s_sleep(1);
+          if (serve_now() - t0 > a.wait_ticks) { flag = -1; break; }
+        }
+        if (flag == 1) {
+          // batches before k are complete and their results written
+          __hip_atomic_store(&a.ctl->done, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+          t0 = serve_now();
+          while (__hip_atomic_load(&a.ctl->head, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) <= k) {
+            if (__hip_atomic_load(&a.ctl->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) {
+              flag = 0;
+              __hip_atomic_store(&a.ctl->state, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+              break;
+            }
+            __builtin_amdgcn_s_sleep(2);
+            if (serve_now() - t0 > a.idle_ticks) {
+              flag = 0;
+              __hip_atomic_store(&a.ctl->state, 2, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+              break;
+            }
+          }
+        } else {
+          __hip_atomic_store(&a.ctl->state, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        }
+        s_flag = flag;
+      }
+      __syncthreads();
+      // copy the descriptor (or an exit command) into device memory
+      const int64_t words = int64_t(sizeof(ServeDesc) / sizeof(int64_t));
+      const int64_t* src = reinterpret_cast<const int64_t*>(&a.ring[k % a.ring_slots]);
+      int64_t* dst = reinterpret_cast<int64_t*>(a.dev_desc);
+      for (int64_t w = tid; w < words; w += blockDim.x) {
+        int64_t v = 0;
+        if (s_flag == 1)
+          v = __hip_atomic_load(&src[w], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+        if (w == 2 && s_flag != 1) v = -1;   // n_req < 0: exit
+        dst[w] = v;
+      }
+      __syncthreads();
+      if (tid == 0) {
+        __threadfence();
+        __hip_atomic_store(&a.bar[1], nbar + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      }
+    } else if (tid == 0) {
+      // covers workgroup 0's two waits: the arrivals and the host
+      const int64_t t0 = serve_now();
+      int ok = 1;
+      while (serve_load(&a.bar[1]) < nbar + 1) {
+        __builtin_amdgcn_s_sleep(2);
+        if (serve_now() - t0 > a.idle_ticks + 2 * a.wait_ticks) { ok = 0; break; }
+      }
+      s_ok = ok;
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    if (b != 0 && !s_ok) return;
+    ++nbar;
+    const ServeDesc* d = a.dev_desc;
+    const int64_t n_req = d->n_req;
+    if (n_req < 0) return;
+    const int64_t n_atoms = d->n_atoms, atom0 = d->atom0;
+
+    // ---- A: adjoint of every atom, one atom per workgroup at a time
+    for (int64_t i = b; i < n_atoms; i += G)
+      adjoint_split_atom<LOG_D, LOG_EPL>(i, a.n_waves, a.x_pool + atom0 * DV, a.element_pool + atom0,
+                                         a.signs, a.bias, a.alpha, a.grad, a.e_atom, a.n_stacks,
+                                         a.n_transforms, a.c_rev, a.g_scale, a.e_scale, red, ered);
+    if (!serve_barrier(a.bar, nbar++, a.wait_ticks, &s_ok)) return;
+
+    // ---- B: force tiles, two per workgroup at a time (waves 0-3 and 4-7)
+    const int64_t total = d->tile_start[n_req];
+    const int half = wv >> 2, wq = wv & 3;
+    const int64_t rounds = (total + 2 * G - 1) / (2 * G);
+    for (int64_t r = 0; r < rounds; ++r) {
+      const int64_t t = 2 * (r * G + b) + half;
+      force_tile(t < total, t, d->mol_ptr, n_req, d->tile_start, d->part_start, a.grad, a.J_pool,
+                 d->j_ptr, a.partial, DV, wq, lane, fred[half]);
+    }
+    if (!serve_barrier(a.bar, nbar++, a.wait_ticks, &s_ok)) return;
+
+    // ---- C: forces and energies into the host result slot [E (max requests) | F]
+    float* out = a.results + d->slot * a.slot_floats;
+    for (int64_t q = b * blockDim.x + tid; q < 3 * n_atoms; q += G * blockDim.x)
+      out[kServeMaxRequests + q] = force_entry(q, d->mol_ptr, n_req, d->part_start, a.partial, DV);
+    for (int64_t m = b * blockDim.x + tid; m < n_req; m += G * blockDim.x)
+      out[m] = molecule_energy(d->mol_ptr[m], d->mol_ptr[m + 1], a.e_atom);
+  }
+}
+
+template <int LOG_D>
+static hipError_t serve_dispatch(const ServeKernelArgs& a, int grid, hipStream_t st) {
+  constexpr int LOG_EPL = default_log_epl<LOG_D>();
+  ServeKernelArgs args = a;
+  void* params[] = {&args};
+  return hipLaunchCooperativeKernel(reinterpret_cast<const void*>(&serve_kernel<LOG_D, LOG_EPL>),
+                                    dim3(unsigned(grid)), dim3(512), params, 0, st);
+}
+
 }  // namespace sorf
 
 using namespace sorf;
+
+size_t sorf_serve_scratch_bytes(int32_t d, int64_t max_atoms) {
+  auto al = [](size_t v) { return (v + 255) & ~size_t(255); };
+  return al(sizeof(ServeDesc)) + al(2 * sizeof(unsigned long long)) +
+         al(sizeof(float) * size_t(max_atoms) * size_t(d)) + al(sizeof(float) * size_t(max_atoms)) +
+         al(sizeof(float) * size_t(kForceMaxChunks) * 3 * size_t(max_atoms));
+}
+
+
+int sorf_adjoint_waves(int32_t d, int32_t n_stacks) {
+  int log_d = 0;
+  while ((1 << log_d) < d) ++log_d;
+  const int log_epl = log_d < 5 ? log_d : 5;
+  const int vpw = 64 >> (log_d - log_epl);
+  const int64_t passes = (int64_t(n_stacks) + vpw - 1) / vpw;
+  return int(passes < kAdjMaxWaves ? passes : kAdjMaxWaves);
+}
+
+void sorf_adjoint_scales(const SorfFeatureArgs& a, float* c_rev, float* g_scale, float* e_scale) {
+  const double D = double(a.d) * a.n_stacks;
+  const double c = double(sorf_c(a));
+  *c_rev = float(c * (1.0 / (2.0 * M_PI)));
+  *g_scale = float(-std::sqrt(2.0 / D) * c);
+  *e_scale = float(std::sqrt(2.0 / D));
+}
+
 
 #define SORF_LOGD_SWITCH(LOGD, CALL) \
   switch (LOGD) {                    \
@@ -765,4 +989,10 @@ hipError_t sorf_launch_fill(float* p, int64_t n, float v, hipStream_t st) {
   if (blocks > 4096) blocks = 4096;
   hipLaunchKernelGGL(fill_kernel, dim3(unsigned(blocks)), dim3(256), 0, st, p, n, v);
   return hipGetLastError();
+}
+
+hipError_t sorf_launch_serve(const ServeKernelArgs& a, int grid, hipStream_t st) {
+#define CALL(L) serve_dispatch<L>(a, grid, st)
+  SORF_LOGD_SWITCH(log2i(a.d), CALL)
+#undef CALL
 }

@@ -199,6 +199,78 @@ struct SorfFeatureArgs {
   int64_t n_atoms, n_mols;
 };
 
+// Force contraction shape of a molecule of n atoms: its J block is
+// [n d rows][3 n columns]; rows are cut into min(ceil(n d / 256), 32) chunks
+// and columns into 64-column blocks. It depends on the molecule alone, so its
+// forces are summed in the same order in any batch.
+constexpr int64_t kForceRowChunk = 256;
+constexpr int64_t kForceMaxChunks = 32;
+struct ForceShape {
+  int64_t nrc;    // row chunks
+  int64_t ncb;    // 64-column blocks
+  int64_t chunk;  // rows per chunk (last may be shorter)
+};
+__host__ __device__ inline ForceShape force_shape(int64_t n, int32_t d) {
+  ForceShape f;
+  const int64_t rows = n * d;
+  const int64_t c = (rows + kForceRowChunk - 1) / kForceRowChunk;
+  f.nrc = c < kForceMaxChunks ? c : kForceMaxChunks;
+  f.chunk = f.nrc > 0 ? (rows + f.nrc - 1) / f.nrc : 0;
+  f.ncb = (3 * n + 63) / 64;
+  return f;
+}
+
+// Persistent serving kernel (energies and forces of batches of requests).
+// The host publishes batches in a ring of descriptors in host-coherent
+// memory and counts them in ServeControl::head; the kernel, resident on
+// every compute unit, takes them in order, writes energies and forces into
+// the batch's host-coherent result slot and counts finished batches in
+// ServeControl::done.
+constexpr int kServeMaxRequests = 64;
+struct ServeDesc {
+  int64_t atom0;        // pool index of the batch's first atom (its requests are contiguous)
+  int64_t n_atoms;
+  int64_t n_req;        // < 0: the kernel exits
+  int64_t slot;         // result slot
+  int64_t mol_ptr[kServeMaxRequests + 1];     // atom offsets relative to atom0
+  int64_t j_ptr[kServeMaxRequests + 1];       // float offsets of the J blocks in the J pool
+  int64_t tile_start[kServeMaxRequests + 1];  // force tiles of the requests before each
+  int64_t part_start[kServeMaxRequests + 1];  // force partial floats before each
+};
+struct ServeControl {
+  int64_t head;      // batches published (host)
+  int64_t done;      // batches finished (device)
+  int32_t stop;      // host: finish the published batches and exit
+  int32_t state;     // device: 0 running, 1 exited on stop, 2 exited idle, 3 exited on a wait limit
+};
+struct ServeKernelArgs {
+  int32_t d, n_stacks, n_transforms, n_waves;
+  const uint32_t* signs;
+  const float* bias;
+  const float* alpha;
+  const float* x_pool;
+  const int32_t* element_pool;
+  const float* J_pool;
+  const ServeDesc* ring;          // host-coherent, ring_slots descriptors
+  ServeControl* ctl;              // host-coherent
+  float* results;                 // host-coherent, ring_slots x slot_floats
+  int64_t ring_slots, slot_floats, max_atoms;
+  ServeDesc* dev_desc;            // device scratch: the current batch
+  unsigned long long* bar;        // device scratch: [0] arrivals, [1] release generation
+  float* grad;                    // device scratch [max_atoms][d]
+  float* e_atom;                  // device scratch [max_atoms]
+  float* partial;                 // device scratch [kForceMaxChunks * 3 * max_atoms]
+  float c_rev, g_scale, e_scale;
+  int64_t idle_ticks, wait_ticks;   // limits on the constant-rate real-time counter
+};
+// Waves per atom of the energy + force adjoint and its scale factors (the
+// serving kernel uses the same, so its results equal sorf_predict's).
+int sorf_adjoint_waves(int32_t d, int32_t n_stacks);
+void sorf_adjoint_scales(const SorfFeatureArgs& a, float* c_rev, float* g_scale, float* e_scale);
+size_t sorf_serve_scratch_bytes(int32_t d, int64_t max_atoms);
+// grid: resident workgroups (one per compute unit); cooperative launch
+hipError_t sorf_launch_serve(const ServeKernelArgs& a, int grid, hipStream_t s);
+
 hipError_t sorf_launch_forward(const SorfFeatureArgs& a, float* Z, hipStream_t s);
 // E[m] = sum_f alpha_f Z[m][f] without storing Z; part: n_mols * n_stacks floats.
 hipError_t sorf_launch_energies(const SorfFeatureArgs& a, const float* alpha, float* part,

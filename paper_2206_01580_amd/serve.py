@@ -70,11 +70,13 @@ class BatchingScheduler:
     device memory the batch holds until it completes."""
 
     def __init__(self, executor, max_batch_atoms: int, max_inflight: int, mem_budget: int,
-                 clock: Callable[[], float] = time.perf_counter, idle: Callable[[], None] = None):
+                 clock: Callable[[], float] = time.perf_counter, idle: Callable[[], None] = None,
+                 max_batch_requests: Optional[int] = None):
         self.ex = executor
         self.max_batch_atoms = max_batch_atoms
         self.max_inflight = max_inflight
         self.mem_budget = mem_budget
+        self.max_batch_requests = max_batch_requests
         self.clock = clock
         self.idle = idle or (lambda: None)
 
@@ -121,6 +123,8 @@ class BatchingScheduler:
                 while pending and pending[0] == last:
                     n = int(sizes[last])
                     if last > first and atoms + n > self.max_batch_atoms:
+                        break
+                    if self.max_batch_requests is not None and last - first >= self.max_batch_requests:
                         break
                     if used + self.ex.bytes_for(first, last + 1) > self.mem_budget:
                         break
@@ -299,3 +303,99 @@ def request_results(executor: GpuExecutor, sizes) -> dict:
             out[r] = (float(E[r - a]), F[3 * off: 3 * (off + n)].copy())
             off += n
     return out
+
+
+# --------------------------------------------------------------------------
+# Native executor: the library's persistent serving kernel
+# --------------------------------------------------------------------------
+
+class _ServerHandle:
+    def __init__(self, server, ticket, first, last):
+        self.server, self.ticket, self.first, self.last = server, ticket, first, last
+        self._done = False
+
+    def done(self) -> bool:
+        if not self._done:
+            q = self.server.lib.sorf_server_query(self.server.h, self.ticket)
+            if q < 0:
+                raise RuntimeError(f"serving kernel exited before batch {self.ticket} (query {q})")
+            if q == 1:
+                self.server._collect(self)
+                self._done = True
+        return self._done
+
+
+class NativeServer:
+    """Executor over sorf_server_*: one persistent kernel resident on the GPU
+    takes batches from a ring in host-coherent memory (a descriptor write per
+    batch, no launch, copy or event) and writes energies and forces straight
+    into host-coherent result slots. Batches are runs of contiguous requests
+    of the staged pool, as the scheduler forms them; at most ``ring_slots``
+    are in flight and each holds at most 64 requests."""
+
+    MAX_REQUESTS = 64
+
+    def __init__(self, model, alpha, pool: RequestPool, max_batch_atoms: int, ring_slots: int = 8,
+                 idle_timeout_s: float = 60.0, device="cuda", copy_back: bool = True):
+        import ctypes
+        import torch
+        from . import _lib
+        self.ctypes, self.lib, self._lib = ctypes, _lib.load(), _lib
+        self.pool, self.copy_back = pool, copy_back
+        self.ring_slots = ring_slots
+        self.max_batch_atoms = max_batch_atoms
+        cfg = _lib.SorfServerConfig(max_batch_atoms, ring_slots, idle_timeout_s)
+        m = model.c_struct()
+        nbytes = self.lib.sorf_server_workspace_bytes(ctypes.byref(m), ctypes.byref(cfg))
+        if nbytes == 0:
+            raise ValueError("invalid model or server configuration")
+        self.ws = torch.empty(nbytes + 256, dtype=torch.uint8, device=device)
+        ws = self.ws.data_ptr() + ((-self.ws.data_ptr()) % 256)
+        self.stream = torch.cuda.Stream(device=device)     # default priority
+        torch.cuda.synchronize()
+        h = ctypes.c_void_p()
+        _lib.check("sorf_server_start", self.lib.sorf_server_start(
+            ctypes.byref(m), alpha.data_ptr(), pool.x.data_ptr(), pool.element.data_ptr(),
+            pool.J.data_ptr(), ctypes.byref(cfg), ws, nbytes, self.stream.cuda_stream,
+            ctypes.byref(h)))
+        self.h = h
+        self._keep = (model, alpha, pool)
+        self.results = {}
+        self._ticket = ctypes.c_int64()
+
+    def bytes_for(self, first: int, last: int) -> int:
+        """Result-slot bytes a batch holds until it is collected."""
+        n = int(self.pool.atom_ptr[last] - self.pool.atom_ptr[first])
+        return 12 * n + 4 * (last - first)
+
+    def slot_bytes(self) -> int:
+        return 12 * self.max_batch_atoms + 4 * self.MAX_REQUESTS
+
+    def submit(self, first: int, last: int) -> _ServerHandle:
+        ctypes, pool = self.ctypes, self.pool
+        ao = np.ascontiguousarray(pool.atom_ptr[first:last + 1], dtype=np.int64)
+        jo = np.ascontiguousarray(pool.J_off[first:last], dtype=np.int64)
+        rc = self.lib.sorf_server_submit(self.h, last - first, ao.ctypes.data, jo.ctypes.data,
+                                         ctypes.byref(self._ticket))
+        self._lib.check("sorf_server_submit", rc)
+        return _ServerHandle(self, self._ticket.value, first, last)
+
+    def _collect(self, hnd: _ServerHandle):
+        if not self.copy_back:
+            return
+        n_req = hnd.last - hnd.first
+        n_at = int(self.pool.atom_ptr[hnd.last] - self.pool.atom_ptr[hnd.first])
+        e = self.lib.sorf_server_energies(self.h, hnd.ticket)
+        f = self.lib.sorf_server_forces(self.h, hnd.ticket)
+        self.results[(hnd.first, hnd.last)] = (np.ctypeslib.as_array(e, shape=(n_req,)).copy(),
+                                              np.ctypeslib.as_array(f, shape=(3 * n_at,)).copy())
+
+    def stop(self) -> int:
+        """Stops the kernel (after the published batches); returns its exit state."""
+        if self.h is None:
+            return 0
+        st = self.ctypes.c_int32(0)
+        rc = self.lib.sorf_server_stop(self.h, self.ctypes.byref(st))
+        self.h = None
+        self._lib.check("sorf_server_stop", rc)
+        return int(st.value)

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.sorf_abi_version() == 6
+    assert lib.sorf_abi_version() == 7
 
 
 def test_struct_layout_matches_c(tmp_path):
@@ -298,3 +298,32 @@ def test_forces_argument_checks(lib):
     assert F(*args) == _lib.SORF_ERR_WORKSPACE
     # no atoms: nothing to do, nothing required
     assert F(64, 0, 3, PTR, None, None, None, None, None, 0, None) == _lib.SORF_OK
+
+
+def test_server_host_checks(lib):
+    """sorf_server_*: invalid configurations and pointers are refused before any HIP
+    call; queries on a NULL server are refused."""
+    m = _model(d=64, n_stacks=4)
+    Cfg = _lib.SorfServerConfig
+    good = Cfg(1024, 4, 1.0)
+    assert lib.sorf_server_workspace_bytes(ctypes.byref(m), ctypes.byref(good)) > 1024 * 64 * 4
+    for bad in (Cfg(0, 4, 1.0), Cfg(1024, 0, 1.0), Cfg(1024, 65, 1.0), Cfg(1024, 4, 0.0),
+                Cfg(1 << 25, 4, 1.0)):
+        assert lib.sorf_server_workspace_bytes(ctypes.byref(m), ctypes.byref(bad)) == 0
+    bad_model = _model(d=3)
+    assert lib.sorf_server_workspace_bytes(ctypes.byref(bad_model), ctypes.byref(good)) == 0
+    h = ctypes.c_void_p(123)
+    assert lib.sorf_server_start(ctypes.byref(m), PTR, PTR, PTR, None, ctypes.byref(good), PTR,
+                                 1 << 30, None, ctypes.byref(h)) == _lib.SORF_ERR_INVALID_ARG
+    assert h.value is None     # cleared on failure
+    assert lib.sorf_server_start(ctypes.byref(m), PTR, PTR, PTR, PTR, ctypes.byref(good), None,
+                                 1 << 30, None, ctypes.byref(h)) == _lib.SORF_ERR_WORKSPACE
+    assert lib.sorf_server_start(ctypes.byref(m), PTR, PTR, PTR, PTR, ctypes.byref(good), 257,
+                                 1 << 30, None, ctypes.byref(h)) == _lib.SORF_ERR_WORKSPACE
+    t = ctypes.c_int64()
+    ao = (ctypes.c_int64 * 2)(0, 5)
+    assert lib.sorf_server_submit(None, 1, ao, ao, ctypes.byref(t)) == _lib.SORF_ERR_INVALID_ARG
+    assert lib.sorf_server_query(None, 0) == -2
+    assert not lib.sorf_server_energies(None, 0)
+    assert lib.sorf_server_stop(None, None) == _lib.SORF_ERR_INVALID_ARG
+    assert lib.sorf_status_string(_lib.SORF_ERR_BUSY) == b"SORF_ERR_BUSY"

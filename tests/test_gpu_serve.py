@@ -131,3 +131,91 @@ def test_staggered_arrivals_at_the_serving_shape():
         blk = Jd[int(tr.J_off[r]):int(tr.J_off[r]) + nJ].cpu().numpy()
         Fo = O.forces(g, blk, np.array([0, nJ]), ptr)
         assert np.abs(res_b[r][1].astype(np.float64) - Fo).max() <= 1e-5 * np.abs(Fo).max()
+
+
+def _predict_solo(tr, Jd, model, alpha, r):
+    """sorf_predict on request r alone (its Jacobian block at its pool offset)."""
+    from paper_2206_01580_amd import sorf
+    a0, n = int(np.sum(tr.sizes[:r])), int(tr.sizes[r])
+    batch = sorf.Batch(torch.from_numpy(np.ascontiguousarray(tr.x[a0:a0 + n])).cuda(),
+                       torch.from_numpy(np.ascontiguousarray(tr.element[a0:a0 + n])).cuda(),
+                       torch.tensor([0, n], dtype=torch.int64, device="cuda"))
+    jp = torch.tensor([int(tr.J_off[r]), 0], dtype=torch.int64, device="cuda")
+    E, F = sorf.Predictor(model)(batch, alpha, Jd, jp)
+    torch.cuda.synchronize()
+    return float(E.cpu().numpy()[0]), F.cpu().numpy()
+
+
+@pytest.mark.parametrize("shape", [(128, 128, 20000.0, 48), (32, 8, 200000.0, 300)],
+                         ids=["d128-S128", "d32-S8-many"])
+def test_native_server_equals_predict_bitwise(shape):
+    """The persistent serving kernel (sorf_server_*): requests arrive on the
+    clock while earlier batches are on the device (d = 128, D = 16384, 5..300
+    atoms, about one every 50 us; and a stream of small d = 32 requests fast
+    enough that batches reach the 64-request limit). Every request's energy and
+    forces are bitwise those of sorf_predict on it alone; the kernel stops on
+    request."""
+    from paper_2206_01580_amd import serve, sorf
+    d, S_, rate, R = shape
+    tr = W.serving_trace(rate_hz=rate, duration_s=1.0, max_requests=R, j_pool_floats=1 << 24,
+                         d=d, n_stacks=S_)
+    Jd = W.device_normal(tr.J_pool_floats, tr.J_seed, 0.1)
+    pool = serve.RequestPool(tr.x, tr.element, tr.sizes, Jd, tr.J_off)
+    model = sorf.Model.from_problem(tr.model)
+    alpha = torch.from_numpy(tr.model.alpha).cuda()
+    R = len(tr.sizes)
+    cap = 8192
+    print(f"native server: d {d}, {S_} stacks, {R} requests, {int(tr.sizes.sum())} atoms", flush=True)
+    srv = serve.NativeServer(model, alpha, pool, max_batch_atoms=cap, ring_slots=4, idle_timeout_s=5.0)
+    try:
+        st = serve.BatchingScheduler(srv, cap, 4, 1 << 40, max_batch_requests=64).run(tr.arrival_s, tr.sizes)
+    finally:
+        state = srv.stop()
+    assert state == 1, state
+    res = serve.request_results(srv, tr.sizes)
+    assert sorted(res) == list(range(R))
+    sizes = [b - a for a, b in st.batches]
+    print("batches:", len(st.batches), "largest", max(sizes), "beside in-flight",
+          st.summary()["launches_beside_inflight"])
+    if d == 32:
+        assert max(sizes) == 64           # the per-batch request limit is reached
+    for r in range(R):
+        E, F = _predict_solo(tr, Jd, model, alpha, r)
+        assert np.float32(res[r][0]).tobytes() == np.float32(E).tobytes(), r
+        assert res[r][1].tobytes() == F.tobytes(), r
+
+
+def test_native_server_idle_exit_and_busy_ring():
+    """A server with one ring slot: a second batch submitted before the first
+    is done gets SORF_ERR_BUSY (or goes through if the first already finished);
+    with no batches the kernel exits on its idle timeout and reports it."""
+    import ctypes
+    from paper_2206_01580_amd import _lib, serve, sorf
+    tr = W.serving_trace(rate_hz=1000.0, duration_s=1.0, max_requests=4, j_pool_floats=1 << 22,
+                         d=32, n_stacks=8)
+    Jd = W.device_normal(tr.J_pool_floats, tr.J_seed, 0.1)
+    pool = serve.RequestPool(tr.x, tr.element, tr.sizes, Jd, tr.J_off)
+    model = sorf.Model.from_problem(tr.model)
+    alpha = torch.from_numpy(tr.model.alpha).cuda()
+    srv = serve.NativeServer(model, alpha, pool, max_batch_atoms=1024, ring_slots=1, idle_timeout_s=0.5)
+    lib = srv.lib
+    ao = np.ascontiguousarray(pool.atom_ptr[0:2], dtype=np.int64)
+    jo = np.ascontiguousarray(pool.J_off[0:1], dtype=np.int64)
+    t = ctypes.c_int64()
+    assert lib.sorf_server_submit(srv.h, 1, ao.ctypes.data, jo.ctypes.data, ctypes.byref(t)) == 0
+    rc = lib.sorf_server_submit(srv.h, 1, ao.ctypes.data, jo.ctypes.data, ctypes.byref(t))
+    assert rc in (_lib.SORF_OK, _lib.SORF_ERR_BUSY)
+    # invalid batches are refused before anything is published
+    bad = np.array([0, 0], dtype=np.int64)
+    assert lib.sorf_server_submit(srv.h, 1, bad.ctypes.data, jo.ctypes.data, ctypes.byref(t)) == \
+        _lib.SORF_ERR_INVALID_ARG
+    assert lib.sorf_server_submit(srv.h, 65, ao.ctypes.data, jo.ctypes.data, ctypes.byref(t)) == \
+        _lib.SORF_ERR_INVALID_ARG
+    import time
+    t0 = time.perf_counter()
+    while lib.sorf_server_query(srv.h, 0) == 0 and time.perf_counter() - t0 < 5.0:
+        pass
+    assert lib.sorf_server_query(srv.h, 0) == 1
+    time.sleep(1.5)                      # longer than the idle timeout
+    state = srv.stop()
+    assert state == 2, state
