@@ -433,9 +433,11 @@ sorf_status sorf_forces(int32_t d, int64_t n_atoms, int64_t n_mols, const int64_
  * whatever batch it is served in.
  * Exceptions to the conventions above: sorf_server_start allocates the ring,
  * control word and result slots in pinned host memory (hipHostMalloc) and
- * sorf_server_stop frees them; while the kernel runs, other work on the device
- * competes with it for compute units; sorf_server_stop blocks until the kernel
- * has exited. A server is used from one host thread at a time.
+ * sorf_server_stop frees them; while the kernel runs it holds nearly all the
+ * vector registers of every compute unit, so other kernels on the device wait
+ * until it exits (sorf_server_stop, or the idle timeout): a served device serves
+ * only; sorf_server_stop blocks until the kernel has exited. A server is used
+ * from one host thread at a time.
  * --------------------------------------------------------------------------- */
 typedef struct sorf_server sorf_server;   /* opaque, owned by the caller between start and stop */
 typedef struct {

@@ -703,8 +703,8 @@ static hipError_t adjoint_dispatch(const SorfFeatureArgs& a, const float* alpha,
 // Every result is summed in the order sorf_predict uses, so a request's
 // energy and forces are bitwise those of sorf_predict on it alone. Every wait
 // is bounded: a wait that exceeds its limit ends the kernel with state 3.
-__device__ __forceinline__ unsigned long long serve_load(unsigned long long* p) {
-  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+__device__ __forceinline__ unsigned long long serve_poll(unsigned long long* p) {
+  return __hip_atomic_load(p, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
 }
 // constant-rate real-time counter (the device's wall clock)
 __device__ __forceinline__ int64_t serve_now() {
@@ -713,25 +713,29 @@ __device__ __forceinline__ int64_t serve_now() {
 
 // Grid-wide barrier number `n` (counted from 0 over the kernel's life):
 // returns false when the wait limit was reached.
-// Every thread releases its own writes at device scope before the workgroup
-// arrives, and acquires after the wait.
+// One thread per workgroup carries the synchronisation: after the workgroup
+// barrier (every wave's stores have reached the compute unit's L2) it
+// releases at device scope, which writes the L2 back once for the whole
+// workgroup, and after the wait it acquires once (one L2 invalidation)
+// before the second workgroup barrier lets the other waves read. The wait
+// itself polls with relaxed loads: an acquire load would invalidate the L2
+// on every poll and make the workgroups that are still working miss.
 __device__ __forceinline__ bool serve_barrier(unsigned long long* bar, unsigned long long n,
                                               int64_t limit, int* lds_ok) {
-  __threadfence();
   __syncthreads();
   if (threadIdx.x == 0) {
     __hip_atomic_fetch_add(&bar[0], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
     const unsigned long long target = (n + 1) * gridDim.x;
     const int64_t t0 = serve_now();
     int ok = 1;
-    while (serve_load(&bar[0]) < target) {
+    while (serve_poll(&bar[0]) < target) {
       __builtin_amdgcn_s_sleep(1);
       if (serve_now() - t0 > limit) { ok = 0; break; }
     }
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     *lds_ok = ok;
   }
   __syncthreads();
-  __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
   return *lds_ok != 0;
 }
 
@@ -748,26 +752,27 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void s
   const int64_t G = gridDim.x, b = blockIdx.x;
   unsigned long long nbar = 0;   // barriers passed
   for (int64_t k = 0;; ++k) {
-    // ---- B0: batch boundary
-    __threadfence_system();   // this thread's result writes have reached the host
+    // ---- B0: batch boundary. The workgroup's result writes (host memory)
+    // are released at system scope by one thread, after the workgroup barrier.
     __syncthreads();
     if (tid == 0)
-      __hip_atomic_fetch_add(&a.bar[0], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+      __hip_atomic_fetch_add(&a.bar[0], 1ull, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
     if (b == 0) {
       if (tid == 0) {
         int64_t flag = 1;   // 1: run, 0: exit (stop or idle), -1: exit (limit)
         const unsigned long long target = (nbar + 1) * G;
         int64_t t0 = serve_now();
-        while (serve_load(&a.bar[0]) < target) {
+        while (serve_poll(&a.bar[0]) < target) {
           __builtin_amdgcn_s_sleep(1);
           if (serve_now() - t0 > a.wait_ticks) { flag = -1; break; }
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // every workgroup's results, system scope
         if (flag == 1) {
           // batches before k are complete and their results written
           __hip_atomic_store(&a.ctl->done, k, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
           t0 = serve_now();
-          while (__hip_atomic_load(&a.ctl->head, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM) <= k) {
-            if (__hip_atomic_load(&a.ctl->stop, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_SYSTEM)) {
+          while (__hip_atomic_load(&a.ctl->head, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM) <= k) {
+            if (__hip_atomic_load(&a.ctl->stop, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM)) {
               flag = 0;
               __hip_atomic_store(&a.ctl->state, 1, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
               break;
@@ -782,6 +787,7 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void s
         } else {
           __hip_atomic_store(&a.ctl->state, 3, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
         }
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "");   // the descriptor published with head
         s_flag = flag;
       }
       __syncthreads();
@@ -797,22 +803,20 @@ __global__ __launch_bounds__(512) __attribute__((amdgpu_waves_per_eu(2))) void s
         dst[w] = v;
       }
       __syncthreads();
-      if (tid == 0) {
-        __threadfence();
+      if (tid == 0)
         __hip_atomic_store(&a.bar[1], nbar + 1, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
-      }
     } else if (tid == 0) {
       // covers workgroup 0's two waits: the arrivals and the host
       const int64_t t0 = serve_now();
       int ok = 1;
-      while (serve_load(&a.bar[1]) < nbar + 1) {
+      while (serve_poll(&a.bar[1]) < nbar + 1) {
         __builtin_amdgcn_s_sleep(2);
         if (serve_now() - t0 > a.idle_ticks + 2 * a.wait_ticks) { ok = 0; break; }
       }
+      __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");   // the descriptor
       s_ok = ok;
     }
     __syncthreads();
-    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
     if (b != 0 && !s_ok) return;
     ++nbar;
     const ServeDesc* d = a.dev_desc;

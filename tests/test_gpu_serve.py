@@ -146,13 +146,13 @@ def _predict_solo(tr, Jd, model, alpha, r):
     return float(E.cpu().numpy()[0]), F.cpu().numpy()
 
 
-@pytest.mark.parametrize("shape", [(128, 128, 20000.0, 48), (32, 8, 200000.0, 300)],
+@pytest.mark.parametrize("shape", [(128, 128, 20000.0, 48), (32, 8, 2.0e7, 300)],
                          ids=["d128-S128", "d32-S8-many"])
 def test_native_server_equals_predict_bitwise(shape):
     """The persistent serving kernel (sorf_server_*): requests arrive on the
     clock while earlier batches are on the device (d = 128, D = 16384, 5..300
-    atoms, about one every 50 us; and a stream of small d = 32 requests fast
-    enough that batches reach the 64-request limit). Every request's energy and
+    atoms, about one every 50 us; and a burst of 300 small d = 32 requests
+    within 15 us, so that batches reach the 64-request limit). Every request's energy and
     forces are bitwise those of sorf_predict on it alone; the kernel stops on
     request."""
     from paper_2206_01580_amd import serve, sorf
