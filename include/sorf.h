@@ -224,9 +224,10 @@ sorf_status sorf_fchl19_forward(const float* R, const int32_t* element, const in
  *   dR[a] = d(sum_i g_i . rho_i) / dR_a,  so that for g = dE/drho the forces are -dR
  * (the representation's backward pass, GPU impl. of the Representation subsection).
  *   g: [n_atoms][length] FP32 (dE/drho); dR: [n_atoms][3] FP32 out; other arguments as
- *   sorf_fchl19_forward. At most 512 atoms per molecule and 512 neighbours per atom (the
- *   molecule's rows are NaN otherwise). Each molecule is summed in a fixed order
- *   (deterministic). No workspace. */
+ *   sorf_fchl19_forward. Molecules of any size; an atom with more than 512 neighbours gets a
+ *   NaN row (in a molecule of at most 512 atoms none can have more). Every row is summed in an
+ *   order fixed by its molecule alone (deterministic, the same alone as inside any batch).
+ *   No workspace. */
 sorf_status sorf_fchl19_backward(const float* R, const int32_t* element, const int64_t* mol_ptr,
                                  int64_t n_atoms, int64_t n_mols, int32_t n_elements,
                                  const sorf_fchl19_params* params, const float* g, float* dR,

@@ -66,17 +66,17 @@ def _fcut(r, rcut):
 
 
 def _molecule(P, el, n_elements, prm):
-    """rho of the atoms of one molecule: P [N, 3] float64 (may require grad)."""
+    """rho of the atoms of one molecule: P [N, 3] (may require grad), in P's dtype."""
     N = P.shape[0]
     n2, n3 = prm["n2"], prm["n3"]
     rc = prm["rcut"]
     size = fchl19_size(n_elements, n2, n3)
     out = []
-    Rs2 = torch.tensor([rc * (k + 1) / n2 for k in range(n2)], dtype=torch.float64)
-    Rs3 = torch.tensor([rc * k / (n3 - 1) for k in range(n3)], dtype=torch.float64)
+    Rs2 = torch.tensor([rc * (k + 1) / n2 for k in range(n2)], dtype=P.dtype)
+    Rs3 = torch.tensor([rc * k / (n3 - 1) for k in range(n3)], dtype=P.dtype)
     angw = 2.0 * math.exp(-prm["zeta"] ** 2 / 2.0)
     for i in range(N):
-        rho = torch.zeros(size, dtype=torch.float64)
+        rho = torch.zeros(size, dtype=P.dtype)
         with torch.no_grad():
             dist = torch.sqrt(torch.sum((P - P[i]) ** 2, dim=1))
         near = [j for j in range(N) if j != i and float(dist[j]) < rc]
@@ -111,7 +111,9 @@ def _molecule(P, el, n_elements, prm):
             fc = _fcut(rij, rc) * _fcut(rjk, rc) * _fcut(rik, rc)
             rad = math.sqrt(prm["eta3"] / math.pi) * torch.exp(
                 -prm["eta3"] * ((rij + rik)[:, None] / 2.0 - Rs3[None, :]) ** 2)
-            sin_i = torch.sqrt(torch.clamp(1.0 - cos_i * cos_i, min=1e-300))
+            sin_i = torch.sqrt(torch.clamp(1.0 - cos_i * cos_i,
+                                            min=1e-300 if P.dtype == torch.float64
+                                            else torch.finfo(P.dtype).tiny))
             w = xi * fc * angw
             vals = torch.stack([rad * (w * cos_i)[:, None], rad * (w * sin_i)[:, None]], dim=2)
             a_el, b_el = eln[ia], eln[ib]
@@ -121,27 +123,32 @@ def _molecule(P, el, n_elements, prm):
             idx = base[:, None] + torch.arange(2 * n3)[None, :]
             rho = rho.index_add(0, idx.reshape(-1), vals.reshape(-1))
         out.append(rho)
-    return torch.stack(out) if out else torch.zeros((0, size), dtype=torch.float64)
+    return torch.stack(out) if out else torch.zeros((0, size), dtype=P.dtype)
 
 
-def fchl19(R, element, mol_ptr, n_elements: int, prm: dict, requires_grad: bool = False):
-    """rho [A, size] float64 for atoms at R [A, 3] (Angstrom) with element ids
+def fchl19(R, element, mol_ptr, n_elements: int, prm: dict, requires_grad: bool = False,
+           dtype=torch.float64):
+    """rho [A, size] (float64 by default) for atoms at R [A, 3] (Angstrom) with element ids
     ``element`` in [0, n_elements), molecules in CSR form ``mol_ptr``.
-    Returns (rho, R_tensor) so that a caller can differentiate."""
-    Rt = torch.tensor(np.asarray(R, dtype=np.float64), requires_grad=requires_grad)
+    Returns (rho, R_tensor) so that a caller can differentiate. ``dtype``
+    torch.float32 evaluates the same definition in FP32 arithmetic (the
+    rounding floor a test of FP32 code can compare against)."""
+    Rt = torch.tensor(np.asarray(R, dtype=np.float64), dtype=dtype, requires_grad=requires_grad)
     el = np.asarray(element)
     ptr = np.asarray(mol_ptr, dtype=np.int64)
     parts = [_molecule(Rt[ptr[m]:ptr[m + 1]], el[ptr[m]:ptr[m + 1]], n_elements, prm)
              for m in range(len(ptr) - 1)]
     size = fchl19_size(n_elements, prm["n2"], prm["n3"])
-    rho = torch.cat(parts) if parts else torch.zeros((0, size), dtype=torch.float64)
+    rho = torch.cat(parts) if parts else torch.zeros((0, size), dtype=dtype)
     return rho, Rt
 
 
-def fchl19_grad(R, element, mol_ptr, n_elements: int, prm: dict, g) -> np.ndarray:
-    """d(sum_i g_i . rho_i)/dR [A, 3] float64: the coordinate gradient of an
-    energy whose derivative with respect to the representation is g [A, size]."""
-    rho, Rt = fchl19(R, element, mol_ptr, n_elements, prm, requires_grad=True)
-    L = torch.sum(rho * torch.tensor(np.asarray(g, dtype=np.float64)))
+def fchl19_grad(R, element, mol_ptr, n_elements: int, prm: dict, g,
+                dtype=torch.float64) -> np.ndarray:
+    """d(sum_i g_i . rho_i)/dR [A, 3]: the coordinate gradient of an energy
+    whose derivative with respect to the representation is g [A, size]
+    (float64 arithmetic; ``dtype`` as in fchl19)."""
+    rho, Rt = fchl19(R, element, mol_ptr, n_elements, prm, requires_grad=True, dtype=dtype)
+    L = torch.sum(rho * torch.tensor(np.asarray(g, dtype=np.float64), dtype=dtype))
     (dR,) = torch.autograd.grad(L, Rt, allow_unused=True)
     return np.zeros(Rt.shape) if dR is None else dR.numpy()

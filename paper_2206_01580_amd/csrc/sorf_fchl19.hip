@@ -838,10 +838,7 @@ __global__ __launch_bounds__(256) void fchl19_backward_kernel(
   const int64_t a0 = mol_ptr[m];
   const int N = int(mol_ptr[m + 1] - a0);
   if (N <= kFchlSmallAtoms) return;   // fchl19_backward_small_kernel
-  if (N > kFchlBwdMaxAtoms) {   // more atoms than the LDS holds: mark the rows, do not guess
-    for (int t = tid; t < 3 * N; t += 256) dR[3 * a0 + t] = __builtin_nanf("");
-    return;
-  }
+  if (N > kFchlBwdMaxAtoms) return;   // fchl19_backward_gather_kernel
   const float rc = p.rcut;
   const float kPi = 3.14159265358979f;
   for (int t = tid; t < N; t += 256) {
@@ -1024,6 +1021,219 @@ __global__ __launch_bounds__(256) void fchl19_backward_kernel(
   }
 }
 
+// Molecules above kFchlBwdMaxAtoms atoms (any size): one workgroup per atom
+// t gathers the gradient at R_t from every centre whose representation
+// depends on it, t itself and each neighbour c of t:
+//   centre t: -dL/dr (R_s - R_t) / r_ts for the two-body term of every
+//     neighbour s, and -(dL/da (R_j - R_t) / a + dL/db (R_l - R_t) / b) for
+//     every unordered neighbour pair {j, l} (a = r_tj, b = r_tl);
+//   centre c: dL/dr (R_t - R_c) / r_ct for t's two-body term, and for every
+//     other neighbour l of c the pair {t, l}, with sides a = r_ct, b = r_cl,
+//     c = r_tl: dL/da (R_t - R_c) / a + dL/dc (R_t - R_l) / c.
+// The three-body terms are symmetric in the pair's two atoms (the mean
+// distance, the centre's angle and the product of the three cosines do not
+// change when j and l swap), so the pair's sides may be passed in either
+// order. t's neighbours are gathered into LDS as in the forward kernel
+// (kFchlMaxNb at most; more leave t's row NaN); c's neighbours are scanned
+// straight from the molecule's positions. Each thread sums a fixed subset of
+// the terms and the threads' sums are added in thread order: the result is
+// deterministic and does not depend on the rest of the batch; the sums are
+// FP64, since an atom of a large molecule gathers thousands of terms. Every pair
+// derivative of a centre is evaluated once for each of the pair's atoms (three
+// times over), the price of needing no workspace and no bound on the size.
+__device__ void fchl19_backward_atom(int64_t t, int64_t a0, int64_t a1,
+                                     const float* __restrict__ R,
+                                     const int32_t* __restrict__ element, int32_t E,
+                                     const FchlParams& p, int64_t size,
+                                     const float* __restrict__ g, float* __restrict__ dR) {
+  __shared__ int32_t nidx[kFchlMaxNb];
+  __shared__ float nx[kFchlMaxNb], ny[kFchlMaxNb], nz[kFchlMaxNb], nr[kFchlMaxNb];
+  __shared__ int32_t grp[kFchlMaxElements + 1];
+  __shared__ int32_t wcount[4];
+  __shared__ int64_t seg[kFchlMaxElements * (kFchlMaxElements + 1) / 2 + 1];
+  __shared__ double red[3][256];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const float rc = p.rcut;
+  const float angw = 2.0f * expf(-0.5f * p.zeta * p.zeta) * sqrtf(p.eta3 / 3.14159265358979f);
+  const int NP = E * (E + 1) / 2;
+  const float xt = R[3 * t], yt = R[3 * t + 1], zt = R[3 * t + 2];
+  const int et = element[t];
+
+  // t's neighbours grouped by element, atom order inside a group
+  int total = 0;
+  for (int X = 0; X < E; ++X) {
+    if (tid == 0) grp[X] = total;
+    for (int64_t j0 = a0; j0 < a1; j0 += 256) {
+      const int64_t j = j0 + tid;
+      float dx = 0.f, dy = 0.f, dz = 0.f, r = 0.f;
+      bool f = false;
+      if (j < a1 && j != t && element[j] == X) {
+        dx = R[3 * j] - xt;
+        dy = R[3 * j + 1] - yt;
+        dz = R[3 * j + 2] - zt;
+        r = sqrtf(dx * dx + dy * dy + dz * dz);
+        f = r < rc;
+      }
+      const uint64_t mask = __ballot(f);
+      const int before = __popcll(mask & ((uint64_t(1) << lane) - 1));
+      if (lane == 0) wcount[wv] = __popcll(mask);
+      __syncthreads();
+      int off = total;
+      for (int w = 0; w < wv; ++w) off += wcount[w];
+      const int chunk = wcount[0] + wcount[1] + wcount[2] + wcount[3];
+      if (f && off + before < kFchlMaxNb) {
+        const int sl = off + before;
+        nidx[sl] = int32_t(j - a0);
+        nx[sl] = dx;
+        ny[sl] = dy;
+        nz[sl] = dz;
+        nr[sl] = r;
+      }
+      total += chunk;
+      __syncthreads();
+    }
+  }
+  const bool bad = total > kFchlMaxNb;   // uniform: every thread counted the same chunks
+  double px = 0.0, py = 0.0, pz = 0.0;   // FP64 sums: a large centre adds thousands of terms
+  if (!bad) {
+    if (tid == 0) {
+      grp[E] = total;
+      int64_t o = 0;
+      for (int X = 0; X < E; ++X)
+        for (int Y = X; Y < E; ++Y) {
+          seg[fchl_pair(X, Y, E)] = o;
+          const int64_t cxn = grp[X + 1] - grp[X], cyn = grp[Y + 1] - grp[Y];
+          o += X == Y ? cxn * (cxn - 1) / 2 : cxn * cyn;
+        }
+      seg[NP] = o;
+    }
+    __syncthreads();
+    const float* __restrict__ gt = g + t * size;
+    // centre t, two-body
+    for (int sl = tid; sl < total; sl += 256) {
+      int X = 0;
+      while (sl >= grp[X + 1]) ++X;
+      const float r = nr[sl];
+      const float f = fchl_pair_grad(r, gt + X * p.n2, p) / r;
+      px -= f * nx[sl];
+      py -= f * ny[sl];
+      pz -= f * nz[sl];
+    }
+    // centre t, three-body over its unordered neighbour pairs
+    const int64_t n_pairs = seg[NP];
+    for (int64_t q = tid; q < n_pairs; q += 256) {
+      int P = 0;
+      while (q >= seg[P + 1]) ++P;
+      int X = 0;
+      while (fchl_pair(X, X, E) + (E - X) <= P) ++X;
+      const int Y = X + (P - fchl_pair(X, X, E));
+      const int64_t loc = q - seg[P];
+      int sa, sb;
+      if (X != Y) {
+        const int cyn = grp[Y + 1] - grp[Y];
+        sa = grp[X] + int(loc / cyn);
+        sb = grp[Y] + int(loc % cyn);
+      } else {
+        const int cxn = grp[X + 1] - grp[X];
+        const double c2x = 2.0 * cxn - 1.0;
+        int u = int((c2x - sqrt(c2x * c2x - 8.0 * double(loc))) * 0.5);
+        if (u < 0) u = 0;
+        while (u > 0 && int64_t(u) * (2 * cxn - u - 1) / 2 > loc) --u;
+        while (int64_t(u + 1) * (2 * cxn - u - 2) / 2 <= loc) ++u;
+        sa = grp[X] + u;
+        sb = grp[X] + u + 1 + int(loc - int64_t(u) * (2 * cxn - u - 1) / 2);
+      }
+      const float a = nr[sa], b = nr[sb];
+      const float wx = nx[sb] - nx[sa], wy = ny[sb] - ny[sa], wz = nz[sb] - nz[sa];
+      const float c = sqrtf(wx * wx + wy * wy + wz * wz);
+      if (!(c < rc)) continue;   // f_cut(r_jl) and its derivative vanish
+      float dL[3];
+      fchl_triple_grad(a, b, c, gt + int64_t(E) * p.n2 + int64_t(P) * p.n3 * 2, p, angw, dL);
+      const float fa = dL[0] / a, fb = dL[1] / b;
+      px -= fa * nx[sa] + fb * nx[sb];
+      py -= fa * ny[sa] + fb * ny[sb];
+      pz -= fa * nz[sa] + fb * nz[sb];
+    }
+    // each neighbour c of t as a centre
+    for (int cs = 0; cs < total; ++cs) {
+      const int64_t c_at = a0 + nidx[cs];
+      const float* __restrict__ gc = g + c_at * size;
+      const float rct = nr[cs];
+      const float ux = -nx[cs], uy = -ny[cs], uz = -nz[cs];   // R_t - R_c
+      if (tid == 0) {
+        const float f = fchl_pair_grad(rct, gc + et * p.n2, p) / rct;
+        px += f * ux;
+        py += f * uy;
+        pz += f * uz;
+      }
+      const float xc = R[3 * c_at], yc = R[3 * c_at + 1], zc = R[3 * c_at + 2];
+      for (int64_t l = a0 + tid; l < a1; l += 256) {
+        if (l == t || l == c_at) continue;
+        const float lx = R[3 * l], ly = R[3 * l + 1], lz = R[3 * l + 2];
+        const float vx = lx - xc, vy = ly - yc, vz = lz - zc;
+        const float rcl = sqrtf(vx * vx + vy * vy + vz * vz);
+        if (!(rcl < rc)) continue;
+        const float wx = lx - xt, wy = ly - yt, wz = lz - zt;   // R_l - R_t
+        const float rtl = sqrtf(wx * wx + wy * wy + wz * wz);
+        if (!(rtl < rc)) continue;
+        const int el = element[l];
+        const int P = et <= el ? fchl_pair(et, el, E) : fchl_pair(el, et, E);
+        float dL[3];
+        fchl_triple_grad(rct, rcl, rtl, gc + int64_t(E) * p.n2 + int64_t(P) * p.n3 * 2, p, angw,
+                         dL);
+        const float fa = dL[0] / rct, fc = dL[2] / rtl;
+        px += fa * ux - fc * wx;
+        py += fa * uy - fc * wy;
+        pz += fa * uz - fc * wz;
+      }
+    }
+  }
+  red[0][tid] = px;
+  red[1][tid] = py;
+  red[2][tid] = pz;
+  __syncthreads();
+  if (tid < 3) {
+    double sum = 0.0;
+    for (int k = 0; k < 256; ++k) sum += red[tid][k];
+    dR[3 * t + tid] = bad ? __builtin_nanf("") : float(sum);
+  }
+  __syncthreads();   // red[], the neighbour list and seg[] are rewritten for the next atom
+}
+
+// Molecules above kFchlBwdMaxAtoms atoms: a resident grid (three workgroups
+// per compute unit) deals their atoms out, atom j of molecule m to workgroup
+// (m + j) mod G, as the forward kernel deals the atoms of large molecules.
+__global__ __launch_bounds__(256) void fchl19_backward_gather_kernel(
+    const float* __restrict__ R, const int32_t* __restrict__ element,
+    const int64_t* __restrict__ mol_ptr, int64_t n_mols, int32_t E, FchlParams p, int64_t size,
+    const float* __restrict__ g, float* __restrict__ dR) {
+  __shared__ int32_t big[256];
+  __shared__ int32_t wbig[4];
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  const int64_t G = gridDim.x, b = blockIdx.x;
+  for (int64_t m0 = 0; m0 < n_mols; m0 += 256) {
+    const int64_t m = m0 + tid;
+    const bool large = m < n_mols && mol_ptr[m + 1] - mol_ptr[m] > kFchlBwdMaxAtoms;
+    const uint64_t mask = __ballot(large);
+    if (lane == 0) wbig[wv] = __popcll(mask);
+    __syncthreads();
+    int off = 0, nbig = 0;
+    for (int w = 0; w < 4; ++w) {
+      off += w < wv ? wbig[w] : 0;
+      nbig += wbig[w];
+    }
+    if (large) big[off + __popcll(mask & ((uint64_t(1) << lane) - 1))] = tid;
+    __syncthreads();
+    for (int k = 0; k < nbig; ++k) {
+      const int64_t mm = m0 + big[k];
+      const int64_t a0 = mol_ptr[mm], a1 = mol_ptr[mm + 1];
+      for (int64_t j = ((b - mm) % G + G) % G; j < a1 - a0; j += G)
+        fchl19_backward_atom(a0 + j, a0, a1, R, element, E, p, size, g, dR);
+    }
+    __syncthreads();   // big[] and wbig[] are rewritten by the next group of molecules
+  }
+}
+
 }  // namespace sorf
 
 using namespace sorf;
@@ -1079,5 +1289,8 @@ hipError_t sorf_launch_fchl19_backward(const float* R, const int32_t* element,
     e = hipGetLastError();
     if (e != hipSuccess) return e;
   }
-  return hipSuccess;
+  // molecules above kFchlBwdMaxAtoms atoms: a resident grid, one workgroup per atom
+  hipLaunchKernelGGL(fchl19_backward_gather_kernel, dim3(768u), dim3(256), 0, st, R, element,
+                     mol_ptr, n_mols, E, p, size, g, dR);
+  return hipGetLastError();
 }

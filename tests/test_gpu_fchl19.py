@@ -113,8 +113,9 @@ def test_fchl19_too_many_neighbours_gives_nan_rows():
     el = np.zeros(600, np.int32)
     rho = gpu_rho(R, el, np.array([0, 600]), 1, PRM)
     assert np.all(np.isnan(rho))
-    # the backward holds at most 512 atoms of a molecule: all 600 rows are NaN,
-    # and a small molecule in the same batch is unaffected
+    # the backward refuses the same atoms (more neighbours than its LDS list
+    # holds): all 600 rows are NaN, and a small molecule in the same batch is
+    # unaffected
     R2 = np.concatenate([R, W.host_geometries([9], seed=4)]).astype(np.float32)
     el2 = np.zeros(609, np.int32)
     ptr2 = np.array([0, 600, 609])
@@ -263,3 +264,85 @@ def test_fchl19_molecule_results_independent_of_the_batch():
     dR_one = gpu_grad(R[a0:a1], el[a0:a1], [0, a1 - a0], 5, PRM, g[a0:a1])
     assert np.array_equal(rho_all[a0:a1], rho_one)
     assert np.array_equal(dR_all[a0:a1], dR_one)
+
+
+def _cluster_grad_case(sizes, stretches, seed):
+    """Molecules of the given sizes (each from the synthetic generator, scaled
+    by its stretch) with random elements and upstream gradient."""
+    parts = [W.host_geometries([n], seed=seed + k).astype(np.float64) * st
+             for k, (n, st) in enumerate(zip(sizes, stretches))]
+    R = np.concatenate(parts).astype(np.float32)
+    rng = np.random.default_rng(seed)
+    el = rng.integers(0, 5, size=sum(sizes)).astype(np.int32)
+    ptr = np.r_[0, np.cumsum(sizes)].astype(np.int64)
+    g = rng.standard_normal((sum(sizes), 720)).astype(np.float32)
+    return R, el, ptr, g
+
+
+def test_fchl19_myoglobin_sized_molecule():
+    """One 1260-atom molecule (the size of the paper's myoglobin timing) at a
+    protein-like density (7..133 neighbours within r_cut, 74 on average): the
+    forward rows match the oracle with the bound of the other tests, and no
+    row is NaN. The backward (per-atom gather kernel) is held to the larger of
+    that bound and twice the FP32 floor of this molecule: the oracle's own
+    formulas evaluated in FP32 are 3.5e-5 of the molecule's scale off the
+    FP64 result here (near-collinear triples, where sin(theta) and its
+    derivative -cos/sin lose precision in FP32), so 2e-5 is below what FP32
+    arithmetic can deliver for this input."""
+    R, el, ptr, g = _cluster_grad_case([1260], [1.6], seed=51)
+    print("forward", flush=True)
+    rel = check(R, el, ptr, 5, PRM)
+    print(f"forward: max row error / row scale {rel:.2e}", flush=True)
+    got = gpu_grad(R, el, ptr, 5, PRM, g).astype(np.float64)
+    assert not np.isnan(got).any()
+    ref = F.fchl19_grad(R.astype(np.float64), el, ptr, 5, PRM, g.astype(np.float64))
+    ref32 = F.fchl19_grad(R, el, ptr, 5, PRM, g, dtype=torch.float32)
+    err, scale = np.abs(got - ref).max(), np.abs(ref).max()
+    floor = np.abs(ref32 - ref).max()
+    print(f"backward: max gradient error / molecule scale {err / scale:.2e} "
+          f"(FP32 evaluation of the oracle: {floor / scale:.2e})")
+    assert err <= max(2e-5 * scale, 2.0 * floor)
+
+
+def test_fchl19_backward_molecules_above_512_atoms():
+    """A molecule of 560 atoms at a compact density (25..372 neighbours, 190
+    on average) goes to the per-atom gather kernel, beside small molecules of
+    the other two kernels in one call. Each molecule meets the per-molecule
+    bound of the other backward tests against the oracle, and the large
+    molecule's rows are bitwise the same alone as in the batch."""
+    sizes, stretches = [13, 560, 9], [1.0, 1.0, 1.0]
+    R, el, ptr, g = _cluster_grad_case(sizes, stretches, seed=41)
+    got = gpu_grad(R, el, ptr, 5, PRM, g).astype(np.float64)
+    worst = 0.0
+    for m in range(len(sizes)):
+        a0, a1 = int(ptr[m]), int(ptr[m + 1])
+        print(f"molecule {m}: {a1 - a0} atoms", flush=True)
+        ref = F.fchl19_grad(R[a0:a1].astype(np.float64), el[a0:a1], [0, a1 - a0], 5, PRM,
+                            g[a0:a1].astype(np.float64))
+        scale = np.abs(ref).max()
+        err = np.abs(got[a0:a1] - ref).max()
+        worst = max(worst, err / scale)
+        assert err <= 2e-5 * scale, (m, err / scale)
+    print(f"max gradient error / molecule scale {worst:.2e}")
+    a0, a1 = int(ptr[1]), int(ptr[2])
+    one = gpu_grad(R[a0:a1], el[a0:a1], [0, a1 - a0], 5, PRM, g[a0:a1])
+    assert np.array_equal(one, got[a0:a1].astype(np.float32))
+
+
+def test_fchl19_backward_large_molecule_nan_only_where_the_list_overflows():
+    """A 530-atom molecule: 514 atoms packed in a 3 A box (each has at least
+    513 neighbours, more than the 512 the list holds: NaN rows) and, 50 A
+    away, a 16-atom cluster whose rows match the oracle on the cluster alone
+    (no atom of the box is within the cutoff of it)."""
+    rng = np.random.default_rng(43)
+    box = rng.uniform(0.0, 3.0, size=(514, 3))
+    far = W.host_geometries([16], seed=44).astype(np.float64) + 50.0
+    R = np.concatenate([box, far]).astype(np.float32)
+    el = rng.integers(0, 3, size=530).astype(np.int32)
+    L = F.fchl19_size(3, PRM["n2"], PRM["n3"])
+    g = rng.standard_normal((530, L)).astype(np.float32)
+    dR = gpu_grad(R, el, [0, 530], 3, PRM, g)
+    assert np.all(np.isnan(dR[:514]))
+    ref = F.fchl19_grad(R[514:].astype(np.float64), el[514:], [0, 16], 3, PRM,
+                        g[514:].astype(np.float64))
+    assert np.abs(dR[514:] - ref).max() <= 2e-5 * np.abs(ref).max()
