@@ -19,9 +19,11 @@
 // summation in the spirit of the paper's compensated sum); this also cuts
 // the FP32 mode's error by an order of magnitude.
 //
-// Work split. FP32 modes: one workgroup (4 waves, 2 x 2, one per SIMD) per
-// 256 x 128 tile (I, J) of the lower triangle, each wave 128 x 64 (4 x 2 MFMA
-// 32x32 blocks). hi+lo modes (and the split mode's tail): 8 waves (4 x 2, two
+// Work split. FP32 modes: 8 waves (4 x 2, two per SIMD) per 256 x 128 tile
+// (I, J) of the lower triangle, each wave 64 x 64 (2 x 2 MFMA 32x32 blocks),
+// rows staged through a global-to-LDS ring; when the tiles alone would leave
+// compute units idle, a tile's rows are split into slices whose sums are
+// combined in slice order. hi+lo modes (and the split mode's tail): 8 waves (4 x 2, two
 // per SIMD) per 256 x 128 tile, each wave 64 x 64 (2 x 2 blocks). Single
 // product modes (and the split mode's int8 head): 8 waves (2 x 4) per 256 x 256
 // tile, each wave 128 x 64. The 256 x 128 tiles are dealt to the XCDs in
@@ -59,6 +61,8 @@ constexpr int TM = 256, TN = 128;      // workgroup tile
 constexpr int kFlushRows = 256;        // rows per fresh MFMA accumulator
 constexpr int kPackSlabs = 64;         // 16-row slabs per pack workgroup (Z^T y chunk)
 constexpr int kFP32Waves = 8;          // waves of the FP32 ring kernel (4 or 8)
+constexpr int kFP32StageRows = 32;     // rows per ring stage, plain FP32 (8% faster than 16)
+constexpr int kFP32KahanStageRows = 16;   // Kahan: 32 rows would spill 44 registers
 
 __host__ __device__ constexpr bool is_hilo(int mode) {
   return mode == kBF16HiLo || mode == kFP16HiLo || mode == kSplitCross;
@@ -1006,26 +1010,31 @@ __device__ __forceinline__ void flush_sum(f32x16 (&P)[BA][BB], f32x16 (&S)[BA][B
 }
 
 // ------------------------------------------------ FP32 mode, D % 4 == 0
-// Stage = 16 rows of Z: 16 A rows of 256 floats (one wave copy each) and 16 B
-// rows of 128 floats (one copy per pair of rows), in a ring of 4 stages.
+// Stage = SR rows of Z: SR A rows of 256 floats (one wave copy each) and SR B
+// rows of 128 floats (one copy per pair of rows), in a ring of 4 stages of 16
+// rows or 3 of 32. Plain FP32 uses 32 (fewer stage barriers and copy waits per
+// row: 14.1 against 15.3 ms at 20,000 x 8192), the Kahan mode 16 (32 would
+// spill 44 registers).
 // Rows past M are copied from a 1 KB block of zeros; columns past D are
 // clamped into the row (they only reach G entries that are never written).
 // NW = 8 (used): eight waves (4 x 2, two per SIMD) of 64 x 64, so that while
 // one wave of a SIMD waits on the stage barrier or its LDS reads the other
 // keeps the matrix core busy; the Kahan mode then spills 6 registers (47 with
 // NW = 4: four waves, one per SIMD, of 128 x 64).
-template <bool KAHAN, int NW>
+template <bool KAHAN, int NW, int SR>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
                            int64_t nI, int64_t nJ, const float* __restrict__ zeros,
                            float* __restrict__ G, SlicePlan plan, float* __restrict__ part) {
-  constexpr int NS = 4;
-  constexpr int PW = 24 / NW;                  // copies per wave per stage (16 A + 8 B pairs)
-  constexpr int KC = kFlushRows / KB;
+  static_assert(SR == 16 || SR == 32, "stage rows");
+  constexpr int NS = SR == 16 ? 4 : 3;         // ring depth: 96 or 144 kilobytes of LDS
+  constexpr int PW = (SR + SR / 2) / NW;       // copies per wave per stage (SR A rows + SR/2 B pairs)
+  static_assert(PW * NW == SR + SR / 2, "copies per stage");
+  constexpr int KC = kFlushRows / SR;
   constexpr int WR = TM / (NW / 2), WC = TN / 2;   // wave tile
   constexpr int BA = WR / 32, BB = WC / 32;
-  __shared__ float ra[NS][KB][TM];
-  __shared__ float rb[NS][KB][TN];
+  __shared__ float ra[NS][SR][TM];
+  __shared__ float rb[NS][SR][TN];
 
   int64_t I, J;
   const int64_t sp = blockIdx.x / plan.grid1;
@@ -1041,22 +1050,22 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
   // this item's rows [r0, r1)
   const int64_t r0 = sp * plan.rows_per;
   const int64_t r1 = r0 + plan.rows_per < M ? r0 + plan.rows_per : M;
-  const int64_t n_st = r1 > r0 ? (r1 - r0 + KB - 1) / KB : 0;
-  // copy c of a stage (c = wv + NW i): c < 16 is A row c, else B rows 2 (c - 16) + (0, 1)
+  const int64_t n_st = r1 > r0 ? (r1 - r0 + SR - 1) / SR : 0;
+  // copy c of a stage (c = wv + NW i): c < SR is A row c, else B rows 2 (c - SR) + (0, 1)
   auto issue = [&](int64_t st, int slot) {
-    const int64_t m0 = r0 + st * KB;
+    const int64_t m0 = r0 + st * SR;
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
       const int c = wv + NW * i;
-      if (c < KB) {
+      if (c < SR) {
         const int64_t m = m0 + c;
         const float* g = m < r1 ? Z + m * D + colA : zeros + 4 * lane;
         dma16(g, &ra[slot][c][0]);
       } else {
-        const int k = 2 * (c - KB) + (lane >> 5);
+        const int k = 2 * (c - SR) + (lane >> 5);
         const int64_t m = m0 + k;
         const float* g = m < r1 ? Z + m * D + colB : zeros + 4 * lane;
-        dma16(g, &rb[slot][2 * (c - KB)][0]);
+        dma16(g, &rb[slot][2 * (c - SR)][0]);
       }
     }
   };
@@ -1074,25 +1083,25 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
         if (KAHAN) Cc[KAHAN ? a : 0][b][r] = 0.0f;
       }
 
-  // Software pipeline over half-stages (k steps 0..3 and 4..7 of a 16-row
-  // stage): the LDS reads of one half-stage are issued while the products of
-  // the previous one run, so the matrix core keeps working across the stage
-  // barrier. All NS slots are filled up front; after the barrier that
-  // publishes stage s + 1 every wave has read all of stage s, so its slot
-  // takes stage s + NS.
-  constexpr int HK = KB / 4;   // k steps (of 2 rows) per half-stage
+  // Software pipeline over sub-stages of 8 rows (4 k steps): the LDS reads of
+  // one sub-stage are issued while the products of the previous one run, so
+  // the matrix core keeps working across the stage barrier. All NS slots are
+  // filled up front; after the barrier that publishes stage s + 1 every wave
+  // has read all of stage s, so its slot takes stage s + NS.
+  constexpr int HK = 4;            // k steps (of 2 rows) per sub-stage
+  constexpr int NSUB = SR / 8;     // sub-stages per stage (even)
   float a0[HK][BA], b0[HK][BB], a1[HK][BA], b1[HK][BB];
-  auto read_half = [&](int sl, int h, float (&af)[HK][BA], float (&bf)[HK][BB]) {
+  auto read_sub = [&](int sl, int j, float (&af)[HK][BA], float (&bf)[HK][BB]) {
 #pragma unroll
     for (int kk = 0; kk < HK; ++kk) {
-      const int k = 2 * (h * HK + kk) + (lane >> 5);
+      const int k = 2 * (j * HK + kk) + (lane >> 5);
 #pragma unroll
       for (int a = 0; a < BA; ++a) af[kk][a] = ra[sl][k][wy * WR + a * 32 + (lane & 31)];
 #pragma unroll
       for (int b = 0; b < BB; ++b) bf[kk][b] = rb[sl][k][wx * WC + b * 32 + (lane & 31)];
     }
   };
-  auto mma_half = [&](const float (&af)[HK][BA], const float (&bf)[HK][BB]) {
+  auto mma_sub = [&](const float (&af)[HK][BA], const float (&bf)[HK][BB]) {
 #pragma unroll
     for (int kk = 0; kk < HK; ++kk)
 #pragma unroll
@@ -1101,7 +1110,7 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
         for (int b = 0; b < BB; ++b)
           P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][a], bf[kk][b], P[a][b], 0, 0, 0);
   };
-  // the next half-stage's LDS reads interleaved with the first products
+  // the next sub-stage's LDS reads interleaved with the first products
   auto interleave = [] {
     constexpr int NR = HK * (BA + BB), NM = HK * BA * BB;
 #pragma unroll
@@ -1119,15 +1128,25 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
   if (n_st > 0) {
     wait_stage<PW>(n_st - 1 < NS - 1 ? n_st - 1 : NS - 1);
     stage_barrier();
-    read_half(0, 0, a0, b0);
+    read_sub(0, 0, a0, b0);
   }
   int slot = 0;
   int64_t s = 0;
   while (s < n_st) {
     const int64_t g_end = s + KC < n_st ? s + KC : n_st;
     for (; s < g_end; ++s) {
-      read_half(slot, 1, a1, b1);
-      mma_half(a0, b0);
+      // sub-stages 0 .. NSUB - 2 of stage s; sub-stage j sits in a0/b0 when j is even
+#pragma unroll
+      for (int j = 0; j + 2 < NSUB; j += 2) {
+        read_sub(slot, j + 1, a1, b1);
+        mma_sub(a0, b0);
+        interleave();
+        read_sub(slot, j + 2, a0, b0);
+        mma_sub(a1, b1);
+        interleave();
+      }
+      read_sub(slot, NSUB - 1, a1, b1);
+      mma_sub(a0, b0);
       interleave();
       const bool more = s + 1 < n_st;
       const int nslot = more ? (slot + 1 == NS ? 0 : slot + 1) : slot;
@@ -1141,8 +1160,8 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
       }
       // after the last stage this re-reads a published slot with no copy in
       // flight; the values are not used
-      read_half(nslot, 0, a0, b0);
-      mma_half(a1, b1);
+      read_sub(nslot, 0, a0, b0);
+      mma_sub(a1, b1);
       interleave();
       slot = nslot;
     }
@@ -1565,11 +1584,11 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
         float* part = reinterpret_cast<float*>(w + g.zpart_bytes + kZeroBytes);
         const dim3 rgrid{unsigned(plan.grid1 * plan.n_split)};
         if (mode == kFP32Kahan)
-          hipLaunchKernelGGL((gram_fp32_ring_kernel<true, kFP32Waves>), rgrid,
+          hipLaunchKernelGGL((gram_fp32_ring_kernel<true, kFP32Waves, kFP32KahanStageRows>), rgrid,
                              dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G,
                              plan, part);
         else
-          hipLaunchKernelGGL((gram_fp32_ring_kernel<false, kFP32Waves>), rgrid,
+          hipLaunchKernelGGL((gram_fp32_ring_kernel<false, kFP32Waves, kFP32StageRows>), rgrid,
                              dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G,
                              plan, part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
