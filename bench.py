@@ -100,7 +100,7 @@ def parse():
     ap.add_argument("--serve-rate", type=float, default=2000.0)
     ap.add_argument("--serve-slots", type=int, default=8)
     ap.add_argument("--serve-max-atoms", type=int, default=8192)
-    ap.add_argument("--serve-sweep", default="8000,32000",
+    ap.add_argument("--serve-sweep", default="5000,10000,20000,32000",
                     help="extra offered loads (req/s), each a trace of --serve-sweep-requests")
     ap.add_argument("--serve-sweep-requests", type=int, default=4000)
     ap.add_argument("--force-confs", type=int, default=2000,
