@@ -1008,6 +1008,17 @@ __device__ __forceinline__ void flush_sum(f32x16 (&P)[BA][BB], f32x16 (&S)[BA][B
         P[a][b][r] = 0.0f;
       }
 }
+// After the last flush of the Kahan mode: the sum with its carried rounding
+// error taken back, S - C, which is what leaves the kernel.
+template <int BA, int BB>
+__device__ __forceinline__ void fold_compensation(f32x16 (&S)[BA][BB], const f32x16 (&C)[BA][BB]) {
+#pragma unroll
+  for (int a = 0; a < BA; ++a)
+#pragma unroll
+    for (int b = 0; b < BB; ++b)
+#pragma unroll
+      for (int r = 0; r < 16; ++r) S[a][b][r] -= C[a][b][r];
+}
 
 // ------------------------------------------------ FP32 mode, D % 4 == 0
 // Stage = SR rows of Z: SR A rows of 256 floats (one wave copy each) and SR B
@@ -1019,8 +1030,8 @@ __device__ __forceinline__ void flush_sum(f32x16 (&P)[BA][BB], f32x16 (&S)[BA][B
 // clamped into the row (they only reach G entries that are never written).
 // NW = 8 (used): eight waves (4 x 2, two per SIMD) of 64 x 64, so that while
 // one wave of a SIMD waits on the stage barrier or its LDS reads the other
-// keeps the matrix core busy; the Kahan mode then spills 6 registers (47 with
-// NW = 4: four waves, one per SIMD, of 128 x 64).
+// keeps the matrix core busy; the Kahan mode's compensation then spills about
+// 30 registers around the flushes.
 template <bool KAHAN, int NW, int SR>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
@@ -1167,6 +1178,7 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
     }
     flush_sum<KAHAN>(P, S, Cc);
   }
+  if constexpr (KAHAN) fold_compensation(S, Cc);
 
   if (!active) return;
   if (sp > 0) {
@@ -1196,9 +1208,12 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
 }
 
 // G += the partial tiles of slices 1 .. n_split - 1 of every 256 x 128 tile
-// (slice 0 added its sum into G itself), summed in slice order. One workgroup
+// (slice 0 added its sum into G itself), summed in slice order; in the Kahan
+// mode G and the partials are summed with compensation, so that combining the
+// slices rounds once, as the unsliced kernel's final G += S does. One workgroup
 // per 4 rows of a tile, two columns per thread. Entries of waves above the
 // diagonal are never written to the partials; they are not read.
+template <bool KAHAN>
 __global__ __launch_bounds__(256) void gram_slices_combine_kernel(const float* __restrict__ part,
                                                                  int64_t n_tiles, int32_t n_split,
                                                                  int32_t D,
@@ -1212,15 +1227,34 @@ __global__ __launch_bounds__(256) void gram_slices_combine_kernel(const float* _
   const int j = (threadIdx.x & 63) * 2;
   const int64_t gi = I * TM + i, gj = J * TN + j;
   if (gi >= D || gj > gi) return;
-  float2 acc = make_float2(0.0f, 0.0f);
-  for (int sp = 1; sp < n_split; ++sp) {
-    const float2 v = *reinterpret_cast<const float2*>(
-        part + (int64_t(sp - 1) * n_tiles + t) * (TM * TN) + int64_t(i) * TN + j);
-    acc.x += v.x;
-    acc.y += v.y;
+  const bool second = gj + 1 < D && gj + 1 <= gi;
+  if constexpr (KAHAN) {
+    // G (which holds slice 0) and the partials in slice order, compensated
+    float2 sum = make_float2(G[gi * D + gj], second ? G[gi * D + gj + 1] : 0.0f);
+    float2 c = make_float2(0.0f, 0.0f);
+    for (int sp = 1; sp < n_split; ++sp) {
+      const float2 v = *reinterpret_cast<const float2*>(
+          part + (int64_t(sp - 1) * n_tiles + t) * (TM * TN) + int64_t(i) * TN + j);
+      const float yx = v.x - c.x, yy = v.y - c.y;
+      const float tx = sum.x + yx, ty = sum.y + yy;
+      c.x = (tx - sum.x) - yx;
+      c.y = (ty - sum.y) - yy;
+      sum.x = tx;
+      sum.y = ty;
+    }
+    G[gi * D + gj] = sum.x - c.x;
+    if (second) G[gi * D + gj + 1] = sum.y - c.y;
+  } else {
+    float2 acc = make_float2(0.0f, 0.0f);
+    for (int sp = 1; sp < n_split; ++sp) {
+      const float2 v = *reinterpret_cast<const float2*>(
+          part + (int64_t(sp - 1) * n_tiles + t) * (TM * TN) + int64_t(i) * TN + j);
+      acc.x += v.x;
+      acc.y += v.y;
+    }
+    G[gi * D + gj] += acc.x;
+    if (second) G[gi * D + gj + 1] += acc.y;
   }
-  G[gi * D + gj] += acc.x;
-  if (gj + 1 < D && gj + 1 <= gi) G[gi * D + gj + 1] += acc.y;
 }
 
 // ------------------------------------------------ FP32 mode, any D
@@ -1328,6 +1362,7 @@ void gram_fp32_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t
     if (s + 1 < n_stages) store(buf ^ 1);
     __syncthreads();
   }
+  if constexpr (KAHAN) fold_compensation(S, Cc);
 
   if (!active) return;
 #pragma unroll
@@ -1592,9 +1627,14 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
                              dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G,
                              plan, part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
-        if (plan.n_split > 1)
-          hipLaunchKernelGGL(gram_slices_combine_kernel, dim3(unsigned(n_tiles), unsigned(TM / 4)),
-                             blk, 0, st, part, n_tiles, plan.n_split, D, G);
+        if (plan.n_split > 1 && mode == kFP32Kahan)
+          hipLaunchKernelGGL(gram_slices_combine_kernel<true>,
+                             dim3(unsigned(n_tiles), unsigned(TM / 4)), blk, 0, st, part, n_tiles,
+                             plan.n_split, D, G);
+        else if (plan.n_split > 1)
+          hipLaunchKernelGGL(gram_slices_combine_kernel<false>,
+                             dim3(unsigned(n_tiles), unsigned(TM / 4)), blk, 0, st, part, n_tiles,
+                             plan.n_split, D, G);
       } else if (mode == kFP32Kahan) {
         hipLaunchKernelGGL((gram_fp32_kernel<false, true>), grid, blk, 0, st, Z, n_rows, D,
                            n_tiles, nI, nJ, G);
