@@ -114,6 +114,8 @@ def parse():
                     help="run the FP32 round-off study of dense-W RFF vs SORF phases (0 skips it)")
     ap.add_argument("--representation", type=int, default=1,
                     help="run the FCHL19 representation leg (0 skips it)")
+    ap.add_argument("--components", type=int, default=1,
+                    help="time the energy+force chain on single configurations (0 skips it)")
     ap.add_argument("--precision-mols", type=int, default=100000,
                     help="molecules of the precision study (0 skips it)")
     ap.add_argument("--copy-probe-mib", type=int, default=0,
@@ -541,6 +543,111 @@ def fchl19_backward_slots(nb, pairs, n2, n3):
     return 23.0 * nb * n2 + 15.0 * pairs * n3 + 160.0 * pairs
 
 
+# Single configurations of the paper's component timings: atoms, element
+# counts (in the order of the representation's bins) and the mean number of
+# neighbours within r_cut that the paper gives for each system.
+COMPONENT_SYSTEMS = (
+    ("aspirin-like", (8, 9, 4), 17.0),                 # H8 C9 O4
+    ("brass-cluster-like", (225, 20), 46.0),           # Cu225 Zn20
+    ("myoglobin-like", (632, 393, 107, 120, 8), 38.0),  # H C N O S, protein-like shares
+)
+
+
+def component_timing_leg(args, dev, log):
+    """Energy + force evaluation of one configuration at a time, component by
+    component (Results: component timings of one aspirin, one brass-cluster and
+    one myoglobin configuration at N_F = 32768 and r_cut = 6 A). Synthetic
+    molecule-like geometries of 21, 245 and 1260 atoms, scaled so that the mean
+    number of neighbours within r_cut is the paper's (17, 46, 38); elements in
+    the paper's proportions, shuffled. The chain: FCHL19 -> per-element
+    projection to d = 128 -> energies -> dE/dx (d = 128, 256 stacks: N_F =
+    32768) -> projection transpose -> FCHL19 backward (the forces). Each
+    component is timed with HIP events, median of 20 runs after warm-up."""
+    import torch
+
+    from paper_2206_01580_amd import sorf, workloads
+    prm_d = workloads.FCHL19_EF
+    prm = sorf.fchl19_params(**prm_d)
+    d, S, T = 128, 256, 3
+    names = ["fchl19_forward", "project", "energies", "dE_dx", "project_transpose",
+             "fchl19_backward"]
+    out = {}
+    for k, (name, counts, target) in enumerate(COMPONENT_SYSTEMS):
+        rng = np.random.Generator(np.random.PCG64(np.random.SeedSequence([220601580, 60 + k])))
+        n, E = int(sum(counts)), len(counts)
+        X = workloads.molecule_geometry(rng, n)
+        dist = np.sqrt(((X[:, None, :] - X[None, :, :]) ** 2).sum(-1))
+        lo, hi = 0.2, 5.0   # scale of the geometry with the target mean neighbour count
+        for _ in range(50):
+            mid = 0.5 * (lo + hi)
+            if ((dist * mid < prm_d["rcut"]).sum(1) - 1).mean() > target:
+                lo = mid
+            else:
+                hi = mid
+        X = (X * 0.5 * (lo + hi)).astype(np.float32)
+        nb = (np.sqrt(((X[:, None, :] - X[None, :, :]) ** 2).sum(-1)) < prm_d["rcut"]).sum(1) - 1
+        el_np = rng.permutation(np.repeat(np.arange(E, dtype=np.int32), counts)).astype(np.int32)
+        L = E * prm_d["n2"] + E * (E + 1) // 2 * prm_d["n3"] * 2
+        model = sorf.Model.from_arrays(workloads.draw_signs(rng, E, T, S, d),
+                                       workloads.draw_bias(rng, E, S * d), 4.0, dev)
+        alpha = torch.from_numpy(rng.standard_normal(S * d).astype(np.float32)).to(dev)
+        U = torch.from_numpy(workloads.random_projection(220601580 + 70 + k, E, L, d)).to(dev)
+        proj, projT = sorf.Projector(U), sorf.Projector(U.transpose(1, 2).contiguous())
+        Rt = torch.from_numpy(X).to(dev)
+        el = torch.from_numpy(el_np).to(dev)
+        ptr = torch.tensor([0, n], dtype=torch.int64, device=dev)
+        rho = torch.empty((n, L), device=dev)
+        x = torch.empty((n, d), device=dev)
+        gx = torch.empty((n, d), device=dev)
+        grho = torch.empty((n, L), device=dev)
+        dR = torch.empty((n, 3), device=dev)
+        Eout = torch.empty(1, device=dev)
+        predictor = sorf.Predictor(model, dev)
+        bx = sorf.Batch(x, el, ptr)
+
+        def chain(ev=None):
+            def mark(i):
+                if ev is not None:
+                    ev[i].record()
+            mark(0)
+            sorf.fchl19(Rt, el, ptr, E, prm, out=rho)
+            mark(1)
+            proj(rho, el, x)
+            mark(2)
+            predictor(bx, alpha, E=Eout)
+            mark(3)
+            sorf.backward(model, bx, alpha, out=gx)
+            mark(4)
+            projT(gx, el, grho)
+            mark(5)
+            sorf.fchl19_backward(Rt, el, ptr, E, grho, prm, out=dR)
+            mark(6)
+
+        for _ in range(3):
+            chain()
+        torch.cuda.synchronize()
+        times = {nm: [] for nm in names}
+        for _ in range(20):
+            ev = [torch.cuda.Event(enable_timing=True) for _ in range(7)]
+            chain(ev)
+            torch.cuda.synchronize()
+            for i, nm in enumerate(names):
+                times[nm].append(ev[i].elapsed_time(ev[i + 1]))
+        med = {nm: float(np.median(v)) for nm, v in times.items()}
+        total = sum(med.values())
+        out[name] = {"atoms": n, "elements": E, "mean_neighbours": float(nb.mean()),
+                     "max_neighbours": int(nb.max()), "component_ms": med, "total_ms": total,
+                     "fchl19_share": (med["fchl19_forward"] + med["fchl19_backward"]) / total,
+                     "sorf_share": (med["energies"] + med["dE_dx"]) / total}
+        log(f"components: {name} {total:.3f} ms")
+        del rho, x, gx, grho, dR
+    torch.cuda.empty_cache()
+    return {"workload": ("one configuration at a time: 21, 245 and 1260 atoms (aspirin-, brass- and "
+                         "myoglobin-like), FCHL19 energy+force parameters, d=128, 256 stacks "
+                         "(N_F=32768), energies and forces"),
+            "systems": out}
+
+
 def representation_leg(args, p, dev, log):
     """FCHL19 on the QM9-like batch (20,000 molecules, 360,149 atoms on synthetic
     molecule-like geometries, five elements, the paper's energy+force parameters,
@@ -959,6 +1066,9 @@ def main():
     if args.representation:
         log("representation")
         out["representation"] = representation_leg(args, p, dev, log)
+    if args.components:
+        log("component timings")
+        out["component_timings"] = component_timing_leg(args, dev, log)
     if args.precision_mols > 0:
         out["precision_study"] = precision_study(args, dev, log)
     if not args.no_cpu_baseline:

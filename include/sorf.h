@@ -225,7 +225,7 @@ sorf_status sorf_fchl19_forward(const float* R, const int32_t* element, const in
  * (the representation's backward pass, GPU impl. of the Representation subsection).
  *   g: [n_atoms][length] FP32 (dE/drho); dR: [n_atoms][3] FP32 out; other arguments as
  *   sorf_fchl19_forward. Molecules of any size; an atom with more than 512 neighbours gets a
- *   NaN row (in a molecule of at most 512 atoms none can have more). Every row is summed in an
+ *   NaN row. Every row is summed in an
  *   order fixed by its molecule alone (deterministic, the same alone as inside any batch).
  *   No workspace. */
 sorf_status sorf_fchl19_backward(const float* R, const int32_t* element, const int64_t* mol_ptr,

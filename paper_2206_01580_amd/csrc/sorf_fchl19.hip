@@ -525,13 +525,11 @@ __global__ __launch_bounds__(256) void fchl19_forward_small_kernel(
 // its gradient is dL/da u_ij + dL/db u_il + dL/dc u_jl distributed to the
 // three atoms; a two-body term gives dL/dr u_ij to j and minus that to i.
 //
-// One workgroup per molecule, holding the molecule's atoms and its gradient
-// in LDS and walking the centres in order. For each centre the neighbours are
-// gathered as in the forward kernel; one thread per neighbour forms its
-// two-body contribution, one thread per pair its three-body contributions,
-// and then one thread per neighbour adds, in pair order, the contributions
-// that land on its atom, while thread 0 adds the centre's: every gradient
-// entry is summed in a fixed order (deterministic, no atomics).
+// Molecules of at most kFchlSmallAtoms atoms: one workgroup per molecule
+// scatters each centre's contributions to its atoms inside LDS. Larger
+// molecules: one workgroup per atom gathers the contributions that land on
+// it from every centre, so a single large molecule spreads over the chip.
+// Every gradient entry is summed in a fixed order (deterministic, no atomics).
 // ---------------------------------------------------------------------------
 // dL/da, dL/db, dL/dc for one centre i and neighbour pair (j, l) with sides
 // a = r_ij, b = r_il, c = r_jl, where L is the pair's three-body terms
@@ -654,7 +652,7 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
   if (m >= n_mols) return;
   const int64_t a0 = mol_ptr[m];
   const int N = int(mol_ptr[m + 1] - a0);
-  if (N <= 0 || N > kFchlSmallAtoms) return;   // larger molecules: fchl19_backward_kernel
+  if (N <= 0 || N > kFchlSmallAtoms) return;   // larger molecules: fchl19_backward_gather_kernel
   const float rc = p.rcut;
   if (tid < N) {
     ax[tid] = R[3 * (a0 + tid)];
@@ -813,215 +811,7 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
   }
 }
 
-constexpr int kFchlBwdMaxAtoms = 512;    // atoms of one molecule held in LDS
-constexpr int kFchlBwdPairChunk = 512;
-
-__global__ __launch_bounds__(256) void fchl19_backward_kernel(
-    const float* __restrict__ R, const int32_t* __restrict__ element,
-    const int64_t* __restrict__ mol_ptr, int64_t m0, int64_t n_mols, int32_t E, FchlParams p,
-    int64_t size, const float* __restrict__ g, float* __restrict__ dR) {
-  __shared__ float ax[kFchlBwdMaxAtoms], ay[kFchlBwdMaxAtoms], az[kFchlBwdMaxAtoms];
-  __shared__ float gx[kFchlBwdMaxAtoms], gy[kFchlBwdMaxAtoms], gz[kFchlBwdMaxAtoms];
-  __shared__ int32_t ael[kFchlBwdMaxAtoms];
-  __shared__ int32_t nidx[kFchlMaxNb];
-  __shared__ float nx[kFchlMaxNb], ny[kFchlMaxNb], nz[kFchlMaxNb], nr[kFchlMaxNb];
-  __shared__ float sacc[3][kFchlMaxNb];
-  __shared__ int32_t grp[kFchlMaxElements + 1];
-  __shared__ int32_t wcount[4];
-  __shared__ int64_t seg[kFchlMaxElements * (kFchlMaxElements + 1) / 2 + 1];
-  __shared__ float fi[3][kFchlBwdPairChunk], fj[3][kFchlBwdPairChunk], fl[3][kFchlBwdPairChunk];
-  __shared__ int32_t qa[kFchlBwdPairChunk], qb[kFchlBwdPairChunk];
-
-  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
-  const int64_t m = m0 + blockIdx.x;
-  if (m >= n_mols) return;
-  const int64_t a0 = mol_ptr[m];
-  const int N = int(mol_ptr[m + 1] - a0);
-  if (N <= kFchlSmallAtoms) return;   // fchl19_backward_small_kernel
-  if (N > kFchlBwdMaxAtoms) return;   // fchl19_backward_gather_kernel
-  const float rc = p.rcut;
-  const float kPi = 3.14159265358979f;
-  for (int t = tid; t < N; t += 256) {
-    ax[t] = R[3 * (a0 + t)];
-    ay[t] = R[3 * (a0 + t) + 1];
-    az[t] = R[3 * (a0 + t) + 2];
-    ael[t] = element[a0 + t];
-    gx[t] = gy[t] = gz[t] = 0.0f;
-  }
-  __syncthreads();
-  const float angw = 2.0f * expf(-0.5f * p.zeta * p.zeta) * sqrtf(p.eta3 / kPi);
-  const int NP = E * (E + 1) / 2;
-  bool bad = false;
-
-  for (int ci = 0; ci < N; ++ci) {
-    const float* __restrict__ gi = g + (a0 + ci) * size;
-    // neighbours grouped by element, atom order inside a group
-    int total = 0;
-    for (int X = 0; X < E; ++X) {
-      if (tid == 0) grp[X] = total;
-      for (int j0 = 0; j0 < N; j0 += 256) {
-        const int j = j0 + tid;
-        float dx = 0.f, dy = 0.f, dz = 0.f, r = 0.f;
-        bool f = false;
-        if (j < N && j != ci && ael[j] == X) {
-          dx = ax[j] - ax[ci];
-          dy = ay[j] - ay[ci];
-          dz = az[j] - az[ci];
-          r = sqrtf(dx * dx + dy * dy + dz * dz);
-          f = r < rc;
-        }
-        const uint64_t mask = __ballot(f);
-        const int before = __popcll(mask & ((uint64_t(1) << lane) - 1));
-        if (lane == 0) wcount[wv] = __popcll(mask);
-        __syncthreads();
-        int off = total;
-        for (int w = 0; w < wv; ++w) off += wcount[w];
-        const int chunk = wcount[0] + wcount[1] + wcount[2] + wcount[3];
-        if (f && off + before < kFchlMaxNb) {
-          const int sl = off + before;
-          nidx[sl] = j;
-          nx[sl] = dx;
-          ny[sl] = dy;
-          nz[sl] = dz;
-          nr[sl] = r;
-        }
-        total += chunk;
-        __syncthreads();
-      }
-    }
-    if (total > kFchlMaxNb) {
-      bad = true;
-      break;
-    }
-    if (tid == 0) {
-      grp[E] = total;
-      int64_t o = 0;
-      for (int X = 0; X < E; ++X)
-        for (int Y = X; Y < E; ++Y) {
-          seg[fchl_pair(X, Y, E)] = o;
-          const int64_t cx = grp[X + 1] - grp[X], cy = grp[Y + 1] - grp[Y];
-          o += X == Y ? cx * (cx - 1) / 2 : cx * cy;
-        }
-      seg[NP] = o;
-    }
-    __syncthreads();
-
-    // two-body: d/dr of f_cut(r) r^-N2 LN(R_k; mu(r), sigma(r)), summed against g
-    for (int sl = tid; sl < total; sl += 256) {
-      int X = 0;
-      while (sl >= grp[X + 1]) ++X;
-      const float r = nr[sl];
-      const float dL = fchl_pair_grad(r, gi + X * p.n2, p);
-      const float inv = dL / r;
-      sacc[0][sl] = nx[sl] * inv;
-      sacc[1][sl] = ny[sl] * inv;
-      sacc[2][sl] = nz[sl] * inv;
-    }
-    __syncthreads();
-    float cx_acc = 0.f, cy_acc = 0.f, cz_acc = 0.f;   // centre's gradient (thread 0)
-    if (tid == 0)
-      for (int sl = 0; sl < total; ++sl) {
-        cx_acc -= sacc[0][sl];
-        cy_acc -= sacc[1][sl];
-        cz_acc -= sacc[2][sl];
-      }
-
-    // three-body over unordered pairs, in chunks
-    const int64_t n_pairs = seg[NP];
-    for (int64_t q0 = 0; q0 < n_pairs; q0 += kFchlBwdPairChunk) {
-      const int64_t q1 = q0 + kFchlBwdPairChunk < n_pairs ? q0 + kFchlBwdPairChunk : n_pairs;
-      for (int64_t q = q0 + tid; q < q1; q += 256) {
-        int P = 0;
-        while (q >= seg[P + 1]) ++P;
-        int X = 0;
-        while (fchl_pair(X, X, E) + (E - X) <= P) ++X;
-        const int Y = X + (P - fchl_pair(X, X, E));
-        const int64_t loc = q - seg[P];
-        int sa, sb;
-        if (X != Y) {
-          const int cy = grp[Y + 1] - grp[Y];
-          sa = grp[X] + int(loc / cy);
-          sb = grp[Y] + int(loc % cy);
-        } else {
-          const int cxn = grp[X + 1] - grp[X];
-          const double c2x = 2.0 * cxn - 1.0;
-          int u = int((c2x - sqrt(c2x * c2x - 8.0 * double(loc))) * 0.5);
-          if (u < 0) u = 0;
-          while (u > 0 && int64_t(u) * (2 * cxn - u - 1) / 2 > loc) --u;
-          while (int64_t(u + 1) * (2 * cxn - u - 2) / 2 <= loc) ++u;
-          sa = grp[X] + u;
-          sb = grp[X] + u + 1 + int(loc - int64_t(u) * (2 * cxn - u - 1) / 2);
-        }
-        // sides a = r_ij, b = r_il, c = r_jl and unit vectors i->j, i->l, j->l
-        const float a = nr[sa], b = nr[sb];
-        const float wx = nx[sb] - nx[sa], wy = ny[sb] - ny[sa], wz = nz[sb] - nz[sa];
-        const float c = sqrtf(wx * wx + wy * wy + wz * wz);
-        float dL[3];
-        fchl_triple_grad(a, b, c, gi + int64_t(E) * p.n2 + int64_t(P) * p.n3 * 2, p, angw, dL);
-        const float ua[3] = {nx[sa] / a, ny[sa] / a, nz[sa] / a};
-        const float ub[3] = {nx[sb] / b, ny[sb] / b, nz[sb] / b};
-        const float uc[3] = {wx / c, wy / c, wz / c};
-        const int sl = int(q - q0);
-#pragma unroll
-        for (int v = 0; v < 3; ++v) {
-          fi[v][sl] = -dL[0] * ua[v] - dL[1] * ub[v];
-          fj[v][sl] = dL[0] * ua[v] - dL[2] * uc[v];
-          fl[v][sl] = dL[1] * ub[v] + dL[2] * uc[v];
-        }
-        qa[sl] = sa;
-        qb[sl] = sb;
-      }
-      __syncthreads();
-      // each neighbour adds the contributions landing on it, in pair order
-      const int cnt = int(q1 - q0);
-      for (int sl = tid; sl < total; sl += 256) {
-        float sx = sacc[0][sl], sy = sacc[1][sl], sz = sacc[2][sl];
-        for (int t = 0; t < cnt; ++t) {
-          if (qa[t] == sl) {
-            sx += fj[0][t];
-            sy += fj[1][t];
-            sz += fj[2][t];
-          } else if (qb[t] == sl) {
-            sx += fl[0][t];
-            sy += fl[1][t];
-            sz += fl[2][t];
-          }
-        }
-        sacc[0][sl] = sx;
-        sacc[1][sl] = sy;
-        sacc[2][sl] = sz;
-      }
-      if (tid == 0)
-        for (int t = 0; t < cnt; ++t) {
-          cx_acc += fi[0][t];
-          cy_acc += fi[1][t];
-          cz_acc += fi[2][t];
-        }
-      __syncthreads();
-    }
-    // add this centre's contributions to the molecule's gradient
-    for (int sl = tid; sl < total; sl += 256) {
-      const int j = nidx[sl];
-      gx[j] += sacc[0][sl];
-      gy[j] += sacc[1][sl];
-      gz[j] += sacc[2][sl];
-    }
-    __syncthreads();
-    if (tid == 0) {
-      gx[ci] += cx_acc;
-      gy[ci] += cy_acc;
-      gz[ci] += cz_acc;
-    }
-    __syncthreads();
-  }
-  for (int t = tid; t < N; t += 256) {
-    dR[3 * (a0 + t)] = bad ? __builtin_nanf("") : gx[t];
-    dR[3 * (a0 + t) + 1] = bad ? __builtin_nanf("") : gy[t];
-    dR[3 * (a0 + t) + 2] = bad ? __builtin_nanf("") : gz[t];
-  }
-}
-
-// Molecules above kFchlBwdMaxAtoms atoms (any size): one workgroup per atom
+// Molecules above kFchlSmallAtoms atoms (any size): one workgroup per atom
 // t gathers the gradient at R_t from every centre whose representation
 // depends on it, t itself and each neighbour c of t:
 //   centre t: -dL/dr (R_s - R_t) / r_ts for the two-body term of every
@@ -1200,7 +990,7 @@ __device__ void fchl19_backward_atom(int64_t t, int64_t a0, int64_t a1,
   __syncthreads();   // red[], the neighbour list and seg[] are rewritten for the next atom
 }
 
-// Molecules above kFchlBwdMaxAtoms atoms: a resident grid (three workgroups
+// Molecules above kFchlSmallAtoms atoms: a resident grid (three workgroups
 // per compute unit) deals their atoms out, atom j of molecule m to workgroup
 // (m + j) mod G, as the forward kernel deals the atoms of large molecules.
 __global__ __launch_bounds__(256) void fchl19_backward_gather_kernel(
@@ -1213,7 +1003,7 @@ __global__ __launch_bounds__(256) void fchl19_backward_gather_kernel(
   const int64_t G = gridDim.x, b = blockIdx.x;
   for (int64_t m0 = 0; m0 < n_mols; m0 += 256) {
     const int64_t m = m0 + tid;
-    const bool large = m < n_mols && mol_ptr[m + 1] - mol_ptr[m] > kFchlBwdMaxAtoms;
+    const bool large = m < n_mols && mol_ptr[m + 1] - mol_ptr[m] > kFchlSmallAtoms;
     const uint64_t mask = __ballot(large);
     if (lane == 0) wbig[wv] = __popcll(mask);
     __syncthreads();
@@ -1284,12 +1074,8 @@ hipError_t sorf_launch_fchl19_backward(const float* R, const int32_t* element,
                          st, R, element, mol_ptr, m0, n_mols, E, p, size, g, dR);
     hipError_t e = hipGetLastError();
     if (e != hipSuccess) return e;
-    hipLaunchKernelGGL(fchl19_backward_kernel, dim3(unsigned(cnt)), dim3(256), 0, st, R, element,
-                       mol_ptr, m0, n_mols, E, p, size, g, dR);
-    e = hipGetLastError();
-    if (e != hipSuccess) return e;
   }
-  // molecules above kFchlBwdMaxAtoms atoms: a resident grid, one workgroup per atom
+  // molecules above kFchlSmallAtoms atoms: a resident grid, one workgroup per atom
   hipLaunchKernelGGL(fchl19_backward_gather_kernel, dim3(768u), dim3(256), 0, st, R, element,
                      mol_ptr, n_mols, E, p, size, g, dR);
   return hipGetLastError();
