@@ -59,11 +59,20 @@ sorf_status dev(hipError_t e) { return e == hipSuccess ? SORF_OK : SORF_ERR_DEVI
 
 size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
 
+// chunk offsets [n_mols + 1] and chunk partials [chunks][n_stacks] of the
+// energies-only path
+size_t energy_ws(const sorf_model* m, int64_t n_atoms, int64_t n_mols) {
+  return align256(sizeof(int64_t) * size_t(n_mols + 1)) +
+         align256(sizeof(float) * size_t(energy_chunk_bound(n_atoms, n_mols)) *
+                  size_t(m->n_stacks));
+}
+
+// [e_atom | grad | force plan] for energies with forces; the energies-only
+// path uses the energy_ws() bytes at the end.
 size_t predict_ws(const sorf_model* m, int64_t n_atoms, int64_t n_mols) {
   return align256(sizeof(float) * size_t(n_atoms)) +
          align256(sizeof(float) * size_t(n_atoms) * size_t(m->d)) +
-         sorf_force_plan_bytes(n_atoms, n_mols) +
-         align256(sizeof(float) * size_t(n_mols) * size_t(m->n_stacks));
+         sorf_force_plan_bytes(n_atoms, n_mols) + energy_ws(m, n_atoms, n_mols);
 }
 
 }  // namespace
@@ -408,12 +417,14 @@ sorf_status predict_launch(const sorf_model* model, const sorf_batch* batch, con
   const size_t need = predict_ws(model, batch->n_atoms, batch->n_mols);
   const SorfFeatureArgs a = pack(model, batch);
   if (J == nullptr) {
-    // energies only: per (molecule, stack) partials, summed in stack order
+    // energies only: per (chunk of a molecule's atoms, stack) partials
     if (batch->n_atoms == 0) return dev(sorf_launch_fill(E, batch->n_mols, 0.0f, st));
-    float* part = reinterpret_cast<float*>(static_cast<char*>(workspace) + need -
-                                           align256(sizeof(float) * size_t(batch->n_mols) *
-                                                    size_t(model->n_stacks)));
-    return dev(sorf_launch_energies(a, alpha, part, E, st));
+    char* base = static_cast<char*>(workspace) + need -
+                 energy_ws(model, batch->n_atoms, batch->n_mols);
+    int64_t* chunk_ptr = reinterpret_cast<int64_t*>(base);
+    float* part = reinterpret_cast<float*>(
+        base + align256(sizeof(int64_t) * size_t(batch->n_mols + 1)));
+    return dev(sorf_launch_energies(a, alpha, chunk_ptr, part, E, st));
   }
   float* e_atom = static_cast<float*>(workspace);
   const size_t grad_off = align256(sizeof(float) * size_t(batch->n_atoms));

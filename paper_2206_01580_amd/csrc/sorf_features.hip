@@ -31,8 +31,13 @@ __device__ __forceinline__ void lds_wave_sync() {
 // Forward features
 // ---------------------------------------------------------------------------
 // With DOT, the group does not store its features: it writes the stack's
-// share of the molecule's energy, part[m S + s] = sum_f alpha_f z_f over the
-// stack's features, summed over the group's lanes in a fixed order.
+// share of the energy of one chunk of at most kEnergyChunkAtoms atoms of a
+// molecule, part[c S + s] = sum_f alpha_f z_f over the stack's features for
+// chunk c (chunk_ptr[m] .. chunk_ptr[m + 1] - 1 are molecule m's), summed
+// over the group's lanes in a fixed order. A molecule's atoms are walked by
+// one lane group per chunk and stack, so a single large molecule still
+// spreads over the chip; a molecule of at most kEnergyChunkAtoms atoms is one
+// chunk.
 // SHARED (the stack count a multiple of the groups per wave, so that all
 // groups of a wave walk the same molecule): the wave loads the next atom's x
 // row cooperatively (d / 64 floats per lane) while it transforms the current
@@ -42,7 +47,8 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
     const float* __restrict__ x, const int32_t* __restrict__ element,
     const int64_t* __restrict__ mol_ptr, const uint32_t* __restrict__ signs,
     const float* __restrict__ bias, float* __restrict__ Z, const float* __restrict__ alpha,
-    int64_t n_mols, int32_t S, int32_t T, float c_rev, float out_scale) {
+    const int64_t* __restrict__ chunk_ptr, int64_t n_mols, int32_t S, int32_t T, float c_rev,
+    float out_scale) {
   constexpr int DV = 1 << LOG_D;
   constexpr int EPL = 1 << LOG_EPL;
   constexpr int LOGK = LOG_D - LOG_EPL;
@@ -55,11 +61,31 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
   const uint32_t grp = lane >> LOGK;
   const int64_t wave = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
   const int64_t item = wave * VPW + grp;
-  if (item >= n_mols * int64_t(S)) return;  // whole lane groups leave together
-  const int64_t m = item / S;
-  const int32_t s = int32_t(item - m * S);
-  const int64_t a0 = mol_ptr[m];
-  const int64_t a1 = mol_ptr[m + 1];
+  int64_t m, c = 0, a0, a1;
+  int32_t s;
+  if constexpr (DOT) {
+    // item = (chunk, stack); the molecule of chunk c is the m with
+    // chunk_ptr[m] <= c < chunk_ptr[m + 1]
+    if (item >= chunk_ptr[n_mols] * int64_t(S)) return;   // whole lane groups leave together
+    c = item / S;
+    s = int32_t(item - c * S);
+    int64_t lo = 0, hi = n_mols;
+    while (hi - lo > 1) {
+      const int64_t mid = (lo + hi) >> 1;
+      if (chunk_ptr[mid] <= c) lo = mid;
+      else hi = mid;
+    }
+    m = lo;
+    const int64_t m1 = mol_ptr[m + 1];
+    a0 = mol_ptr[m] + (c - chunk_ptr[m]) * kEnergyChunkAtoms;
+    a1 = a0 + kEnergyChunkAtoms < m1 ? a0 + kEnergyChunkAtoms : m1;
+  } else {
+    if (item >= n_mols * int64_t(S)) return;  // whole lane groups leave together
+    m = item / S;
+    s = int32_t(item - m * S);
+    a0 = mol_ptr[m];
+    a1 = mol_ptr[m + 1];
+  }
   const int64_t Dtot = int64_t(S) * DV;
 
   const bool odd = (__builtin_popcount(q) & 1) != 0;
@@ -150,21 +176,60 @@ __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(4))) void f
     if constexpr (LOGK > 3) p += lane_xor<3>(p);
     if constexpr (LOGK > 4) p += lane_xor<4>(p);
     if constexpr (LOGK > 5) p += lane_xor<5>(p);
-    if (q == 0) Z[m * S + s] = p * out_scale;
+    if (q == 0) Z[c * S + s] = p * out_scale;
   } else {
     store_vec<EPL>(Z + m * Dtot + int64_t(s) * DV + q * EPL, acc, out_scale);
   }
 }
 
-// E[m] = sum over the stacks of part[m S + s], in stack order.
+// E[m] = the sum of molecule m's chunk partials: one wave per molecule, lane j
+// adding the stacks j, j + 64, ... (inside a stack its chunks in order), then
+// the 64 lane sums by a fixed butterfly.
 __global__ __launch_bounds__(256) void energy_sum_kernel(const float* __restrict__ part,
+                                                        const int64_t* __restrict__ chunk_ptr,
                                                         int64_t n_mols, int32_t S,
                                                         float* __restrict__ E) {
-  const int64_t m = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
-  if (m >= n_mols) return;
+  const int64_t m = (int64_t(blockIdx.x) * blockDim.x + threadIdx.x) >> 6;
+  const int lane = int(threadIdx.x & 63);
+  if (m >= n_mols) return;   // whole waves
+  const int64_t c0 = chunk_ptr[m], c1 = chunk_ptr[m + 1];
   float e = 0.0f;
-  for (int32_t s = 0; s < S; ++s) e += part[m * S + s];
-  E[m] = e;
+  for (int32_t s = lane; s < S; s += 64)
+    for (int64_t c = c0; c < c1; ++c) e += part[c * S + s];
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) e += __shfl_xor(e, o);
+  if (lane == 0) E[m] = e;
+}
+
+// chunk_ptr[m] = sum over the molecules before m of ceil(N / kEnergyChunkAtoms)
+// (one workgroup of 1024 threads: each thread sums a contiguous run of
+// molecules, the runs' totals are scanned in LDS, then each thread writes its
+// run's offsets; chunk_ptr[n_mols] is the total).
+__global__ __launch_bounds__(1024) void energy_chunks_kernel(const int64_t* __restrict__ mol_ptr,
+                                                            int64_t n_mols,
+                                                            int64_t* __restrict__ chunk_ptr) {
+  __shared__ int64_t tot[1024];
+  const int t = threadIdx.x;
+  const int64_t per = (n_mols + 1023) / 1024;
+  const int64_t m0 = t * per < n_mols ? t * per : n_mols;
+  const int64_t m1 = m0 + per < n_mols ? m0 + per : n_mols;
+  int64_t sum = 0;
+  for (int64_t m = m0; m < m1; ++m)
+    sum += (mol_ptr[m + 1] - mol_ptr[m] + kEnergyChunkAtoms - 1) / kEnergyChunkAtoms;
+  tot[t] = sum;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {   // inclusive scan
+    const int64_t v = t >= off ? tot[t - off] : 0;
+    __syncthreads();
+    tot[t] += v;
+    __syncthreads();
+  }
+  int64_t run = tot[t] - sum;   // exclusive prefix of this thread's run
+  for (int64_t m = m0; m < m1; ++m) {
+    chunk_ptr[m] = run;
+    run += (mol_ptr[m + 1] - mol_ptr[m] + kEnergyChunkAtoms - 1) / kEnergyChunkAtoms;
+  }
+  if (t == 1023) chunk_ptr[n_mols] = tot[1023];
 }
 
 // ---------------------------------------------------------------------------
@@ -633,10 +698,12 @@ inline float sorf_c(const SorfFeatureArgs& a) {
 
 template <int LOG_D>
 static hipError_t forward_dispatch(const SorfFeatureArgs& a, float* Z, const float* alpha,
-                                   hipStream_t st) {
+                                   const int64_t* chunk_ptr, hipStream_t st) {
   constexpr int LOG_EPL = default_log_epl<LOG_D>();
   constexpr int VPW = 64 >> (LOG_D - LOG_EPL);
-  const int64_t items = a.n_mols * int64_t(a.n_stacks);
+  // energies: at most n_mols + ceil(n_atoms / kEnergyChunkAtoms) chunks per stack
+  const int64_t items = (alpha == nullptr ? a.n_mols : energy_chunk_bound(a.n_atoms, a.n_mols)) *
+                        int64_t(a.n_stacks);
   const int64_t waves = (items + VPW - 1) / VPW;
   const int64_t blocks = (waves + 3) / 4;
   const double D = double(a.d) * a.n_stacks;
@@ -649,7 +716,7 @@ static hipError_t forward_dispatch(const SorfFeatureArgs& a, float* Z, const flo
 #define SORF_FWD(DOTV, SH)                                                                     \
   hipLaunchKernelGGL((forward_kernel<LOG_D, LOG_EPL, DOTV, SH>), dim3(unsigned(blocks)),     \
                      dim3(256), 0, st, a.x, a.element, a.mol_ptr, a.signs, a.bias, Z, alpha, \
-                     a.n_mols, a.n_stacks, a.n_transforms, c_rev, scale)
+                     chunk_ptr, a.n_mols, a.n_stacks, a.n_transforms, c_rev, scale)
   if (alpha == nullptr) {
     if (share) SORF_FWD(false, kCanShare);
     else SORF_FWD(false, false);
@@ -913,25 +980,29 @@ static int log2i(int d) {
 
 hipError_t sorf_launch_forward(const SorfFeatureArgs& a, float* Z, hipStream_t st) {
   if (a.n_mols == 0) return hipSuccess;
-#define CALL(L) forward_dispatch<L>(a, Z, nullptr, st)
+#define CALL(L) forward_dispatch<L>(a, Z, nullptr, nullptr, st)
   SORF_LOGD_SWITCH(log2i(a.d), CALL)
 #undef CALL
 }
 
-static hipError_t energy_parts(const SorfFeatureArgs& a, const float* alpha, float* part,
-                               hipStream_t st) {
-#define CALL(L) forward_dispatch<L>(a, part, alpha, st)
+static hipError_t energy_parts(const SorfFeatureArgs& a, const float* alpha,
+                               const int64_t* chunk_ptr, float* part, hipStream_t st) {
+#define CALL(L) forward_dispatch<L>(a, part, alpha, chunk_ptr, st)
   SORF_LOGD_SWITCH(log2i(a.d), CALL)
 #undef CALL
 }
 
-hipError_t sorf_launch_energies(const SorfFeatureArgs& a, const float* alpha, float* part,
-                                float* E, hipStream_t st) {
+hipError_t sorf_launch_energies(const SorfFeatureArgs& a, const float* alpha, int64_t* chunk_ptr,
+                                float* part, float* E, hipStream_t st) {
   if (a.n_mols == 0) return hipSuccess;
-  hipError_t e = energy_parts(a, alpha, part, st);
+  hipLaunchKernelGGL(energy_chunks_kernel, dim3(1), dim3(1024), 0, st, a.mol_ptr, a.n_mols,
+                     chunk_ptr);
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL(energy_sum_kernel, dim3(unsigned((a.n_mols + 255) / 256)), dim3(256), 0, st,
-                     part, a.n_mols, a.n_stacks, E);
+  e = energy_parts(a, alpha, chunk_ptr, part, st);
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL(energy_sum_kernel, dim3(unsigned((a.n_mols + 3) / 4)), dim3(256), 0, st,
+                     part, chunk_ptr, a.n_mols, a.n_stacks, E);
   return hipGetLastError();
 }
 

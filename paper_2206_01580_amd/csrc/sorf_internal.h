@@ -273,8 +273,15 @@ hipError_t sorf_launch_serve(const ServeKernelArgs& a, int grid, hipStream_t s);
 
 hipError_t sorf_launch_forward(const SorfFeatureArgs& a, float* Z, hipStream_t s);
 // E[m] = sum_f alpha_f Z[m][f] without storing Z; part: n_mols * n_stacks floats.
-hipError_t sorf_launch_energies(const SorfFeatureArgs& a, const float* alpha, float* part,
-                                float* E, hipStream_t s);
+// Energies without forces: a molecule's atoms are taken kEnergyChunkAtoms at a
+// time (chunk_ptr: [n_mols + 1] offsets of the molecules' chunks, formed on
+// the device; part: [chunks][n_stacks] partial energies).
+constexpr int64_t kEnergyChunkAtoms = 32;
+__host__ __device__ inline int64_t energy_chunk_bound(int64_t n_atoms, int64_t n_mols) {
+  return n_mols + (n_atoms + kEnergyChunkAtoms - 1) / kEnergyChunkAtoms;
+}
+hipError_t sorf_launch_energies(const SorfFeatureArgs& a, const float* alpha, int64_t* chunk_ptr,
+                                float* part, float* E, hipStream_t st);
 hipError_t sorf_launch_atom_adjoint(const SorfFeatureArgs& a, const float* alpha, const float* dE,
                                     float* grad_x, float* e_atom, hipStream_t s);
 // Workspace of the force contraction: tile and partial offsets per molecule
