@@ -824,13 +824,15 @@ __global__ __launch_bounds__(256) void fchl19_backward_small_kernel(
 // distance, the centre's angle and the product of the three cosines do not
 // change when j and l swap), so the pair's sides may be passed in either
 // order. t's neighbours are gathered into LDS as in the forward kernel
-// (kFchlMaxNb at most; more leave t's row NaN); c's neighbours are scanned
-// straight from the molecule's positions. Each thread sums a fixed subset of
-// the terms and the threads' sums are added in thread order: the result is
-// deterministic and does not depend on the rest of the batch; the sums are
-// FP64, since an atom of a large molecule gathers thousands of terms. Every pair
-// derivative of a centre is evaluated once for each of the pair's atoms (three
-// times over), the price of needing no workspace and no bound on the size.
+// (kFchlMaxNb at most; more leave t's row NaN). A pair {t, l} of a centre c
+// carries f_cut(r_tl), so l is itself a neighbour of t: the centre-c terms
+// come from the pairs (c, l) of t's own list with r_cl < r_cut. Each thread
+// sums a fixed subset of the terms and the threads' sums are added in thread
+// order: the result is deterministic and does not depend on the rest of the
+// batch; the sums are FP64, since an atom of a large molecule gathers
+// thousands of terms. Every pair derivative of a centre is evaluated once for
+// each of the pair's atoms (three times over), the price of needing no
+// workspace and no bound on the molecule's size.
 __device__ void fchl19_backward_atom(int64_t t, int64_t a0, int64_t a1,
                                      const float* __restrict__ R,
                                      const int32_t* __restrict__ element, int32_t E,
@@ -944,38 +946,38 @@ __device__ void fchl19_backward_atom(int64_t t, int64_t a0, int64_t a1,
       py -= fa * ny[sa] + fb * ny[sb];
       pz -= fa * nz[sa] + fb * nz[sb];
     }
-    // each neighbour c of t as a centre
-    for (int cs = 0; cs < total; ++cs) {
-      const int64_t c_at = a0 + nidx[cs];
-      const float* __restrict__ gc = g + c_at * size;
+    // each neighbour c of t as a centre: t's two-body term in c's row, and
+    // the pairs {t, l} of c. A pair's terms carry f_cut(r_tl), so only the
+    // neighbours l of t contribute, and those are in t's list: the pairs
+    // (c, l) of t's list with r_cl < r_cut, flattened over the threads
+    const int et = element[t];
+    for (int cs = tid; cs < total; cs += 256) {
+      const float* __restrict__ gc = g + (a0 + nidx[cs]) * size;
       const float rct = nr[cs];
-      const float ux = -nx[cs], uy = -ny[cs], uz = -nz[cs];   // R_t - R_c
-      if (tid == 0) {
-        const float f = fchl_pair_grad(rct, gc + et * p.n2, p) / rct;
-        px += f * ux;
-        py += f * uy;
-        pz += f * uz;
-      }
-      const float xc = R[3 * c_at], yc = R[3 * c_at + 1], zc = R[3 * c_at + 2];
-      for (int64_t l = a0 + tid; l < a1; l += 256) {
-        if (l == t || l == c_at) continue;
-        const float lx = R[3 * l], ly = R[3 * l + 1], lz = R[3 * l + 2];
-        const float vx = lx - xc, vy = ly - yc, vz = lz - zc;
-        const float rcl = sqrtf(vx * vx + vy * vy + vz * vz);
-        if (!(rcl < rc)) continue;
-        const float wx = lx - xt, wy = ly - yt, wz = lz - zt;   // R_l - R_t
-        const float rtl = sqrtf(wx * wx + wy * wy + wz * wz);
-        if (!(rtl < rc)) continue;
-        const int el = element[l];
-        const int P = et <= el ? fchl_pair(et, el, E) : fchl_pair(el, et, E);
-        float dL[3];
-        fchl_triple_grad(rct, rcl, rtl, gc + int64_t(E) * p.n2 + int64_t(P) * p.n3 * 2, p, angw,
-                         dL);
-        const float fa = dL[0] / rct, fc = dL[2] / rtl;
-        px += fa * ux - fc * wx;
-        py += fa * uy - fc * wy;
-        pz += fa * uz - fc * wz;
-      }
+      const float f = fchl_pair_grad(rct, gc + et * p.n2, p) / rct;
+      px -= f * nx[cs];   // (R_t - R_c) = -(R_c - R_t)
+      py -= f * ny[cs];
+      pz -= f * nz[cs];
+    }
+    const int64_t n_cl = int64_t(total) * total;
+    for (int64_t q = tid; q < n_cl; q += 256) {
+      const int cs = int(q / total), ls = int(q - int64_t(cs) * total);
+      if (ls == cs) continue;
+      const float wx = nx[ls] - nx[cs], wy = ny[ls] - ny[cs], wz = nz[ls] - nz[cs];   // R_l - R_c
+      const float rcl = sqrtf(wx * wx + wy * wy + wz * wz);
+      if (!(rcl < rc)) continue;
+      int Y = 0;
+      while (ls >= grp[Y + 1]) ++Y;
+      const int P = et <= Y ? fchl_pair(et, Y, E) : fchl_pair(Y, et, E);
+      const float* __restrict__ gc = g + (a0 + nidx[cs]) * size;
+      const float rct = nr[cs], rtl = nr[ls];
+      float dL[3];
+      fchl_triple_grad(rct, rcl, rtl, gc + int64_t(E) * p.n2 + int64_t(P) * p.n3 * 2, p, angw, dL);
+      // dL/da (R_t - R_c) / a + dL/dc (R_t - R_l) / c, with R_x - R_t = n[x]
+      const float fa = dL[0] / rct, fc = dL[2] / rtl;
+      px -= fa * nx[cs] + fc * nx[ls];
+      py -= fa * ny[cs] + fc * ny[ls];
+      pz -= fa * nz[cs] + fc * nz[ls];
     }
   }
   red[0][tid] = px;
