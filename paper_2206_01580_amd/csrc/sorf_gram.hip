@@ -14,8 +14,8 @@
 // bits of small addends with a bias: over 20,000 QM9-like rows the single
 // running accumulator of the hi+lo modes drifted by about -3e-7 sqrt(G_ii
 // G_jj) off the diagonal, enough to make G + 1e-6 I indefinite. Here every
-// mode accumulates 256 rows at a time in a fresh MFMA accumulator P and adds
-// P into an FP32 sum S with ordinary round-to-nearest VALU adds (a blocked
+// mode accumulates 256 rows (plain FP32: 240) at a time in a fresh MFMA
+// accumulator P and adds P into an FP32 sum S with round-to-nearest adds (a blocked
 // summation in the spirit of the paper's compensated sum); this also cuts
 // the FP32 mode's error by an order of magnitude.
 //
@@ -61,7 +61,7 @@ constexpr int TM = 256, TN = 128;      // workgroup tile
 constexpr int kFlushRows = 256;        // rows per fresh MFMA accumulator
 constexpr int kPackSlabs = 64;         // 16-row slabs per pack workgroup (Z^T y chunk)
 constexpr int kFP32Waves = 8;          // waves of the FP32 ring kernel (4 or 8)
-constexpr int kFP32StageRows = 32;     // rows per ring stage, plain FP32 (8% faster than 16)
+constexpr int kFP32StageRows = 48;     // rows per ring stage, plain FP32 (3-11% faster than 32, 16)
 constexpr int kFP32KahanStageRows = 16;   // Kahan: 32 rows would spill 44 registers
 
 __host__ __device__ constexpr bool is_hilo(int mode) {
@@ -1023,9 +1023,12 @@ __device__ __forceinline__ void fold_compensation(f32x16 (&S)[BA][BB], const f32
 // ------------------------------------------------ FP32 mode, D % 4 == 0
 // Stage = SR rows of Z: SR A rows of 256 floats (one wave copy each) and SR B
 // rows of 128 floats (one copy per pair of rows), in a ring of 4 stages of 16
-// rows or 3 of 32. Plain FP32 uses 32 (fewer stage barriers and copy waits per
-// row: 14.1 against 15.3 ms at 20,000 x 8192), the Kahan mode 16 (32 would
-// spill 44 registers).
+// rows, 3 of 32 or 2 of 48. Plain FP32 uses 48 (fewer stage barriers and copy
+// waits per row: 13.7 against 14.1 ms with 32 and 15.3 with 16 at 20,000 x
+// 8192; its block sums then flush every 240 rows), the Kahan mode 16 (32 would
+// spill 44 registers). With two stages the copies of stage s + 2 are issued
+// after the barrier that publishes s + 1 and have the products of s + 1 (about
+// 8 us) to land.
 // Rows past M are copied from a 1 KB block of zeros; columns past D are
 // clamped into the row (they only reach G entries that are never written).
 // NW = 8 (used): eight waves (4 x 2, two per SIMD) of 64 x 64, so that while
@@ -1037,11 +1040,12 @@ __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4,
 void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
                            int64_t nI, int64_t nJ, const float* __restrict__ zeros,
                            float* __restrict__ G, SlicePlan plan, float* __restrict__ part) {
-  static_assert(SR == 16 || SR == 32, "stage rows");
-  constexpr int NS = SR == 16 ? 4 : 3;         // ring depth: 96 or 144 kilobytes of LDS
+  static_assert(SR == 16 || SR == 32 || SR == 48, "stage rows");
+  constexpr int NS = SR == 16 ? 4 : (SR == 32 ? 3 : 2);   // ring depth: 96, 144, 144 KB of LDS
   constexpr int PW = (SR + SR / 2) / NW;       // copies per wave per stage (SR A rows + SR/2 B pairs)
   static_assert(PW * NW == SR + SR / 2, "copies per stage");
-  constexpr int KC = kFlushRows / SR;
+  // stages per flush: 256 rows, or 240 with 48-row stages
+  constexpr int KC = SR == 48 ? 5 : kFlushRows / SR;
   constexpr int WR = TM / (NW / 2), WC = TN / 2;   // wave tile
   constexpr int BA = WR / 32, BB = WC / 32;
   __shared__ float ra[NS][SR][TM];
