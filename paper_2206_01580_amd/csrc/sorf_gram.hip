@@ -652,7 +652,7 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
 // G + lambda I indefinite (100,000 rows, lambda = 1e-8); G itself is summed
 // in FP32 with round-to-nearest.
 //
-// Scheduling: with one 128 KB workgroup per CU, the tiles run in rounds of
+// Scheduling: with one 160 KB workgroup per CU, the tiles run in rounds of
 // kX1Slots. The first n_whole tiles (whole rounds) are computed over all rows
 // and added to G directly; each remaining tail tile is split into n_split
 // slices of the rows so that the last round is filled with short items.
@@ -741,7 +741,7 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   constexpr int NW = kX1Waves;
   constexpr int BA = 4, BB = 2;       // 32 x 32 blocks per wave: 128 x 64
   constexpr int FW = NF / NW;         // copies per wave per stage
-  constexpr int NS = 4;
+  constexpr int NS = 5;               // ring depth: 5 x 32 KB, the whole LDS of a CU
   __shared__ u16x8 ring[NS][NF][64];
 
   int64_t w0, nw, q0, nq;
