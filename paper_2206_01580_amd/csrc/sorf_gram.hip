@@ -14,13 +14,13 @@
 // bits of small addends with a bias: over 20,000 QM9-like rows the single
 // running accumulator of the hi+lo modes drifted by about -3e-7 sqrt(G_ii
 // G_jj) off the diagonal, enough to make G + 1e-6 I indefinite. Here every
-// mode accumulates 256 rows (plain FP32: 240) at a time in a fresh MFMA
+// mode accumulates 256 rows at a time in a fresh MFMA
 // accumulator P and adds P into an FP32 sum S with round-to-nearest adds (a blocked
 // summation in the spirit of the paper's compensated sum); this also cuts
 // the FP32 mode's error by an order of magnitude.
 //
-// Work split. FP32 modes: 8 waves (4 x 2, two per SIMD) per 256 x 128 tile
-// (I, J) of the lower triangle, each wave 64 x 64 (2 x 2 MFMA 32x32 blocks),
+// Work split. FP32 modes: 16 waves (8 x 2, four per SIMD) per 256 x 128 tile
+// (I, J) of the lower triangle, each wave 32 x 64 (1 x 2 MFMA 32x32 blocks),
 // rows staged through a global-to-LDS ring; when the tiles alone would leave
 // compute units idle, a tile's rows are split into slices whose sums are
 // combined in slice order. hi+lo modes (and the split mode's tail): 8 waves (4 x 2, two
@@ -60,9 +60,10 @@ constexpr int KB = 16;                 // rows per fragment / FP32 stage
 constexpr int TM = 256, TN = 128;      // workgroup tile
 constexpr int kFlushRows = 256;        // rows per fresh MFMA accumulator
 constexpr int kPackSlabs = 64;         // 16-row slabs per pack workgroup (Z^T y chunk)
-constexpr int kFP32Waves = 8;          // waves of the FP32 ring kernel (4 or 8)
-constexpr int kFP32StageRows = 48;     // rows per ring stage, plain FP32 (3-11% faster than 32, 16)
-constexpr int kFP32KahanStageRows = 16;   // Kahan: 32 rows would spill 44 registers
+constexpr int kFP32Waves = 16;         // waves of the FP32 ring kernel (four per SIMD)
+constexpr int kFP32KahanWaves = 16;    // the same for its Kahan variant
+constexpr int kFP32StageRows = 32;     // rows per ring stage (3 stages), plain FP32
+constexpr int kFP32KahanStageRows = 32;   // and Kahan
 
 __host__ __device__ constexpr bool is_hilo(int mode) {
   return mode == kBF16HiLo || mode == kFP16HiLo || mode == kSplitCross;
@@ -1023,18 +1024,21 @@ __device__ __forceinline__ void fold_compensation(f32x16 (&S)[BA][BB], const f32
 // ------------------------------------------------ FP32 mode, D % 4 == 0
 // Stage = SR rows of Z: SR A rows of 256 floats (one wave copy each) and SR B
 // rows of 128 floats (one copy per pair of rows), in a ring of 4 stages of 16
-// rows, 3 of 32 or 2 of 48. Plain FP32 uses 48 (fewer stage barriers and copy
-// waits per row: 13.7 against 14.1 ms with 32 and 15.3 with 16 at 20,000 x
-// 8192; its block sums then flush every 240 rows), the Kahan mode 16 (32 would
-// spill 44 registers). With two stages the copies of stage s + 2 are issued
-// after the barrier that publishes s + 1 and have the products of s + 1 (about
-// 8 us) to land.
+// rows, 3 of 32 or 2 of 48 (96, 144, 144 KB of LDS: one workgroup per CU).
+// With two stages the copies of stage s + 2 are issued after the barrier that
+// publishes s + 1 and have the products of s + 1 to land.
 // Rows past M are copied from a 1 KB block of zeros; columns past D are
 // clamped into the row (they only reach G entries that are never written).
-// NW = 8 (used): eight waves (4 x 2, two per SIMD) of 64 x 64, so that while
-// one wave of a SIMD waits on the stage barrier or its LDS reads the other
-// keeps the matrix core busy; the Kahan mode's compensation then spills about
-// 30 registers around the flushes.
+// Waves: NW / 2 x 2 waves of (512 / NW) x 64. Used: NW = 16 (four per SIMD,
+// 32 x 64 each, at most 128 registers) with 3 stages of 32 rows, for both
+// modes: while one wave of a SIMD waits on the stage barrier or its LDS reads,
+// three others can keep the matrix core busy. At 20,000 x 8192 the plain mode
+// takes 13.4 ms against 13.7 with eight waves of 64 x 64 and 2 stages of 48
+// (two per SIMD, about 240 registers), and the Kahan mode 14.4 against 14.7
+// with eight waves and 4 stages of 16; it spills about 19 registers around
+// the flushes. The block size of the products stays 32 x 32
+// (v_mfma_f32_32x32x2f32): v_mfma_f32_16x16x4f32 with the same wave tiles
+// took 13.5 ms (sixteen waves) and 13.8 ms (eight).
 template <bool KAHAN, int NW, int SR>
 __global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
 void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
@@ -1125,6 +1129,10 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
         for (int b = 0; b < BB; ++b)
           P[a][b] = __builtin_amdgcn_mfma_f32_32x32x2f32(af[kk][a], bf[kk][b], P[a][b], 0, 0, 0);
   };
+  // sum r of a lane sits in row 4 (lane / 32) + rr(r) of its 32 x 32 block,
+  // column lane % 32 (the lane-dependent offsets are formed once, outside the
+  // unrolled stores: indexing each store from the lane kept more registers live)
+  auto rr = [](int r) { return 8 * (r >> 2) + (r & 3); };
   // the next sub-stage's LDS reads interleaved with the first products
   auto interleave = [] {
     constexpr int NR = HK * (BA + BB), NM = HK * BA * BB;
@@ -1186,27 +1194,25 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
 
   if (!active) return;
   if (sp > 0) {
-    float* out = part + ((sp - 1) * n_tiles + tile_index(I, J)) * (TM * TN);
+    float* out = part + ((sp - 1) * n_tiles + tile_index(I, J)) * (TM * TN) +
+                 (wy * WR + 4 * (lane >> 5)) * TN + wx * WC + (lane & 31);
 #pragma unroll
     for (int a = 0; a < BA; ++a)
 #pragma unroll
       for (int b = 0; b < BB; ++b)
 #pragma unroll
-        for (int r = 0; r < 16; ++r) {
-          const int i = wy * WR + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-          const int j = wx * WC + b * 32 + (lane & 31);
-          out[i * TN + j] = S[a][b][r];
-        }
+        for (int r = 0; r < 16; ++r) out[(a * 32 + rr(r)) * TN + b * 32] = S[a][b][r];
     return;
   }
+  const int64_t i0 = A0 + wy * WR + 4 * (lane >> 5), j0 = B0 + wx * WC + (lane & 31);
 #pragma unroll
   for (int a = 0; a < BA; ++a)
 #pragma unroll
     for (int b = 0; b < BB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int64_t gi = A0 + wy * WR + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
-        const int64_t gj = B0 + wx * WC + b * 32 + (lane & 31);
+        const int64_t gi = i0 + a * 32 + rr(r);
+        const int64_t gj = j0 + b * 32;
         if (gi < D && gj < D && gi >= gj) G[gi * D + gj] += S[a][b][r];
       }
 }
@@ -1623,8 +1629,8 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
         float* part = reinterpret_cast<float*>(w + g.zpart_bytes + kZeroBytes);
         const dim3 rgrid{unsigned(plan.grid1 * plan.n_split)};
         if (mode == kFP32Kahan)
-          hipLaunchKernelGGL((gram_fp32_ring_kernel<true, kFP32Waves, kFP32KahanStageRows>), rgrid,
-                             dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G,
+          hipLaunchKernelGGL((gram_fp32_ring_kernel<true, kFP32KahanWaves, kFP32KahanStageRows>),
+                             rgrid, dim3(64 * kFP32KahanWaves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G,
                              plan, part);
         else
           hipLaunchKernelGGL((gram_fp32_ring_kernel<false, kFP32Waves, kFP32StageRows>), rgrid,
