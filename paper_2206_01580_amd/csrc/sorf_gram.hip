@@ -643,10 +643,13 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
 }
 
 // ------------------------------------------ 16-bit single-product modes
-// One workgroup (8 waves, 2 x 4, two per SIMD) per 256 x 256 square tile of
-// the lower triangle; each wave owns 128 x 64 (4 x 2 blocks of 32 x 32), so
-// while one wave of a SIMD waits on a barrier or a copy the other keeps the
-// matrix core busy.
+// One workgroup per 256 x 256 square tile of the lower triangle. bf16/fp16:
+// 16 waves (4 x 4, four per SIMD), each owning 64 x 64 (2 x 2 blocks of
+// 32 x 32, 128 registers), so that while one wave of a SIMD waits on a
+// barrier or a copy three others can keep the matrix core busy (1.88 against
+// 1.93 ms at 20,000 x 8192 and 29.2 against 30.5 ms at 100,000 x 16384 with
+// 8 waves of 128 x 64). The split mode's int8 head keeps 8 waves of 128 x 64
+// (two per SIMD): with 16 its FP64 epilogue would spill 32 registers.
 // A launch covers at most kX1LaunchStages stages (32 rows each) and adds its
 // tiles to G, so the matrix-core accumulators never run over more rows than
 // that: a single accumulator over a long row range drifts enough to make
@@ -663,7 +666,8 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
 // its L2) followed by a contiguous run of slices.
 constexpr int TX = 256;        // square tile of the single-product kernel
 constexpr int kX1Slots = 256;  // concurrent workgroups: one per CU of the chip
-constexpr int kX1Waves = 8;    // 2 x 4 waves of 128 x 64, two per SIMD
+// waves per workgroup of the single-product kernel, by mode
+__host__ __device__ constexpr int x1_waves(int mode) { return mode == kSplitHead ? 8 : 16; }
 constexpr int64_t kX1LaunchStages = 256;   // 8192 rows per launch
 
 __host__ __device__ inline int64_t x1_tiles(int64_t D) {
@@ -727,7 +731,8 @@ __host__ __device__ inline void x1_xcd_items(const X1Plan& p, int x, int64_t& w0
 }
 
 template <int MODE>
-__global__ __launch_bounds__(64 * kX1Waves) __attribute__((amdgpu_waves_per_eu(2, 2)))
+__global__ __launch_bounds__(64 * x1_waves(MODE))
+__attribute__((amdgpu_waves_per_eu(x1_waves(MODE) / 4, x1_waves(MODE) / 4)))
 void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_count,
                     int32_t ncb, int32_t D, X1Plan plan, float gscale, float* __restrict__ G,
                     float* __restrict__ part, double* __restrict__ G64,
@@ -739,9 +744,11 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   using Acc = std::conditional_t<HEAD, i32x16, f32x16>;
   constexpr int AF = 2 * (TX / 32);   // A fragments per stage (2 slabs)
   constexpr int NF = 2 * AF;          // A and B
-  constexpr int NW = kX1Waves;
-  constexpr int BA = 4, BB = 2;       // 32 x 32 blocks per wave: 128 x 64
+  constexpr int NW = x1_waves(MODE);
+  constexpr int WR = TX / (NW / 4);   // wave rows: NW / 4 x 4 waves of WR x 64
+  constexpr int BA = WR / 32, BB = 2;  // 32 x 32 blocks per wave
   constexpr int FW = NF / NW;         // copies per wave per stage
+  static_assert(FW * NW == NF, "copies per stage");
   constexpr int NS = 5;               // ring depth: 5 x 32 KB, the whole LDS of a CU
   __shared__ u16x8 ring[NS][NF][64];
 
@@ -761,8 +768,8 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
-  const int wy = wv >> 2, wx = wv & 3;   // rows [128 wy, +128), columns [64 wx, +64)
-  const bool active = I * TX + wy * 128 + 127 >= J * TX + wx * 64;
+  const int wy = wv >> 2, wx = wv & 3;   // rows [WR wy, +WR), columns [64 wx, +64)
+  const bool active = I * TX + wy * WR + WR - 1 >= J * TX + wx * 64;
 
   // the slice of 2-slab stages this item accumulates
   const int64_t s0 = st_begin + st_count * sp / n_split;
@@ -815,14 +822,15 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
           P[a][b] = mma16<MODE>(af[a], bf[b], P[a][b]);
       }
   };
-  // the next half-stage's 6 LDS reads interleaved with the first 6 of 8 MFMAs
+  // the next half-stage's BA + BB LDS reads interleaved with the first MFMAs
   auto interleave = [] {
 #pragma unroll
     for (int i = 0; i < BA + BB; ++i) {
       __builtin_amdgcn_sched_group_barrier(0x008, 1, 0);
       __builtin_amdgcn_sched_group_barrier(0x100, 1, 0);
     }
-    __builtin_amdgcn_sched_group_barrier(0x008, BA * BB - (BA + BB), 0);
+    if constexpr (BA * BB > BA + BB)
+      __builtin_amdgcn_sched_group_barrier(0x008, BA * BB - (BA + BB), 0);
   };
 
 #pragma unroll
@@ -864,7 +872,7 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
       for (int b = 0; b < BB; ++b)
 #pragma unroll
         for (int r = 0; r < 16; ++r) {
-          const int64_t gi = I * TX + wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+          const int64_t gi = I * TX + wy * WR + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
           const int64_t gj = J * TX + wx * 64 + b * 32 + (lane & 31);
           if (gi < D && gj < D && gi >= gj) {
             if constexpr (HEAD)
@@ -883,7 +891,7 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
     for (int b = 0; b < BB; ++b)
 #pragma unroll
       for (int r = 0; r < 16; ++r) {
-        const int i = wy * 128 + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
+        const int i = wy * WR + a * 32 + 8 * (r >> 2) + 4 * (lane >> 5) + (r & 3);
         const int j = wx * 64 + b * 32 + (lane & 31);
         out[i * TX + j] = P[a][b][r];
       }
@@ -1630,8 +1638,8 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
         const dim3 rgrid{unsigned(plan.grid1 * plan.n_split)};
         if (mode == kFP32Kahan)
           hipLaunchKernelGGL((gram_fp32_ring_kernel<true, kFP32KahanWaves, kFP32KahanStageRows>),
-                             rgrid, dim3(64 * kFP32KahanWaves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G,
-                             plan, part);
+                             rgrid, dim3(64 * kFP32KahanWaves), 0, st, Z, n_rows, D, n_tiles, nI,
+                             nJ, zeros, G, plan, part);
         else
           hipLaunchKernelGGL((gram_fp32_ring_kernel<false, kFP32Waves, kFP32StageRows>), rgrid,
                              dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G,
@@ -1662,11 +1670,11 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
         const X1Plan plan = x1_plan(D, cnt);
         const dim3 xg{unsigned(x1_grid(plan))};
         if (mode == kBF16)
-          hipLaunchKernelGGL(gram_x1_kernel<kBF16>, xg, dim3(64 * kX1Waves), 0, st, hi, s0, cnt,
-                             g.ncb, D, plan, gs, G, part, nullptr, nullptr);
+          hipLaunchKernelGGL(gram_x1_kernel<kBF16>, xg, dim3(64 * x1_waves(kBF16)), 0, st, hi, s0,
+                             cnt, g.ncb, D, plan, gs, G, part, nullptr, nullptr);
         else
-          hipLaunchKernelGGL(gram_x1_kernel<kFP16>, xg, dim3(64 * kX1Waves), 0, st, hi, s0, cnt,
-                             g.ncb, D, plan, gs, G, part, nullptr, nullptr);
+          hipLaunchKernelGGL(gram_x1_kernel<kFP16>, xg, dim3(64 * x1_waves(kFP16)), 0, st, hi, s0,
+                             cnt, g.ncb, D, plan, gs, G, part, nullptr, nullptr);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (plan.n_split > 1) {
           const dim3 cg{unsigned(plan.n_tiles - plan.n_whole), unsigned(TX / 4)};
@@ -1768,8 +1776,8 @@ hipError_t sorf_launch_gram_split(int64_t n_rows, int32_t D, const float* Z, con
     const int64_t cnt = n_st - s0 < kHeadLaunchStages ? n_st - s0 : kHeadLaunchStages;
     const X1Plan plan = x1_plan(D, cnt);
     hipLaunchKernelGGL(gram_x1_kernel<kSplitHead>, dim3(unsigned(x1_grid(plan))),
-                       dim3(64 * kX1Waves), 0, st, hi8, s0, cnt, g.ncb, D, plan, 1.0f, nullptr,
-                       reinterpret_cast<float*>(hpart), G, exps);
+                       dim3(64 * x1_waves(kSplitHead)), 0, st, hi8, s0, cnt, g.ncb, D, plan, 1.0f,
+                       nullptr, reinterpret_cast<float*>(hpart), G, exps);
     if ((e = hipGetLastError()) != hipSuccess) return e;
     if (plan.n_split > 1) {
       const dim3 cg{unsigned(plan.n_tiles - plan.n_whole), unsigned(TX / 4)};
