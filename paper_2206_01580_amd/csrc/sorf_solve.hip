@@ -752,16 +752,110 @@ static __device__ __forceinline__ void syrk_tile(double* __restrict__ A, int32_t
       }
 }
 
+// Rows [RP h, RP h + RP) of tile (I, J), RP = 128 / NP: the same update as
+// syrk_tile with the 8 waves on RP / 16 x 128 / (16 BB) blocks of 16 x 16 (BB
+// MFMA blocks each), so that a tile takes NP workgroups. On a diagonal tile
+// the rows are rows RP h .. of the J slab.
+template <int NP>
+static __device__ __forceinline__ void syrk_part_tile(double* __restrict__ A, int32_t D,
+                                                      int32_t k, int64_t I, int64_t J, int h,
+                                                      SyrkSlab& sI, SyrkSlab& sJ) {
+  constexpr int KC = SKC;
+  constexpr int RP = ST / NP;            // rows of the part
+  constexpr int WYN = RP / 16;           // wave rows
+  constexpr int WC = ST / (8 / WYN);     // columns per wave
+  constexpr int BB = WC / 16;            // MFMA blocks per wave
+  static_assert(WYN >= 1 && WYN <= 8 && BB >= 1, "part shape");
+  const bool diag = (I == J);
+  const int64_t s0 = int64_t(k) + NB;
+  const int64_t J0 = s0 + J * ST, I0 = s0 + I * ST + RP * h;
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wv = tid >> 6;
+  const int wy = wv % WYN, wx = wv / WYN;   // rows [16 wy, +16) of the part, columns [WC wx, +WC)
+  const bool idle = diag && (RP * h + 16 * wy + 15 < WC * wx);
+  const int lr = tid >> 2;          // row 0..127 of the J slab (0..RP-1 of the I slab)
+  const int lp = (tid & 3) * 8;     // 8 consecutive k
+  const bool loadI = !diag && lr < RP;
+  const bool okI = I0 + lr < D, okJ = J0 + lr < D;
+  const double* pI = A + min(I0 + (lr % RP), int64_t(D) - 1) * D + k + lp;
+  const double* pJ = A + min(J0 + lr, int64_t(D) - 1) * D + k + lp;
+  double rI[8], rJ[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double a = pI[q], b = pJ[q];
+    rI[q] = okI ? a : 0.0;
+    rJ[q] = okJ ? b : 0.0;
+  }
+  double c[BB][4];
+#pragma unroll
+  for (int b = 0; b < BB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t gi = I0 + wy * 16 + (lane >> 4) + 4 * r;
+      const int64_t gj = J0 + wx * WC + b * 16 + (lane & 15);
+      const bool ok = !idle && gi < D && gj < D && gi >= gj;
+      c[b][r] = ok ? A[gi * D + gj] : 0.0;
+    }
+  f64x4 acc[BB];
+#pragma unroll
+  for (int b = 0; b < BB; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  // A operand: row 16 wy + (lane & 15) of the I slab, or row RP h + ... of the J slab
+  const double (*sa)[KC + 1] = diag ? sJ : sI;
+  const int ra = (diag ? RP * h : 0) + wy * 16 + (lane & 15);
+  for (int c0 = 0; c0 < NB; c0 += KC) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (loadI) sI[lr][lp + q] = rI[q];
+      sJ[lr][lp + q] = rJ[q];
+    }
+    __syncthreads();
+    if (c0 + KC < NB) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double a = pI[c0 + KC + q], b = pJ[c0 + KC + q];
+        rI[q] = okI ? a : 0.0;
+        rJ[q] = okJ ? b : 0.0;
+      }
+    }
+    if (!idle) {
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int p = kk + (lane >> 4);
+        const double av = sa[ra][p];
+        double bv[BB];
+#pragma unroll
+        for (int b = 0; b < BB; ++b) bv[b] = sJ[wx * WC + b * 16 + (lane & 15)][p];
+#pragma unroll
+        for (int b = 0; b < BB; ++b) acc[b] = mfma64(av, bv[b], acc[b]);
+      }
+    }
+    __syncthreads();
+  }
+  if (idle) return;
+#pragma unroll
+  for (int b = 0; b < BB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t gi = I0 + wy * 16 + (lane >> 4) + 4 * r;
+      const int64_t gj = J0 + wx * WC + b * 16 + (lane & 15);
+      if (gi < D && gj < D && gi >= gj) A[gi * D + gj] = c[b][r] - acc[b][r];
+    }
+}
+
 // The part of the trailing update that the next panel reads: the tiles of the
 // trailing matrix's first block column below its diagonal, (I, 0) for
 // I >= 1, and the diagonal tile (1, 1) of the block after next (the tile
-// (0, 0) is updated by the panel kernel).
+// (0, 0) is updated by the panel kernel). kNextParts workgroups per tile
+// (row parts): these few tiles would otherwise leave most compute units idle.
+constexpr int kNextParts = 4;
 __global__ __launch_bounds__(512) void syrk_next_kernel(double* __restrict__ A, int32_t D,
                                                        int32_t k, int32_t nt) {
   __shared__ SyrkSlab sI, sJ;
-  const int64_t t = blockIdx.x;
-  if (t + 1 < nt) syrk_tile(A, D, k, t + 1, 0, sI, sJ);
-  else syrk_tile(A, D, k, 1, 1, sI, sJ);
+  const int64_t t = blockIdx.x / kNextParts;
+  const int h = int(blockIdx.x % kNextParts);
+  if (t + 1 < nt) syrk_part_tile<kNextParts>(A, D, k, t + 1, 0, h, sI, sJ);
+  else syrk_part_tile<kNextParts>(A, D, k, 1, 1, h, sI, sJ);
 }
 
 // The rest of the trailing update, tiles (I, J) with 1 <= J <= I other than
@@ -1147,8 +1241,8 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
         hipLaunchKernelGGL(panel_kernel, dim3(unsigned(nwg - strips)), dim3(512), 0, side, w.A,
                            D, k, int32_t(strips), w.Linv, w.pflags, info);
       if (nt > 1)
-        hipLaunchKernelGGL(syrk_next_kernel, dim3(unsigned(nt)), dim3(512), 0, side, w.A, D, k,
-                           int32_t(nt));
+        hipLaunchKernelGGL(syrk_next_kernel, dim3(unsigned(kNextParts * nt)), dim3(512), 0, side,
+                           w.A, D, k, int32_t(nt));
       if (two && (e = hipEventRecord(ev_next, side)) != hipSuccess) return e;
       const int64_t n_sub = (nt - 1) * nt / 2;   // sub-triangle from (1, 1)
       if (n_sub > 1) {
