@@ -64,7 +64,7 @@ struct SolveWs {
   double* y;     // [D]
   double* dx;    // [D]
   double* part;  // [nt][nt][64] partial sums of the symmetric product
-  int32_t* pflags;  // [4] strip flags of the panel kernel (epoch = block index + 1)
+  int32_t* pflags;  // [8] strip flags of the panel kernel, then of syrk_next (epoch = block + 1)
 };
 
 static size_t align256(size_t n) { return (n + 255) & ~size_t(255); }
@@ -94,7 +94,7 @@ __global__ __launch_bounds__(256) void promote_kernel(const TG* __restrict__ G, 
   const int64_t i = blockIdx.y;
   const int64_t j = int64_t(blockIdx.x) * 256 + threadIdx.x;
   if (i == 0 && j == 0) *info = 0;
-  if (i == 0 && j < 4) pflags[j] = 0;
+  if (i == 0 && j < 8) pflags[j] = 0;
   if (i == 0 && j < D) signal_store(y + j, not_ready());   // output of the first forward sweep
   if (j <= i && j < D) A[i * D + j] = double(G[i * D + j]) + (i == j ? lambda : 0.0);
 }
@@ -519,14 +519,14 @@ __global__ __launch_bounds__(256) void transpose_blocks_kernel(const double* __r
     }
 }
 
-// Panel below the diagonal block, fused with the update of the next diagonal
-// tile: workgroup b (blockIdx.x + wg0) computes the 32 rows
+// Next block row of the panel, fused with the update of the next diagonal
+// tile: workgroup b (0..3) computes the 32 rows
 // L21 = A21 (L11^{-1})^T starting at k + NB + 32 b (8 waves of 16 x 32, 1 x 2 FP64 MFMA blocks; the inverse
 // block sits in LDS; each lane loads its A operands for all of K at once,
 // four consecutive k per row: the MFMA's k index t = lane / 16 stands for
 // k = kb + 4 t + s in step s, and the B operands use the same order).
-// Workgroups 0..3 own the next block row. Each publishes its rows (agent
-// release, then flags[b] = epoch), waits for the lower-numbered ones (which
+// (The panel rows below the next block row are formed by syrk_next.) Each
+// workgroup publishes its rows (agent release, then flags[b] = epoch), waits for the lower-numbered ones (which
 // are dispatched first, so the waits end), and then applies
 //   A[r][c] -= sum_p L21[r][p] L21[c][p]
 // to its 32 rows r of the next diagonal tile and the columns c <= r. The
@@ -539,14 +539,14 @@ constexpr int PR = 32;        // rows per panel workgroup
 constexpr uint64_t kPanelWaitTicks = uint64_t(1) << 28;   // about 2.7 s
 
 __global__ __launch_bounds__(512) void panel_kernel(double* __restrict__ A, int32_t D, int32_t k,
-                                                   int32_t wg0, const double* __restrict__ Linv,
+                                                   const double* __restrict__ Linv,
                                                    int32_t* __restrict__ flags,
                                                    int32_t* __restrict__ info) {
   __shared__ double sL[NB][PLD];
   const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
   const int wy = wv >> 2, wx = wv & 3;   // rows [16 wy, +16), columns [32 wx, +32)
   const int li = lane & 15, lt = lane >> 4;
-  const int b = int(blockIdx.x) + wg0;
+  const int b = int(blockIdx.x);
   const int64_t r0 = int64_t(k) + NB + int64_t(b) * PR;
   const double* inv = Linv + int64_t(k / NB) * NB * NB;
   for (int t = tid; t < NB * NB / 2; t += 512) {
@@ -590,7 +590,6 @@ __global__ __launch_bounds__(512) void panel_kernel(double* __restrict__ A, int3
       const int64_t row = r0 + 16 * wy + lt + 4 * r;
       if (row < D) A[row * D + k + 32 * wx + 16 * c + li] = acc[c][r];
     }
-  if (b >= NB / PR) return;
   // publish this strip of the next block row
   const int32_t epoch = k / NB + 1;
   __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
@@ -843,19 +842,172 @@ static __device__ __forceinline__ void syrk_part_tile(double* __restrict__ A, in
     }
 }
 
-// The part of the trailing update that the next panel reads: the tiles of the
-// trailing matrix's first block column below its diagonal, (I, 0) for
-// I >= 1, and the diagonal tile (1, 1) of the block after next (the tile
-// (0, 0) is updated by the panel kernel). kNextParts workgroups per tile
-// (row parts): these few tiles would otherwise leave most compute units idle.
+// The part of the trailing update that the next panel reads, fused with the
+// panel rows it needs. Tiles of the trailing matrix's first block column
+// below its diagonal, (I, 0) for I >= 1, each in kNextParts workgroups of
+// RP = 32 rows: a workgroup first forms its 32 panel rows
+// L_I = A_I (L_kk^{-1})^T (K = NB in chunks of 32 through LDS, the same
+// products as the panel kernel), stores them in A and keeps them in LDS, then
+// updates its rows of the tile with C -= L_I L_0^T, L_0 being the next block
+// row that the chain's panel kernel wrote. The last kNextParts workgroups
+// update the diagonal tile (1, 1) of the block after next (the tile (0, 0) is
+// updated by the panel kernel) once the workgroups of tile (1, 0) have
+// published L_1 (flags[4 + h] = epoch): those have lower indices and are
+// dispatched first, so the wait ends; past kPanelWaitTicks it sets *info = -1.
+// Splitting tiles into row parts keeps most compute units busy on these few
+// tiles, and forming the panel rows here saves a launch and a pass over them.
 constexpr int kNextParts = 4;
+constexpr int kNextRows = ST / kNextParts;   // 32
 __global__ __launch_bounds__(512) void syrk_next_kernel(double* __restrict__ A, int32_t D,
-                                                       int32_t k, int32_t nt) {
+                                                       int32_t k, int32_t nt,
+                                                       const double* __restrict__ Linv,
+                                                       int32_t* __restrict__ flags,
+                                                       int32_t* __restrict__ info) {
   __shared__ SyrkSlab sI, sJ;
+  __shared__ double sP[kNextRows][NB + 1];
+  constexpr int KC = SKC, RP = kNextRows, WC = 32, BB = 2;
   const int64_t t = blockIdx.x / kNextParts;
   const int h = int(blockIdx.x % kNextParts);
-  if (t + 1 < nt) syrk_part_tile<kNextParts>(A, D, k, t + 1, 0, h, sI, sJ);
-  else syrk_part_tile<kNextParts>(A, D, k, 1, 1, h, sI, sJ);
+  const int32_t epoch = k / NB + 1;
+  const int tid = threadIdx.x, lane = tid & 63, wv = tid >> 6;
+  if (t + 1 >= nt) {   // diagonal tile (1, 1): wait for L_1
+    if (tid == 0) {
+      const uint64_t t0 = __builtin_amdgcn_s_memrealtime();
+      for (int q = 0; q < kNextParts; ++q) {
+        while (__hip_atomic_load(flags + 4 + q, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) <
+               epoch) {
+          if (__builtin_amdgcn_s_memrealtime() - t0 > kPanelWaitTicks) {
+            int32_t expect = 0;
+            __hip_atomic_compare_exchange_strong(info, &expect, -1, __ATOMIC_RELAXED,
+                                                 __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+            break;
+          }
+          __builtin_amdgcn_s_sleep(1);
+        }
+      }
+    }
+    __syncthreads();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    syrk_part_tile<kNextParts>(A, D, k, 1, 1, h, sI, sJ);
+    return;
+  }
+  const int64_t I = t + 1;
+  const int64_t s0 = int64_t(k) + NB;
+  const int64_t R0 = s0 + I * ST + RP * h;   // first row of this part
+  const int wy = wv & 1, wx = wv >> 1;       // rows [16 wy, +16), columns [32 wx, +32)
+  const int lr = tid >> 2;                   // row 0..127 of the J slab (0..31 of the I slab)
+  const int lp = (tid & 3) * 8;              // 8 consecutive k
+  // 1. panel rows: sI <- A rows R0 + lr (columns k ..), sJ <- rows of L_kk^{-1}
+  {
+    const bool okI = R0 + lr < D;
+    const double* pI = A + min(R0 + (lr % RP), int64_t(D) - 1) * D + k + lp;
+    const double* pJ = Linv + int64_t(k / NB) * NB * NB + lr * NB + lp;
+    double rI[8], rJ[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double a = pI[q];
+      rI[q] = okI ? a : 0.0;
+      rJ[q] = pJ[q];
+    }
+    f64x4 acc[BB];
+#pragma unroll
+    for (int b = 0; b < BB; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+    for (int c0 = 0; c0 < NB; c0 += KC) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        if (lr < RP) sI[lr][lp + q] = rI[q];
+        sJ[lr][lp + q] = rJ[q];
+      }
+      __syncthreads();
+      if (c0 + KC < NB) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const double a = pI[c0 + KC + q];
+          rI[q] = okI ? a : 0.0;
+          rJ[q] = pJ[c0 + KC + q];
+        }
+      }
+#pragma unroll
+      for (int kk = 0; kk < KC; kk += 4) {
+        const int p = kk + (lane >> 4);
+        const double av = sI[wy * 16 + (lane & 15)][p];
+        double bv[BB];
+#pragma unroll
+        for (int b = 0; b < BB; ++b) bv[b] = sJ[wx * WC + b * 16 + (lane & 15)][p];
+#pragma unroll
+        for (int b = 0; b < BB; ++b) acc[b] = mfma64(av, bv[b], acc[b]);
+      }
+      __syncthreads();
+    }
+#pragma unroll
+    for (int b = 0; b < BB; ++b)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int i = wy * 16 + (lane >> 4) + 4 * r, j = wx * WC + b * 16 + (lane & 15);
+        sP[i][j] = acc[b][r];
+        if (R0 + i < D) A[(R0 + i) * D + k + j] = acc[b][r];
+      }
+  }
+  if (I == 1) {   // publish this part of L_1 for the diagonal tile's workgroups
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+    __syncthreads();
+    if (tid == 0) __hip_atomic_store(flags + 4 + h, epoch, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+  }
+  __syncthreads();
+  if (R0 >= D) return;
+  // 2. C -= L_I L_0^T on rows R0 .., columns J0 .. of the tile (I, 0)
+  const int64_t J0 = s0;
+  const bool okJ = J0 + lr < D;
+  const double* pJ = A + min(J0 + lr, int64_t(D) - 1) * D + k + lp;
+  double rJ[8];
+#pragma unroll
+  for (int q = 0; q < 8; ++q) {
+    const double b = pJ[q];
+    rJ[q] = okJ ? b : 0.0;
+  }
+  double c[BB][4];
+#pragma unroll
+  for (int b = 0; b < BB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t gi = R0 + wy * 16 + (lane >> 4) + 4 * r;
+      const int64_t gj = J0 + wx * WC + b * 16 + (lane & 15);
+      c[b][r] = gi < D && gj < D ? A[gi * D + gj] : 0.0;
+    }
+  f64x4 acc[BB];
+#pragma unroll
+  for (int b = 0; b < BB; ++b) acc[b] = f64x4{0.0, 0.0, 0.0, 0.0};
+  for (int c0 = 0; c0 < NB; c0 += KC) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) sJ[lr][lp + q] = rJ[q];
+    __syncthreads();
+    if (c0 + KC < NB) {
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double b = pJ[c0 + KC + q];
+        rJ[q] = okJ ? b : 0.0;
+      }
+    }
+#pragma unroll
+    for (int kk = 0; kk < KC; kk += 4) {
+      const int p = kk + (lane >> 4);
+      const double av = sP[wy * 16 + (lane & 15)][c0 + p];
+      double bv[BB];
+#pragma unroll
+      for (int b = 0; b < BB; ++b) bv[b] = sJ[wx * WC + b * 16 + (lane & 15)][p];
+#pragma unroll
+      for (int b = 0; b < BB; ++b) acc[b] = mfma64(av, bv[b], acc[b]);
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int b = 0; b < BB; ++b)
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      const int64_t gi = R0 + wy * 16 + (lane >> 4) + 4 * r;
+      const int64_t gj = J0 + wx * WC + b * 16 + (lane & 15);
+      if (gi < D && gj < D) A[gi * D + gj] = c[b][r] - acc[b][r];
+    }
 }
 
 // The rest of the trailing update, tiles (I, J) with 1 <= J <= I other than
@@ -1229,20 +1381,18 @@ static hipError_t launch_solve(int32_t D, const TG* G, const TG* Zty, double lam
     const int64_t nt = (rest + 127) / 128;
     const int64_t nwg = (rest + PR - 1) / PR;
     const int64_t strips = nwg < NB / PR ? nwg : NB / PR;
-    hipLaunchKernelGGL(panel_kernel, dim3(unsigned(strips)), dim3(512), 0, st, w.A, D, k, 0,
-                       w.Linv, w.pflags, info);
-    const bool side_work = nwg > strips || nt > 1;
+    hipLaunchKernelGGL(panel_kernel, dim3(unsigned(strips)), dim3(512), 0, st, w.A, D, k, w.Linv,
+                       w.pflags, info);
+    // rows below the next block row (nt > 1): their panel rows are formed by
+    // syrk_next together with the tiles that read them
+    const bool side_work = nt > 1;
     if (side_work) {
       if (two) {
         if ((e = hipEventRecord(ev_panel, st)) != hipSuccess) return e;
         if ((e = hipStreamWaitEvent(side, ev_panel, 0)) != hipSuccess) return e;
       }
-      if (nwg > strips)
-        hipLaunchKernelGGL(panel_kernel, dim3(unsigned(nwg - strips)), dim3(512), 0, side, w.A,
-                           D, k, int32_t(strips), w.Linv, w.pflags, info);
-      if (nt > 1)
-        hipLaunchKernelGGL(syrk_next_kernel, dim3(unsigned(kNextParts * nt)), dim3(512), 0, side,
-                           w.A, D, k, int32_t(nt));
+      hipLaunchKernelGGL(syrk_next_kernel, dim3(unsigned(kNextParts * nt)), dim3(512), 0, side,
+                         w.A, D, k, int32_t(nt), w.Linv, w.pflags, info);
       if (two && (e = hipEventRecord(ev_next, side)) != hipSuccess) return e;
       const int64_t n_sub = (nt - 1) * nt / 2;   // sub-triangle from (1, 1)
       if (n_sub > 1) {
