@@ -650,7 +650,10 @@ void gram_packed_kernel(const u16x8* __restrict__ hi, const u16x8* __restrict__ 
 // 1.93 ms at 20,000 x 8192 and 29.2 against 30.5 ms at 100,000 x 16384 with
 // 8 waves of 128 x 64). The split mode's int8 head keeps 8 waves of 128 x 64
 // (two per SIMD): with 16 its FP64 epilogue would spill 32 registers.
-// A launch covers at most kX1LaunchStages stages (32 rows each) and adds its
+// Ring: 16-bit stages of 4 slabs (64 rows, 64 KB), 2 deep; the int8 head's
+// stages of 2 slabs (64 rows, 32 KB), 5 deep (64-row 16-bit stages took
+// 1.85-1.88 against 1.88-1.90 ms with 32-row stages 5 deep at 20,000 x 8192).
+// A launch covers at most kX1LaunchStages stages (8192 rows) and adds its
 // tiles to G, so the matrix-core accumulators never run over more rows than
 // that: a single accumulator over a long row range drifts enough to make
 // G + lambda I indefinite (100,000 rows, lambda = 1e-8); G itself is summed
@@ -668,7 +671,10 @@ constexpr int TX = 256;        // square tile of the single-product kernel
 constexpr int kX1Slots = 256;  // concurrent workgroups: one per CU of the chip
 // waves per workgroup of the single-product kernel, by mode
 __host__ __device__ constexpr int x1_waves(int mode) { return mode == kSplitHead ? 8 : 16; }
-constexpr int64_t kX1LaunchStages = 256;   // 8192 rows per launch
+// fragment slabs per ring stage: 16-bit slabs hold 16 rows, int8 head slabs 32
+__host__ __device__ constexpr int x1_stage_slabs(int mode) { return mode == kSplitHead ? 2 : 4; }
+// 8192 rows per launch: stages of x1_stage_slabs(kBF16) 16-row slabs
+constexpr int64_t kX1LaunchStages = 8192 / (KB * x1_stage_slabs(kBF16));
 
 __host__ __device__ inline int64_t x1_tiles(int64_t D) {
   const int64_t n = (D + TX - 1) / TX;
@@ -742,14 +748,15 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   // sums are exact, and the result goes to the FP64 G scaled by 2^-(e_i + e_j)
   constexpr bool HEAD = MODE == kSplitHead;
   using Acc = std::conditional_t<HEAD, i32x16, f32x16>;
-  constexpr int AF = 2 * (TX / 32);   // A fragments per stage (2 slabs)
+  constexpr int SL = x1_stage_slabs(MODE);   // fragment slabs per stage
+  constexpr int AF = SL * (TX / 32);  // A fragments per stage
   constexpr int NF = 2 * AF;          // A and B
   constexpr int NW = x1_waves(MODE);
   constexpr int WR = TX / (NW / 4);   // wave rows: NW / 4 x 4 waves of WR x 64
   constexpr int BA = WR / 32, BB = 2;  // 32 x 32 blocks per wave
   constexpr int FW = NF / NW;         // copies per wave per stage
   static_assert(FW * NW == NF, "copies per stage");
-  constexpr int NS = 5;               // ring depth: 5 x 32 KB, the whole LDS of a CU
+  constexpr int NS = 160 / NF;        // ring depth: the whole LDS of a CU (NF KB per stage)
   __shared__ u16x8 ring[NS][NF][64];
 
   int64_t w0, nw, q0, nq;
@@ -771,7 +778,7 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
   const int wy = wv >> 2, wx = wv & 3;   // rows [WR wy, +WR), columns [64 wx, +64)
   const bool active = I * TX + wy * WR + WR - 1 >= J * TX + wx * 64;
 
-  // the slice of 2-slab stages this item accumulates
+  // the slice of stages this item accumulates
   const int64_t s0 = st_begin + st_count * sp / n_split;
   const int64_t n_st = st_begin + st_count * (sp + 1) / n_split - s0;
 
@@ -781,9 +788,9 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
     const int f = wv + NW * c;
     const int slab = (f % AF) / (TX / 32);
     const int64_t cbf = (f < AF ? I : J) * (TX / 32) + (f % AF) % (TX / 32);
-    src[c] = ((2 * s0 + slab) * int64_t(ncb) + cbf) * 64 + lane;
+    src[c] = ((SL * s0 + slab) * int64_t(ncb) + cbf) * 64 + lane;
   }
-  const int64_t stage_stride = int64_t(2) * ncb * 64;
+  const int64_t stage_stride = int64_t(SL) * ncb * 64;
   auto issue = [&](int64_t st, int slot) {
     const int64_t off = st * stage_stride;
 #pragma unroll
@@ -798,10 +805,11 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
 #pragma unroll
       for (int r = 0; r < 16; ++r) P[a][b][r] = 0;
 
-  // Software pipeline over half-stages: the fragments of one half-stage are
-  // read from LDS while the MFMAs of the previous half-stage run. All NS
-  // slots are filled up front; after the barrier that publishes stage st + 1
-  // every wave has read all of stage st, so its slot takes stage st + NS.
+  // Software pipeline over the SL slabs of a stage: the fragments of one slab
+  // are read from LDS while the MFMAs of the previous slab run. All NS slots
+  // are filled up front; after the barrier that publishes stage st + 1 every
+  // wave has read all of stage st, so its slot takes stage st + NS.
+  static_assert(SL % 2 == 0, "slabs per stage");
   u16x8 a0[BA], b0[BB], a1[BA], b1[BB];
   auto read_half = [&](int slot, int kk, u16x8 (&af)[BA], u16x8 (&bf)[BB]) {
 #pragma unroll
@@ -822,7 +830,7 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
           P[a][b] = mma16<MODE>(af[a], bf[b], P[a][b]);
       }
   };
-  // the next half-stage's BA + BB LDS reads interleaved with the first MFMAs
+  // the next slab's BA + BB LDS reads interleaved with the first MFMAs
   auto interleave = [] {
 #pragma unroll
     for (int i = 0; i < BA + BB; ++i) {
@@ -841,10 +849,24 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
     stage_barrier();
     read_half(0, 0, a0, b0);
   }
+  // slabs 0 .. SL - 2 of a stage whose slab 0 sits in a0/b0; slab SL - 1 is
+  // left in a1/b1
+  auto inner = [&](int sl) {
+#pragma unroll
+    for (int j = 0; j + 2 < SL; j += 2) {
+      read_half(sl, j + 1, a1, b1);
+      mma_half(a0, b0);
+      interleave();
+      read_half(sl, j + 2, a0, b0);
+      mma_half(a1, b1);
+      interleave();
+    }
+    read_half(sl, SL - 1, a1, b1);
+  };
   int slot = 0;
   for (int64_t st = 0; st + 1 < n_st; ++st) {
     const int nslot = slot + 1 == NS ? 0 : slot + 1;
-    read_half(slot, 1, a1, b1);
+    inner(slot);
     mma_half(a0, b0);
     interleave();
     const int64_t ahead = n_st - 2 - st;
@@ -859,7 +881,7 @@ void gram_x1_kernel(const u16x8* __restrict__ hi, int64_t st_begin, int64_t st_c
     slot = nslot;
   }
   if (n_st > 0) {
-    read_half(slot, 1, a1, b1);
+    inner(slot);
     mma_half(a0, b0);
     mma_half(a1, b1);
   }
@@ -1500,7 +1522,7 @@ namespace {
 size_t al256(size_t b) { return (b + 255) & ~size_t(255); }
 // Workspace: [Z^T y partials][1 KB of zeros][packed hi][packed lo]
 struct GramLayout {
-  int64_t n_slabs;   // 16-row slabs, padded to whole 2-slab stages
+  int64_t n_slabs;   // 16-row slabs, padded to whole 4-slab stages
   int32_t ncb;       // 32-column blocks, padded to whole 256-column tiles
   int64_t chunks;    // Z^T y partial chunks
   size_t part_bytes, zpart_bytes;
@@ -1508,7 +1530,7 @@ struct GramLayout {
 constexpr size_t kZeroBytes = 1024;
 GramLayout gram_layout(int64_t M, int32_t D) {
   GramLayout g;
-  g.n_slabs = ((M + 2 * KB - 1) / (2 * KB)) * 2;
+  g.n_slabs = ((M + 4 * KB - 1) / (4 * KB)) * 4;
   g.ncb = int32_t(((int64_t(D) + TM - 1) / TM) * (TM / 32));
   g.chunks = (g.n_slabs + kPackSlabs - 1) / kPackSlabs;
   g.part_bytes = al256(size_t(g.n_slabs) * size_t(g.ncb) * 1024);
@@ -1525,7 +1547,7 @@ static size_t x1_plan_partial_bytes(const X1Plan& p) {
 
 size_t x1_partial_bytes(int64_t n_rows, int32_t D) {
   const GramLayout g = gram_layout(n_rows, D);
-  const int64_t n_st = g.n_slabs / 2;
+  const int64_t n_st = g.n_slabs / x1_stage_slabs(kBF16);
   const int64_t full = n_st < kX1LaunchStages ? n_st : kX1LaunchStages;
   const int64_t last = n_st % kX1LaunchStages;
   size_t b = x1_plan_partial_bytes(x1_plan(D, full));
@@ -1664,7 +1686,7 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
     case kBF16:
     case kFP16: {
       float* part = reinterpret_cast<float*>(w + g.zpart_bytes + kZeroBytes + g.part_bytes);
-      const int64_t n_st = g.n_slabs / 2;
+      const int64_t n_st = g.n_slabs / x1_stage_slabs(kBF16);
       for (int64_t s0 = 0; s0 < n_st; s0 += kX1LaunchStages) {
         const int64_t cnt = n_st - s0 < kX1LaunchStages ? n_st - s0 : kX1LaunchStages;
         const X1Plan plan = x1_plan(D, cnt);
