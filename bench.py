@@ -895,13 +895,14 @@ def main():
     gram_ws.get(M, D, args.gram) if args.gram != "fp64" else None   # allocate before timing
     solver = sorf.Solver(D, device=dev)
     alpha = torch.empty(D, device=dev, dtype=torch.float64)
-    predictor = sorf.Predictor(model, dev)
+    energy_grad = sorf.EnergyGrad(model, dev)
     E = torch.empty(M, device=dev)
     grad = torch.empty(A, p.d, device=dev)
     scale_exp = sorf.fp16_scale_exp(29 * math.sqrt(2.0 / D)) if args.gram.startswith("fp16") else 0
     torch.cuda.synchronize()
 
-    phases = ["forward", "gram", "solve", "predict", "backward"]
+    # energies and dE/dx come from one adjoint pass over the features
+    phases = ["forward", "gram", "solve", "energy_grad"]
     ev = {k: (torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
           for k in phases}
     times = {k: [] for k in phases}
@@ -923,12 +924,9 @@ def main():
         solver(G, Zty, args.lam, args.n_refine, out=alpha)
         mark("solve", 1)
         a32 = alpha.float()
-        mark("predict", 0)
-        predictor(batch, a32, E=E)
-        mark("predict", 1)
-        mark("backward", 0)
-        sorf.backward(model, batch, a32, out=grad)
-        mark("backward", 1)
+        mark("energy_grad", 0)
+        energy_grad(batch, a32, E=E, grad=grad)
+        mark("energy_grad", 1)
 
     for _ in range(args.warmup):
         step(False)
@@ -953,7 +951,7 @@ def main():
     fwd_slots = valu_slots_per_feature(p.d, p.n_transforms) * af
     fwd_tops = fwd_slots / (med["forward"] * 1e-3) / 1e12
     bwd_slots = valu_slots_per_feature(p.d, p.n_transforms, backward=True) * af
-    bwd_tops = bwd_slots / (med["backward"] * 1e-3) / 1e12
+    bwd_tops = bwd_slots / (med["energy_grad"] * 1e-3) / 1e12
     chol_flop = D ** 3 / 3.0
     mfma_work = MFMA_WORK.get(args.gram, 1.0)
     rooflines = {
@@ -964,26 +962,21 @@ def main():
         "forward": {"bound": "alu", "achieved": fwd_tops, "peak": PEAK_VALU_TOPS,
                     "unit": "T VALU-slots/s", "frac": fwd_tops / PEAK_VALU_TOPS, "traffic": None,
                     "ms": med["forward"]},
-        "backward": {"bound": "alu", "achieved": bwd_tops, "peak": PEAK_VALU_TOPS,
-                     "unit": "T VALU-slots/s", "frac": bwd_tops / PEAK_VALU_TOPS, "traffic": None,
-                     "ms": med["backward"]},
+        "energy_grad": {"bound": "alu", "achieved": bwd_tops, "peak": PEAK_VALU_TOPS,
+                        "unit": "T VALU-slots/s", "frac": bwd_tops / PEAK_VALU_TOPS,
+                        "traffic": None, "ms": med["energy_grad"]},
         "solve": {"bound": "mfma", "achieved": chol_flop / (med["solve"] * 1e-3) / 1e12,
                   "peak": PEAK_MFMA_TFLOPS["fp64"], "unit": "TFLOP/s",
                   "frac": chol_flop / (med["solve"] * 1e-3) / 1e12 / PEAK_MFMA_TFLOPS["fp64"],
                   "traffic": None, "ms": med["solve"]},
     }
-    pred_slots = (valu_slots_per_feature(p.d, p.n_transforms) + 1) * af
-    pred_tops = pred_slots / (med["predict"] * 1e-3) / 1e12
-    rooflines["predict"] = {"bound": "alu", "achieved": pred_tops, "peak": PEAK_VALU_TOPS,
-                            "unit": "T VALU-slots/s", "frac": pred_tops / PEAK_VALU_TOPS,
-                            "traffic": None, "ms": med["predict"]}
     # the dominant single kernel launch (the solve phase is ~1000 launches of 9 kernels)
     cnt = measured_gram_counters(args.gram, M, D)
     if cnt is not None:
         rooflines["gram"]["traffic"] = cnt["hbm_bytes"]
         rooflines["gram"]["mfma_busy_counter"] = cnt["mfma_busy"]
         rooflines["gram"]["clock_ghz_counter"] = cnt["clock_ghz"]
-    dominant = max(("gram", "forward", "backward", "predict"), key=lambda k: med[k])
+    dominant = max(("gram", "forward", "energy_grad"), key=lambda k: med[k])
     roof = {k: v for k, v in rooflines[dominant].items() if k != "ms"}
     roof["kernel"] = dominant
 
@@ -1005,10 +998,10 @@ def main():
         "data": "synthetic",
         "config": {"workload": "qm9-like train+infer step: 20000 molecules (3..29 atoms), d=128, "
                                "64 stacks (D=8192), 3 transforms, sigma=4; forward, Gram (" + args.gram +
-                               "), FP64 solve, energies, dE/dx",
+                               "), FP64 solve, energies and dE/dx (one adjoint pass)",
                    "n_mols": M, "n_atoms": A, "D": D, "gram": args.gram, "lambda": args.lam,
                    "n_refine": args.n_refine},
-        "fwd_bwd_atom_features_per_s": af / ((med["forward"] + med["backward"]) * 1e-3),
+        "fwd_bwd_atom_features_per_s": af / ((med["forward"] + med["energy_grad"]) * 1e-3),
         "gram_tflops": gram_tf,
         "roofline": roof,
         "phase_ms": med,

@@ -48,7 +48,7 @@
 extern "C" {
 #endif
 
-#define SORF_ABI_VERSION 7
+#define SORF_ABI_VERSION 8
 
 typedef void* sorf_stream_t; /* a hipStream_t */
 
@@ -133,6 +133,24 @@ sorf_status sorf_forward(const sorf_model* model, const sorf_batch* batch, float
  *   grad_x: [n_atoms][d] FP32, overwritten. */
 sorf_status sorf_backward(const sorf_model* model, const sorf_batch* batch, const float* alpha,
                           const float* dE, float* grad_x, sorf_stream_t stream);
+
+/* Bytes of workspace sorf_energy_grad needs for n_atoms atoms (host-only query,
+ * nondecreasing). Returns 0 for negative sizes. */
+size_t sorf_energy_grad_workspace_bytes(int64_t n_atoms);
+
+/* Energies and their gradient with respect to the inputs in one pass over the features
+ * (RFF subsection: E_m = Z_m alpha through the atomic energy decomposition, and its
+ * derivative, the adjoint above with dE = 1): each atom's features are formed once and
+ * give both its energy share alpha^T z(x_i) and its gradient row.
+ *   alpha: [D] FP32.  E: [n_mols] FP32 out, each molecule's atom shares summed in atom
+ *   order (as sorf_predict with J: equal to sorf_predict's energies without J to FP32
+ *   rounding, not bitwise).  grad_x: [n_atoms][d] FP32 out, the same values as
+ *   sorf_backward with dE = NULL.
+ *   workspace: device memory of at least sorf_energy_grad_workspace_bytes(n_atoms),
+ *   256-byte aligned (the atoms' energy shares). */
+sorf_status sorf_energy_grad(const sorf_model* model, const sorf_batch* batch, const float* alpha,
+                             float* E, float* grad_x, void* workspace, size_t workspace_bytes,
+                             sorf_stream_t stream);
 
 /* Derivative feature matrix of the force-trained normal equation (RFF subsection:
  * ((Z, dZ)^T (Z, dZ) + lambda I) alpha = (Z, dZ)^T (E, F), dZ with one row per atomic

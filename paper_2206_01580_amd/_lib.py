@@ -27,7 +27,7 @@ GRAM_MODES = {"fp32": 0, "bf16": 1, "fp16": 2, "bf16_hilo": 3, "fp16_hilo": 4,
 # every function the header declares; the load test checks each is exported
 EXPORTS = (
     "sorf_abi_version", "sorf_status_string", "sorf_forward", "sorf_backward",
-    "sorf_derivative_features", "sorf_project_workspace_bytes", "sorf_project",
+    "sorf_energy_grad_workspace_bytes", "sorf_energy_grad", "sorf_derivative_features", "sorf_project_workspace_bytes", "sorf_project",
     "sorf_projection_fit_workspace_bytes", "sorf_projection_fit",
     "sorf_fchl19_length", "sorf_fchl19_forward", "sorf_fchl19_backward",
     "sorf_gram_workspace_bytes", "sorf_gram_accumulate", "sorf_gram_accumulate_f64",
@@ -131,6 +131,8 @@ def load() -> ctypes.CDLL:
         "sorf_status_string": (ctypes.c_char_p, [ctypes.c_int]),
         "sorf_forward": (ctypes.c_int, [MP, BP, P, P]),
         "sorf_backward": (ctypes.c_int, [MP, BP, P, P, P, P]),
+        "sorf_energy_grad_workspace_bytes": (sz, [i64]),
+        "sorf_energy_grad": (ctypes.c_int, [MP, BP, P, P, P, P, sz, P]),
         "sorf_derivative_features": (ctypes.c_int, [MP, BP, P, P, P, P]),
         "sorf_project_workspace_bytes": (sz, [i64, i32]),
         "sorf_project": (ctypes.c_int, [i64, i32, P, P, i32, P, i32, P, P, sz, P]),

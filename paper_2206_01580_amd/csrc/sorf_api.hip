@@ -114,6 +114,28 @@ sorf_status sorf_backward(const sorf_model* model, const sorf_batch* batch, cons
                                       hipStream_t(stream)));
 }
 
+size_t sorf_energy_grad_workspace_bytes(int64_t n_atoms) {
+  if (n_atoms < 0 || n_atoms > (int64_t(1) << 40)) return 0;
+  return ((sizeof(float) * size_t(n_atoms)) + 255) & ~size_t(255);
+}
+
+sorf_status sorf_energy_grad(const sorf_model* model, const sorf_batch* batch, const float* alpha,
+                             float* E, float* grad_x, void* workspace, size_t workspace_bytes,
+                             sorf_stream_t stream) {
+  sorf_status s = check_model(model);
+  if (s != SORF_OK) return s;
+  if ((s = check_batch(batch)) != SORF_OK) return s;
+  if (batch->n_mols > 0 && E == nullptr) return SORF_ERR_INVALID_ARG;
+  if (batch->n_atoms > 0 && (alpha == nullptr || grad_x == nullptr)) return SORF_ERR_INVALID_ARG;
+  if (!aligned16(alpha) || !aligned16(grad_x)) return SORF_ERR_INVALID_ARG;
+  const size_t need = sorf_energy_grad_workspace_bytes(batch->n_atoms);
+  if (batch->n_atoms > 0 && (workspace == nullptr || workspace_bytes < need))
+    return SORF_ERR_WORKSPACE;
+  if ((reinterpret_cast<uintptr_t>(workspace) & 255u) != 0) return SORF_ERR_WORKSPACE;
+  return dev(sorf_launch_energy_grad(pack(model, batch), alpha, grad_x,
+                                     static_cast<float*>(workspace), E, hipStream_t(stream)));
+}
+
 sorf_status sorf_derivative_features(const sorf_model* model, const sorf_batch* batch,
                                      const float* J, const int64_t* J_ptr, float* dZ,
                                      sorf_stream_t stream) {

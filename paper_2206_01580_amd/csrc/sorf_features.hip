@@ -728,9 +728,11 @@ static hipError_t forward_dispatch(const SorfFeatureArgs& a, float* Z, const flo
   return hipGetLastError();
 }
 
+// latency: energies with gradients in the latency form (several waves per
+// atom); otherwise one wave per atom.
 template <int LOG_D>
 static hipError_t adjoint_dispatch(const SorfFeatureArgs& a, const float* alpha, const float* dE,
-                                   float* grad_x, float* e_atom, hipStream_t st) {
+                                   float* grad_x, float* e_atom, bool latency, hipStream_t st) {
   constexpr int LOG_EPL = default_log_epl<LOG_D>();
   const int64_t blocks = (a.n_atoms + 3) / 4;
   float c_rev, g_scale, e_scale;
@@ -740,7 +742,7 @@ static hipError_t adjoint_dispatch(const SorfFeatureArgs& a, const float* alpha,
   hipLaunchKernelGGL((atom_adjoint_kernel<LOG_D, LOG_EPL, WE, WG>), grid, block, 0, st, a.x,   \
                      a.element, a.mol_ptr, a.signs, a.bias, alpha, dE, grad_x, e_atom,        \
                      a.n_atoms, a.n_mols, a.n_stacks, a.n_transforms, c_rev, g_scale, e_scale)
-  if (e_atom && grad_x && dE == nullptr) {
+  if (e_atom && grad_x && dE == nullptr && latency) {
     // energies with forces: the latency form, one pass of stacks per wave
     const int nw = sorf_adjoint_waves(a.d, a.n_stacks);
     const int64_t grid = a.n_atoms < (int64_t(1) << 20) ? a.n_atoms : (int64_t(1) << 20);
@@ -1009,9 +1011,21 @@ hipError_t sorf_launch_energies(const SorfFeatureArgs& a, const float* alpha, in
 hipError_t sorf_launch_atom_adjoint(const SorfFeatureArgs& a, const float* alpha, const float* dE,
                                     float* grad_x, float* e_atom, hipStream_t st) {
   if (a.n_atoms == 0) return hipSuccess;
-#define CALL(L) adjoint_dispatch<L>(a, alpha, dE, grad_x, e_atom, st)
+#define CALL(L) adjoint_dispatch<L>(a, alpha, dE, grad_x, e_atom, true, st)
   SORF_LOGD_SWITCH(log2i(a.d), CALL)
 #undef CALL
+}
+
+hipError_t sorf_launch_energy_grad(const SorfFeatureArgs& a, const float* alpha, float* grad_x,
+                                   float* e_atom, float* E, hipStream_t st) {
+  if (a.n_atoms > 0) {
+    hipError_t e;
+#define CALL(L) adjoint_dispatch<L>(a, alpha, nullptr, grad_x, e_atom, false, st)
+    auto adj = [&]() -> hipError_t { SORF_LOGD_SWITCH(log2i(a.d), CALL) };
+#undef CALL
+    if ((e = adj()) != hipSuccess) return e;
+  }
+  return sorf_launch_molecule_reduce(a, e_atom, grad_x, nullptr, nullptr, E, nullptr, nullptr, st);
 }
 
 size_t sorf_force_plan_bytes(int64_t n_atoms, int64_t n_mols) {

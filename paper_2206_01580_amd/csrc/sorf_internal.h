@@ -284,6 +284,10 @@ hipError_t sorf_launch_energies(const SorfFeatureArgs& a, const float* alpha, in
                                 float* part, float* E, hipStream_t st);
 hipError_t sorf_launch_atom_adjoint(const SorfFeatureArgs& a, const float* alpha, const float* dE,
                                     float* grad_x, float* e_atom, hipStream_t s);
+// Energies E [n_mols] and dE/dx [n_atoms][d] in one adjoint pass (one wave per
+// atom); e_atom: [n_atoms] workspace of the atoms' energy shares.
+hipError_t sorf_launch_energy_grad(const SorfFeatureArgs& a, const float* alpha, float* grad_x,
+                                   float* e_atom, float* E, hipStream_t s);
 // Workspace of the force contraction: tile and partial offsets per molecule
 // plus at most 32 partial rows of 3 N_m floats per molecule.
 size_t sorf_force_plan_bytes(int64_t n_atoms, int64_t n_mols);

@@ -160,6 +160,38 @@ def backward(model: Model, batch: Batch, alpha: torch.Tensor, dE: Optional[torch
     return out
 
 
+class EnergyGrad:
+    """Energies E [n_mols] and dE/dx [n_atoms, d] in one pass over the features
+    (sorf_energy_grad), with the workspace kept between calls."""
+
+    def __init__(self, model: Model, device="cuda"):
+        self.model = model
+        self.device = torch.device(device)
+        self.ws = torch.empty(0, dtype=torch.uint8, device=self.device)
+
+    def __call__(self, batch: Batch, alpha: torch.Tensor, E: Optional[torch.Tensor] = None,
+                 grad: Optional[torch.Tensor] = None):
+        model = self.model
+        batch.check(model)
+        _need(alpha, torch.float32, "alpha", model.n_features)
+        if E is None:
+            E = torch.empty(batch.n_mols, dtype=torch.float32, device=self.device)
+        if grad is None:
+            grad = torch.empty((batch.n_atoms, model.d), dtype=torch.float32, device=self.device)
+        _need(E, torch.float32, "E", batch.n_mols)
+        _need(grad, torch.float32, "grad_x", batch.n_atoms * model.d)
+        lib = _lib.load()
+        need = lib.sorf_energy_grad_workspace_bytes(batch.n_atoms)
+        if self.ws.numel() < need + 256:
+            self.ws = torch.empty(need + 256, dtype=torch.uint8, device=self.device)
+        off = (-self.ws.data_ptr()) % 256
+        m, b = model.c_struct(), batch.c_struct()
+        _lib.check("sorf_energy_grad", lib.sorf_energy_grad(
+            ctypes.byref(m), ctypes.byref(b), _ptr(alpha), _ptr(E), _ptr(grad),
+            self.ws.data_ptr() + off, need, _stream()))
+        return E, grad
+
+
 def derivative_features(model: Model, batch: Batch, J: torch.Tensor, J_ptr: torch.Tensor,
                         out: Optional[torch.Tensor] = None) -> torch.Tensor:
     """dZ [3 n_atoms, D]: minus the coordinate derivatives of the molecules'

@@ -44,7 +44,7 @@ def test_library_exports_every_declared_symbol(lib):
 
 
 def test_abi_version(lib):
-    assert lib.sorf_abi_version() == 7
+    assert lib.sorf_abi_version() == 8
 
 
 def test_struct_layout_matches_c(tmp_path):
@@ -122,6 +122,23 @@ def test_null_outputs_rejected(lib):
     assert P(ctypes.byref(m), ctypes.byref(b), PTR, None, None, PTR, PTR, 256, 1 << 30, None) == _lib.SORF_ERR_INVALID_ARG
 
 
+def test_energy_grad_argument_and_workspace_checks(lib):
+    m, b = _model(), _batch()
+    EG, Q = lib.sorf_energy_grad, lib.sorf_energy_grad_workspace_bytes
+    I, W = _lib.SORF_ERR_INVALID_ARG, _lib.SORF_ERR_WORKSPACE
+    assert Q(-1) == 0 and Q(0) == 0 and Q(1) == 256 and Q(65) == 512
+    need = Q(b.n_atoms)
+    assert EG(ctypes.byref(_model(d=3)), ctypes.byref(b), PTR, PTR, PTR, PTR, need, None) == I
+    assert EG(ctypes.byref(m), ctypes.byref(_batch(x=None)), PTR, PTR, PTR, PTR, need, None) == I
+    assert EG(ctypes.byref(m), ctypes.byref(b), None, PTR, PTR, PTR, need, None) == I   # alpha
+    assert EG(ctypes.byref(m), ctypes.byref(b), PTR, None, PTR, PTR, need, None) == I   # E
+    assert EG(ctypes.byref(m), ctypes.byref(b), PTR, PTR, None, PTR, need, None) == I   # grad_x
+    assert EG(ctypes.byref(m), ctypes.byref(b), PTR + 4, PTR, PTR, PTR, need, None) == I
+    assert EG(ctypes.byref(m), ctypes.byref(b), PTR, PTR, PTR, None, need, None) == W
+    assert EG(ctypes.byref(m), ctypes.byref(b), PTR, PTR, PTR, PTR, need - 1, None) == W
+    assert EG(ctypes.byref(m), ctypes.byref(b), PTR, PTR, PTR, PTR + 16, need, None) == W
+
+
 def test_predict_workspace_checks(lib):
     m, b = _model(), _batch()
     need = lib.sorf_predict_workspace_bytes(ctypes.byref(m), 5, 2)
@@ -152,8 +169,9 @@ def test_gram_workspace_query_and_checks(lib):
     assert Q(0, 64, 1) == 0 and Q(10, 0, 1) == 0 and Q(-1, 64, 0) == 0 and Q(10, 64, 7) == 0
     fp32, bf, hilo = Q(10, 64, 0), Q(10, 64, 1), Q(10, 64, 3)
     assert 0 < fp32 < bf < hilo
-    # 16-bit packing: 32 padded rows x 256 padded columns x 2 bytes per part
-    assert bf - fp32 == 32 * 256 * 2 and hilo - fp32 == 2 * (32 * 256 * 2)
+    # 16-bit packing: 64 padded rows (whole 64-row stages) x 256 padded columns x 2 bytes
+    # per part
+    assert bf - fp32 == 64 * 256 * 2 and hilo - fp32 == 2 * (64 * 256 * 2)
     assert Q(100000, 16384, 3) >= 2 * 100000 * 16384 * 2
     G = lib.sorf_gram_accumulate
     W = _lib.SORF_ERR_WORKSPACE

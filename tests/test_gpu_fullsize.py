@@ -83,6 +83,33 @@ def test_qm9_energies_sampled(qm9):
     assert err.max() <= 1e-5, err.max()
 
 
+def test_qm9_energy_grad_sampled(qm9):
+    """Energies and dE/dx in one pass over the whole training set (the launch
+    the benchmark's energy + gradient phase times): sampled molecules'
+    energies and their atoms' gradient rows against the oracle."""
+    p, _, _, _ = qm9
+    s = S()
+    model, batch = s.Model.from_problem(p), s.Batch.from_problem(p)
+    rng = np.random.default_rng(14)
+    alpha = rng.standard_normal(p.n_features).astype(np.float32)
+    E, g = s.EnergyGrad(model)(batch, torch.from_numpy(alpha).cuda())
+    torch.cuda.synchronize()
+    E, g = E.cpu().numpy().astype(np.float64), g.cpu().numpy().astype(np.float64)
+    sizes = p.mol_sizes()
+    mols = np.unique(np.concatenate([[0, p.n_mols - 1, int(np.argmax(sizes))],
+                                     rng.choice(p.n_mols, 29, replace=False)]))
+    Zo = O.molecule_features(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, mols=mols)
+    Eo = Zo @ alpha.astype(np.float64)
+    scale = np.abs(Zo * alpha[None, :]).sum(axis=1)
+    assert (np.abs(E[mols] - Eo) / scale).max() <= 1e-5
+    # the sampled molecules' atoms as one small batch for the oracle
+    atoms = np.concatenate([np.arange(p.mol_ptr[m], p.mol_ptr[m + 1]) for m in mols])
+    ptr = np.concatenate([[0], np.cumsum(sizes[mols])]).astype(np.int64)
+    go = O.grad_x(p.x[atoms], p.element[atoms], ptr, p.signs, p.bias, p.sigma, alpha)
+    err = np.abs(g[atoms] - go).max(axis=1) / np.abs(go).max(axis=1)
+    assert err.max() <= 1e-5, err.max()
+
+
 def test_qm9_feature_columns(qm9):
     p, Z, cols, Zc = qm9
     Zg = Z[:, torch.from_numpy(cols).cuda()].cpu().numpy().astype(np.float64)

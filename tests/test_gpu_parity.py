@@ -201,6 +201,34 @@ def test_predict_energies_and_forces(shape):
             assert np.abs(Fg[a0:a1] - Fo[a0:a1]).max() <= 1e-5 * np.abs(Fo[a0:a1]).max()
 
 
+@pytest.mark.parametrize("shape", [(8, 3, 3, 2, 7, 0, 5), (64, 4, 3, 3, 9, 1, 10),
+                                   (128, 16, 3, 5, 6, 0, 9), (256, 3, 2, 2, 4, 1, 6),
+                                   (1024, 3, 2, 2, 3, 1, 3)],
+                         ids=lambda s: "d{}-S{}-T{}".format(*s[:3]))
+def test_energy_grad_matches_oracle_and_separate_calls(shape):
+    """sorf_energy_grad: energies within the energy bound of the oracle, dE/dx
+    within the gradient bound and bitwise equal to sorf_backward (same kernel
+    family and summation order), energies equal to sorf_predict's to FP32
+    rounding. Includes empty molecules (lo = 0)."""
+    d, S_, T, E, M, lo, hi = shape
+    p = W.random_problem(3500 + d, d, S_, T, E, M, hi, lo, sigma=32.0 if d >= 1024 else None)
+    model, batch = dev_problem(p)
+    alpha = torch.from_numpy(p.alpha).cuda()
+    eg = S().EnergyGrad(model)
+    Eg, g = eg(batch, alpha)
+    gb = S().backward(model, batch, alpha)
+    En = S().predict(model, batch, alpha)
+    torch.cuda.synchronize()
+    _check_energy(Eg.cpu().numpy(), p, p.alpha)
+    go = O.grad_x(p.x, p.element, p.mol_ptr, p.signs, p.bias, p.sigma, p.alpha)
+    check_rows(g.cpu().numpy(), go)
+    assert torch.equal(g, gb)
+    Zo = oracle_forward(p)
+    scale = np.abs(Zo * p.alpha[None, :]).sum(axis=1)
+    diff = np.abs(Eg.cpu().numpy().astype(np.float64) - En.cpu().numpy())
+    assert np.all(diff <= 2e-5 * np.maximum(scale, 1e-30))
+
+
 def test_predict_conformations_subset_with_jacobians():
     p = W.conformations(n_conf=6)
     model, batch = dev_problem(p)
