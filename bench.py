@@ -1040,7 +1040,7 @@ def main():
         del Gm, rm
         log(f"gram {mode}: {ms:.2f} ms")
     out["gram_modes"] = extra
-    del Z, G, model, batch, predictor, solver, grad, gram_ws
+    del Z, G, model, batch, energy_grad, solver, grad, gram_ws
     torch.cuda.empty_cache()
     if args.serve_seconds > 0:
         out["serving"] = serving_leg(args, dev, log, args.serve_rate, args.serve_seconds)
