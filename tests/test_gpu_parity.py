@@ -203,8 +203,11 @@ def test_predict_energies_and_forces(shape):
 
 @pytest.mark.parametrize("shape", [(8, 3, 3, 2, 7, 0, 5), (64, 4, 3, 3, 9, 1, 10),
                                    (128, 16, 3, 5, 6, 0, 9), (256, 3, 2, 2, 4, 1, 6),
-                                   (1024, 3, 2, 2, 3, 1, 3)],
-                         ids=lambda s: "d{}-S{}-T{}".format(*s[:3]))
+                                   (1024, 3, 2, 2, 3, 1, 3),
+                                   # molecules of up to 300 atoms (energy sums over many
+                                   # groups of 16 atoms)
+                                   (32, 4, 3, 3, 4, 40, 300)],
+                         ids=lambda s: "d{}-S{}-T{}-N{}".format(s[0], s[1], s[2], s[6]))
 def test_energy_grad_matches_oracle_and_separate_calls(shape):
     """sorf_energy_grad: energies within the energy bound of the oracle, dE/dx
     within the gradient bound and bitwise equal to sorf_backward (same kernel
@@ -227,6 +230,24 @@ def test_energy_grad_matches_oracle_and_separate_calls(shape):
     scale = np.abs(Zo * p.alpha[None, :]).sum(axis=1)
     diff = np.abs(Eg.cpu().numpy().astype(np.float64) - En.cpu().numpy())
     assert np.all(diff <= 2e-5 * np.maximum(scale, 1e-30))
+
+
+def test_energy_grad_empty_batch_gives_zero_energies():
+    """No atoms, three (empty) molecules: E = 0 exactly, no workspace needed."""
+    from paper_2206_01580_amd import _lib
+    import ctypes
+    p = W.random_problem(77, 16, 2, 2, 2, 3, 0, 0)
+    assert p.x.shape[0] == 0
+    model, batch = dev_problem(p)
+    lib = _lib.load()
+    E = torch.full((3,), 7.0, device="cuda")
+    alpha = torch.from_numpy(p.alpha).cuda()
+    m, b = model.c_struct(), batch.c_struct()
+    st = lib.sorf_energy_grad(ctypes.byref(m), ctypes.byref(b), alpha.data_ptr(), E.data_ptr(),
+                              None, None, 0, torch.cuda.current_stream().cuda_stream)
+    assert st == _lib.SORF_OK
+    torch.cuda.synchronize()
+    assert torch.equal(E, torch.zeros(3, device="cuda"))
 
 
 def test_predict_conformations_subset_with_jacobians():
