@@ -19,9 +19,10 @@
 // summation in the spirit of the paper's compensated sum); this also cuts
 // the FP32 mode's error by an order of magnitude.
 //
-// Work split. FP32 modes: 16 waves (8 x 2, four per SIMD) per 256 x 128 tile
-// (I, J) of the lower triangle, each wave 32 x 64 (1 x 2 MFMA 32x32 blocks),
-// rows staged through a global-to-LDS ring; when the tiles alone would leave
+// Work split. FP32 modes: 16 waves (four per SIMD) per 256 x 128 tile (I, J)
+// of the lower triangle, each wave 32 x 64 (1 x 2 MFMA 32x32 blocks), as two
+// 8-wave workgroups of 128 x 128 that share a compute unit, rows staged
+// through a global-to-LDS ring; when the tiles alone would leave
 // compute units idle, a tile's rows are split into slices whose sums are
 // combined in slice order. hi+lo modes (and the split mode's tail): 8 waves (4 x 2, two
 // per SIMD) per 256 x 128 tile, each wave 64 x 64 (2 x 2 blocks). Single
@@ -60,10 +61,11 @@ constexpr int KB = 16;                 // rows per fragment / FP32 stage
 constexpr int TM = 256, TN = 128;      // workgroup tile
 constexpr int kFlushRows = 256;        // rows per fresh MFMA accumulator
 constexpr int kPackSlabs = 64;         // 16-row slabs per pack workgroup (Z^T y chunk)
-constexpr int kFP32Waves = 16;         // waves of the FP32 ring kernel (four per SIMD)
-constexpr int kFP32KahanWaves = 16;    // the same for its Kahan variant
-constexpr int kFP32StageRows = 32;     // rows per ring stage (3 stages), plain FP32
-constexpr int kFP32KahanStageRows = 32;   // and Kahan
+// FP32 ring kernel (both FP32 modes): half tiles, two 8-wave workgroups per
+// CU, 32-row stages
+constexpr int kFP32Waves = 8;
+constexpr bool kFP32Half = true;
+constexpr int kFP32StageRows = 32;
 
 __host__ __device__ constexpr bool is_hilo(int mode) {
   return mode == kBF16HiLo || mode == kFP16HiLo || mode == kSplitCross;
@@ -1059,62 +1061,80 @@ __device__ __forceinline__ void fold_compensation(f32x16 (&S)[BA][BB], const f32
 // publishes s + 1 and have the products of s + 1 to land.
 // Rows past M are copied from a 1 KB block of zeros; columns past D are
 // clamped into the row (they only reach G entries that are never written).
-// Waves: NW / 2 x 2 waves of (512 / NW) x 64. Used: NW = 16 (four per SIMD,
-// 32 x 64 each, at most 128 registers) with 3 stages of 32 rows, for both
-// modes: while one wave of a SIMD waits on the stage barrier or its LDS reads,
-// three others can keep the matrix core busy. At 20,000 x 8192 the plain mode
-// takes 13.4 ms against 13.7 with eight waves of 64 x 64 and 2 stages of 48
-// (two per SIMD, about 240 registers), and the Kahan mode 14.4 against 14.7
-// with eight waves and 4 stages of 16; it spills about 19 registers around
-// the flushes. The block size of the products stays 32 x 32
+// Waves: NW / 2 x 2 waves of (2 TA / NW) x 64, TA the A columns of a workgroup.
+// HALF: the two row halves of a 256 x 128 tile (TA = 128) go to two
+// workgroups of 8 waves of 32 x 64 with a 64 KB ring (2 stages of 32 rows),
+// so two workgroups share a compute unit and each passes its stage barriers
+// on its own: while one waits on a barrier or a copy, the other's waves keep
+// the matrix cores busy. Each entry of G is summed in the same order either
+// way (bitwise the same G). Plain FP32 uses half tiles: 12.6 ms at 20,000 x
+// 8192 against 13.4 with one 16-wave workgroup per tile (four waves per SIMD,
+// 3 stages of 32 rows), 13.7 with eight waves of 64 x 64 and 2 stages of 48,
+// and 13.3 with half tiles and 16-row stages; 216 against 232 ms at 100,000
+// x 16384. The Kahan mode likewise: 13.6 ms against 14.4 in whole 16-wave
+// tiles and 14.7 with eight waves of 64 x 64 and 4 stages of 16 (it spills
+// about 24 registers around the flushes). The block size of the products stays 32 x 32
 // (v_mfma_f32_32x32x2f32): v_mfma_f32_16x16x4f32 with the same wave tiles
 // took 13.5 ms (sixteen waves) and 13.8 ms (eight).
-template <bool KAHAN, int NW, int SR>
-__global__ __launch_bounds__(64 * NW) __attribute__((amdgpu_waves_per_eu(NW / 4, NW / 4)))
+template <bool KAHAN, int NW, int SR, bool HALF>
+__global__ __launch_bounds__(64 * NW)
+__attribute__((amdgpu_waves_per_eu(HALF ? NW / 2 : NW / 4, HALF ? NW / 2 : NW / 4)))
 void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, int64_t n_tiles,
                            int64_t nI, int64_t nJ, const float* __restrict__ zeros,
                            float* __restrict__ G, SlicePlan plan, float* __restrict__ part) {
   static_assert(SR == 16 || SR == 32 || SR == 48, "stage rows");
-  constexpr int NS = SR == 16 ? 4 : (SR == 32 ? 3 : 2);   // ring depth: 96, 144, 144 KB of LDS
-  constexpr int PW = (SR + SR / 2) / NW;       // copies per wave per stage (SR A rows + SR/2 B pairs)
-  static_assert(PW * NW == SR + SR / 2, "copies per stage");
+  constexpr int TA = HALF ? TM / 2 : TM;      // A columns (rows of G) per workgroup
+  // ring depth: 96, 144, 144 KB of LDS for whole tiles, 64 KB for half tiles
+  constexpr int NS = HALF ? 64 / SR : (SR == 16 ? 4 : (SR == 32 ? 3 : 2));
+  // copies per stage: SR A rows (HALF: SR / 2 pairs) and SR / 2 pairs of B rows
+  constexpr int NCP = HALF ? SR : SR + SR / 2;
+  constexpr int PW = NCP / NW;                 // copies per wave per stage
+  static_assert(PW * NW == NCP && NS >= 2, "copies per stage, ring depth");
   // stages per flush: 256 rows, or 240 with 48-row stages
   constexpr int KC = SR == 48 ? 5 : kFlushRows / SR;
-  constexpr int WR = TM / (NW / 2), WC = TN / 2;   // wave tile
+  constexpr int WR = TA / (NW / 2), WC = TN / 2;   // wave tile
   constexpr int BA = WR / 32, BB = WC / 32;
-  __shared__ float ra[NS][SR][TM];
+  __shared__ float ra[NS][SR][TA];
   __shared__ float rb[NS][SR][TN];
 
+  // HALF: workgroups b and b + 8 of each group of 16 take the two row halves
+  // of the same item, on the same XCD (b mod 8)
   int64_t I, J;
-  const int64_t sp = blockIdx.x / plan.grid1;
-  if (!super_tile(blockIdx.x % plan.grid1, D, nI, nJ, I, J)) return;
+  const int64_t hb = HALF ? (blockIdx.x / 8) & 1 : 0;
+  const int64_t bid = HALF ? (blockIdx.x / 16) * 8 + blockIdx.x % 8 : blockIdx.x;
+  const int64_t sp = bid / plan.grid1;
+  if (!super_tile(bid % plan.grid1, D, nI, nJ, I, J)) return;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wv = tid >> 6;
   const int wy = wv >> 1, wx = wv & 1;
-  const bool active = I * TM + wy * WR + WR - 1 >= J * TN + wx * WC;
-  const int64_t A0 = I * TM, B0 = J * TN;
-  const int64_t colA = (A0 + 4 * lane < D - 4 ? A0 + 4 * lane : D - 4);
+  const int64_t A0 = I * TM + hb * TA, B0 = J * TN;
+  const bool active = A0 + wy * WR + WR - 1 >= B0 + wx * WC;
+  const int la = HALF ? (lane & 31) : lane;
+  const int64_t colA = (A0 + 4 * la < D - 4 ? A0 + 4 * la : D - 4);
   const int64_t colB = (B0 + 4 * (lane & 31) < D - 4 ? B0 + 4 * (lane & 31) : D - 4);
   // this item's rows [r0, r1)
   const int64_t r0 = sp * plan.rows_per;
   const int64_t r1 = r0 + plan.rows_per < M ? r0 + plan.rows_per : M;
   const int64_t n_st = r1 > r0 ? (r1 - r0 + SR - 1) / SR : 0;
-  // copy c of a stage (c = wv + NW i): c < SR is A row c, else B rows 2 (c - SR) + (0, 1)
+  // copy c of a stage (c = wv + NW i): c < NA is A row c (HALF: rows 2 c + (0, 1)),
+  // else B rows 2 (c - NA) + (0, 1)
   auto issue = [&](int64_t st, int slot) {
     const int64_t m0 = r0 + st * SR;
 #pragma unroll
     for (int i = 0; i < PW; ++i) {
       const int c = wv + NW * i;
-      if (c < SR) {
-        const int64_t m = m0 + c;
+      constexpr int NA = HALF ? SR / 2 : SR;
+      if (c < NA) {
+        const int k = HALF ? 2 * c + (lane >> 5) : c;
+        const int64_t m = m0 + k;
         const float* g = m < r1 ? Z + m * D + colA : zeros + 4 * lane;
-        dma16(g, &ra[slot][c][0]);
+        dma16(g, &ra[slot][HALF ? 2 * c : c][0]);
       } else {
-        const int k = 2 * (c - SR) + (lane >> 5);
+        const int k = 2 * (c - NA) + (lane >> 5);
         const int64_t m = m0 + k;
         const float* g = m < r1 ? Z + m * D + colB : zeros + 4 * lane;
-        dma16(g, &rb[slot][2 * (c - SR)][0]);
+        dma16(g, &rb[slot][2 * (c - NA)][0]);
       }
     }
   };
@@ -1225,7 +1245,7 @@ void gram_fp32_ring_kernel(const float* __restrict__ Z, int64_t M, int32_t D, in
   if (!active) return;
   if (sp > 0) {
     float* out = part + ((sp - 1) * n_tiles + tile_index(I, J)) * (TM * TN) +
-                 (wy * WR + 4 * (lane >> 5)) * TN + wx * WC + (lane & 31);
+                 (hb * TA + wy * WR + 4 * (lane >> 5)) * TN + wx * WC + (lane & 31);
 #pragma unroll
     for (int a = 0; a < BA; ++a)
 #pragma unroll
@@ -1659,13 +1679,13 @@ hipError_t sorf_launch_gram(int64_t n_rows, int32_t D, const float* Z, const flo
         float* part = reinterpret_cast<float*>(w + g.zpart_bytes + kZeroBytes);
         const dim3 rgrid{unsigned(plan.grid1 * plan.n_split)};
         if (mode == kFP32Kahan)
-          hipLaunchKernelGGL((gram_fp32_ring_kernel<true, kFP32KahanWaves, kFP32KahanStageRows>),
-                             rgrid, dim3(64 * kFP32KahanWaves), 0, st, Z, n_rows, D, n_tiles, nI,
-                             nJ, zeros, G, plan, part);
+          hipLaunchKernelGGL((gram_fp32_ring_kernel<true, kFP32Waves, kFP32StageRows, kFP32Half>),
+                             dim3((kFP32Half ? 2 : 1) * rgrid.x), dim3(64 * kFP32Waves), 0, st, Z,
+                             n_rows, D, n_tiles, nI, nJ, zeros, G, plan, part);
         else
-          hipLaunchKernelGGL((gram_fp32_ring_kernel<false, kFP32Waves, kFP32StageRows>), rgrid,
-                             dim3(64 * kFP32Waves), 0, st, Z, n_rows, D, n_tiles, nI, nJ, zeros, G,
-                             plan, part);
+          hipLaunchKernelGGL((gram_fp32_ring_kernel<false, kFP32Waves, kFP32StageRows, kFP32Half>),
+                             dim3((kFP32Half ? 2 : 1) * rgrid.x), dim3(64 * kFP32Waves), 0, st, Z,
+                             n_rows, D, n_tiles, nI, nJ, zeros, G, plan, part);
         if ((e = hipGetLastError()) != hipSuccess) return e;
         if (plan.n_split > 1 && mode == kFP32Kahan)
           hipLaunchKernelGGL(gram_slices_combine_kernel<true>,
