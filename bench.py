@@ -1040,6 +1040,32 @@ def main():
         del Gm, rm
         log(f"gram {mode}: {ms:.2f} ms")
     out["gram_modes"] = extra
+    # context for the solve: the vendor FP64 Cholesky (torch.linalg.cholesky_ex,
+    # rocSOLVER) on the same G + lambda I, against the factorisation and first
+    # solve here (no refinement); median of 3 after one untimed call each
+    if G.dtype == torch.float32:
+        A64 = G.double()
+        A64 = torch.tril(A64) + torch.tril(A64, -1).t()
+        A64.diagonal().add_(args.lam)
+
+        def med3(fn):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(3):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return float(np.median(ts))
+        vendor_ms = med3(lambda: torch.linalg.cholesky_ex(A64))
+        ours_ms = med3(lambda: solver(G, Zty, args.lam, 0, out=alpha))
+        out["solve_vs_vendor"] = {"torch_cholesky_ex_f64_ms": vendor_ms,
+                                  "factor_and_first_solve_ms": ours_ms, "D": D}
+        log(f"solve: vendor cholesky {vendor_ms:.2f} ms, ours (no refinement) {ours_ms:.2f} ms")
+        del A64
     del Z, G, model, batch, energy_grad, solver, grad, gram_ws
     torch.cuda.empty_cache()
     if args.serve_seconds > 0:
